@@ -1,0 +1,230 @@
+"""FP64 CPU oracle of the MOL^T Cahn-Hilliard method (arXiv:1611.04214).
+
+TEST INFRASTRUCTURE ONLY: the plain, slow reference the GPU library is checked
+against.  Only the test suite, the smoke check and the CPU-baseline leg of the
+benchmark may import it.  It shares no code with the GPU library; the two meet
+only through the seeded input generators.
+
+The arithmetic lives in ``molt_oracle.c`` (plain C, FP64, OpenMP over lines);
+this module builds it with gcc and marshals numpy arrays through ctypes.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "molt_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+BC_PERIODIC, BC_NEUMANN, BC_DIRICHLET = 0, 1, 2
+BE, BDF2 = 0, 1
+INIT_PREV, INIT_LINEAR = 0, 1
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (-O2, OpenMP).  Returns the library path."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        cmd = ["gcc", "-O2", "-std=c11", "-D_DEFAULT_SOURCE", "-fopenmp", "-fPIC", "-shared",
+               "-o", tmp, _SRC, "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int),
+                ("x0", ctypes.c_double), ("x1", ctypes.c_double),
+                ("y0", ctypes.c_double), ("y1", ctypes.c_double),
+                ("bc", ctypes.c_int), ("M", ctypes.c_int)]
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("eps", ctypes.c_double), ("dt", ctypes.c_double), ("tol", ctypes.c_double),
+                ("sigma0", ctypes.c_double), ("stepper", ctypes.c_int), ("max_iter", ctypes.c_int),
+                ("init", ctypes.c_int), ("fixed_iters", ctypes.c_int),
+                ("reaction", ctypes.c_int), ("react_k", ctypes.c_double)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("residual", ctypes.c_double),
+                ("mass", ctypes.c_double), ("energy", ctypes.c_double),
+                ("s1", ctypes.c_double), ("s2", ctypes.c_double), ("sigma", ctypes.c_double)]
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        lib = ctypes.CDLL(_LIB)
+        dp = ctypes.POINTER(ctypes.c_double)
+        lib.oracle_pqr.argtypes = [ctypes.c_double, dp, dp, dp]
+        lib.oracle_weights.argtypes = [ctypes.c_int, ctypes.c_double, dp, dp]
+        lib.oracle_weights_window.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_int, dp, dp]
+        lib.oracle_sweep.argtypes = [ctypes.POINTER(_Grid), ctypes.c_int, ctypes.c_double, dp, dp]
+        lib.oracle_step.argtypes = [ctypes.POINTER(_Grid), ctypes.POINTER(_Params), dp, dp,
+                                    ctypes.POINTER(_Info)]
+        lib.oracle_solve.argtypes = [ctypes.POINTER(_Grid), ctypes.POINTER(_Params), dp,
+                                     ctypes.c_int, ctypes.POINTER(_Info)]
+        lib.oracle_mass.argtypes = [ctypes.POINTER(_Grid), dp]
+        lib.oracle_mass.restype = ctypes.c_double
+        lib.oracle_energy.argtypes = [ctypes.POINTER(_Grid), ctypes.c_double, dp]
+        lib.oracle_energy.restype = ctypes.c_double
+        lib.oracle_stepper_params.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                              ctypes.c_int, ctypes.c_double, dp]
+        _lib = lib
+    return _lib
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+@dataclass
+class Grid:
+    nx: int
+    ny: int = 1
+    x0: float = 0.0
+    x1: float = 2 * np.pi
+    y0: float = 0.0
+    y1: float = 2 * np.pi
+    bc: int = BC_PERIODIC
+    M: int = 4
+
+    def c(self) -> _Grid:
+        return _Grid(self.nx, self.ny, self.x0, self.x1, self.y0, self.y1, self.bc, self.M)
+
+    @property
+    def hx(self) -> float:
+        return (self.x1 - self.x0) / (self.nx if self.bc == BC_PERIODIC else self.nx - 1)
+
+    @property
+    def hy(self) -> float:
+        if self.ny == 1:
+            return 1.0
+        return (self.y1 - self.y0) / (self.ny if self.bc == BC_PERIODIC else self.ny - 1)
+
+    def nodes_x(self) -> np.ndarray:
+        return self.x0 + self.hx * np.arange(self.nx)
+
+    def nodes_y(self) -> np.ndarray:
+        return self.y0 + self.hy * np.arange(self.ny)
+
+
+@dataclass
+class Params:
+    eps: float
+    dt: float
+    tol: float = 1e-10
+    stepper: int = BE
+    max_iter: int = 300
+    init: int = INIT_PREV
+    fixed_iters: int = 0
+    sigma0: float = 2.0
+    reaction: int = 0          # 0: Cahn-Hilliard cubic; 1: linear f(v) = react_k*v (test hook)
+    react_k: float = 0.0
+
+    def c(self) -> _Params:
+        return _Params(self.eps, self.dt, self.tol, self.sigma0, self.stepper, self.max_iter,
+                       self.init, self.fixed_iters, self.reaction, self.react_k)
+
+
+@dataclass
+class Info:
+    iters: int
+    residual: float
+    mass: float
+    energy: float
+    s1: float
+    s2: float
+    sigma: float
+
+
+def _info(i: _Info) -> Info:
+    return Info(i.iters, i.residual, i.mass, i.energy, i.s1, i.s2, i.sigma)
+
+
+def pqr(nu: float):
+    """The printed M=2 weights P, Q, R (Sec. 3.2)."""
+    lib = _load()
+    P, Q, R = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    lib.oracle_pqr(nu, ctypes.byref(P), ctypes.byref(Q), ctypes.byref(R))
+    return P.value, Q.value, R.value
+
+
+def weights(M: int, nu: float, r: int | None = None):
+    """Cell weights (wl, wr) of window position r (default: centred)."""
+    lib = _load()
+    wl = np.zeros(M + 1)
+    wr = np.zeros(M + 1)
+    if r is None:
+        rc = lib.oracle_weights(M, nu, _dp(wl), _dp(wr))
+    else:
+        rc = lib.oracle_weights_window(M, nu, r, _dp(wl), _dp(wr))
+    if rc != 0:
+        raise ValueError("bad weight arguments")
+    return wl, wr
+
+
+def sweep(grid: Grid, axis: int, alpha: float, field: np.ndarray) -> np.ndarray:
+    """Apply L^{-1} = (I - d^2/alpha^2)^{-1} line by line along axis (0 = x, 1 = y)."""
+    lib = _load()
+    f = np.ascontiguousarray(field, dtype=np.float64).reshape(grid.ny, grid.nx)
+    out = np.empty_like(f)
+    rc = lib.oracle_sweep(ctypes.byref(grid.c()), axis, alpha, _dp(f), _dp(out))
+    if rc != 0:
+        raise ValueError("oracle_sweep: bad arguments")
+    return out.reshape(np.shape(field)) if np.ndim(field) == 2 else out.reshape(-1)
+
+
+def step(grid: Grid, params: Params, u: np.ndarray, u_prev: np.ndarray | None = None):
+    """One time step; returns (u_next, Info).  u_prev=None gives a BE step."""
+    lib = _load()
+    uu = np.ascontiguousarray(u, dtype=np.float64).copy()
+    up = None if u_prev is None else np.ascontiguousarray(u_prev, dtype=np.float64)
+    info = _Info()
+    rc = lib.oracle_step(ctypes.byref(grid.c()), ctypes.byref(params.c()), _dp(uu),
+                         None if up is None else _dp(up), ctypes.byref(info))
+    if rc < 0:
+        raise ValueError("oracle_step failed (%d)" % rc)
+    return uu, _info(info)
+
+
+def solve(grid: Grid, params: Params, u: np.ndarray, nsteps: int):
+    """nsteps steps (BDF2: BE first step).  Returns (u_final, [Info])."""
+    lib = _load()
+    uu = np.ascontiguousarray(u, dtype=np.float64).copy()
+    infos = (_Info * max(nsteps, 1))()
+    rc = lib.oracle_solve(ctypes.byref(grid.c()), ctypes.byref(params.c()), _dp(uu), nsteps, infos)
+    if rc < 0:
+        raise ValueError("oracle_solve failed (%d)" % rc)
+    return uu, [_info(infos[i]) for i in range(nsteps)]
+
+
+def mass(grid: Grid, u: np.ndarray) -> float:
+    lib = _load()
+    uu = np.ascontiguousarray(u, dtype=np.float64)
+    return lib.oracle_mass(ctypes.byref(grid.c()), _dp(uu))
+
+
+def energy(grid: Grid, eps: float, u: np.ndarray) -> float:
+    lib = _load()
+    uu = np.ascontiguousarray(u, dtype=np.float64)
+    return lib.oracle_energy(ctypes.byref(grid.c()), eps, _dp(uu))
+
+
+def stepper_params(eps: float, dt: float, stepper: int, first: bool, sigma0: float = 2.0):
+    """(s1, s2, sigma) of the factored operator (I - s1 Lap)(I - s2 Lap)."""
+    lib = _load()
+    out = np.zeros(3)
+    lib.oracle_stepper_params(eps, dt, stepper, 1 if first else 0, sigma0, _dp(out))
+    return float(out[0]), float(out[1]), float(out[2])
