@@ -1,0 +1,184 @@
+/*
+ * molt.h -- C-ABI of the MI355X (gfx950) MOL^T Cahn-Hilliard library (libmolt.so).
+ *
+ * Method: Causley, Cho, Christlieb, "Method of lines transpose: energy gradient
+ * flows using direct operator inversion for phase field models",
+ * arXiv:1611.04214.  The library applies the line-by-line O(N) inverse of the
+ * modified Helmholtz operator L = I - d_xx/alpha^2 (Sec. 3.1-3.2, eqs. L_Inverse,
+ * Iu, IL, IR, homogeneous) and takes Backward Euler / BDF2 time steps of the
+ * Cahn-Hilliard equation with the factored fourth-order operator and the
+ * splitting-absorbing fixed-point iteration (Sec. 3.1, 4.1, 5.1).
+ *
+ * Conventions shared by every entry point
+ *  - Fields are row-major, f[iy*nx + ix]: rows are x-lines, columns y-lines.
+ *    ny == 1 is a one-dimensional problem.
+ *  - All field pointers are DEVICE pointers owned by the caller; the library
+ *    never allocates or frees device memory.  Scratch memory is the caller's
+ *    workspace (d_work, work_bytes), sized by the *_workspace_bytes queries.
+ *  - Element type: double for MOLT_F64, float for MOLT_F32.  Device pointers
+ *    must be aligned to the element size; 16-byte alignment is faster.
+ *  - stream is a hipStream_t (NULL: the default stream).  Work is enqueued on
+ *    it; mol_t_helmholtz_sweep returns without waiting, ch_step / ch_solve
+ *    synchronize the stream before they return (they report per-step data).
+ *  - Return value: MOLT_OK (0), MOLT_NOT_CONVERGED (+1: a step reached max_iter;
+ *    the state is still advanced) or a negative error code.  No exception
+ *    crosses the ABI.  molt_strerror() names a code, molt_last_error() gives
+ *    the calling thread's last detailed message.
+ *  - Calls that share a workspace must not overlap.
+ */
+#ifndef MOLT_H
+#define MOLT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define MOLT_OK 0
+#define MOLT_NOT_CONVERGED 1
+#define MOLT_EINVAL (-1)       /* bad argument: sizes, alpha, eps, dt, enum, NULL pointer */
+#define MOLT_EUNSUPPORTED (-2) /* valid but not implemented (e.g. line longer than 8192) */
+#define MOLT_EHIP (-3)         /* a HIP runtime call failed; see molt_last_error() */
+#define MOLT_EWORKSPACE (-4)   /* work_bytes smaller than the query returned */
+
+/* boundary conditions of every line (Sec. 3.2: periodic eq. homogeneous;
+ * Neumann and Dirichlet: the analogous 2x2 solve) */
+#define MOLT_BC_PERIODIC 0
+#define MOLT_BC_NEUMANN 1
+#define MOLT_BC_DIRICHLET 2
+
+/* time steppers (Sec. 3.1 eq. CH_BE; Sec. 4.1 eq. BDF2) */
+#define MOLT_BE 0
+#define MOLT_BDF2 1
+
+/* initial iterate of the fixed point: previous step, or R = A1^{-1} A2^{-1} rhs */
+#define MOLT_INIT_PREV 0
+#define MOLT_INIT_LINEAR 1
+
+/* arithmetic of the sweeps and fixed-point updates (weights, boundary solves,
+ * residual, mass and energy are FP64 in both) */
+#define MOLT_F64 0
+#define MOLT_F32 1
+
+/*
+ * Grid (Sec. 3.2: nodes a = x_0 < ... < x_N = b, uniform spacing).
+ *  periodic: nx (ny) UNIQUE nodes per line, h = (x1-x0)/nx, x_N = x_0;
+ *  Neumann / Dirichlet: nx (ny) nodes including both ends, h = (x1-x0)/(nx-1).
+ * order_M: local quadrature order M (2, 4 or 6; Sec. 3.2).  Every line needs
+ * at least M+1 nodes.  Lines are limited to 8192 nodes along x.
+ */
+typedef struct {
+  int32_t nx, ny;
+  double x0, x1, y0, y1;
+  int32_t bc;
+  int32_t order_M;
+} molt_grid;
+
+/*
+ * Cahn-Hilliard step parameters (Sec. 3.1, 4.1, 4.4).
+ *  eps, dt      > 0
+ *  tol          stop when max|v^{k+1} - v^k| < tol (ignored if fixed_iters > 0)
+ *  sigma0       f'(0) of the shifted reaction; 2 for Cahn-Hilliard
+ *  stepper      MOLT_BE or MOLT_BDF2
+ *  max_iter     iteration cap (the step reports MOLT_NOT_CONVERGED if reached)
+ *  init         MOLT_INIT_PREV or MOLT_INIT_LINEAR
+ *  precision    MOLT_F64 or MOLT_F32
+ *  fixed_iters  > 0: run exactly this many iterations (parity mode)
+ *  have_prev    ch_step only: 1 if d_u_prev holds u^{n-1} (a BDF2 step), 0 for
+ *               the start-up step (taken as BE)
+ */
+typedef struct {
+  double eps, dt, tol;
+  double sigma0;
+  int32_t stepper;
+  int32_t max_iter;
+  int32_t init;
+  int32_t precision;
+  int32_t fixed_iters;
+  int32_t have_prev;
+} molt_ch_params;
+
+/* Per-step report.  residual: last max-norm increment (FP64); mass and energy
+ * of u^{n+1} (FP64 reductions; periodic: h-weighted sum / forward-difference
+ * energy, non-periodic: trapezoid weights); s1 >= s2: the factors of
+ * (I - s1 Lap)(I - s2 Lap); sigma: the linear part moved to the left side. */
+typedef struct {
+  int32_t iters;
+  int32_t converged;
+  double residual;
+  double mass, energy;
+  double s1, s2, sigma;
+} molt_step_info;
+
+/*
+ * mol_t_helmholtz_sweep -- apply L^{-1} = (I - d^2/alpha^2)^{-1} along one axis
+ * of `batch` stacked fields (Sec. 3.2: eqs. IL/IR recursions with the order-M
+ * local quadrature, I = (IL + IR)/2, plus the boundary terms B_a e^{-alpha(x-a)}
+ * + B_b e^{-alpha(b-x)}).
+ *  axis: 0 = x (every row), 1 = y (every column; the identity when ny == 1).
+ *  d_in, d_out: batch*ny*nx elements each; d_in == d_out is allowed.
+ *  d_work: at least molt_sweep_workspace_bytes() bytes (may be 0 for axis x).
+ * Asynchronous on `stream`.
+ */
+int32_t mol_t_helmholtz_sweep(const molt_grid* grid, int32_t axis, double alpha, int32_t precision,
+                              const void* d_in, void* d_out, int64_t batch, void* d_work,
+                              size_t work_bytes, void* stream);
+size_t molt_sweep_workspace_bytes(const molt_grid* grid, int32_t axis, int32_t precision, int64_t batch);
+
+/*
+ * ch_workspace_bytes -- bytes of device workspace ch_step / ch_solve need for
+ * this grid and these parameters (0 on invalid arguments).
+ */
+size_t ch_workspace_bytes(const molt_grid* grid, const molt_ch_params* params);
+
+/*
+ * ch_step -- one time step of the Cahn-Hilliard equation (Sec. 3.1 eq. CH_BE,
+ * Sec. 4.1 eq. BDF2) by the factored fixed point of Sec. 5.1.
+ *  d_u:      in u^n, out u^{n+1} (the paper's u; the shift v = u+1 is internal).
+ *  d_u_prev: BDF2 history.  If params->have_prev and stepper == BDF2 it holds
+ *            u^{n-1} and a BDF2 step is taken; otherwise a BE step.  If not
+ *            NULL it receives u^n on return (history rotated in place).
+ *  info:     filled when not NULL.
+ * Synchronizes `stream` before returning.
+ */
+int32_t ch_step(const molt_grid* grid, const molt_ch_params* params, void* d_u, void* d_u_prev,
+                void* d_work, size_t work_bytes, molt_step_info* info, void* stream);
+
+/*
+ * ch_solve -- nsteps steps from d_u (BDF2: BE start-up step, then BDF2 with
+ * the history kept in the workspace).  per_step: nsteps entries or NULL.
+ * Returns MOLT_NOT_CONVERGED if any step reached max_iter.
+ */
+int32_t ch_solve(const molt_grid* grid, const molt_ch_params* params, void* d_u, int64_t nsteps,
+                 void* d_work, size_t work_bytes, molt_step_info* per_step, void* stream);
+
+/*
+ * Kernel timing (not part of the method): HIP events recorded around every
+ * kernel the library launches, on the launch stream, accumulated per kind.
+ * kind = family*8 + program; family 0 x-pass, 1 y-pass totals, 2 y-pass
+ * combine, 3 y-pass final, 4 pointwise; program 0 sweep, 1 rhs sweep, 2-5 the
+ * four fixed-point passes P1-P4.  molt_profile(1) enables and resets,
+ * molt_profile(0) disables; molt_profile_read fills up to max_entries kinds
+ * that ran and returns how many.  Process-wide; use from one thread.
+ */
+typedef struct {
+  int32_t kind;
+  int64_t launches;
+  double total_ms;
+} molt_prof_entry;
+int32_t molt_profile(int32_t enable);
+int32_t molt_profile_read(molt_prof_entry* out, int32_t max_entries);
+
+/* Static name of a status code. */
+const char* molt_strerror(int32_t status);
+
+/* Last detailed error message of the calling thread ("" if none). */
+const char* molt_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MOLT_H */

@@ -1,0 +1,559 @@
+// molt_host.cpp -- host side of libmolt: argument checks, stepper parameters,
+// quadrature weights, workspace layout, the time-step driver and the C-ABI.
+#include <math.h>
+#include <string.h>
+
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "molt.h"
+#include "molt_internal.h"
+
+namespace molt {
+hipError_t launch_xpass(int prec, int prog, const LineCoef& c, const PassArgs& a, DevState* st, int nlines,
+                        int doresid, hipStream_t s);
+hipError_t launch_ypass(int prec, int prog, const LineCoef& c, const PassArgs& a, DevState* st, int nx, int batch,
+                        void* tot, void* jln, hipStream_t s);
+hipError_t launch_pointwise(int prec, int prog, const PassArgs& a, DevState* st, size_t nelem, hipStream_t s);
+hipError_t launch_state_init(DevState* st, double tol, int max_iter, int fixed, hipStream_t s);
+hipError_t launch_copy(int prec, void* dst, const void* src, size_t n, hipStream_t s);
+hipError_t launch_finalize(int prec, void* u, const void* base, const void* W, size_t n, hipStream_t s);
+hipError_t launch_diag(int prec, const void* u, int nx, int ny, int bc, double hx, double hy, double eps,
+                       double* partials, DevState* st, hipStream_t s);
+size_t ypass_tot_elems(int prec, int n, int nx, int batch);
+int diag_blocks(size_t n);
+int xpass_max_n(int prec);
+
+enum { PROG_SWEEP = 0, PROG_RHS = 1, PROG_P1 = 2, PROG_P2 = 3, PROG_P3 = 4, PROG_P4 = 5 };
+
+// --------------------------------------------------------------------------
+// errors
+// --------------------------------------------------------------------------
+static thread_local std::string g_err;
+
+static int32_t fail(int32_t code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                       \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess) return fail(MOLT_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// --------------------------------------------------------------------------
+// per-kernel HIP-event profiler (process-wide; meant for one profiling thread)
+// --------------------------------------------------------------------------
+bool g_prof_on = false;
+namespace {
+struct PendingEv {
+  int kind;
+  hipEvent_t b, e;
+};
+std::mutex g_prof_mu;
+std::vector<hipEvent_t> g_ev_pool;
+std::vector<PendingEv> g_pending;
+hipEvent_t g_open[kProfKinds];
+double g_prof_ms[kProfKinds];
+long long g_prof_n[kProfKinds];
+
+hipEvent_t ev_get() {
+  if (!g_ev_pool.empty()) {
+    hipEvent_t e = g_ev_pool.back();
+    g_ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+}  // namespace
+
+void prof_begin(int kind, hipStream_t s) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  hipEvent_t e = ev_get();
+  if (e) hipEventRecord(e, s);
+  g_open[kind] = e;
+}
+
+void prof_end(int kind, hipStream_t s) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  hipEvent_t e = ev_get();
+  if (e) hipEventRecord(e, s);
+  if (g_open[kind] && e) g_pending.push_back({kind, g_open[kind], e});
+  g_open[kind] = nullptr;
+}
+
+// accumulate every recorded pair (the caller has synchronized the stream)
+static void prof_drain() {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  for (const PendingEv& p : g_pending) {
+    float ms = 0.f;
+    if (hipEventSynchronize(p.e) == hipSuccess && hipEventElapsedTime(&ms, p.b, p.e) == hipSuccess) {
+      g_prof_ms[p.kind] += ms;
+      g_prof_n[p.kind] += 1;
+    }
+    g_ev_pool.push_back(p.b);
+    g_ev_pool.push_back(p.e);
+  }
+  g_pending.clear();
+}
+
+// --------------------------------------------------------------------------
+// quadrature weights (Sec. 3.2): the local integral over one cell with kernel
+// alpha*exp(-alpha|x_j - x'|) of the degree-M Lagrange interpolant on the M+1
+// nodes centred at j.  With s = |x_j - x'|/h in [0,1]:
+//   J^L weight of node j+t_i = sum_p c_p mu_p,  l_i(-s) = sum_p c_p s^p,
+//   mu_p(nu) = nu * int_0^1 exp(-nu s) s^p ds,
+// and J^R the same with l_i(+s).  mu_p in long double: power series for
+// nu <= M+1, the upward recurrence mu_p = (p/nu) mu_{p-1} - e^{-nu} (stable for
+// p < nu) above.
+// --------------------------------------------------------------------------
+static void moments(int M, long double nu, long double* mu) {
+  if (nu > (long double)(M + 1)) {
+    const long double e = expl(-nu);
+    mu[0] = -expm1l(-nu);
+    for (int p = 1; p <= M; ++p) mu[p] = ((long double)p / nu) * mu[p - 1] - e;
+  } else {
+    for (int p = 0; p <= M; ++p) {
+      long double sum = 0.0L, term = 1.0L;  // (-nu)^q / q!
+      for (int q = 0; q < 400; ++q) {
+        const long double add = term / (long double)(p + q + 1);
+        sum += add;
+        if (q > 2 && fabsl(add) < 1e-24L * fabsl(sum)) break;
+        term *= -nu / (long double)(q + 1);
+      }
+      mu[p] = nu * sum;
+    }
+  }
+}
+
+// coefficients in s of the Lagrange basis polynomial i on nodes t_k = k - M/2,
+// evaluated at sign*s
+static void lagrange_in_s(int M, int i, int sign, long double* coef) {
+  for (int p = 0; p <= M; ++p) coef[p] = 0.0L;
+  coef[0] = 1.0L;
+  int deg = 0;
+  const long double ti = (long double)(i - M / 2);
+  for (int k = 0; k <= M; ++k) {
+    if (k == i) continue;
+    const long double tk = (long double)(k - M / 2);
+    const long double den = ti - tk;
+    // multiply by (sign*s - tk)/den
+    long double nw[kMaxM + 2];
+    for (int p = 0; p <= deg + 1; ++p) nw[p] = 0.0L;
+    for (int p = 0; p <= deg; ++p) {
+      nw[p] += -tk * coef[p] / den;
+      nw[p + 1] += (long double)sign * coef[p] / den;
+    }
+    ++deg;
+    for (int p = 0; p <= deg; ++p) coef[p] = nw[p];
+  }
+}
+
+// Lagrange basis i on nodes 0..M at x
+static long double lagrange_at(int M, int i, long double x) {
+  long double p = 1.0L;
+  for (int k = 0; k <= M; ++k)
+    if (k != i) p *= (x - (long double)k) / (long double)(i - k);
+  return p;
+}
+
+static double spacing(int bc, int n, double a, double b) {
+  return bc == MOLT_BC_PERIODIC ? (b - a) / n : (b - a) / (n - 1);
+}
+
+static LineCoef make_line(int n, int bc, int M, double alpha, double h) {
+  LineCoef c;
+  memset(&c, 0, sizeof(c));
+  c.n = n;
+  c.N = bc == MOLT_BC_PERIODIC ? n : n - 1;
+  c.bc = bc;
+  c.M = M;
+  const long double nu = (long double)alpha * (long double)h;
+  c.nu = (double)nu;
+  c.d = (double)expl(-nu);
+  c.mu = (double)expl(-nu * (long double)c.N);
+  long double mu[kMaxM + 1], cf[kMaxM + 2];
+  moments(M, nu, mu);
+  for (int i = 0; i <= M; ++i) {
+    long double sl = 0.0L, sr = 0.0L;
+    lagrange_in_s(M, i, -1, cf);
+    for (int p = 0; p <= M; ++p) sl += cf[p] * mu[p];
+    lagrange_in_s(M, i, +1, cf);
+    for (int p = 0; p <= M; ++p) sr += cf[p] * mu[p];
+    c.wl[i] = (double)sl;
+    c.wr[i] = (double)sr;
+  }
+  for (int g = 1; g <= M / 2; ++g)
+    for (int i = 0; i <= M; ++i) {
+      c.ghostL[g - 1][i] = (double)lagrange_at(M, i, -(long double)g);
+      c.ghostR[g - 1][i] = (double)lagrange_at(M, i, (long double)(M + g));
+    }
+  return c;
+}
+
+// --------------------------------------------------------------------------
+// stepper parameters (Sec. 3.1, 4.1): (I - sigma a Lap + a eps^2 Lap^2) =
+// (I - s1 Lap)(I - s2 Lap), a = beta dt; sigma = sigma0 when the roots are real
+// (factorization), otherwise the square is completed with sigma = 2 eps/sqrt(a)
+// and s1 = s2 = eps sqrt(a).
+// --------------------------------------------------------------------------
+struct StepParams {
+  double a, s1, s2, sigma;
+};
+
+static StepParams step_params(double eps, double dt, double beta, double sigma0) {
+  StepParams p;
+  p.a = beta * dt;
+  const double half = 0.5 * sigma0 * p.a, prod = p.a * eps * eps;
+  if (half * half >= prod) {
+    p.sigma = sigma0;
+    p.s1 = half + sqrt(half * half - prod);
+    p.s2 = prod / p.s1;
+  } else {
+    p.s1 = p.s2 = sqrt(prod);
+    p.sigma = 2.0 * eps / sqrt(p.a);
+  }
+  return p;
+}
+
+// --------------------------------------------------------------------------
+// validation and workspace layout
+// --------------------------------------------------------------------------
+static int32_t check_grid(const molt_grid* g, int prec) {
+  if (!g) return fail(MOLT_EINVAL, "grid is NULL");
+  if (g->order_M != 2 && g->order_M != 4 && g->order_M != 6) return fail(MOLT_EINVAL, "order_M must be 2, 4 or 6");
+  if (g->bc != MOLT_BC_PERIODIC && g->bc != MOLT_BC_NEUMANN && g->bc != MOLT_BC_DIRICHLET)
+    return fail(MOLT_EINVAL, "unknown boundary condition");
+  if (prec != MOLT_F64 && prec != MOLT_F32) return fail(MOLT_EINVAL, "unknown precision");
+  if (g->nx < g->order_M + 1) return fail(MOLT_EINVAL, "nx must be at least M+1");
+  if (g->ny != 1 && g->ny < g->order_M + 1) return fail(MOLT_EINVAL, "ny must be 1 or at least M+1");
+  if (!(g->x1 > g->x0)) return fail(MOLT_EINVAL, "x1 must exceed x0");
+  if (g->ny > 1 && !(g->y1 > g->y0)) return fail(MOLT_EINVAL, "y1 must exceed y0");
+  if (g->nx > xpass_max_n(prec)) return fail(MOLT_EUNSUPPORTED, "rows longer than the x-pass limit");
+  return MOLT_OK;
+}
+
+static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+enum { F_R = 0, F_DL, F_W, F_A1, F_B1, F_C, F_Q, F_M, F_N, F_HIST, F_COUNT };
+
+struct Layout {
+  size_t fld[F_COUNT];
+  size_t tot, jln, state, partials, total;
+};
+
+static Layout ch_layout(const molt_grid* g, int prec) {
+  Layout L;
+  const size_t esz = prec == MOLT_F64 ? 8 : 4;
+  const size_t n = (size_t)g->nx * g->ny;
+  size_t off = 0;
+  for (int i = 0; i < F_COUNT; ++i) {
+    L.fld[i] = off;
+    off += al256(n * esz);
+  }
+  L.tot = off;
+  off += al256(g->ny > 1 ? ypass_tot_elems(prec, g->ny, g->nx, 1) * esz : 0);
+  L.jln = off;
+  off += al256((size_t)2 * g->nx * esz);
+  L.state = off;
+  off += al256(sizeof(DevState));
+  L.partials = off;
+  off += al256((size_t)2 * diag_blocks(n) * sizeof(double));
+  L.total = off;
+  return L;
+}
+
+// --------------------------------------------------------------------------
+// one step
+// --------------------------------------------------------------------------
+static int32_t step_impl(const molt_grid* g, const molt_ch_params* p, void* d_u, void* d_u_prev, bool bdf2,
+                         void* d_work, size_t work_bytes, molt_step_info* info, hipStream_t s, int iter_hint) {
+  const int prec = p->precision;
+  const Layout L = ch_layout(g, prec);
+  if (!d_work || work_bytes < L.total) return fail(MOLT_EWORKSPACE, "workspace smaller than ch_workspace_bytes()");
+  char* w = (char*)d_work;
+  void* F[F_COUNT];
+  for (int i = 0; i < F_COUNT; ++i) F[i] = w + L.fld[i];
+  void* tot = w + L.tot;
+  void* jln = w + L.jln;
+  DevState* st = (DevState*)(w + L.state);
+  double* partials = (double*)(w + L.partials);
+
+  const int nx = g->nx, ny = g->ny, M = g->order_M, bc = g->bc;
+  const size_t n = (size_t)nx * ny;
+  const bool two_d = ny > 1;
+  const StepParams sp = step_params(p->eps, p->dt, bdf2 ? 2.0 / 3.0 : 1.0, p->sigma0);
+  const double al1 = 1.0 / sqrt(sp.s1), al2 = 1.0 / sqrt(sp.s2);
+  const double hx = spacing(bc, nx, g->x0, g->x1);
+  const double hy = two_d ? spacing(bc, ny, g->y0, g->y1) : 1.0;
+  const LineCoef cx1 = make_line(nx, bc, M, al1, hx), cx2 = make_line(nx, bc, M, al2, hx);
+  LineCoef cy1, cy2;
+  if (two_d) {
+    cy1 = make_line(ny, bc, M, al1, hy);
+    cy2 = make_line(ny, bc, M, al2, hy);
+  }
+
+  HIPCHK(launch_state_init(st, p->tol, p->max_iter, p->fixed_iters, s));
+
+  // R = A1^{-1} A2^{-1} rhs, A_i^{-1} = Lx_i^{-1} Ly_i^{-1}
+  PassArgs a;
+  memset(&a, 0, sizeof(a));
+  a.bdf2 = bdf2 ? 1 : 0;
+  a.in[0] = d_u;
+  a.in[1] = bdf2 ? d_u_prev : d_u;
+  if (two_d) {
+    a.out[0] = F[F_A1];
+    HIPCHK(launch_ypass(prec, PROG_RHS, cy2, a, nullptr, nx, 1, tot, jln, s));
+    a.in[0] = F[F_A1];
+    a.out[0] = F[F_B1];
+    HIPCHK(launch_xpass(prec, PROG_SWEEP, cx2, a, nullptr, ny, 0, s));
+    a.in[0] = F[F_B1];
+    a.out[0] = F[F_A1];
+    HIPCHK(launch_ypass(prec, PROG_SWEEP, cy1, a, nullptr, nx, 1, tot, jln, s));
+    a.in[0] = F[F_A1];
+    a.out[0] = F[F_R];
+    HIPCHK(launch_xpass(prec, PROG_SWEEP, cx1, a, nullptr, ny, 0, s));
+  } else {
+    a.out[0] = F[F_B1];
+    HIPCHK(launch_xpass(prec, PROG_RHS, cx2, a, nullptr, 1, 0, s));
+    a.in[0] = F[F_B1];
+    a.out[0] = F[F_R];
+    HIPCHK(launch_xpass(prec, PROG_SWEEP, cx1, a, nullptr, 1, 0, s));
+  }
+  // history: u^n -> u_prev (after the rhs has consumed u^{n-1})
+  if (d_u_prev) HIPCHK(launch_copy(prec, d_u_prev, d_u, n, s));
+
+  void* base = p->init == MOLT_INIT_LINEAR ? F[F_R] : d_u;
+  const int fixed = p->fixed_iters;
+  const int cap = fixed > 0 ? fixed : p->max_iter;
+  int it = 0;
+  int batch = iter_hint > 1 ? iter_hint - 1 : 2;
+  DevState hst;
+  memset(&hst, 0, sizeof(hst));
+  for (;;) {
+    const int nb = batch < cap - it ? batch : cap - it;
+    for (int b = 0; b < nb; ++b, ++it) {
+      PassArgs q;
+      memset(&q, 0, sizeof(q));
+      q.sigma = sp.sigma;
+      q.kappa = sp.a / sp.s1;
+      q.mode = it == 0 ? 0 : 1;
+      // P1 (y, alpha1): a1 = Y1 e, b1 = Y1 lin
+      q.in[0] = base;
+      q.in[1] = F[F_W];
+      q.in[2] = F[F_DL];
+      q.out[0] = F[F_A1];
+      q.out[1] = F[F_B1];
+      if (two_d)
+        HIPCHK(launch_ypass(prec, PROG_P1, cy1, q, st, nx, 1, tot, jln, s));
+      else
+        HIPCHK(launch_pointwise(prec, PROG_P1, q, st, n, s));
+      // P2 (x, alpha1): C, q
+      q.in[0] = F[F_A1];
+      q.in[1] = F[F_B1];
+      q.in[2] = base;
+      q.in[3] = F[F_W];
+      q.in[4] = F[F_DL];
+      q.out[0] = F[F_C];
+      q.out[1] = F[F_Q];
+      HIPCHK(launch_xpass(prec, PROG_P2, cx1, q, st, ny, 0, s));
+      // P3 (y, alpha2): m, n
+      q.in[0] = F[F_C];
+      q.in[1] = F[F_Q];
+      q.out[0] = F[F_M];
+      q.out[1] = F[F_N];
+      if (two_d)
+        HIPCHK(launch_ypass(prec, PROG_P3, cy2, q, st, nx, 1, tot, jln, s));
+      else
+        HIPCHK(launch_pointwise(prec, PROG_P3, q, st, n, s));
+      // P4 (x, alpha2): increment and running sum, residual
+      q.in[0] = F[F_M];
+      q.in[1] = F[F_N];
+      q.in[2] = q.mode ? F[F_DL] : F[F_R];
+      q.in[3] = F[F_W];
+      q.out[0] = F[F_DL];
+      q.out[1] = F[F_W];
+      HIPCHK(launch_xpass(prec, PROG_P4, cx2, q, st, ny, 1, s));
+    }
+    HIPCHK(hipMemcpyAsync(&hst, st, sizeof(DevState), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (g_prof_on) prof_drain();
+    if (hst.done || it >= cap) break;
+    batch = batch < 32 ? batch * 2 : 32;
+  }
+  HIPCHK(launch_finalize(prec, d_u, base, F[F_W], n, s));
+  HIPCHK(launch_diag(prec, d_u, nx, ny, bc, hx, hy, p->eps, partials, st, s));
+  HIPCHK(hipMemcpyAsync(&hst, st, sizeof(DevState), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (g_prof_on) prof_drain();
+  const bool conv = fixed > 0 || hst.last_resid < p->tol;
+  if (info) {
+    info->iters = hst.iters;
+    info->converged = conv ? 1 : 0;
+    info->residual = hst.last_resid;
+    info->mass = hst.mass;
+    info->energy = hst.energy;
+    info->s1 = sp.s1;
+    info->s2 = sp.s2;
+    info->sigma = sp.sigma;
+  }
+  return conv ? MOLT_OK : MOLT_NOT_CONVERGED;
+}
+
+static int32_t check_params(const molt_ch_params* p) {
+  if (!p) return fail(MOLT_EINVAL, "params is NULL");
+  if (!(p->eps > 0) || !(p->dt > 0)) return fail(MOLT_EINVAL, "eps and dt must be positive");
+  if (!(p->sigma0 > 0)) return fail(MOLT_EINVAL, "sigma0 must be positive");
+  if (p->stepper != MOLT_BE && p->stepper != MOLT_BDF2) return fail(MOLT_EINVAL, "unknown stepper");
+  if (p->init != MOLT_INIT_PREV && p->init != MOLT_INIT_LINEAR) return fail(MOLT_EINVAL, "unknown init");
+  if (p->fixed_iters < 0) return fail(MOLT_EINVAL, "fixed_iters must be >= 0");
+  if (p->fixed_iters == 0 && (p->max_iter < 1 || !(p->tol >= 0))) return fail(MOLT_EINVAL, "need max_iter >= 1 and tol >= 0");
+  return MOLT_OK;
+}
+
+}  // namespace molt
+
+using namespace molt;
+
+extern "C" {
+
+const char* molt_strerror(int32_t status) {
+  switch (status) {
+    case MOLT_OK: return "ok";
+    case MOLT_NOT_CONVERGED: return "fixed-point iteration reached max_iter";
+    case MOLT_EINVAL: return "invalid argument";
+    case MOLT_EUNSUPPORTED: return "unsupported configuration";
+    case MOLT_EHIP: return "HIP runtime error";
+    case MOLT_EWORKSPACE: return "workspace too small";
+  }
+  return "unknown status";
+}
+
+const char* molt_last_error(void) { return g_err.c_str(); }
+
+int32_t molt_profile(int32_t enable) {
+  prof_drain();
+  for (int k = 0; k < kProfKinds; ++k) {
+    g_prof_ms[k] = 0.0;
+    g_prof_n[k] = 0;
+  }
+  g_prof_on = enable != 0;
+  return MOLT_OK;
+}
+
+int32_t molt_profile_read(molt_prof_entry* out, int32_t max_entries) {
+  if (!out || max_entries < 0) return fail(MOLT_EINVAL, "bad profile buffer");
+  prof_drain();
+  int32_t m = 0;
+  for (int k = 0; k < kProfKinds && m < max_entries; ++k) {
+    if (g_prof_n[k] == 0) continue;
+    out[m].kind = k;
+    out[m].launches = g_prof_n[k];
+    out[m].total_ms = g_prof_ms[k];
+    ++m;
+  }
+  return m;
+}
+
+size_t molt_sweep_workspace_bytes(const molt_grid* g, int32_t axis, int32_t precision, int64_t batch) {
+  g_err.clear();
+  if (check_grid(g, precision) != MOLT_OK || batch < 1 || (axis != 0 && axis != 1)) return 0;
+  if (axis == 0 || g->ny == 1) return 256;
+  const size_t esz = precision == MOLT_F64 ? 8 : 4;
+  return al256(ypass_tot_elems(precision, g->ny, g->nx, (int)batch) * esz) + al256((size_t)2 * g->nx * batch * esz) +
+         al256((size_t)g->nx * g->ny * batch * esz);
+}
+
+int32_t mol_t_helmholtz_sweep(const molt_grid* g, int32_t axis, double alpha, int32_t precision, const void* d_in,
+                              void* d_out, int64_t batch, void* d_work, size_t work_bytes, void* stream) {
+  g_err.clear();
+  int32_t rc = check_grid(g, precision);
+  if (rc != MOLT_OK) return rc;
+  if (axis != 0 && axis != 1) return fail(MOLT_EINVAL, "axis must be 0 or 1");
+  if (!(alpha > 0) || !isfinite(alpha)) return fail(MOLT_EINVAL, "alpha must be positive");
+  if (batch < 1 || batch > 65535) return fail(MOLT_EINVAL, "batch must be in 1..65535");
+  if (!d_in || !d_out) return fail(MOLT_EINVAL, "NULL field pointer");
+  hipStream_t s = (hipStream_t)stream;
+  const size_t n = (size_t)g->nx * g->ny;
+  const size_t esz = precision == MOLT_F64 ? 8 : 4;
+  PassArgs a;
+  memset(&a, 0, sizeof(a));
+  a.in[0] = d_in;
+  a.out[0] = d_out;
+  if (axis == 0) {
+    const double hx = spacing(g->bc, g->nx, g->x0, g->x1);
+    const LineCoef c = make_line(g->nx, g->bc, g->order_M, alpha, hx);
+    const long long nlines = (long long)g->ny * batch;
+    if (nlines > 0x7fffffffLL) return fail(MOLT_EUNSUPPORTED, "too many lines");
+    HIPCHK(launch_xpass(precision, PROG_SWEEP, c, a, nullptr, (int)nlines, 0, s));
+    return MOLT_OK;
+  }
+  if (g->ny == 1) {  // y-direction of a 1D problem: identity
+    if (d_in != d_out) HIPCHK(hipMemcpyAsync(d_out, d_in, n * esz * batch, hipMemcpyDeviceToDevice, s));
+    return MOLT_OK;
+  }
+  const size_t need = molt_sweep_workspace_bytes(g, axis, precision, batch);
+  if (!d_work || work_bytes < need) return fail(MOLT_EWORKSPACE, "workspace smaller than molt_sweep_workspace_bytes()");
+  char* w = (char*)d_work;
+  void* tot = w;
+  void* jln = w + al256(ypass_tot_elems(precision, g->ny, g->nx, (int)batch) * esz);
+  void* cpy = (char*)jln + al256((size_t)2 * g->nx * batch * esz);
+  if (d_in == d_out) {  // neighbouring segments read each other's rows: sweep from a copy
+    HIPCHK(launch_copy(precision, cpy, d_in, n * batch, s));
+    a.in[0] = cpy;
+  }
+  const double hy = spacing(g->bc, g->ny, g->y0, g->y1);
+  const LineCoef c = make_line(g->ny, g->bc, g->order_M, alpha, hy);
+  HIPCHK(launch_ypass(precision, PROG_SWEEP, c, a, nullptr, g->nx, (int)batch, tot, jln, s));
+  return MOLT_OK;
+}
+
+size_t ch_workspace_bytes(const molt_grid* g, const molt_ch_params* p) {
+  g_err.clear();
+  if (check_params(p) != MOLT_OK || check_grid(g, p->precision) != MOLT_OK) return 0;
+  return ch_layout(g, p->precision).total;
+}
+
+int32_t ch_step(const molt_grid* g, const molt_ch_params* p, void* d_u, void* d_u_prev, void* d_work,
+                size_t work_bytes, molt_step_info* info, void* stream) {
+  g_err.clear();
+  int32_t rc = check_params(p);
+  if (rc != MOLT_OK) return rc;
+  rc = check_grid(g, p->precision);
+  if (rc != MOLT_OK) return rc;
+  if (!d_u) return fail(MOLT_EINVAL, "d_u is NULL");
+  const bool bdf2 = p->stepper == MOLT_BDF2 && p->have_prev && d_u_prev != nullptr;
+  return step_impl(g, p, d_u, d_u_prev, bdf2, d_work, work_bytes, info, (hipStream_t)stream, 0);
+}
+
+int32_t ch_solve(const molt_grid* g, const molt_ch_params* p, void* d_u, int64_t nsteps, void* d_work,
+                 size_t work_bytes, molt_step_info* per_step, void* stream) {
+  g_err.clear();
+  int32_t rc = check_params(p);
+  if (rc != MOLT_OK) return rc;
+  rc = check_grid(g, p->precision);
+  if (rc != MOLT_OK) return rc;
+  if (!d_u || nsteps < 0) return fail(MOLT_EINVAL, "d_u is NULL or nsteps < 0");
+  const Layout L = ch_layout(g, p->precision);
+  if (!d_work || work_bytes < L.total) return fail(MOLT_EWORKSPACE, "workspace smaller than ch_workspace_bytes()");
+  void* hist = (char*)d_work + L.fld[F_HIST];
+  int32_t status = MOLT_OK;
+  int hint = 0;
+  for (int64_t k = 0; k < nsteps; ++k) {
+    const bool bdf2 = p->stepper == MOLT_BDF2 && k > 0;
+    molt_step_info inf;
+    rc = step_impl(g, p, d_u, p->stepper == MOLT_BDF2 ? hist : nullptr, bdf2, d_work, work_bytes, &inf,
+                   (hipStream_t)stream, hint);
+    if (rc < 0) return rc;
+    if (rc == MOLT_NOT_CONVERGED) status = MOLT_NOT_CONVERGED;
+    hint = inf.iters;
+    if (per_step) per_step[k] = inf;
+  }
+  return status;
+}
+
+}  // extern "C"

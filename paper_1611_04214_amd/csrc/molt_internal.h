@@ -1,0 +1,74 @@
+// molt_internal.h -- types shared by the host driver and the HIP kernels of
+// libmolt (not part of the public ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "molt.h"
+
+namespace molt {
+
+constexpr int kMaxM = 6;
+
+// Coefficients of one line inverse L^{-1} = (I - d^2/alpha^2)^{-1} along one
+// axis (Sec. 3.2), built in FP64 on the host.
+//  - wl/wr: weights of the centred (M+1)-point stencils of J^L_j and J^R_j,
+//    index i <-> node j + i - M/2 (kernel alpha*exp, so the particular
+//    solution is (IL + IR)/2).
+//  - Non-periodic lines use the same centred stencil with ghost values beyond
+//    each end, extrapolated by the degree-M polynomial through the M+1 end
+//    nodes; a centred window that leaves the line then interpolates exactly
+//    the polynomial of the nearest in-range window, which is the boundary
+//    treatment of the oracle.  ghostL[g-1][i]: weight of node i (0..M) for the
+//    value at node -g; ghostR[g-1][i]: weight of node n-1-M+i for node n-1+g.
+struct LineCoef {
+  int32_t n;    // nodes per line
+  int32_t N;    // cells per line (n periodic, n-1 otherwise)
+  int32_t bc;   // MOLT_BC_*
+  int32_t M;    // stencil order
+  double nu;    // alpha*h
+  double d;     // exp(-nu)
+  double mu;    // exp(-nu*N)
+  double wl[kMaxM + 1];
+  double wr[kMaxM + 1];
+  double ghostL[kMaxM / 2][kMaxM + 1];
+  double ghostR[kMaxM / 2][kMaxM + 1];
+};
+
+// Fixed-point iteration control kept on the device so that queued
+// iterations after convergence become no-ops (no host round trip per
+// iteration).
+struct DevState {
+  unsigned long long resid_bits;  // atomicMax of the FP64 bits of max|delta| (>= 0)
+  unsigned int blocks_done;       // last-block counter of the residual kernel
+  int done;                       // 1: converged or max_iter reached
+  int iters;                      // iterations completed in this step
+  int max_iter;
+  int fixed;                      // >0: never stop early
+  int pad0;
+  double tol;
+  double last_resid;
+  double mass, energy;
+};
+
+// Arguments of the pass kernels (pointers are device pointers of element type T,
+// passed as void* so one struct serves both precisions).
+struct PassArgs {
+  const void* in[6];
+  void* out[3];
+  double sigma;    // linear part of f moved to the left-hand side
+  double kappa;    // a/s1
+  int mode;        // 0: full form (first iteration), 1: increment form
+  int bdf2;        // rhs program: 1 -> (4u - u_prev)/3
+};
+
+// Optional per-kernel timing with HIP events on the launch stream (off unless
+// molt_profile(1) was called).  kind = family * 8 + program.
+enum KernelFamily { KF_XPASS = 0, KF_YTOT = 1, KF_YCOMB = 2, KF_YFIN = 3, KF_POINTWISE = 4, KF_OTHER = 5 };
+constexpr int kProfKinds = 48;
+void prof_begin(int kind, hipStream_t s);
+void prof_end(int kind, hipStream_t s);
+extern bool g_prof_on;
+
+}  // namespace molt

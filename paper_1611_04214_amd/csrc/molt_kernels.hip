@@ -1,0 +1,987 @@
+// molt_kernels.hip -- HIP kernels (gfx950 / CDNA4) of the MOL^T Cahn-Hilliard
+// hot path: the line inverse L^{-1} = (I - d^2/alpha^2)^{-1} of Sec. 3.2 along
+// x-lines and y-lines, fused with the pointwise work of the fixed-point
+// iteration of Sec. 5.1.
+//
+// One line inverse, for nodes j = 0..n-1 with J^L_j, J^R_j the order-M local
+// quadratures (centred stencils; J^L_0 = 0, and J^R_{n-1} = 0 when the line is
+// not periodic):
+//   S^L_j = d S^L_{j-1} + J^L_j,   S^R_j = d S^R_{j+1} + J^R_j        (eqs. IL, IR)
+//   w_j   = (S^L_j + S^R_j)/2 + B_a d^j + B_b d^{N-j}                 (eq. L_Inverse)
+// with B_a, B_b from the boundary 2x2 solve (FP64).  The recurrences are
+// evaluated as a parallel scan: each thread owns K consecutive nodes, first
+// computes its zero-seeded totals, the carries between threads are combined
+// (wave shuffles + LDS along x, a per-column FP64 combine kernel along y), and
+// a second seeded scan gives the final values.  The boundary terms are folded
+// into the seeds: Z^L_j = S^L_j + 2 B_a d^j satisfies the same recurrence, so a
+// thread starting at node j0 seeds its scan with d*carry + 2 B_a d^{j0}.
+//
+// Pass "programs" define the pointwise work around the sweeps: what is swept
+// (sin), what is kept per node (ext) and how outputs are formed (fin).
+#include <math.h>
+#include <stdint.h>
+
+#include "molt_internal.h"
+
+namespace molt {
+
+// --------------------------------------------------------------------------
+// small helpers
+// --------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T dpow(double nu, double e);
+template <>
+__device__ __forceinline__ float dpow<float>(double nu, double e) {
+  return __expf(-(float)(nu * e));
+}
+template <>
+__device__ __forceinline__ double dpow<double>(double nu, double e) {
+  return exp(-nu * e);
+}
+
+__device__ __forceinline__ int wrapi(int j, int n) {
+  int r = j % n;
+  return r < 0 ? r + n : r;
+}
+
+// --------------------------------------------------------------------------
+// pass programs
+//   F: number of fields swept, E: per-node values kept for the output.
+//   sin(a, i, s):  sweep inputs at element i
+//   ext(a, i, e):  kept values at element i (owned nodes only)
+//   fin(a, i, w, e): outputs at element i from the swept values w; returns
+//                  the node's contribution to the residual max.
+// The iteration works in u (= v - 1): every linear operator of the scheme
+// maps constants to themselves (L^{-1}[1] = 1) or to zero (D, C1), so the
+// shift only changes the reaction: g = f(v) - sigma v = u^3 - (1+sigma) u - sigma,
+// and the constant drops out of C1 g.
+// --------------------------------------------------------------------------
+enum ProgId { PROG_SWEEP = 0, PROG_RHS = 1, PROG_P1 = 2, PROG_P2 = 3, PROG_P3 = 4, PROG_P4 = 5 };
+
+template <typename T>
+struct ProgSweep {  // w = L^{-1} in0
+  static constexpr int F = 1, E = 0;
+  __device__ static void sin(const PassArgs& a, size_t i, T* s) { s[0] = ((const T*)a.in[0])[i]; }
+  __device__ static void ext(const PassArgs&, size_t, T*) {}
+  __device__ static double fin(const PassArgs& a, size_t i, const T* w, const T*) {
+    ((T*)a.out[0])[i] = w[0];
+    return 0.0;
+  }
+};
+
+template <typename T>
+struct ProgRhs {  // w = L^{-1} rhs, rhs = u^n (BE) or (4u^n - u^{n-1})/3 (BDF2)
+  static constexpr int F = 1, E = 0;
+  __device__ static void sin(const PassArgs& a, size_t i, T* s) {
+    T u = ((const T*)a.in[0])[i];
+    if (a.bdf2) {
+      T up = ((const T*)a.in[1])[i];
+      s[0] = (T(4) * u - up) * T(1.0 / 3.0);
+    } else {
+      s[0] = u;
+    }
+  }
+  __device__ static void ext(const PassArgs&, size_t, T*) {}
+  __device__ static double fin(const PassArgs& a, size_t i, const T* w, const T*) {
+    ((T*)a.out[0])[i] = w[0];
+    return 0.0;
+  }
+};
+
+// reaction part and linear part of the current iterate
+//  full form:      e = g(u) (constant dropped), lin = u
+//  increment form: e = g(p) - g(q) = dl*(p^2 + p q + q^2 - 1 - sigma), lin = dl,
+//                  p = base + W (current iterate), q = p - dl (previous)
+template <typename T>
+__device__ __forceinline__ void react_lin(const PassArgs& a, size_t i, const T* base, const T* W,
+                                          const T* dl, T& e, T& lin) {
+  const T sg = (T)a.sigma;
+  if (a.mode == 0) {
+    T u = base[i];
+    e = u * u * u - (T(1) + sg) * u;
+    lin = u;
+  } else {
+    T p = base[i] + W[i];
+    T d = dl[i];
+    T q = p - d;
+    e = d * (p * p + p * q + q * q - T(1) - sg);
+    lin = d;
+  }
+}
+
+template <typename T>
+struct ProgP1 {  // y, alpha1: a1 = Y1 e, b1 = Y1 lin
+  static constexpr int F = 2, E = 0;
+  __device__ static void sin(const PassArgs& a, size_t i, T* s) {
+    react_lin<T>(a, i, (const T*)a.in[0], (const T*)a.in[1], (const T*)a.in[2], s[0], s[1]);
+  }
+  __device__ static void ext(const PassArgs&, size_t, T*) {}
+  __device__ static double fin(const PassArgs& a, size_t i, const T* w, const T*) {
+    ((T*)a.out[0])[i] = w[0];
+    ((T*)a.out[1])[i] = w[1];
+    return 0.0;
+  }
+};
+
+template <typename T>
+struct ProgP2 {  // x, alpha1: C = X1(2 a1 - e) - a1, q = b1 + X1(lin - b1)
+  static constexpr int F = 2, E = 2;
+  __device__ static void sin(const PassArgs& a, size_t i, T* s) {
+    T e, lin;
+    react_lin<T>(a, i, (const T*)a.in[2], (const T*)a.in[3], (const T*)a.in[4], e, lin);
+    T a1 = ((const T*)a.in[0])[i], b1 = ((const T*)a.in[1])[i];
+    s[0] = T(2) * a1 - e;
+    s[1] = lin - b1;
+  }
+  __device__ static void ext(const PassArgs& a, size_t i, T* x) {
+    x[0] = ((const T*)a.in[0])[i];
+    x[1] = ((const T*)a.in[1])[i];
+  }
+  __device__ static double fin(const PassArgs& a, size_t i, const T* w, const T* x) {
+    ((T*)a.out[0])[i] = w[0] - x[0];
+    ((T*)a.out[1])[i] = x[1] + w[1];
+    return 0.0;
+  }
+};
+
+template <typename T>
+struct ProgP3 {  // y, alpha2: m = Y2(q + kappa C) - q, n = Y2 q
+  static constexpr int F = 2, E = 1;
+  __device__ static void sin(const PassArgs& a, size_t i, T* s) {
+    T C = ((const T*)a.in[0])[i], q = ((const T*)a.in[1])[i];
+    s[0] = q + (T)a.kappa * C;
+    s[1] = q;
+  }
+  __device__ static void ext(const PassArgs& a, size_t i, T* x) { x[0] = ((const T*)a.in[1])[i]; }
+  __device__ static double fin(const PassArgs& a, size_t i, const T* w, const T* x) {
+    ((T*)a.out[0])[i] = w[0] - x[0];
+    ((T*)a.out[1])[i] = w[1];
+    return 0.0;
+  }
+};
+
+template <typename T>
+struct ProgP4 {  // x, alpha2: dl' = (dl | R) + X2 m - n ; W' = W + dl' (| dl')
+  static constexpr int F = 1, E = 3;
+  __device__ static void sin(const PassArgs& a, size_t i, T* s) { s[0] = ((const T*)a.in[0])[i]; }
+  __device__ static void ext(const PassArgs& a, size_t i, T* x) {
+    x[0] = ((const T*)a.in[1])[i];
+    x[1] = ((const T*)a.in[2])[i];
+    x[2] = a.mode ? ((const T*)a.in[3])[i] : T(0);
+  }
+  __device__ static double fin(const PassArgs& a, size_t i, const T* w, const T* x) {
+    T dn = x[1] + w[0] - x[0];
+    ((T*)a.out[0])[i] = dn;
+    ((T*)a.out[1])[i] = x[2] + dn;
+    return fabs((double)dn);
+  }
+};
+
+template <int P, typename T>
+struct ProgOf;
+template <typename T> struct ProgOf<PROG_SWEEP, T> { using type = ProgSweep<T>; };
+template <typename T> struct ProgOf<PROG_RHS, T> { using type = ProgRhs<T>; };
+template <typename T> struct ProgOf<PROG_P1, T> { using type = ProgP1<T>; };
+template <typename T> struct ProgOf<PROG_P2, T> { using type = ProgP2<T>; };
+template <typename T> struct ProgOf<PROG_P3, T> { using type = ProgP3<T>; };
+template <typename T> struct ProgOf<PROG_P4, T> { using type = ProgP4<T>; };
+
+// --------------------------------------------------------------------------
+// Per-thread line segment: sweep inputs on nodes j0-H .. j0+K+H-1, the two
+// local quadratures on the K owned nodes, zero-seeded totals and the final
+// seeded scans.  `stride` is the element distance between consecutive nodes
+// of the line (1 along x, nx along y); `lbase` the element index of node 0.
+// --------------------------------------------------------------------------
+template <typename T, class P, int K, int M>
+struct Seg {
+  static constexpr int H = M / 2, F = P::F, W = K + 2 * H;
+  T JL[F][K], JR[F][K];
+  T jln[F];  // periodic: J^L of the cell ending at node n (= node 0)
+
+  __device__ void build(const LineCoef& c, const PassArgs& a, size_t lbase, size_t stride, int j0) {
+    const int n = c.n;
+    const bool per = c.bc == MOLT_BC_PERIODIC;
+    T s[F][W];
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+      int j = j0 - H + k;
+      int jj = per ? wrapi(j, n) : min(max(j, 0), n - 1);
+      T v[F];
+      P::sin(a, lbase + (size_t)jj * stride, v);
+#pragma unroll
+      for (int f = 0; f < F; ++f) s[f][k] = v[f];
+    }
+    T wl[M + 1], wr[M + 1];
+#pragma unroll
+    for (int i = 0; i <= M; ++i) {
+      wl[i] = (T)c.wl[i];
+      wr[i] = (T)c.wr[i];
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int j = j0 + k;
+      const bool real = j < n;
+#pragma unroll
+      for (int f = 0; f < F; ++f) {
+        T l = T(0), r = T(0);
+#pragma unroll
+        for (int i = 0; i <= M; ++i) {
+          l += wl[i] * s[f][k + i];
+          r += wr[i] * s[f][k + i];
+        }
+        if (k == 0) jln[f] = l;
+        JL[f][k] = (real && j != 0) ? l : T(0);
+        JR[f][k] = (real && (per || j != n - 1)) ? r : T(0);
+      }
+    }
+    if (!per && (j0 < H || j0 + K + H > n)) boundary_nodes(c, a, lbase, stride, j0, s);
+  }
+
+  // Nodes whose centred window leaves a non-periodic line (j < H or j > n-1-H).
+  // The window is completed by ghost values extrapolated with the degree-M
+  // polynomial through the M+1 end nodes; the extrapolation weights are large
+  // (up to ~2800 for M=6), so the ghosts and these few stencils are formed in
+  // FP64 and only the result is rounded to T.
+  __device__ void boundary_nodes(const LineCoef& c, const PassArgs& a, size_t lbase, size_t stride, int j0,
+                                 const T (&s)[F][W]) {
+    const int n = c.n;
+    double gl[F][H], gr[F][H];
+#pragma unroll
+    for (int f = 0; f < F; ++f)
+#pragma unroll
+      for (int g = 0; g < H; ++g) gl[f][g] = gr[f][g] = 0.0;
+    if (j0 < H) {
+      double e[F][M + 1];
+#pragma unroll
+      for (int i = 0; i <= M; ++i) {
+        T v[F];
+        P::sin(a, lbase + (size_t)i * stride, v);
+#pragma unroll
+        for (int f = 0; f < F; ++f) e[f][i] = (double)v[f];
+      }
+#pragma unroll
+      for (int f = 0; f < F; ++f)
+#pragma unroll
+        for (int g = 0; g < H; ++g) {
+          double acc = 0.0;
+#pragma unroll
+          for (int i = 0; i <= M; ++i) acc += c.ghostL[g][i] * e[f][i];
+          gl[f][g] = acc;
+        }
+    }
+    if (j0 + K + H > n) {
+      double e[F][M + 1];
+#pragma unroll
+      for (int i = 0; i <= M; ++i) {
+        T v[F];
+        P::sin(a, lbase + (size_t)(n - 1 - M + i) * stride, v);
+#pragma unroll
+        for (int f = 0; f < F; ++f) e[f][i] = (double)v[f];
+      }
+#pragma unroll
+      for (int f = 0; f < F; ++f)
+#pragma unroll
+        for (int g = 0; g < H; ++g) {
+          double acc = 0.0;
+#pragma unroll
+          for (int i = 0; i <= M; ++i) acc += c.ghostR[g][i] * e[f][i];
+          gr[f][g] = acc;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int j = j0 + k;
+      if (j < n && (j < H || j > n - 1 - H)) {
+#pragma unroll
+        for (int f = 0; f < F; ++f) {
+          double l = 0.0, r = 0.0;
+#pragma unroll
+          for (int i = 0; i <= M; ++i) {
+            const int jw = j - H + i;
+            double v = (double)s[f][k + i];
+#pragma unroll
+            for (int g = 1; g <= H; ++g) {
+              v = (jw == -g) ? gl[f][g - 1] : v;
+              v = (jw == n - 1 + g) ? gr[f][g - 1] : v;
+            }
+            l += c.wl[i] * v;
+            r += c.wr[i] * v;
+          }
+          JL[f][k] = (j != 0) ? (T)l : T(0);
+          JR[f][k] = (j != n - 1) ? (T)r : T(0);
+        }
+      }
+    }
+  }
+
+  // zero-seeded totals: AL at the thread's last real node, AR at its first node
+  __device__ void totals(T d, int j0, int n, T* AL, T* AR) const {
+    const int jlast = min(j0 + K - 1, n - 1);
+#pragma unroll
+    for (int f = 0; f < F; ++f) {
+      T x = T(0), xl = T(0);
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        x = d * x + JL[f][k];
+        if (j0 + k == jlast) xl = x;
+      }
+      AL[f] = xl;
+      T y = T(0);
+#pragma unroll
+      for (int k = K - 1; k >= 0; --k) y = d * y + JR[f][k];
+      AR[f] = y;
+    }
+  }
+
+  // seeded scans; w[f][k] = (Z^L + Z^R)/2
+  __device__ void finalize(T d, int j0, int n, const T* gL, const T* gR, T (&w)[F][K]) const {
+    const int jlast = min(j0 + K - 1, n - 1);
+#pragma unroll
+    for (int f = 0; f < F; ++f) {
+      T x = T(0);
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        x = (k == 0) ? (JL[f][0] + gL[f]) : (d * x + JL[f][k]);
+        w[f][k] = x;
+      }
+      T y = T(0);
+#pragma unroll
+      for (int k = K - 1; k >= 0; --k) {
+        const int j = j0 + k;
+        y = (j > jlast) ? T(0) : ((j == jlast) ? (JR[f][k] + gR[f]) : (d * y + JR[f][k]));
+        w[f][k] = T(0.5) * (w[f][k] + y);
+      }
+    }
+  }
+};
+
+// Boundary coefficients of one line from its zero-seeded totals (Sec. 3.2).
+//  TLl = S^L_{n-1}, TRl = S^R_0 (zero-seeded), jlnv = J^L of the cell ending at
+//  node N (periodic only).  I_N = IL~_N / 2, I_0 = IR~_0 / 2.
+__device__ __forceinline__ void boundary_terms(const LineCoef& c, double TLl, double TRl, double jlnv,
+                                               double& Ba, double& Bb) {
+  const double d = c.d, mu = c.mu;
+  if (c.bc == MOLT_BC_PERIODIC) {
+    const double IN = 0.5 * (d * TLl + jlnv), I0 = 0.5 * TRl;
+    Ba = IN / (1.0 - mu);
+    Bb = I0 / (1.0 - mu);
+  } else {
+    const double IN = 0.5 * TLl, I0 = 0.5 * TRl;
+    const double den = 1.0 - mu * mu;
+    if (c.bc == MOLT_BC_NEUMANN) {
+      Ba = (I0 + mu * IN) / den;
+      Bb = (IN + mu * I0) / den;
+    } else {
+      Ba = (mu * IN - I0) / den;
+      Bb = (mu * I0 - IN) / den;
+    }
+  }
+}
+
+// residual: block max, one atomicMax per block, last block closes the iteration
+__device__ void residual_close(double r, DevState* st) {
+  __shared__ double red[4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) r = fmax(r, __shfl_down(r, off));
+  if (lane == 0) red[wave] = r;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double b = red[0];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) b = fmax(b, red[w]);
+    atomicMax(&st->resid_bits, (unsigned long long)__double_as_longlong(b));
+    __threadfence();
+    unsigned int prev = atomicAdd(&st->blocks_done, 1u);
+    if (prev == gridDim.x * gridDim.y * gridDim.z - 1) {
+      __threadfence();
+      unsigned long long bits = atomicAdd(&st->resid_bits, 0ull);
+      double res = __longlong_as_double((long long)bits);
+      int it = st->iters + 1;
+      st->iters = it;
+      st->last_resid = res;
+      if (st->fixed > 0) {
+        if (it >= st->fixed) st->done = 1;
+      } else if (res < st->tol || it >= st->max_iter) {
+        st->done = 1;
+      }
+      atomicExch(&st->resid_bits, 0ull);
+      atomicExch(&st->blocks_done, 0u);
+      __threadfence();
+    }
+  }
+}
+
+// --------------------------------------------------------------------------
+// x-direction pass: rows are contiguous; TL threads (a multiple of 64) own one
+// row, 256/TL rows per 256-thread block.
+// --------------------------------------------------------------------------
+template <typename T, int PI, int K, int M>
+__global__ void __launch_bounds__(256) xpass_kernel(const LineCoef c, const PassArgs a, DevState* st,
+                                                    int nlines, int TL, int doresid) {
+  using P = typename ProgOf<PI, T>::type;
+  constexpr int F = P::F, E = P::E;
+  if (st != nullptr && st->done) return;
+  __shared__ T sh_tot[F][2][4];
+  __shared__ double sh_line[4][F][3];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int lil = tid / TL;
+  const int t = tid - lil * TL;
+  const int wl0 = lil * (TL >> 6);
+  const int line = blockIdx.x * (256 / TL) + lil;
+  const bool act = line < nlines;
+  const int n = c.n;
+  const int j0 = t * K;
+  const bool has = act && j0 < n;
+  const size_t lbase = (size_t)(act ? line : 0) * (size_t)n;
+  const T d = (T)c.d;
+
+  Seg<T, P, K, M> seg;
+  T ex[E > 0 ? E : 1][K];
+  T AL[F], AR[F];
+  if (has) {
+    seg.build(c, a, lbase, 1, j0);
+    if constexpr (E > 0) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        T x[E > 0 ? E : 1];
+        P::ext(a, lbase + (size_t)min(j0 + k, n - 1), x);
+#pragma unroll
+        for (int e = 0; e < E; ++e) ex[e][k] = x[e];
+      }
+    }
+    seg.totals(d, j0, n, AL, AR);
+  } else {
+#pragma unroll
+    for (int f = 0; f < F; ++f) {
+      AL[f] = T(0);
+      AR[f] = T(0);
+      seg.jln[f] = T(0);
+    }
+  }
+
+  // carries between threads of the line: multiplier m = d^K per thread
+  const T m = dpow<T>(c.nu, (double)K);
+  T mp[6];
+  mp[0] = m;
+#pragma unroll
+  for (int s = 1; s < 6; ++s) mp[s] = mp[s - 1] * mp[s - 1];
+  const T m64 = mp[5] * mp[5];
+  T exL[F], exR[F];
+#pragma unroll
+  for (int f = 0; f < F; ++f) {
+    T xL = AL[f], xR = AR[f];
+#pragma unroll
+    for (int s = 0; s < 6; ++s) {
+      const int off = 1 << s;
+      T yL = __shfl_up(xL, off);
+      T yR = __shfl_down(xR, off);
+      if (lane >= off) xL += mp[s] * yL;
+      if (lane + off < 64) xR += mp[s] * yR;
+    }
+    T eL = __shfl_up(xL, 1);
+    T eR = __shfl_down(xR, 1);
+    exL[f] = lane == 0 ? T(0) : eL;
+    exR[f] = lane == 63 ? T(0) : eR;
+    if (lane == 63) sh_tot[f][0][wave] = xL;
+    if (lane == 0) sh_tot[f][1][wave] = xR;
+  }
+  __syncthreads();
+  const int nw = TL >> 6, wv = t >> 6;
+  const T mlane = dpow<T>(c.nu, (double)K * lane);
+  const T mlane_r = dpow<T>(c.nu, (double)K * (63 - lane));
+  T cL[F], cR[F];
+#pragma unroll
+  for (int f = 0; f < F; ++f) {
+    T CL = T(0), CR = T(0);
+    for (int w = 0; w < wv; ++w) CL = m64 * CL + sh_tot[f][0][wl0 + w];
+    for (int w = nw - 1; w > wv; --w) CR = m64 * CR + sh_tot[f][1][wl0 + w];
+    cL[f] = exL[f] + mlane * CL;
+    cR[f] = exR[f] + mlane_r * CR;
+  }
+  // line totals for the boundary solve
+  const int tstar = (n - 1) / K;
+  if (act && t == tstar) {
+    const T dk = dpow<T>(c.nu, (double)(n - 1 - tstar * K + 1));
+#pragma unroll
+    for (int f = 0; f < F; ++f) sh_line[lil][f][0] = (double)AL[f] + (double)dk * (double)cL[f];
+  }
+  if (act && t == 0) {
+#pragma unroll
+    for (int f = 0; f < F; ++f) {
+      sh_line[lil][f][1] = (double)AR[f] + (double)m * (double)cR[f];
+      sh_line[lil][f][2] = (double)seg.jln[f];
+    }
+  }
+  __syncthreads();
+
+  double resid = 0.0;
+  if (has) {
+    const int jlast = min(j0 + K - 1, n - 1);
+    const double pL = exp(-c.nu * (double)j0);
+    const double pR = exp(-c.nu * (double)(c.N - jlast));
+    T gL[F], gR[F];
+#pragma unroll
+    for (int f = 0; f < F; ++f) {
+      double Ba, Bb;
+      boundary_terms(c, sh_line[lil][f][0], sh_line[lil][f][1], sh_line[lil][f][2], Ba, Bb);
+      gL[f] = (T)(c.d * (double)cL[f] + 2.0 * Ba * pL);
+      gR[f] = (T)(c.d * (double)cR[f] + 2.0 * Bb * pR);
+    }
+    T w[F][K];
+    seg.finalize(d, j0, n, gL, gR, w);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      if (j0 + k < n) {
+        T wk[F], xk[E > 0 ? E : 1];
+#pragma unroll
+        for (int f = 0; f < F; ++f) wk[f] = w[f][k];
+#pragma unroll
+        for (int e = 0; e < E; ++e) xk[e] = ex[e][k];
+        resid = fmax(resid, P::fin(a, lbase + (size_t)(j0 + k), wk, xk));
+      }
+    }
+  }
+  if (doresid) residual_close(resid, st);
+}
+
+// --------------------------------------------------------------------------
+// y-direction pass.  Block = 64 consecutive columns (one wave wide: every row
+// access is a coalesced 64-element segment) x RG thread rows; thread (col, t)
+// owns rows t*K .. t*K+K-1 of its column.  Three kernels:
+//  ytot: zero-seeded totals per thread -> tot[f][dir][t][col]
+//  ycomb: per column, FP64 exclusive scans over threads, line totals, the
+//         boundary solve and the seeds, written over tot
+//  yfin: seeded scans and the program outputs
+// --------------------------------------------------------------------------
+constexpr int kRG = 4;
+
+template <typename T, int PI, int K, int M>
+__global__ void __launch_bounds__(256) ytot_kernel(const LineCoef c, const PassArgs a, DevState* st, int nx,
+                                                   int nth, size_t fstride, T* tot, T* jlnb) {
+  using P = typename ProgOf<PI, T>::type;
+  constexpr int F = P::F;
+  if (st != nullptr && st->done) return;
+  const int col = blockIdx.x * 64 + threadIdx.x;
+  const int t = blockIdx.y * kRG + threadIdx.y;
+  const int b = blockIdx.z;
+  if (col >= nx || t >= nth) return;
+  const int n = c.n, j0 = t * K;
+  const size_t lbase = (size_t)b * fstride + (size_t)col;
+  Seg<T, P, K, M> seg;
+  seg.build(c, a, lbase, (size_t)nx, j0);
+  T AL[F], AR[F];
+  seg.totals((T)c.d, j0, n, AL, AR);
+  T* tb = tot + (size_t)b * (size_t)(F * 2) * nth * nx;
+#pragma unroll
+  for (int f = 0; f < F; ++f) {
+    tb[((size_t)(f * 2 + 0) * nth + t) * nx + col] = AL[f];
+    tb[((size_t)(f * 2 + 1) * nth + t) * nx + col] = AR[f];
+  }
+  if (t == 0) {
+#pragma unroll
+    for (int f = 0; f < F; ++f) jlnb[((size_t)b * F + f) * nx + col] = seg.jln[f];
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) ycomb_kernel(const LineCoef c, DevState* st, int nx, int nth, int K, int F,
+                                                    int batch, T* tot, const T* jlnb) {
+  if (st != nullptr && st->done) return;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nx * F * batch) return;
+  const int col = idx % nx;
+  const int f = (idx / nx) % F;
+  const int b = idx / (nx * F);
+  const int n = c.n;
+  T* tb = tot + (size_t)b * (size_t)(F * 2) * nth * nx;
+  T* AL = tb + (size_t)(f * 2 + 0) * nth * nx + col;
+  T* AR = tb + (size_t)(f * 2 + 1) * nth * nx + col;
+  const double d = c.d, m = exp(-c.nu * (double)K);
+  const int tstar = (n - 1) / K;
+  double cl = 0.0, TLl = 0.0;
+  for (int t = 0; t < nth; ++t) {
+    const double v = (double)AL[(size_t)t * nx];
+    if (t == tstar) TLl = v + exp(-c.nu * (double)(n - 1 - tstar * K + 1)) * cl;
+    cl = m * cl + v;
+  }
+  double cr = 0.0, TRl = 0.0;
+  for (int t = nth - 1; t >= 0; --t) {
+    const double v = (double)AR[(size_t)t * nx];
+    if (t == 0) TRl = v + m * cr;
+    cr = m * cr + v;
+  }
+  double Ba, Bb;
+  boundary_terms(c, TLl, TRl, (double)jlnb[((size_t)b * F + f) * nx + col], Ba, Bb);
+  cl = 0.0;
+  for (int t = 0; t < nth; ++t) {
+    const double v = (double)AL[(size_t)t * nx];
+    AL[(size_t)t * nx] = (T)(d * cl + 2.0 * Ba * exp(-c.nu * (double)(t * K)));
+    cl = m * cl + v;
+  }
+  cr = 0.0;
+  for (int t = nth - 1; t >= 0; --t) {
+    const double v = (double)AR[(size_t)t * nx];
+    const int jlast = min(t * K + K - 1, n - 1);
+    AR[(size_t)t * nx] = (T)(d * cr + 2.0 * Bb * exp(-c.nu * (double)(c.N - jlast)));
+    cr = m * cr + v;
+  }
+}
+
+template <typename T, int PI, int K, int M>
+__global__ void __launch_bounds__(256) yfin_kernel(const LineCoef c, const PassArgs a, DevState* st, int nx,
+                                                   int nth, size_t fstride, const T* seeds) {
+  using P = typename ProgOf<PI, T>::type;
+  constexpr int F = P::F, E = P::E;
+  if (st != nullptr && st->done) return;
+  const int col = blockIdx.x * 64 + threadIdx.x;
+  const int t = blockIdx.y * kRG + threadIdx.y;
+  const int b = blockIdx.z;
+  if (col >= nx || t >= nth) return;
+  const int n = c.n, j0 = t * K;
+  const size_t lbase = (size_t)b * fstride + (size_t)col;
+  Seg<T, P, K, M> seg;
+  seg.build(c, a, lbase, (size_t)nx, j0);
+  const T* sb = seeds + (size_t)b * (size_t)(F * 2) * nth * nx;
+  T gL[F], gR[F];
+#pragma unroll
+  for (int f = 0; f < F; ++f) {
+    gL[f] = sb[((size_t)(f * 2 + 0) * nth + t) * nx + col];
+    gR[f] = sb[((size_t)(f * 2 + 1) * nth + t) * nx + col];
+  }
+  T w[F][K];
+  seg.finalize((T)c.d, j0, n, gL, gR, w);
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int j = j0 + k;
+    if (j < n) {
+      const size_t i = lbase + (size_t)j * nx;
+      T wk[F], xk[E > 0 ? E : 1];
+#pragma unroll
+      for (int f = 0; f < F; ++f) wk[f] = w[f][k];
+      if constexpr (E > 0) P::ext(a, i, xk);
+      P::fin(a, i, wk, xk);
+    }
+  }
+}
+
+// pointwise program with the identity in place of the sweep (the y-direction
+// of a one-dimensional problem)
+template <typename T, int PI>
+__global__ void __launch_bounds__(256) pointwise_kernel(const PassArgs a, DevState* st, size_t nelem) {
+  using P = typename ProgOf<PI, T>::type;
+  constexpr int F = P::F, E = P::E;
+  if (st != nullptr && st->done) return;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < nelem; i += (size_t)gridDim.x * blockDim.x) {
+    T s[F], x[E > 0 ? E : 1];
+    P::sin(a, i, s);
+    if constexpr (E > 0) P::ext(a, i, x);
+    P::fin(a, i, s, x);
+  }
+}
+
+// --------------------------------------------------------------------------
+// step bookkeeping
+// --------------------------------------------------------------------------
+__global__ void state_init_kernel(DevState* st, double tol, int max_iter, int fixed) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    st->resid_bits = 0ull;
+    st->blocks_done = 0u;
+    st->done = 0;
+    st->iters = 0;
+    st->max_iter = max_iter;
+    st->fixed = fixed;
+    st->pad0 = 0;
+    st->tol = tol;
+    st->last_resid = 0.0;
+    st->mass = 0.0;
+    st->energy = 0.0;
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) copy_kernel(T* dst, const T* src, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
+// u^{n+1} = base + W
+template <typename T>
+__global__ void __launch_bounds__(256) finalize_kernel(T* u, const T* base, const T* W, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    u[i] = base[i] + W[i];
+}
+
+// FP64 mass and energy partial sums (fixed grid, fixed order: deterministic)
+template <typename T>
+__global__ void __launch_bounds__(256) diag_kernel(const T* u, int nx, int ny, int bc, double hx, double hy,
+                                                   double eps, double* partials) {
+  __shared__ double sm[2][4];
+  const bool per = bc == MOLT_BC_PERIODIC;
+  double ms = 0.0, en = 0.0;
+  const size_t n = (size_t)nx * ny;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const int ix = (int)(i % nx), iy = (int)(i / nx);
+    const double wx = per ? 1.0 : ((ix == 0 || ix == nx - 1) ? 0.5 : 1.0);
+    const double wy = (ny == 1 || per) ? 1.0 : ((iy == 0 || iy == ny - 1) ? 0.5 : 1.0);
+    const double uu = (double)u[i];
+    ms += wx * wy * uu;
+    const double q = uu * uu - 1.0;
+    en += wx * wy * 0.25 * q * q;
+    if (per || ix < nx - 1) {
+      const double un = (double)u[(size_t)iy * nx + (ix + 1 == nx ? 0 : ix + 1)];
+      const double g = (un - uu) / hx;
+      en += 0.5 * eps * eps * g * g * wy;
+    }
+    if (ny > 1 && (per || iy < ny - 1)) {
+      const double un = (double)u[(size_t)(iy + 1 == ny ? 0 : iy + 1) * nx + ix];
+      const double g = (un - uu) / hy;
+      en += 0.5 * eps * eps * g * g * wx;
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    ms += __shfl_down(ms, off);
+    en += __shfl_down(en, off);
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+    sm[0][wave] = ms;
+    sm[1][wave] = en;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = 0.0, b = 0.0;
+    for (int w = 0; w < 4; ++w) {
+      a += sm[0][w];
+      b += sm[1][w];
+    }
+    partials[2 * blockIdx.x] = a;
+    partials[2 * blockIdx.x + 1] = b;
+  }
+}
+
+__global__ void __launch_bounds__(256) diag_final_kernel(const double* partials, int nblocks, double area,
+                                                         DevState* st) {
+  __shared__ double sm[2][256];
+  double a = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < nblocks; i += blockDim.x) {
+    a += partials[2 * i];
+    b += partials[2 * i + 1];
+  }
+  sm[0][threadIdx.x] = a;
+  sm[1][threadIdx.x] = b;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      sm[0][threadIdx.x] += sm[0][threadIdx.x + s];
+      sm[1][threadIdx.x] += sm[1][threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    st->mass = sm[0][0] * area;
+    st->energy = sm[1][0] * area;
+  }
+}
+
+// --------------------------------------------------------------------------
+// launchers
+// --------------------------------------------------------------------------
+static int pick_kx(int n, int prec) {
+  const int ks[4] = {4, 8, 16, 32};
+  const int kmax = prec == MOLT_F64 ? 16 : 32;
+  for (int i = 0; i < 4; ++i)
+    if (ks[i] <= kmax && n <= 256 * ks[i]) return ks[i];
+  return 0;
+}
+
+int xpass_max_n(int prec) { return prec == MOLT_F64 ? 4096 : 8192; }
+
+template <typename T, int PI, int K>
+static hipError_t xpass_k(const LineCoef& c, const PassArgs& a, DevState* st, int nlines, int doresid, hipStream_t s) {
+  // threads per line: 64, 128 or 256, so that 256/TL rows tile the block exactly
+  const int need = (c.n + K - 1) / K;
+  const int TL = need <= 64 ? 64 : (need <= 128 ? 128 : 256);
+  const int lpb = 256 / TL;
+  dim3 grid((nlines + lpb - 1) / lpb);
+  if (g_prof_on) prof_begin(KF_XPASS * 8 + PI, s);
+  switch (c.M) {
+    case 2: hipLaunchKernelGGL((xpass_kernel<T, PI, K, 2>), grid, dim3(256), 0, s, c, a, st, nlines, TL, doresid); break;
+    case 4: hipLaunchKernelGGL((xpass_kernel<T, PI, K, 4>), grid, dim3(256), 0, s, c, a, st, nlines, TL, doresid); break;
+    case 6: hipLaunchKernelGGL((xpass_kernel<T, PI, K, 6>), grid, dim3(256), 0, s, c, a, st, nlines, TL, doresid); break;
+    default: return hipErrorInvalidValue;
+  }
+  if (g_prof_on) prof_end(KF_XPASS * 8 + PI, s);
+  return hipGetLastError();
+}
+
+template <typename T, int PI>
+static hipError_t xpass_t(const LineCoef& c, const PassArgs& a, DevState* st, int nlines, int doresid, hipStream_t s,
+                          int prec) {
+  switch (pick_kx(c.n, prec)) {
+    case 4: return xpass_k<T, PI, 4>(c, a, st, nlines, doresid, s);
+    case 8: return xpass_k<T, PI, 8>(c, a, st, nlines, doresid, s);
+    case 16: return xpass_k<T, PI, 16>(c, a, st, nlines, doresid, s);
+    case 32:
+      if constexpr (sizeof(T) == 4) return xpass_k<T, PI, 32>(c, a, st, nlines, doresid, s);
+      return hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_xpass(int prec, int prog, const LineCoef& c, const PassArgs& a, DevState* st, int nlines,
+                        int doresid, hipStream_t s) {
+  if (prec == MOLT_F64) {
+    switch (prog) {
+      case PROG_SWEEP: return xpass_t<double, PROG_SWEEP>(c, a, st, nlines, doresid, s, prec);
+      case PROG_RHS: return xpass_t<double, PROG_RHS>(c, a, st, nlines, doresid, s, prec);
+      case PROG_P2: return xpass_t<double, PROG_P2>(c, a, st, nlines, doresid, s, prec);
+      case PROG_P4: return xpass_t<double, PROG_P4>(c, a, st, nlines, doresid, s, prec);
+    }
+  } else {
+    switch (prog) {
+      case PROG_SWEEP: return xpass_t<float, PROG_SWEEP>(c, a, st, nlines, doresid, s, prec);
+      case PROG_RHS: return xpass_t<float, PROG_RHS>(c, a, st, nlines, doresid, s, prec);
+      case PROG_P2: return xpass_t<float, PROG_P2>(c, a, st, nlines, doresid, s, prec);
+      case PROG_P4: return xpass_t<float, PROG_P4>(c, a, st, nlines, doresid, s, prec);
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
+static int ky_of(int prec) { return prec == MOLT_F64 ? 8 : 16; }
+
+size_t ypass_tot_elems(int prec, int n, int nx, int batch) {
+  const int K = ky_of(prec);
+  const int nth = (n + K - 1) / K;
+  return (size_t)2 * 2 * nth * nx * batch;  // F <= 2 fields, 2 directions
+}
+
+template <typename T, int PI, int K, int M>
+static hipError_t ypass_km(const LineCoef& c, const PassArgs& a, DevState* st, int nx, int batch, T* tot, T* jln,
+                           hipStream_t s) {
+  using P = typename ProgOf<PI, T>::type;
+  const int nth = (c.n + K - 1) / K;
+  const size_t fstride = (size_t)c.n * nx;
+  dim3 blk(64, kRG);
+  dim3 grid((nx + 63) / 64, (nth + kRG - 1) / kRG, batch);
+  if (g_prof_on) prof_begin(KF_YTOT * 8 + PI, s);
+  hipLaunchKernelGGL((ytot_kernel<T, PI, K, M>), grid, blk, 0, s, c, a, st, nx, nth, fstride, tot, jln);
+  if (g_prof_on) prof_end(KF_YTOT * 8 + PI, s);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int ncomb = nx * P::F * batch;
+  if (g_prof_on) prof_begin(KF_YCOMB * 8 + PI, s);
+  hipLaunchKernelGGL((ycomb_kernel<T>), dim3((ncomb + 255) / 256), dim3(256), 0, s, c, st, nx, nth, K, P::F, batch,
+                     tot, (const T*)jln);
+  if (g_prof_on) prof_end(KF_YCOMB * 8 + PI, s);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (g_prof_on) prof_begin(KF_YFIN * 8 + PI, s);
+  hipLaunchKernelGGL((yfin_kernel<T, PI, K, M>), grid, blk, 0, s, c, a, st, nx, nth, fstride, (const T*)tot);
+  if (g_prof_on) prof_end(KF_YFIN * 8 + PI, s);
+  return hipGetLastError();
+}
+
+template <typename T, int PI>
+static hipError_t ypass_t(const LineCoef& c, const PassArgs& a, DevState* st, int nx, int batch, void* tot, void* jln,
+                          hipStream_t s) {
+  constexpr int K = sizeof(T) == 8 ? 8 : 16;
+  switch (c.M) {
+    case 2: return ypass_km<T, PI, K, 2>(c, a, st, nx, batch, (T*)tot, (T*)jln, s);
+    case 4: return ypass_km<T, PI, K, 4>(c, a, st, nx, batch, (T*)tot, (T*)jln, s);
+    case 6: return ypass_km<T, PI, K, 6>(c, a, st, nx, batch, (T*)tot, (T*)jln, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_ypass(int prec, int prog, const LineCoef& c, const PassArgs& a, DevState* st, int nx, int batch,
+                        void* tot, void* jln, hipStream_t s) {
+  if (prec == MOLT_F64) {
+    switch (prog) {
+      case PROG_SWEEP: return ypass_t<double, PROG_SWEEP>(c, a, st, nx, batch, tot, jln, s);
+      case PROG_RHS: return ypass_t<double, PROG_RHS>(c, a, st, nx, batch, tot, jln, s);
+      case PROG_P1: return ypass_t<double, PROG_P1>(c, a, st, nx, batch, tot, jln, s);
+      case PROG_P3: return ypass_t<double, PROG_P3>(c, a, st, nx, batch, tot, jln, s);
+    }
+  } else {
+    switch (prog) {
+      case PROG_SWEEP: return ypass_t<float, PROG_SWEEP>(c, a, st, nx, batch, tot, jln, s);
+      case PROG_RHS: return ypass_t<float, PROG_RHS>(c, a, st, nx, batch, tot, jln, s);
+      case PROG_P1: return ypass_t<float, PROG_P1>(c, a, st, nx, batch, tot, jln, s);
+      case PROG_P3: return ypass_t<float, PROG_P3>(c, a, st, nx, batch, tot, jln, s);
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
+static dim3 grid_1d(size_t n) {
+  size_t b = (n + 255) / 256;
+  if (b > 8192) b = 8192;
+  if (b < 1) b = 1;
+  return dim3((unsigned)b);
+}
+
+hipError_t launch_pointwise(int prec, int prog, const PassArgs& a, DevState* st, size_t nelem, hipStream_t s) {
+  dim3 g = grid_1d(nelem);
+  if (g_prof_on) prof_begin(KF_POINTWISE * 8 + prog, s);
+  if (prec == MOLT_F64) {
+    if (prog == PROG_P1) hipLaunchKernelGGL((pointwise_kernel<double, PROG_P1>), g, dim3(256), 0, s, a, st, nelem);
+    else if (prog == PROG_P3) hipLaunchKernelGGL((pointwise_kernel<double, PROG_P3>), g, dim3(256), 0, s, a, st, nelem);
+    else return hipErrorInvalidValue;
+  } else {
+    if (prog == PROG_P1) hipLaunchKernelGGL((pointwise_kernel<float, PROG_P1>), g, dim3(256), 0, s, a, st, nelem);
+    else if (prog == PROG_P3) hipLaunchKernelGGL((pointwise_kernel<float, PROG_P3>), g, dim3(256), 0, s, a, st, nelem);
+    else return hipErrorInvalidValue;
+  }
+  if (g_prof_on) prof_end(KF_POINTWISE * 8 + prog, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_state_init(DevState* st, double tol, int max_iter, int fixed, hipStream_t s) {
+  hipLaunchKernelGGL(state_init_kernel, dim3(1), dim3(64), 0, s, st, tol, max_iter, fixed);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(int prec, void* dst, const void* src, size_t n, hipStream_t s) {
+  if (prec == MOLT_F64)
+    hipLaunchKernelGGL((copy_kernel<double>), grid_1d(n), dim3(256), 0, s, (double*)dst, (const double*)src, n);
+  else
+    hipLaunchKernelGGL((copy_kernel<float>), grid_1d(n), dim3(256), 0, s, (float*)dst, (const float*)src, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(int prec, void* u, const void* base, const void* W, size_t n, hipStream_t s) {
+  if (prec == MOLT_F64)
+    hipLaunchKernelGGL((finalize_kernel<double>), grid_1d(n), dim3(256), 0, s, (double*)u, (const double*)base,
+                       (const double*)W, n);
+  else
+    hipLaunchKernelGGL((finalize_kernel<float>), grid_1d(n), dim3(256), 0, s, (float*)u, (const float*)base,
+                       (const float*)W, n);
+  return hipGetLastError();
+}
+
+int diag_blocks(size_t n) {
+  size_t b = (n + 255) / 256;
+  if (b > 1024) b = 1024;
+  return (int)(b < 1 ? 1 : b);
+}
+
+hipError_t launch_diag(int prec, const void* u, int nx, int ny, int bc, double hx, double hy, double eps,
+                       double* partials, DevState* st, hipStream_t s) {
+  const int nb = diag_blocks((size_t)nx * ny);
+  if (prec == MOLT_F64)
+    hipLaunchKernelGGL((diag_kernel<double>), dim3(nb), dim3(256), 0, s, (const double*)u, nx, ny, bc, hx, hy, eps,
+                       partials);
+  else
+    hipLaunchKernelGGL((diag_kernel<float>), dim3(nb), dim3(256), 0, s, (const float*)u, nx, ny, bc, hx, hy, eps,
+                       partials);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(diag_final_kernel, dim3(1), dim3(256), 0, s, (const double*)partials, nb, hx * hy, st);
+  return hipGetLastError();
+}
+
+}  // namespace molt

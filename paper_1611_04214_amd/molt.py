@@ -1,0 +1,226 @@
+"""ctypes binding of libmolt (C-ABI in include/molt.h).
+
+Argument marshalling only: every step of the solver runs in the HIP library.
+The functions keep the C names; device buffers are passed as integer device
+addresses (e.g. ``tensor.data_ptr()``) and streams as integer handles
+(``torch.cuda.current_stream().cuda_stream``).  A missing or unloadable
+library raises immediately -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmolt.so")
+
+MOLT_OK, MOLT_NOT_CONVERGED = 0, 1
+MOLT_EINVAL, MOLT_EUNSUPPORTED, MOLT_EHIP, MOLT_EWORKSPACE = -1, -2, -3, -4
+MOLT_BC_PERIODIC, MOLT_BC_NEUMANN, MOLT_BC_DIRICHLET = 0, 1, 2
+MOLT_BE, MOLT_BDF2 = 0, 1
+MOLT_INIT_PREV, MOLT_INIT_LINEAR = 0, 1
+MOLT_F64, MOLT_F32 = 0, 1
+
+#: every symbol include/molt.h declares
+EXPORTS = ("mol_t_helmholtz_sweep", "molt_sweep_workspace_bytes", "ch_workspace_bytes", "ch_step",
+           "ch_solve", "molt_strerror", "molt_last_error", "molt_profile", "molt_profile_read")
+
+KERNEL_FAMILIES = ("xpass", "ytot", "ycomb", "yfin", "pointwise", "other")
+PROGRAMS = ("sweep", "rhs", "P1", "P2", "P3", "P4")
+
+
+def kind_name(kind: int) -> str:
+    f, p = divmod(kind, 8)
+    return f"{KERNEL_FAMILIES[f]}_{PROGRAMS[p] if p < len(PROGRAMS) else p}"
+
+
+class molt_grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("x0", ctypes.c_double), ("x1", ctypes.c_double),
+                ("y0", ctypes.c_double), ("y1", ctypes.c_double),
+                ("bc", ctypes.c_int32), ("order_M", ctypes.c_int32)]
+
+
+class molt_ch_params(ctypes.Structure):
+    _fields_ = [("eps", ctypes.c_double), ("dt", ctypes.c_double), ("tol", ctypes.c_double),
+                ("sigma0", ctypes.c_double), ("stepper", ctypes.c_int32), ("max_iter", ctypes.c_int32),
+                ("init", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("fixed_iters", ctypes.c_int32), ("have_prev", ctypes.c_int32)]
+
+
+class molt_step_info(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("residual", ctypes.c_double), ("mass", ctypes.c_double), ("energy", ctypes.c_double),
+                ("s1", ctypes.c_double), ("s2", ctypes.c_double), ("sigma", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class molt_prof_entry(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Open libmolt.so (raises OSError if it is missing: build it first)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise OSError(f"libmolt.so not found at {path}; run `python -m paper_1611_04214_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, sz = ctypes.c_void_p, ctypes.c_size_t
+    G, P = ctypes.POINTER(molt_grid), ctypes.POINTER(molt_ch_params)
+    lib.mol_t_helmholtz_sweep.argtypes = [G, ctypes.c_int32, ctypes.c_double, ctypes.c_int32, vp, vp,
+                                          ctypes.c_int64, vp, sz, vp]
+    lib.mol_t_helmholtz_sweep.restype = ctypes.c_int32
+    lib.molt_sweep_workspace_bytes.argtypes = [G, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64]
+    lib.molt_sweep_workspace_bytes.restype = sz
+    lib.ch_workspace_bytes.argtypes = [G, P]
+    lib.ch_workspace_bytes.restype = sz
+    lib.ch_step.argtypes = [G, P, vp, vp, vp, sz, ctypes.POINTER(molt_step_info), vp]
+    lib.ch_step.restype = ctypes.c_int32
+    lib.ch_solve.argtypes = [G, P, vp, ctypes.c_int64, vp, sz, ctypes.POINTER(molt_step_info), vp]
+    lib.ch_solve.restype = ctypes.c_int32
+    lib.molt_strerror.argtypes = [ctypes.c_int32]
+    lib.molt_strerror.restype = ctypes.c_char_p
+    lib.molt_last_error.argtypes = []
+    lib.molt_last_error.restype = ctypes.c_char_p
+    lib.molt_profile.argtypes = [ctypes.c_int32]
+    lib.molt_profile.restype = ctypes.c_int32
+    lib.molt_profile_read.argtypes = [ctypes.POINTER(molt_prof_entry), ctypes.c_int32]
+    lib.molt_profile_read.restype = ctypes.c_int32
+    _lib = lib
+    return lib
+
+
+class MoltError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        lib = load()
+        super().__init__(f"{where}: {lib.molt_strerror(status).decode()} ({status}): "
+                         f"{lib.molt_last_error().decode()}")
+        self.status = status
+
+
+def _check(status: int, where: str, allow_not_converged: bool = True) -> int:
+    if status < 0 or (status == MOLT_NOT_CONVERGED and not allow_not_converged):
+        raise MoltError(status, where)
+    return status
+
+
+# ---------------------------------------------------------------- raw C-ABI --
+def mol_t_helmholtz_sweep(grid: molt_grid, axis: int, alpha: float, precision: int, d_in: int, d_out: int,
+                          batch: int, d_work: int, work_bytes: int, stream: int = 0) -> int:
+    return load().mol_t_helmholtz_sweep(ctypes.byref(grid), axis, alpha, precision, d_in, d_out, batch,
+                                        d_work or None, work_bytes, stream or None)
+
+
+def molt_sweep_workspace_bytes(grid: molt_grid, axis: int, precision: int, batch: int) -> int:
+    return load().molt_sweep_workspace_bytes(ctypes.byref(grid), axis, precision, batch)
+
+
+def ch_workspace_bytes(grid: molt_grid, params: molt_ch_params) -> int:
+    return load().ch_workspace_bytes(ctypes.byref(grid), ctypes.byref(params))
+
+
+def ch_step(grid: molt_grid, params: molt_ch_params, d_u: int, d_u_prev: int, d_work: int, work_bytes: int,
+            info: molt_step_info | None = None, stream: int = 0) -> int:
+    return load().ch_step(ctypes.byref(grid), ctypes.byref(params), d_u, d_u_prev or None, d_work or None,
+                          work_bytes, ctypes.byref(info) if info is not None else None, stream or None)
+
+
+def ch_solve(grid: molt_grid, params: molt_ch_params, d_u: int, nsteps: int, d_work: int, work_bytes: int,
+             per_step=None, stream: int = 0) -> int:
+    return load().ch_solve(ctypes.byref(grid), ctypes.byref(params), d_u, nsteps, d_work or None, work_bytes,
+                           per_step, stream or None)
+
+
+def molt_strerror(status: int) -> str:
+    return load().molt_strerror(status).decode()
+
+
+def molt_last_error() -> str:
+    return load().molt_last_error().decode()
+
+
+def molt_profile(enable: int) -> int:
+    return load().molt_profile(enable)
+
+
+def molt_profile_read(max_entries: int = 48) -> dict:
+    """{kind name: (launches, total_ms)} of the kernels timed since molt_profile(1)."""
+    buf = (molt_prof_entry * max_entries)()
+    m = load().molt_profile_read(buf, max_entries)
+    if m < 0:
+        raise MoltError(m, "molt_profile_read")
+    return {kind_name(buf[i].kind): (buf[i].launches, buf[i].total_ms) for i in range(m)}
+
+
+# ------------------------------------------------- torch-tensor conveniences --
+def make_grid(nx: int, ny: int = 1, x0: float = 0.0, x1: float = 1.0, y0: float = 0.0, y1: float = 1.0,
+              bc: int = MOLT_BC_PERIODIC, M: int = 4) -> molt_grid:
+    return molt_grid(nx, ny, x0, x1, y0, y1, bc, M)
+
+
+def make_params(eps: float, dt: float, tol: float = 1e-10, stepper: int = MOLT_BE, max_iter: int = 300,
+                init: int = MOLT_INIT_PREV, precision: int = MOLT_F64, fixed_iters: int = 0,
+                have_prev: int = 0, sigma0: float = 2.0) -> molt_ch_params:
+    return molt_ch_params(eps, dt, tol, sigma0, stepper, max_iter, init, precision, fixed_iters, have_prev)
+
+
+def _stream(torch):
+    return torch.cuda.current_stream().cuda_stream
+
+
+def workspace(nbytes: int, device="cuda"):
+    """A caller-owned device workspace (uint8 tensor) of nbytes."""
+    import torch
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+def sweep(field, grid: molt_grid, axis: int, alpha: float, out=None, work=None):
+    """L^{-1} along axis of a (batch, ny, nx) / (ny, nx) / (nx,) device tensor."""
+    import torch
+    prec = MOLT_F64 if field.dtype == torch.float64 else MOLT_F32
+    f = field.contiguous()
+    batch = f.numel() // (grid.nx * grid.ny)
+    out = torch.empty_like(f) if out is None else out
+    need = molt_sweep_workspace_bytes(grid, axis, prec, batch)
+    if need == 0:
+        raise MoltError(MOLT_EINVAL, "molt_sweep_workspace_bytes")
+    if work is None or work.numel() < need:
+        work = workspace(need, f.device)
+    _check(mol_t_helmholtz_sweep(grid, axis, alpha, prec, f.data_ptr(), out.data_ptr(), batch, work.data_ptr(),
+                                 work.numel(), _stream(torch)), "mol_t_helmholtz_sweep")
+    return out
+
+
+def step(u, grid: molt_grid, params: molt_ch_params, u_prev=None, work=None) -> molt_step_info:
+    """One ch_step in place on the device tensor u (u_prev: BDF2 history, rotated in place)."""
+    import torch
+    need = ch_workspace_bytes(grid, params)
+    if need == 0:
+        raise MoltError(MOLT_EINVAL, "ch_workspace_bytes")
+    if work is None or work.numel() < need:
+        work = workspace(need, u.device)
+    info = molt_step_info()
+    _check(ch_step(grid, params, u.data_ptr(), 0 if u_prev is None else u_prev.data_ptr(), work.data_ptr(),
+                   work.numel(), info, _stream(torch)), "ch_step")
+    return info
+
+
+def solve(u, grid: molt_grid, params: molt_ch_params, nsteps: int, work=None):
+    """ch_solve in place on u; returns (status, [molt_step_info])."""
+    import torch
+    need = ch_workspace_bytes(grid, params)
+    if need == 0:
+        raise MoltError(MOLT_EINVAL, "ch_workspace_bytes")
+    if work is None or work.numel() < need:
+        work = workspace(need, u.device)
+    infos = (molt_step_info * max(nsteps, 1))()
+    st = _check(ch_solve(grid, params, u.data_ptr(), nsteps, work.data_ptr(), work.numel(), infos,
+                         _stream(torch)), "ch_solve")
+    return st, [infos[i] for i in range(nsteps)]

@@ -1,0 +1,100 @@
+"""The C-ABI library loads and exports what include/molt.h declares; host-only
+argument checks and workspace queries (no device work is launched here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1611_04214_amd import molt
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "molt.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = set(re.findall(r"\b([a-z_][a-z0-9_]*)\s*\(", src))
+    return sorted(n for n in names if n not in {"defined", "sizeof"})
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(molt.LIB_PATH):
+        pytest.fail("libmolt.so is not built (run __graft_entry__.build())")
+    return molt.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    decl = _declared()
+    assert set(decl) == set(molt.EXPORTS), decl
+    for name in decl:
+        assert hasattr(lib, name), name
+
+
+def test_struct_layouts_match_header():
+    # natural C alignment of the header's structs
+    assert ctypes.sizeof(molt.molt_grid) == 48
+    assert ctypes.sizeof(molt.molt_ch_params) == 56
+    assert ctypes.sizeof(molt.molt_step_info) == 56
+
+
+def test_strerror_names_every_status(lib):
+    for code in (0, 1, -1, -2, -3, -4):
+        assert molt.molt_strerror(code) not in ("", "unknown status")
+    assert molt.molt_strerror(99) == "unknown status"
+
+
+def test_workspace_queries(lib):
+    g = molt.make_grid(64, 48, bc=molt.MOLT_BC_NEUMANN, M=4)
+    p = molt.make_params(0.02, 1e-4, precision=molt.MOLT_F32)
+    w32 = molt.ch_workspace_bytes(g, p)
+    p.precision = molt.MOLT_F64
+    w64 = molt.ch_workspace_bytes(g, p)
+    assert w32 > 10 * 64 * 48 * 4 and w64 > w32
+    assert molt.molt_sweep_workspace_bytes(g, 0, molt.MOLT_F32, 1) > 0
+    assert molt.molt_sweep_workspace_bytes(g, 1, molt.MOLT_F32, 3) > 3 * 64 * 48 * 4
+
+
+@pytest.mark.parametrize("change,code", [
+    (dict(nx=4), molt.MOLT_EINVAL),          # fewer than M+1 nodes
+    (dict(order_M=3), molt.MOLT_EINVAL),
+    (dict(bc=7), molt.MOLT_EINVAL),
+    (dict(x1=0.0), molt.MOLT_EINVAL),
+    (dict(nx=20000), molt.MOLT_EUNSUPPORTED),
+])
+def test_bad_grids_are_rejected_before_any_device_work(lib, change, code):
+    g = molt.make_grid(32, 32, M=4)
+    for k, v in change.items():
+        setattr(g, k, v)
+    p = molt.make_params(0.05, 1e-3)
+    assert molt.ch_workspace_bytes(g, p) == 0
+    rc = molt.ch_step(g, p, 1, 0, 1, 1 << 30)
+    assert rc == code, (rc, molt.molt_last_error())
+    assert molt.molt_last_error() != ""
+
+
+@pytest.mark.parametrize("change", [dict(eps=0.0), dict(dt=-1.0), dict(stepper=5), dict(init=9),
+                                    dict(max_iter=0), dict(fixed_iters=-2), dict(precision=3)])
+def test_bad_params_are_rejected(lib, change):
+    g = molt.make_grid(32, 32, M=4)
+    p = molt.make_params(0.05, 1e-3)
+    for k, v in change.items():
+        setattr(p, k, v)
+    assert molt.ch_step(g, p, 1, 0, 1, 1 << 30) == molt.MOLT_EINVAL
+
+
+def test_small_workspace_is_rejected(lib):
+    g = molt.make_grid(32, 32, M=4)
+    p = molt.make_params(0.05, 1e-3)
+    need = molt.ch_workspace_bytes(g, p)
+    assert molt.ch_step(g, p, 1, 0, 1, need - 1) == molt.MOLT_EWORKSPACE
+    assert molt.ch_solve(g, p, 1, 3, 1, need - 1) == molt.MOLT_EWORKSPACE
+
+
+def test_sweep_argument_checks(lib):
+    g = molt.make_grid(32, 16, M=4)
+    assert molt.mol_t_helmholtz_sweep(g, 2, 1.0, 0, 1, 1, 1, 0, 0) == molt.MOLT_EINVAL
+    assert molt.mol_t_helmholtz_sweep(g, 0, -1.0, 0, 1, 1, 1, 0, 0) == molt.MOLT_EINVAL
+    assert molt.mol_t_helmholtz_sweep(g, 0, 1.0, 0, 0, 1, 1, 0, 0) == molt.MOLT_EINVAL
+    assert molt.mol_t_helmholtz_sweep(g, 1, 1.0, 0, 1, 1, 1, 0, 0) == molt.MOLT_EWORKSPACE
