@@ -22,26 +22,29 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
     objs = []
     for src in SOURCES:
         obj = os.path.join(CSRC, src + ".o")
-        cmd = ["hipcc", "-c"] + FLAGS + (["-x", "hip"] if src.endswith(".hip") else []) + \
-              [os.path.join(CSRC, src), "-o", obj]
+        cmd = ["hipcc", "-c"] + FLAGS + [f"-D{d}" for d in defines] + \
+              (["-x", "hip"] if src.endswith(".hip") else []) + [os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.check_call(cmd)
         objs.append(obj)
-    tmp = LIB + ".tmp"
+    tmp = out + ".tmp"
     cmd = ["hipcc", "-shared", f"--offload-arch={ARCH}", "-fPIC", "-o", tmp] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
+    os.replace(tmp, out)
     for o in objs:
         os.remove(o)
-    return LIB
+    return out
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    args = [a for a in sys.argv[1:] if a != "-v"]
+    defs = [a[2:] for a in args if a.startswith("-D")]
+    outs = [a[len("--out="):] for a in args if a.startswith("--out=")]
+    print(build(verbose="-v" in sys.argv, out=outs[0] if outs else LIB, defines=defs))

@@ -12,7 +12,7 @@
 
 namespace molt {
 hipError_t launch_xpass(int prec, int prog, const LineCoef& c, const PassArgs& a, DevState* st, int nlines,
-                        int doresid, hipStream_t s);
+                        double* rpart, hipStream_t s);
 hipError_t launch_ypass(int prec, int prog, const LineCoef& c, const PassArgs& a, DevState* st, int nx, int batch,
                         void* tot, void* jln, hipStream_t s);
 hipError_t launch_pointwise(int prec, int prog, const PassArgs& a, DevState* st, size_t nelem, hipStream_t s);
@@ -233,7 +233,8 @@ static int32_t check_grid(const molt_grid* g, int prec) {
   if (g->ny != 1 && g->ny < g->order_M + 1) return fail(MOLT_EINVAL, "ny must be 1 or at least M+1");
   if (!(g->x1 > g->x0)) return fail(MOLT_EINVAL, "x1 must exceed x0");
   if (g->ny > 1 && !(g->y1 > g->y0)) return fail(MOLT_EINVAL, "y1 must exceed y0");
-  if (g->nx > xpass_max_n(prec)) return fail(MOLT_EUNSUPPORTED, "rows longer than the x-pass limit");
+  if (g->nx > xpass_max_n(prec) || g->ny > xpass_max_n(prec))
+    return fail(MOLT_EUNSUPPORTED, "lines longer than 8192 (FP32) / 4096 (FP64) nodes");
   return MOLT_OK;
 }
 
@@ -243,7 +244,7 @@ enum { F_R = 0, F_DL, F_W, F_A1, F_B1, F_C, F_Q, F_M, F_N, F_HIST, F_COUNT };
 
 struct Layout {
   size_t fld[F_COUNT];
-  size_t tot, jln, state, partials, total;
+  size_t tot, jln, state, partials, rpart, total;
 };
 
 static Layout ch_layout(const molt_grid* g, int prec) {
@@ -263,6 +264,8 @@ static Layout ch_layout(const molt_grid* g, int prec) {
   off += al256(sizeof(DevState));
   L.partials = off;
   off += al256((size_t)2 * diag_blocks(n) * sizeof(double));
+  L.rpart = off;  // one residual slot per x-pass block (at most one block per row)
+  off += al256((size_t)g->ny * sizeof(double));
   L.total = off;
   return L;
 }
@@ -282,6 +285,7 @@ static int32_t step_impl(const molt_grid* g, const molt_ch_params* p, void* d_u,
   void* jln = w + L.jln;
   DevState* st = (DevState*)(w + L.state);
   double* partials = (double*)(w + L.partials);
+  double* rpart = (double*)(w + L.rpart);
 
   const int nx = g->nx, ny = g->ny, M = g->order_M, bc = g->bc;
   const size_t n = (size_t)nx * ny;
@@ -310,19 +314,19 @@ static int32_t step_impl(const molt_grid* g, const molt_ch_params* p, void* d_u,
     HIPCHK(launch_ypass(prec, PROG_RHS, cy2, a, nullptr, nx, 1, tot, jln, s));
     a.in[0] = F[F_A1];
     a.out[0] = F[F_B1];
-    HIPCHK(launch_xpass(prec, PROG_SWEEP, cx2, a, nullptr, ny, 0, s));
+    HIPCHK(launch_xpass(prec, PROG_SWEEP, cx2, a, nullptr, ny, nullptr, s));
     a.in[0] = F[F_B1];
     a.out[0] = F[F_A1];
     HIPCHK(launch_ypass(prec, PROG_SWEEP, cy1, a, nullptr, nx, 1, tot, jln, s));
     a.in[0] = F[F_A1];
     a.out[0] = F[F_R];
-    HIPCHK(launch_xpass(prec, PROG_SWEEP, cx1, a, nullptr, ny, 0, s));
+    HIPCHK(launch_xpass(prec, PROG_SWEEP, cx1, a, nullptr, ny, nullptr, s));
   } else {
     a.out[0] = F[F_B1];
-    HIPCHK(launch_xpass(prec, PROG_RHS, cx2, a, nullptr, 1, 0, s));
+    HIPCHK(launch_xpass(prec, PROG_RHS, cx2, a, nullptr, 1, nullptr, s));
     a.in[0] = F[F_B1];
     a.out[0] = F[F_R];
-    HIPCHK(launch_xpass(prec, PROG_SWEEP, cx1, a, nullptr, 1, 0, s));
+    HIPCHK(launch_xpass(prec, PROG_SWEEP, cx1, a, nullptr, 1, nullptr, s));
   }
   // history: u^n -> u_prev (after the rhs has consumed u^{n-1})
   if (d_u_prev) HIPCHK(launch_copy(prec, d_u_prev, d_u, n, s));
@@ -360,7 +364,7 @@ static int32_t step_impl(const molt_grid* g, const molt_ch_params* p, void* d_u,
       q.in[4] = F[F_DL];
       q.out[0] = F[F_C];
       q.out[1] = F[F_Q];
-      HIPCHK(launch_xpass(prec, PROG_P2, cx1, q, st, ny, 0, s));
+      HIPCHK(launch_xpass(prec, PROG_P2, cx1, q, st, ny, nullptr, s));
       // P3 (y, alpha2): m, n
       q.in[0] = F[F_C];
       q.in[1] = F[F_Q];
@@ -377,7 +381,7 @@ static int32_t step_impl(const molt_grid* g, const molt_ch_params* p, void* d_u,
       q.in[3] = F[F_W];
       q.out[0] = F[F_DL];
       q.out[1] = F[F_W];
-      HIPCHK(launch_xpass(prec, PROG_P4, cx2, q, st, ny, 1, s));
+      HIPCHK(launch_xpass(prec, PROG_P4, cx2, q, st, ny, rpart, s));
     }
     HIPCHK(hipMemcpyAsync(&hst, st, sizeof(DevState), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -489,7 +493,7 @@ int32_t mol_t_helmholtz_sweep(const molt_grid* g, int32_t axis, double alpha, in
     const LineCoef c = make_line(g->nx, g->bc, g->order_M, alpha, hx);
     const long long nlines = (long long)g->ny * batch;
     if (nlines > 0x7fffffffLL) return fail(MOLT_EUNSUPPORTED, "too many lines");
-    HIPCHK(launch_xpass(precision, PROG_SWEEP, c, a, nullptr, (int)nlines, 0, s));
+    HIPCHK(launch_xpass(precision, PROG_SWEEP, c, a, nullptr, (int)nlines, nullptr, s));
     return MOLT_OK;
   }
   if (g->ny == 1) {  // y-direction of a 1D problem: identity

@@ -23,6 +23,12 @@
 
 #include "molt_internal.h"
 
+// Minimum waves per SIMD requested for the line-pass kernels (caps their VGPRs).
+#ifndef MOLT_OCC
+#define MOLT_OCC 2
+#endif
+#define MOLT_PASS_ATTR __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MOLT_OCC)))
+
 namespace molt {
 
 // --------------------------------------------------------------------------
@@ -46,11 +52,11 @@ __device__ __forceinline__ int wrapi(int j, int n) {
 
 // --------------------------------------------------------------------------
 // pass programs
-//   F: number of fields swept, E: per-node values kept for the output.
-//   sin(a, i, s):  sweep inputs at element i
-//   ext(a, i, e):  kept values at element i (owned nodes only)
-//   fin(a, i, w, e): outputs at element i from the swept values w; returns
-//                  the node's contribution to the residual max.
+//   NR raw input fields a.in[0..NR-1]; need(a, r) says whether field r is read
+//   sin(a, r, s):    the F swept fields of a node from its NR raw values
+//   ext(a, r, x):    the E values kept on owned nodes for the output
+//   fin(a, w, x, o): the NO outputs (a.out[0..NO-1]) from the swept values w;
+//                    returns the node's contribution to the residual max.
 // The iteration works in u (= v - 1): every linear operator of the scheme
 // maps constants to themselves (L^{-1}[1] = 1) or to zero (D, C1), so the
 // shift only changes the reaction: g = f(v) - sigma v = u^3 - (1+sigma) u - sigma,
@@ -60,30 +66,26 @@ enum ProgId { PROG_SWEEP = 0, PROG_RHS = 1, PROG_P1 = 2, PROG_P2 = 3, PROG_P3 = 
 
 template <typename T>
 struct ProgSweep {  // w = L^{-1} in0
-  static constexpr int F = 1, E = 0;
-  __device__ static void sin(const PassArgs& a, size_t i, T* s) { s[0] = ((const T*)a.in[0])[i]; }
-  __device__ static void ext(const PassArgs&, size_t, T*) {}
-  __device__ static double fin(const PassArgs& a, size_t i, const T* w, const T*) {
-    ((T*)a.out[0])[i] = w[0];
+  static constexpr int F = 1, E = 0, NR = 1, NO = 1;
+  __device__ static bool need(const PassArgs&, int) { return true; }
+  __device__ static void sin(const PassArgs&, const T* r, T* s) { s[0] = r[0]; }
+  __device__ static void ext(const PassArgs&, const T*, T*) {}
+  __device__ static double fin(const PassArgs&, const T* w, const T*, T* o) {
+    o[0] = w[0];
     return 0.0;
   }
 };
 
 template <typename T>
 struct ProgRhs {  // w = L^{-1} rhs, rhs = u^n (BE) or (4u^n - u^{n-1})/3 (BDF2)
-  static constexpr int F = 1, E = 0;
-  __device__ static void sin(const PassArgs& a, size_t i, T* s) {
-    T u = ((const T*)a.in[0])[i];
-    if (a.bdf2) {
-      T up = ((const T*)a.in[1])[i];
-      s[0] = (T(4) * u - up) * T(1.0 / 3.0);
-    } else {
-      s[0] = u;
-    }
+  static constexpr int F = 1, E = 0, NR = 2, NO = 1;
+  __device__ static bool need(const PassArgs& a, int r) { return r == 0 || a.bdf2; }
+  __device__ static void sin(const PassArgs& a, const T* r, T* s) {
+    s[0] = a.bdf2 ? (T(4) * r[0] - r[1]) * T(1.0 / 3.0) : r[0];
   }
-  __device__ static void ext(const PassArgs&, size_t, T*) {}
-  __device__ static double fin(const PassArgs& a, size_t i, const T* w, const T*) {
-    ((T*)a.out[0])[i] = w[0];
+  __device__ static void ext(const PassArgs&, const T*, T*) {}
+  __device__ static double fin(const PassArgs&, const T* w, const T*, T* o) {
+    o[0] = w[0];
     return 0.0;
   }
 };
@@ -93,86 +95,83 @@ struct ProgRhs {  // w = L^{-1} rhs, rhs = u^n (BE) or (4u^n - u^{n-1})/3 (BDF2)
 //  increment form: e = g(p) - g(q) = dl*(p^2 + p q + q^2 - 1 - sigma), lin = dl,
 //                  p = base + W (current iterate), q = p - dl (previous)
 template <typename T>
-__device__ __forceinline__ void react_lin(const PassArgs& a, size_t i, const T* base, const T* W,
-                                          const T* dl, T& e, T& lin) {
+__device__ __forceinline__ void react_lin(const PassArgs& a, T base, T W, T dl, T& e, T& lin) {
   const T sg = (T)a.sigma;
   if (a.mode == 0) {
-    T u = base[i];
-    e = u * u * u - (T(1) + sg) * u;
-    lin = u;
+    e = base * base * base - (T(1) + sg) * base;
+    lin = base;
   } else {
-    T p = base[i] + W[i];
-    T d = dl[i];
-    T q = p - d;
-    e = d * (p * p + p * q + q * q - T(1) - sg);
-    lin = d;
+    const T p = base + W;
+    const T q = p - dl;
+    e = dl * (p * p + p * q + q * q - T(1) - sg);
+    lin = dl;
   }
 }
 
 template <typename T>
-struct ProgP1 {  // y, alpha1: a1 = Y1 e, b1 = Y1 lin
-  static constexpr int F = 2, E = 0;
-  __device__ static void sin(const PassArgs& a, size_t i, T* s) {
-    react_lin<T>(a, i, (const T*)a.in[0], (const T*)a.in[1], (const T*)a.in[2], s[0], s[1]);
-  }
-  __device__ static void ext(const PassArgs&, size_t, T*) {}
-  __device__ static double fin(const PassArgs& a, size_t i, const T* w, const T*) {
-    ((T*)a.out[0])[i] = w[0];
-    ((T*)a.out[1])[i] = w[1];
+struct ProgP1 {  // y, alpha1: raw (base, W, dl) -> a1 = Y1 e, b1 = Y1 lin
+  static constexpr int F = 2, E = 0, NR = 3, NO = 2;
+  __device__ static bool need(const PassArgs& a, int r) { return r == 0 || a.mode; }
+  __device__ static void sin(const PassArgs& a, const T* r, T* s) { react_lin<T>(a, r[0], r[1], r[2], s[0], s[1]); }
+  __device__ static void ext(const PassArgs&, const T*, T*) {}
+  __device__ static double fin(const PassArgs&, const T* w, const T*, T* o) {
+    o[0] = w[0];
+    o[1] = w[1];
     return 0.0;
   }
 };
 
 template <typename T>
-struct ProgP2 {  // x, alpha1: C = X1(2 a1 - e) - a1, q = b1 + X1(lin - b1)
-  static constexpr int F = 2, E = 2;
-  __device__ static void sin(const PassArgs& a, size_t i, T* s) {
+struct ProgP2 {  // x, alpha1: raw (a1, b1, base, W, dl) -> C = X1(2 a1 - e) - a1, q = b1 + X1(lin - b1)
+  static constexpr int F = 2, E = 2, NR = 5, NO = 2;
+  __device__ static bool need(const PassArgs& a, int r) { return r < 3 || a.mode; }
+  __device__ static void sin(const PassArgs& a, const T* r, T* s) {
     T e, lin;
-    react_lin<T>(a, i, (const T*)a.in[2], (const T*)a.in[3], (const T*)a.in[4], e, lin);
-    T a1 = ((const T*)a.in[0])[i], b1 = ((const T*)a.in[1])[i];
-    s[0] = T(2) * a1 - e;
-    s[1] = lin - b1;
+    react_lin<T>(a, r[2], r[3], r[4], e, lin);
+    s[0] = T(2) * r[0] - e;
+    s[1] = lin - r[1];
   }
-  __device__ static void ext(const PassArgs& a, size_t i, T* x) {
-    x[0] = ((const T*)a.in[0])[i];
-    x[1] = ((const T*)a.in[1])[i];
+  __device__ static void ext(const PassArgs&, const T* r, T* x) {
+    x[0] = r[0];
+    x[1] = r[1];
   }
-  __device__ static double fin(const PassArgs& a, size_t i, const T* w, const T* x) {
-    ((T*)a.out[0])[i] = w[0] - x[0];
-    ((T*)a.out[1])[i] = x[1] + w[1];
+  __device__ static double fin(const PassArgs&, const T* w, const T* x, T* o) {
+    o[0] = w[0] - x[0];
+    o[1] = x[1] + w[1];
     return 0.0;
   }
 };
 
 template <typename T>
-struct ProgP3 {  // y, alpha2: m = Y2(q + kappa C) - q, n = Y2 q
-  static constexpr int F = 2, E = 1;
-  __device__ static void sin(const PassArgs& a, size_t i, T* s) {
-    T C = ((const T*)a.in[0])[i], q = ((const T*)a.in[1])[i];
-    s[0] = q + (T)a.kappa * C;
-    s[1] = q;
+struct ProgP3 {  // y, alpha2: raw (C, q) -> m = Y2(q + kappa C) - q, n = Y2 q
+  static constexpr int F = 2, E = 1, NR = 2, NO = 2;
+  __device__ static bool need(const PassArgs&, int) { return true; }
+  __device__ static void sin(const PassArgs& a, const T* r, T* s) {
+    s[0] = r[1] + (T)a.kappa * r[0];
+    s[1] = r[1];
   }
-  __device__ static void ext(const PassArgs& a, size_t i, T* x) { x[0] = ((const T*)a.in[1])[i]; }
-  __device__ static double fin(const PassArgs& a, size_t i, const T* w, const T* x) {
-    ((T*)a.out[0])[i] = w[0] - x[0];
-    ((T*)a.out[1])[i] = w[1];
+  __device__ static void ext(const PassArgs&, const T* r, T* x) { x[0] = r[1]; }
+  __device__ static double fin(const PassArgs&, const T* w, const T* x, T* o) {
+    o[0] = w[0] - x[0];
+    o[1] = w[1];
     return 0.0;
   }
 };
 
 template <typename T>
-struct ProgP4 {  // x, alpha2: dl' = (dl | R) + X2 m - n ; W' = W + dl' (| dl')
-  static constexpr int F = 1, E = 3;
-  __device__ static void sin(const PassArgs& a, size_t i, T* s) { s[0] = ((const T*)a.in[0])[i]; }
-  __device__ static void ext(const PassArgs& a, size_t i, T* x) {
-    x[0] = ((const T*)a.in[1])[i];
-    x[1] = ((const T*)a.in[2])[i];
-    x[2] = a.mode ? ((const T*)a.in[3])[i] : T(0);
+struct ProgP4 {  // x, alpha2: raw (m, n, dl|R, W) -> dl' = (dl|R) + X2 m - n ; W' = W + dl' (| dl')
+  static constexpr int F = 1, E = 3, NR = 4, NO = 2;
+  __device__ static bool need(const PassArgs& a, int r) { return r < 3 || a.mode; }
+  __device__ static void sin(const PassArgs&, const T* r, T* s) { s[0] = r[0]; }
+  __device__ static void ext(const PassArgs& a, const T* r, T* x) {
+    x[0] = r[1];
+    x[1] = r[2];
+    x[2] = a.mode ? r[3] : T(0);
   }
-  __device__ static double fin(const PassArgs& a, size_t i, const T* w, const T* x) {
-    T dn = x[1] + w[0] - x[0];
-    ((T*)a.out[0])[i] = dn;
-    ((T*)a.out[1])[i] = x[2] + dn;
+  __device__ static double fin(const PassArgs&, const T* w, const T* x, T* o) {
+    const T dn = x[1] + w[0] - x[0];
+    o[0] = dn;
+    o[1] = x[2] + dn;
     return fabs((double)dn);
   }
 };
@@ -186,31 +185,110 @@ template <typename T> struct ProgOf<PROG_P2, T> { using type = ProgP2<T>; };
 template <typename T> struct ProgOf<PROG_P3, T> { using type = ProgP3<T>; };
 template <typename T> struct ProgOf<PROG_P4, T> { using type = ProgP4<T>; };
 
+// raw values of one node (scalar loads; fields the program does not read are 0)
+template <typename T, class P>
+__device__ __forceinline__ void load_raw(const PassArgs& a, size_t i, T* r) {
+#pragma unroll
+  for (int f = 0; f < P::NR; ++f) r[f] = P::need(a, f) ? ((const T*)a.in[f])[i] : T(0);
+}
+
+// 16-byte vector access of 16/sizeof(T) consecutive elements
+__device__ __forceinline__ void ld16(const float* p, float* o) {
+  const float4 v = *(const float4*)p;
+  o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+}
+__device__ __forceinline__ void ld16(const double* p, double* o) {
+  const double2 v = *(const double2*)p;
+  o[0] = v.x; o[1] = v.y;
+}
+__device__ __forceinline__ void st16(float* p, const float* o) { *(float4*)p = make_float4(o[0], o[1], o[2], o[3]); }
+__device__ __forceinline__ void st16(double* p, const double* o) { *(double2*)p = make_double2(o[0], o[1]); }
+
 // --------------------------------------------------------------------------
 // Per-thread line segment: sweep inputs on nodes j0-H .. j0+K+H-1, the two
 // local quadratures on the K owned nodes, zero-seeded totals and the final
 // seeded scans.  `stride` is the element distance between consecutive nodes
 // of the line (1 along x, nx along y); `lbase` the element index of node 0.
+// With `vec` (stride 1, 16-byte aligned fields, line length a multiple of
+// 16/sizeof(T)) owned nodes are read with 16-byte loads.
 // --------------------------------------------------------------------------
-template <typename T, class P, int K, int M>
+template <typename T, class P, int K, int M, bool PER>
 struct Seg {
-  static constexpr int H = M / 2, F = P::F, W = K + 2 * H;
+  static constexpr int H = M / 2, F = P::F, E = P::E, NR = P::NR, W = K + 2 * H;
+  static constexpr int V = 16 / (int)sizeof(T);
   T JL[F][K], JR[F][K];
-  T jln[F];  // periodic: J^L of the cell ending at node n (= node 0)
+  T jln[F];                    // periodic: J^L of the cell ending at node n (= node 0)
+  T ex[E > 0 ? E : 1][K];      // kept values of the owned nodes
 
-  __device__ void build(const LineCoef& c, const PassArgs& a, size_t lbase, size_t stride, int j0) {
+  __device__ void build(const LineCoef& c, const PassArgs& a, size_t lbase, size_t stride, int j0, bool vec) {
     const int n = c.n;
-    const bool per = c.bc == MOLT_BC_PERIODIC;
+    constexpr bool per = PER;
     T s[F][W];
+    if (vec && j0 + K <= n) {
 #pragma unroll
-    for (int k = 0; k < W; ++k) {
-      int j = j0 - H + k;
-      int jj = per ? wrapi(j, n) : min(max(j, 0), n - 1);
-      T v[F];
-      P::sin(a, lbase + (size_t)jj * stride, v);
+      for (int q = 0; q < K / V; ++q) {
+        T r[NR][V];
 #pragma unroll
-      for (int f = 0; f < F; ++f) s[f][k] = v[f];
+        for (int f = 0; f < NR; ++f) {
+          if (P::need(a, f)) {
+            ld16((const T*)a.in[f] + lbase + (size_t)(j0 + q * V), r[f]);
+          } else {
+#pragma unroll
+            for (int v = 0; v < V; ++v) r[f][v] = T(0);
+          }
+        }
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          T rv[NR], sv[F], xv[E > 0 ? E : 1];
+#pragma unroll
+          for (int f = 0; f < NR; ++f) rv[f] = r[f][v];
+          P::sin(a, rv, sv);
+#pragma unroll
+          for (int f = 0; f < F; ++f) s[f][H + q * V + v] = sv[f];
+          if constexpr (E > 0) {
+            P::ext(a, rv, xv);
+#pragma unroll
+            for (int e = 0; e < E; ++e) ex[e][q * V + v] = xv[e];
+          }
+        }
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const int j = j0 + k;
+        const int jj = per ? wrapi(j, n) : min(j, n - 1);
+        T rv[NR], sv[F], xv[E > 0 ? E : 1];
+        load_raw<T, P>(a, lbase + (size_t)jj * stride, rv);
+        P::sin(a, rv, sv);
+#pragma unroll
+        for (int f = 0; f < F; ++f) s[f][H + k] = sv[f];
+        if constexpr (E > 0) {
+          P::ext(a, rv, xv);
+#pragma unroll
+          for (int e = 0; e < E; ++e) ex[e][k] = xv[e];
+        }
+      }
     }
+#pragma unroll
+    for (int k = 0; k < 2 * H; ++k) {  // halo nodes (ends of non-periodic lines: clamped, replaced below)
+      const int kk = k < H ? k : K + k;
+      const int j = j0 - H + kk;
+      const int jj = per ? wrapi(j, n) : min(max(j, 0), n - 1);
+      T rv[NR], sv[F];
+      load_raw<T, P>(a, lbase + (size_t)jj * stride, rv);
+      P::sin(a, rv, sv);
+#pragma unroll
+      for (int f = 0; f < F; ++f) s[f][kk] = sv[f];
+    }
+    stencils(c, a, lbase, stride, j0, s);
+  }
+
+  // J^L, J^R on the owned nodes from the window values s (nodes j0-H ..
+  // j0+K+H-1); boundary nodes of non-periodic lines are redone in FP64
+  __device__ void stencils(const LineCoef& c, const PassArgs& a, size_t lbase, size_t stride, int j0,
+                           const T (&s)[F][W]) {
+    const int n = c.n;
+    constexpr bool per = PER;
     T wl[M + 1], wr[M + 1];
 #pragma unroll
     for (int i = 0; i <= M; ++i) {
@@ -234,30 +312,36 @@ struct Seg {
         JR[f][k] = (real && (per || j != n - 1)) ? r : T(0);
       }
     }
-    if (!per && (j0 < H || j0 + K + H > n)) boundary_nodes(c, a, lbase, stride, j0, s);
+    if constexpr (!PER) {
+      if (j0 < H || j0 + K + H > n) boundary_nodes(c, a, lbase, stride, j0);
+    }
   }
 
   // Nodes whose centred window leaves a non-periodic line (j < H or j > n-1-H).
   // The window is completed by ghost values extrapolated with the degree-M
   // polynomial through the M+1 end nodes; the extrapolation weights are large
   // (up to ~2800 for M=6), so the ghosts and these few stencils are formed in
-  // FP64 and only the result is rounded to T.
-  __device__ void boundary_nodes(const LineCoef& c, const PassArgs& a, size_t lbase, size_t stride, int j0,
-                                 const T (&s)[F][W]) {
+  // FP64 and only the result is rounded to T.  The in-range window values are
+  // reloaded here (only the threads at the two ends of a line get here), so
+  // the window array of the interior path is not kept alive.
+  __device__ void boundary_nodes(const LineCoef& c, const PassArgs& a, size_t lbase, size_t stride, int j0) {
     const int n = c.n;
     double gl[F][H], gr[F][H];
 #pragma unroll
     for (int f = 0; f < F; ++f)
 #pragma unroll
       for (int g = 0; g < H; ++g) gl[f][g] = gr[f][g] = 0.0;
-    if (j0 < H) {
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      if (side == 0 ? (j0 >= H) : (j0 + K + H <= n)) continue;
       double e[F][M + 1];
 #pragma unroll
       for (int i = 0; i <= M; ++i) {
-        T v[F];
-        P::sin(a, lbase + (size_t)i * stride, v);
+        T rv[NR], sv[F];
+        load_raw<T, P>(a, lbase + (size_t)(side == 0 ? i : n - 1 - M + i) * stride, rv);
+        P::sin(a, rv, sv);
 #pragma unroll
-        for (int f = 0; f < F; ++f) e[f][i] = (double)v[f];
+        for (int f = 0; f < F; ++f) e[f][i] = (double)sv[f];
       }
 #pragma unroll
       for (int f = 0; f < F; ++f)
@@ -265,27 +349,11 @@ struct Seg {
         for (int g = 0; g < H; ++g) {
           double acc = 0.0;
 #pragma unroll
-          for (int i = 0; i <= M; ++i) acc += c.ghostL[g][i] * e[f][i];
-          gl[f][g] = acc;
-        }
-    }
-    if (j0 + K + H > n) {
-      double e[F][M + 1];
-#pragma unroll
-      for (int i = 0; i <= M; ++i) {
-        T v[F];
-        P::sin(a, lbase + (size_t)(n - 1 - M + i) * stride, v);
-#pragma unroll
-        for (int f = 0; f < F; ++f) e[f][i] = (double)v[f];
-      }
-#pragma unroll
-      for (int f = 0; f < F; ++f)
-#pragma unroll
-        for (int g = 0; g < H; ++g) {
-          double acc = 0.0;
-#pragma unroll
-          for (int i = 0; i <= M; ++i) acc += c.ghostR[g][i] * e[f][i];
-          gr[f][g] = acc;
+          for (int i = 0; i <= M; ++i) acc += (side == 0 ? c.ghostL[g][i] : c.ghostR[g][i]) * e[f][i];
+          if (side == 0)
+            gl[f][g] = acc;
+          else
+            gr[f][g] = acc;
         }
     }
 #pragma unroll
@@ -298,7 +366,10 @@ struct Seg {
 #pragma unroll
           for (int i = 0; i <= M; ++i) {
             const int jw = j - H + i;
-            double v = (double)s[f][k + i];
+            T rv[NR], sv[F];
+            load_raw<T, P>(a, lbase + (size_t)min(max(jw, 0), n - 1) * stride, rv);
+            P::sin(a, rv, sv);
+            double v = (double)sv[f];
 #pragma unroll
             for (int g = 1; g <= H; ++g) {
               v = (jw == -g) ? gl[f][g - 1] : v;
@@ -353,6 +424,49 @@ struct Seg {
       }
     }
   }
+
+  // outputs of the owned nodes; returns the residual max over them
+  __device__ double store(const PassArgs& a, size_t lbase, size_t stride, int j0, int n, bool vec,
+                          const T (&w)[F][K]) const {
+    constexpr int NO = P::NO;
+    double res = 0.0;
+    if (vec && j0 + K <= n) {
+#pragma unroll
+      for (int q = 0; q < K / V; ++q) {
+        T o[NO][V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          const int k = q * V + v;
+          T wk[F], xk[E > 0 ? E : 1], ok[NO];
+#pragma unroll
+          for (int f = 0; f < F; ++f) wk[f] = w[f][k];
+#pragma unroll
+          for (int e = 0; e < E; ++e) xk[e] = ex[e][k];
+          res = fmax(res, P::fin(a, wk, xk, ok));
+#pragma unroll
+          for (int f = 0; f < NO; ++f) o[f][v] = ok[f];
+        }
+#pragma unroll
+        for (int f = 0; f < NO; ++f) st16((T*)a.out[f] + lbase + (size_t)(j0 + q * V), o[f]);
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const int j = j0 + k;
+        if (j < n) {
+          T wk[F], xk[E > 0 ? E : 1], ok[NO];
+#pragma unroll
+          for (int f = 0; f < F; ++f) wk[f] = w[f][k];
+#pragma unroll
+          for (int e = 0; e < E; ++e) xk[e] = ex[e][k];
+          res = fmax(res, P::fin(a, wk, xk, ok));
+#pragma unroll
+          for (int f = 0; f < NO; ++f) ((T*)a.out[f])[lbase + (size_t)j * stride] = ok[f];
+        }
+      }
+    }
+    return res;
+  }
 };
 
 // Boundary coefficients of one line from its zero-seeded totals (Sec. 3.2).
@@ -378,8 +492,9 @@ __device__ __forceinline__ void boundary_terms(const LineCoef& c, double TLl, do
   }
 }
 
-// residual: block max, one atomicMax per block, last block closes the iteration
-__device__ void residual_close(double r, DevState* st) {
+// residual: block max written to a per-block slot; a one-block close kernel
+// folds the slots (order-independent max) and advances the iteration state.
+__device__ void residual_block(double r, double* partials) {
   __shared__ double red[4];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
@@ -389,24 +504,29 @@ __device__ void residual_close(double r, DevState* st) {
   if (threadIdx.x == 0) {
     double b = red[0];
     for (int w = 1; w < (int)(blockDim.x >> 6); ++w) b = fmax(b, red[w]);
-    atomicMax(&st->resid_bits, (unsigned long long)__double_as_longlong(b));
-    __threadfence();
-    unsigned int prev = atomicAdd(&st->blocks_done, 1u);
-    if (prev == gridDim.x * gridDim.y * gridDim.z - 1) {
-      __threadfence();
-      unsigned long long bits = atomicAdd(&st->resid_bits, 0ull);
-      double res = __longlong_as_double((long long)bits);
-      int it = st->iters + 1;
-      st->iters = it;
-      st->last_resid = res;
-      if (st->fixed > 0) {
-        if (it >= st->fixed) st->done = 1;
-      } else if (res < st->tol || it >= st->max_iter) {
-        st->done = 1;
-      }
-      atomicExch(&st->resid_bits, 0ull);
-      atomicExch(&st->blocks_done, 0u);
-      __threadfence();
+    partials[blockIdx.x] = b;
+  }
+}
+
+__global__ void __launch_bounds__(256) residual_close_kernel(const double* partials, int nblocks, DevState* st) {
+  if (st->done) return;
+  __shared__ double red[4];
+  double r = 0.0;
+  for (int i = threadIdx.x; i < nblocks; i += blockDim.x) r = fmax(r, partials[i]);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) r = fmax(r, __shfl_down(r, off));
+  if (lane == 0) red[wave] = r;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double res = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    const int it = st->iters + 1;
+    st->iters = it;
+    st->last_resid = res;
+    if (st->fixed > 0) {
+      if (it >= st->fixed) st->done = 1;
+    } else if (res < st->tol || it >= st->max_iter) {
+      st->done = 1;
     }
   }
 }
@@ -415,14 +535,21 @@ __device__ void residual_close(double r, DevState* st) {
 // x-direction pass: rows are contiguous; TL threads (a multiple of 64) own one
 // row, 256/TL rows per 256-thread block.
 // --------------------------------------------------------------------------
-template <typename T, int PI, int K, int M>
-__global__ void __launch_bounds__(256) xpass_kernel(const LineCoef c, const PassArgs a, DevState* st,
-                                                    int nlines, int TL, int doresid) {
+template <typename T, int PI, int K, int M, bool PER>
+__global__ void MOLT_PASS_ATTR xpass_kernel(const LineCoef c, const PassArgs a, DevState* st,
+                                            int nlines, int TL, double* rpart, int vec) {
   using P = typename ProgOf<PI, T>::type;
-  constexpr int F = P::F, E = P::E;
+  constexpr int F = P::F, E = P::E, NR = P::NR, NO = P::NO;
+  constexpr int H = M / 2, W = K + 2 * H;
+  constexpr int V = 16 / (int)sizeof(T);
+  constexpr int ROW = 256 * K;  // nodes of all rows of one block
   if (st != nullptr && st->done) return;
   __shared__ T sh_tot[F][2][4];
   __shared__ double sh_line[4][F][3];
+  // swept fields (then the swept results) of the block's rows, one padding
+  // word per 16 so that a thread's K consecutive nodes sit 17 words from its
+  // neighbour's (no bank conflicts)
+  __shared__ T sh_row[F][ROW + ROW / 16];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -435,22 +562,82 @@ __global__ void __launch_bounds__(256) xpass_kernel(const LineCoef c, const Pass
   const int j0 = t * K;
   const bool has = act && j0 < n;
   const size_t lbase = (size_t)(act ? line : 0) * (size_t)n;
+  const int rowoff = lil * TL * K;
   const T d = (T)c.d;
+#define MOLT_PAD(e) ((e) + ((e) >> 4))
 
-  Seg<T, P, K, M> seg;
-  T ex[E > 0 ? E : 1][K];
-  T AL[F], AR[F];
-  if (has) {
-    seg.build(c, a, lbase, 1, j0);
-    if constexpr (E > 0) {
+  Seg<T, P, K, M, PER> seg;
+  // phase A: coalesced loads, the program's pointwise part in the load layout
+  if (act) {
+    if (vec) {
 #pragma unroll
-      for (int k = 0; k < K; ++k) {
-        T x[E > 0 ? E : 1];
-        P::ext(a, lbase + (size_t)min(j0 + k, n - 1), x);
+      for (int it = 0; it < K / V; ++it) {
+        const int e0 = (it * TL + t) * V;
+        if (e0 < n) {
+          T r[NR][V];
 #pragma unroll
-        for (int e = 0; e < E; ++e) ex[e][k] = x[e];
+          for (int f = 0; f < NR; ++f) {
+            if (P::need(a, f)) {
+              ld16((const T*)a.in[f] + lbase + (size_t)e0, r[f]);
+            } else {
+#pragma unroll
+              for (int v = 0; v < V; ++v) r[f][v] = T(0);
+            }
+          }
+#pragma unroll
+          for (int v = 0; v < V; ++v) {
+            T rv[NR], sv[F], xv[E > 0 ? E : 1];
+#pragma unroll
+            for (int f = 0; f < NR; ++f) rv[f] = r[f][v];
+            P::sin(a, rv, sv);
+#pragma unroll
+            for (int f = 0; f < F; ++f) sh_row[f][MOLT_PAD(rowoff + e0 + v)] = sv[f];
+            if constexpr (E > 0) {
+              P::ext(a, rv, xv);
+#pragma unroll
+              for (int e = 0; e < E; ++e) seg.ex[e][it * V + v] = xv[e];
+            }
+          }
+        }
+      }
+    } else {
+#pragma unroll
+      for (int it = 0; it < K; ++it) {
+        const int e = it * TL + t;
+        if (e < n) {
+          T rv[NR], sv[F], xv[E > 0 ? E : 1];
+          load_raw<T, P>(a, lbase + (size_t)e, rv);
+          P::sin(a, rv, sv);
+#pragma unroll
+          for (int f = 0; f < F; ++f) sh_row[f][MOLT_PAD(rowoff + e)] = sv[f];
+          if constexpr (E > 0) {
+            P::ext(a, rv, xv);
+#pragma unroll
+            for (int q = 0; q < E; ++q) seg.ex[q][it] = xv[q];
+          }
+        }
       }
     }
+  }
+  __syncthreads();
+
+  // phase B: each thread's window of K + 2H nodes from LDS, local quadratures
+  T AL[F], AR[F];
+  if (has) {
+    T sw[F][W];
+    const bool near = n >= K + H;  // then one wrap suffices
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+      const int j = j0 - H + k;
+      int jj;
+      if (PER)
+        jj = near ? (j < 0 ? j + n : (j >= n ? j - n : j)) : wrapi(j, n);
+      else
+        jj = min(max(j, 0), n - 1);
+#pragma unroll
+      for (int f = 0; f < F; ++f) sw[f][k] = sh_row[f][MOLT_PAD(rowoff + jj)];
+    }
+    seg.stencils(c, a, lbase, 1, j0, sw);
     seg.totals(d, j0, n, AL, AR);
   } else {
 #pragma unroll
@@ -516,7 +703,8 @@ __global__ void __launch_bounds__(256) xpass_kernel(const LineCoef c, const Pass
   }
   __syncthreads();
 
-  double resid = 0.0;
+  // phase C: seeded scans; the swept values go back to LDS (every read of the
+  // window happened before the barriers of the carry scan above)
   if (has) {
     const int jlast = min(j0 + K - 1, n - 1);
     const double pL = exp(-c.nu * (double)j0);
@@ -532,18 +720,57 @@ __global__ void __launch_bounds__(256) xpass_kernel(const LineCoef c, const Pass
     T w[F][K];
     seg.finalize(d, j0, n, gL, gR, w);
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
+    for (int k = 0; k < K; ++k)
       if (j0 + k < n) {
-        T wk[F], xk[E > 0 ? E : 1];
 #pragma unroll
-        for (int f = 0; f < F; ++f) wk[f] = w[f][k];
+        for (int f = 0; f < F; ++f) sh_row[f][MOLT_PAD(rowoff + j0 + k)] = w[f][k];
+      }
+  }
+  __syncthreads();
+
+  // phase D: outputs in the coalesced layout of phase A
+  double resid = 0.0;
+  if (act) {
+    if (vec) {
 #pragma unroll
-        for (int e = 0; e < E; ++e) xk[e] = ex[e][k];
-        resid = fmax(resid, P::fin(a, lbase + (size_t)(j0 + k), wk, xk));
+      for (int it = 0; it < K / V; ++it) {
+        const int e0 = (it * TL + t) * V;
+        if (e0 < n) {
+          T o[NO][V];
+#pragma unroll
+          for (int v = 0; v < V; ++v) {
+            T wk[F], xk[E > 0 ? E : 1], ok[NO];
+#pragma unroll
+            for (int f = 0; f < F; ++f) wk[f] = sh_row[f][MOLT_PAD(rowoff + e0 + v)];
+#pragma unroll
+            for (int e = 0; e < E; ++e) xk[e] = seg.ex[e][it * V + v];
+            resid = fmax(resid, P::fin(a, wk, xk, ok));
+#pragma unroll
+            for (int f = 0; f < NO; ++f) o[f][v] = ok[f];
+          }
+#pragma unroll
+          for (int f = 0; f < NO; ++f) st16((T*)a.out[f] + lbase + (size_t)e0, o[f]);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int it = 0; it < K; ++it) {
+        const int e = it * TL + t;
+        if (e < n) {
+          T wk[F], xk[E > 0 ? E : 1], ok[NO];
+#pragma unroll
+          for (int f = 0; f < F; ++f) wk[f] = sh_row[f][MOLT_PAD(rowoff + e)];
+#pragma unroll
+          for (int q = 0; q < E; ++q) xk[q] = seg.ex[q][it];
+          resid = fmax(resid, P::fin(a, wk, xk, ok));
+#pragma unroll
+          for (int f = 0; f < NO; ++f) ((T*)a.out[f])[lbase + (size_t)e] = ok[f];
+        }
       }
     }
   }
-  if (doresid) residual_close(resid, st);
+#undef MOLT_PAD
+  if (rpart != nullptr) residual_block(resid, rpart);
 }
 
 // --------------------------------------------------------------------------
@@ -557,8 +784,8 @@ __global__ void __launch_bounds__(256) xpass_kernel(const LineCoef c, const Pass
 // --------------------------------------------------------------------------
 constexpr int kRG = 4;
 
-template <typename T, int PI, int K, int M>
-__global__ void __launch_bounds__(256) ytot_kernel(const LineCoef c, const PassArgs a, DevState* st, int nx,
+template <typename T, int PI, int K, int M, bool PER>
+__global__ void MOLT_PASS_ATTR ytot_kernel(const LineCoef c, const PassArgs a, DevState* st, int nx,
                                                    int nth, size_t fstride, T* tot, T* jlnb) {
   using P = typename ProgOf<PI, T>::type;
   constexpr int F = P::F;
@@ -569,8 +796,8 @@ __global__ void __launch_bounds__(256) ytot_kernel(const LineCoef c, const PassA
   if (col >= nx || t >= nth) return;
   const int n = c.n, j0 = t * K;
   const size_t lbase = (size_t)b * fstride + (size_t)col;
-  Seg<T, P, K, M> seg;
-  seg.build(c, a, lbase, (size_t)nx, j0);
+  Seg<T, P, K, M, PER> seg;
+  seg.build(c, a, lbase, (size_t)nx, j0, false);
   T AL[F], AR[F];
   seg.totals((T)c.d, j0, n, AL, AR);
   T* tb = tot + (size_t)b * (size_t)(F * 2) * nth * nx;
@@ -585,55 +812,103 @@ __global__ void __launch_bounds__(256) ytot_kernel(const LineCoef c, const PassA
   }
 }
 
-template <typename T>
-__global__ void __launch_bounds__(256) ycomb_kernel(const LineCoef c, DevState* st, int nx, int nth, int K, int F,
-                                                    int batch, T* tot, const T* jlnb) {
+// ycomb: one block = 64 columns x 16 waves for one field of one batch entry.
+// Wave w owns threads [w*CT, w*CT + CT) of every column (CT = ceil(nth/16) <=
+// CTMAX): chunk-local scans, chunk carries through LDS, then the line totals,
+// the FP64 boundary solve and the seeds, written over the totals.
+constexpr int kCombWaves = 16;
+
+template <typename T, int CTMAX>
+__global__ void __launch_bounds__(1024) ycomb_kernel(const LineCoef c, DevState* st, int nx, int nth, int K, int F,
+                                                     T* tot, const T* jlnb) {
   if (st != nullptr && st->done) return;
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= nx * F * batch) return;
-  const int col = idx % nx;
-  const int f = (idx / nx) % F;
-  const int b = idx / (nx * F);
+  __shared__ double shL[kCombWaves][64], shR[kCombWaves][64];
+  __shared__ double shTL[64], shTR[64];
+  const int lane = threadIdx.x, w = threadIdx.y;
+  const int col = blockIdx.x * 64 + lane;
+  const int f = blockIdx.y, b = blockIdx.z;
+  const bool ok = col < nx;
   const int n = c.n;
+  const int CT = (nth + kCombWaves - 1) / kCombWaves;
+  const int t0 = w * CT;
   T* tb = tot + (size_t)b * (size_t)(F * 2) * nth * nx;
-  T* AL = tb + (size_t)(f * 2 + 0) * nth * nx + col;
-  T* AR = tb + (size_t)(f * 2 + 1) * nth * nx + col;
-  const double d = c.d, m = exp(-c.nu * (double)K);
+  T* AL = tb + (size_t)(f * 2 + 0) * nth * nx + (ok ? col : 0);
+  T* AR = tb + (size_t)(f * 2 + 1) * nth * nx + (ok ? col : 0);
+  const double d = c.d, nu = c.nu;
+  const double m = exp(-nu * (double)K), mC = exp(-nu * (double)K * (double)CT);
+  T vL[CTMAX], vR[CTMAX];
+#pragma unroll
+  for (int i = 0; i < CTMAX; ++i) {
+    const int t = t0 + i;
+    const bool in = ok && i < CT && t < nth;
+    vL[i] = in ? AL[(size_t)t * nx] : T(0);
+    vR[i] = in ? AR[(size_t)t * nx] : T(0);
+  }
+  // chunk totals over the chunk's own entries (entries past nth are zero)
+  double xl = 0.0, xr = 0.0;
+#pragma unroll
+  for (int i = 0; i < CTMAX; ++i)
+    if (i < CT) xl = m * xl + (double)vL[i];
+#pragma unroll
+  for (int i = CTMAX - 1; i >= 0; --i) xr = m * xr + (double)vR[i];
+  shL[w][lane] = xl;
+  shR[w][lane] = xr;
+  __syncthreads();
+  double CL = 0.0, CR = 0.0;
+  for (int v = 0; v < w; ++v) CL = mC * CL + shL[v][lane];
+  for (int v = kCombWaves - 1; v > w; --v) CR = mC * CR + shR[v][lane];
   const int tstar = (n - 1) / K;
-  double cl = 0.0, TLl = 0.0;
-  for (int t = 0; t < nth; ++t) {
-    const double v = (double)AL[(size_t)t * nx];
-    if (t == tstar) TLl = v + exp(-c.nu * (double)(n - 1 - tstar * K + 1)) * cl;
+  const double dk = exp(-nu * (double)(n - 1 - tstar * K + 1));
+  double cl = CL;
+#pragma unroll
+  for (int i = 0; i < CTMAX; ++i) {
+    const int t = t0 + i;
+    const double v = (double)vL[i];
+    if (i < CT && t == tstar) shTL[lane] = v + dk * cl;
+    vL[i] = (T)cl;  // exclusive carry into thread t
     cl = m * cl + v;
   }
-  double cr = 0.0, TRl = 0.0;
-  for (int t = nth - 1; t >= 0; --t) {
-    const double v = (double)AR[(size_t)t * nx];
-    if (t == 0) TRl = v + m * cr;
-    cr = m * cr + v;
+  double cr = CR;
+#pragma unroll
+  for (int i = CTMAX - 1; i >= 0; --i) {
+    if (i < CT) {  // entries past the chunk must not decay the carry
+      const int t = t0 + i;
+      const double v = (double)vR[i];
+      if (t == 0) shTR[lane] = v + m * cr;
+      vR[i] = (T)cr;
+      cr = m * cr + v;
+    }
   }
+  __syncthreads();
+  if (!ok) return;
   double Ba, Bb;
-  boundary_terms(c, TLl, TRl, (double)jlnb[((size_t)b * F + f) * nx + col], Ba, Bb);
-  cl = 0.0;
-  for (int t = 0; t < nth; ++t) {
-    const double v = (double)AL[(size_t)t * nx];
-    AL[(size_t)t * nx] = (T)(d * cl + 2.0 * Ba * exp(-c.nu * (double)(t * K)));
-    cl = m * cl + v;
+  boundary_terms(c, shTL[lane], shTR[lane], (double)jlnb[((size_t)b * F + f) * nx + col], Ba, Bb);
+  double pL = exp(-nu * (double)t0 * (double)K);
+#pragma unroll
+  for (int i = 0; i < CTMAX; ++i) {
+    const int t = t0 + i;
+    if (i < CT && t < nth) AL[(size_t)t * nx] = (T)(d * (double)vL[i] + 2.0 * Ba * pL);
+    pL *= m;
   }
-  cr = 0.0;
-  for (int t = nth - 1; t >= 0; --t) {
-    const double v = (double)AR[(size_t)t * nx];
-    const int jlast = min(t * K + K - 1, n - 1);
-    AR[(size_t)t * nx] = (T)(d * cr + 2.0 * Bb * exp(-c.nu * (double)(c.N - jlast)));
-    cr = m * cr + v;
+  double pR = 0.0;
+  bool first = true;
+#pragma unroll
+  for (int i = CTMAX - 1; i >= 0; --i) {
+    const int t = t0 + i;
+    if (i < CT && t < nth) {
+      const int jlast = min(t * K + K - 1, n - 1);
+      pR = (first || t >= nth - 2) ? exp(-nu * (double)(c.N - jlast)) : pR * m;
+      first = false;
+      AR[(size_t)t * nx] = (T)(d * (double)vR[i] + 2.0 * Bb * pR);
+    }
   }
 }
 
-template <typename T, int PI, int K, int M>
-__global__ void __launch_bounds__(256) yfin_kernel(const LineCoef c, const PassArgs a, DevState* st, int nx,
+template <typename T, int PI, int K, int M, bool PER>
+__global__ void MOLT_PASS_ATTR yfin_kernel(const LineCoef c, const PassArgs a, DevState* st, int nx,
                                                    int nth, size_t fstride, const T* seeds) {
   using P = typename ProgOf<PI, T>::type;
-  constexpr int F = P::F, E = P::E;
+  constexpr int F = P::F;
   if (st != nullptr && st->done) return;
   const int col = blockIdx.x * 64 + threadIdx.x;
   const int t = blockIdx.y * kRG + threadIdx.y;
@@ -641,8 +916,8 @@ __global__ void __launch_bounds__(256) yfin_kernel(const LineCoef c, const PassA
   if (col >= nx || t >= nth) return;
   const int n = c.n, j0 = t * K;
   const size_t lbase = (size_t)b * fstride + (size_t)col;
-  Seg<T, P, K, M> seg;
-  seg.build(c, a, lbase, (size_t)nx, j0);
+  Seg<T, P, K, M, PER> seg;
+  seg.build(c, a, lbase, (size_t)nx, j0, false);
   const T* sb = seeds + (size_t)b * (size_t)(F * 2) * nth * nx;
   T gL[F], gR[F];
 #pragma unroll
@@ -652,18 +927,7 @@ __global__ void __launch_bounds__(256) yfin_kernel(const LineCoef c, const PassA
   }
   T w[F][K];
   seg.finalize((T)c.d, j0, n, gL, gR, w);
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const int j = j0 + k;
-    if (j < n) {
-      const size_t i = lbase + (size_t)j * nx;
-      T wk[F], xk[E > 0 ? E : 1];
-#pragma unroll
-      for (int f = 0; f < F; ++f) wk[f] = w[f][k];
-      if constexpr (E > 0) P::ext(a, i, xk);
-      P::fin(a, i, wk, xk);
-    }
-  }
+  seg.store(a, lbase, (size_t)nx, j0, n, false, w);
 }
 
 // pointwise program with the identity in place of the sweep (the y-direction
@@ -671,13 +935,16 @@ __global__ void __launch_bounds__(256) yfin_kernel(const LineCoef c, const PassA
 template <typename T, int PI>
 __global__ void __launch_bounds__(256) pointwise_kernel(const PassArgs a, DevState* st, size_t nelem) {
   using P = typename ProgOf<PI, T>::type;
-  constexpr int F = P::F, E = P::E;
+  constexpr int F = P::F, E = P::E, NR = P::NR, NO = P::NO;
   if (st != nullptr && st->done) return;
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < nelem; i += (size_t)gridDim.x * blockDim.x) {
-    T s[F], x[E > 0 ? E : 1];
-    P::sin(a, i, s);
-    if constexpr (E > 0) P::ext(a, i, x);
-    P::fin(a, i, s, x);
+    T r[NR], s[F], x[E > 0 ? E : 1], o[NO];
+    load_raw<T, P>(a, i, r);
+    P::sin(a, r, s);
+    if constexpr (E > 0) P::ext(a, r, x);
+    P::fin(a, s, x, o);
+#pragma unroll
+    for (int f = 0; f < NO; ++f) ((T*)a.out[f])[i] = o[f];
   }
 }
 
@@ -799,53 +1066,78 @@ static int pick_kx(int n, int prec) {
 
 int xpass_max_n(int prec) { return prec == MOLT_F64 ? 4096 : 8192; }
 
+// 16-byte vector access is used when every field pointer is 16-byte aligned and
+// rows are a whole number of 16-byte words
+template <typename T, int PI>
+static int can_vec(const PassArgs& a, int n) {
+  using P = typename ProgOf<PI, T>::type;
+  if ((n * (int)sizeof(T)) % 16 != 0) return 0;
+  for (int f = 0; f < P::NR; ++f)
+    if (((uintptr_t)a.in[f]) % 16 != 0) return 0;
+  for (int f = 0; f < P::NO; ++f)
+    if (((uintptr_t)a.out[f]) % 16 != 0) return 0;
+  return 1;
+}
+
 template <typename T, int PI, int K>
-static hipError_t xpass_k(const LineCoef& c, const PassArgs& a, DevState* st, int nlines, int doresid, hipStream_t s) {
+static hipError_t xpass_k(const LineCoef& c, const PassArgs& a, DevState* st, int nlines, double* rpart, hipStream_t s) {
+  const int vec = can_vec<T, PI>(a, c.n);
   // threads per line: 64, 128 or 256, so that 256/TL rows tile the block exactly
   const int need = (c.n + K - 1) / K;
   const int TL = need <= 64 ? 64 : (need <= 128 ? 128 : 256);
   const int lpb = 256 / TL;
   dim3 grid((nlines + lpb - 1) / lpb);
   if (g_prof_on) prof_begin(KF_XPASS * 8 + PI, s);
+  const bool per = c.bc == MOLT_BC_PERIODIC;
+#define MOLT_XL(MM, PP) \
+  hipLaunchKernelGGL((xpass_kernel<T, PI, K, MM, PP>), grid, dim3(256), 0, s, c, a, st, nlines, TL, rpart, vec)
   switch (c.M) {
-    case 2: hipLaunchKernelGGL((xpass_kernel<T, PI, K, 2>), grid, dim3(256), 0, s, c, a, st, nlines, TL, doresid); break;
-    case 4: hipLaunchKernelGGL((xpass_kernel<T, PI, K, 4>), grid, dim3(256), 0, s, c, a, st, nlines, TL, doresid); break;
-    case 6: hipLaunchKernelGGL((xpass_kernel<T, PI, K, 6>), grid, dim3(256), 0, s, c, a, st, nlines, TL, doresid); break;
+    case 2: if (per) MOLT_XL(2, true); else MOLT_XL(2, false); break;
+    case 4: if (per) MOLT_XL(4, true); else MOLT_XL(4, false); break;
+    case 6: if (per) MOLT_XL(6, true); else MOLT_XL(6, false); break;
     default: return hipErrorInvalidValue;
   }
+#undef MOLT_XL
   if (g_prof_on) prof_end(KF_XPASS * 8 + PI, s);
+  if (rpart != nullptr) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (g_prof_on) prof_begin(KF_OTHER * 8, s);
+    hipLaunchKernelGGL(residual_close_kernel, dim3(1), dim3(256), 0, s, (const double*)rpart, (int)grid.x, st);
+    if (g_prof_on) prof_end(KF_OTHER * 8, s);
+  }
   return hipGetLastError();
 }
 
 template <typename T, int PI>
-static hipError_t xpass_t(const LineCoef& c, const PassArgs& a, DevState* st, int nlines, int doresid, hipStream_t s,
+static hipError_t xpass_t(const LineCoef& c, const PassArgs& a, DevState* st, int nlines, double* rpart, hipStream_t s,
                           int prec) {
   switch (pick_kx(c.n, prec)) {
-    case 4: return xpass_k<T, PI, 4>(c, a, st, nlines, doresid, s);
-    case 8: return xpass_k<T, PI, 8>(c, a, st, nlines, doresid, s);
-    case 16: return xpass_k<T, PI, 16>(c, a, st, nlines, doresid, s);
+    case 4: return xpass_k<T, PI, 4>(c, a, st, nlines, rpart, s);
+    case 8: return xpass_k<T, PI, 8>(c, a, st, nlines, rpart, s);
+    case 16: return xpass_k<T, PI, 16>(c, a, st, nlines, rpart, s);
     case 32:
-      if constexpr (sizeof(T) == 4) return xpass_k<T, PI, 32>(c, a, st, nlines, doresid, s);
+      if constexpr (sizeof(T) == 4) return xpass_k<T, PI, 32>(c, a, st, nlines, rpart, s);
       return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
   }
 }
 
 hipError_t launch_xpass(int prec, int prog, const LineCoef& c, const PassArgs& a, DevState* st, int nlines,
-                        int doresid, hipStream_t s) {
+                        double* rpart, hipStream_t s) {
   if (prec == MOLT_F64) {
     switch (prog) {
-      case PROG_SWEEP: return xpass_t<double, PROG_SWEEP>(c, a, st, nlines, doresid, s, prec);
-      case PROG_RHS: return xpass_t<double, PROG_RHS>(c, a, st, nlines, doresid, s, prec);
-      case PROG_P2: return xpass_t<double, PROG_P2>(c, a, st, nlines, doresid, s, prec);
-      case PROG_P4: return xpass_t<double, PROG_P4>(c, a, st, nlines, doresid, s, prec);
+      case PROG_SWEEP: return xpass_t<double, PROG_SWEEP>(c, a, st, nlines, rpart, s, prec);
+      case PROG_RHS: return xpass_t<double, PROG_RHS>(c, a, st, nlines, rpart, s, prec);
+      case PROG_P2: return xpass_t<double, PROG_P2>(c, a, st, nlines, rpart, s, prec);
+      case PROG_P4: return xpass_t<double, PROG_P4>(c, a, st, nlines, rpart, s, prec);
     }
   } else {
     switch (prog) {
-      case PROG_SWEEP: return xpass_t<float, PROG_SWEEP>(c, a, st, nlines, doresid, s, prec);
-      case PROG_RHS: return xpass_t<float, PROG_RHS>(c, a, st, nlines, doresid, s, prec);
-      case PROG_P2: return xpass_t<float, PROG_P2>(c, a, st, nlines, doresid, s, prec);
-      case PROG_P4: return xpass_t<float, PROG_P4>(c, a, st, nlines, doresid, s, prec);
+      case PROG_SWEEP: return xpass_t<float, PROG_SWEEP>(c, a, st, nlines, rpart, s, prec);
+      case PROG_RHS: return xpass_t<float, PROG_RHS>(c, a, st, nlines, rpart, s, prec);
+      case PROG_P2: return xpass_t<float, PROG_P2>(c, a, st, nlines, rpart, s, prec);
+      case PROG_P4: return xpass_t<float, PROG_P4>(c, a, st, nlines, rpart, s, prec);
     }
   }
   return hipErrorInvalidValue;
@@ -859,7 +1151,7 @@ size_t ypass_tot_elems(int prec, int n, int nx, int batch) {
   return (size_t)2 * 2 * nth * nx * batch;  // F <= 2 fields, 2 directions
 }
 
-template <typename T, int PI, int K, int M>
+template <typename T, int PI, int K, int M, bool PER>
 static hipError_t ypass_km(const LineCoef& c, const PassArgs& a, DevState* st, int nx, int batch, T* tot, T* jln,
                            hipStream_t s) {
   using P = typename ProgOf<PI, T>::type;
@@ -868,19 +1160,26 @@ static hipError_t ypass_km(const LineCoef& c, const PassArgs& a, DevState* st, i
   dim3 blk(64, kRG);
   dim3 grid((nx + 63) / 64, (nth + kRG - 1) / kRG, batch);
   if (g_prof_on) prof_begin(KF_YTOT * 8 + PI, s);
-  hipLaunchKernelGGL((ytot_kernel<T, PI, K, M>), grid, blk, 0, s, c, a, st, nx, nth, fstride, tot, jln);
+  hipLaunchKernelGGL((ytot_kernel<T, PI, K, M, PER>), grid, blk, 0, s, c, a, st, nx, nth, fstride, tot, jln);
   if (g_prof_on) prof_end(KF_YTOT * 8 + PI, s);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int ncomb = nx * P::F * batch;
+  const int ct = (nth + kCombWaves - 1) / kCombWaves;
+  const dim3 cgrid((nx + 63) / 64, P::F, batch), cblk(64, kCombWaves);
   if (g_prof_on) prof_begin(KF_YCOMB * 8 + PI, s);
-  hipLaunchKernelGGL((ycomb_kernel<T>), dim3((ncomb + 255) / 256), dim3(256), 0, s, c, st, nx, nth, K, P::F, batch,
-                     tot, (const T*)jln);
+  if (ct <= 8)
+    hipLaunchKernelGGL((ycomb_kernel<T, 8>), cgrid, cblk, 0, s, c, st, nx, nth, K, P::F, tot, (const T*)jln);
+  else if (ct <= 16)
+    hipLaunchKernelGGL((ycomb_kernel<T, 16>), cgrid, cblk, 0, s, c, st, nx, nth, K, P::F, tot, (const T*)jln);
+  else if (ct <= 32)
+    hipLaunchKernelGGL((ycomb_kernel<T, 32>), cgrid, cblk, 0, s, c, st, nx, nth, K, P::F, tot, (const T*)jln);
+  else
+    return hipErrorInvalidValue;
   if (g_prof_on) prof_end(KF_YCOMB * 8 + PI, s);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (g_prof_on) prof_begin(KF_YFIN * 8 + PI, s);
-  hipLaunchKernelGGL((yfin_kernel<T, PI, K, M>), grid, blk, 0, s, c, a, st, nx, nth, fstride, (const T*)tot);
+  hipLaunchKernelGGL((yfin_kernel<T, PI, K, M, PER>), grid, blk, 0, s, c, a, st, nx, nth, fstride, (const T*)tot);
   if (g_prof_on) prof_end(KF_YFIN * 8 + PI, s);
   return hipGetLastError();
 }
@@ -889,10 +1188,14 @@ template <typename T, int PI>
 static hipError_t ypass_t(const LineCoef& c, const PassArgs& a, DevState* st, int nx, int batch, void* tot, void* jln,
                           hipStream_t s) {
   constexpr int K = sizeof(T) == 8 ? 8 : 16;
+  const bool per = c.bc == MOLT_BC_PERIODIC;
   switch (c.M) {
-    case 2: return ypass_km<T, PI, K, 2>(c, a, st, nx, batch, (T*)tot, (T*)jln, s);
-    case 4: return ypass_km<T, PI, K, 4>(c, a, st, nx, batch, (T*)tot, (T*)jln, s);
-    case 6: return ypass_km<T, PI, K, 6>(c, a, st, nx, batch, (T*)tot, (T*)jln, s);
+    case 2: return per ? ypass_km<T, PI, K, 2, true>(c, a, st, nx, batch, (T*)tot, (T*)jln, s)
+                       : ypass_km<T, PI, K, 2, false>(c, a, st, nx, batch, (T*)tot, (T*)jln, s);
+    case 4: return per ? ypass_km<T, PI, K, 4, true>(c, a, st, nx, batch, (T*)tot, (T*)jln, s)
+                       : ypass_km<T, PI, K, 4, false>(c, a, st, nx, batch, (T*)tot, (T*)jln, s);
+    case 6: return per ? ypass_km<T, PI, K, 6, true>(c, a, st, nx, batch, (T*)tot, (T*)jln, s)
+                       : ypass_km<T, PI, K, 6, false>(c, a, st, nx, batch, (T*)tot, (T*)jln, s);
   }
   return hipErrorInvalidValue;
 }

@@ -12,7 +12,8 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libmolt.so")
+#: the in-tree library; MOLT_LIB may name another build of the same sources
+LIB_PATH = os.environ.get("MOLT_LIB", os.path.join(HERE, "libmolt.so"))
 
 MOLT_OK, MOLT_NOT_CONVERGED = 0, 1
 MOLT_EINVAL, MOLT_EUNSUPPORTED, MOLT_EHIP, MOLT_EWORKSPACE = -1, -2, -3, -4
