@@ -172,6 +172,17 @@ typedef struct {
 int32_t molt_profile(int32_t enable);
 int32_t molt_profile_read(molt_prof_entry* out, int32_t max_entries);
 
+/*
+ * Tuning options (process-wide; not part of the method).
+ *  MOLT_OPT_FUSED_Y_MIN_ITEMS: the single-kernel y-pass (FP32, periodic) is
+ *    used when a pass has at least this many (64-column x segment) work items;
+ *    0 uses it whenever it applies; the default (2^40) never does, because
+ *    on the 4096^2 workload it has not yet beaten the three-kernel y-pass.
+ * Returns MOLT_OK or MOLT_EINVAL for an unknown option or a negative value.
+ */
+#define MOLT_OPT_FUSED_Y_MIN_ITEMS 1
+int32_t molt_set_option(int32_t option, int64_t value);
+
 /* Static name of a status code. */
 const char* molt_strerror(int32_t status);
 

@@ -14,7 +14,10 @@ namespace molt {
 hipError_t launch_xpass(int prec, int prog, const LineCoef& c, const PassArgs& a, DevState* st, int nlines,
                         double* rpart, hipStream_t s);
 hipError_t launch_ypass(int prec, int prog, const LineCoef& c, const PassArgs& a, DevState* st, int nx, int batch,
-                        void* tot, void* jln, hipStream_t s);
+                        void* tot, void* jln, const YFused* fz, hipStream_t s);
+size_t yfused_items(int n, int nx, int batch);
+size_t yfused_rec_words(int n, int nx, int batch);
+hipError_t launch_zero_ints(int* p, int n, hipStream_t s);
 hipError_t launch_pointwise(int prec, int prog, const PassArgs& a, DevState* st, size_t nelem, hipStream_t s);
 hipError_t launch_state_init(DevState* st, double tol, int max_iter, int fixed, hipStream_t s);
 hipError_t launch_copy(int prec, void* dst, const void* src, size_t n, hipStream_t s);
@@ -47,6 +50,7 @@ static int32_t fail(int32_t code, const std::string& msg) {
 // per-kernel HIP-event profiler (process-wide; meant for one profiling thread)
 // --------------------------------------------------------------------------
 bool g_prof_on = false;
+static long long g_fused_min_items = 1LL << 40;  // single-kernel y-pass off by default
 namespace {
 struct PendingEv {
   int kind;
@@ -74,14 +78,14 @@ hipEvent_t ev_get() {
 void prof_begin(int kind, hipStream_t s) {
   std::lock_guard<std::mutex> lk(g_prof_mu);
   hipEvent_t e = ev_get();
-  if (e) hipEventRecord(e, s);
+  if (e) (void)hipEventRecord(e, s);
   g_open[kind] = e;
 }
 
 void prof_end(int kind, hipStream_t s) {
   std::lock_guard<std::mutex> lk(g_prof_mu);
   hipEvent_t e = ev_get();
-  if (e) hipEventRecord(e, s);
+  if (e) (void)hipEventRecord(e, s);
   if (g_open[kind] && e) g_pending.push_back({kind, g_open[kind], e});
   g_open[kind] = nullptr;
 }
@@ -244,7 +248,7 @@ enum { F_R = 0, F_DL, F_W, F_A1, F_B1, F_C, F_Q, F_M, F_N, F_HIST, F_COUNT };
 
 struct Layout {
   size_t fld[F_COUNT];
-  size_t tot, jln, state, partials, rpart, total;
+  size_t tot, jln, state, partials, rpart, frec, total;
 };
 
 static Layout ch_layout(const molt_grid* g, int prec) {
@@ -266,6 +270,8 @@ static Layout ch_layout(const molt_grid* g, int prec) {
   off += al256((size_t)2 * diag_blocks(n) * sizeof(double));
   L.rpart = off;  // one residual slot per x-pass block (at most one block per row)
   off += al256((size_t)g->ny * sizeof(double));
+  L.frec = off;  // fused y-pass: published segment totals
+  off += al256(g->ny > 1 ? yfused_rec_words(g->ny, g->nx, 1) * sizeof(unsigned long long) : 0);
   L.total = off;
   return L;
 }
@@ -302,6 +308,17 @@ static int32_t step_impl(const molt_grid* g, const molt_ch_params* p, void* d_u,
   }
 
   HIPCHK(launch_state_init(st, p->tol, p->max_iter, p->fixed_iters, s));
+  YFused fz;
+  memset(&fz, 0, sizeof(fz));
+  if (two_d) {
+    fz.rec = w + L.frec;
+    fz.max_items = yfused_items(ny, nx, 1);
+    fz.min_items = g_fused_min_items > 0x7fffffffLL ? 0x7fffffff : (int)g_fused_min_items;
+    fz.epoch = 0;
+    fz.spin_limit = 1LL << 26;
+    // epochs restart at 1 every step: clear the words (as 32-bit ints)
+    HIPCHK(launch_zero_ints((int*)fz.rec, (int)(2 * yfused_rec_words(ny, nx, 1)), s));
+  }
 
   // R = A1^{-1} A2^{-1} rhs, A_i^{-1} = Lx_i^{-1} Ly_i^{-1}
   PassArgs a;
@@ -311,13 +328,15 @@ static int32_t step_impl(const molt_grid* g, const molt_ch_params* p, void* d_u,
   a.in[1] = bdf2 ? d_u_prev : d_u;
   if (two_d) {
     a.out[0] = F[F_A1];
-    HIPCHK(launch_ypass(prec, PROG_RHS, cy2, a, nullptr, nx, 1, tot, jln, s));
+    ++fz.epoch;
+    HIPCHK(launch_ypass(prec, PROG_RHS, cy2, a, st, nx, 1, tot, jln, &fz, s));
     a.in[0] = F[F_A1];
     a.out[0] = F[F_B1];
     HIPCHK(launch_xpass(prec, PROG_SWEEP, cx2, a, nullptr, ny, nullptr, s));
     a.in[0] = F[F_B1];
     a.out[0] = F[F_A1];
-    HIPCHK(launch_ypass(prec, PROG_SWEEP, cy1, a, nullptr, nx, 1, tot, jln, s));
+    ++fz.epoch;
+    HIPCHK(launch_ypass(prec, PROG_SWEEP, cy1, a, st, nx, 1, tot, jln, &fz, s));
     a.in[0] = F[F_A1];
     a.out[0] = F[F_R];
     HIPCHK(launch_xpass(prec, PROG_SWEEP, cx1, a, nullptr, ny, nullptr, s));
@@ -352,10 +371,12 @@ static int32_t step_impl(const molt_grid* g, const molt_ch_params* p, void* d_u,
       q.in[2] = F[F_DL];
       q.out[0] = F[F_A1];
       q.out[1] = F[F_B1];
-      if (two_d)
-        HIPCHK(launch_ypass(prec, PROG_P1, cy1, q, st, nx, 1, tot, jln, s));
-      else
+      if (two_d) {
+        ++fz.epoch;
+        HIPCHK(launch_ypass(prec, PROG_P1, cy1, q, st, nx, 1, tot, jln, &fz, s));
+      } else {
         HIPCHK(launch_pointwise(prec, PROG_P1, q, st, n, s));
+      }
       // P2 (x, alpha1): C, q
       q.in[0] = F[F_A1];
       q.in[1] = F[F_B1];
@@ -370,10 +391,12 @@ static int32_t step_impl(const molt_grid* g, const molt_ch_params* p, void* d_u,
       q.in[1] = F[F_Q];
       q.out[0] = F[F_M];
       q.out[1] = F[F_N];
-      if (two_d)
-        HIPCHK(launch_ypass(prec, PROG_P3, cy2, q, st, nx, 1, tot, jln, s));
-      else
+      if (two_d) {
+        ++fz.epoch;
+        HIPCHK(launch_ypass(prec, PROG_P3, cy2, q, st, nx, 1, tot, jln, &fz, s));
+      } else {
         HIPCHK(launch_pointwise(prec, PROG_P3, q, st, n, s));
+      }
       // P4 (x, alpha2): increment and running sum, residual
       q.in[0] = F[F_M];
       q.in[1] = F[F_N];
@@ -394,6 +417,7 @@ static int32_t step_impl(const molt_grid* g, const molt_ch_params* p, void* d_u,
   HIPCHK(hipMemcpyAsync(&hst, st, sizeof(DevState), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   if (g_prof_on) prof_drain();
+  if (hst.error) return fail(MOLT_EHIP, "a y-pass segment exchange exceeded its wait bound");
   const bool conv = fixed > 0 || hst.last_resid < p->tol;
   if (info) {
     info->iters = hst.iters;
@@ -438,6 +462,14 @@ const char* molt_strerror(int32_t status) {
 }
 
 const char* molt_last_error(void) { return g_err.c_str(); }
+
+int32_t molt_set_option(int32_t option, int64_t value) {
+  if (option == MOLT_OPT_FUSED_Y_MIN_ITEMS && value >= 0) {
+    g_fused_min_items = value;
+    return MOLT_OK;
+  }
+  return fail(MOLT_EINVAL, "unknown option or negative value");
+}
 
 int32_t molt_profile(int32_t enable) {
   prof_drain();
@@ -512,7 +544,7 @@ int32_t mol_t_helmholtz_sweep(const molt_grid* g, int32_t axis, double alpha, in
   }
   const double hy = spacing(g->bc, g->ny, g->y0, g->y1);
   const LineCoef c = make_line(g->ny, g->bc, g->order_M, alpha, hy);
-  HIPCHK(launch_ypass(precision, PROG_SWEEP, c, a, nullptr, g->nx, (int)batch, tot, jln, s));
+  HIPCHK(launch_ypass(precision, PROG_SWEEP, c, a, nullptr, g->nx, (int)batch, tot, jln, nullptr, s));
   return MOLT_OK;
 }
 

@@ -46,7 +46,7 @@ struct DevState {
   int iters;                      // iterations completed in this step
   int max_iter;
   int fixed;                      // >0: never stop early
-  int pad0;
+  int error;                      // set by a kernel whose bounded wait expired
   double tol;
   double last_resid;
   double mass, energy;
@@ -61,6 +61,15 @@ struct PassArgs {
   double kappa;    // a/s1
   int mode;        // 0: full form (first iteration), 1: increment form
   int bdf2;        // rhs program: 1 -> (4u - u_prev)/3
+};
+
+// Workspace and control of the fused (single-kernel) y-pass.
+struct YFused {
+  void* rec;               // per work item: published segment totals, 64-bit (value, epoch) words
+  size_t max_items;        // capacity of rec in work items
+  int min_items;           // use the fused path only from this many work items
+  int epoch;               // differs from every epoch left in rec since it was zeroed
+  long long spin_limit;    // bound of the wait loop (sets DevState::error when hit)
 };
 
 // Optional per-kernel timing with HIP events on the launch stream (off unless

@@ -221,9 +221,16 @@ struct Seg {
   T ex[E > 0 ? E : 1][K];      // kept values of the owned nodes
 
   __device__ void build(const LineCoef& c, const PassArgs& a, size_t lbase, size_t stride, int j0, bool vec) {
+    T s[F][W];
+    window(c, a, lbase, stride, j0, vec, s);
+    stencils(c, a, lbase, stride, j0, s);
+  }
+
+  // swept values on nodes j0-H .. j0+K+H-1 (and the kept values of the owned nodes)
+  __device__ void window(const LineCoef& c, const PassArgs& a, size_t lbase, size_t stride, int j0, bool vec,
+                         T (&s)[F][W]) {
     const int n = c.n;
     constexpr bool per = PER;
-    T s[F][W];
     if (vec && j0 + K <= n) {
 #pragma unroll
       for (int q = 0; q < K / V; ++q) {
@@ -280,7 +287,6 @@ struct Seg {
 #pragma unroll
       for (int f = 0; f < F; ++f) s[f][kk] = sv[f];
     }
-    stencils(c, a, lbase, stride, j0, s);
   }
 
   // J^L, J^R on the owned nodes from the window values s (nodes j0-H ..
@@ -702,20 +708,26 @@ __global__ void MOLT_PASS_ATTR xpass_kernel(const LineCoef c, const PassArgs a, 
     }
   }
   __syncthreads();
+  // the FP64 2x2 boundary solve, once per line
+  if (act && t < F) {
+    double Ba, Bb;
+    boundary_terms(c, sh_line[lil][t][0], sh_line[lil][t][1], sh_line[lil][t][2], Ba, Bb);
+    sh_line[lil][t][0] = Ba;
+    sh_line[lil][t][1] = Bb;
+  }
+  __syncthreads();
 
   // phase C: seeded scans; the swept values go back to LDS (every read of the
   // window happened before the barriers of the carry scan above)
   if (has) {
     const int jlast = min(j0 + K - 1, n - 1);
-    const double pL = exp(-c.nu * (double)j0);
-    const double pR = exp(-c.nu * (double)(c.N - jlast));
+    const T pL = dpow<T>(c.nu, (double)j0);
+    const T pR = dpow<T>(c.nu, (double)(c.N - jlast));
     T gL[F], gR[F];
 #pragma unroll
     for (int f = 0; f < F; ++f) {
-      double Ba, Bb;
-      boundary_terms(c, sh_line[lil][f][0], sh_line[lil][f][1], sh_line[lil][f][2], Ba, Bb);
-      gL[f] = (T)(c.d * (double)cL[f] + 2.0 * Ba * pL);
-      gR[f] = (T)(c.d * (double)cR[f] + 2.0 * Bb * pR);
+      gL[f] = d * cL[f] + (T)(2.0 * sh_line[lil][f][0]) * pL;
+      gR[f] = d * cR[f] + (T)(2.0 * sh_line[lil][f][1]) * pR;
     }
     T w[F][K];
     seg.finalize(d, j0, n, gL, gR, w);
@@ -785,30 +797,58 @@ __global__ void MOLT_PASS_ATTR xpass_kernel(const LineCoef c, const PassArgs a, 
 constexpr int kRG = 4;
 
 template <typename T, int PI, int K, int M, bool PER>
-__global__ void MOLT_PASS_ATTR ytot_kernel(const LineCoef c, const PassArgs a, DevState* st, int nx,
-                                                   int nth, size_t fstride, T* tot, T* jlnb) {
+__global__ void MOLT_PASS_ATTR ytot_kernel(const LineCoef c, const PassArgs a, DevState* st, int nx, int nth,
+                                           int nseg, size_t fstride, T* agg, T* jlnb) {
   using P = typename ProgOf<PI, T>::type;
   constexpr int F = P::F;
   if (st != nullptr && st->done) return;
-  const int col = blockIdx.x * 64 + threadIdx.x;
-  const int t = blockIdx.y * kRG + threadIdx.y;
+  __shared__ T shA[F][2][kRG][64];
+  const int lx = threadIdx.x, r = threadIdx.y;
+  const int col = blockIdx.x * 64 + lx;
+  const int sg = blockIdx.y;
+  const int t = sg * kRG + r;
   const int b = blockIdx.z;
-  if (col >= nx || t >= nth) return;
+  const bool ok = col < nx && t < nth;
   const int n = c.n, j0 = t * K;
-  const size_t lbase = (size_t)b * fstride + (size_t)col;
-  Seg<T, P, K, M, PER> seg;
-  seg.build(c, a, lbase, (size_t)nx, j0, false);
+  const size_t lbase = (size_t)b * fstride + (size_t)(col < nx ? col : 0);
   T AL[F], AR[F];
-  seg.totals((T)c.d, j0, n, AL, AR);
-  T* tb = tot + (size_t)b * (size_t)(F * 2) * nth * nx;
+  if (ok) {
+    Seg<T, P, K, M, PER> seg;
+    seg.build(c, a, lbase, (size_t)nx, j0, false);
+    seg.totals((T)c.d, j0, n, AL, AR);
+    if (t == 0) {
+#pragma unroll
+      for (int f = 0; f < F; ++f) jlnb[((size_t)b * F + f) * nx + col] = seg.jln[f];
+    }
+  } else {
+#pragma unroll
+    for (int f = 0; f < F; ++f) AL[f] = AR[f] = T(0);
+  }
 #pragma unroll
   for (int f = 0; f < F; ++f) {
-    tb[((size_t)(f * 2 + 0) * nth + t) * nx + col] = AL[f];
-    tb[((size_t)(f * 2 + 1) * nth + t) * nx + col] = AR[f];
+    shA[f][0][r][lx] = AL[f];
+    shA[f][1][r][lx] = AR[f];
   }
-  if (t == 0) {
+  __syncthreads();
+  if (r != 0 || col >= nx) return;
+  // the segment's zero-seeded totals: L at its last row, R at its first row
+  const int j0s = sg * kRG * K;
+  const int jls = min(j0s + kRG * K - 1, n - 1);
+  T* ab = agg + (size_t)b * (size_t)(F * 2) * nseg * nx;
 #pragma unroll
-    for (int f = 0; f < F; ++f) jlnb[((size_t)b * F + f) * nx + col] = seg.jln[f];
+  for (int f = 0; f < F; ++f) {
+    T L = T(0), R = T(0);
+#pragma unroll
+    for (int g = 0; g < kRG; ++g) {
+      const int tt = sg * kRG + g;
+      if (tt < nth) {
+        const int jl = min(tt * K + K - 1, n - 1);
+        L += dpow<T>(c.nu, (double)(jls - jl)) * shA[f][0][g][lx];
+        R += dpow<T>(c.nu, (double)(tt * K - j0s)) * shA[f][1][g][lx];
+      }
+    }
+    ab[((size_t)(f * 2 + 0) * nseg + sg) * nx + col] = L;
+    ab[((size_t)(f * 2 + 1) * nseg + sg) * nx + col] = R;
   }
 }
 
@@ -905,29 +945,247 @@ __global__ void __launch_bounds__(1024) ycomb_kernel(const LineCoef c, DevState*
 }
 
 template <typename T, int PI, int K, int M, bool PER>
-__global__ void MOLT_PASS_ATTR yfin_kernel(const LineCoef c, const PassArgs a, DevState* st, int nx,
-                                                   int nth, size_t fstride, const T* seeds) {
+__global__ void MOLT_PASS_ATTR yfin_kernel(const LineCoef c, const PassArgs a, DevState* st, int nx, int nth,
+                                           int nseg, size_t fstride, const T* seeds) {
   using P = typename ProgOf<PI, T>::type;
   constexpr int F = P::F;
   if (st != nullptr && st->done) return;
-  const int col = blockIdx.x * 64 + threadIdx.x;
-  const int t = blockIdx.y * kRG + threadIdx.y;
+  __shared__ T shA[F][2][kRG][64];
+  const int lx = threadIdx.x, r = threadIdx.y;
+  const int col = blockIdx.x * 64 + lx;
+  const int sg = blockIdx.y;
+  const int t = sg * kRG + r;
   const int b = blockIdx.z;
-  if (col >= nx || t >= nth) return;
+  const bool ok = col < nx && t < nth;
   const int n = c.n, j0 = t * K;
-  const size_t lbase = (size_t)b * fstride + (size_t)col;
+  const size_t lbase = (size_t)b * fstride + (size_t)(col < nx ? col : 0);
+  const T d = (T)c.d;
   Seg<T, P, K, M, PER> seg;
-  seg.build(c, a, lbase, (size_t)nx, j0, false);
-  const T* sb = seeds + (size_t)b * (size_t)(F * 2) * nth * nx;
+  T AL[F], AR[F];
+  if (ok) {
+    seg.build(c, a, lbase, (size_t)nx, j0, false);
+    seg.totals(d, j0, n, AL, AR);
+  } else {
+#pragma unroll
+    for (int f = 0; f < F; ++f) AL[f] = AR[f] = T(0);
+  }
+#pragma unroll
+  for (int f = 0; f < F; ++f) {
+    shA[f][0][r][lx] = AL[f];
+    shA[f][1][r][lx] = AR[f];
+  }
+  __syncthreads();
+  if (!ok) return;
+  // carries from the other thread rows of the segment (all rows before a
+  // thread with nodes are full, rows after it start K apart), then the
+  // segment's seeds propagated to this thread's first / last node
+  const T mK = dpow<T>(c.nu, (double)K);
+  const int j0s = sg * kRG * K;
+  const int jls = min(j0s + kRG * K - 1, n - 1);
+  const int jlt = min(j0 + K - 1, n - 1);
+  const T* sb = seeds + (size_t)b * (size_t)(F * 2) * nseg * nx;
+  const T pl = dpow<T>(c.nu, (double)(j0 - j0s)), pr = dpow<T>(c.nu, (double)(jls - jlt));
   T gL[F], gR[F];
 #pragma unroll
   for (int f = 0; f < F; ++f) {
-    gL[f] = sb[((size_t)(f * 2 + 0) * nth + t) * nx + col];
-    gR[f] = sb[((size_t)(f * 2 + 1) * nth + t) * nx + col];
+    T cl = T(0), cr = T(0);
+    for (int g = 0; g < r; ++g) cl = mK * cl + shA[f][0][g][lx];
+    for (int g = kRG - 1; g > r; --g)
+      if (sg * kRG + g < nth) cr = mK * cr + shA[f][1][g][lx];
+    gL[f] = d * cl + pl * sb[((size_t)(f * 2 + 0) * nseg + sg) * nx + col];
+    gR[f] = d * cr + pr * sb[((size_t)(f * 2 + 1) * nseg + sg) * nx + col];
   }
   T w[F][K];
-  seg.finalize((T)c.d, j0, n, gL, gR, w);
+  seg.finalize(d, j0, n, gL, gR, w);
   seg.store(a, lbase, (size_t)nx, j0, n, false, w);
+}
+
+// --------------------------------------------------------------------------
+// Fused y-pass (one kernel, no second read of the inputs).  A block is 64
+// columns x kRGF thread rows (a segment of kRGF*K rows).  Work items are
+// (batch entry, 64-column strip, segment), strip-major; the grid is launched
+// cooperatively (every block resident) and walks the items in rounds of
+// gridDim.x, a multiple of the segments per strip, so all segments of a strip
+// run at the same time.  Per item: window and zero-seeded totals in registers,
+// the segment's totals published with agent-scope atomic stores and a release
+// flag, a bounded wait for the strip's other segments, an FP64 combine (carries
+// into this segment, line totals, boundary solve), then the seeded scans and
+// outputs from the registers.
+// --------------------------------------------------------------------------
+// thread rows per block of the fused y-pass
+#ifndef MOLT_RGF
+#define MOLT_RGF 16
+#endif
+constexpr int kRGF = MOLT_RGF;
+// rows per thread of the fused y-pass (its window and stencils must fit the
+// 128 VGPRs a 1024-thread block allows)
+#ifndef MOLT_KF
+#define MOLT_KF 16
+#endif
+constexpr int kKF = MOLT_KF;
+
+// A published value travels with the epoch of its launch in one 64-bit word
+// (relaxed agent-scope atomics): a reader that sees the current epoch sees the
+// value, so no flags and no release/acquire fences are needed.
+__device__ __forceinline__ unsigned long long pack_ep(float v, int epoch) {
+  return ((unsigned long long)(unsigned)epoch << 32) | (unsigned long long)__float_as_uint(v);
+}
+constexpr int kMaxGF = 32;  // segments per strip the fused y-pass combines in LDS
+
+template <typename T, int PI, int K, int M, bool PER>
+__global__ void __launch_bounds__(64 * kRGF) yfused_kernel(const LineCoef c, const PassArgs a, DevState* st, int nx,
+                                                      int nth, int G, int nstrips, int nitems, size_t fstride,
+                                                      unsigned long long* rec, int epoch, long long spin_limit) {
+  using P = typename ProgOf<PI, T>::type;
+  constexpr int F = P::F;
+  constexpr int REC = 3 * F * 64;  // words per item: [f][L,R][lane], then [f][lane] J^L of the wrap cell
+  if (st != nullptr && st->done) return;
+  __shared__ T shA[F][2][kRGF][64];
+  __shared__ float shG[F][2][kMaxGF][64];
+  __shared__ float shJ[F][64];
+  __shared__ T shSeed[F][2][64];
+  const int lx = threadIdx.x, r = threadIdx.y;
+  const int n = c.n;
+  const T d = (T)c.d;
+  const int S = kRGF * K;
+  const double mS = exp(-c.nu * (double)S);
+  const T mK = dpow<T>(c.nu, (double)K);
+  for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
+    const int g = item % G;
+    const int qb = item / G;
+    const int q = qb % nstrips;
+    const int b = qb / nstrips;
+    const int col = q * 64 + lx;
+    const int t = g * kRGF + r;
+    const bool ok = col < nx && t < nth;
+    const int j0 = t * K;
+    const size_t lbase = (size_t)b * fstride + (size_t)(col < nx ? col : 0);
+    Seg<T, P, K, M, PER> seg;
+    T sw[F][Seg<T, P, K, M, PER>::W];  // kept across the wait; the stencils are formed twice
+    T AL[F], AR[F];
+    if (ok) {
+      seg.window(c, a, lbase, (size_t)nx, j0, false, sw);
+      seg.stencils(c, a, lbase, (size_t)nx, j0, sw);
+      seg.totals(d, j0, n, AL, AR);
+    } else {
+#pragma unroll
+      for (int f = 0; f < F; ++f) AL[f] = AR[f] = T(0);
+    }
+#pragma unroll
+    for (int f = 0; f < F; ++f) {
+      shA[f][0][r][lx] = AL[f];
+      shA[f][1][r][lx] = AR[f];
+    }
+    __syncthreads();
+    const int j0s = g * S;
+    const int jls = min(j0s + S - 1, n - 1);
+    // publish this segment's zero-seeded totals (L at its last row, R at its first)
+    if (r == 0) {
+      unsigned long long* mine = rec + (size_t)item * REC;
+#pragma unroll
+      for (int f = 0; f < F; ++f) {
+        float L = 0.f, R = 0.f;
+        for (int gg = 0; gg < kRGF; ++gg) {
+          const int tt = g * kRGF + gg;
+          if (tt < nth) {
+            L += (float)(dpow<T>(c.nu, (double)(jls - min(tt * K + K - 1, n - 1))) * shA[f][0][gg][lx]);
+            R += (float)(dpow<T>(c.nu, (double)(tt * K - j0s)) * shA[f][1][gg][lx]);
+          }
+        }
+        __hip_atomic_store(mine + (f * 2 + 0) * 64 + lx, pack_ep(L, epoch), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(mine + (f * 2 + 1) * 64 + lx, pack_ep(R, epoch), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+        if (g == 0)
+          __hip_atomic_store(mine + (2 * F + f) * 64 + lx, pack_ep(ok ? (float)seg.jln[f] : 0.f, epoch),
+                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+    // gather the strip's totals: thread row r polls segments r, r+kRGF, ...
+    // (bounded: a resident grid never needs the bound)
+    {
+      const unsigned long long* strip = rec + (size_t)qb * G * REC;
+      long long spins = 0;
+      bool timed_out = false;
+      for (int gg = r; gg < G; gg += kRGF) {
+#pragma unroll
+        for (int fd = 0; fd < 2 * F; ++fd) {
+          const unsigned long long* p = strip + (size_t)gg * REC + fd * 64 + lx;
+          unsigned long long wv = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          while ((int)(wv >> 32) != epoch && !timed_out) {
+            __builtin_amdgcn_s_sleep(1);
+            wv = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            timed_out = ++spins > spin_limit;
+          }
+          shG[fd >> 1][fd & 1][gg][lx] = __uint_as_float((unsigned)(wv & 0xffffffffull));
+        }
+      }
+      if (r == 0) {
+#pragma unroll
+        for (int f = 0; f < F; ++f) {
+          const unsigned long long* p = strip + (2 * F + f) * 64 + lx;
+          unsigned long long wv = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          while ((int)(wv >> 32) != epoch && !timed_out) {
+            __builtin_amdgcn_s_sleep(1);
+            wv = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            timed_out = ++spins > spin_limit;
+          }
+          shJ[f][lx] = __uint_as_float((unsigned)(wv & 0xffffffffull));
+        }
+      }
+      if (timed_out && st != nullptr) __hip_atomic_store(&st->error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    // FP64 combine over the strip's segments: this segment's seeds
+    if (r == 0 && col < nx) {
+#pragma unroll
+      for (int f = 0; f < F; ++f) {
+        double run = 0.0, cLg = 0.0, TLl = 0.0;
+        for (int gg = 0; gg < G; ++gg) {
+          const double v = (double)shG[f][0][gg][lx];
+          if (gg == g) cLg = run;
+          if (gg == G - 1) TLl = v + exp(-c.nu * (double)(n - gg * S)) * run;
+          run = mS * run + v;
+        }
+        double cRg = 0.0, TRl = 0.0;
+        run = 0.0;
+        for (int gg = G - 1; gg >= 0; --gg) {
+          const double v = (double)shG[f][1][gg][lx];
+          if (gg == g) cRg = run;
+          if (gg == 0) TRl = v + mS * run;
+          run = mS * run + v;
+        }
+        double Ba, Bb;
+        boundary_terms(c, TLl, TRl, (double)shJ[f][lx], Ba, Bb);
+        shSeed[f][0][lx] = (T)(c.d * cLg + 2.0 * Ba * exp(-c.nu * (double)j0s));
+        shSeed[f][1][lx] = (T)(c.d * cRg + 2.0 * Bb * exp(-c.nu * (double)(c.N - jls)));
+      }
+    }
+    __syncthreads();
+    if (ok) {
+      const int jlt = min(j0 + K - 1, n - 1);
+      const T pl = dpow<T>(c.nu, (double)(j0 - j0s)), pr = dpow<T>(c.nu, (double)(jls - jlt));
+      T gL[F], gR[F];
+#pragma unroll
+      for (int f = 0; f < F; ++f) {
+        T cl = T(0), cr = T(0);
+        for (int gg = 0; gg < r; ++gg) cl = mK * cl + shA[f][0][gg][lx];
+        for (int gg = kRGF - 1; gg > r; --gg)
+          if (g * kRGF + gg < nth) cr = mK * cr + shA[f][1][gg][lx];
+        gL[f] = d * cl + pl * shSeed[f][0][lx];
+        gR[f] = d * cr + pr * shSeed[f][1][lx];
+      }
+      seg.stencils(c, a, lbase, (size_t)nx, j0, sw);
+      T w[F][K];
+      seg.finalize(d, j0, n, gL, gR, w);
+      seg.store(a, lbase, (size_t)nx, j0, n, false, w);
+    }
+    __syncthreads();  // LDS is reused by the next item
+  }
+}
+
+__global__ void __launch_bounds__(256) zero_ints_kernel(int* p, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
 }
 
 // pointwise program with the identity in place of the sweep (the y-direction
@@ -959,7 +1217,7 @@ __global__ void state_init_kernel(DevState* st, double tol, int max_iter, int fi
     st->iters = 0;
     st->max_iter = max_iter;
     st->fixed = fixed;
-    st->pad0 = 0;
+    st->error = 0;
     st->tol = tol;
     st->last_resid = 0.0;
     st->mass = 0.0;
@@ -1145,10 +1403,23 @@ hipError_t launch_xpass(int prec, int prog, const LineCoef& c, const PassArgs& a
 
 static int ky_of(int prec) { return prec == MOLT_F64 ? 8 : 16; }
 
+// fused y-pass work items and record elements (FP32 path)
+size_t yfused_items(int n, int nx, int batch) {
+  const int nth = (n + kKF - 1) / kKF;
+  return (size_t)batch * ((nx + 63) / 64) * ((nth + kRGF - 1) / kRGF);
+}
+size_t yfused_rec_words(int n, int nx, int batch) { return yfused_items(n, nx, batch) * 3 * 2 * 64; }
+
+hipError_t launch_zero_ints(int* p, int n, hipStream_t s) {
+  hipLaunchKernelGGL(zero_ints_kernel, dim3((n + 255) / 256 < 1024 ? (n + 255) / 256 : 1024), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+
 size_t ypass_tot_elems(int prec, int n, int nx, int batch) {
   const int K = ky_of(prec);
   const int nth = (n + K - 1) / K;
-  return (size_t)2 * 2 * nth * nx * batch;  // F <= 2 fields, 2 directions
+  const int nseg = (nth + kRG - 1) / kRG;
+  return (size_t)2 * 2 * nseg * nx * batch;  // F <= 2 fields, 2 directions, one entry per segment
 }
 
 template <typename T, int PI, int K, int M, bool PER>
@@ -1156,38 +1427,97 @@ static hipError_t ypass_km(const LineCoef& c, const PassArgs& a, DevState* st, i
                            hipStream_t s) {
   using P = typename ProgOf<PI, T>::type;
   const int nth = (c.n + K - 1) / K;
+  const int nseg = (nth + kRG - 1) / kRG;
   const size_t fstride = (size_t)c.n * nx;
   dim3 blk(64, kRG);
-  dim3 grid((nx + 63) / 64, (nth + kRG - 1) / kRG, batch);
+  dim3 grid((nx + 63) / 64, nseg, batch);
   if (g_prof_on) prof_begin(KF_YTOT * 8 + PI, s);
-  hipLaunchKernelGGL((ytot_kernel<T, PI, K, M, PER>), grid, blk, 0, s, c, a, st, nx, nth, fstride, tot, jln);
+  hipLaunchKernelGGL((ytot_kernel<T, PI, K, M, PER>), grid, blk, 0, s, c, a, st, nx, nth, nseg, fstride, tot, jln);
   if (g_prof_on) prof_end(KF_YTOT * 8 + PI, s);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int ct = (nth + kCombWaves - 1) / kCombWaves;
+  // the combine runs over segments of kRG*K rows
+  const int ct = (nseg + kCombWaves - 1) / kCombWaves;
   const dim3 cgrid((nx + 63) / 64, P::F, batch), cblk(64, kCombWaves);
+  const int S = kRG * K;
   if (g_prof_on) prof_begin(KF_YCOMB * 8 + PI, s);
   if (ct <= 8)
-    hipLaunchKernelGGL((ycomb_kernel<T, 8>), cgrid, cblk, 0, s, c, st, nx, nth, K, P::F, tot, (const T*)jln);
+    hipLaunchKernelGGL((ycomb_kernel<T, 8>), cgrid, cblk, 0, s, c, st, nx, nseg, S, P::F, tot, (const T*)jln);
   else if (ct <= 16)
-    hipLaunchKernelGGL((ycomb_kernel<T, 16>), cgrid, cblk, 0, s, c, st, nx, nth, K, P::F, tot, (const T*)jln);
+    hipLaunchKernelGGL((ycomb_kernel<T, 16>), cgrid, cblk, 0, s, c, st, nx, nseg, S, P::F, tot, (const T*)jln);
   else if (ct <= 32)
-    hipLaunchKernelGGL((ycomb_kernel<T, 32>), cgrid, cblk, 0, s, c, st, nx, nth, K, P::F, tot, (const T*)jln);
+    hipLaunchKernelGGL((ycomb_kernel<T, 32>), cgrid, cblk, 0, s, c, st, nx, nseg, S, P::F, tot, (const T*)jln);
   else
     return hipErrorInvalidValue;
   if (g_prof_on) prof_end(KF_YCOMB * 8 + PI, s);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (g_prof_on) prof_begin(KF_YFIN * 8 + PI, s);
-  hipLaunchKernelGGL((yfin_kernel<T, PI, K, M, PER>), grid, blk, 0, s, c, a, st, nx, nth, fstride, (const T*)tot);
+  hipLaunchKernelGGL((yfin_kernel<T, PI, K, M, PER>), grid, blk, 0, s, c, a, st, nx, nth, nseg, fstride,
+                     (const T*)tot);
   if (g_prof_on) prof_end(KF_YFIN * 8 + PI, s);
   return hipGetLastError();
 }
 
+// Fused y-pass launch (FP32, periodic, large grids): returns hipSuccess with
+// *used = false when the three-kernel path must be taken instead.
+template <typename T, int PI, int K, int M>
+static hipError_t yfused_km(const LineCoef& c, const PassArgs& a, DevState* st, int nx, int batch, const YFused& fz,
+                            hipStream_t s, bool* used) {
+  *used = false;
+  const int nth = (c.n + K - 1) / K;
+  const int G = (nth + kRGF - 1) / kRGF;
+  const int nstrips = (nx + 63) / 64;
+  const int nitems = batch * nstrips * G;
+  if (nitems < fz.min_items || (size_t)nitems > fz.max_items || G > kMaxGF) return hipSuccess;
+  static int per_cu = -1, ncu = 0;
+  if (per_cu < 0) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return hipErrorInvalidValue;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) ncu = 0;
+    int coop = 0;
+    if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop) ncu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)yfused_kernel<T, PI, K, M, true>,
+                                                     64 * kRGF, 0) != hipSuccess)
+      per_cu = 0;
+  }
+  const int resident = per_cu * ncu;
+  if (resident < G) return hipSuccess;
+  int grid = (resident / G) * G;
+  if (grid > nitems) grid = nitems;
+  LineCoef cc = c;
+  PassArgs aa = a;
+  DevState* stp = st;
+  int nxv = nx, nthv = nth, Gv = G, nsv = nstrips, niv = nitems, ep = fz.epoch;
+  size_t fstride = (size_t)c.n * nx;
+  unsigned long long* rec = (unsigned long long*)fz.rec;
+  long long spin = fz.spin_limit;
+  void* args[] = {&cc, &aa, &stp, &nxv, &nthv, &Gv, &nsv, &niv, &fstride, &rec, &ep, &spin};
+  if (g_prof_on) prof_begin(KF_YFIN * 8 + PI, s);
+  hipError_t e = hipLaunchCooperativeKernel((const void*)yfused_kernel<T, PI, K, M, true>, dim3(grid),
+                                            dim3(64, kRGF), args, 0, s);
+  if (g_prof_on) prof_end(KF_YFIN * 8 + PI, s);
+  if (e == hipSuccess) *used = true;
+  return e;
+}
+
 template <typename T, int PI>
 static hipError_t ypass_t(const LineCoef& c, const PassArgs& a, DevState* st, int nx, int batch, void* tot, void* jln,
-                          hipStream_t s) {
+                          const YFused* fz, hipStream_t s) {
   constexpr int K = sizeof(T) == 8 ? 8 : 16;
+  if constexpr (sizeof(T) == 4) {
+    if (fz != nullptr && fz->rec != nullptr && c.bc == MOLT_BC_PERIODIC) {
+      bool used = false;
+      hipError_t e = hipSuccess;
+      switch (c.M) {
+        case 2: e = yfused_km<T, PI, kKF, 2>(c, a, st, nx, batch, *fz, s, &used); break;
+        case 4: e = yfused_km<T, PI, kKF, 4>(c, a, st, nx, batch, *fz, s, &used); break;
+        case 6: e = yfused_km<T, PI, kKF, 6>(c, a, st, nx, batch, *fz, s, &used); break;
+      }
+      if (e != hipSuccess) return e;
+      if (used) return hipSuccess;
+    }
+  }
   const bool per = c.bc == MOLT_BC_PERIODIC;
   switch (c.M) {
     case 2: return per ? ypass_km<T, PI, K, 2, true>(c, a, st, nx, batch, (T*)tot, (T*)jln, s)
@@ -1201,20 +1531,20 @@ static hipError_t ypass_t(const LineCoef& c, const PassArgs& a, DevState* st, in
 }
 
 hipError_t launch_ypass(int prec, int prog, const LineCoef& c, const PassArgs& a, DevState* st, int nx, int batch,
-                        void* tot, void* jln, hipStream_t s) {
+                        void* tot, void* jln, const YFused* fz, hipStream_t s) {
   if (prec == MOLT_F64) {
     switch (prog) {
-      case PROG_SWEEP: return ypass_t<double, PROG_SWEEP>(c, a, st, nx, batch, tot, jln, s);
-      case PROG_RHS: return ypass_t<double, PROG_RHS>(c, a, st, nx, batch, tot, jln, s);
-      case PROG_P1: return ypass_t<double, PROG_P1>(c, a, st, nx, batch, tot, jln, s);
-      case PROG_P3: return ypass_t<double, PROG_P3>(c, a, st, nx, batch, tot, jln, s);
+      case PROG_SWEEP: return ypass_t<double, PROG_SWEEP>(c, a, st, nx, batch, tot, jln, fz, s);
+      case PROG_RHS: return ypass_t<double, PROG_RHS>(c, a, st, nx, batch, tot, jln, fz, s);
+      case PROG_P1: return ypass_t<double, PROG_P1>(c, a, st, nx, batch, tot, jln, fz, s);
+      case PROG_P3: return ypass_t<double, PROG_P3>(c, a, st, nx, batch, tot, jln, fz, s);
     }
   } else {
     switch (prog) {
-      case PROG_SWEEP: return ypass_t<float, PROG_SWEEP>(c, a, st, nx, batch, tot, jln, s);
-      case PROG_RHS: return ypass_t<float, PROG_RHS>(c, a, st, nx, batch, tot, jln, s);
-      case PROG_P1: return ypass_t<float, PROG_P1>(c, a, st, nx, batch, tot, jln, s);
-      case PROG_P3: return ypass_t<float, PROG_P3>(c, a, st, nx, batch, tot, jln, s);
+      case PROG_SWEEP: return ypass_t<float, PROG_SWEEP>(c, a, st, nx, batch, tot, jln, fz, s);
+      case PROG_RHS: return ypass_t<float, PROG_RHS>(c, a, st, nx, batch, tot, jln, fz, s);
+      case PROG_P1: return ypass_t<float, PROG_P1>(c, a, st, nx, batch, tot, jln, fz, s);
+      case PROG_P3: return ypass_t<float, PROG_P3>(c, a, st, nx, batch, tot, jln, fz, s);
     }
   }
   return hipErrorInvalidValue;

@@ -24,7 +24,9 @@ MOLT_F64, MOLT_F32 = 0, 1
 
 #: every symbol include/molt.h declares
 EXPORTS = ("mol_t_helmholtz_sweep", "molt_sweep_workspace_bytes", "ch_workspace_bytes", "ch_step",
-           "ch_solve", "molt_strerror", "molt_last_error", "molt_profile", "molt_profile_read")
+           "ch_solve", "molt_strerror", "molt_last_error", "molt_profile", "molt_profile_read",
+           "molt_set_option")
+MOLT_OPT_FUSED_Y_MIN_ITEMS = 1
 
 KERNEL_FAMILIES = ("xpass", "ytot", "ycomb", "yfin", "pointwise", "other")
 PROGRAMS = ("sweep", "rhs", "P1", "P2", "P3", "P4")
@@ -90,6 +92,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.molt_strerror.restype = ctypes.c_char_p
     lib.molt_last_error.argtypes = []
     lib.molt_last_error.restype = ctypes.c_char_p
+    lib.molt_set_option.argtypes = [ctypes.c_int32, ctypes.c_int64]
+    lib.molt_set_option.restype = ctypes.c_int32
     lib.molt_profile.argtypes = [ctypes.c_int32]
     lib.molt_profile.restype = ctypes.c_int32
     lib.molt_profile_read.argtypes = [ctypes.POINTER(molt_prof_entry), ctypes.c_int32]
@@ -145,6 +149,10 @@ def molt_strerror(status: int) -> str:
 
 def molt_last_error() -> str:
     return load().molt_last_error().decode()
+
+
+def molt_set_option(option: int, value: int) -> int:
+    return load().molt_set_option(option, value)
 
 
 def molt_profile(enable: int) -> int:

@@ -220,3 +220,38 @@ def test_solve_fp32_against_fp64_oracle(bc):
           f"iters gpu {[i.iters for i in infos][:6]} oracle {[i.iters for i in rinf][:6]}", flush=True)
     assert st == molt.MOLT_OK
     assert err.max() <= 1e-5
+
+
+@pytest.mark.parametrize("shape", [(256, 300), (200, 320), (520, 192)])
+def test_fused_ypass_step_fp32(shape):
+    """The single-kernel y-pass (forced on small grids) against the FP64 oracle
+    and against the three-kernel y-pass: ragged column strips and a ragged last
+    segment; one BE step with 4 fixed iterations, then 3 BDF2 steps of 40."""
+    ny, nx = shape
+    g = molt.make_grid(nx, ny, 0.0, 1.0, 0.0, ny / nx, molt.MOLT_BC_PERIODIC, 4)
+    u0 = synth.u0_uniform_noise(synth.BASE_SEED + 31, ny, nx, 0.3, mean=0.1)
+    po = oracle.Params(eps=0.02, dt=2e-4, fixed_iters=4)
+    ref, _ = oracle.step(_og(g), po, u0)
+    outs = {}
+    try:
+        for name, thr in (("fused", 0), ("three", 1 << 40)):
+            assert molt.molt_set_option(molt.MOLT_OPT_FUSED_Y_MIN_ITEMS, thr) == 0
+            x = torch.tensor(u0, dtype=torch.float32, device=DEV)
+            info = molt.step(x, g, molt.make_params(0.02, 2e-4, precision=molt.MOLT_F32, fixed_iters=4))
+            assert info.iters == 4
+            outs[name] = x.cpu().double().numpy()
+            p = molt.make_params(0.02, 2e-4, stepper=molt.MOLT_BDF2, precision=molt.MOLT_F32, fixed_iters=40)
+            x2 = torch.tensor(u0, dtype=torch.float32, device=DEV)
+            st, infos = molt.solve(x2, g, p, 3)
+            assert st == molt.MOLT_OK and [i.iters for i in infos] == [40, 40, 40]
+            outs[name + "_solve"] = x2.cpu().double().numpy()
+    finally:
+        molt.molt_set_option(molt.MOLT_OPT_FUSED_Y_MIN_ITEMS, 1 << 40)
+    print(f"fused shape={shape}: |fused-oracle| {np.abs(outs['fused'] - ref).max():.2e} "
+          f"|three-oracle| {np.abs(outs['three'] - ref).max():.2e}", flush=True)
+    assert np.abs(outs["fused"] - ref).max() <= 1e-5
+    assert np.abs(outs["three"] - ref).max() <= 1e-5
+    assert np.abs(outs["fused"] - outs["three"]).max() <= 5e-6
+    ref3, _ = oracle.solve(_og(g), oracle.Params(eps=0.02, dt=2e-4, stepper=oracle.BDF2, fixed_iters=40), u0, 3)
+    assert np.abs(outs["fused_solve"] - ref3).max() <= 1e-5
+    assert np.abs(outs["fused_solve"] - outs["three_solve"]).max() <= 1e-5
