@@ -156,6 +156,43 @@ int32_t ch_solve(const molt_grid* grid, const molt_ch_params* params, void* d_u,
                  void* d_work, size_t work_bytes, molt_step_info* per_step, void* stream);
 
 /*
+ * Batched instances (independent problems advanced together on one device).
+ *  grid, params: as for ch_solve; params.have_prev is ignored (a BDF2
+ *                instance starts with a BE step, as in ch_solve).
+ *  d_u:          the instance's device field, u^0 in, u^nsteps out.
+ *  nsteps:       time steps of this instance (0: left unchanged).
+ * Every instance must use the same precision and be two-dimensional (ny > 1)
+ * with periodic or Neumann boundaries; sizes, eps, dt, stepper, tolerance,
+ * order M and boundary kind may differ.  Instances must not share fields.
+ */
+typedef struct {
+  molt_grid grid;
+  molt_ch_params params;
+  void* d_u;
+  int64_t nsteps;
+} molt_instance;
+
+/* Bytes of device workspace ch_solve_batch needs (0 on invalid arguments). */
+size_t ch_batch_workspace_bytes(const molt_instance* inst, int32_t count);
+
+/*
+ * ch_solve_batch -- ch_solve of `count` instances at once (1..65535).  Each
+ * instance advances through its own steps: every device tick runs one
+ * fixed-point iteration (Sec. 5.1) for every instance that is iterating, and
+ * the rhs sweeps R = A1^{-1} A2^{-1} rhs (Sec. 3.1, 4.1) for every instance
+ * that starts a step, so instances with few iterations per step do not wait
+ * for the others.  An instance's results are bitwise independent of the other
+ * instances in the batch.
+ *  per_step: sum(nsteps) records, instance-major (instance 0's steps first),
+ *            or NULL.
+ * Returns MOLT_NOT_CONVERGED if any step of any instance reached max_iter.
+ * Synchronizes `stream` before returning.  With a non-NULL stream the ticks
+ * are replayed as a captured HIP graph (see MOLT_OPT_BATCH_GRAPH).
+ */
+int32_t ch_solve_batch(const molt_instance* inst, int32_t count, void* d_work, size_t work_bytes,
+                       molt_step_info* per_step, void* stream);
+
+/*
  * Kernel timing (not part of the method): HIP events recorded around every
  * kernel the library launches, on the launch stream, accumulated per kind.
  * kind = family*8 + program; family 0 x-pass, 1 y-pass totals, 2 y-pass
@@ -178,9 +215,16 @@ int32_t molt_profile_read(molt_prof_entry* out, int32_t max_entries);
  *    used when a pass has at least this many (64-column x segment) work items;
  *    0 uses it whenever it applies; the default (2^40) never does, because
  *    on the 4096^2 workload it has not yet beaten the three-kernel y-pass.
- * Returns MOLT_OK or MOLT_EINVAL for an unknown option or a negative value.
+ * Returns MOLT_OK or MOLT_EINVAL for an unknown option or a value out of range.
  */
 #define MOLT_OPT_FUSED_Y_MIN_ITEMS 1
+/*  MOLT_OPT_BATCH_TICKS (1..1024, default 8): device ticks of ch_solve_batch
+ *    between two host checks of whether every instance has finished.
+ *  MOLT_OPT_BATCH_GRAPH (0 or 1, default 1): replay those ticks as one
+ *    captured HIP graph (used when the stream is not NULL and kernel timing is
+ *    off); 0 launches the kernels one by one. */
+#define MOLT_OPT_BATCH_TICKS 2
+#define MOLT_OPT_BATCH_GRAPH 3
 int32_t molt_set_option(int32_t option, int64_t value);
 
 /* Static name of a status code. */

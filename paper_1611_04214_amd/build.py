@@ -16,22 +16,29 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmolt.so")
 ARCH = os.environ.get("MOLT_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["molt_kernels.hip", "molt_host.cpp"]
+SOURCES = ["molt_kernels.hip", "molt_batch.hip", "molt_host.cpp"]
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
 
 def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
-    objs = []
-    for src in SOURCES:
-        obj = os.path.join(CSRC, src + ".o")
+    objs, procs = [], []
+    tag = f".{os.getpid()}.o"
+    for src in SOURCES:  # the translation units compile in parallel
+        obj = os.path.join(CSRC, src + tag)
         cmd = ["hipcc", "-c"] + FLAGS + [f"-D{d}" for d in defines] + \
               (["-x", "hip"] if src.endswith(".hip") else []) + [os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.check_call(cmd)
+        procs.append((subprocess.Popen(cmd), cmd))
         objs.append(obj)
+    failed = [cmd for p, cmd in procs if p.wait() != 0]
+    if failed:
+        for o in objs:
+            if os.path.exists(o):
+                os.remove(o)
+        raise subprocess.CalledProcessError(1, failed[0])
     tmp = out + ".tmp"
     cmd = ["hipcc", "-shared", f"--offload-arch={ARCH}", "-fPIC", "-o", tmp] + objs
     if verbose:

@@ -1,0 +1,416 @@
+// molt_batch.hip -- batched kernels: the line passes and the step bookkeeping of
+// many independent Cahn-Hilliard problems ("slots") in one launch per kernel
+// and (stencil order, boundary kind[, x-pass thread granularity]) group.
+//
+// A tick is: y-pass 1, x-pass 2, y-pass 3, x-pass 4, iteration close, step
+// finish, diagnostics, tick end.  A slot in phase PH_R spends its tick on
+// R = A1^{-1} A2^{-1} rhs (Sec. 5.1: y(alpha2) of the rhs, x(alpha2), y(alpha1),
+// x(alpha1)); a slot in phase PH_IT on one fixed-point iteration (the passes
+// P1..P4 of the single-problem path).  When an iteration converges the same
+// tick finishes the step (history rotation, u^{n+1}, mass and energy) and the
+// tick end moves the slot to the R phase of its next step, or to PH_IDLE.
+// Every block finds its (slot, block) in a static map and runs exactly the
+// device body of the single-problem kernels with that slot's coefficients,
+// so a slot's arithmetic does not depend on the other slots of the batch.
+#include "molt_device.h"
+
+namespace molt {
+
+template <typename T>
+struct YK {
+  static constexpr int K = sizeof(T) == 8 ? 8 : 16;  // nodes per thread along y
+};
+
+// arguments of pass `pass` (1..4) of a slot in phase ph (the same fields as
+// the single-problem driver uses)
+__device__ __forceinline__ PassArgs slot_args(const SlotDesc& d, int ph, int pass, int var, int mode) {
+  PassArgs a;
+#pragma unroll
+  for (int i = 0; i < 6; ++i) a.in[i] = nullptr;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) a.out[i] = nullptr;
+  void* const* F = d.fld;
+  if (ph == PH_R) {
+    a.sigma = 0.0;
+    a.kappa = 0.0;
+    a.mode = 0;
+    a.bdf2 = var;
+    if (pass == 1) {
+      a.in[0] = d.u;
+      a.in[1] = var ? F[F_HIST] : d.u;
+      a.out[0] = F[F_A1];
+    } else if (pass == 2) {
+      a.in[0] = F[F_A1];
+      a.out[0] = F[F_B1];
+    } else if (pass == 3) {
+      a.in[0] = F[F_B1];
+      a.out[0] = F[F_A1];
+    } else {
+      a.in[0] = F[F_A1];
+      a.out[0] = F[F_R];
+    }
+  } else {
+    a.sigma = d.sigma[var];
+    a.kappa = d.kappa[var];
+    a.mode = mode;
+    a.bdf2 = 0;
+    const void* base = d.init == MOLT_INIT_LINEAR ? F[F_R] : d.u;
+    if (pass == 1) {
+      a.in[0] = base;
+      a.in[1] = F[F_W];
+      a.in[2] = F[F_DL];
+      a.out[0] = F[F_A1];
+      a.out[1] = F[F_B1];
+    } else if (pass == 2) {
+      a.in[0] = F[F_A1];
+      a.in[1] = F[F_B1];
+      a.in[2] = base;
+      a.in[3] = F[F_W];
+      a.in[4] = F[F_DL];
+      a.out[0] = F[F_C];
+      a.out[1] = F[F_Q];
+    } else if (pass == 3) {
+      a.in[0] = F[F_C];
+      a.in[1] = F[F_Q];
+      a.out[0] = F[F_M];
+      a.out[1] = F[F_N];
+    } else {
+      a.in[0] = F[F_M];
+      a.in[1] = F[F_N];
+      a.in[2] = mode ? F[F_DL] : F[F_R];
+      a.in[3] = F[F_W];
+      a.out[0] = F[F_DL];
+      a.out[1] = F[F_W];
+    }
+  }
+  return a;
+}
+
+// y-pass `PASS` (1 or 3): totals (FIN = false) or final scans (FIN = true)
+template <typename T, int M, bool PER, int PASS, bool FIN>
+__global__ void MOLT_PASS_ATTR ypass_batch_kernel(const SlotDesc* __restrict__ sd, const SlotCtl* __restrict__ ctl,
+                                                  const BlkMap* __restrict__ map) {
+  constexpr int K = YK<T>::K;
+  const BlkMap e = map[blockIdx.x];
+  const SlotDesc& d = sd[e.slot];
+  const SlotCtl cc = ctl[e.slot];
+  if (cc.phase == PH_IDLE) return;
+  const int bx = e.blk % d.ycols, by = e.blk / d.ycols;
+  const size_t fstride = (size_t)d.ny * (size_t)d.nx;
+  const int var = cc.var;
+  if (cc.phase == PH_R) {
+    constexpr int PR = PASS == 1 ? PROG_RHS : PROG_SWEEP;
+    const PassArgs a = slot_args(d, PH_R, PASS, var, 0);
+    const LineCoef& c = d.cy[var][PASS == 1 ? 1 : 0];
+    if constexpr (FIN)
+      yfin_body<T, PR, K, M, PER>(c, a, nullptr, d.nx, d.ynth, d.ynseg, fstride, (const T*)d.tot, bx, by, 0);
+    else
+      ytot_body<T, PR, K, M, PER>(c, a, nullptr, d.nx, d.ynth, d.ynseg, fstride, (T*)d.tot, (T*)d.jln, bx, by, 0);
+  } else {
+    DevState* st = d.st;
+    if (st->done) return;
+    constexpr int PI = PASS == 1 ? PROG_P1 : PROG_P3;
+    const PassArgs a = slot_args(d, PH_IT, PASS, var, st->iters > 0 ? 1 : 0);
+    const LineCoef& c = d.cy[var][PASS == 1 ? 0 : 1];
+    if constexpr (FIN)
+      yfin_body<T, PI, K, M, PER>(c, a, st, d.nx, d.ynth, d.ynseg, fstride, (const T*)d.tot, bx, by, 0);
+    else
+      ytot_body<T, PI, K, M, PER>(c, a, st, d.nx, d.ynth, d.ynseg, fstride, (T*)d.tot, (T*)d.jln, bx, by, 0);
+  }
+}
+
+// y-pass combine of every slot: map block = (slot, strip + ycols * field)
+template <typename T>
+__global__ void __launch_bounds__(1024) ycomb_batch_kernel(const SlotDesc* __restrict__ sd,
+                                                           const SlotCtl* __restrict__ ctl,
+                                                           const BlkMap* __restrict__ map, int pass) {
+  constexpr int K = YK<T>::K;
+  const BlkMap e = map[blockIdx.x];
+  const SlotDesc& d = sd[e.slot];
+  const SlotCtl cc = ctl[e.slot];
+  if (cc.phase == PH_IDLE) return;
+  const bool r = cc.phase == PH_R;
+  const int F = r ? 1 : 2;
+  const int bx = e.blk % d.ycols, f = e.blk / d.ycols;
+  if (f >= F) return;
+  // pass 1: alpha2 in the R phase, alpha1 in an iteration; pass 3 the other way
+  const LineCoef& c = d.cy[cc.var][((pass == 1) == r) ? 1 : 0];
+  ycomb_body<T, 8>(c, r ? nullptr : d.st, d.nx, d.ynseg, kRG * K, F, (T*)d.tot, (const T*)d.jln, bx, f, 0);
+}
+
+// x-pass `PASS` (2 or 4)
+template <typename T, int K, int M, bool PER, int PASS>
+__global__ void MOLT_PASS_ATTR xpass_batch_kernel(const SlotDesc* __restrict__ sd, const SlotCtl* __restrict__ ctl,
+                                                  const BlkMap* __restrict__ map) {
+  const BlkMap e = map[blockIdx.x];
+  const SlotDesc& d = sd[e.slot];
+  const SlotCtl cc = ctl[e.slot];
+  if (cc.phase == PH_IDLE) return;
+  const int var = cc.var;
+  if (cc.phase == PH_R) {
+    const PassArgs a = slot_args(d, PH_R, PASS, var, 0);
+    xpass_body<T, PROG_SWEEP, K, M, PER>(d.cx[var][PASS == 2 ? 1 : 0], a, nullptr, d.ny, d.tlx, nullptr, d.vecx,
+                                         e.blk);
+  } else {
+    DevState* st = d.st;
+    if (st->done) return;
+    constexpr int PI = PASS == 2 ? PROG_P2 : PROG_P4;
+    const PassArgs a = slot_args(d, PH_IT, PASS, var, st->iters > 0 ? 1 : 0);
+    xpass_body<T, PI, K, M, PER>(d.cx[var][PASS == 2 ? 0 : 1], a, st, d.ny, d.tlx, PASS == 4 ? d.rpart : nullptr,
+                                 d.vecx, e.blk);
+  }
+}
+
+// iteration close: one block per slot
+__global__ void __launch_bounds__(256) close_batch_kernel(const SlotDesc* __restrict__ sd,
+                                                          const SlotCtl* __restrict__ ctl) {
+  const SlotDesc& d = sd[blockIdx.x];
+  if (ctl[blockIdx.x].phase != PH_IT) return;
+  residual_close_body(d.rpart, d.xblocks, d.st);
+}
+
+// step finish of converged slots: u^{n-1} <- u^n (the BDF2 history), u^{n+1} = base + W
+template <typename T>
+__global__ void __launch_bounds__(256) finish_batch_kernel(const SlotDesc* __restrict__ sd,
+                                                           const SlotCtl* __restrict__ ctl,
+                                                           const BlkMap* __restrict__ map) {
+  const BlkMap e = map[blockIdx.x];
+  const SlotDesc& d = sd[e.slot];
+  if (ctl[e.slot].phase != PH_IT || !d.st->done) return;
+  const size_t n = (size_t)d.nx * (size_t)d.ny;
+  T* u = (T*)d.u;
+  T* h = (T*)d.fld[F_HIST];
+  const T* base = d.init == MOLT_INIT_LINEAR ? (const T*)d.fld[F_R] : u;
+  const T* W = (const T*)d.fld[F_W];
+  for (size_t i = (size_t)e.blk * blockDim.x + threadIdx.x; i < n; i += (size_t)d.dblocks * blockDim.x) {
+    const T uo = u[i];
+    const T b = base[i];
+    h[i] = uo;
+    u[i] = b + W[i];
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) diag_batch_kernel(const SlotDesc* __restrict__ sd,
+                                                         const SlotCtl* __restrict__ ctl,
+                                                         const BlkMap* __restrict__ map) {
+  const BlkMap e = map[blockIdx.x];
+  const SlotDesc& d = sd[e.slot];
+  if (ctl[e.slot].phase != PH_IT || !d.st->done) return;
+  diag_body<T>((const T*)d.u, d.nx, d.ny, d.bc, d.hx, d.hy, d.eps, d.partials, e.blk, d.dblocks);
+}
+
+// tick end, one block per slot: R -> first iteration (state reset); a finished
+// step -> mass and energy, the step record, then the next step's R phase or idle
+__global__ void __launch_bounds__(256) tick_end_batch_kernel(const SlotDesc* __restrict__ sd, SlotCtl* ctl) {
+  const int slot = blockIdx.x;
+  const SlotDesc& d = sd[slot];
+  const SlotCtl cc = ctl[slot];
+  DevState* st = d.st;
+  const int done = cc.phase == PH_IT ? st->done : 0;
+  __syncthreads();  // every thread has read the control word before it changes
+  if (cc.phase == PH_R) {
+    if (threadIdx.x == 0) {
+      st->resid_bits = 0ull;
+      st->blocks_done = 0u;
+      st->done = 0;
+      st->iters = 0;
+      st->max_iter = d.max_iter;
+      st->fixed = d.fixed;
+      st->error = 0;
+      st->tol = d.tol;
+      st->last_resid = 0.0;
+      st->mass = 0.0;
+      st->energy = 0.0;
+      SlotCtl nc = cc;
+      nc.phase = PH_IT;
+      ctl[slot] = nc;
+    }
+    return;
+  }
+  if (cc.phase != PH_IT || !done) return;
+  diag_final_body(d.partials, d.dblocks, d.area, st);
+  if (threadIdx.x == 0) {
+    const int var = cc.var;
+    molt_step_info r;
+    r.iters = st->iters;
+    r.converged = (d.fixed > 0 || st->last_resid < d.tol) ? 1 : 0;
+    r.residual = st->last_resid;
+    r.mass = st->mass;
+    r.energy = st->energy;
+    r.s1 = d.s1[var];
+    r.s2 = d.s2[var];
+    r.sigma = d.sigma[var];
+    d.rec[cc.step] = r;
+    SlotCtl nc;
+    nc.step = cc.step + 1;
+    nc.pad = 0;
+    if (nc.step < d.nsteps) {
+      nc.phase = PH_R;
+      nc.var = d.stepper == MOLT_BDF2 ? 1 : 0;
+    } else {
+      nc.phase = PH_IDLE;
+      nc.var = var;
+    }
+    ctl[slot] = nc;
+  }
+}
+
+__global__ void __launch_bounds__(256) init_batch_kernel(const SlotDesc* __restrict__ sd, SlotCtl* ctl, int nslots) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nslots; i += gridDim.x * blockDim.x) {
+    SlotCtl c;
+    c.phase = sd[i].nsteps > 0 ? PH_R : PH_IDLE;
+    c.step = 0;
+    c.var = 0;
+    c.pad = 0;
+    ctl[i] = c;
+  }
+}
+
+// number of slots not yet idle -> *out
+__global__ void __launch_bounds__(256) count_active_kernel(const SlotCtl* __restrict__ ctl, int nslots, int* out) {
+  __shared__ int red[4];
+  int c = 0;
+  for (int i = threadIdx.x; i < nslots; i += blockDim.x) c += ctl[i].phase != PH_IDLE ? 1 : 0;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) c += __shfl_down(c, off);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) out[0] = red[0] + red[1] + red[2] + red[3];
+}
+
+// --------------------------------------------------------------------------
+// launchers
+// --------------------------------------------------------------------------
+template <typename T, int M, bool PER>
+static hipError_t ybatch_m(int pass, bool fin, const SlotDesc* sd, const SlotCtl* ctl, const BlkMap* map, int nblk,
+                           hipStream_t s) {
+  const dim3 blk(64, kRG);
+  if (pass == 1) {
+    if (fin) hipLaunchKernelGGL((ypass_batch_kernel<T, M, PER, 1, true>), dim3(nblk), blk, 0, s, sd, ctl, map);
+    else hipLaunchKernelGGL((ypass_batch_kernel<T, M, PER, 1, false>), dim3(nblk), blk, 0, s, sd, ctl, map);
+  } else {
+    if (fin) hipLaunchKernelGGL((ypass_batch_kernel<T, M, PER, 3, true>), dim3(nblk), blk, 0, s, sd, ctl, map);
+    else hipLaunchKernelGGL((ypass_batch_kernel<T, M, PER, 3, false>), dim3(nblk), blk, 0, s, sd, ctl, map);
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t ybatch_t(int M, bool per, int pass, bool fin, const SlotDesc* sd, const SlotCtl* ctl,
+                           const BlkMap* map, int nblk, hipStream_t s) {
+  switch (M) {
+    case 2: return per ? ybatch_m<T, 2, true>(pass, fin, sd, ctl, map, nblk, s)
+                       : ybatch_m<T, 2, false>(pass, fin, sd, ctl, map, nblk, s);
+    case 4: return per ? ybatch_m<T, 4, true>(pass, fin, sd, ctl, map, nblk, s)
+                       : ybatch_m<T, 4, false>(pass, fin, sd, ctl, map, nblk, s);
+    case 6: return per ? ybatch_m<T, 6, true>(pass, fin, sd, ctl, map, nblk, s)
+                       : ybatch_m<T, 6, false>(pass, fin, sd, ctl, map, nblk, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_batch_y(int prec, int M, bool per, int pass, bool fin, const SlotDesc* sd, const SlotCtl* ctl,
+                          const BlkMap* map, int nblk, hipStream_t s) {
+  if (nblk <= 0) return hipSuccess;
+  const int kind = (fin ? KF_YFIN : KF_YTOT) * 8 + (pass == 1 ? PROG_P1 : PROG_P3);
+  if (g_prof_on) prof_begin(kind, s);
+  const hipError_t e = prec == MOLT_F64 ? ybatch_t<double>(M, per, pass, fin, sd, ctl, map, nblk, s)
+                                        : ybatch_t<float>(M, per, pass, fin, sd, ctl, map, nblk, s);
+  if (g_prof_on) prof_end(kind, s);
+  return e;
+}
+
+hipError_t launch_batch_comb(int prec, int pass, const SlotDesc* sd, const SlotCtl* ctl, const BlkMap* map, int nblk,
+                             hipStream_t s) {
+  if (nblk <= 0) return hipSuccess;
+  const int kind = KF_YCOMB * 8 + (pass == 1 ? PROG_P1 : PROG_P3);
+  if (g_prof_on) prof_begin(kind, s);
+  const dim3 blk(64, kCombWaves);
+  if (prec == MOLT_F64)
+    hipLaunchKernelGGL((ycomb_batch_kernel<double>), dim3(nblk), blk, 0, s, sd, ctl, map, pass);
+  else
+    hipLaunchKernelGGL((ycomb_batch_kernel<float>), dim3(nblk), blk, 0, s, sd, ctl, map, pass);
+  if (g_prof_on) prof_end(kind, s);
+  return hipGetLastError();
+}
+
+template <typename T, int K, int M, bool PER>
+static hipError_t xbatch_m(int pass, const SlotDesc* sd, const SlotCtl* ctl, const BlkMap* map, int nblk,
+                           hipStream_t s) {
+  if (pass == 2)
+    hipLaunchKernelGGL((xpass_batch_kernel<T, K, M, PER, 2>), dim3(nblk), dim3(256), 0, s, sd, ctl, map);
+  else
+    hipLaunchKernelGGL((xpass_batch_kernel<T, K, M, PER, 4>), dim3(nblk), dim3(256), 0, s, sd, ctl, map);
+  return hipGetLastError();
+}
+
+template <typename T, int K>
+static hipError_t xbatch_k(int M, bool per, int pass, const SlotDesc* sd, const SlotCtl* ctl, const BlkMap* map,
+                           int nblk, hipStream_t s) {
+  switch (M) {
+    case 2: return per ? xbatch_m<T, K, 2, true>(pass, sd, ctl, map, nblk, s)
+                       : xbatch_m<T, K, 2, false>(pass, sd, ctl, map, nblk, s);
+    case 4: return per ? xbatch_m<T, K, 4, true>(pass, sd, ctl, map, nblk, s)
+                       : xbatch_m<T, K, 4, false>(pass, sd, ctl, map, nblk, s);
+    case 6: return per ? xbatch_m<T, K, 6, true>(pass, sd, ctl, map, nblk, s)
+                       : xbatch_m<T, K, 6, false>(pass, sd, ctl, map, nblk, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename T>
+static hipError_t xbatch_t(int K, int M, bool per, int pass, const SlotDesc* sd, const SlotCtl* ctl,
+                           const BlkMap* map, int nblk, hipStream_t s) {
+  switch (K) {
+    case 4: return xbatch_k<T, 4>(M, per, pass, sd, ctl, map, nblk, s);
+    case 8: return xbatch_k<T, 8>(M, per, pass, sd, ctl, map, nblk, s);
+    case 16: return xbatch_k<T, 16>(M, per, pass, sd, ctl, map, nblk, s);
+    case 32:
+      if constexpr (sizeof(T) == 4) return xbatch_k<T, 32>(M, per, pass, sd, ctl, map, nblk, s);
+      return hipErrorInvalidValue;
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_batch_x(int prec, int K, int M, bool per, int pass, const SlotDesc* sd, const SlotCtl* ctl,
+                          const BlkMap* map, int nblk, hipStream_t s) {
+  if (nblk <= 0) return hipSuccess;
+  const int kind = KF_XPASS * 8 + (pass == 2 ? PROG_P2 : PROG_P4);
+  if (g_prof_on) prof_begin(kind, s);
+  const hipError_t e = prec == MOLT_F64 ? xbatch_t<double>(K, M, per, pass, sd, ctl, map, nblk, s)
+                                        : xbatch_t<float>(K, M, per, pass, sd, ctl, map, nblk, s);
+  if (g_prof_on) prof_end(kind, s);
+  return e;
+}
+
+// close, step finish, diagnostics and tick end (kind "other_1")
+hipError_t launch_batch_tail(int prec, const SlotDesc* sd, SlotCtl* ctl, int nslots, const BlkMap* pmap, int npblk,
+                             hipStream_t s) {
+  if (nslots <= 0) return hipSuccess;
+  if (g_prof_on) prof_begin(KF_OTHER * 8 + 1, s);
+  hipLaunchKernelGGL(close_batch_kernel, dim3(nslots), dim3(256), 0, s, sd, (const SlotCtl*)ctl);
+  if (prec == MOLT_F64) {
+    hipLaunchKernelGGL((finish_batch_kernel<double>), dim3(npblk), dim3(256), 0, s, sd, (const SlotCtl*)ctl, pmap);
+    hipLaunchKernelGGL((diag_batch_kernel<double>), dim3(npblk), dim3(256), 0, s, sd, (const SlotCtl*)ctl, pmap);
+  } else {
+    hipLaunchKernelGGL((finish_batch_kernel<float>), dim3(npblk), dim3(256), 0, s, sd, (const SlotCtl*)ctl, pmap);
+    hipLaunchKernelGGL((diag_batch_kernel<float>), dim3(npblk), dim3(256), 0, s, sd, (const SlotCtl*)ctl, pmap);
+  }
+  hipLaunchKernelGGL(tick_end_batch_kernel, dim3(nslots), dim3(256), 0, s, sd, ctl);
+  if (g_prof_on) prof_end(KF_OTHER * 8 + 1, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_init(const SlotDesc* sd, SlotCtl* ctl, int nslots, hipStream_t s) {
+  const int nb = (nslots + 255) / 256;
+  hipLaunchKernelGGL(init_batch_kernel, dim3(nb < 1 ? 1 : nb), dim3(256), 0, s, sd, ctl, nslots);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_count(const SlotCtl* ctl, int nslots, int* out, hipStream_t s) {
+  hipLaunchKernelGGL(count_active_kernel, dim3(1), dim3(256), 0, s, ctl, nslots, out);
+  return hipGetLastError();
+}
+
+}  // namespace molt

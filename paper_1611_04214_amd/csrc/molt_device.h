@@ -1,0 +1,1085 @@
+// molt_device.h -- device code shared by the HIP translation units of libmolt:
+// the pass programs, the per-thread line segment, the boundary solve and the
+// bodies of the line-pass kernels (block index passed explicitly, so that the
+// single-problem kernels and the batched kernels run the same code).
+//
+// The MOL^T Cahn-Hilliard hot path: the line inverse L^{-1} =
+// (I - d^2/alpha^2)^{-1} of Sec. 3.2 along x-lines and y-lines, fused with the
+// pointwise work of the fixed-point iteration of Sec. 5.1.
+//
+// One line inverse, for nodes j = 0..n-1 with J^L_j, J^R_j the order-M local
+// quadratures (centred stencils; J^L_0 = 0, and J^R_{n-1} = 0 when the line is
+// not periodic):
+//   S^L_j = d S^L_{j-1} + J^L_j,   S^R_j = d S^R_{j+1} + J^R_j        (eqs. IL, IR)
+//   w_j   = (S^L_j + S^R_j)/2 + B_a d^j + B_b d^{N-j}                 (eq. L_Inverse)
+// with B_a, B_b from the boundary 2x2 solve (FP64).  The recurrences are
+// evaluated as a parallel scan: each thread owns K consecutive nodes, first
+// computes its zero-seeded totals, the carries between threads are combined
+// (wave shuffles + LDS along x, a per-column FP64 combine kernel along y), and
+// a second seeded scan gives the final values.  The boundary terms are folded
+// into the seeds: Z^L_j = S^L_j + 2 B_a d^j satisfies the same recurrence, so a
+// thread starting at node j0 seeds its scan with d*carry + 2 B_a d^{j0}.
+//
+// Pass "programs" define the pointwise work around the sweeps: what is swept
+// (sin), what is kept per node (ext) and how outputs are formed (fin).
+#pragma once
+#include <math.h>
+#include <stdint.h>
+
+#include "molt_internal.h"
+
+// Minimum waves per SIMD requested for the line-pass kernels (caps their VGPRs).
+#ifndef MOLT_OCC
+#define MOLT_OCC 2
+#endif
+#define MOLT_PASS_ATTR __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MOLT_OCC)))
+
+namespace molt {
+
+// --------------------------------------------------------------------------
+// small helpers
+// --------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T dpow(double nu, double e);
+template <>
+__device__ __forceinline__ float dpow<float>(double nu, double e) {
+  return __expf(-(float)(nu * e));
+}
+template <>
+__device__ __forceinline__ double dpow<double>(double nu, double e) {
+  return exp(-nu * e);
+}
+
+__device__ __forceinline__ int wrapi(int j, int n) {
+  int r = j % n;
+  return r < 0 ? r + n : r;
+}
+
+// --------------------------------------------------------------------------
+// pass programs
+//   NR raw input fields a.in[0..NR-1]; need(a, r) says whether field r is read
+//   sin(a, r, s):    the F swept fields of a node from its NR raw values
+//   ext(a, r, x):    the E values kept on owned nodes for the output
+//   fin(a, w, x, o): the NO outputs (a.out[0..NO-1]) from the swept values w;
+//                    returns the node's contribution to the residual max.
+// The iteration works in u (= v - 1): every linear operator of the scheme
+// maps constants to themselves (L^{-1}[1] = 1) or to zero (D, C1), so the
+// shift only changes the reaction: g = f(v) - sigma v = u^3 - (1+sigma) u - sigma,
+// and the constant drops out of C1 g.
+// --------------------------------------------------------------------------
+enum ProgId { PROG_SWEEP = 0, PROG_RHS = 1, PROG_P1 = 2, PROG_P2 = 3, PROG_P3 = 4, PROG_P4 = 5 };
+
+template <typename T>
+struct ProgSweep {  // w = L^{-1} in0
+  static constexpr int F = 1, E = 0, NR = 1, NO = 1;
+  __device__ static bool need(const PassArgs&, int) { return true; }
+  __device__ static void sin(const PassArgs&, const T* r, T* s) { s[0] = r[0]; }
+  __device__ static void ext(const PassArgs&, const T*, T*) {}
+  __device__ static double fin(const PassArgs&, const T* w, const T*, T* o) {
+    o[0] = w[0];
+    return 0.0;
+  }
+};
+
+template <typename T>
+struct ProgRhs {  // w = L^{-1} rhs, rhs = u^n (BE) or (4u^n - u^{n-1})/3 (BDF2)
+  static constexpr int F = 1, E = 0, NR = 2, NO = 1;
+  __device__ static bool need(const PassArgs& a, int r) { return r == 0 || a.bdf2; }
+  __device__ static void sin(const PassArgs& a, const T* r, T* s) {
+    s[0] = a.bdf2 ? (T(4) * r[0] - r[1]) * T(1.0 / 3.0) : r[0];
+  }
+  __device__ static void ext(const PassArgs&, const T*, T*) {}
+  __device__ static double fin(const PassArgs&, const T* w, const T*, T* o) {
+    o[0] = w[0];
+    return 0.0;
+  }
+};
+
+// reaction part and linear part of the current iterate
+//  full form:      e = g(u) (constant dropped), lin = u
+//  increment form: e = g(p) - g(q) = dl*(p^2 + p q + q^2 - 1 - sigma), lin = dl,
+//                  p = base + W (current iterate), q = p - dl (previous)
+template <typename T>
+__device__ __forceinline__ void react_lin(const PassArgs& a, T base, T W, T dl, T& e, T& lin) {
+  const T sg = (T)a.sigma;
+  if (a.mode == 0) {
+    e = base * base * base - (T(1) + sg) * base;
+    lin = base;
+  } else {
+    const T p = base + W;
+    const T q = p - dl;
+    e = dl * (p * p + p * q + q * q - T(1) - sg);
+    lin = dl;
+  }
+}
+
+template <typename T>
+struct ProgP1 {  // y, alpha1: raw (base, W, dl) -> a1 = Y1 e, b1 = Y1 lin
+  static constexpr int F = 2, E = 0, NR = 3, NO = 2;
+  __device__ static bool need(const PassArgs& a, int r) { return r == 0 || a.mode; }
+  __device__ static void sin(const PassArgs& a, const T* r, T* s) { react_lin<T>(a, r[0], r[1], r[2], s[0], s[1]); }
+  __device__ static void ext(const PassArgs&, const T*, T*) {}
+  __device__ static double fin(const PassArgs&, const T* w, const T*, T* o) {
+    o[0] = w[0];
+    o[1] = w[1];
+    return 0.0;
+  }
+};
+
+template <typename T>
+struct ProgP2 {  // x, alpha1: raw (a1, b1, base, W, dl) -> C = X1(2 a1 - e) - a1, q = b1 + X1(lin - b1)
+  static constexpr int F = 2, E = 2, NR = 5, NO = 2;
+  __device__ static bool need(const PassArgs& a, int r) { return r < 3 || a.mode; }
+  __device__ static void sin(const PassArgs& a, const T* r, T* s) {
+    T e, lin;
+    react_lin<T>(a, r[2], r[3], r[4], e, lin);
+    s[0] = T(2) * r[0] - e;
+    s[1] = lin - r[1];
+  }
+  __device__ static void ext(const PassArgs&, const T* r, T* x) {
+    x[0] = r[0];
+    x[1] = r[1];
+  }
+  __device__ static double fin(const PassArgs&, const T* w, const T* x, T* o) {
+    o[0] = w[0] - x[0];
+    o[1] = x[1] + w[1];
+    return 0.0;
+  }
+};
+
+template <typename T>
+struct ProgP3 {  // y, alpha2: raw (C, q) -> m = Y2(q + kappa C) - q, n = Y2 q
+  static constexpr int F = 2, E = 1, NR = 2, NO = 2;
+  __device__ static bool need(const PassArgs&, int) { return true; }
+  __device__ static void sin(const PassArgs& a, const T* r, T* s) {
+    s[0] = r[1] + (T)a.kappa * r[0];
+    s[1] = r[1];
+  }
+  __device__ static void ext(const PassArgs&, const T* r, T* x) { x[0] = r[1]; }
+  __device__ static double fin(const PassArgs&, const T* w, const T* x, T* o) {
+    o[0] = w[0] - x[0];
+    o[1] = w[1];
+    return 0.0;
+  }
+};
+
+template <typename T>
+struct ProgP4 {  // x, alpha2: raw (m, n, dl|R, W) -> dl' = (dl|R) + X2 m - n ; W' = W + dl' (| dl')
+  static constexpr int F = 1, E = 3, NR = 4, NO = 2;
+  __device__ static bool need(const PassArgs& a, int r) { return r < 3 || a.mode; }
+  __device__ static void sin(const PassArgs&, const T* r, T* s) { s[0] = r[0]; }
+  __device__ static void ext(const PassArgs& a, const T* r, T* x) {
+    x[0] = r[1];
+    x[1] = r[2];
+    x[2] = a.mode ? r[3] : T(0);
+  }
+  __device__ static double fin(const PassArgs&, const T* w, const T* x, T* o) {
+    const T dn = x[1] + w[0] - x[0];
+    o[0] = dn;
+    o[1] = x[2] + dn;
+    return fabs((double)dn);
+  }
+};
+
+template <int P, typename T>
+struct ProgOf;
+template <typename T> struct ProgOf<PROG_SWEEP, T> { using type = ProgSweep<T>; };
+template <typename T> struct ProgOf<PROG_RHS, T> { using type = ProgRhs<T>; };
+template <typename T> struct ProgOf<PROG_P1, T> { using type = ProgP1<T>; };
+template <typename T> struct ProgOf<PROG_P2, T> { using type = ProgP2<T>; };
+template <typename T> struct ProgOf<PROG_P3, T> { using type = ProgP3<T>; };
+template <typename T> struct ProgOf<PROG_P4, T> { using type = ProgP4<T>; };
+
+// raw values of one node (scalar loads; fields the program does not read are 0)
+template <typename T, class P>
+__device__ __forceinline__ void load_raw(const PassArgs& a, size_t i, T* r) {
+#pragma unroll
+  for (int f = 0; f < P::NR; ++f) r[f] = P::need(a, f) ? ((const T*)a.in[f])[i] : T(0);
+}
+
+// 16-byte vector access of 16/sizeof(T) consecutive elements
+__device__ __forceinline__ void ld16(const float* p, float* o) {
+  const float4 v = *(const float4*)p;
+  o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+}
+__device__ __forceinline__ void ld16(const double* p, double* o) {
+  const double2 v = *(const double2*)p;
+  o[0] = v.x; o[1] = v.y;
+}
+__device__ __forceinline__ void st16(float* p, const float* o) { *(float4*)p = make_float4(o[0], o[1], o[2], o[3]); }
+__device__ __forceinline__ void st16(double* p, const double* o) { *(double2*)p = make_double2(o[0], o[1]); }
+
+// --------------------------------------------------------------------------
+// Per-thread line segment: sweep inputs on nodes j0-H .. j0+K+H-1, the two
+// local quadratures on the K owned nodes, zero-seeded totals and the final
+// seeded scans.  `stride` is the element distance between consecutive nodes
+// of the line (1 along x, nx along y); `lbase` the element index of node 0.
+// With `vec` (stride 1, 16-byte aligned fields, line length a multiple of
+// 16/sizeof(T)) owned nodes are read with 16-byte loads.
+// --------------------------------------------------------------------------
+template <typename T, class P, int K, int M, bool PER>
+struct Seg {
+  static constexpr int H = M / 2, F = P::F, E = P::E, NR = P::NR, W = K + 2 * H;
+  static constexpr int V = 16 / (int)sizeof(T);
+  T JL[F][K], JR[F][K];
+  T jln[F];                    // periodic: J^L of the cell ending at node n (= node 0)
+  T ex[E > 0 ? E : 1][K];      // kept values of the owned nodes
+
+  __device__ void build(const LineCoef& c, const PassArgs& a, size_t lbase, size_t stride, int j0, bool vec) {
+    T s[F][W];
+    window(c, a, lbase, stride, j0, vec, s);
+    stencils(c, a, lbase, stride, j0, s);
+  }
+
+  // swept values on nodes j0-H .. j0+K+H-1 (and the kept values of the owned nodes)
+  __device__ void window(const LineCoef& c, const PassArgs& a, size_t lbase, size_t stride, int j0, bool vec,
+                         T (&s)[F][W]) {
+    const int n = c.n;
+    constexpr bool per = PER;
+    if (vec && j0 + K <= n) {
+#pragma unroll
+      for (int q = 0; q < K / V; ++q) {
+        T r[NR][V];
+#pragma unroll
+        for (int f = 0; f < NR; ++f) {
+          if (P::need(a, f)) {
+            ld16((const T*)a.in[f] + lbase + (size_t)(j0 + q * V), r[f]);
+          } else {
+#pragma unroll
+            for (int v = 0; v < V; ++v) r[f][v] = T(0);
+          }
+        }
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          T rv[NR], sv[F], xv[E > 0 ? E : 1];
+#pragma unroll
+          for (int f = 0; f < NR; ++f) rv[f] = r[f][v];
+          P::sin(a, rv, sv);
+#pragma unroll
+          for (int f = 0; f < F; ++f) s[f][H + q * V + v] = sv[f];
+          if constexpr (E > 0) {
+            P::ext(a, rv, xv);
+#pragma unroll
+            for (int e = 0; e < E; ++e) ex[e][q * V + v] = xv[e];
+          }
+        }
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const int j = j0 + k;
+        const int jj = per ? wrapi(j, n) : min(j, n - 1);
+        T rv[NR], sv[F], xv[E > 0 ? E : 1];
+        load_raw<T, P>(a, lbase + (size_t)jj * stride, rv);
+        P::sin(a, rv, sv);
+#pragma unroll
+        for (int f = 0; f < F; ++f) s[f][H + k] = sv[f];
+        if constexpr (E > 0) {
+          P::ext(a, rv, xv);
+#pragma unroll
+          for (int e = 0; e < E; ++e) ex[e][k] = xv[e];
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 2 * H; ++k) {  // halo nodes (ends of non-periodic lines: clamped, replaced below)
+      const int kk = k < H ? k : K + k;
+      const int j = j0 - H + kk;
+      const int jj = per ? wrapi(j, n) : min(max(j, 0), n - 1);
+      T rv[NR], sv[F];
+      load_raw<T, P>(a, lbase + (size_t)jj * stride, rv);
+      P::sin(a, rv, sv);
+#pragma unroll
+      for (int f = 0; f < F; ++f) s[f][kk] = sv[f];
+    }
+  }
+
+  // J^L, J^R on the owned nodes from the window values s (nodes j0-H ..
+  // j0+K+H-1); boundary nodes of non-periodic lines are redone in FP64
+  __device__ void stencils(const LineCoef& c, const PassArgs& a, size_t lbase, size_t stride, int j0,
+                           const T (&s)[F][W]) {
+    const int n = c.n;
+    constexpr bool per = PER;
+    T wl[M + 1], wr[M + 1];
+#pragma unroll
+    for (int i = 0; i <= M; ++i) {
+      wl[i] = (T)c.wl[i];
+      wr[i] = (T)c.wr[i];
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int j = j0 + k;
+      const bool real = j < n;
+#pragma unroll
+      for (int f = 0; f < F; ++f) {
+        T l = T(0), r = T(0);
+#pragma unroll
+        for (int i = 0; i <= M; ++i) {
+          l += wl[i] * s[f][k + i];
+          r += wr[i] * s[f][k + i];
+        }
+        if (k == 0) jln[f] = l;
+        JL[f][k] = (real && j != 0) ? l : T(0);
+        JR[f][k] = (real && (per || j != n - 1)) ? r : T(0);
+      }
+    }
+    if constexpr (!PER) {
+      if (j0 < H || j0 + K + H > n) boundary_nodes(c, a, lbase, stride, j0);
+    }
+  }
+
+  // Nodes whose centred window leaves a non-periodic line (j < H or j > n-1-H).
+  // The window is completed by ghost values extrapolated with the degree-M
+  // polynomial through the M+1 end nodes; the extrapolation weights are large
+  // (up to ~2800 for M=6), so the ghosts and these few stencils are formed in
+  // FP64 and only the result is rounded to T.  The in-range window values are
+  // reloaded here (only the threads at the two ends of a line get here), so
+  // the window array of the interior path is not kept alive.
+  __device__ void boundary_nodes(const LineCoef& c, const PassArgs& a, size_t lbase, size_t stride, int j0) {
+    const int n = c.n;
+    double gl[F][H], gr[F][H];
+#pragma unroll
+    for (int f = 0; f < F; ++f)
+#pragma unroll
+      for (int g = 0; g < H; ++g) gl[f][g] = gr[f][g] = 0.0;
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      if (side == 0 ? (j0 >= H) : (j0 + K + H <= n)) continue;
+      double e[F][M + 1];
+#pragma unroll
+      for (int i = 0; i <= M; ++i) {
+        T rv[NR], sv[F];
+        load_raw<T, P>(a, lbase + (size_t)(side == 0 ? i : n - 1 - M + i) * stride, rv);
+        P::sin(a, rv, sv);
+#pragma unroll
+        for (int f = 0; f < F; ++f) e[f][i] = (double)sv[f];
+      }
+#pragma unroll
+      for (int f = 0; f < F; ++f)
+#pragma unroll
+        for (int g = 0; g < H; ++g) {
+          double acc = 0.0;
+#pragma unroll
+          for (int i = 0; i <= M; ++i) acc += (side == 0 ? c.ghostL[g][i] : c.ghostR[g][i]) * e[f][i];
+          if (side == 0)
+            gl[f][g] = acc;
+          else
+            gr[f][g] = acc;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int j = j0 + k;
+      if (j < n && (j < H || j > n - 1 - H)) {
+#pragma unroll
+        for (int f = 0; f < F; ++f) {
+          double l = 0.0, r = 0.0;
+#pragma unroll
+          for (int i = 0; i <= M; ++i) {
+            const int jw = j - H + i;
+            T rv[NR], sv[F];
+            load_raw<T, P>(a, lbase + (size_t)min(max(jw, 0), n - 1) * stride, rv);
+            P::sin(a, rv, sv);
+            double v = (double)sv[f];
+#pragma unroll
+            for (int g = 1; g <= H; ++g) {
+              v = (jw == -g) ? gl[f][g - 1] : v;
+              v = (jw == n - 1 + g) ? gr[f][g - 1] : v;
+            }
+            l += c.wl[i] * v;
+            r += c.wr[i] * v;
+          }
+          JL[f][k] = (j != 0) ? (T)l : T(0);
+          JR[f][k] = (j != n - 1) ? (T)r : T(0);
+        }
+      }
+    }
+  }
+
+  // zero-seeded totals: AL at the thread's last real node, AR at its first node
+  __device__ void totals(T d, int j0, int n, T* AL, T* AR) const {
+    const int jlast = min(j0 + K - 1, n - 1);
+#pragma unroll
+    for (int f = 0; f < F; ++f) {
+      T x = T(0), xl = T(0);
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        x = d * x + JL[f][k];
+        if (j0 + k == jlast) xl = x;
+      }
+      AL[f] = xl;
+      T y = T(0);
+#pragma unroll
+      for (int k = K - 1; k >= 0; --k) y = d * y + JR[f][k];
+      AR[f] = y;
+    }
+  }
+
+  // seeded scans; w[f][k] = (Z^L + Z^R)/2
+  __device__ void finalize(T d, int j0, int n, const T* gL, const T* gR, T (&w)[F][K]) const {
+    const int jlast = min(j0 + K - 1, n - 1);
+#pragma unroll
+    for (int f = 0; f < F; ++f) {
+      T x = T(0);
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        x = (k == 0) ? (JL[f][0] + gL[f]) : (d * x + JL[f][k]);
+        w[f][k] = x;
+      }
+      T y = T(0);
+#pragma unroll
+      for (int k = K - 1; k >= 0; --k) {
+        const int j = j0 + k;
+        y = (j > jlast) ? T(0) : ((j == jlast) ? (JR[f][k] + gR[f]) : (d * y + JR[f][k]));
+        w[f][k] = T(0.5) * (w[f][k] + y);
+      }
+    }
+  }
+
+  // outputs of the owned nodes; returns the residual max over them
+  __device__ double store(const PassArgs& a, size_t lbase, size_t stride, int j0, int n, bool vec,
+                          const T (&w)[F][K]) const {
+    constexpr int NO = P::NO;
+    double res = 0.0;
+    if (vec && j0 + K <= n) {
+#pragma unroll
+      for (int q = 0; q < K / V; ++q) {
+        T o[NO][V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          const int k = q * V + v;
+          T wk[F], xk[E > 0 ? E : 1], ok[NO];
+#pragma unroll
+          for (int f = 0; f < F; ++f) wk[f] = w[f][k];
+#pragma unroll
+          for (int e = 0; e < E; ++e) xk[e] = ex[e][k];
+          res = fmax(res, P::fin(a, wk, xk, ok));
+#pragma unroll
+          for (int f = 0; f < NO; ++f) o[f][v] = ok[f];
+        }
+#pragma unroll
+        for (int f = 0; f < NO; ++f) st16((T*)a.out[f] + lbase + (size_t)(j0 + q * V), o[f]);
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const int j = j0 + k;
+        if (j < n) {
+          T wk[F], xk[E > 0 ? E : 1], ok[NO];
+#pragma unroll
+          for (int f = 0; f < F; ++f) wk[f] = w[f][k];
+#pragma unroll
+          for (int e = 0; e < E; ++e) xk[e] = ex[e][k];
+          res = fmax(res, P::fin(a, wk, xk, ok));
+#pragma unroll
+          for (int f = 0; f < NO; ++f) ((T*)a.out[f])[lbase + (size_t)j * stride] = ok[f];
+        }
+      }
+    }
+    return res;
+  }
+};
+
+// Boundary coefficients of one line from its zero-seeded totals (Sec. 3.2).
+//  TLl = S^L_{n-1}, TRl = S^R_0 (zero-seeded), jlnv = J^L of the cell ending at
+//  node N (periodic only).  I_N = IL~_N / 2, I_0 = IR~_0 / 2.
+__device__ __forceinline__ void boundary_terms(const LineCoef& c, double TLl, double TRl, double jlnv,
+                                               double& Ba, double& Bb) {
+  const double d = c.d, mu = c.mu;
+  if (c.bc == MOLT_BC_PERIODIC) {
+    const double IN = 0.5 * (d * TLl + jlnv), I0 = 0.5 * TRl;
+    Ba = IN / (1.0 - mu);
+    Bb = I0 / (1.0 - mu);
+  } else {
+    const double IN = 0.5 * TLl, I0 = 0.5 * TRl;
+    const double den = 1.0 - mu * mu;
+    if (c.bc == MOLT_BC_NEUMANN) {
+      Ba = (I0 + mu * IN) / den;
+      Bb = (IN + mu * I0) / den;
+    } else {
+      Ba = (mu * IN - I0) / den;
+      Bb = (mu * I0 - IN) / den;
+    }
+  }
+}
+
+// residual: block max written to a per-block slot; a one-block close kernel
+// folds the slots (order-independent max) and advances the iteration state.
+__device__ inline void residual_block(double r, double* partials, int slot) {
+  __shared__ double red[4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) r = fmax(r, __shfl_down(r, off));
+  if (lane == 0) red[wave] = r;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double b = red[0];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) b = fmax(b, red[w]);
+    partials[slot] = b;
+  }
+}
+
+__device__ inline void residual_close_body(const double* partials, int nblocks, DevState* st) {
+  if (st->done) return;
+  __shared__ double red[4];
+  double r = 0.0;
+  for (int i = threadIdx.x; i < nblocks; i += blockDim.x) r = fmax(r, partials[i]);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) r = fmax(r, __shfl_down(r, off));
+  if (lane == 0) red[wave] = r;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double res = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    const int it = st->iters + 1;
+    st->iters = it;
+    st->last_resid = res;
+    if (st->fixed > 0) {
+      if (it >= st->fixed) st->done = 1;
+    } else if (res < st->tol || it >= st->max_iter) {
+      st->done = 1;
+    }
+  }
+}
+
+
+// --------------------------------------------------------------------------
+// x-direction pass: rows are contiguous; TL threads (a multiple of 64) own one
+// row, 256/TL rows per 256-thread block.
+// --------------------------------------------------------------------------
+template <typename T, int PI, int K, int M, bool PER>
+__device__ __forceinline__ void xpass_body(const LineCoef& c, const PassArgs& a, DevState* st, int nlines, int TL,
+                                           double* rpart, int vec, int bx) {
+  using P = typename ProgOf<PI, T>::type;
+  constexpr int F = P::F, E = P::E, NR = P::NR, NO = P::NO;
+  constexpr int H = M / 2, W = K + 2 * H;
+  constexpr int V = 16 / (int)sizeof(T);
+  constexpr int ROW = 256 * K;  // nodes of all rows of one block
+  if (st != nullptr && st->done) return;
+  __shared__ T sh_tot[F][2][4];
+  __shared__ double sh_line[4][F][3];
+  // swept fields (then the swept results) of the block's rows, one padding
+  // word per 16 so that a thread's K consecutive nodes sit 17 words from its
+  // neighbour's (no bank conflicts)
+  __shared__ T sh_row[F][ROW + ROW / 16];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int lil = tid / TL;
+  const int t = tid - lil * TL;
+  const int wl0 = lil * (TL >> 6);
+  const int line = bx * (256 / TL) + lil;
+  const bool act = line < nlines;
+  const int n = c.n;
+  const int j0 = t * K;
+  const bool has = act && j0 < n;
+  const size_t lbase = (size_t)(act ? line : 0) * (size_t)n;
+  const int rowoff = lil * TL * K;
+  const T d = (T)c.d;
+#define MOLT_PAD(e) ((e) + ((e) >> 4))
+
+  Seg<T, P, K, M, PER> seg;
+  // phase A: coalesced loads, the program's pointwise part in the load layout
+  if (act) {
+    if (vec) {
+#pragma unroll
+      for (int it = 0; it < K / V; ++it) {
+        const int e0 = (it * TL + t) * V;
+        if (e0 < n) {
+          T r[NR][V];
+#pragma unroll
+          for (int f = 0; f < NR; ++f) {
+            if (P::need(a, f)) {
+              ld16((const T*)a.in[f] + lbase + (size_t)e0, r[f]);
+            } else {
+#pragma unroll
+              for (int v = 0; v < V; ++v) r[f][v] = T(0);
+            }
+          }
+#pragma unroll
+          for (int v = 0; v < V; ++v) {
+            T rv[NR], sv[F], xv[E > 0 ? E : 1];
+#pragma unroll
+            for (int f = 0; f < NR; ++f) rv[f] = r[f][v];
+            P::sin(a, rv, sv);
+#pragma unroll
+            for (int f = 0; f < F; ++f) sh_row[f][MOLT_PAD(rowoff + e0 + v)] = sv[f];
+            if constexpr (E > 0) {
+              P::ext(a, rv, xv);
+#pragma unroll
+              for (int e = 0; e < E; ++e) seg.ex[e][it * V + v] = xv[e];
+            }
+          }
+        }
+      }
+    } else {
+#pragma unroll
+      for (int it = 0; it < K; ++it) {
+        const int e = it * TL + t;
+        if (e < n) {
+          T rv[NR], sv[F], xv[E > 0 ? E : 1];
+          load_raw<T, P>(a, lbase + (size_t)e, rv);
+          P::sin(a, rv, sv);
+#pragma unroll
+          for (int f = 0; f < F; ++f) sh_row[f][MOLT_PAD(rowoff + e)] = sv[f];
+          if constexpr (E > 0) {
+            P::ext(a, rv, xv);
+#pragma unroll
+            for (int q = 0; q < E; ++q) seg.ex[q][it] = xv[q];
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+
+  // phase B: each thread's window of K + 2H nodes from LDS, local quadratures
+  T AL[F], AR[F];
+  if (has) {
+    T sw[F][W];
+    const bool near = n >= K + H;  // then one wrap suffices
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+      const int j = j0 - H + k;
+      int jj;
+      if (PER)
+        jj = near ? (j < 0 ? j + n : (j >= n ? j - n : j)) : wrapi(j, n);
+      else
+        jj = min(max(j, 0), n - 1);
+#pragma unroll
+      for (int f = 0; f < F; ++f) sw[f][k] = sh_row[f][MOLT_PAD(rowoff + jj)];
+    }
+    seg.stencils(c, a, lbase, 1, j0, sw);
+    seg.totals(d, j0, n, AL, AR);
+  } else {
+#pragma unroll
+    for (int f = 0; f < F; ++f) {
+      AL[f] = T(0);
+      AR[f] = T(0);
+      seg.jln[f] = T(0);
+    }
+  }
+
+  // carries between threads of the line: multiplier m = d^K per thread
+  const T m = dpow<T>(c.nu, (double)K);
+  T mp[6];
+  mp[0] = m;
+#pragma unroll
+  for (int s = 1; s < 6; ++s) mp[s] = mp[s - 1] * mp[s - 1];
+  const T m64 = mp[5] * mp[5];
+  T exL[F], exR[F];
+#pragma unroll
+  for (int f = 0; f < F; ++f) {
+    T xL = AL[f], xR = AR[f];
+#pragma unroll
+    for (int s = 0; s < 6; ++s) {
+      const int off = 1 << s;
+      T yL = __shfl_up(xL, off);
+      T yR = __shfl_down(xR, off);
+      if (lane >= off) xL += mp[s] * yL;
+      if (lane + off < 64) xR += mp[s] * yR;
+    }
+    T eL = __shfl_up(xL, 1);
+    T eR = __shfl_down(xR, 1);
+    exL[f] = lane == 0 ? T(0) : eL;
+    exR[f] = lane == 63 ? T(0) : eR;
+    if (lane == 63) sh_tot[f][0][wave] = xL;
+    if (lane == 0) sh_tot[f][1][wave] = xR;
+  }
+  __syncthreads();
+  const int nw = TL >> 6, wv = t >> 6;
+  const T mlane = dpow<T>(c.nu, (double)K * lane);
+  const T mlane_r = dpow<T>(c.nu, (double)K * (63 - lane));
+  T cL[F], cR[F];
+#pragma unroll
+  for (int f = 0; f < F; ++f) {
+    T CL = T(0), CR = T(0);
+    for (int w = 0; w < wv; ++w) CL = m64 * CL + sh_tot[f][0][wl0 + w];
+    for (int w = nw - 1; w > wv; --w) CR = m64 * CR + sh_tot[f][1][wl0 + w];
+    cL[f] = exL[f] + mlane * CL;
+    cR[f] = exR[f] + mlane_r * CR;
+  }
+  // line totals for the boundary solve
+  const int tstar = (n - 1) / K;
+  if (act && t == tstar) {
+    const T dk = dpow<T>(c.nu, (double)(n - 1 - tstar * K + 1));
+#pragma unroll
+    for (int f = 0; f < F; ++f) sh_line[lil][f][0] = (double)AL[f] + (double)dk * (double)cL[f];
+  }
+  if (act && t == 0) {
+#pragma unroll
+    for (int f = 0; f < F; ++f) {
+      sh_line[lil][f][1] = (double)AR[f] + (double)m * (double)cR[f];
+      sh_line[lil][f][2] = (double)seg.jln[f];
+    }
+  }
+  __syncthreads();
+  // the FP64 2x2 boundary solve, once per line
+  if (act && t < F) {
+    double Ba, Bb;
+    boundary_terms(c, sh_line[lil][t][0], sh_line[lil][t][1], sh_line[lil][t][2], Ba, Bb);
+    sh_line[lil][t][0] = Ba;
+    sh_line[lil][t][1] = Bb;
+  }
+  __syncthreads();
+
+  // phase C: seeded scans; the swept values go back to LDS (every read of the
+  // window happened before the barriers of the carry scan above)
+  if (has) {
+    const int jlast = min(j0 + K - 1, n - 1);
+    const T pL = dpow<T>(c.nu, (double)j0);
+    const T pR = dpow<T>(c.nu, (double)(c.N - jlast));
+    T gL[F], gR[F];
+#pragma unroll
+    for (int f = 0; f < F; ++f) {
+      gL[f] = d * cL[f] + (T)(2.0 * sh_line[lil][f][0]) * pL;
+      gR[f] = d * cR[f] + (T)(2.0 * sh_line[lil][f][1]) * pR;
+    }
+    T w[F][K];
+    seg.finalize(d, j0, n, gL, gR, w);
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+      if (j0 + k < n) {
+#pragma unroll
+        for (int f = 0; f < F; ++f) sh_row[f][MOLT_PAD(rowoff + j0 + k)] = w[f][k];
+      }
+  }
+  __syncthreads();
+
+  // phase D: outputs in the coalesced layout of phase A
+  double resid = 0.0;
+  if (act) {
+    if (vec) {
+#pragma unroll
+      for (int it = 0; it < K / V; ++it) {
+        const int e0 = (it * TL + t) * V;
+        if (e0 < n) {
+          T o[NO][V];
+#pragma unroll
+          for (int v = 0; v < V; ++v) {
+            T wk[F], xk[E > 0 ? E : 1], ok[NO];
+#pragma unroll
+            for (int f = 0; f < F; ++f) wk[f] = sh_row[f][MOLT_PAD(rowoff + e0 + v)];
+#pragma unroll
+            for (int e = 0; e < E; ++e) xk[e] = seg.ex[e][it * V + v];
+            resid = fmax(resid, P::fin(a, wk, xk, ok));
+#pragma unroll
+            for (int f = 0; f < NO; ++f) o[f][v] = ok[f];
+          }
+#pragma unroll
+          for (int f = 0; f < NO; ++f) st16((T*)a.out[f] + lbase + (size_t)e0, o[f]);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int it = 0; it < K; ++it) {
+        const int e = it * TL + t;
+        if (e < n) {
+          T wk[F], xk[E > 0 ? E : 1], ok[NO];
+#pragma unroll
+          for (int f = 0; f < F; ++f) wk[f] = sh_row[f][MOLT_PAD(rowoff + e)];
+#pragma unroll
+          for (int q = 0; q < E; ++q) xk[q] = seg.ex[q][it];
+          resid = fmax(resid, P::fin(a, wk, xk, ok));
+#pragma unroll
+          for (int f = 0; f < NO; ++f) ((T*)a.out[f])[lbase + (size_t)e] = ok[f];
+        }
+      }
+    }
+  }
+#undef MOLT_PAD
+  if (rpart != nullptr) residual_block(resid, rpart, bx);
+}
+
+
+// --------------------------------------------------------------------------
+// y-direction pass.  Block = 64 consecutive columns (one wave wide: every row
+// access is a coalesced 64-element segment) x RG thread rows; thread (col, t)
+// owns rows t*K .. t*K+K-1 of its column.  Three kernels:
+//  ytot: zero-seeded totals per thread -> tot[f][dir][t][col]
+//  ycomb: per column, FP64 exclusive scans over threads, line totals, the
+//         boundary solve and the seeds, written over tot
+//  yfin: seeded scans and the program outputs
+// --------------------------------------------------------------------------
+constexpr int kRG = 4;
+
+template <typename T, int PI, int K, int M, bool PER>
+__device__ __forceinline__ void ytot_body(const LineCoef& c, const PassArgs& a, DevState* st, int nx, int nth,
+                                          int nseg, size_t fstride, T* agg, T* jlnb, int bx, int by, int bz) {
+  using P = typename ProgOf<PI, T>::type;
+  constexpr int F = P::F;
+  if (st != nullptr && st->done) return;
+  __shared__ T shA[F][2][kRG][64];
+  const int lx = threadIdx.x, r = threadIdx.y;
+  const int col = bx * 64 + lx;
+  const int sg = by;
+  const int t = sg * kRG + r;
+  const int b = bz;
+  const bool ok = col < nx && t < nth;
+  const int n = c.n, j0 = t * K;
+  const size_t lbase = (size_t)b * fstride + (size_t)(col < nx ? col : 0);
+  T AL[F], AR[F];
+  if (ok) {
+    Seg<T, P, K, M, PER> seg;
+    seg.build(c, a, lbase, (size_t)nx, j0, false);
+    seg.totals((T)c.d, j0, n, AL, AR);
+    if (t == 0) {
+#pragma unroll
+      for (int f = 0; f < F; ++f) jlnb[((size_t)b * F + f) * nx + col] = seg.jln[f];
+    }
+  } else {
+#pragma unroll
+    for (int f = 0; f < F; ++f) AL[f] = AR[f] = T(0);
+  }
+#pragma unroll
+  for (int f = 0; f < F; ++f) {
+    shA[f][0][r][lx] = AL[f];
+    shA[f][1][r][lx] = AR[f];
+  }
+  __syncthreads();
+  if (r != 0 || col >= nx) return;
+  // the segment's zero-seeded totals: L at its last row, R at its first row
+  const int j0s = sg * kRG * K;
+  const int jls = min(j0s + kRG * K - 1, n - 1);
+  T* ab = agg + (size_t)b * (size_t)(F * 2) * nseg * nx;
+#pragma unroll
+  for (int f = 0; f < F; ++f) {
+    T L = T(0), R = T(0);
+#pragma unroll
+    for (int g = 0; g < kRG; ++g) {
+      const int tt = sg * kRG + g;
+      if (tt < nth) {
+        const int jl = min(tt * K + K - 1, n - 1);
+        L += dpow<T>(c.nu, (double)(jls - jl)) * shA[f][0][g][lx];
+        R += dpow<T>(c.nu, (double)(tt * K - j0s)) * shA[f][1][g][lx];
+      }
+    }
+    ab[((size_t)(f * 2 + 0) * nseg + sg) * nx + col] = L;
+    ab[((size_t)(f * 2 + 1) * nseg + sg) * nx + col] = R;
+  }
+}
+
+
+// ycomb: one block = 64 columns x 16 waves for one field of one batch entry.
+// Wave w owns threads [w*CT, w*CT + CT) of every column (CT = ceil(nth/16) <=
+// CTMAX): chunk-local scans, chunk carries through LDS, then the line totals,
+// the FP64 boundary solve and the seeds, written over the totals.
+constexpr int kCombWaves = 16;
+
+template <typename T, int CTMAX>
+__device__ __forceinline__ void ycomb_body(const LineCoef& c, DevState* st, int nx, int nth, int K, int F, T* tot,
+                                           const T* jlnb, int bx, int by, int bz) {
+  if (st != nullptr && st->done) return;
+  __shared__ double shL[kCombWaves][64], shR[kCombWaves][64];
+  __shared__ double shTL[64], shTR[64];
+  const int lane = threadIdx.x, w = threadIdx.y;
+  const int col = bx * 64 + lane;
+  const int f = by, b = bz;
+  const bool ok = col < nx;
+  const int n = c.n;
+  const int CT = (nth + kCombWaves - 1) / kCombWaves;
+  const int t0 = w * CT;
+  T* tb = tot + (size_t)b * (size_t)(F * 2) * nth * nx;
+  T* AL = tb + (size_t)(f * 2 + 0) * nth * nx + (ok ? col : 0);
+  T* AR = tb + (size_t)(f * 2 + 1) * nth * nx + (ok ? col : 0);
+  const double d = c.d, nu = c.nu;
+  const double m = exp(-nu * (double)K), mC = exp(-nu * (double)K * (double)CT);
+  T vL[CTMAX], vR[CTMAX];
+#pragma unroll
+  for (int i = 0; i < CTMAX; ++i) {
+    const int t = t0 + i;
+    const bool in = ok && i < CT && t < nth;
+    vL[i] = in ? AL[(size_t)t * nx] : T(0);
+    vR[i] = in ? AR[(size_t)t * nx] : T(0);
+  }
+  // chunk totals over the chunk's own entries (entries past nth are zero)
+  double xl = 0.0, xr = 0.0;
+#pragma unroll
+  for (int i = 0; i < CTMAX; ++i)
+    if (i < CT) xl = m * xl + (double)vL[i];
+#pragma unroll
+  for (int i = CTMAX - 1; i >= 0; --i) xr = m * xr + (double)vR[i];
+  shL[w][lane] = xl;
+  shR[w][lane] = xr;
+  __syncthreads();
+  double CL = 0.0, CR = 0.0;
+  for (int v = 0; v < w; ++v) CL = mC * CL + shL[v][lane];
+  for (int v = kCombWaves - 1; v > w; --v) CR = mC * CR + shR[v][lane];
+  const int tstar = (n - 1) / K;
+  const double dk = exp(-nu * (double)(n - 1 - tstar * K + 1));
+  double cl = CL;
+#pragma unroll
+  for (int i = 0; i < CTMAX; ++i) {
+    const int t = t0 + i;
+    const double v = (double)vL[i];
+    if (i < CT && t == tstar) shTL[lane] = v + dk * cl;
+    vL[i] = (T)cl;  // exclusive carry into thread t
+    cl = m * cl + v;
+  }
+  double cr = CR;
+#pragma unroll
+  for (int i = CTMAX - 1; i >= 0; --i) {
+    if (i < CT) {  // entries past the chunk must not decay the carry
+      const int t = t0 + i;
+      const double v = (double)vR[i];
+      if (t == 0) shTR[lane] = v + m * cr;
+      vR[i] = (T)cr;
+      cr = m * cr + v;
+    }
+  }
+  __syncthreads();
+  if (!ok) return;
+  double Ba, Bb;
+  boundary_terms(c, shTL[lane], shTR[lane], (double)jlnb[((size_t)b * F + f) * nx + col], Ba, Bb);
+  double pL = exp(-nu * (double)t0 * (double)K);
+#pragma unroll
+  for (int i = 0; i < CTMAX; ++i) {
+    const int t = t0 + i;
+    if (i < CT && t < nth) AL[(size_t)t * nx] = (T)(d * (double)vL[i] + 2.0 * Ba * pL);
+    pL *= m;
+  }
+  double pR = 0.0;
+  bool first = true;
+#pragma unroll
+  for (int i = CTMAX - 1; i >= 0; --i) {
+    const int t = t0 + i;
+    if (i < CT && t < nth) {
+      const int jlast = min(t * K + K - 1, n - 1);
+      pR = (first || t >= nth - 2) ? exp(-nu * (double)(c.N - jlast)) : pR * m;
+      first = false;
+      AR[(size_t)t * nx] = (T)(d * (double)vR[i] + 2.0 * Bb * pR);
+    }
+  }
+}
+
+
+template <typename T, int PI, int K, int M, bool PER>
+__device__ __forceinline__ void yfin_body(const LineCoef& c, const PassArgs& a, DevState* st, int nx, int nth,
+                                          int nseg, size_t fstride, const T* seeds, int bx, int by, int bz) {
+  using P = typename ProgOf<PI, T>::type;
+  constexpr int F = P::F;
+  if (st != nullptr && st->done) return;
+  __shared__ T shA[F][2][kRG][64];
+  const int lx = threadIdx.x, r = threadIdx.y;
+  const int col = bx * 64 + lx;
+  const int sg = by;
+  const int t = sg * kRG + r;
+  const int b = bz;
+  const bool ok = col < nx && t < nth;
+  const int n = c.n, j0 = t * K;
+  const size_t lbase = (size_t)b * fstride + (size_t)(col < nx ? col : 0);
+  const T d = (T)c.d;
+  Seg<T, P, K, M, PER> seg;
+  T AL[F], AR[F];
+  if (ok) {
+    seg.build(c, a, lbase, (size_t)nx, j0, false);
+    seg.totals(d, j0, n, AL, AR);
+  } else {
+#pragma unroll
+    for (int f = 0; f < F; ++f) AL[f] = AR[f] = T(0);
+  }
+#pragma unroll
+  for (int f = 0; f < F; ++f) {
+    shA[f][0][r][lx] = AL[f];
+    shA[f][1][r][lx] = AR[f];
+  }
+  __syncthreads();
+  if (!ok) return;
+  // carries from the other thread rows of the segment (all rows before a
+  // thread with nodes are full, rows after it start K apart), then the
+  // segment's seeds propagated to this thread's first / last node
+  const T mK = dpow<T>(c.nu, (double)K);
+  const int j0s = sg * kRG * K;
+  const int jls = min(j0s + kRG * K - 1, n - 1);
+  const int jlt = min(j0 + K - 1, n - 1);
+  const T* sb = seeds + (size_t)b * (size_t)(F * 2) * nseg * nx;
+  const T pl = dpow<T>(c.nu, (double)(j0 - j0s)), pr = dpow<T>(c.nu, (double)(jls - jlt));
+  T gL[F], gR[F];
+#pragma unroll
+  for (int f = 0; f < F; ++f) {
+    T cl = T(0), cr = T(0);
+    for (int g = 0; g < r; ++g) cl = mK * cl + shA[f][0][g][lx];
+    for (int g = kRG - 1; g > r; --g)
+      if (sg * kRG + g < nth) cr = mK * cr + shA[f][1][g][lx];
+    gL[f] = d * cl + pl * sb[((size_t)(f * 2 + 0) * nseg + sg) * nx + col];
+    gR[f] = d * cr + pr * sb[((size_t)(f * 2 + 1) * nseg + sg) * nx + col];
+  }
+  T w[F][K];
+  seg.finalize(d, j0, n, gL, gR, w);
+  seg.store(a, lbase, (size_t)nx, j0, n, false, w);
+}
+
+// FP64 mass and energy partial sums (fixed grid, fixed order: deterministic)
+template <typename T>
+__device__ __forceinline__ void diag_body(const T* u, int nx, int ny, int bc, double hx, double hy, double eps,
+                                          double* partials, int bx, int nb) {
+  __shared__ double sm[2][4];
+  const bool per = bc == MOLT_BC_PERIODIC;
+  double ms = 0.0, en = 0.0;
+  const size_t n = (size_t)nx * ny;
+  for (size_t i = (size_t)bx * blockDim.x + threadIdx.x; i < n; i += (size_t)nb * blockDim.x) {
+    const int ix = (int)(i % nx), iy = (int)(i / nx);
+    const double wx = per ? 1.0 : ((ix == 0 || ix == nx - 1) ? 0.5 : 1.0);
+    const double wy = (ny == 1 || per) ? 1.0 : ((iy == 0 || iy == ny - 1) ? 0.5 : 1.0);
+    const double uu = (double)u[i];
+    ms += wx * wy * uu;
+    const double q = uu * uu - 1.0;
+    en += wx * wy * 0.25 * q * q;
+    if (per || ix < nx - 1) {
+      const double un = (double)u[(size_t)iy * nx + (ix + 1 == nx ? 0 : ix + 1)];
+      const double g = (un - uu) / hx;
+      en += 0.5 * eps * eps * g * g * wy;
+    }
+    if (ny > 1 && (per || iy < ny - 1)) {
+      const double un = (double)u[(size_t)(iy + 1 == ny ? 0 : iy + 1) * nx + ix];
+      const double g = (un - uu) / hy;
+      en += 0.5 * eps * eps * g * g * wx;
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    ms += __shfl_down(ms, off);
+    en += __shfl_down(en, off);
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+    sm[0][wave] = ms;
+    sm[1][wave] = en;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = 0.0, b = 0.0;
+    for (int w = 0; w < 4; ++w) {
+      a += sm[0][w];
+      b += sm[1][w];
+    }
+    partials[2 * bx] = a;
+    partials[2 * bx + 1] = b;
+  }
+}
+
+// mass and energy of the field from the per-block partial sums
+__device__ __forceinline__ void diag_final_body(const double* partials, int nblocks, double area, DevState* st) {
+  __shared__ double sm[2][256];
+  double a = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < nblocks; i += blockDim.x) {
+    a += partials[2 * i];
+    b += partials[2 * i + 1];
+  }
+  sm[0][threadIdx.x] = a;
+  sm[1][threadIdx.x] = b;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      sm[0][threadIdx.x] += sm[0][threadIdx.x + s];
+      sm[1][threadIdx.x] += sm[1][threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    st->mass = sm[0][0] * area;
+    st->energy = sm[1][0] * area;
+  }
+}
+
+}  // namespace molt

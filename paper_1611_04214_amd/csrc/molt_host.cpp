@@ -28,6 +28,20 @@ size_t ypass_tot_elems(int prec, int n, int nx, int batch);
 int diag_blocks(size_t n);
 int xpass_max_n(int prec);
 
+int xpass_pick_k(int n, int prec);
+int xpass_tl(int n, int K);
+void ypass_shape(int prec, int n, int* nth, int* nseg);
+hipError_t launch_batch_y(int prec, int M, bool per, int pass, bool fin, const SlotDesc* sd, const SlotCtl* ctl,
+                          const BlkMap* map, int nblk, hipStream_t s);
+hipError_t launch_batch_comb(int prec, int pass, const SlotDesc* sd, const SlotCtl* ctl, const BlkMap* map, int nblk,
+                             hipStream_t s);
+hipError_t launch_batch_x(int prec, int K, int M, bool per, int pass, const SlotDesc* sd, const SlotCtl* ctl,
+                          const BlkMap* map, int nblk, hipStream_t s);
+hipError_t launch_batch_tail(int prec, const SlotDesc* sd, SlotCtl* ctl, int nslots, const BlkMap* pmap, int npblk,
+                             hipStream_t s);
+hipError_t launch_batch_init(const SlotDesc* sd, SlotCtl* ctl, int nslots, hipStream_t s);
+hipError_t launch_batch_count(const SlotCtl* ctl, int nslots, int* out, hipStream_t s);
+
 enum { PROG_SWEEP = 0, PROG_RHS = 1, PROG_P1 = 2, PROG_P2 = 3, PROG_P3 = 4, PROG_P4 = 5 };
 
 // --------------------------------------------------------------------------
@@ -51,6 +65,8 @@ static int32_t fail(int32_t code, const std::string& msg) {
 // --------------------------------------------------------------------------
 bool g_prof_on = false;
 static long long g_fused_min_items = 1LL << 40;  // single-kernel y-pass off by default
+static int g_batch_ticks = 8;                     // batched solve: ticks between host checks
+static int g_batch_graph = 1;                     // batched solve: replay the ticks as a HIP graph
 namespace {
 struct PendingEv {
   int kind;
@@ -243,8 +259,6 @@ static int32_t check_grid(const molt_grid* g, int prec) {
 }
 
 static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
-
-enum { F_R = 0, F_DL, F_W, F_A1, F_B1, F_C, F_Q, F_M, F_N, F_HIST, F_COUNT };
 
 struct Layout {
   size_t fld[F_COUNT];
@@ -443,6 +457,311 @@ static int32_t check_params(const molt_ch_params* p) {
   return MOLT_OK;
 }
 
+// --------------------------------------------------------------------------
+// batched instances
+// --------------------------------------------------------------------------
+struct BatchGroup {
+  int K, M, per;
+  size_t off;  // first map entry
+  int nblk;
+};
+
+struct BatchPlan {
+  int prec = 0;
+  std::vector<size_t> slot_off;  // workspace offset of each slot's problem workspace
+  std::vector<Layout> lay;
+  std::vector<size_t> rec_first;  // first record of each slot
+  size_t nrec = 0;
+  size_t desc = 0, ctl = 0, rec = 0, map = 0, cnt = 0, total = 0;
+  std::vector<BatchGroup> yg, xg;
+  size_t comb_off = 0, pt_off = 0;
+  int comb_n = 0, pt_n = 0;
+  size_t nmap = 0;
+  long long max_ticks = 0;  // upper bound of the ticks any slot needs
+};
+
+static int32_t check_instance(const molt_instance& in, int prec) {
+  int32_t rc = check_params(&in.params);
+  if (rc != MOLT_OK) return rc;
+  if (in.params.precision != prec) return fail(MOLT_EINVAL, "all instances of a batch must use one precision");
+  rc = check_grid(&in.grid, prec);
+  if (rc != MOLT_OK) return rc;
+  if (in.grid.ny < 2) return fail(MOLT_EUNSUPPORTED, "batched instances must be two-dimensional");
+  if (in.grid.bc == MOLT_BC_DIRICHLET) return fail(MOLT_EUNSUPPORTED, "Dirichlet boundaries are sweep-only");
+  if (!in.d_u) return fail(MOLT_EINVAL, "instance field is NULL");
+  if (in.nsteps < 0 || in.nsteps > 0x7fffffffLL) return fail(MOLT_EINVAL, "nsteps out of range");
+  return MOLT_OK;
+}
+
+// Workspace layout and block maps of a batch (maps filled when `maps` is given).
+static int32_t batch_plan(const molt_instance* inst, int count, BatchPlan& P, std::vector<BlkMap>* maps) {
+  if (!inst || count < 1 || count > 65535) return fail(MOLT_EINVAL, "count must be in 1..65535");
+  P.prec = inst[0].params.precision;
+  const int prec = P.prec;
+  size_t off = 0;
+  P.slot_off.resize(count);
+  P.lay.resize(count);
+  P.rec_first.resize(count);
+  P.nrec = 0;
+  P.max_ticks = 0;
+  for (int i = 0; i < count; ++i) {
+    const int32_t rc = check_instance(inst[i], prec);
+    if (rc != MOLT_OK) return fail(rc, "instance " + std::to_string(i) + ": " + g_err);
+    P.lay[i] = ch_layout(&inst[i].grid, prec);
+    P.slot_off[i] = off;
+    off += al256(P.lay[i].total);
+    P.rec_first[i] = P.nrec;
+    P.nrec += (size_t)inst[i].nsteps;
+    const molt_ch_params& p = inst[i].params;
+    const long long cap = p.fixed_iters > 0 ? p.fixed_iters : p.max_iter;
+    const long long ticks = (long long)inst[i].nsteps * (cap + 1);
+    if (ticks > P.max_ticks) P.max_ticks = ticks;
+  }
+  P.desc = off;
+  off += al256((size_t)count * sizeof(SlotDesc));
+  P.ctl = off;
+  off += al256((size_t)count * sizeof(SlotCtl));
+  P.rec = off;
+  off += al256(P.nrec * sizeof(molt_step_info));
+  P.cnt = off;
+  off += 256;
+  // groups: y-passes by (M, boundary kind); x-passes by (K, M, boundary kind)
+  P.yg.clear();
+  P.xg.clear();
+  size_t nm = 0;
+  for (int M = 2; M <= 6; M += 2)
+    for (int per = 1; per >= 0; --per) {
+      BatchGroup g{0, M, per, nm, 0};
+      for (int i = 0; i < count; ++i) {
+        const molt_grid& gr = inst[i].grid;
+        if (gr.order_M != M || (gr.bc == MOLT_BC_PERIODIC) != (per == 1)) continue;
+        int nth, nseg;
+        ypass_shape(prec, gr.ny, &nth, &nseg);
+        const int nb = ((gr.nx + 63) / 64) * nseg;
+        if (maps)
+          for (int b = 0; b < nb; ++b) maps->push_back(BlkMap{i, b});
+        g.nblk += nb;
+      }
+      if (g.nblk > 0) P.yg.push_back(g);
+      nm += g.nblk;
+    }
+  P.comb_off = nm;
+  P.comb_n = 0;
+  for (int i = 0; i < count; ++i) {
+    const int nb = 2 * ((inst[i].grid.nx + 63) / 64);
+    if (maps)
+      for (int b = 0; b < nb; ++b) maps->push_back(BlkMap{i, b});
+    P.comb_n += nb;
+  }
+  nm += P.comb_n;
+  const int ks[4] = {4, 8, 16, 32};
+  for (int kk = 0; kk < 4; ++kk)
+    for (int M = 2; M <= 6; M += 2)
+      for (int per = 1; per >= 0; --per) {
+        BatchGroup g{ks[kk], M, per, nm, 0};
+        for (int i = 0; i < count; ++i) {
+          const molt_grid& gr = inst[i].grid;
+          if (gr.order_M != M || (gr.bc == MOLT_BC_PERIODIC) != (per == 1)) continue;
+          const int K = xpass_pick_k(gr.nx, prec);
+          if (K != ks[kk]) continue;
+          const int lpb = 256 / xpass_tl(gr.nx, K);
+          const int nb = (gr.ny + lpb - 1) / lpb;
+          if (maps)
+            for (int b = 0; b < nb; ++b) maps->push_back(BlkMap{i, b});
+          g.nblk += nb;
+        }
+        if (g.nblk > 0) P.xg.push_back(g);
+        nm += g.nblk;
+      }
+  P.pt_off = nm;
+  P.pt_n = 0;
+  for (int i = 0; i < count; ++i) {
+    const int nb = diag_blocks((size_t)inst[i].grid.nx * inst[i].grid.ny);
+    if (maps)
+      for (int b = 0; b < nb; ++b) maps->push_back(BlkMap{i, b});
+    P.pt_n += nb;
+  }
+  nm += P.pt_n;
+  if (nm > 0x7fffffffULL) return fail(MOLT_EUNSUPPORTED, "batch too large");
+  P.nmap = nm;
+  P.map = off;
+  off += al256(nm * sizeof(BlkMap));
+  P.total = off;
+  return MOLT_OK;
+}
+
+static void fill_slot(const molt_instance& in, const Layout& L, char* w, molt_step_info* rec, SlotDesc& d) {
+  memset(&d, 0, sizeof(d));
+  const molt_grid& g = in.grid;
+  const molt_ch_params& p = in.params;
+  const int prec = p.precision;
+  const size_t esz = prec == MOLT_F64 ? 8 : 4;
+  const double hx = spacing(g.bc, g.nx, g.x0, g.x1), hy = spacing(g.bc, g.ny, g.y0, g.y1);
+  for (int v = 0; v < 2; ++v) {
+    // v = 1 (BDF2) only differs for a BDF2 instance after its start-up step
+    const double beta = (v == 1 && p.stepper == MOLT_BDF2) ? 2.0 / 3.0 : 1.0;
+    const StepParams sp = step_params(p.eps, p.dt, beta, p.sigma0);
+    const double al[2] = {1.0 / sqrt(sp.s1), 1.0 / sqrt(sp.s2)};
+    for (int k = 0; k < 2; ++k) {
+      d.cx[v][k] = make_line(g.nx, g.bc, g.order_M, al[k], hx);
+      d.cy[v][k] = make_line(g.ny, g.bc, g.order_M, al[k], hy);
+    }
+    d.sigma[v] = sp.sigma;
+    d.kappa[v] = sp.a / sp.s1;
+    d.s1[v] = sp.s1;
+    d.s2[v] = sp.s2;
+  }
+  d.u = in.d_u;
+  for (int f = 0; f < F_COUNT; ++f) d.fld[f] = w + L.fld[f];
+  d.tot = w + L.tot;
+  d.jln = w + L.jln;
+  d.st = (DevState*)(w + L.state);
+  d.rpart = (double*)(w + L.rpart);
+  d.partials = (double*)(w + L.partials);
+  d.rec = rec;
+  d.hx = hx;
+  d.hy = hy;
+  d.eps = p.eps;
+  d.area = hx * hy;
+  d.tol = p.tol;
+  d.nx = g.nx;
+  d.ny = g.ny;
+  d.bc = g.bc;
+  d.M = g.order_M;
+  d.stepper = p.stepper;
+  d.init = p.init;
+  d.nsteps = (int32_t)in.nsteps;
+  d.max_iter = p.max_iter;
+  d.fixed = p.fixed_iters;
+  const int K = xpass_pick_k(g.nx, prec);
+  d.tlx = xpass_tl(g.nx, K);
+  d.vecx = ((size_t)g.nx * esz) % 16 == 0 && (uintptr_t)in.d_u % 16 == 0 && (uintptr_t)w % 16 == 0;
+  d.xblocks = (g.ny + 256 / d.tlx - 1) / (256 / d.tlx);
+  ypass_shape(prec, g.ny, &d.ynth, &d.ynseg);
+  d.ycols = (g.nx + 63) / 64;
+  d.dblocks = diag_blocks((size_t)g.nx * g.ny);
+}
+
+static hipError_t batch_tick(const BatchPlan& P, const SlotDesc* sd, SlotCtl* ctl, const BlkMap* map, int count,
+                             hipStream_t s) {
+  const int prec = P.prec;
+  hipError_t e;
+  for (int pass = 1; pass <= 3; pass += 2) {
+    for (const BatchGroup& g : P.yg)
+      if ((e = launch_batch_y(prec, g.M, g.per != 0, pass, false, sd, ctl, map + g.off, g.nblk, s)) != hipSuccess)
+        return e;
+    if ((e = launch_batch_comb(prec, pass, sd, ctl, map + P.comb_off, P.comb_n, s)) != hipSuccess) return e;
+    for (const BatchGroup& g : P.yg)
+      if ((e = launch_batch_y(prec, g.M, g.per != 0, pass, true, sd, ctl, map + g.off, g.nblk, s)) != hipSuccess)
+        return e;
+    for (const BatchGroup& g : P.xg)
+      if ((e = launch_batch_x(prec, g.K, g.M, g.per != 0, pass + 1, sd, ctl, map + g.off, g.nblk, s)) != hipSuccess)
+        return e;
+  }
+  return launch_batch_tail(prec, sd, ctl, count, map + P.pt_off, P.pt_n, s);
+}
+
+static int32_t solve_batch_impl(const molt_instance* inst, int count, void* d_work, size_t work_bytes,
+                                molt_step_info* per_step, hipStream_t s) {
+  BatchPlan P;
+  std::vector<BlkMap> maps;
+  int32_t rc = batch_plan(inst, count, P, nullptr);
+  if (rc != MOLT_OK) return rc;
+  maps.reserve(P.nmap);
+  rc = batch_plan(inst, count, P, &maps);
+  if (rc != MOLT_OK) return rc;
+  if (!d_work || work_bytes < P.total) return fail(MOLT_EWORKSPACE, "workspace smaller than ch_batch_workspace_bytes()");
+  char* w = (char*)d_work;
+  std::vector<SlotDesc> descs(count);
+  molt_step_info* drec = (molt_step_info*)(w + P.rec);
+  for (int i = 0; i < count; ++i) fill_slot(inst[i], P.lay[i], w + P.slot_off[i], drec + P.rec_first[i], descs[i]);
+  SlotDesc* sd = (SlotDesc*)(w + P.desc);
+  SlotCtl* ctl = (SlotCtl*)(w + P.ctl);
+  BlkMap* map = (BlkMap*)(w + P.map);
+  int* dcnt = (int*)(w + P.cnt);
+  HIPCHK(hipMemcpyAsync(sd, descs.data(), (size_t)count * sizeof(SlotDesc), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(map, maps.data(), P.nmap * sizeof(BlkMap), hipMemcpyHostToDevice, s));
+  HIPCHK(launch_batch_init(sd, ctl, count, s));
+
+  const int ticks = g_batch_ticks;
+  const bool use_graph = g_batch_graph && s != nullptr && !g_prof_on;
+  hipGraphExec_t exec = nullptr;
+  if (use_graph) {
+    hipGraph_t graph = nullptr;
+    HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < ticks && e == hipSuccess; ++k) e = batch_tick(P, sd, ctl, map, count, s);
+    if (e == hipSuccess) e = launch_batch_count(ctl, count, dcnt, s);
+    const hipError_t e2 = hipStreamEndCapture(s, &graph);
+    if (e != hipSuccess || e2 != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return fail(MOLT_EHIP, std::string("batched tick capture: ") + hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(MOLT_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  }
+  // two pinned words and events: round r's active count is read while round
+  // r+1 runs
+  static thread_local int* pin = nullptr;
+  if (!pin && hipHostMalloc((void**)&pin, 2 * sizeof(int), hipHostMallocDefault) != hipSuccess) {
+    pin = nullptr;
+    if (exec) (void)hipGraphExecDestroy(exec);
+    return fail(MOLT_EHIP, "hipHostMalloc of the batch status words failed");
+  }
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  int32_t status = MOLT_OK;
+  std::string err;
+  for (int b = 0; b < 2 && err.empty(); ++b)
+    if (hipEventCreateWithFlags(&ev[b], hipEventDisableTiming) != hipSuccess) err = "hipEventCreate failed";
+  const long long max_rounds = P.max_ticks / ticks + 3;
+  long long rounds = 0;
+  bool finished = false;
+  while (err.empty() && !finished) {
+    const int b = (int)(rounds & 1);
+    hipError_t e = hipSuccess;
+    if (exec) {
+      e = hipGraphLaunch(exec, s);
+    } else {
+      for (int k = 0; k < ticks && e == hipSuccess; ++k) e = batch_tick(P, sd, ctl, map, count, s);
+      if (e == hipSuccess) e = launch_batch_count(ctl, count, dcnt, s);
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(&pin[b], dcnt, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipEventRecord(ev[b], s);
+    if (e != hipSuccess) {
+      err = std::string("batched round: ") + hipGetErrorString(e);
+      break;
+    }
+    ++rounds;
+    if (rounds >= 2) {
+      e = hipEventSynchronize(ev[1 - b]);
+      if (e != hipSuccess) {
+        err = std::string("hipEventSynchronize: ") + hipGetErrorString(e);
+        break;
+      }
+      if (g_prof_on) prof_drain();
+      if (pin[1 - b] == 0) finished = true;
+    }
+    if (!finished && rounds > max_rounds) err = "batched solve exceeded its tick bound";
+  }
+  const hipError_t es = hipStreamSynchronize(s);
+  if (err.empty() && es != hipSuccess) err = std::string("hipStreamSynchronize: ") + hipGetErrorString(es);
+  if (g_prof_on) prof_drain();
+  for (int b = 0; b < 2; ++b)
+    if (ev[b]) (void)hipEventDestroy(ev[b]);
+  if (exec) (void)hipGraphExecDestroy(exec);
+  if (!err.empty()) return fail(MOLT_EHIP, err);
+  std::vector<molt_step_info> rec(P.nrec);
+  if (P.nrec > 0) {
+    HIPCHK(hipMemcpyAsync(rec.data(), drec, P.nrec * sizeof(molt_step_info), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+  }
+  for (size_t r = 0; r < P.nrec; ++r)
+    if (!rec[r].converged) status = MOLT_NOT_CONVERGED;
+  if (per_step && P.nrec > 0) memcpy(per_step, rec.data(), P.nrec * sizeof(molt_step_info));
+  return status;
+}
+
 }  // namespace molt
 
 using namespace molt;
@@ -468,7 +787,15 @@ int32_t molt_set_option(int32_t option, int64_t value) {
     g_fused_min_items = value;
     return MOLT_OK;
   }
-  return fail(MOLT_EINVAL, "unknown option or negative value");
+  if (option == MOLT_OPT_BATCH_TICKS && value >= 1 && value <= 1024) {
+    g_batch_ticks = (int)value;
+    return MOLT_OK;
+  }
+  if (option == MOLT_OPT_BATCH_GRAPH && (value == 0 || value == 1)) {
+    g_batch_graph = (int)value;
+    return MOLT_OK;
+  }
+  return fail(MOLT_EINVAL, "unknown option or value out of range");
 }
 
 int32_t molt_profile(int32_t enable) {
@@ -590,6 +917,19 @@ int32_t ch_solve(const molt_grid* g, const molt_ch_params* p, void* d_u, int64_t
     if (per_step) per_step[k] = inf;
   }
   return status;
+}
+
+size_t ch_batch_workspace_bytes(const molt_instance* inst, int32_t count) {
+  g_err.clear();
+  BatchPlan P;
+  if (batch_plan(inst, count, P, nullptr) != MOLT_OK) return 0;
+  return P.total;
+}
+
+int32_t ch_solve_batch(const molt_instance* inst, int32_t count, void* d_work, size_t work_bytes,
+                       molt_step_info* per_step, void* stream) {
+  g_err.clear();
+  return solve_batch_impl(inst, count, d_work, work_bytes, per_step, (hipStream_t)stream);
 }
 
 }  // extern "C"

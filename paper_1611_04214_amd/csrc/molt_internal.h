@@ -72,6 +72,49 @@ struct YFused {
   long long spin_limit;    // bound of the wait loop (sets DevState::error when hit)
 };
 
+// --------------------------------------------------------------------------
+// Batched instances: every instance ("slot") advances on its own through the
+// phases of its time steps; each tick runs the four line passes once over all
+// slots (the rhs/R sweeps for slots in PH_R, one fixed-point iteration for
+// slots in PH_IT), then closes iterations and finishes converged steps.
+// --------------------------------------------------------------------------
+enum SlotPhase { PH_R = 0, PH_IT = 1, PH_IDLE = 2 };
+
+// workspace fields of one problem
+enum { F_R = 0, F_DL, F_W, F_A1, F_B1, F_C, F_Q, F_M, F_N, F_HIST, F_COUNT };
+
+struct SlotCtl {  // mutable control of one slot (device)
+  int phase;      // SlotPhase
+  int step;       // steps completed
+  int var;        // coefficient set of the current step: 0 BE, 1 BDF2
+  int pad;
+};
+
+struct SlotDesc {          // constants of one slot, built on the host
+  LineCoef cx[2][2];       // [BE, BDF2][alpha1, alpha2] along x
+  LineCoef cy[2][2];       // the same along y
+  double sigma[2], kappa[2], s1[2], s2[2];
+  void* u;                 // the caller's field (u^n in, u^{n+1} out)
+  void* fld[F_COUNT];      // workspace fields
+  void* tot;               // y-pass segment totals / seeds
+  void* jln;               // y-pass periodic closing-cell quadratures
+  DevState* st;
+  double* rpart;           // residual partials, one per x-pass block
+  double* partials;        // mass / energy partials, two per diagnostic block
+  molt_step_info* rec;     // nsteps per-step records
+  double hx, hy, eps, area;
+  double tol;
+  int32_t nx, ny, bc, M;
+  int32_t stepper, init, nsteps, max_iter;
+  int32_t fixed, tlx, vecx, xblocks;  // x-pass: threads per row, 16-byte access, blocks
+  int32_t ynth, ynseg, ycols, dblocks;  // y-pass: threads per column, segments, 64-column strips
+};
+
+// one block of a batched launch: (slot, block index within the slot)
+struct BlkMap {
+  int32_t slot, blk;
+};
+
 // Optional per-kernel timing with HIP events on the launch stream (off unless
 // molt_profile(1) was called).  kind = family * 8 + program.
 enum KernelFamily { KF_XPASS = 0, KF_YTOT = 1, KF_YCOMB = 2, KF_YFIN = 3, KF_POINTWISE = 4, KF_OTHER = 5 };

@@ -24,9 +24,9 @@ MOLT_F64, MOLT_F32 = 0, 1
 
 #: every symbol include/molt.h declares
 EXPORTS = ("mol_t_helmholtz_sweep", "molt_sweep_workspace_bytes", "ch_workspace_bytes", "ch_step",
-           "ch_solve", "molt_strerror", "molt_last_error", "molt_profile", "molt_profile_read",
-           "molt_set_option")
-MOLT_OPT_FUSED_Y_MIN_ITEMS = 1
+           "ch_solve", "ch_batch_workspace_bytes", "ch_solve_batch", "molt_strerror", "molt_last_error",
+           "molt_profile", "molt_profile_read", "molt_set_option")
+MOLT_OPT_FUSED_Y_MIN_ITEMS, MOLT_OPT_BATCH_TICKS, MOLT_OPT_BATCH_GRAPH = 1, 2, 3
 
 KERNEL_FAMILIES = ("xpass", "ytot", "ycomb", "yfin", "pointwise", "other")
 PROGRAMS = ("sweep", "rhs", "P1", "P2", "P3", "P4")
@@ -60,6 +60,11 @@ class molt_step_info(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class molt_instance(ctypes.Structure):
+    _fields_ = [("grid", molt_grid), ("params", molt_ch_params), ("d_u", ctypes.c_void_p),
+                ("nsteps", ctypes.c_int64)]
+
+
 class molt_prof_entry(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double)]
 
@@ -88,6 +93,11 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.ch_step.restype = ctypes.c_int32
     lib.ch_solve.argtypes = [G, P, vp, ctypes.c_int64, vp, sz, ctypes.POINTER(molt_step_info), vp]
     lib.ch_solve.restype = ctypes.c_int32
+    I = ctypes.POINTER(molt_instance)
+    lib.ch_batch_workspace_bytes.argtypes = [I, ctypes.c_int32]
+    lib.ch_batch_workspace_bytes.restype = sz
+    lib.ch_solve_batch.argtypes = [I, ctypes.c_int32, vp, sz, ctypes.POINTER(molt_step_info), vp]
+    lib.ch_solve_batch.restype = ctypes.c_int32
     lib.molt_strerror.argtypes = [ctypes.c_int32]
     lib.molt_strerror.restype = ctypes.c_char_p
     lib.molt_last_error.argtypes = []
@@ -141,6 +151,14 @@ def ch_solve(grid: molt_grid, params: molt_ch_params, d_u: int, nsteps: int, d_w
              per_step=None, stream: int = 0) -> int:
     return load().ch_solve(ctypes.byref(grid), ctypes.byref(params), d_u, nsteps, d_work or None, work_bytes,
                            per_step, stream or None)
+
+
+def ch_batch_workspace_bytes(inst, count: int) -> int:
+    return load().ch_batch_workspace_bytes(inst, count)
+
+
+def ch_solve_batch(inst, count: int, d_work: int, work_bytes: int, per_step=None, stream: int = 0) -> int:
+    return load().ch_solve_batch(inst, count, d_work or None, work_bytes, per_step, stream or None)
 
 
 def molt_strerror(status: int) -> str:
@@ -233,3 +251,36 @@ def solve(u, grid: molt_grid, params: molt_ch_params, nsteps: int, work=None):
     st = _check(ch_solve(grid, params, u.data_ptr(), nsteps, work.data_ptr(), work.numel(), infos,
                          _stream(torch)), "ch_solve")
     return st, [infos[i] for i in range(nsteps)]
+
+
+def make_instances(specs) -> "ctypes.Array":
+    """molt_instance array from (grid, params, device tensor, nsteps) tuples."""
+    arr = (molt_instance * len(specs))()
+    for i, (g, p, u, ns) in enumerate(specs):
+        arr[i].grid = g
+        arr[i].params = p
+        arr[i].d_u = u.data_ptr()
+        arr[i].nsteps = ns
+    return arr
+
+
+def solve_batch(specs, work=None, stream=None):
+    """ch_solve_batch over (grid, params, device tensor, nsteps) tuples, in place on
+    the tensors; returns (status, per-instance lists of molt_step_info)."""
+    import torch
+    inst = make_instances(specs)
+    need = ch_batch_workspace_bytes(inst, len(specs))
+    if need == 0:
+        raise MoltError(MOLT_EINVAL, "ch_batch_workspace_bytes")
+    dev = specs[0][2].device
+    if work is None or work.numel() < need:
+        work = workspace(need, dev)
+    nrec = sum(int(s[3]) for s in specs)
+    recs = (molt_step_info * max(nrec, 1))()
+    st = _check(ch_solve_batch(inst, len(specs), work.data_ptr(), work.numel(), recs,
+                               _stream(torch) if stream is None else stream), "ch_solve_batch")
+    out, k = [], 0
+    for s in specs:
+        out.append([recs[k + j] for j in range(int(s[3]))])
+        k += int(s[3])
+    return st, out

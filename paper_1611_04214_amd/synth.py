@@ -99,3 +99,31 @@ def workload_u0(name: str, n: int | None = None) -> np.ndarray:
     if name == "ch2d_periodic_bdf2_4096":
         return u0_normal_noise(seed, side, side, 0.3, 0.05)
     raise KeyError(name)
+
+
+# Batched workload: independent 2D instances with uneven sizes and parameters.
+#: seed of the batched workload's draws (fourth workload recipe)
+BATCH_SEED = BASE_SEED + 4
+
+
+def batch_instances(count: int = 256, seed: int = BATCH_SEED, steps: int = 100) -> list:
+    """Seeded instance draws: side n = round(exp(U(ln 64, ln 1024))), eps ~ U[0.005, 0.05],
+    dt ~ U[1e-6, 1e-4], boundary periodic/Neumann and stepper BE/BDF2 each with
+    probability 1/2, domain [0,1]^2, M = 4, tolerance 1e-8, `steps` steps each."""
+    un, ue, ut = uniform(seed, count, 0), uniform(seed, count, 1), uniform(seed, count, 2)
+    ub, us = uniform(seed, count, 3), uniform(seed, count, 4)
+    lo, hi = np.log(64.0), np.log(1024.0)
+    out = []
+    for i in range(count):
+        out.append(dict(n=int(round(float(np.exp(lo + un[i] * (hi - lo))))),
+                        eps=0.005 + 0.045 * float(ue[i]), dt=1e-6 + (1e-4 - 1e-6) * float(ut[i]),
+                        bc="periodic" if ub[i] < 0.5 else "neumann",
+                        stepper="BE" if us[i] < 0.5 else "BDF2",
+                        steps=steps, M=4, L=1.0, tol=1e-8, seed=seed, stream=16 + i))
+    return out
+
+
+def instance_u0(inst: dict) -> np.ndarray:
+    """0.05 U(-1,1) i.i.d. per node on the instance's own stream (n x n)."""
+    n = inst["n"]
+    return (0.05 * (2.0 * uniform(inst["seed"], n * n, inst["stream"]) - 1.0)).reshape(n, n)

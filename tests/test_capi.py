@@ -37,6 +37,7 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(molt.molt_grid) == 48
     assert ctypes.sizeof(molt.molt_ch_params) == 56
     assert ctypes.sizeof(molt.molt_step_info) == 56
+    assert ctypes.sizeof(molt.molt_instance) == 120
 
 
 def test_strerror_names_every_status(lib):
@@ -98,3 +99,64 @@ def test_sweep_argument_checks(lib):
     assert molt.mol_t_helmholtz_sweep(g, 0, -1.0, 0, 1, 1, 1, 0, 0) == molt.MOLT_EINVAL
     assert molt.mol_t_helmholtz_sweep(g, 0, 1.0, 0, 0, 1, 1, 0, 0) == molt.MOLT_EINVAL
     assert molt.mol_t_helmholtz_sweep(g, 1, 1.0, 0, 1, 1, 1, 0, 0) == molt.MOLT_EWORKSPACE
+
+
+def _inst(specs):
+    arr = (molt.molt_instance * len(specs))()
+    for i, (g, p, ns) in enumerate(specs):
+        arr[i].grid, arr[i].params, arr[i].d_u, arr[i].nsteps = g, p, 4096 * (i + 1), ns
+    return arr
+
+
+def test_batch_workspace_query(lib):
+    p = molt.make_params(0.02, 1e-5, precision=molt.MOLT_F32, stepper=molt.MOLT_BDF2)
+    gs = [molt.make_grid(n, n + 3, bc=bc, M=4) for n, bc in ((64, 0), (100, 1), (300, 0))]
+    one = [molt.ch_workspace_bytes(g, p) for g in gs]
+    arr = _inst([(g, p, 5) for g in gs])
+    need = molt.ch_batch_workspace_bytes(arr, 3)
+    assert need >= sum(one)
+    # a batch of one needs the instance's workspace plus its descriptors and maps only
+    assert molt.ch_batch_workspace_bytes(_inst([(gs[0], p, 5)]), 1) < one[0] + (1 << 16)
+
+
+@pytest.mark.parametrize("case", ["count0", "mixed_precision", "one_d", "dirichlet", "null_field",
+                                  "negative_steps", "bad_params"])
+def test_batch_argument_checks(lib, case):
+    p = molt.make_params(0.02, 1e-5, precision=molt.MOLT_F32)
+    g = molt.make_grid(64, 64, bc=molt.MOLT_BC_PERIODIC, M=4)
+    specs = [(g, p, 3), (molt.make_grid(80, 72, bc=molt.MOLT_BC_NEUMANN, M=4), p, 2)]
+    count = 2
+    arr = _inst(specs)
+    if case == "count0":
+        count = 0
+    elif case == "mixed_precision":
+        arr[1].params.precision = molt.MOLT_F64
+    elif case == "one_d":
+        arr[1].grid.ny = 1
+    elif case == "dirichlet":
+        arr[0].grid.bc = molt.MOLT_BC_DIRICHLET
+    elif case == "null_field":
+        arr[1].d_u = None
+    elif case == "negative_steps":
+        arr[0].nsteps = -1
+    elif case == "bad_params":
+        arr[1].params.eps = -1.0
+    assert molt.ch_batch_workspace_bytes(arr, count) == 0
+    rc = molt.ch_solve_batch(arr, count, 1, 1 << 40)
+    assert rc in (molt.MOLT_EINVAL, molt.MOLT_EUNSUPPORTED), rc
+    assert molt.molt_last_error() != ""
+
+
+def test_batch_small_workspace_is_rejected(lib):
+    p = molt.make_params(0.02, 1e-5, precision=molt.MOLT_F32)
+    arr = _inst([(molt.make_grid(64, 64, M=4), p, 3)])
+    need = molt.ch_batch_workspace_bytes(arr, 1)
+    assert molt.ch_solve_batch(arr, 1, 1, need - 1) == molt.MOLT_EWORKSPACE
+
+
+def test_batch_options(lib):
+    assert molt.molt_set_option(molt.MOLT_OPT_BATCH_TICKS, 0) == molt.MOLT_EINVAL
+    assert molt.molt_set_option(molt.MOLT_OPT_BATCH_TICKS, 8) == molt.MOLT_OK
+    assert molt.molt_set_option(molt.MOLT_OPT_BATCH_GRAPH, 2) == molt.MOLT_EINVAL
+    assert molt.molt_set_option(molt.MOLT_OPT_BATCH_GRAPH, 1) == molt.MOLT_OK
+    assert molt.molt_set_option(99, 1) == molt.MOLT_EINVAL
