@@ -193,6 +193,30 @@ int32_t ch_solve_batch(const molt_instance* inst, int32_t count, void* d_work, s
                        molt_step_info* per_step, void* stream);
 
 /*
+ * Line-block shapes (not part of the method; they change only the rounding
+ * order of the scans).  Per precision and line-length class (class c holds
+ * lines of n <= 128 * 2^c nodes, c = 0..MOLT_TUNE_CLASSES-1, the last class
+ * up to the longest supported line) the table holds kx, the nodes per thread
+ * of an x-line (4, 8, 16, 32 FP32 only; a line fits one 256-thread block:
+ * n <= 256*kx), and ky, the nodes per thread of a y-line (4, 8, 16 FP32 only).
+ * Every path reads the table at call time, so ch_step, ch_solve and
+ * ch_solve_batch agree bit for bit under one table.  Process-wide; change it
+ * only while no solve is running.
+ *  molt_tune_get / molt_tune_set: read / write one class (MOLT_EINVAL if the
+ *    shape is not valid for the class).
+ *  molt_autotune: for every class up to max_n (128..8192 FP32, ..4096 FP64),
+ *    times an iteration y-pass for each ky, then an iteration x-pass for each
+ *    kx, on an n x n periodic field in the caller's workspace (at least
+ *    molt_autotune_workspace_bytes), and stores the fastest shapes.
+ *    Synchronizes `stream`.
+ */
+#define MOLT_TUNE_CLASSES 7
+int32_t molt_tune_get(int32_t precision, int32_t size_class, int32_t* kx, int32_t* ky);
+int32_t molt_tune_set(int32_t precision, int32_t size_class, int32_t kx, int32_t ky);
+size_t molt_autotune_workspace_bytes(int32_t precision, int32_t max_n);
+int32_t molt_autotune(int32_t precision, int32_t max_n, void* d_work, size_t work_bytes, void* stream);
+
+/*
  * Kernel timing (not part of the method): HIP events recorded around every
  * kernel the library launches, on the launch stream, accumulated per kind.
  * kind = family*8 + program; family 0 x-pass, 1 y-pass totals, 2 y-pass

@@ -16,11 +16,6 @@
 
 namespace molt {
 
-template <typename T>
-struct YK {
-  static constexpr int K = sizeof(T) == 8 ? 8 : 16;  // nodes per thread along y
-};
-
 // arguments of pass `pass` (1..4) of a slot in phase ph (the same fields as
 // the single-problem driver uses)
 __device__ __forceinline__ PassArgs slot_args(const SlotDesc& d, int ph, int pass, int var, int mode) {
@@ -86,11 +81,11 @@ __device__ __forceinline__ PassArgs slot_args(const SlotDesc& d, int ph, int pas
   return a;
 }
 
-// y-pass `PASS` (1 or 3): totals (FIN = false) or final scans (FIN = true)
-template <typename T, int M, bool PER, int PASS, bool FIN>
+// y-pass `PASS` (1 or 3) with K nodes per thread: totals (FIN = false) or
+// final scans (FIN = true)
+template <typename T, int K, int M, bool PER, int PASS, bool FIN>
 __global__ void MOLT_PASS_ATTR ypass_batch_kernel(const SlotDesc* __restrict__ sd, const SlotCtl* __restrict__ ctl,
                                                   const BlkMap* __restrict__ map) {
-  constexpr int K = YK<T>::K;
   const BlkMap e = map[blockIdx.x];
   const SlotDesc& d = sd[e.slot];
   const SlotCtl cc = ctl[e.slot];
@@ -124,7 +119,6 @@ template <typename T>
 __global__ void __launch_bounds__(1024) ycomb_batch_kernel(const SlotDesc* __restrict__ sd,
                                                            const SlotCtl* __restrict__ ctl,
                                                            const BlkMap* __restrict__ map, int pass) {
-  constexpr int K = YK<T>::K;
   const BlkMap e = map[blockIdx.x];
   const SlotDesc& d = sd[e.slot];
   const SlotCtl cc = ctl[e.slot];
@@ -135,7 +129,11 @@ __global__ void __launch_bounds__(1024) ycomb_batch_kernel(const SlotDesc* __res
   if (f >= F) return;
   // pass 1: alpha2 in the R phase, alpha1 in an iteration; pass 3 the other way
   const LineCoef& c = d.cy[cc.var][((pass == 1) == r) ? 1 : 0];
-  ycomb_body<T, 8>(c, r ? nullptr : d.st, d.nx, d.ynseg, kRG * K, F, (T*)d.tot, (const T*)d.jln, bx, f, 0);
+  const int ct = (d.ynseg + kCombWaves - 1) / kCombWaves;
+  if (ct <= 8)
+    ycomb_body<T, 8>(c, r ? nullptr : d.st, d.nx, d.ynseg, kRG * d.yk, F, (T*)d.tot, (const T*)d.jln, bx, f, 0);
+  else
+    ycomb_body<T, 32>(c, r ? nullptr : d.st, d.nx, d.ynseg, kRG * d.yk, F, (T*)d.tot, (const T*)d.jln, bx, f, 0);
 }
 
 // x-pass `PASS` (2 or 4)
@@ -161,11 +159,13 @@ __global__ void MOLT_PASS_ATTR xpass_batch_kernel(const SlotDesc* __restrict__ s
   }
 }
 
-// iteration close: one block per slot
+// iteration close: one block per listed slot
 __global__ void __launch_bounds__(256) close_batch_kernel(const SlotDesc* __restrict__ sd,
-                                                          const SlotCtl* __restrict__ ctl) {
-  const SlotDesc& d = sd[blockIdx.x];
-  if (ctl[blockIdx.x].phase != PH_IT) return;
+                                                          const SlotCtl* __restrict__ ctl,
+                                                          const BlkMap* __restrict__ slots) {
+  const int slot = slots[blockIdx.x].slot;
+  const SlotDesc& d = sd[slot];
+  if (ctl[slot].phase != PH_IT) return;
   residual_close_body(d.rpart, d.xblocks, d.st);
 }
 
@@ -202,8 +202,9 @@ __global__ void __launch_bounds__(256) diag_batch_kernel(const SlotDesc* __restr
 
 // tick end, one block per slot: R -> first iteration (state reset); a finished
 // step -> mass and energy, the step record, then the next step's R phase or idle
-__global__ void __launch_bounds__(256) tick_end_batch_kernel(const SlotDesc* __restrict__ sd, SlotCtl* ctl) {
-  const int slot = blockIdx.x;
+__global__ void __launch_bounds__(256) tick_end_batch_kernel(const SlotDesc* __restrict__ sd, SlotCtl* ctl,
+                                                             const BlkMap* __restrict__ slots) {
+  const int slot = slots[blockIdx.x].slot;
   const SlotDesc& d = sd[slot];
   const SlotCtl cc = ctl[slot];
   DevState* st = d.st;
@@ -282,41 +283,54 @@ __global__ void __launch_bounds__(256) count_active_kernel(const SlotCtl* __rest
 // --------------------------------------------------------------------------
 // launchers
 // --------------------------------------------------------------------------
-template <typename T, int M, bool PER>
+template <typename T, int K, int M, bool PER>
 static hipError_t ybatch_m(int pass, bool fin, const SlotDesc* sd, const SlotCtl* ctl, const BlkMap* map, int nblk,
                            hipStream_t s) {
   const dim3 blk(64, kRG);
   if (pass == 1) {
-    if (fin) hipLaunchKernelGGL((ypass_batch_kernel<T, M, PER, 1, true>), dim3(nblk), blk, 0, s, sd, ctl, map);
-    else hipLaunchKernelGGL((ypass_batch_kernel<T, M, PER, 1, false>), dim3(nblk), blk, 0, s, sd, ctl, map);
+    if (fin) hipLaunchKernelGGL((ypass_batch_kernel<T, K, M, PER, 1, true>), dim3(nblk), blk, 0, s, sd, ctl, map);
+    else hipLaunchKernelGGL((ypass_batch_kernel<T, K, M, PER, 1, false>), dim3(nblk), blk, 0, s, sd, ctl, map);
   } else {
-    if (fin) hipLaunchKernelGGL((ypass_batch_kernel<T, M, PER, 3, true>), dim3(nblk), blk, 0, s, sd, ctl, map);
-    else hipLaunchKernelGGL((ypass_batch_kernel<T, M, PER, 3, false>), dim3(nblk), blk, 0, s, sd, ctl, map);
+    if (fin) hipLaunchKernelGGL((ypass_batch_kernel<T, K, M, PER, 3, true>), dim3(nblk), blk, 0, s, sd, ctl, map);
+    else hipLaunchKernelGGL((ypass_batch_kernel<T, K, M, PER, 3, false>), dim3(nblk), blk, 0, s, sd, ctl, map);
   }
   return hipGetLastError();
 }
 
-template <typename T>
-static hipError_t ybatch_t(int M, bool per, int pass, bool fin, const SlotDesc* sd, const SlotCtl* ctl,
+template <typename T, int K>
+static hipError_t ybatch_k(int M, bool per, int pass, bool fin, const SlotDesc* sd, const SlotCtl* ctl,
                            const BlkMap* map, int nblk, hipStream_t s) {
   switch (M) {
-    case 2: return per ? ybatch_m<T, 2, true>(pass, fin, sd, ctl, map, nblk, s)
-                       : ybatch_m<T, 2, false>(pass, fin, sd, ctl, map, nblk, s);
-    case 4: return per ? ybatch_m<T, 4, true>(pass, fin, sd, ctl, map, nblk, s)
-                       : ybatch_m<T, 4, false>(pass, fin, sd, ctl, map, nblk, s);
-    case 6: return per ? ybatch_m<T, 6, true>(pass, fin, sd, ctl, map, nblk, s)
-                       : ybatch_m<T, 6, false>(pass, fin, sd, ctl, map, nblk, s);
+    case 2: return per ? ybatch_m<T, K, 2, true>(pass, fin, sd, ctl, map, nblk, s)
+                       : ybatch_m<T, K, 2, false>(pass, fin, sd, ctl, map, nblk, s);
+    case 4: return per ? ybatch_m<T, K, 4, true>(pass, fin, sd, ctl, map, nblk, s)
+                       : ybatch_m<T, K, 4, false>(pass, fin, sd, ctl, map, nblk, s);
+    case 6: return per ? ybatch_m<T, K, 6, true>(pass, fin, sd, ctl, map, nblk, s)
+                       : ybatch_m<T, K, 6, false>(pass, fin, sd, ctl, map, nblk, s);
   }
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_batch_y(int prec, int M, bool per, int pass, bool fin, const SlotDesc* sd, const SlotCtl* ctl,
-                          const BlkMap* map, int nblk, hipStream_t s) {
+template <typename T>
+static hipError_t ybatch_t(int K, int M, bool per, int pass, bool fin, const SlotDesc* sd, const SlotCtl* ctl,
+                           const BlkMap* map, int nblk, hipStream_t s) {
+  switch (K) {
+    case 4: return ybatch_k<T, 4>(M, per, pass, fin, sd, ctl, map, nblk, s);
+    case 8: return ybatch_k<T, 8>(M, per, pass, fin, sd, ctl, map, nblk, s);
+    case 16:
+      if constexpr (sizeof(T) == 4) return ybatch_k<T, 16>(M, per, pass, fin, sd, ctl, map, nblk, s);
+      return hipErrorInvalidValue;
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_batch_y(int prec, int K, int M, bool per, int pass, bool fin, const SlotDesc* sd,
+                          const SlotCtl* ctl, const BlkMap* map, int nblk, hipStream_t s) {
   if (nblk <= 0) return hipSuccess;
   const int kind = (fin ? KF_YFIN : KF_YTOT) * 8 + (pass == 1 ? PROG_P1 : PROG_P3);
   if (g_prof_on) prof_begin(kind, s);
-  const hipError_t e = prec == MOLT_F64 ? ybatch_t<double>(M, per, pass, fin, sd, ctl, map, nblk, s)
-                                        : ybatch_t<float>(M, per, pass, fin, sd, ctl, map, nblk, s);
+  const hipError_t e = prec == MOLT_F64 ? ybatch_t<double>(K, M, per, pass, fin, sd, ctl, map, nblk, s)
+                                        : ybatch_t<float>(K, M, per, pass, fin, sd, ctl, map, nblk, s);
   if (g_prof_on) prof_end(kind, s);
   return e;
 }
@@ -384,12 +398,12 @@ hipError_t launch_batch_x(int prec, int K, int M, bool per, int pass, const Slot
   return e;
 }
 
-// close, step finish, diagnostics and tick end (kind "other_1")
-hipError_t launch_batch_tail(int prec, const SlotDesc* sd, SlotCtl* ctl, int nslots, const BlkMap* pmap, int npblk,
-                             hipStream_t s) {
+// close, step finish, diagnostics and tick end (kind "other_1") of the listed slots
+hipError_t launch_batch_tail(int prec, const SlotDesc* sd, SlotCtl* ctl, const BlkMap* slots, int nslots,
+                             const BlkMap* pmap, int npblk, hipStream_t s) {
   if (nslots <= 0) return hipSuccess;
   if (g_prof_on) prof_begin(KF_OTHER * 8 + 1, s);
-  hipLaunchKernelGGL(close_batch_kernel, dim3(nslots), dim3(256), 0, s, sd, (const SlotCtl*)ctl);
+  hipLaunchKernelGGL(close_batch_kernel, dim3(nslots), dim3(256), 0, s, sd, (const SlotCtl*)ctl, slots);
   if (prec == MOLT_F64) {
     hipLaunchKernelGGL((finish_batch_kernel<double>), dim3(npblk), dim3(256), 0, s, sd, (const SlotCtl*)ctl, pmap);
     hipLaunchKernelGGL((diag_batch_kernel<double>), dim3(npblk), dim3(256), 0, s, sd, (const SlotCtl*)ctl, pmap);
@@ -397,7 +411,7 @@ hipError_t launch_batch_tail(int prec, const SlotDesc* sd, SlotCtl* ctl, int nsl
     hipLaunchKernelGGL((finish_batch_kernel<float>), dim3(npblk), dim3(256), 0, s, sd, (const SlotCtl*)ctl, pmap);
     hipLaunchKernelGGL((diag_batch_kernel<float>), dim3(npblk), dim3(256), 0, s, sd, (const SlotCtl*)ctl, pmap);
   }
-  hipLaunchKernelGGL(tick_end_batch_kernel, dim3(nslots), dim3(256), 0, s, sd, ctl);
+  hipLaunchKernelGGL(tick_end_batch_kernel, dim3(nslots), dim3(256), 0, s, sd, ctl, slots);
   if (g_prof_on) prof_end(KF_OTHER * 8 + 1, s);
   return hipGetLastError();
 }

@@ -31,14 +31,21 @@ int xpass_max_n(int prec);
 int xpass_pick_k(int n, int prec);
 int xpass_tl(int n, int K);
 void ypass_shape(int prec, int n, int* nth, int* nseg);
-hipError_t launch_batch_y(int prec, int M, bool per, int pass, bool fin, const SlotDesc* sd, const SlotCtl* ctl,
-                          const BlkMap* map, int nblk, hipStream_t s);
+hipError_t launch_batch_y(int prec, int K, int M, bool per, int pass, bool fin, const SlotDesc* sd,
+                          const SlotCtl* ctl, const BlkMap* map, int nblk, hipStream_t s);
+int ypass_pick_k(int n, int prec);
+int ypass_max_segments(int n);
+int xpass_min_k(int n, int prec);
+int tune_class(int n);
+bool tune_valid(int prec, int cls, int kx, int ky);
+void tune_get(int prec, int cls, int* kx, int* ky);
+void tune_set(int prec, int cls, int kx, int ky);
 hipError_t launch_batch_comb(int prec, int pass, const SlotDesc* sd, const SlotCtl* ctl, const BlkMap* map, int nblk,
                              hipStream_t s);
 hipError_t launch_batch_x(int prec, int K, int M, bool per, int pass, const SlotDesc* sd, const SlotCtl* ctl,
                           const BlkMap* map, int nblk, hipStream_t s);
-hipError_t launch_batch_tail(int prec, const SlotDesc* sd, SlotCtl* ctl, int nslots, const BlkMap* pmap, int npblk,
-                             hipStream_t s);
+hipError_t launch_batch_tail(int prec, const SlotDesc* sd, SlotCtl* ctl, const BlkMap* slots, int nslots,
+                             const BlkMap* pmap, int npblk, hipStream_t s);
 hipError_t launch_batch_init(const SlotDesc* sd, SlotCtl* ctl, int nslots, hipStream_t s);
 hipError_t launch_batch_count(const SlotCtl* ctl, int nslots, int* out, hipStream_t s);
 
@@ -473,11 +480,16 @@ struct BatchPlan {
   std::vector<size_t> rec_first;  // first record of each slot
   size_t nrec = 0;
   size_t desc = 0, ctl = 0, rec = 0, map = 0, cnt = 0, total = 0;
-  std::vector<BatchGroup> yg, xg;
-  size_t comb_off = 0, pt_off = 0;
-  int comb_n = 0, pt_n = 0;
-  size_t nmap = 0;
+  size_t nmap = 0;          // capacity of the map area in entries
   long long max_ticks = 0;  // upper bound of the ticks any slot needs
+};
+
+// Block maps of the slots in `act` (ascending): per-group ranges of one map.
+struct BatchMaps {
+  std::vector<BatchGroup> yg, xg;
+  size_t comb_off = 0, pt_off = 0, sl_off = 0;
+  int comb_n = 0, pt_n = 0, sl_n = 0;
+  std::vector<BlkMap> map;
 };
 
 static int32_t check_instance(const molt_instance& in, int prec) {
@@ -493,8 +505,66 @@ static int32_t check_instance(const molt_instance& in, int prec) {
   return MOLT_OK;
 }
 
-// Workspace layout and block maps of a batch (maps filled when `maps` is given).
-static int32_t batch_plan(const molt_instance* inst, int count, BatchPlan& P, std::vector<BlkMap>* maps) {
+// y-passes are grouped by (M, boundary kind), x-passes by (K, M, boundary
+// kind); the combine, pointwise and per-slot kernels take every listed slot.
+static void batch_maps(const molt_instance* inst, const std::vector<int>& act, int prec, BatchMaps& B) {
+  B.yg.clear();
+  B.xg.clear();
+  B.map.clear();
+  std::vector<BlkMap>& m = B.map;
+  const int ks[4] = {4, 8, 16, 32};
+  for (int kk = 0; kk < 3; ++kk)
+  for (int M = 2; M <= 6; M += 2)
+    for (int per = 1; per >= 0; --per) {
+      BatchGroup g{ks[kk], M, per, m.size(), 0};
+      for (int i : act) {
+        const molt_grid& gr = inst[i].grid;
+        if (gr.order_M != M || (gr.bc == MOLT_BC_PERIODIC) != (per == 1)) continue;
+        if (ypass_pick_k(gr.ny, prec) != ks[kk]) continue;
+        int nth, nseg;
+        ypass_shape(prec, gr.ny, &nth, &nseg);
+        const int nb = ((gr.nx + 63) / 64) * nseg;
+        for (int b = 0; b < nb; ++b) m.push_back(BlkMap{i, b});
+      }
+      g.nblk = (int)(m.size() - g.off);
+      if (g.nblk > 0) B.yg.push_back(g);
+    }
+  B.comb_off = m.size();
+  for (int i : act) {
+    const int nb = 2 * ((inst[i].grid.nx + 63) / 64);
+    for (int b = 0; b < nb; ++b) m.push_back(BlkMap{i, b});
+  }
+  B.comb_n = (int)(m.size() - B.comb_off);
+  for (int kk = 0; kk < 4; ++kk)
+    for (int M = 2; M <= 6; M += 2)
+      for (int per = 1; per >= 0; --per) {
+        BatchGroup g{ks[kk], M, per, m.size(), 0};
+        for (int i : act) {
+          const molt_grid& gr = inst[i].grid;
+          if (gr.order_M != M || (gr.bc == MOLT_BC_PERIODIC) != (per == 1)) continue;
+          const int K = xpass_pick_k(gr.nx, prec);
+          if (K != ks[kk]) continue;
+          const int lpb = 256 / xpass_tl(gr.nx, K);
+          const int nb = (gr.ny + lpb - 1) / lpb;
+          for (int b = 0; b < nb; ++b) m.push_back(BlkMap{i, b});
+        }
+        g.nblk = (int)(m.size() - g.off);
+        if (g.nblk > 0) B.xg.push_back(g);
+      }
+  B.pt_off = m.size();
+  for (int i : act) {
+    const int nb = diag_blocks((size_t)inst[i].grid.nx * inst[i].grid.ny);
+    for (int b = 0; b < nb; ++b) m.push_back(BlkMap{i, b});
+  }
+  B.pt_n = (int)(m.size() - B.pt_off);
+  B.sl_off = m.size();
+  for (int i : act) m.push_back(BlkMap{i, 0});
+  B.sl_n = (int)(m.size() - B.sl_off);
+}
+
+// Workspace layout of a batch; the map area holds the maps of every slot (the
+// maps of any subset are shorter).
+static int32_t batch_plan(const molt_instance* inst, int count, BatchPlan& P) {
   if (!inst || count < 1 || count > 65535) return fail(MOLT_EINVAL, "count must be in 1..65535");
   P.prec = inst[0].params.precision;
   const int prec = P.prec;
@@ -504,6 +574,7 @@ static int32_t batch_plan(const molt_instance* inst, int count, BatchPlan& P, st
   P.rec_first.resize(count);
   P.nrec = 0;
   P.max_ticks = 0;
+  size_t nmap = 0;
   for (int i = 0; i < count; ++i) {
     const int32_t rc = check_instance(inst[i], prec);
     if (rc != MOLT_OK) return fail(rc, "instance " + std::to_string(i) + ": " + g_err);
@@ -516,7 +587,16 @@ static int32_t batch_plan(const molt_instance* inst, int count, BatchPlan& P, st
     const long long cap = p.fixed_iters > 0 ? p.fixed_iters : p.max_iter;
     const long long ticks = (long long)inst[i].nsteps * (cap + 1);
     if (ticks > P.max_ticks) P.max_ticks = ticks;
+    // map entries of the most fine-grained shapes the table allows
+    const molt_grid& gr = inst[i].grid;
+    const int nseg = ypass_max_segments(gr.ny);
+    const int ycols = (gr.nx + 63) / 64;
+    const int K = xpass_min_k(gr.nx, prec);
+    const int lpb = 256 / xpass_tl(gr.nx, K);
+    nmap += (size_t)ycols * nseg + 2 * (size_t)ycols + (size_t)((gr.ny + lpb - 1) / lpb) +
+            (size_t)diag_blocks((size_t)gr.nx * gr.ny) + 1;
   }
+  if (nmap > 0x7fffffffULL) return fail(MOLT_EUNSUPPORTED, "batch too large");
   P.desc = off;
   off += al256((size_t)count * sizeof(SlotDesc));
   P.ctl = off;
@@ -525,67 +605,9 @@ static int32_t batch_plan(const molt_instance* inst, int count, BatchPlan& P, st
   off += al256(P.nrec * sizeof(molt_step_info));
   P.cnt = off;
   off += 256;
-  // groups: y-passes by (M, boundary kind); x-passes by (K, M, boundary kind)
-  P.yg.clear();
-  P.xg.clear();
-  size_t nm = 0;
-  for (int M = 2; M <= 6; M += 2)
-    for (int per = 1; per >= 0; --per) {
-      BatchGroup g{0, M, per, nm, 0};
-      for (int i = 0; i < count; ++i) {
-        const molt_grid& gr = inst[i].grid;
-        if (gr.order_M != M || (gr.bc == MOLT_BC_PERIODIC) != (per == 1)) continue;
-        int nth, nseg;
-        ypass_shape(prec, gr.ny, &nth, &nseg);
-        const int nb = ((gr.nx + 63) / 64) * nseg;
-        if (maps)
-          for (int b = 0; b < nb; ++b) maps->push_back(BlkMap{i, b});
-        g.nblk += nb;
-      }
-      if (g.nblk > 0) P.yg.push_back(g);
-      nm += g.nblk;
-    }
-  P.comb_off = nm;
-  P.comb_n = 0;
-  for (int i = 0; i < count; ++i) {
-    const int nb = 2 * ((inst[i].grid.nx + 63) / 64);
-    if (maps)
-      for (int b = 0; b < nb; ++b) maps->push_back(BlkMap{i, b});
-    P.comb_n += nb;
-  }
-  nm += P.comb_n;
-  const int ks[4] = {4, 8, 16, 32};
-  for (int kk = 0; kk < 4; ++kk)
-    for (int M = 2; M <= 6; M += 2)
-      for (int per = 1; per >= 0; --per) {
-        BatchGroup g{ks[kk], M, per, nm, 0};
-        for (int i = 0; i < count; ++i) {
-          const molt_grid& gr = inst[i].grid;
-          if (gr.order_M != M || (gr.bc == MOLT_BC_PERIODIC) != (per == 1)) continue;
-          const int K = xpass_pick_k(gr.nx, prec);
-          if (K != ks[kk]) continue;
-          const int lpb = 256 / xpass_tl(gr.nx, K);
-          const int nb = (gr.ny + lpb - 1) / lpb;
-          if (maps)
-            for (int b = 0; b < nb; ++b) maps->push_back(BlkMap{i, b});
-          g.nblk += nb;
-        }
-        if (g.nblk > 0) P.xg.push_back(g);
-        nm += g.nblk;
-      }
-  P.pt_off = nm;
-  P.pt_n = 0;
-  for (int i = 0; i < count; ++i) {
-    const int nb = diag_blocks((size_t)inst[i].grid.nx * inst[i].grid.ny);
-    if (maps)
-      for (int b = 0; b < nb; ++b) maps->push_back(BlkMap{i, b});
-    P.pt_n += nb;
-  }
-  nm += P.pt_n;
-  if (nm > 0x7fffffffULL) return fail(MOLT_EUNSUPPORTED, "batch too large");
-  P.nmap = nm;
   P.map = off;
-  off += al256(nm * sizeof(BlkMap));
+  P.nmap = nmap;
+  off += al256(nmap * sizeof(BlkMap));
   P.total = off;
   return MOLT_OK;
 }
@@ -638,39 +660,51 @@ static void fill_slot(const molt_instance& in, const Layout& L, char* w, molt_st
   d.vecx = ((size_t)g.nx * esz) % 16 == 0 && (uintptr_t)in.d_u % 16 == 0 && (uintptr_t)w % 16 == 0;
   d.xblocks = (g.ny + 256 / d.tlx - 1) / (256 / d.tlx);
   ypass_shape(prec, g.ny, &d.ynth, &d.ynseg);
+  d.yk = ypass_pick_k(g.ny, prec);
   d.ycols = (g.nx + 63) / 64;
   d.dblocks = diag_blocks((size_t)g.nx * g.ny);
 }
 
-static hipError_t batch_tick(const BatchPlan& P, const SlotDesc* sd, SlotCtl* ctl, const BlkMap* map, int count,
+static hipError_t batch_tick(int prec, const BatchMaps& B, const SlotDesc* sd, SlotCtl* ctl, const BlkMap* map,
                              hipStream_t s) {
-  const int prec = P.prec;
   hipError_t e;
   for (int pass = 1; pass <= 3; pass += 2) {
-    for (const BatchGroup& g : P.yg)
-      if ((e = launch_batch_y(prec, g.M, g.per != 0, pass, false, sd, ctl, map + g.off, g.nblk, s)) != hipSuccess)
+    for (const BatchGroup& g : B.yg)
+      if ((e = launch_batch_y(prec, g.K, g.M, g.per != 0, pass, false, sd, ctl, map + g.off, g.nblk, s)) != hipSuccess)
         return e;
-    if ((e = launch_batch_comb(prec, pass, sd, ctl, map + P.comb_off, P.comb_n, s)) != hipSuccess) return e;
-    for (const BatchGroup& g : P.yg)
-      if ((e = launch_batch_y(prec, g.M, g.per != 0, pass, true, sd, ctl, map + g.off, g.nblk, s)) != hipSuccess)
+    if ((e = launch_batch_comb(prec, pass, sd, ctl, map + B.comb_off, B.comb_n, s)) != hipSuccess) return e;
+    for (const BatchGroup& g : B.yg)
+      if ((e = launch_batch_y(prec, g.K, g.M, g.per != 0, pass, true, sd, ctl, map + g.off, g.nblk, s)) != hipSuccess)
         return e;
-    for (const BatchGroup& g : P.xg)
+    for (const BatchGroup& g : B.xg)
       if ((e = launch_batch_x(prec, g.K, g.M, g.per != 0, pass + 1, sd, ctl, map + g.off, g.nblk, s)) != hipSuccess)
         return e;
   }
-  return launch_batch_tail(prec, sd, ctl, count, map + P.pt_off, P.pt_n, s);
+  return launch_batch_tail(prec, sd, ctl, map + B.sl_off, B.sl_n, map + B.pt_off, B.pt_n, s);
+}
+
+// `ticks` ticks and the active-slot count, captured as one executable graph
+static hipError_t capture_round(int prec, const BatchMaps& B, const SlotDesc* sd, SlotCtl* ctl, const BlkMap* map,
+                                int count, int* dcnt, int ticks, hipStream_t s, hipGraphExec_t* exec) {
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed);
+  if (e != hipSuccess) return e;
+  for (int k = 0; k < ticks && e == hipSuccess; ++k) e = batch_tick(prec, B, sd, ctl, map, s);
+  if (e == hipSuccess) e = launch_batch_count(ctl, count, dcnt, s);
+  const hipError_t e2 = hipStreamEndCapture(s, &graph);
+  if (e == hipSuccess) e = e2;
+  if (e == hipSuccess) e = hipGraphInstantiate(exec, graph, nullptr, nullptr, 0);
+  if (graph) (void)hipGraphDestroy(graph);
+  return e;
 }
 
 static int32_t solve_batch_impl(const molt_instance* inst, int count, void* d_work, size_t work_bytes,
                                 molt_step_info* per_step, hipStream_t s) {
   BatchPlan P;
-  std::vector<BlkMap> maps;
-  int32_t rc = batch_plan(inst, count, P, nullptr);
-  if (rc != MOLT_OK) return rc;
-  maps.reserve(P.nmap);
-  rc = batch_plan(inst, count, P, &maps);
+  int32_t rc = batch_plan(inst, count, P);
   if (rc != MOLT_OK) return rc;
   if (!d_work || work_bytes < P.total) return fail(MOLT_EWORKSPACE, "workspace smaller than ch_batch_workspace_bytes()");
+  const int prec = P.prec;
   char* w = (char*)d_work;
   std::vector<SlotDesc> descs(count);
   molt_step_info* drec = (molt_step_info*)(w + P.rec);
@@ -679,51 +713,50 @@ static int32_t solve_batch_impl(const molt_instance* inst, int count, void* d_wo
   SlotCtl* ctl = (SlotCtl*)(w + P.ctl);
   BlkMap* map = (BlkMap*)(w + P.map);
   int* dcnt = (int*)(w + P.cnt);
+  std::vector<int> act;
+  for (int i = 0; i < count; ++i)
+    if (inst[i].nsteps > 0) act.push_back(i);
+  BatchMaps B;
+  batch_maps(inst, act, prec, B);
+  if (B.map.size() > P.nmap) return fail(MOLT_EHIP, "internal: batch maps exceed their area");
   HIPCHK(hipMemcpyAsync(sd, descs.data(), (size_t)count * sizeof(SlotDesc), hipMemcpyHostToDevice, s));
-  HIPCHK(hipMemcpyAsync(map, maps.data(), P.nmap * sizeof(BlkMap), hipMemcpyHostToDevice, s));
+  if (!B.map.empty())
+    HIPCHK(hipMemcpyAsync(map, B.map.data(), B.map.size() * sizeof(BlkMap), hipMemcpyHostToDevice, s));
   HIPCHK(launch_batch_init(sd, ctl, count, s));
 
   const int ticks = g_batch_ticks;
   const bool use_graph = g_batch_graph && s != nullptr && !g_prof_on;
-  hipGraphExec_t exec = nullptr;
-  if (use_graph) {
-    hipGraph_t graph = nullptr;
-    HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
-    hipError_t e = hipSuccess;
-    for (int k = 0; k < ticks && e == hipSuccess; ++k) e = batch_tick(P, sd, ctl, map, count, s);
-    if (e == hipSuccess) e = launch_batch_count(ctl, count, dcnt, s);
-    const hipError_t e2 = hipStreamEndCapture(s, &graph);
-    if (e != hipSuccess || e2 != hipSuccess) {
-      if (graph) (void)hipGraphDestroy(graph);
-      return fail(MOLT_EHIP, std::string("batched tick capture: ") + hipGetErrorString(e != hipSuccess ? e : e2));
-    }
-    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(graph);
-    if (e != hipSuccess) return fail(MOLT_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
-  }
   // two pinned words and events: round r's active count is read while round
   // r+1 runs
   static thread_local int* pin = nullptr;
   if (!pin && hipHostMalloc((void**)&pin, 2 * sizeof(int), hipHostMallocDefault) != hipSuccess) {
     pin = nullptr;
-    if (exec) (void)hipGraphExecDestroy(exec);
     return fail(MOLT_EHIP, "hipHostMalloc of the batch status words failed");
   }
   hipEvent_t ev[2] = {nullptr, nullptr};
-  int32_t status = MOLT_OK;
+  hipGraphExec_t exec = nullptr;
   std::string err;
   for (int b = 0; b < 2 && err.empty(); ++b)
     if (hipEventCreateWithFlags(&ev[b], hipEventDisableTiming) != hipSuccess) err = "hipEventCreate failed";
+  std::vector<SlotCtl> hctl;
   const long long max_rounds = P.max_ticks / ticks + 3;
-  long long rounds = 0;
-  bool finished = false;
+  long long rounds = 0, since = 0;  // rounds in all, rounds since the maps were last built
+  int planned = (int)act.size();
+  bool finished = act.empty();
   while (err.empty() && !finished) {
-    const int b = (int)(rounds & 1);
     hipError_t e = hipSuccess;
+    if (use_graph && !exec) {
+      e = capture_round(prec, B, sd, ctl, map, count, dcnt, ticks, s, &exec);
+      if (e != hipSuccess) {
+        err = std::string("batched tick capture: ") + hipGetErrorString(e);
+        break;
+      }
+    }
+    const int b = (int)(since & 1);
     if (exec) {
       e = hipGraphLaunch(exec, s);
     } else {
-      for (int k = 0; k < ticks && e == hipSuccess; ++k) e = batch_tick(P, sd, ctl, map, count, s);
+      for (int k = 0; k < ticks && e == hipSuccess; ++k) e = batch_tick(prec, B, sd, ctl, map, s);
       if (e == hipSuccess) e = launch_batch_count(ctl, count, dcnt, s);
     }
     if (e == hipSuccess) e = hipMemcpyAsync(&pin[b], dcnt, sizeof(int), hipMemcpyDeviceToHost, s);
@@ -733,16 +766,50 @@ static int32_t solve_batch_impl(const molt_instance* inst, int count, void* d_wo
       break;
     }
     ++rounds;
-    if (rounds >= 2) {
-      e = hipEventSynchronize(ev[1 - b]);
+    ++since;
+    if (rounds > max_rounds) {
+      err = "batched solve exceeded its tick bound";
+      break;
+    }
+    if (since < 2) continue;
+    e = hipEventSynchronize(ev[1 - b]);
+    if (e != hipSuccess) {
+      err = std::string("hipEventSynchronize: ") + hipGetErrorString(e);
+      break;
+    }
+    if (g_prof_on) prof_drain();
+    const int active = pin[1 - b];
+    if (active == 0) {
+      finished = true;
+    } else if (2 * active <= planned) {
+      // half the planned slots are idle: rebuild the maps for the others
+      e = hipStreamSynchronize(s);
+      hctl.resize(count);
+      if (e == hipSuccess) e = hipMemcpy(hctl.data(), ctl, (size_t)count * sizeof(SlotCtl), hipMemcpyDeviceToHost);
       if (e != hipSuccess) {
-        err = std::string("hipEventSynchronize: ") + hipGetErrorString(e);
+        err = std::string("batch re-plan: ") + hipGetErrorString(e);
         break;
       }
-      if (g_prof_on) prof_drain();
-      if (pin[1 - b] == 0) finished = true;
+      act.clear();
+      for (int i = 0; i < count; ++i)
+        if (hctl[i].phase != PH_IDLE) act.push_back(i);
+      if (act.empty()) {
+        finished = true;
+        break;
+      }
+      batch_maps(inst, act, prec, B);
+      e = hipMemcpy(map, B.map.data(), B.map.size() * sizeof(BlkMap), hipMemcpyHostToDevice);
+      if (e != hipSuccess) {
+        err = std::string("batch re-plan: ") + hipGetErrorString(e);
+        break;
+      }
+      planned = (int)act.size();
+      since = 0;
+      if (exec) {
+        (void)hipGraphExecDestroy(exec);
+        exec = nullptr;
+      }
     }
-    if (!finished && rounds > max_rounds) err = "batched solve exceeded its tick bound";
   }
   const hipError_t es = hipStreamSynchronize(s);
   if (err.empty() && es != hipSuccess) err = std::string("hipStreamSynchronize: ") + hipGetErrorString(es);
@@ -751,6 +818,7 @@ static int32_t solve_batch_impl(const molt_instance* inst, int count, void* d_wo
     if (ev[b]) (void)hipEventDestroy(ev[b]);
   if (exec) (void)hipGraphExecDestroy(exec);
   if (!err.empty()) return fail(MOLT_EHIP, err);
+  int32_t status = MOLT_OK;
   std::vector<molt_step_info> rec(P.nrec);
   if (P.nrec > 0) {
     HIPCHK(hipMemcpyAsync(rec.data(), drec, P.nrec * sizeof(molt_step_info), hipMemcpyDeviceToHost, s));
@@ -919,10 +987,112 @@ int32_t ch_solve(const molt_grid* g, const molt_ch_params* p, void* d_u, int64_t
   return status;
 }
 
+int32_t molt_tune_get(int32_t precision, int32_t size_class, int32_t* kx, int32_t* ky) {
+  g_err.clear();
+  if ((precision != MOLT_F64 && precision != MOLT_F32) || size_class < 0 || size_class >= kTuneClasses || !kx || !ky)
+    return fail(MOLT_EINVAL, "bad precision, size class or output pointer");
+  int a, b;
+  tune_get(precision, size_class, &a, &b);
+  *kx = a;
+  *ky = b;
+  return MOLT_OK;
+}
+
+int32_t molt_tune_set(int32_t precision, int32_t size_class, int32_t kx, int32_t ky) {
+  g_err.clear();
+  if (!tune_valid(precision, size_class, kx, ky))
+    return fail(MOLT_EINVAL, "shape not valid for this precision and size class");
+  tune_set(precision, size_class, kx, ky);
+  return MOLT_OK;
+}
+
+static size_t autotune_bytes(int prec, int n) {
+  const size_t esz = prec == MOLT_F64 ? 8 : 4;
+  return 7 * al256((size_t)n * n * esz) + al256(ypass_tot_elems(prec, n, n, 1) * esz) + al256((size_t)2 * n * esz);
+}
+
+size_t molt_autotune_workspace_bytes(int32_t precision, int32_t max_n) {
+  g_err.clear();
+  if ((precision != MOLT_F64 && precision != MOLT_F32) || max_n < 128 || max_n > xpass_max_n(precision)) return 0;
+  return autotune_bytes(precision, max_n);
+}
+
+int32_t molt_autotune(int32_t precision, int32_t max_n, void* d_work, size_t work_bytes, void* stream) {
+  g_err.clear();
+  const size_t need = molt_autotune_workspace_bytes(precision, max_n);
+  if (need == 0) return fail(MOLT_EINVAL, "precision or max_n out of range (128..8192 FP32, ..4096 FP64)");
+  if (!d_work || work_bytes < need) return fail(MOLT_EWORKSPACE, "workspace smaller than molt_autotune_workspace_bytes()");
+  hipStream_t s = (hipStream_t)stream;
+  const bool prof = g_prof_on;
+  g_prof_on = false;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int32_t rc = MOLT_OK;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = fail(MOLT_EHIP, "hipEventCreate");
+  char* w = (char*)d_work;
+  if (rc == MOLT_OK && launch_zero_ints((int*)w, (int)(need / 4), s) != hipSuccess)
+    rc = fail(MOLT_EHIP, "workspace clear failed");
+  const int reps = 4;
+  // average time of `reps` launches of fn (after one warm-up launch), ms
+  auto timed = [&](auto fn) -> float {
+    if (fn() != hipSuccess) return -1.0f;
+    (void)hipEventRecord(e0, s);
+    for (int r = 0; r < reps; ++r)
+      if (fn() != hipSuccess) return -1.0f;
+    (void)hipEventRecord(e1, s);
+    if (hipEventSynchronize(e1) != hipSuccess) return -1.0f;
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return -1.0f;
+    return ms / reps;
+  };
+  const size_t esz = precision == MOLT_F64 ? 8 : 4;
+  for (int cls = 0; rc == MOLT_OK && cls <= tune_class(max_n); ++cls) {
+    const int n = (128 << cls) < max_n ? (128 << cls) : max_n;
+    const size_t fb = al256((size_t)n * n * esz);
+    void* F[7];
+    for (int f = 0; f < 7; ++f) F[f] = w + f * fb;
+    void* tot = w + 7 * fb;
+    void* jln = (char*)tot + al256(ypass_tot_elems(precision, n, n, 1) * esz);
+    const LineCoef lc = make_line(n, MOLT_BC_PERIODIC, 4, 0.3 * n, 1.0 / n);  // nu = 0.3
+    PassArgs a;
+    memset(&a, 0, sizeof(a));
+    a.sigma = 2.0;
+    a.kappa = 0.5;
+    a.mode = 1;
+    int kx0, ky0;
+    tune_get(precision, cls, &kx0, &ky0);
+    int best_ky = ky0, best_kx = kx0;
+    float best = -1.0f;
+    for (int ky = 4; ky <= 16; ky *= 2) {
+      if (!tune_valid(precision, cls, kx0, ky)) continue;
+      tune_set(precision, cls, kx0, ky);
+      a.in[0] = F[0]; a.in[1] = F[1]; a.in[2] = F[2];
+      a.out[0] = F[3]; a.out[1] = F[4];
+      const float ms = timed([&] { return launch_ypass(precision, PROG_P1, lc, a, nullptr, n, 1, tot, jln, nullptr, s); });
+      if (ms < 0) { rc = fail(MOLT_EHIP, "autotune y-pass launch failed"); break; }
+      if (best < 0 || ms < best) { best = ms; best_ky = ky; }
+    }
+    best = -1.0f;
+    for (int kx = 4; rc == MOLT_OK && kx <= 32; kx *= 2) {
+      if (!tune_valid(precision, cls, kx, best_ky)) continue;
+      tune_set(precision, cls, kx, best_ky);
+      a.in[0] = F[0]; a.in[1] = F[1]; a.in[2] = F[2]; a.in[3] = F[3]; a.in[4] = F[4];
+      a.out[0] = F[5]; a.out[1] = F[6];
+      const float ms = timed([&] { return launch_xpass(precision, PROG_P2, lc, a, nullptr, n, nullptr, s); });
+      if (ms < 0) { rc = fail(MOLT_EHIP, "autotune x-pass launch failed"); break; }
+      if (best < 0 || ms < best) { best = ms; best_kx = kx; }
+    }
+    tune_set(precision, cls, rc == MOLT_OK ? best_kx : kx0, rc == MOLT_OK ? best_ky : ky0);
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  g_prof_on = prof;
+  return rc;
+}
+
 size_t ch_batch_workspace_bytes(const molt_instance* inst, int32_t count) {
   g_err.clear();
   BatchPlan P;
-  if (batch_plan(inst, count, P, nullptr) != MOLT_OK) return 0;
+  if (batch_plan(inst, count, P) != MOLT_OK) return 0;
   return P.total;
 }
 

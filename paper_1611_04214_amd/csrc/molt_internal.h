@@ -10,6 +10,7 @@
 namespace molt {
 
 constexpr int kMaxM = 6;
+constexpr int kTuneClasses = 7;  // line length classes n <= 128, 256, ..., 8192 of the shape table
 
 // Coefficients of one line inverse L^{-1} = (I - d^2/alpha^2)^{-1} along one
 // axis (Sec. 3.2), built in FP64 on the host.
@@ -108,6 +109,7 @@ struct SlotDesc {          // constants of one slot, built on the host
   int32_t stepper, init, nsteps, max_iter;
   int32_t fixed, tlx, vecx, xblocks;  // x-pass: threads per row, 16-byte access, blocks
   int32_t ynth, ynseg, ycols, dblocks;  // y-pass: threads per column, segments, 64-column strips
+  int32_t yk, pad_;                     // y-pass nodes per thread
 };
 
 // one block of a batched launch: (slot, block index within the slot)

@@ -295,14 +295,57 @@ static int pick_kx(int n, int prec) {
 
 int xpass_max_n(int prec) { return prec == MOLT_F64 ? 4096 : 8192; }
 
+// --------------------------------------------------------------------------
+// Line-block shapes: nodes per thread along x (kx) and along y (ky) per line
+// length class (n <= 128, 256, ..., 8192) and precision; process-wide, set by
+// molt_tune_set or measured by molt_autotune.  Defaults: the smallest kx that
+// fits a line in one 256-thread block; ky = 16 (FP32) / 8 (FP64).
+// --------------------------------------------------------------------------
+static int g_kx[2][kTuneClasses] = {{4, 4, 4, 4, 8, 16, 16}, {4, 4, 4, 4, 8, 16, 32}};
+static int g_ky[2][kTuneClasses] = {{8, 8, 8, 8, 8, 8, 8}, {16, 16, 16, 16, 16, 16, 16}};
+
+int tune_class(int n) {
+  int c = 0;
+  while (c < kTuneClasses - 1 && n > (128 << c)) ++c;
+  return c;
+}
+
+bool tune_valid(int prec, int cls, int kx, int ky) {
+  if (cls < 0 || cls >= kTuneClasses || (prec != MOLT_F64 && prec != MOLT_F32)) return false;
+  const bool kx_ok = kx == 4 || kx == 8 || kx == 16 || (kx == 32 && prec == MOLT_F32);
+  const bool ky_ok = ky == 4 || ky == 8 || (ky == 16 && prec == MOLT_F32);
+  const int nmax = cls == kTuneClasses - 1 ? xpass_max_n(prec) : (128 << cls);
+  return kx_ok && ky_ok && nmax <= 256 * kx;
+}
+
+void tune_get(int prec, int cls, int* kx, int* ky) {
+  *kx = g_kx[prec == MOLT_F32][cls];
+  *ky = g_ky[prec == MOLT_F32][cls];
+}
+
+void tune_set(int prec, int cls, int kx, int ky) {
+  g_kx[prec == MOLT_F32][cls] = kx;
+  g_ky[prec == MOLT_F32][cls] = ky;
+}
+
 // launch shapes shared with the batched driver
-int xpass_pick_k(int n, int prec) { return pick_kx(n, prec); }
+int xpass_pick_k(int n, int prec) {
+  const int k = g_kx[prec == MOLT_F32][tune_class(n)];
+  return n <= 256 * k ? k : pick_kx(n, prec);
+}
+int ypass_pick_k(int n, int prec) { return g_ky[prec == MOLT_F32][tune_class(n)]; }
+// the largest block counts any shape of the table can give (workspace sizing)
+int ypass_max_segments(int n) {
+  const int nth = (n + 3) / 4;
+  return (nth + kRG - 1) / kRG;
+}
+int xpass_min_k(int n, int prec) { return pick_kx(n, prec); }
 int xpass_tl(int n, int K) {
   const int need = (n + K - 1) / K;
   return need <= 64 ? 64 : (need <= 128 ? 128 : 256);
 }
 void ypass_shape(int prec, int n, int* nth, int* nseg) {
-  const int K = prec == MOLT_F64 ? 8 : 16;
+  const int K = ypass_pick_k(n, prec);
   *nth = (n + K - 1) / K;
   *nseg = (*nth + kRG - 1) / kRG;
 }
@@ -352,7 +395,7 @@ static hipError_t xpass_k(const LineCoef& c, const PassArgs& a, DevState* st, in
 template <typename T, int PI>
 static hipError_t xpass_t(const LineCoef& c, const PassArgs& a, DevState* st, int nlines, double* rpart, hipStream_t s,
                           int prec) {
-  switch (pick_kx(c.n, prec)) {
+  switch (xpass_pick_k(c.n, prec)) {
     case 4: return xpass_k<T, PI, 4>(c, a, st, nlines, rpart, s);
     case 8: return xpass_k<T, PI, 8>(c, a, st, nlines, rpart, s);
     case 16: return xpass_k<T, PI, 16>(c, a, st, nlines, rpart, s);
@@ -383,8 +426,6 @@ hipError_t launch_xpass(int prec, int prog, const LineCoef& c, const PassArgs& a
   return hipErrorInvalidValue;
 }
 
-static int ky_of(int prec) { return prec == MOLT_F64 ? 8 : 16; }
-
 // fused y-pass work items and record elements (FP32 path)
 size_t yfused_items(int n, int nx, int batch) {
   const int nth = (n + kKF - 1) / kKF;
@@ -398,7 +439,8 @@ hipError_t launch_zero_ints(int* p, int n, hipStream_t s) {
 }
 
 size_t ypass_tot_elems(int prec, int n, int nx, int batch) {
-  const int K = ky_of(prec);
+  (void)prec;
+  const int K = 4;  // the smallest ky: room for every shape
   const int nth = (n + K - 1) / K;
   const int nseg = (nth + kRG - 1) / kRG;
   return (size_t)2 * 2 * nseg * nx * batch;  // F <= 2 fields, 2 directions, one entry per segment
@@ -483,10 +525,24 @@ static hipError_t yfused_km(const LineCoef& c, const PassArgs& a, DevState* st, 
   return e;
 }
 
+template <typename T, int PI, int K>
+static hipError_t ypass_k(const LineCoef& c, const PassArgs& a, DevState* st, int nx, int batch, void* tot, void* jln,
+                          hipStream_t s) {
+  const bool per = c.bc == MOLT_BC_PERIODIC;
+  switch (c.M) {
+    case 2: return per ? ypass_km<T, PI, K, 2, true>(c, a, st, nx, batch, (T*)tot, (T*)jln, s)
+                       : ypass_km<T, PI, K, 2, false>(c, a, st, nx, batch, (T*)tot, (T*)jln, s);
+    case 4: return per ? ypass_km<T, PI, K, 4, true>(c, a, st, nx, batch, (T*)tot, (T*)jln, s)
+                       : ypass_km<T, PI, K, 4, false>(c, a, st, nx, batch, (T*)tot, (T*)jln, s);
+    case 6: return per ? ypass_km<T, PI, K, 6, true>(c, a, st, nx, batch, (T*)tot, (T*)jln, s)
+                       : ypass_km<T, PI, K, 6, false>(c, a, st, nx, batch, (T*)tot, (T*)jln, s);
+  }
+  return hipErrorInvalidValue;
+}
+
 template <typename T, int PI>
 static hipError_t ypass_t(const LineCoef& c, const PassArgs& a, DevState* st, int nx, int batch, void* tot, void* jln,
                           const YFused* fz, hipStream_t s) {
-  constexpr int K = sizeof(T) == 8 ? 8 : 16;
   if constexpr (sizeof(T) == 4) {
     if (fz != nullptr && fz->rec != nullptr && c.bc == MOLT_BC_PERIODIC) {
       bool used = false;
@@ -500,14 +556,12 @@ static hipError_t ypass_t(const LineCoef& c, const PassArgs& a, DevState* st, in
       if (used) return hipSuccess;
     }
   }
-  const bool per = c.bc == MOLT_BC_PERIODIC;
-  switch (c.M) {
-    case 2: return per ? ypass_km<T, PI, K, 2, true>(c, a, st, nx, batch, (T*)tot, (T*)jln, s)
-                       : ypass_km<T, PI, K, 2, false>(c, a, st, nx, batch, (T*)tot, (T*)jln, s);
-    case 4: return per ? ypass_km<T, PI, K, 4, true>(c, a, st, nx, batch, (T*)tot, (T*)jln, s)
-                       : ypass_km<T, PI, K, 4, false>(c, a, st, nx, batch, (T*)tot, (T*)jln, s);
-    case 6: return per ? ypass_km<T, PI, K, 6, true>(c, a, st, nx, batch, (T*)tot, (T*)jln, s)
-                       : ypass_km<T, PI, K, 6, false>(c, a, st, nx, batch, (T*)tot, (T*)jln, s);
+  switch (ypass_pick_k(c.n, sizeof(T) == 8 ? MOLT_F64 : MOLT_F32)) {
+    case 4: return ypass_k<T, PI, 4>(c, a, st, nx, batch, tot, jln, s);
+    case 8: return ypass_k<T, PI, 8>(c, a, st, nx, batch, tot, jln, s);
+    case 16:
+      if constexpr (sizeof(T) == 4) return ypass_k<T, PI, 16>(c, a, st, nx, batch, tot, jln, s);
+      return hipErrorInvalidValue;
   }
   return hipErrorInvalidValue;
 }

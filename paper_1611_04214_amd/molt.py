@@ -24,8 +24,10 @@ MOLT_F64, MOLT_F32 = 0, 1
 
 #: every symbol include/molt.h declares
 EXPORTS = ("mol_t_helmholtz_sweep", "molt_sweep_workspace_bytes", "ch_workspace_bytes", "ch_step",
-           "ch_solve", "ch_batch_workspace_bytes", "ch_solve_batch", "molt_strerror", "molt_last_error",
+           "ch_solve", "ch_batch_workspace_bytes", "ch_solve_batch", "molt_tune_get", "molt_tune_set",
+           "molt_autotune_workspace_bytes", "molt_autotune", "molt_strerror", "molt_last_error",
            "molt_profile", "molt_profile_read", "molt_set_option")
+MOLT_TUNE_CLASSES = 7
 MOLT_OPT_FUSED_Y_MIN_ITEMS, MOLT_OPT_BATCH_TICKS, MOLT_OPT_BATCH_GRAPH = 1, 2, 3
 
 KERNEL_FAMILIES = ("xpass", "ytot", "ycomb", "yfin", "pointwise", "other")
@@ -98,6 +100,15 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.ch_batch_workspace_bytes.restype = sz
     lib.ch_solve_batch.argtypes = [I, ctypes.c_int32, vp, sz, ctypes.POINTER(molt_step_info), vp]
     lib.ch_solve_batch.restype = ctypes.c_int32
+    i32, pi32 = ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)
+    lib.molt_tune_get.argtypes = [i32, i32, pi32, pi32]
+    lib.molt_tune_get.restype = i32
+    lib.molt_tune_set.argtypes = [i32, i32, i32, i32]
+    lib.molt_tune_set.restype = i32
+    lib.molt_autotune_workspace_bytes.argtypes = [i32, i32]
+    lib.molt_autotune_workspace_bytes.restype = sz
+    lib.molt_autotune.argtypes = [i32, i32, vp, sz, vp]
+    lib.molt_autotune.restype = i32
     lib.molt_strerror.argtypes = [ctypes.c_int32]
     lib.molt_strerror.restype = ctypes.c_char_p
     lib.molt_last_error.argtypes = []
@@ -159,6 +170,41 @@ def ch_batch_workspace_bytes(inst, count: int) -> int:
 
 def ch_solve_batch(inst, count: int, d_work: int, work_bytes: int, per_step=None, stream: int = 0) -> int:
     return load().ch_solve_batch(inst, count, d_work or None, work_bytes, per_step, stream or None)
+
+
+def molt_tune_get(precision: int, size_class: int):
+    """(kx, ky) of one line-length class."""
+    kx, ky = ctypes.c_int32(), ctypes.c_int32()
+    _check(load().molt_tune_get(precision, size_class, ctypes.byref(kx), ctypes.byref(ky)), "molt_tune_get")
+    return kx.value, ky.value
+
+
+def molt_tune_set(precision: int, size_class: int, kx: int, ky: int) -> int:
+    return load().molt_tune_set(precision, size_class, kx, ky)
+
+
+def molt_autotune_workspace_bytes(precision: int, max_n: int) -> int:
+    return load().molt_autotune_workspace_bytes(precision, max_n)
+
+
+def molt_autotune(precision: int, max_n: int, d_work: int, work_bytes: int, stream: int = 0) -> int:
+    return load().molt_autotune(precision, max_n, d_work or None, work_bytes, stream or None)
+
+
+def tune_table(precision: int):
+    """The whole shape table of one precision: [(kx, ky)] by size class."""
+    return [molt_tune_get(precision, c) for c in range(MOLT_TUNE_CLASSES)]
+
+
+def autotune(precision: int, max_n: int):
+    """molt_autotune with a temporary workspace; returns the new table."""
+    import torch
+    need = molt_autotune_workspace_bytes(precision, max_n)
+    if need == 0:
+        raise MoltError(MOLT_EINVAL, "molt_autotune_workspace_bytes")
+    work = workspace(need)
+    _check(molt_autotune(precision, max_n, work.data_ptr(), work.numel(), _stream(torch)), "molt_autotune")
+    return tune_table(precision)
 
 
 def molt_strerror(status: int) -> str:

@@ -160,3 +160,20 @@ def test_batch_options(lib):
     assert molt.molt_set_option(molt.MOLT_OPT_BATCH_GRAPH, 2) == molt.MOLT_EINVAL
     assert molt.molt_set_option(molt.MOLT_OPT_BATCH_GRAPH, 1) == molt.MOLT_OK
     assert molt.molt_set_option(99, 1) == molt.MOLT_EINVAL
+
+
+def test_tune_table_defaults_and_validation(lib):
+    # defaults: the smallest kx that fits a line in one block; ky 16 (FP32) / 8 (FP64)
+    assert molt.tune_table(molt.MOLT_F32) == [(4, 16), (4, 16), (4, 16), (4, 16), (8, 16), (16, 16), (32, 16)]
+    assert molt.tune_table(molt.MOLT_F64) == [(4, 8), (4, 8), (4, 8), (4, 8), (8, 8), (16, 8), (16, 8)]
+    assert molt.molt_tune_set(molt.MOLT_F32, 4, 4, 16) == molt.MOLT_EINVAL   # 2048 nodes need kx >= 8
+    assert molt.molt_tune_set(molt.MOLT_F64, 0, 32, 8) == molt.MOLT_EINVAL   # kx 32 is FP32 only
+    assert molt.molt_tune_set(molt.MOLT_F64, 0, 4, 16) == molt.MOLT_EINVAL   # ky 16 is FP32 only
+    assert molt.molt_tune_set(molt.MOLT_F32, 7, 4, 4) == molt.MOLT_EINVAL
+    assert molt.molt_tune_set(molt.MOLT_F32, 2, 8, 4) == molt.MOLT_OK
+    assert molt.molt_tune_get(molt.MOLT_F32, 2) == (8, 4)
+    assert molt.molt_tune_set(molt.MOLT_F32, 2, 4, 16) == molt.MOLT_OK
+    assert molt.molt_autotune_workspace_bytes(molt.MOLT_F64, 8192) == 0
+    assert molt.molt_autotune_workspace_bytes(molt.MOLT_F32, 100) == 0
+    assert molt.molt_autotune_workspace_bytes(molt.MOLT_F32, 1024) > 7 * 1024 * 1024 * 4
+    assert molt.molt_autotune(molt.MOLT_F32, 1024, 1, 10) == molt.MOLT_EWORKSPACE
