@@ -22,7 +22,10 @@ Also printed on the same JSON line:
                 launch stream over the timed region, against 8 TB/s;
   cpu_baseline  the FP64 oracle on a bounded sample of the same workload
                 (first BE step of the full field with a fixed number of
-                iterations), on this host's cores.
+                iterations), on this host's cores;
+  batched       the batched workload (256 seeded instances of uneven sizes and
+                parameters, shapes autotuned): ch_solve_batch against one plain
+                ch_solve per instance, steps/s and Gpt-sweeps/s of each.
 """
 from __future__ import annotations
 
@@ -55,6 +58,31 @@ BYTES_PER_POINT = {
 BYTES_PER_POINT_FUSED = {"yfin_P1": (12 + 8, 4 + 8), "yfin_P3": (8 + 8, 8 + 8)}
 
 
+COUNTERS = os.path.join(ROOT, "profiles", "xpass_4096_fp32_hbm_counters.md")
+KERNEL_SOURCES = ("molt_device.h", "molt_kernels.hip", "molt_internal.h")
+
+
+def counter_traffic(kernel: str, n: int):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (calibrated FETCH_SIZE + WRITE_SIZE), or None when the summary is for
+    another kernel or size, or the kernel sources changed since it was taken."""
+    import hashlib
+    if n != 4096 or not os.path.exists(COUNTERS):
+        return None
+    kv = {}
+    for line in open(COUNTERS):
+        if "=" in line and line.startswith("    "):
+            k, v = line.strip().split("=", 1)
+            kv[k.strip()] = v.strip()
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1611_04214_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if kv.get("kernel") != kernel or kv.get("kernel_sources_sha256") != h.hexdigest():
+        return None
+    return float(kv["traffic_bytes_per_launch"])
+
+
 def parse():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -64,7 +92,11 @@ def parse():
     ap.add_argument("--init", choices=["prev", "linear"], default="linear")
     ap.add_argument("--max-iter", type=int, default=50000, help="iteration cap per step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=2, help="oracle iterations in the CPU sample")
+    ap.add_argument("--cpu-iters", type=int, default=24, help="oracle iterations in the CPU sample")
+    ap.add_argument("--batch-steps", type=int, default=10,
+                    help="steps per instance of the batched workload (0: skip it)")
+    ap.add_argument("--batch-count", type=int, default=256, help="instances of the batched workload")
+    ap.add_argument("--no-batch-plain", action="store_true", help="skip the plain-path timing of the batch")
     ap.add_argument("--no-profile", action="store_true", help="do not time kernels with HIP events")
     ap.add_argument("--fused-min-items", type=int, default=None,
                     help="work items from which the single-kernel y-pass is used (library default 256)")
@@ -83,6 +115,70 @@ def copy_calibration(mib: int):
     torch.cuda.synchronize()
     print(json.dumps({"copy_calibration_bytes_read": n * 4, "copy_calibration_bytes_written": n * 4,
                       "launches": 3}))
+
+
+def run_batched(args, molt, synth):
+    """The batched workload: `count` seeded instances (sides 64..1024
+    log-uniform, eps, dt, boundary and stepper drawn per instance, FP32, tol
+    1e-8), line-block shapes autotuned first; ch_solve_batch against one plain
+    ch_solve per instance on the same GPU and the same inputs."""
+    import numpy as np
+    import torch
+    t0 = time.perf_counter()
+    table = molt.autotune(molt.MOLT_F32, 1024)
+    tune_s = time.perf_counter() - t0
+    inst = synth.batch_instances(args.batch_count, steps=args.batch_steps)
+
+    def spec(d):
+        bc = molt.MOLT_BC_PERIODIC if d["bc"] == "periodic" else molt.MOLT_BC_NEUMANN
+        g = molt.make_grid(d["n"], d["n"], 0.0, d["L"], 0.0, d["L"], bc, d["M"])
+        p = molt.make_params(d["eps"], d["dt"], tol=d["tol"], max_iter=20000, init=molt.MOLT_INIT_LINEAR,
+                             stepper=molt.MOLT_BDF2 if d["stepper"] == "BDF2" else molt.MOLT_BE,
+                             precision=molt.MOLT_F32)
+        return g, p
+
+    u0 = [torch.tensor(synth.instance_u0(d), dtype=torch.float32, device="cuda:0") for d in inst]
+    xs = [u.clone() for u in u0]
+    specs = [spec(d) + (xs[i], args.batch_steps) for i, d in enumerate(inst)]
+    work = molt.workspace(molt.ch_batch_workspace_bytes(molt.make_instances(specs), len(specs)))
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s):
+        t0 = time.perf_counter()
+        st, recs = molt.solve_batch(specs, work=work)
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t0
+    iters = [[r.iters for r in rr] for rr in recs]
+    pts = np.array([d["n"] ** 2 for d in inst], dtype=np.float64)
+    sweeps = float(sum(pts[i] * sum(4 + 7 * k for k in iters[i]) for i in range(len(inst))))
+    nsteps = args.batch_steps * len(inst)
+    ticks = [sum(1 + k for k in it) for it in iters]
+    out = {"workload": f"{len(inst)} instances, sides 64..1024 log-uniform (sum n^2 = {int(pts.sum())}), "
+                       f"eps U[0.005,0.05], dt U[1e-6,1e-4], periodic/Neumann, BE/BDF2, FP32 tol 1e-8, "
+                       f"{args.batch_steps} steps each, u0 = 0.05 U(-1,1)",
+           "status": st, "batched_s": round(tb, 3), "batched_steps_per_s": round(nsteps / tb, 1),
+           "batched_gpt_sweeps_per_s": round(sweeps / tb / 1e9, 2),
+           "ticks_max": max(ticks), "ticks_median": int(np.median(ticks)),
+           "mean_iters_per_step": round(float(np.mean([np.mean(x) for x in iters])), 1),
+           "autotune_s": round(tune_s, 3), "shape_table_fp32": table[:4]}
+    if not args.no_batch_plain:
+        xp = [u.clone() for u in u0]
+        ws = molt.workspace(max(molt.ch_workspace_bytes(*spec(d)) for d in inst))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        iters_p = []
+        for i, d in enumerate(inst):
+            g, p = spec(d)
+            _, infos = molt.solve(xp[i], g, p, args.batch_steps, work=ws)
+            iters_p.append([r.iters for r in infos])
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - t0
+        out.update({"plain_s": round(tp, 3), "plain_steps_per_s": round(nsteps / tp, 1),
+                    "speedup_vs_plain": round(tp / tb, 2),
+                    "bitwise_equal_to_plain": all(torch.equal(xp[i], xs[i]) for i in range(len(inst))),
+                    "same_iterations_as_plain": iters_p == iters})
+    print(f"batched: {json.dumps(out)}", file=sys.stderr, flush=True)
+    return out
 
 
 def main():
@@ -178,11 +274,13 @@ def main():
             avg_s = ms / 1e3 / real
             achieved = per_launch / avg_s / 1e9
             roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": counter_traffic(dom, n),
                     "kernel": dom + (" (single-kernel y-pass)" if fused and dom.startswith("yfin") else ""),
                     "bytes_per_launch": per_launch, "avg_launch_us": round(avg_s * 1e6, 2)}
             total_ms = sum(v[1] for v in prof.values())
             roof["kernel_share_of_gpu_time"] = round(ms / total_ms, 3) if total_ms > 0 else None
+
+    batched = run_batched(args, molt, synth) if args.batch_steps > 0 else None
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -223,6 +321,7 @@ def main():
         "gpt_sweeps_nominal_8_per_iter": round(nominal / elapsed / 1e9, 3),
         "roofline": roof,
         "cpu_baseline": cpu,
+        "batched": batched,
         "kernels": kernels,
     }
     print(json.dumps(out), flush=True)
