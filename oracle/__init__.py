@@ -54,7 +54,8 @@ class _Params(ctypes.Structure):
 class _Info(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("residual", ctypes.c_double),
                 ("mass", ctypes.c_double), ("energy", ctypes.c_double),
-                ("s1", ctypes.c_double), ("s2", ctypes.c_double), ("sigma", ctypes.c_double)]
+                ("s1", ctypes.c_double), ("s2", ctypes.c_double), ("sigma", ctypes.c_double),
+                ("mass2", ctypes.c_double)]
 
 
 _lib = None
@@ -81,6 +82,15 @@ def _load():
         lib.oracle_energy.restype = ctypes.c_double
         lib.oracle_stepper_params.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int,
                                               ctypes.c_int, ctypes.c_double, dp]
+        lib.oracle_vch_W.argtypes = [ctypes.c_double, ctypes.c_double]
+        lib.oracle_vch_W.restype = ctypes.c_double
+        lib.oracle_vch_gradW.argtypes = [ctypes.c_double, ctypes.c_double, dp]
+        lib.oracle_vch_energy.argtypes = [ctypes.POINTER(_Grid), ctypes.c_double, dp]
+        lib.oracle_vch_energy.restype = ctypes.c_double
+        lib.oracle_vch_step.argtypes = [ctypes.POINTER(_Grid), ctypes.POINTER(_Params), dp, dp,
+                                        ctypes.POINTER(_Info)]
+        lib.oracle_vch_solve.argtypes = [ctypes.POINTER(_Grid), ctypes.POINTER(_Params), dp,
+                                         ctypes.c_int, ctypes.POINTER(_Info)]
         _lib = lib
     return _lib
 
@@ -147,10 +157,11 @@ class Info:
     s1: float
     s2: float
     sigma: float
+    mass2: float = 0.0
 
 
 def _info(i: _Info) -> Info:
-    return Info(i.iters, i.residual, i.mass, i.energy, i.s1, i.s2, i.sigma)
+    return Info(i.iters, i.residual, i.mass, i.energy, i.s1, i.s2, i.sigma, i.mass2)
 
 
 def pqr(nu: float):
@@ -228,3 +239,49 @@ def stepper_params(eps: float, dt: float, stepper: int, first: bool, sigma0: flo
     out = np.zeros(3)
     lib.oracle_stepper_params(eps, dt, stepper, 1 if first else 0, sigma0, _dp(out))
     return float(out[0]), float(out[1]), float(out[2])
+
+
+# ------------------------------------------------------------- vector model --
+#: sigma0 of the vector model: the Hessian of W at its minima is 18 I (Sec. 5.2)
+VCH_SIGMA0 = 18.0
+
+
+def vch_W(u1: float, u2: float) -> float:
+    """W(u) = prod |u - z_i|^2 (eq. CH_vector_reaction)."""
+    return _load().oracle_vch_W(u1, u2)
+
+
+def vch_gradW(u1: float, u2: float) -> np.ndarray:
+    g = np.zeros(2)
+    _load().oracle_vch_gradW(u1, u2, _dp(g))
+    return g
+
+
+def vch_energy(grid: Grid, eps: float, u: np.ndarray) -> float:
+    """Energy of eq. EnergyFunctional_vector; u is (2, ny, nx) or component-major flat."""
+    uu = np.ascontiguousarray(u, dtype=np.float64)
+    return _load().oracle_vch_energy(ctypes.byref(grid.c()), eps, _dp(uu))
+
+
+def vch_step(grid: Grid, params: Params, u: np.ndarray, u_prev: np.ndarray | None = None):
+    """One vector-model step; u (2, ny, nx).  Returns (u_next, Info)."""
+    lib = _load()
+    uu = np.ascontiguousarray(u, dtype=np.float64).copy()
+    up = None if u_prev is None else np.ascontiguousarray(u_prev, dtype=np.float64)
+    info = _Info()
+    rc = lib.oracle_vch_step(ctypes.byref(grid.c()), ctypes.byref(params.c()), _dp(uu),
+                             None if up is None else _dp(up), ctypes.byref(info))
+    if rc < 0:
+        raise ValueError("oracle_vch_step failed (%d)" % rc)
+    return uu, _info(info)
+
+
+def vch_solve(grid: Grid, params: Params, u: np.ndarray, nsteps: int):
+    """nsteps vector-model steps (BDF2: BE first step).  Returns (u_final, [Info])."""
+    lib = _load()
+    uu = np.ascontiguousarray(u, dtype=np.float64).copy()
+    infos = (_Info * max(nsteps, 1))()
+    rc = lib.oracle_vch_solve(ctypes.byref(grid.c()), ctypes.byref(params.c()), _dp(uu), nsteps, infos)
+    if rc < 0:
+        raise ValueError("oracle_vch_solve failed (%d)" % rc)
+    return uu, [_info(infos[i]) for i in range(nsteps)]

@@ -50,15 +50,18 @@ typedef struct {
   int max_iter;
   int init;            /* OR_INIT_PREV (v^{n+1,0} = v^n) or OR_INIT_LINEAR (v^{n+1,0} = R) */
   int fixed_iters;     /* >0: run exactly this many iterations (parity mode) */
-  int reaction;        /* 0: Cahn-Hilliard f(v) = v^3 - 3v^2 + 2v; 1: linear f(v) = react_k*v (test hook) */
+  int reaction;        /* 0: Cahn-Hilliard f(v) = v^3 - 3v^2 + 2v; 1: linear f(v) = react_k*v (test hook);
+                          2: the vector model's reaction on the real axis, f(v) = 6((v-1)^5 - (v-1)^2)
+                          (test hook) */
   double react_k;
 } or_params;
 
 typedef struct {
   int iters;
   double residual;     /* last max-norm increment */
-  double mass, energy; /* of u^{n+1} */
+  double mass, energy; /* of u^{n+1} (vector model: mass of the first component) */
   double s1, s2, sigma;
+  double mass2;        /* vector model: mass of the second component */
 } or_info;
 
 /* ------------------------------------------------------------------------ */
@@ -505,8 +508,18 @@ int oracle_step(const or_grid *g, const or_params *p, double *u, const double *u
   double res = 0.0;
   for (;;) {
     /* g(v^k) = f(v^k) - sigma v^k */
-    for (size_t i = 0; i < n; i++)
-      gk[i] = (p->reaction == 1 ? p->react_k * v[i] : f_react(v[i])) - sigma * v[i];
+    for (size_t i = 0; i < n; i++) {
+      double f;
+      if (p->reaction == 1) {
+        f = p->react_k * v[i];
+      } else if (p->reaction == 2) {
+        const double x = v[i] - 1.0;
+        f = 6.0 * (x * x * x * x * x - x * x);
+      } else {
+        f = f_react(v[i]);
+      }
+      gk[i] = f - sigma * v[i];
+    }
     /* C1 g = A1^{-1} g - g + D1 g */
     Ainv(g, al1, gk, c1, t1);
     Dop(g, al1, gk, t2, t1, n);
@@ -540,6 +553,7 @@ int oracle_step(const or_grid *g, const or_params *p, double *u, const double *u
     info->s1 = s1;
     info->s2 = s2;
     info->sigma = sigma;
+    info->mass2 = 0.0;
   }
   free(vn); free(rhs); free(R); free(v); free(gk); free(c1);
   free(t1); free(t2); free(dv); free(q); free(vnew);
@@ -561,6 +575,183 @@ int oracle_solve(const or_grid *g, const or_params *p, double *u, int nsteps, or
     if (rc < 0) { status = rc; break; }
     if (rc > 0) status = 1;
     memcpy(prev, cur, sizeof(double) * n);
+  }
+  free(prev);
+  free(cur);
+  return status;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Vector Cahn-Hilliard (Sec. 2 eqs. CH_vector, CH_vector_reaction; Sec. 5.2 */
+/* eqs. CH_vector_linearize, CH_vector_BE, CH_vector_fixed1/2).              */
+/* u = (u1, u2); W(u) = prod_{i=1..3} |u - z_i|^2 with z_i the cube roots of */
+/* unity in the (u1,u2) plane.  The scheme shifts by z_3 = (-1/2,-sqrt3/2): */
+/* v = u - z_3, and applies the scalar machinery to each component with the  */
+/* reaction g_c(v) = dW/du_c(v + z_3) - sigma v_c and sigma0 = 18 (the       */
+/* Hessian of W at its minima, eq. Jacobian); the two factorizations of      */
+/* eqs. CH_vector_fixed1/2 are the unified stepper with sigma0 = 18.         */
+/* A vector field is stored component-major: u[0..n) = u1, u[n..2n) = u2.    */
+/* ------------------------------------------------------------------------ */
+static const double OR_Z[3][2] = {{1.0, 0.0},
+                                  {-0.5, 0.86602540378443864676372317075294},
+                                  {-0.5, -0.86602540378443864676372317075294}};
+
+/* W from its definition: the product of the three squared distances. */
+double oracle_vch_W(double u1, double u2) {
+  double w = 1.0;
+  for (int i = 0; i < 3; i++) {
+    const double a = u1 - OR_Z[i][0], b = u2 - OR_Z[i][1];
+    w *= a * a + b * b;
+  }
+  return w;
+}
+
+/* grad W by the product rule: dW/du_c = sum_i 2 (u_c - z_{i,c}) prod_{j != i} d_j. */
+void oracle_vch_gradW(double u1, double u2, double *g) {
+  double d[3];
+  for (int i = 0; i < 3; i++) {
+    const double a = u1 - OR_Z[i][0], b = u2 - OR_Z[i][1];
+    d[i] = a * a + b * b;
+  }
+  g[0] = g[1] = 0.0;
+  for (int i = 0; i < 3; i++) {
+    const double others = d[(i + 1) % 3] * d[(i + 2) % 3];
+    g[0] += 2.0 * (u1 - OR_Z[i][0]) * others;
+    g[1] += 2.0 * (u2 - OR_Z[i][1]) * others;
+  }
+}
+
+/* Energy of eq. EnergyFunctional_vector with the discretization of
+ * oracle_energy (forward differences, trapezoid weights off the periodic case). */
+double oracle_vch_energy(const or_grid *g, double eps, const double *u) {
+  const int nx = g->nx, ny = g->ny;
+  const size_t n = (size_t)nx * ny;
+  const int per = g->bc == OR_BC_PERIODIC;
+  double hx = spacing(g->bc, nx, g->x0, g->x1);
+  double hy = ny > 1 ? spacing(g->bc, ny, g->y0, g->y1) : 1.0;
+  double e = 0.0;
+  for (int iy = 0; iy < ny; iy++) {
+    double wy = ny > 1 ? tw(g->bc, iy, ny) : 1.0;
+    for (int ix = 0; ix < nx; ix++) {
+      double wx = tw(g->bc, ix, nx);
+      const size_t i = (size_t)iy * nx + ix;
+      e += wx * wy * oracle_vch_W(u[i], u[n + i]) * hx * hy;
+      for (int c = 0; c < 2; c++) {
+        const double *uc = u + c * n;
+        if (per || ix < nx - 1) {
+          double gx = (uc[(size_t)iy * nx + (ix + 1) % nx] - uc[i]) / hx;
+          e += 0.5 * eps * eps * gx * gx * wy * hx * hy;
+        }
+        if (ny > 1 && (per || iy < ny - 1)) {
+          double gy = (uc[(size_t)((iy + 1) % ny) * nx + ix] - uc[i]) / hy;
+          e += 0.5 * eps * eps * gy * gy * wx * hx * hy;
+        }
+      }
+    }
+  }
+  return e;
+}
+
+/* One time step of the vector model: for each component the iteration of
+ * oracle_step (same operators, same readings), coupled through g. */
+int oracle_vch_step(const or_grid *g, const or_params *p, double *u, const double *u_prev, or_info *info) {
+  if (!grid_ok(g) || !p || !u) return -1;
+  if (!(p->eps > 0) || !(p->dt > 0) || !(p->sigma0 > 0)) return -1;
+  const size_t n = (size_t)g->nx * g->ny;
+  const int bdf2 = (p->stepper == OR_BDF2) && u_prev != NULL;
+  const double a = (bdf2 ? 2.0 / 3.0 : 1.0) * p->dt;
+  double s1, s2, sigma;
+  stepper_params(p->eps, a, p->sigma0, &s1, &s2, &sigma);
+  const double al1 = 1.0 / sqrt(s1), al2 = 1.0 / sqrt(s2);
+  const double kappa = a / s1;
+  const size_t n2 = 2 * n;
+  double *vn = (double *)malloc(sizeof(double) * n2);
+  double *R = (double *)malloc(sizeof(double) * n2);
+  double *v = (double *)malloc(sizeof(double) * n2);
+  double *gk = (double *)malloc(sizeof(double) * n2);
+  double *vnew = (double *)malloc(sizeof(double) * n2);
+  double *rhs = (double *)malloc(sizeof(double) * n);
+  double *c1 = (double *)malloc(sizeof(double) * n);
+  double *t1 = (double *)malloc(sizeof(double) * n);
+  double *t2 = (double *)malloc(sizeof(double) * n);
+  double *dv = (double *)malloc(sizeof(double) * n);
+  double *q = (double *)malloc(sizeof(double) * n);
+  if (!vn || !R || !v || !gk || !vnew || !rhs || !c1 || !t1 || !t2 || !dv || !q) return -2;
+
+  for (int c = 0; c < 2; c++)
+    for (size_t i = 0; i < n; i++) vn[c * n + i] = u[c * n + i] - OR_Z[2][c];
+  for (int c = 0; c < 2; c++) {
+    for (size_t i = 0; i < n; i++)
+      rhs[i] = bdf2 ? (4.0 * vn[c * n + i] - (u_prev[c * n + i] - OR_Z[2][c])) / 3.0 : vn[c * n + i];
+    Ainv(g, al2, rhs, t2, t1);
+    Ainv(g, al1, t2, R + c * n, t1);
+  }
+  memcpy(v, p->init == OR_INIT_LINEAR ? R : vn, sizeof(double) * n2);
+
+  int k = 0;
+  double res = 0.0;
+  for (;;) {
+    for (size_t i = 0; i < n; i++) {
+      double gw[2];
+      oracle_vch_gradW(v[i] + OR_Z[2][0], v[n + i] + OR_Z[2][1], gw);
+      gk[i] = gw[0] - sigma * v[i];
+      gk[n + i] = gw[1] - sigma * v[n + i];
+    }
+    res = 0.0;
+    for (int c = 0; c < 2; c++) {
+      const double *gc = gk + c * n, *vc = v + c * n, *Rc = R + c * n;
+      Ainv(g, al1, gc, c1, t1);
+      Dop(g, al1, gc, t2, t1, n);
+      for (size_t i = 0; i < n; i++) c1[i] = c1[i] - gc[i] + t2[i];
+      Ainv(g, al2, c1, t2, t1);
+      Dop(g, al1, vc, dv, t1, n);
+      for (size_t i = 0; i < n; i++) q[i] = vc[i] - dv[i];
+      Dop(g, al2, q, c1, t1, n);
+      for (size_t i = 0; i < n; i++) {
+        const double x = Rc[i] + kappa * t2[i] + dv[i] + c1[i];
+        const double e = fabs(x - vc[i]);
+        if (e > res) res = e;
+        vnew[c * n + i] = x;
+      }
+    }
+    memcpy(v, vnew, sizeof(double) * n2);
+    k++;
+    if (p->fixed_iters > 0) {
+      if (k >= p->fixed_iters) break;
+    } else if (res < p->tol || k >= p->max_iter) {
+      break;
+    }
+  }
+  for (int c = 0; c < 2; c++)
+    for (size_t i = 0; i < n; i++) u[c * n + i] = v[c * n + i] + OR_Z[2][c];
+  if (info) {
+    info->iters = k;
+    info->residual = res;
+    info->mass = oracle_mass(g, u);
+    info->mass2 = oracle_mass(g, u + n);
+    info->energy = oracle_vch_energy(g, p->eps, u);
+    info->s1 = s1;
+    info->s2 = s2;
+    info->sigma = sigma;
+  }
+  free(vn); free(R); free(v); free(gk); free(vnew); free(rhs);
+  free(c1); free(t1); free(t2); free(dv); free(q);
+  return (p->fixed_iters <= 0 && res >= p->tol) ? 1 : 0;
+}
+
+/* nsteps steps of the vector model (BDF2: BE first step, as oracle_solve). */
+int oracle_vch_solve(const or_grid *g, const or_params *p, double *u, int nsteps, or_info *infos) {
+  if (!grid_ok(g) || !p || !u || nsteps < 0) return -1;
+  const size_t n2 = 2 * (size_t)g->nx * g->ny;
+  double *prev = (double *)malloc(sizeof(double) * n2);
+  double *cur = (double *)malloc(sizeof(double) * n2);
+  int status = 0;
+  for (int s = 0; s < nsteps; s++) {
+    memcpy(cur, u, sizeof(double) * n2);
+    int rc = oracle_vch_step(g, p, u, s == 0 ? NULL : prev, infos ? &infos[s] : NULL);
+    if (rc < 0) { status = rc; break; }
+    if (rc > 0) status = 1;
+    memcpy(prev, cur, sizeof(double) * n2);
   }
   free(prev);
   free(cur);

@@ -127,3 +127,19 @@ def instance_u0(inst: dict) -> np.ndarray:
     """0.05 U(-1,1) i.i.d. per node on the instance's own stream (n x n)."""
     n = inst["n"]
     return (0.05 * (2.0 * uniform(inst["seed"], n * n, inst["stream"]) - 1.0)).reshape(n, n)
+
+
+# Vector (three-phase) model: fractions c_i >= 0, sum 1, mapped to
+# u = sum_i c_i z_i with z_i the cube roots of unity in the (u1, u2) plane.
+VCH_Z = np.array([[1.0, 0.0], [-0.5, np.sqrt(3.0) / 2.0], [-0.5, -np.sqrt(3.0) / 2.0]])
+
+
+def u0_vch(seed: int, ny: int, nx: int, stream: int = 0) -> np.ndarray:
+    """Fractions c = 0.9 (1/3, 1/3, 1/3) + 0.1 Dirichlet(1,1,1) per node (the
+    Dirichlet draw as normalized exponentials of three uniform streams); returns
+    u as (2, ny, nx), component-major."""
+    n = ny * nx
+    e = np.stack([-np.log(np.maximum(uniform(seed, n, 3 * stream + k), 2.0 ** -53)) for k in range(3)])
+    c = 0.9 / 3.0 + 0.1 * e / e.sum(axis=0)
+    u = VCH_Z.T @ c
+    return u.reshape(2, ny, nx)
