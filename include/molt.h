@@ -54,6 +54,11 @@ extern "C" {
 #define MOLT_BE 0
 #define MOLT_BDF2 1
 
+/* models: the Cahn-Hilliard equation (eq. CahnHilliard) or the vector model of
+ * three phases (eqs. CH_vector, CH_vector_reaction; Sec. 5.2) */
+#define MOLT_MODEL_CH 0
+#define MOLT_MODEL_VCH 1
+
 /* initial iterate of the fixed point: previous step, or R = A1^{-1} A2^{-1} rhs */
 #define MOLT_INIT_PREV 0
 #define MOLT_INIT_LINEAR 1
@@ -89,6 +94,11 @@ typedef struct {
  *  fixed_iters  > 0: run exactly this many iterations (parity mode)
  *  have_prev    ch_step only: 1 if d_u_prev holds u^{n-1} (a BDF2 step), 0 for
  *               the start-up step (taken as BE)
+ *  model        MOLT_MODEL_CH, or MOLT_MODEL_VCH: u = (u1, u2) with
+ *               W(u) = prod_i |u - z_i|^2 over the cube roots of unity z_i; the
+ *               scheme shifts by z_3 and the paper's sigma0 is 18 (Sec. 5.2).
+ *               Every field of a VCH problem holds two components,
+ *               component-major: u1 at [0, nx*ny), u2 at [nx*ny, 2*nx*ny).
  */
 typedef struct {
   double eps, dt, tol;
@@ -99,18 +109,22 @@ typedef struct {
   int32_t precision;
   int32_t fixed_iters;
   int32_t have_prev;
+  int32_t model;
+  int32_t reserved;  /* 0 */
 } molt_ch_params;
 
 /* Per-step report.  residual: last max-norm increment (FP64); mass and energy
  * of u^{n+1} (FP64 reductions; periodic: h-weighted sum / forward-difference
- * energy, non-periodic: trapezoid weights); s1 >= s2: the factors of
- * (I - s1 Lap)(I - s2 Lap); sigma: the linear part moved to the left side. */
+ * energy, non-periodic: trapezoid weights; VCH: the energy of
+ * eq. EnergyFunctional_vector, mass of u1, mass2 of u2); s1 >= s2: the factors
+ * of (I - s1 Lap)(I - s2 Lap); sigma: the linear part moved to the left side. */
 typedef struct {
   int32_t iters;
   int32_t converged;
   double residual;
   double mass, energy;
   double s1, s2, sigma;
+  double mass2;
 } molt_step_info;
 
 /*

@@ -16,7 +16,11 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmolt.so")
 ARCH = os.environ.get("MOLT_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["molt_kernels.hip", "molt_batch.hip", "molt_host.cpp"]
+# (source, extra defines): the kernel files compile once per precision (and
+# the single-problem kernels once per pass direction), in parallel
+SOURCES = [("molt_kernels.hip", ("MOLT_PART_X",)), ("molt_kernels.hip", ("MOLT_PART_Y",)),
+           ("molt_kernels.hip", ("MOLT_PART_X", "MOLT_PREC_F64")), ("molt_kernels.hip", ("MOLT_PART_Y", "MOLT_PREC_F64")),
+           ("molt_batch.hip", ()), ("molt_batch.hip", ("MOLT_BATCH_F64",)), ("molt_host.cpp", ())]
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(ROOT, "include"), "-I", CSRC]
@@ -25,9 +29,9 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
 def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
     objs, procs = [], []
     tag = f".{os.getpid()}.o"
-    for src in SOURCES:  # the translation units compile in parallel
-        obj = os.path.join(CSRC, src + tag)
-        cmd = ["hipcc", "-c"] + FLAGS + [f"-D{d}" for d in defines] + \
+    for k, (src, extra) in enumerate(SOURCES):  # the translation units compile in parallel
+        obj = os.path.join(CSRC, f"{src}.{k}{tag}")
+        cmd = ["hipcc", "-c"] + FLAGS + [f"-D{d}" for d in tuple(defines) + tuple(extra)] + \
               (["-x", "hip"] if src.endswith(".hip") else []) + [os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)

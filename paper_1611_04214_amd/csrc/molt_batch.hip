@@ -12,7 +12,18 @@
 // Every block finds its (slot, block) in a static map and runs exactly the
 // device body of the single-problem kernels with that slot's coefficients,
 // so a slot's arithmetic does not depend on the other slots of the batch.
+//
+// The file is compiled once per precision (MOLT_BATCH_F64 selects double); the
+// launchers carry the precision in their names and the host dispatches.
 #include "molt_device.h"
+
+#ifdef MOLT_BATCH_F64
+#define MOLT_BT double
+#define MOLT_BFN(name) name##_f64
+#else
+#define MOLT_BT float
+#define MOLT_BFN(name) name##_f32
+#endif
 
 namespace molt {
 
@@ -50,18 +61,25 @@ __device__ __forceinline__ PassArgs slot_args(const SlotDesc& d, int ph, int pas
     a.mode = mode;
     a.bdf2 = 0;
     const void* base = d.init == MOLT_INIT_LINEAR ? F[F_R] : d.u;
-    if (pass == 1) {
+    const bool vch = d.model == MOLT_MODEL_VCH;
+    if (pass == 0) {  // vector model: the pointwise reaction pass
       a.in[0] = base;
       a.in[1] = F[F_W];
       a.in[2] = F[F_DL];
+      a.out[0] = F[F_E];
+      a.out[1] = F[F_LIN];
+    } else if (pass == 1) {
+      a.in[0] = vch ? F[F_E] : base;
+      a.in[1] = vch ? F[F_LIN] : F[F_W];
+      a.in[2] = vch ? nullptr : F[F_DL];
       a.out[0] = F[F_A1];
       a.out[1] = F[F_B1];
     } else if (pass == 2) {
       a.in[0] = F[F_A1];
       a.in[1] = F[F_B1];
-      a.in[2] = base;
-      a.in[3] = F[F_W];
-      a.in[4] = F[F_DL];
+      a.in[2] = vch ? F[F_E] : base;
+      a.in[3] = vch ? F[F_LIN] : F[F_W];
+      a.in[4] = vch ? nullptr : F[F_DL];
       a.out[0] = F[F_C];
       a.out[1] = F[F_Q];
     } else if (pass == 3) {
@@ -90,7 +108,9 @@ __global__ void MOLT_PASS_ATTR ypass_batch_kernel(const SlotDesc* __restrict__ s
   const SlotDesc& d = sd[e.slot];
   const SlotCtl cc = ctl[e.slot];
   if (cc.phase == PH_IDLE) return;
-  const int bx = e.blk % d.ycols, by = e.blk / d.ycols;
+  // block = (strip bx, segment by, component bz)
+  const int bx = e.blk % d.ycols, rest = e.blk / d.ycols;
+  const int by = rest % d.ynseg, bz = rest / d.ynseg;
   const size_t fstride = (size_t)d.ny * (size_t)d.nx;
   const int var = cc.var;
   if (cc.phase == PH_R) {
@@ -98,19 +118,29 @@ __global__ void MOLT_PASS_ATTR ypass_batch_kernel(const SlotDesc* __restrict__ s
     const PassArgs a = slot_args(d, PH_R, PASS, var, 0);
     const LineCoef& c = d.cy[var][PASS == 1 ? 1 : 0];
     if constexpr (FIN)
-      yfin_body<T, PR, K, M, PER>(c, a, nullptr, d.nx, d.ynth, d.ynseg, fstride, (const T*)d.tot, bx, by, 0);
+      yfin_body<T, PR, K, M, PER>(c, a, nullptr, d.nx, d.ynth, d.ynseg, fstride, (const T*)d.tot, bx, by, bz);
     else
-      ytot_body<T, PR, K, M, PER>(c, a, nullptr, d.nx, d.ynth, d.ynseg, fstride, (T*)d.tot, (T*)d.jln, bx, by, 0);
+      ytot_body<T, PR, K, M, PER>(c, a, nullptr, d.nx, d.ynth, d.ynseg, fstride, (T*)d.tot, (T*)d.jln, bx, by, bz);
   } else {
     DevState* st = d.st;
     if (st->done) return;
-    constexpr int PI = PASS == 1 ? PROG_P1 : PROG_P3;
     const PassArgs a = slot_args(d, PH_IT, PASS, var, st->iters > 0 ? 1 : 0);
     const LineCoef& c = d.cy[var][PASS == 1 ? 0 : 1];
+    if constexpr (PASS == 1) {
+      if (d.model == MOLT_MODEL_VCH) {
+        if constexpr (FIN)
+          yfin_body<T, PROG_P1V, K, M, PER>(c, a, st, d.nx, d.ynth, d.ynseg, fstride, (const T*)d.tot, bx, by, bz);
+        else
+          ytot_body<T, PROG_P1V, K, M, PER>(c, a, st, d.nx, d.ynth, d.ynseg, fstride, (T*)d.tot, (T*)d.jln, bx, by,
+                                            bz);
+        return;
+      }
+    }
+    constexpr int PI = PASS == 1 ? PROG_P1 : PROG_P3;
     if constexpr (FIN)
-      yfin_body<T, PI, K, M, PER>(c, a, st, d.nx, d.ynth, d.ynseg, fstride, (const T*)d.tot, bx, by, 0);
+      yfin_body<T, PI, K, M, PER>(c, a, st, d.nx, d.ynth, d.ynseg, fstride, (const T*)d.tot, bx, by, bz);
     else
-      ytot_body<T, PI, K, M, PER>(c, a, st, d.nx, d.ynth, d.ynseg, fstride, (T*)d.tot, (T*)d.jln, bx, by, 0);
+      ytot_body<T, PI, K, M, PER>(c, a, st, d.nx, d.ynth, d.ynseg, fstride, (T*)d.tot, (T*)d.jln, bx, by, bz);
   }
 }
 
@@ -125,41 +155,52 @@ __global__ void __launch_bounds__(1024) ycomb_batch_kernel(const SlotDesc* __res
   if (cc.phase == PH_IDLE) return;
   const bool r = cc.phase == PH_R;
   const int F = r ? 1 : 2;
-  const int bx = e.blk % d.ycols, f = e.blk / d.ycols;
+  // block = (strip bx, field f, component b)
+  const int bx = e.blk % d.ycols, rest = e.blk / d.ycols;
+  const int f = rest % 2, b = rest / 2;
   if (f >= F) return;
   // pass 1: alpha2 in the R phase, alpha1 in an iteration; pass 3 the other way
   const LineCoef& c = d.cy[cc.var][((pass == 1) == r) ? 1 : 0];
   const int ct = (d.ynseg + kCombWaves - 1) / kCombWaves;
   if (ct <= 8)
-    ycomb_body<T, 8>(c, r ? nullptr : d.st, d.nx, d.ynseg, kRG * d.yk, F, (T*)d.tot, (const T*)d.jln, bx, f, 0);
+    ycomb_body<T, 8>(c, r ? nullptr : d.st, d.nx, d.ynseg, kRG * d.yk, F, (T*)d.tot, (const T*)d.jln, bx, f, b);
   else
-    ycomb_body<T, 32>(c, r ? nullptr : d.st, d.nx, d.ynseg, kRG * d.yk, F, (T*)d.tot, (const T*)d.jln, bx, f, 0);
+    ycomb_body<T, 32>(c, r ? nullptr : d.st, d.nx, d.ynseg, kRG * d.yk, F, (T*)d.tot, (const T*)d.jln, bx, f, b);
 }
 
 // x-pass `PASS` (2 or 4)
 template <typename T, int K, int M, bool PER, int PASS>
 __global__ void MOLT_PASS_ATTR xpass_batch_kernel(const SlotDesc* __restrict__ sd, const SlotCtl* __restrict__ ctl,
                                                   const BlkMap* __restrict__ map) {
+  __shared__ T smem[XRow<T, K>::ELEMS];  // shared by the pass bodies below
   const BlkMap e = map[blockIdx.x];
   const SlotDesc& d = sd[e.slot];
   const SlotCtl cc = ctl[e.slot];
   if (cc.phase == PH_IDLE) return;
   const int var = cc.var;
+  const int nlines = d.ny * d.ncomp;  // the components' rows, stacked
   if (cc.phase == PH_R) {
     const PassArgs a = slot_args(d, PH_R, PASS, var, 0);
-    xpass_body<T, PROG_SWEEP, K, M, PER>(d.cx[var][PASS == 2 ? 1 : 0], a, nullptr, d.ny, d.tlx, nullptr, d.vecx,
-                                         e.blk);
+    xpass_body<T, PROG_SWEEP, K, M, PER>(d.cx[var][PASS == 2 ? 1 : 0], a, nullptr, nlines, d.tlx, nullptr, d.vecx,
+                                         e.blk, smem);
   } else {
     DevState* st = d.st;
     if (st->done) return;
-    constexpr int PI = PASS == 2 ? PROG_P2 : PROG_P4;
     const PassArgs a = slot_args(d, PH_IT, PASS, var, st->iters > 0 ? 1 : 0);
-    xpass_body<T, PI, K, M, PER>(d.cx[var][PASS == 2 ? 0 : 1], a, st, d.ny, d.tlx, PASS == 4 ? d.rpart : nullptr,
-                                 d.vecx, e.blk);
+    if constexpr (PASS == 2) {
+      if (d.model == MOLT_MODEL_VCH) {
+        xpass_body<T, PROG_P2V, K, M, PER>(d.cx[var][0], a, st, nlines, d.tlx, nullptr, d.vecx, e.blk, smem);
+        return;
+      }
+    }
+    constexpr int PI = PASS == 2 ? PROG_P2 : PROG_P4;
+    xpass_body<T, PI, K, M, PER>(d.cx[var][PASS == 2 ? 0 : 1], a, st, nlines, d.tlx, PASS == 4 ? d.rpart : nullptr,
+                                 d.vecx, e.blk, smem);
   }
 }
 
 // iteration close: one block per listed slot
+template <typename T>
 __global__ void __launch_bounds__(256) close_batch_kernel(const SlotDesc* __restrict__ sd,
                                                           const SlotCtl* __restrict__ ctl,
                                                           const BlkMap* __restrict__ slots) {
@@ -177,7 +218,7 @@ __global__ void __launch_bounds__(256) finish_batch_kernel(const SlotDesc* __res
   const BlkMap e = map[blockIdx.x];
   const SlotDesc& d = sd[e.slot];
   if (ctl[e.slot].phase != PH_IT || !d.st->done) return;
-  const size_t n = (size_t)d.nx * (size_t)d.ny;
+  const size_t n = (size_t)d.nx * (size_t)d.ny * (size_t)d.ncomp;
   T* u = (T*)d.u;
   T* h = (T*)d.fld[F_HIST];
   const T* base = d.init == MOLT_INIT_LINEAR ? (const T*)d.fld[F_R] : u;
@@ -197,11 +238,29 @@ __global__ void __launch_bounds__(256) diag_batch_kernel(const SlotDesc* __restr
   const BlkMap e = map[blockIdx.x];
   const SlotDesc& d = sd[e.slot];
   if (ctl[e.slot].phase != PH_IT || !d.st->done) return;
-  diag_body<T>((const T*)d.u, d.nx, d.ny, d.bc, d.hx, d.hy, d.eps, d.partials, e.blk, d.dblocks);
+  if (d.model == MOLT_MODEL_VCH)
+    diag_vch_body<T>((const T*)d.u, d.nx, d.ny, d.bc, d.hx, d.hy, d.eps, d.partials, e.blk, d.dblocks);
+  else
+    diag_body<T>((const T*)d.u, d.nx, d.ny, d.bc, d.hx, d.hy, d.eps, d.partials, e.blk, d.dblocks);
+}
+
+// vector model: the pointwise reaction pass of slots in an iteration
+template <typename T>
+__global__ void __launch_bounds__(256) react_batch_kernel(const SlotDesc* __restrict__ sd,
+                                                          const SlotCtl* __restrict__ ctl,
+                                                          const BlkMap* __restrict__ map) {
+  const BlkMap e = map[blockIdx.x];
+  const SlotDesc& d = sd[e.slot];
+  const SlotCtl cc = ctl[e.slot];
+  if (d.model != MOLT_MODEL_VCH || cc.phase != PH_IT || d.st->done) return;
+  const PassArgs a = slot_args(d, PH_IT, 0, cc.var, d.st->iters > 0 ? 1 : 0);
+  vch_react_body<T>(a, (size_t)d.nx * (size_t)d.ny, (size_t)e.blk * blockDim.x + threadIdx.x,
+                    (size_t)d.dblocks * blockDim.x);
 }
 
 // tick end, one block per slot: R -> first iteration (state reset); a finished
 // step -> mass and energy, the step record, then the next step's R phase or idle
+template <typename T>
 __global__ void __launch_bounds__(256) tick_end_batch_kernel(const SlotDesc* __restrict__ sd, SlotCtl* ctl,
                                                              const BlkMap* __restrict__ slots) {
   const int slot = slots[blockIdx.x].slot;
@@ -223,6 +282,7 @@ __global__ void __launch_bounds__(256) tick_end_batch_kernel(const SlotDesc* __r
       st->last_resid = 0.0;
       st->mass = 0.0;
       st->energy = 0.0;
+      st->mass2 = 0.0;
       SlotCtl nc = cc;
       nc.phase = PH_IT;
       ctl[slot] = nc;
@@ -230,7 +290,10 @@ __global__ void __launch_bounds__(256) tick_end_batch_kernel(const SlotDesc* __r
     return;
   }
   if (cc.phase != PH_IT || !done) return;
-  diag_final_body(d.partials, d.dblocks, d.area, st);
+  if (d.model == MOLT_MODEL_VCH)
+    diag_vch_final_body(d.partials, d.dblocks, d.area, st);
+  else
+    diag_final_body(d.partials, d.dblocks, d.area, st);
   if (threadIdx.x == 0) {
     const int var = cc.var;
     molt_step_info r;
@@ -242,6 +305,7 @@ __global__ void __launch_bounds__(256) tick_end_batch_kernel(const SlotDesc* __r
     r.s1 = d.s1[var];
     r.s2 = d.s2[var];
     r.sigma = d.sigma[var];
+    r.mass2 = st->mass2;
     d.rec[cc.step] = r;
     SlotCtl nc;
     nc.step = cc.step + 1;
@@ -257,6 +321,7 @@ __global__ void __launch_bounds__(256) tick_end_batch_kernel(const SlotDesc* __r
   }
 }
 
+template <typename T>
 __global__ void __launch_bounds__(256) init_batch_kernel(const SlotDesc* __restrict__ sd, SlotCtl* ctl, int nslots) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nslots; i += gridDim.x * blockDim.x) {
     SlotCtl c;
@@ -269,6 +334,7 @@ __global__ void __launch_bounds__(256) init_batch_kernel(const SlotDesc* __restr
 }
 
 // number of slots not yet idle -> *out
+template <typename T>
 __global__ void __launch_bounds__(256) count_active_kernel(const SlotCtl* __restrict__ ctl, int nslots, int* out) {
   __shared__ int red[4];
   int c = 0;
@@ -324,27 +390,22 @@ static hipError_t ybatch_t(int K, int M, bool per, int pass, bool fin, const Slo
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_batch_y(int prec, int K, int M, bool per, int pass, bool fin, const SlotDesc* sd,
-                          const SlotCtl* ctl, const BlkMap* map, int nblk, hipStream_t s) {
+hipError_t MOLT_BFN(launch_batch_y)(int K, int M, bool per, int pass, bool fin, const SlotDesc* sd,
+                                   const SlotCtl* ctl, const BlkMap* map, int nblk, hipStream_t s) {
   if (nblk <= 0) return hipSuccess;
   const int kind = (fin ? KF_YFIN : KF_YTOT) * 8 + (pass == 1 ? PROG_P1 : PROG_P3);
   if (g_prof_on) prof_begin(kind, s);
-  const hipError_t e = prec == MOLT_F64 ? ybatch_t<double>(K, M, per, pass, fin, sd, ctl, map, nblk, s)
-                                        : ybatch_t<float>(K, M, per, pass, fin, sd, ctl, map, nblk, s);
+  const hipError_t e = ybatch_t<MOLT_BT>(K, M, per, pass, fin, sd, ctl, map, nblk, s);
   if (g_prof_on) prof_end(kind, s);
   return e;
 }
 
-hipError_t launch_batch_comb(int prec, int pass, const SlotDesc* sd, const SlotCtl* ctl, const BlkMap* map, int nblk,
-                             hipStream_t s) {
+hipError_t MOLT_BFN(launch_batch_comb)(int pass, const SlotDesc* sd, const SlotCtl* ctl, const BlkMap* map,
+                                      int nblk, hipStream_t s) {
   if (nblk <= 0) return hipSuccess;
   const int kind = KF_YCOMB * 8 + (pass == 1 ? PROG_P1 : PROG_P3);
   if (g_prof_on) prof_begin(kind, s);
-  const dim3 blk(64, kCombWaves);
-  if (prec == MOLT_F64)
-    hipLaunchKernelGGL((ycomb_batch_kernel<double>), dim3(nblk), blk, 0, s, sd, ctl, map, pass);
-  else
-    hipLaunchKernelGGL((ycomb_batch_kernel<float>), dim3(nblk), blk, 0, s, sd, ctl, map, pass);
+  hipLaunchKernelGGL((ycomb_batch_kernel<MOLT_BT>), dim3(nblk), dim3(64, kCombWaves), 0, s, sd, ctl, map, pass);
   if (g_prof_on) prof_end(kind, s);
   return hipGetLastError();
 }
@@ -387,43 +448,46 @@ static hipError_t xbatch_t(int K, int M, bool per, int pass, const SlotDesc* sd,
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_batch_x(int prec, int K, int M, bool per, int pass, const SlotDesc* sd, const SlotCtl* ctl,
-                          const BlkMap* map, int nblk, hipStream_t s) {
+hipError_t MOLT_BFN(launch_batch_x)(int K, int M, bool per, int pass, const SlotDesc* sd, const SlotCtl* ctl,
+                                   const BlkMap* map, int nblk, hipStream_t s) {
   if (nblk <= 0) return hipSuccess;
   const int kind = KF_XPASS * 8 + (pass == 2 ? PROG_P2 : PROG_P4);
   if (g_prof_on) prof_begin(kind, s);
-  const hipError_t e = prec == MOLT_F64 ? xbatch_t<double>(K, M, per, pass, sd, ctl, map, nblk, s)
-                                        : xbatch_t<float>(K, M, per, pass, sd, ctl, map, nblk, s);
+  const hipError_t e = xbatch_t<MOLT_BT>(K, M, per, pass, sd, ctl, map, nblk, s);
   if (g_prof_on) prof_end(kind, s);
   return e;
 }
 
 // close, step finish, diagnostics and tick end (kind "other_1") of the listed slots
-hipError_t launch_batch_tail(int prec, const SlotDesc* sd, SlotCtl* ctl, const BlkMap* slots, int nslots,
-                             const BlkMap* pmap, int npblk, hipStream_t s) {
+hipError_t MOLT_BFN(launch_batch_tail)(const SlotDesc* sd, SlotCtl* ctl, const BlkMap* slots, int nslots,
+                                      const BlkMap* pmap, int npblk, hipStream_t s) {
   if (nslots <= 0) return hipSuccess;
   if (g_prof_on) prof_begin(KF_OTHER * 8 + 1, s);
-  hipLaunchKernelGGL(close_batch_kernel, dim3(nslots), dim3(256), 0, s, sd, (const SlotCtl*)ctl, slots);
-  if (prec == MOLT_F64) {
-    hipLaunchKernelGGL((finish_batch_kernel<double>), dim3(npblk), dim3(256), 0, s, sd, (const SlotCtl*)ctl, pmap);
-    hipLaunchKernelGGL((diag_batch_kernel<double>), dim3(npblk), dim3(256), 0, s, sd, (const SlotCtl*)ctl, pmap);
-  } else {
-    hipLaunchKernelGGL((finish_batch_kernel<float>), dim3(npblk), dim3(256), 0, s, sd, (const SlotCtl*)ctl, pmap);
-    hipLaunchKernelGGL((diag_batch_kernel<float>), dim3(npblk), dim3(256), 0, s, sd, (const SlotCtl*)ctl, pmap);
-  }
-  hipLaunchKernelGGL(tick_end_batch_kernel, dim3(nslots), dim3(256), 0, s, sd, ctl, slots);
+  hipLaunchKernelGGL((close_batch_kernel<MOLT_BT>), dim3(nslots), dim3(256), 0, s, sd, (const SlotCtl*)ctl, slots);
+  hipLaunchKernelGGL((finish_batch_kernel<MOLT_BT>), dim3(npblk), dim3(256), 0, s, sd, (const SlotCtl*)ctl, pmap);
+  hipLaunchKernelGGL((diag_batch_kernel<MOLT_BT>), dim3(npblk), dim3(256), 0, s, sd, (const SlotCtl*)ctl, pmap);
+  hipLaunchKernelGGL((tick_end_batch_kernel<MOLT_BT>), dim3(nslots), dim3(256), 0, s, sd, ctl, slots);
   if (g_prof_on) prof_end(KF_OTHER * 8 + 1, s);
   return hipGetLastError();
 }
 
-hipError_t launch_batch_init(const SlotDesc* sd, SlotCtl* ctl, int nslots, hipStream_t s) {
-  const int nb = (nslots + 255) / 256;
-  hipLaunchKernelGGL(init_batch_kernel, dim3(nb < 1 ? 1 : nb), dim3(256), 0, s, sd, ctl, nslots);
+hipError_t MOLT_BFN(launch_batch_react)(const SlotDesc* sd, const SlotCtl* ctl, const BlkMap* pmap, int npblk,
+                                       hipStream_t s) {
+  if (npblk <= 0) return hipSuccess;
+  if (g_prof_on) prof_begin(KF_POINTWISE * 8 + PROG_P1V, s);
+  hipLaunchKernelGGL((react_batch_kernel<MOLT_BT>), dim3(npblk), dim3(256), 0, s, sd, ctl, pmap);
+  if (g_prof_on) prof_end(KF_POINTWISE * 8 + PROG_P1V, s);
   return hipGetLastError();
 }
 
-hipError_t launch_batch_count(const SlotCtl* ctl, int nslots, int* out, hipStream_t s) {
-  hipLaunchKernelGGL(count_active_kernel, dim3(1), dim3(256), 0, s, ctl, nslots, out);
+hipError_t MOLT_BFN(launch_batch_init)(const SlotDesc* sd, SlotCtl* ctl, int nslots, hipStream_t s) {
+  const int nb = (nslots + 255) / 256;
+  hipLaunchKernelGGL((init_batch_kernel<MOLT_BT>), dim3(nb < 1 ? 1 : nb), dim3(256), 0, s, sd, ctl, nslots);
+  return hipGetLastError();
+}
+
+hipError_t MOLT_BFN(launch_batch_count)(const SlotCtl* ctl, int nslots, int* out, hipStream_t s) {
+  hipLaunchKernelGGL((count_active_kernel<MOLT_BT>), dim3(1), dim3(256), 0, s, ctl, nslots, out);
   return hipGetLastError();
 }
 

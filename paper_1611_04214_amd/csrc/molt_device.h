@@ -67,7 +67,8 @@ __device__ __forceinline__ int wrapi(int j, int n) {
 // shift only changes the reaction: g = f(v) - sigma v = u^3 - (1+sigma) u - sigma,
 // and the constant drops out of C1 g.
 // --------------------------------------------------------------------------
-enum ProgId { PROG_SWEEP = 0, PROG_RHS = 1, PROG_P1 = 2, PROG_P2 = 3, PROG_P3 = 4, PROG_P4 = 5 };
+enum ProgId { PROG_SWEEP = 0, PROG_RHS = 1, PROG_P1 = 2, PROG_P2 = 3, PROG_P3 = 4, PROG_P4 = 5, PROG_P1V = 6,
+              PROG_P2V = 7 };
 
 template <typename T>
 struct ProgSweep {  // w = L^{-1} in0
@@ -181,8 +182,48 @@ struct ProgP4 {  // x, alpha2: raw (m, n, dl|R, W) -> dl' = (dl|R) + X2 m - n ; 
   }
 };
 
+// Vector model: the reaction and linear parts (e, lin) of both components are
+// formed by a pointwise pre-pass (vch_react_body); P1 and P2 then sweep them
+// like any stacked pair of fields.
+template <typename T>
+struct ProgP1V {  // y, alpha1: raw (e, lin) -> a1 = Y1 e, b1 = Y1 lin
+  static constexpr int F = 2, E = 0, NR = 2, NO = 2;
+  __device__ static bool need(const PassArgs&, int) { return true; }
+  __device__ static void sin(const PassArgs&, const T* r, T* s) {
+    s[0] = r[0];
+    s[1] = r[1];
+  }
+  __device__ static void ext(const PassArgs&, const T*, T*) {}
+  __device__ static double fin(const PassArgs&, const T* w, const T*, T* o) {
+    o[0] = w[0];
+    o[1] = w[1];
+    return 0.0;
+  }
+};
+
+template <typename T>
+struct ProgP2V {  // x, alpha1: raw (a1, b1, e, lin) -> C = X1(2 a1 - e) - a1, q = b1 + X1(lin - b1)
+  static constexpr int F = 2, E = 2, NR = 4, NO = 2;
+  __device__ static bool need(const PassArgs&, int) { return true; }
+  __device__ static void sin(const PassArgs&, const T* r, T* s) {
+    s[0] = T(2) * r[0] - r[2];
+    s[1] = r[3] - r[1];
+  }
+  __device__ static void ext(const PassArgs&, const T* r, T* x) {
+    x[0] = r[0];
+    x[1] = r[1];
+  }
+  __device__ static double fin(const PassArgs&, const T* w, const T* x, T* o) {
+    o[0] = w[0] - x[0];
+    o[1] = x[1] + w[1];
+    return 0.0;
+  }
+};
+
 template <int P, typename T>
 struct ProgOf;
+template <typename T> struct ProgOf<PROG_P1V, T> { using type = ProgP1V<T>; };
+template <typename T> struct ProgOf<PROG_P2V, T> { using type = ProgP2V<T>; };
 template <typename T> struct ProgOf<PROG_SWEEP, T> { using type = ProgSweep<T>; };
 template <typename T> struct ProgOf<PROG_RHS, T> { using type = ProgRhs<T>; };
 template <typename T> struct ProgOf<PROG_P1, T> { using type = ProgP1<T>; };
@@ -547,9 +588,17 @@ __device__ inline void residual_close_body(const double* partials, int nblocks, 
 // x-direction pass: rows are contiguous; TL threads (a multiple of 64) own one
 // row, 256/TL rows per 256-thread block.
 // --------------------------------------------------------------------------
+// LDS of one x-pass block: F <= 2 swept rows of 256*K nodes, one pad word per 16
+template <typename T, int K>
+struct XRow {
+  static constexpr int ROW = 256 * K;
+  static constexpr int PADDED = ROW + ROW / 16;
+  static constexpr int ELEMS = 2 * PADDED;
+};
+
 template <typename T, int PI, int K, int M, bool PER>
 __device__ __forceinline__ void xpass_body(const LineCoef& c, const PassArgs& a, DevState* st, int nlines, int TL,
-                                           double* rpart, int vec, int bx) {
+                                           double* rpart, int vec, int bx, T* smem) {
   using P = typename ProgOf<PI, T>::type;
   constexpr int F = P::F, E = P::E, NR = P::NR, NO = P::NO;
   constexpr int H = M / 2, W = K + 2 * H;
@@ -561,7 +610,7 @@ __device__ __forceinline__ void xpass_body(const LineCoef& c, const PassArgs& a,
   // swept fields (then the swept results) of the block's rows, one padding
   // word per 16 so that a thread's K consecutive nodes sit 17 words from its
   // neighbour's (no bank conflicts)
-  __shared__ T sh_row[F][ROW + ROW / 16];
+  T (*sh_row)[ROW + ROW / 16] = reinterpret_cast<T (*)[ROW + ROW / 16]>(smem);  // [F][padded row]
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -1079,6 +1128,155 @@ __device__ __forceinline__ void diag_final_body(const double* partials, int nblo
   if (threadIdx.x == 0) {
     st->mass = sm[0][0] * area;
     st->energy = sm[1][0] * area;
+  }
+}
+
+// --------------------------------------------------------------------------
+// Vector model (Sec. 2 eq. CH_vector_reaction, Sec. 5.2).  With w = u1 + i u2,
+// prod_i |u - z_i|^2 over the cube roots of unity is |w^3 - 1|^2, so
+// grad W = (Re G, Im G) with G = 2 dW/d(conj w) = 6 conj(w)^2 (w^3 - 1)
+//        = 6 (|w|^4 w - conj(w)^2).
+// In u the shifted reaction g(v) = grad W(v + z3) - sigma v is
+// grad W(u) - sigma u up to a constant, which C1 annihilates.
+//  full form:      e = G(p) - sigma p, lin = p
+//  increment form: e = G(p) - G(q) - sigma d, lin = d  (p = q + d), with
+//    G(p) - G(q) = 6 [ |p|^4 d + (|p|^2 - |q|^2)(|p|^2 + |q|^2) q - conj(d) conj(p + q) ],
+//    |p|^2 - |q|^2 = Re(d conj(p + q)): every term is proportional to d, so an
+//    FP32 increment keeps its relative accuracy.
+// --------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void vch_react(T b1, T b2, T w1, T w2, T d1, T d2, T sigma, int mode, T* e, T* lin) {
+  if (mode == 0) {
+    const T p2 = b1 * b1 + b2 * b2;
+    const T p4 = p2 * p2;
+    // conj(w)^2 = (b1^2 - b2^2, -2 b1 b2)
+    e[0] = T(6) * (p4 * b1 - (b1 * b1 - b2 * b2)) - sigma * b1;
+    e[1] = T(6) * (p4 * b2 + T(2) * b1 * b2) - sigma * b2;
+    lin[0] = b1;
+    lin[1] = b2;
+  } else {
+    const T p1 = b1 + w1, p2c = b2 + w2;  // current iterate p
+    const T q1 = p1 - d1, q2 = p2c - d2;  // previous iterate q
+    const T s1 = p1 + q1, s2 = p2c + q2;
+    const T P2 = p1 * p1 + p2c * p2c, Q2 = q1 * q1 + q2 * q2;
+    const T dr = d1 * s1 + d2 * s2;  // |p|^2 - |q|^2
+    const T tq = dr * (P2 + Q2);      // |p|^4 - |q|^4
+    const T P4 = P2 * P2;
+    // conj(d) conj(s) = conj(d s) = (d1 s1 - d2 s2, -(d1 s2 + d2 s1))
+    const T c1 = d1 * s1 - d2 * s2, c2 = -(d1 * s2 + d2 * s1);
+    e[0] = T(6) * (P4 * d1 + tq * q1 - c1) - sigma * d1;
+    e[1] = T(6) * (P4 * d2 + tq * q2 - c2) - sigma * d2;
+    lin[0] = d1;
+    lin[1] = d2;
+  }
+}
+
+// (e, lin) of both components at nodes [i0, n) with stride `step`: in = (base,
+// W, dl), out = (e, lin), every field component-major with n nodes per component
+template <typename T>
+__device__ __forceinline__ void vch_react_body(const PassArgs& a, size_t n, size_t i0, size_t step) {
+  const T* B = (const T*)a.in[0];
+  const T* Wf = (const T*)a.in[1];
+  const T* D = (const T*)a.in[2];
+  T* E = (T*)a.out[0];
+  T* L = (T*)a.out[1];
+  const T sg = (T)a.sigma;
+  for (size_t i = i0; i < n; i += step) {
+    T e[2], lin[2];
+    if (a.mode == 0)
+      vch_react<T>(B[i], B[n + i], T(0), T(0), T(0), T(0), sg, 0, e, lin);
+    else
+      vch_react<T>(B[i], B[n + i], Wf[i], Wf[n + i], D[i], D[n + i], sg, 1, e, lin);
+    E[i] = e[0];
+    E[n + i] = e[1];
+    L[i] = lin[0];
+    L[n + i] = lin[1];
+  }
+}
+
+// FP64 mass of each component and the energy of eq. EnergyFunctional_vector
+// (forward differences, trapezoid end weights off the periodic case); three
+// partial sums per block
+template <typename T>
+__device__ __forceinline__ void diag_vch_body(const T* u, int nx, int ny, int bc, double hx, double hy, double eps,
+                                              double* partials, int bx, int nb) {
+  __shared__ double sm[3][4];
+  const bool per = bc == MOLT_BC_PERIODIC;
+  double m1 = 0.0, m2 = 0.0, en = 0.0;
+  const size_t n = (size_t)nx * ny;
+  for (size_t i = (size_t)bx * blockDim.x + threadIdx.x; i < n; i += (size_t)nb * blockDim.x) {
+    const int ix = (int)(i % nx), iy = (int)(i / nx);
+    const double wx = per ? 1.0 : ((ix == 0 || ix == nx - 1) ? 0.5 : 1.0);
+    const double wy = (ny == 1 || per) ? 1.0 : ((iy == 0 || iy == ny - 1) ? 0.5 : 1.0);
+    const double a = (double)u[i], b = (double)u[n + i];
+    m1 += wx * wy * a;
+    m2 += wx * wy * b;
+    // |w^3 - 1|^2 with w^3 = (a^3 - 3ab^2, 3a^2 b - b^3)
+    const double r = a * a * a - 3.0 * a * b * b - 1.0, s = 3.0 * a * a * b - b * b * b;
+    en += wx * wy * (r * r + s * s);
+    for (int c = 0; c < 2; ++c) {
+      const T* uc = u + c * n;
+      const double uu = (double)uc[i];
+      if (per || ix < nx - 1) {
+        const double g = ((double)uc[(size_t)iy * nx + (ix + 1 == nx ? 0 : ix + 1)] - uu) / hx;
+        en += 0.5 * eps * eps * g * g * wy;
+      }
+      if (ny > 1 && (per || iy < ny - 1)) {
+        const double g = ((double)uc[(size_t)(iy + 1 == ny ? 0 : iy + 1) * nx + ix] - uu) / hy;
+        en += 0.5 * eps * eps * g * g * wx;
+      }
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    m1 += __shfl_down(m1, off);
+    m2 += __shfl_down(m2, off);
+    en += __shfl_down(en, off);
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+    sm[0][wave] = m1;
+    sm[1][wave] = m2;
+    sm[2][wave] = en;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double x = 0.0, y = 0.0, z = 0.0;
+    for (int w = 0; w < 4; ++w) {
+      x += sm[0][w];
+      y += sm[1][w];
+      z += sm[2][w];
+    }
+    partials[3 * bx] = x;
+    partials[3 * bx + 1] = y;
+    partials[3 * bx + 2] = z;
+  }
+}
+
+__device__ __forceinline__ void diag_vch_final_body(const double* partials, int nblocks, double area, DevState* st) {
+  __shared__ double sm[3][256];
+  double a = 0.0, b = 0.0, c = 0.0;
+  for (int i = threadIdx.x; i < nblocks; i += blockDim.x) {
+    a += partials[3 * i];
+    b += partials[3 * i + 1];
+    c += partials[3 * i + 2];
+  }
+  sm[0][threadIdx.x] = a;
+  sm[1][threadIdx.x] = b;
+  sm[2][threadIdx.x] = c;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      sm[0][threadIdx.x] += sm[0][threadIdx.x + s];
+      sm[1][threadIdx.x] += sm[1][threadIdx.x + s];
+      sm[2][threadIdx.x] += sm[2][threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    st->mass = sm[0][0] * area;
+    st->mass2 = sm[1][0] * area;
+    st->energy = sm[2][0] * area;
   }
 }
 

@@ -11,19 +11,57 @@
 #include "molt_internal.h"
 
 namespace molt {
+// single-problem kernels, one translation unit per precision and pass direction
+#define MOLT_KERN_DECL(sfx)                                                                                     \
+  hipError_t launch_xpass_##sfx(int prog, const LineCoef& c, const PassArgs& a, DevState* st, int nlines,     \
+                                double* rpart, hipStream_t s);                                                 \
+  hipError_t launch_ypass_##sfx(int prog, const LineCoef& c, const PassArgs& a, DevState* st, int nx,         \
+                                int batch, void* tot, void* jln, const YFused* fz, hipStream_t s);             \
+  hipError_t launch_pointwise_##sfx(int prog, const PassArgs& a, DevState* st, size_t nelem, hipStream_t s);  \
+  hipError_t launch_copy_##sfx(void* dst, const void* src, size_t n, hipStream_t s);                          \
+  hipError_t launch_finalize_##sfx(void* u, const void* base, const void* W, size_t n, hipStream_t s);        \
+  hipError_t launch_diag_##sfx(const void* u, int nx, int ny, int bc, double hx, double hy, double eps,       \
+                               double* partials, DevState* st, hipStream_t s);                                \
+  hipError_t launch_diag_vch_##sfx(const void* u, int nx, int ny, int bc, double hx, double hy, double eps,   \
+                                   double* partials, DevState* st, hipStream_t s);                             \
+  hipError_t launch_vch_react_##sfx(const PassArgs& a, DevState* st, size_t n, hipStream_t s);
+MOLT_KERN_DECL(f32)
+MOLT_KERN_DECL(f64)
+#undef MOLT_KERN_DECL
+#define MOLT_PREC(call) (prec == MOLT_F64 ? call##_f64 : call##_f32)
 hipError_t launch_xpass(int prec, int prog, const LineCoef& c, const PassArgs& a, DevState* st, int nlines,
-                        double* rpart, hipStream_t s);
+                        double* rpart, hipStream_t s) {
+  return MOLT_PREC(launch_xpass)(prog, c, a, st, nlines, rpart, s);
+}
 hipError_t launch_ypass(int prec, int prog, const LineCoef& c, const PassArgs& a, DevState* st, int nx, int batch,
-                        void* tot, void* jln, const YFused* fz, hipStream_t s);
+                        void* tot, void* jln, const YFused* fz, hipStream_t s) {
+  return MOLT_PREC(launch_ypass)(prog, c, a, st, nx, batch, tot, jln, fz, s);
+}
+static hipError_t launch_pointwise(int prec, int prog, const PassArgs& a, DevState* st, size_t nelem, hipStream_t s) {
+  return MOLT_PREC(launch_pointwise)(prog, a, st, nelem, s);
+}
+static hipError_t launch_copy(int prec, void* dst, const void* src, size_t n, hipStream_t s) {
+  return MOLT_PREC(launch_copy)(dst, src, n, s);
+}
+static hipError_t launch_finalize(int prec, void* u, const void* base, const void* W, size_t n, hipStream_t s) {
+  return MOLT_PREC(launch_finalize)(u, base, W, n, s);
+}
+static hipError_t launch_diag(int prec, const void* u, int nx, int ny, int bc, double hx, double hy, double eps,
+                              double* partials, DevState* st, hipStream_t s) {
+  return MOLT_PREC(launch_diag)(u, nx, ny, bc, hx, hy, eps, partials, st, s);
+}
+static hipError_t launch_diag_vch(int prec, const void* u, int nx, int ny, int bc, double hx, double hy, double eps,
+                                  double* partials, DevState* st, hipStream_t s) {
+  return MOLT_PREC(launch_diag_vch)(u, nx, ny, bc, hx, hy, eps, partials, st, s);
+}
+static hipError_t launch_vch_react(int prec, const PassArgs& a, DevState* st, size_t n, hipStream_t s) {
+  return MOLT_PREC(launch_vch_react)(a, st, n, s);
+}
+#undef MOLT_PREC
 size_t yfused_items(int n, int nx, int batch);
 size_t yfused_rec_words(int n, int nx, int batch);
 hipError_t launch_zero_ints(int* p, int n, hipStream_t s);
-hipError_t launch_pointwise(int prec, int prog, const PassArgs& a, DevState* st, size_t nelem, hipStream_t s);
 hipError_t launch_state_init(DevState* st, double tol, int max_iter, int fixed, hipStream_t s);
-hipError_t launch_copy(int prec, void* dst, const void* src, size_t n, hipStream_t s);
-hipError_t launch_finalize(int prec, void* u, const void* base, const void* W, size_t n, hipStream_t s);
-hipError_t launch_diag(int prec, const void* u, int nx, int ny, int bc, double hx, double hy, double eps,
-                       double* partials, DevState* st, hipStream_t s);
 size_t ypass_tot_elems(int prec, int n, int nx, int batch);
 int diag_blocks(size_t n);
 int xpass_max_n(int prec);
@@ -31,8 +69,23 @@ int xpass_max_n(int prec);
 int xpass_pick_k(int n, int prec);
 int xpass_tl(int n, int K);
 void ypass_shape(int prec, int n, int* nth, int* nseg);
-hipError_t launch_batch_y(int prec, int K, int M, bool per, int pass, bool fin, const SlotDesc* sd,
-                          const SlotCtl* ctl, const BlkMap* map, int nblk, hipStream_t s);
+// batched kernels, one translation unit per precision
+#define MOLT_BATCH_DECL(sfx)                                                                                    \
+  hipError_t launch_batch_y_##sfx(int K, int M, bool per, int pass, bool fin, const SlotDesc* sd,              \
+                                  const SlotCtl* ctl, const BlkMap* map, int nblk, hipStream_t s);             \
+  hipError_t launch_batch_comb_##sfx(int pass, const SlotDesc* sd, const SlotCtl* ctl, const BlkMap* map,      \
+                                     int nblk, hipStream_t s);                                                 \
+  hipError_t launch_batch_x_##sfx(int K, int M, bool per, int pass, const SlotDesc* sd, const SlotCtl* ctl,    \
+                                  const BlkMap* map, int nblk, hipStream_t s);                                 \
+  hipError_t launch_batch_tail_##sfx(const SlotDesc* sd, SlotCtl* ctl, const BlkMap* slots, int nslots,        \
+                                     const BlkMap* pmap, int npblk, hipStream_t s);                            \
+  hipError_t launch_batch_react_##sfx(const SlotDesc* sd, const SlotCtl* ctl, const BlkMap* pmap, int npblk,   \
+                                      hipStream_t s);                                                          \
+  hipError_t launch_batch_init_##sfx(const SlotDesc* sd, SlotCtl* ctl, int nslots, hipStream_t s);             \
+  hipError_t launch_batch_count_##sfx(const SlotCtl* ctl, int nslots, int* out, hipStream_t s);
+MOLT_BATCH_DECL(f32)
+MOLT_BATCH_DECL(f64)
+#undef MOLT_BATCH_DECL
 int ypass_pick_k(int n, int prec);
 int ypass_max_segments(int n);
 int xpass_min_k(int n, int prec);
@@ -40,16 +93,8 @@ int tune_class(int n);
 bool tune_valid(int prec, int cls, int kx, int ky);
 void tune_get(int prec, int cls, int* kx, int* ky);
 void tune_set(int prec, int cls, int kx, int ky);
-hipError_t launch_batch_comb(int prec, int pass, const SlotDesc* sd, const SlotCtl* ctl, const BlkMap* map, int nblk,
-                             hipStream_t s);
-hipError_t launch_batch_x(int prec, int K, int M, bool per, int pass, const SlotDesc* sd, const SlotCtl* ctl,
-                          const BlkMap* map, int nblk, hipStream_t s);
-hipError_t launch_batch_tail(int prec, const SlotDesc* sd, SlotCtl* ctl, const BlkMap* slots, int nslots,
-                             const BlkMap* pmap, int npblk, hipStream_t s);
-hipError_t launch_batch_init(const SlotDesc* sd, SlotCtl* ctl, int nslots, hipStream_t s);
-hipError_t launch_batch_count(const SlotCtl* ctl, int nslots, int* out, hipStream_t s);
 
-enum { PROG_SWEEP = 0, PROG_RHS = 1, PROG_P1 = 2, PROG_P2 = 3, PROG_P3 = 4, PROG_P4 = 5 };
+enum { PROG_SWEEP = 0, PROG_RHS = 1, PROG_P1 = 2, PROG_P2 = 3, PROG_P3 = 4, PROG_P4 = 5, PROG_P1V = 6, PROG_P2V = 7 };
 
 // --------------------------------------------------------------------------
 // errors
@@ -272,27 +317,30 @@ struct Layout {
   size_t tot, jln, state, partials, rpart, frec, total;
 };
 
-static Layout ch_layout(const molt_grid* g, int prec) {
+static int ncomp_of(const molt_ch_params* p) { return p->model == MOLT_MODEL_VCH ? 2 : 1; }
+
+static Layout ch_layout(const molt_grid* g, int prec, int ncomp) {
   Layout L;
   const size_t esz = prec == MOLT_F64 ? 8 : 4;
   const size_t n = (size_t)g->nx * g->ny;
   size_t off = 0;
   for (int i = 0; i < F_COUNT; ++i) {
     L.fld[i] = off;
-    off += al256(n * esz);
+    const bool used = (i != F_E && i != F_LIN) || ncomp == 2;
+    off += used ? al256(n * ncomp * esz) : 0;
   }
   L.tot = off;
-  off += al256(g->ny > 1 ? ypass_tot_elems(prec, g->ny, g->nx, 1) * esz : 0);
+  off += al256(g->ny > 1 ? ypass_tot_elems(prec, g->ny, g->nx, ncomp) * esz : 0);
   L.jln = off;
-  off += al256((size_t)2 * g->nx * esz);
+  off += al256((size_t)2 * g->nx * ncomp * esz);
   L.state = off;
   off += al256(sizeof(DevState));
-  L.partials = off;
-  off += al256((size_t)2 * diag_blocks(n) * sizeof(double));
+  L.partials = off;  // mass / energy partials: up to three per diagnostic block
+  off += al256((size_t)3 * diag_blocks(n) * sizeof(double));
   L.rpart = off;  // one residual slot per x-pass block (at most one block per row)
-  off += al256((size_t)g->ny * sizeof(double));
+  off += al256((size_t)g->ny * ncomp * sizeof(double));
   L.frec = off;  // fused y-pass: published segment totals
-  off += al256(g->ny > 1 ? yfused_rec_words(g->ny, g->nx, 1) * sizeof(unsigned long long) : 0);
+  off += al256(g->ny > 1 ? yfused_rec_words(g->ny, g->nx, ncomp) * sizeof(unsigned long long) : 0);
   L.total = off;
   return L;
 }
@@ -303,7 +351,9 @@ static Layout ch_layout(const molt_grid* g, int prec) {
 static int32_t step_impl(const molt_grid* g, const molt_ch_params* p, void* d_u, void* d_u_prev, bool bdf2,
                          void* d_work, size_t work_bytes, molt_step_info* info, hipStream_t s, int iter_hint) {
   const int prec = p->precision;
-  const Layout L = ch_layout(g, prec);
+  const int nc = ncomp_of(p);
+  const bool vch = nc == 2;
+  const Layout L = ch_layout(g, prec, nc);
   if (!d_work || work_bytes < L.total) return fail(MOLT_EWORKSPACE, "workspace smaller than ch_workspace_bytes()");
   char* w = (char*)d_work;
   void* F[F_COUNT];
@@ -333,12 +383,12 @@ static int32_t step_impl(const molt_grid* g, const molt_ch_params* p, void* d_u,
   memset(&fz, 0, sizeof(fz));
   if (two_d) {
     fz.rec = w + L.frec;
-    fz.max_items = yfused_items(ny, nx, 1);
+    fz.max_items = yfused_items(ny, nx, nc);
     fz.min_items = g_fused_min_items > 0x7fffffffLL ? 0x7fffffff : (int)g_fused_min_items;
     fz.epoch = 0;
     fz.spin_limit = 1LL << 26;
     // epochs restart at 1 every step: clear the words (as 32-bit ints)
-    HIPCHK(launch_zero_ints((int*)fz.rec, (int)(2 * yfused_rec_words(ny, nx, 1)), s));
+    HIPCHK(launch_zero_ints((int*)fz.rec, (int)(2 * yfused_rec_words(ny, nx, nc)), s));
   }
 
   // R = A1^{-1} A2^{-1} rhs, A_i^{-1} = Lx_i^{-1} Ly_i^{-1}
@@ -347,29 +397,32 @@ static int32_t step_impl(const molt_grid* g, const molt_ch_params* p, void* d_u,
   a.bdf2 = bdf2 ? 1 : 0;
   a.in[0] = d_u;
   a.in[1] = bdf2 ? d_u_prev : d_u;
+  // (vector model: both components at once, stacked as a batch of y-sweeps
+  // and as 2*ny rows of x-sweeps)
+  const int xl = ny * nc;
   if (two_d) {
     a.out[0] = F[F_A1];
     ++fz.epoch;
-    HIPCHK(launch_ypass(prec, PROG_RHS, cy2, a, st, nx, 1, tot, jln, &fz, s));
+    HIPCHK(launch_ypass(prec, PROG_RHS, cy2, a, st, nx, nc, tot, jln, &fz, s));
     a.in[0] = F[F_A1];
     a.out[0] = F[F_B1];
-    HIPCHK(launch_xpass(prec, PROG_SWEEP, cx2, a, nullptr, ny, nullptr, s));
+    HIPCHK(launch_xpass(prec, PROG_SWEEP, cx2, a, nullptr, xl, nullptr, s));
     a.in[0] = F[F_B1];
     a.out[0] = F[F_A1];
     ++fz.epoch;
-    HIPCHK(launch_ypass(prec, PROG_SWEEP, cy1, a, st, nx, 1, tot, jln, &fz, s));
+    HIPCHK(launch_ypass(prec, PROG_SWEEP, cy1, a, st, nx, nc, tot, jln, &fz, s));
     a.in[0] = F[F_A1];
     a.out[0] = F[F_R];
-    HIPCHK(launch_xpass(prec, PROG_SWEEP, cx1, a, nullptr, ny, nullptr, s));
+    HIPCHK(launch_xpass(prec, PROG_SWEEP, cx1, a, nullptr, xl, nullptr, s));
   } else {
     a.out[0] = F[F_B1];
-    HIPCHK(launch_xpass(prec, PROG_RHS, cx2, a, nullptr, 1, nullptr, s));
+    HIPCHK(launch_xpass(prec, PROG_RHS, cx2, a, nullptr, xl, nullptr, s));
     a.in[0] = F[F_B1];
     a.out[0] = F[F_R];
-    HIPCHK(launch_xpass(prec, PROG_SWEEP, cx1, a, nullptr, 1, nullptr, s));
+    HIPCHK(launch_xpass(prec, PROG_SWEEP, cx1, a, nullptr, xl, nullptr, s));
   }
   // history: u^n -> u_prev (after the rhs has consumed u^{n-1})
-  if (d_u_prev) HIPCHK(launch_copy(prec, d_u_prev, d_u, n, s));
+  if (d_u_prev) HIPCHK(launch_copy(prec, d_u_prev, d_u, n * nc, s));
 
   void* base = p->init == MOLT_INIT_LINEAR ? F[F_R] : d_u;
   const int fixed = p->fixed_iters;
@@ -386,37 +439,54 @@ static int32_t step_impl(const molt_grid* g, const molt_ch_params* p, void* d_u,
       q.sigma = sp.sigma;
       q.kappa = sp.a / sp.s1;
       q.mode = it == 0 ? 0 : 1;
-      // P1 (y, alpha1): a1 = Y1 e, b1 = Y1 lin
+      // P1 (y, alpha1): a1 = Y1 e, b1 = Y1 lin (vector model: e, lin from the
+      // pointwise reaction pass, then both components swept as a batch)
       q.in[0] = base;
       q.in[1] = F[F_W];
       q.in[2] = F[F_DL];
+      if (vch) {
+        q.out[0] = F[F_E];
+        q.out[1] = F[F_LIN];
+        HIPCHK(launch_vch_react(prec, q, st, n, s));
+        q.in[0] = F[F_E];
+        q.in[1] = F[F_LIN];
+        q.in[2] = nullptr;
+      }
       q.out[0] = F[F_A1];
       q.out[1] = F[F_B1];
+      const int p1 = vch ? PROG_P1V : PROG_P1;
       if (two_d) {
         ++fz.epoch;
-        HIPCHK(launch_ypass(prec, PROG_P1, cy1, q, st, nx, 1, tot, jln, &fz, s));
+        HIPCHK(launch_ypass(prec, p1, cy1, q, st, nx, nc, tot, jln, &fz, s));
       } else {
-        HIPCHK(launch_pointwise(prec, PROG_P1, q, st, n, s));
+        HIPCHK(launch_pointwise(prec, p1, q, st, n * nc, s));
       }
       // P2 (x, alpha1): C, q
       q.in[0] = F[F_A1];
       q.in[1] = F[F_B1];
-      q.in[2] = base;
-      q.in[3] = F[F_W];
-      q.in[4] = F[F_DL];
+      if (vch) {
+        q.in[2] = F[F_E];
+        q.in[3] = F[F_LIN];
+        q.in[4] = nullptr;
+      } else {
+        q.in[2] = base;
+        q.in[3] = F[F_W];
+        q.in[4] = F[F_DL];
+      }
       q.out[0] = F[F_C];
       q.out[1] = F[F_Q];
-      HIPCHK(launch_xpass(prec, PROG_P2, cx1, q, st, ny, nullptr, s));
+      HIPCHK(launch_xpass(prec, vch ? PROG_P2V : PROG_P2, cx1, q, st, xl, nullptr, s));
       // P3 (y, alpha2): m, n
       q.in[0] = F[F_C];
       q.in[1] = F[F_Q];
+      q.in[2] = q.in[3] = q.in[4] = nullptr;
       q.out[0] = F[F_M];
       q.out[1] = F[F_N];
       if (two_d) {
         ++fz.epoch;
-        HIPCHK(launch_ypass(prec, PROG_P3, cy2, q, st, nx, 1, tot, jln, &fz, s));
+        HIPCHK(launch_ypass(prec, PROG_P3, cy2, q, st, nx, nc, tot, jln, &fz, s));
       } else {
-        HIPCHK(launch_pointwise(prec, PROG_P3, q, st, n, s));
+        HIPCHK(launch_pointwise(prec, PROG_P3, q, st, n * nc, s));
       }
       // P4 (x, alpha2): increment and running sum, residual
       q.in[0] = F[F_M];
@@ -425,7 +495,7 @@ static int32_t step_impl(const molt_grid* g, const molt_ch_params* p, void* d_u,
       q.in[3] = F[F_W];
       q.out[0] = F[F_DL];
       q.out[1] = F[F_W];
-      HIPCHK(launch_xpass(prec, PROG_P4, cx2, q, st, ny, rpart, s));
+      HIPCHK(launch_xpass(prec, PROG_P4, cx2, q, st, xl, rpart, s));
     }
     HIPCHK(hipMemcpyAsync(&hst, st, sizeof(DevState), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -433,8 +503,11 @@ static int32_t step_impl(const molt_grid* g, const molt_ch_params* p, void* d_u,
     if (hst.done || it >= cap) break;
     batch = batch < 32 ? batch * 2 : 32;
   }
-  HIPCHK(launch_finalize(prec, d_u, base, F[F_W], n, s));
-  HIPCHK(launch_diag(prec, d_u, nx, ny, bc, hx, hy, p->eps, partials, st, s));
+  HIPCHK(launch_finalize(prec, d_u, base, F[F_W], n * nc, s));
+  if (vch)
+    HIPCHK(launch_diag_vch(prec, d_u, nx, ny, bc, hx, hy, p->eps, partials, st, s));
+  else
+    HIPCHK(launch_diag(prec, d_u, nx, ny, bc, hx, hy, p->eps, partials, st, s));
   HIPCHK(hipMemcpyAsync(&hst, st, sizeof(DevState), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   if (g_prof_on) prof_drain();
@@ -449,6 +522,7 @@ static int32_t step_impl(const molt_grid* g, const molt_ch_params* p, void* d_u,
     info->s1 = sp.s1;
     info->s2 = sp.s2;
     info->sigma = sp.sigma;
+    info->mass2 = hst.mass2;
   }
   return conv ? MOLT_OK : MOLT_NOT_CONVERGED;
 }
@@ -460,6 +534,7 @@ static int32_t check_params(const molt_ch_params* p) {
   if (p->stepper != MOLT_BE && p->stepper != MOLT_BDF2) return fail(MOLT_EINVAL, "unknown stepper");
   if (p->init != MOLT_INIT_PREV && p->init != MOLT_INIT_LINEAR) return fail(MOLT_EINVAL, "unknown init");
   if (p->fixed_iters < 0) return fail(MOLT_EINVAL, "fixed_iters must be >= 0");
+  if (p->model != MOLT_MODEL_CH && p->model != MOLT_MODEL_VCH) return fail(MOLT_EINVAL, "unknown model");
   if (p->fixed_iters == 0 && (p->max_iter < 1 || !(p->tol >= 0))) return fail(MOLT_EINVAL, "need max_iter >= 1 and tol >= 0");
   return MOLT_OK;
 }
@@ -467,6 +542,34 @@ static int32_t check_params(const molt_ch_params* p) {
 // --------------------------------------------------------------------------
 // batched instances
 // --------------------------------------------------------------------------
+#define MOLT_BATCH_PREC(call) (prec == MOLT_F64 ? call##_f64 : call##_f32)
+static hipError_t launch_batch_y(int prec, int K, int M, bool per, int pass, bool fin, const SlotDesc* sd,
+                                 const SlotCtl* ctl, const BlkMap* map, int nblk, hipStream_t s) {
+  return MOLT_BATCH_PREC(launch_batch_y)(K, M, per, pass, fin, sd, ctl, map, nblk, s);
+}
+static hipError_t launch_batch_comb(int prec, int pass, const SlotDesc* sd, const SlotCtl* ctl, const BlkMap* map,
+                                    int nblk, hipStream_t s) {
+  return MOLT_BATCH_PREC(launch_batch_comb)(pass, sd, ctl, map, nblk, s);
+}
+static hipError_t launch_batch_x(int prec, int K, int M, bool per, int pass, const SlotDesc* sd, const SlotCtl* ctl,
+                                 const BlkMap* map, int nblk, hipStream_t s) {
+  return MOLT_BATCH_PREC(launch_batch_x)(K, M, per, pass, sd, ctl, map, nblk, s);
+}
+static hipError_t launch_batch_tail(int prec, const SlotDesc* sd, SlotCtl* ctl, const BlkMap* slots, int nslots,
+                                    const BlkMap* pmap, int npblk, hipStream_t s) {
+  return MOLT_BATCH_PREC(launch_batch_tail)(sd, ctl, slots, nslots, pmap, npblk, s);
+}
+static hipError_t launch_batch_react(int prec, const SlotDesc* sd, const SlotCtl* ctl, const BlkMap* pmap, int npblk,
+                                     hipStream_t s) {
+  return MOLT_BATCH_PREC(launch_batch_react)(sd, ctl, pmap, npblk, s);
+}
+static hipError_t launch_batch_init(int prec, const SlotDesc* sd, SlotCtl* ctl, int nslots, hipStream_t s) {
+  return MOLT_BATCH_PREC(launch_batch_init)(sd, ctl, nslots, s);
+}
+static hipError_t launch_batch_count(int prec, const SlotCtl* ctl, int nslots, int* out, hipStream_t s) {
+  return MOLT_BATCH_PREC(launch_batch_count)(ctl, nslots, out, s);
+}
+#undef MOLT_BATCH_PREC
 struct BatchGroup {
   int K, M, per;
   size_t off;  // first map entry
@@ -486,6 +589,7 @@ struct BatchPlan {
 
 // Block maps of the slots in `act` (ascending): per-group ranges of one map.
 struct BatchMaps {
+  bool any_vch = false;  // a vector-model slot is listed: the tick runs the reaction pass
   std::vector<BatchGroup> yg, xg;
   size_t comb_off = 0, pt_off = 0, sl_off = 0;
   int comb_n = 0, pt_n = 0, sl_n = 0;
@@ -511,6 +615,8 @@ static void batch_maps(const molt_instance* inst, const std::vector<int>& act, i
   B.yg.clear();
   B.xg.clear();
   B.map.clear();
+  B.any_vch = false;
+  for (int i : act) B.any_vch = B.any_vch || inst[i].params.model == MOLT_MODEL_VCH;
   std::vector<BlkMap>& m = B.map;
   const int ks[4] = {4, 8, 16, 32};
   for (int kk = 0; kk < 3; ++kk)
@@ -523,7 +629,7 @@ static void batch_maps(const molt_instance* inst, const std::vector<int>& act, i
         if (ypass_pick_k(gr.ny, prec) != ks[kk]) continue;
         int nth, nseg;
         ypass_shape(prec, gr.ny, &nth, &nseg);
-        const int nb = ((gr.nx + 63) / 64) * nseg;
+        const int nb = ((gr.nx + 63) / 64) * nseg * ncomp_of(&inst[i].params);
         for (int b = 0; b < nb; ++b) m.push_back(BlkMap{i, b});
       }
       g.nblk = (int)(m.size() - g.off);
@@ -531,7 +637,7 @@ static void batch_maps(const molt_instance* inst, const std::vector<int>& act, i
     }
   B.comb_off = m.size();
   for (int i : act) {
-    const int nb = 2 * ((inst[i].grid.nx + 63) / 64);
+    const int nb = 2 * ((inst[i].grid.nx + 63) / 64) * ncomp_of(&inst[i].params);
     for (int b = 0; b < nb; ++b) m.push_back(BlkMap{i, b});
   }
   B.comb_n = (int)(m.size() - B.comb_off);
@@ -545,7 +651,8 @@ static void batch_maps(const molt_instance* inst, const std::vector<int>& act, i
           const int K = xpass_pick_k(gr.nx, prec);
           if (K != ks[kk]) continue;
           const int lpb = 256 / xpass_tl(gr.nx, K);
-          const int nb = (gr.ny + lpb - 1) / lpb;
+          const int lines = gr.ny * ncomp_of(&inst[i].params);
+          const int nb = (lines + lpb - 1) / lpb;
           for (int b = 0; b < nb; ++b) m.push_back(BlkMap{i, b});
         }
         g.nblk = (int)(m.size() - g.off);
@@ -578,7 +685,8 @@ static int32_t batch_plan(const molt_instance* inst, int count, BatchPlan& P) {
   for (int i = 0; i < count; ++i) {
     const int32_t rc = check_instance(inst[i], prec);
     if (rc != MOLT_OK) return fail(rc, "instance " + std::to_string(i) + ": " + g_err);
-    P.lay[i] = ch_layout(&inst[i].grid, prec);
+    const int nc = ncomp_of(&inst[i].params);
+    P.lay[i] = ch_layout(&inst[i].grid, prec, nc);
     P.slot_off[i] = off;
     off += al256(P.lay[i].total);
     P.rec_first[i] = P.nrec;
@@ -593,7 +701,7 @@ static int32_t batch_plan(const molt_instance* inst, int count, BatchPlan& P) {
     const int ycols = (gr.nx + 63) / 64;
     const int K = xpass_min_k(gr.nx, prec);
     const int lpb = 256 / xpass_tl(gr.nx, K);
-    nmap += (size_t)ycols * nseg + 2 * (size_t)ycols + (size_t)((gr.ny + lpb - 1) / lpb) +
+    nmap += ((size_t)ycols * nseg + 2 * (size_t)ycols + (size_t)((gr.ny + lpb - 1) / lpb)) * nc +
             (size_t)diag_blocks((size_t)gr.nx * gr.ny) + 1;
   }
   if (nmap > 0x7fffffffULL) return fail(MOLT_EUNSUPPORTED, "batch too large");
@@ -658,7 +766,9 @@ static void fill_slot(const molt_instance& in, const Layout& L, char* w, molt_st
   const int K = xpass_pick_k(g.nx, prec);
   d.tlx = xpass_tl(g.nx, K);
   d.vecx = ((size_t)g.nx * esz) % 16 == 0 && (uintptr_t)in.d_u % 16 == 0 && (uintptr_t)w % 16 == 0;
-  d.xblocks = (g.ny + 256 / d.tlx - 1) / (256 / d.tlx);
+  d.model = p.model;
+  d.ncomp = ncomp_of(&p);
+  d.xblocks = (g.ny * d.ncomp + 256 / d.tlx - 1) / (256 / d.tlx);
   ypass_shape(prec, g.ny, &d.ynth, &d.ynseg);
   d.yk = ypass_pick_k(g.ny, prec);
   d.ycols = (g.nx + 63) / 64;
@@ -668,6 +778,7 @@ static void fill_slot(const molt_instance& in, const Layout& L, char* w, molt_st
 static hipError_t batch_tick(int prec, const BatchMaps& B, const SlotDesc* sd, SlotCtl* ctl, const BlkMap* map,
                              hipStream_t s) {
   hipError_t e;
+  if (B.any_vch && (e = launch_batch_react(prec, sd, ctl, map + B.pt_off, B.pt_n, s)) != hipSuccess) return e;
   for (int pass = 1; pass <= 3; pass += 2) {
     for (const BatchGroup& g : B.yg)
       if ((e = launch_batch_y(prec, g.K, g.M, g.per != 0, pass, false, sd, ctl, map + g.off, g.nblk, s)) != hipSuccess)
@@ -690,7 +801,7 @@ static hipError_t capture_round(int prec, const BatchMaps& B, const SlotDesc* sd
   hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed);
   if (e != hipSuccess) return e;
   for (int k = 0; k < ticks && e == hipSuccess; ++k) e = batch_tick(prec, B, sd, ctl, map, s);
-  if (e == hipSuccess) e = launch_batch_count(ctl, count, dcnt, s);
+  if (e == hipSuccess) e = launch_batch_count(prec, ctl, count, dcnt, s);
   const hipError_t e2 = hipStreamEndCapture(s, &graph);
   if (e == hipSuccess) e = e2;
   if (e == hipSuccess) e = hipGraphInstantiate(exec, graph, nullptr, nullptr, 0);
@@ -722,7 +833,7 @@ static int32_t solve_batch_impl(const molt_instance* inst, int count, void* d_wo
   HIPCHK(hipMemcpyAsync(sd, descs.data(), (size_t)count * sizeof(SlotDesc), hipMemcpyHostToDevice, s));
   if (!B.map.empty())
     HIPCHK(hipMemcpyAsync(map, B.map.data(), B.map.size() * sizeof(BlkMap), hipMemcpyHostToDevice, s));
-  HIPCHK(launch_batch_init(sd, ctl, count, s));
+  HIPCHK(launch_batch_init(prec, sd, ctl, count, s));
 
   const int ticks = g_batch_ticks;
   const bool use_graph = g_batch_graph && s != nullptr && !g_prof_on;
@@ -757,7 +868,7 @@ static int32_t solve_batch_impl(const molt_instance* inst, int count, void* d_wo
       e = hipGraphLaunch(exec, s);
     } else {
       for (int k = 0; k < ticks && e == hipSuccess; ++k) e = batch_tick(prec, B, sd, ctl, map, s);
-      if (e == hipSuccess) e = launch_batch_count(ctl, count, dcnt, s);
+      if (e == hipSuccess) e = launch_batch_count(prec, ctl, count, dcnt, s);
     }
     if (e == hipSuccess) e = hipMemcpyAsync(&pin[b], dcnt, sizeof(int), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipEventRecord(ev[b], s);
@@ -946,7 +1057,7 @@ int32_t mol_t_helmholtz_sweep(const molt_grid* g, int32_t axis, double alpha, in
 size_t ch_workspace_bytes(const molt_grid* g, const molt_ch_params* p) {
   g_err.clear();
   if (check_params(p) != MOLT_OK || check_grid(g, p->precision) != MOLT_OK) return 0;
-  return ch_layout(g, p->precision).total;
+  return ch_layout(g, p->precision, ncomp_of(p)).total;
 }
 
 int32_t ch_step(const molt_grid* g, const molt_ch_params* p, void* d_u, void* d_u_prev, void* d_work,
@@ -969,7 +1080,7 @@ int32_t ch_solve(const molt_grid* g, const molt_ch_params* p, void* d_u, int64_t
   rc = check_grid(g, p->precision);
   if (rc != MOLT_OK) return rc;
   if (!d_u || nsteps < 0) return fail(MOLT_EINVAL, "d_u is NULL or nsteps < 0");
-  const Layout L = ch_layout(g, p->precision);
+  const Layout L = ch_layout(g, p->precision, ncomp_of(p));
   if (!d_work || work_bytes < L.total) return fail(MOLT_EWORKSPACE, "workspace smaller than ch_workspace_bytes()");
   void* hist = (char*)d_work + L.fld[F_HIST];
   int32_t status = MOLT_OK;

@@ -51,6 +51,7 @@ struct DevState {
   double tol;
   double last_resid;
   double mass, energy;
+  double mass2;                   // vector model: mass of the second component
 };
 
 // Arguments of the pass kernels (pointers are device pointers of element type T,
@@ -82,7 +83,9 @@ struct YFused {
 enum SlotPhase { PH_R = 0, PH_IT = 1, PH_IDLE = 2 };
 
 // workspace fields of one problem
-enum { F_R = 0, F_DL, F_W, F_A1, F_B1, F_C, F_Q, F_M, F_N, F_HIST, F_COUNT };
+// (vector model: every field holds both components; F_E, F_LIN hold the
+// reaction and linear parts of the iterate, empty for Cahn-Hilliard)
+enum { F_R = 0, F_DL, F_W, F_A1, F_B1, F_C, F_Q, F_M, F_N, F_HIST, F_E, F_LIN, F_COUNT };
 
 struct SlotCtl {  // mutable control of one slot (device)
   int phase;      // SlotPhase
@@ -109,7 +112,9 @@ struct SlotDesc {          // constants of one slot, built on the host
   int32_t stepper, init, nsteps, max_iter;
   int32_t fixed, tlx, vecx, xblocks;  // x-pass: threads per row, 16-byte access, blocks
   int32_t ynth, ynseg, ycols, dblocks;  // y-pass: threads per column, segments, 64-column strips
-  int32_t yk, pad_;                     // y-pass nodes per thread
+  int32_t yk;                           // y-pass nodes per thread
+  int32_t model, ncomp;                 // MOLT_MODEL_*, field components (1 or 2)
+  int32_t pad_;
 };
 
 // one block of a batched launch: (slot, block index within the slot)

@@ -1,10 +1,38 @@
 // molt_kernels.hip -- HIP kernels (gfx950 / CDNA4) of one problem: the line
 // pass kernels, the fused y-pass, pointwise and bookkeeping kernels, and
 // their launchers.  The device bodies live in molt_device.h.
+//
+// The file is compiled four times, once per precision (MOLT_PREC_F64 selects
+// double) and pass direction (MOLT_PART_X: x-passes and the shape table;
+// MOLT_PART_Y: y-passes and the pointwise kernels), so the template-heavy
+// parts build in parallel; the launchers carry the precision in their names
+// and the host dispatches.
 #include "molt_device.h"
+
+#ifdef MOLT_PREC_F64
+#define MOLT_KT double
+#define MOLT_KFN(name) name##_f64
+#else
+#define MOLT_KT float
+#define MOLT_KFN(name) name##_f32
+#endif
+#if !defined(MOLT_PART_X) && !defined(MOLT_PART_Y)
+#error "define MOLT_PART_X or MOLT_PART_Y"
+#endif
+#if defined(MOLT_PART_X) && !defined(MOLT_PREC_F64)
+#define MOLT_PART_COMMON 1  // precision-independent helpers: one translation unit only
+#endif
 
 namespace molt {
 
+// helpers defined once (MOLT_PART_COMMON) and used by every part
+int xpass_max_n(int prec);
+int xpass_pick_k(int n, int prec);
+int ypass_pick_k(int n, int prec);
+int xpass_tl(int n, int K);
+int diag_blocks(size_t n);
+
+template <typename T>
 __global__ void __launch_bounds__(256) residual_close_kernel(const double* partials, int nblocks, DevState* st) {
   residual_close_body(partials, nblocks, st);
 }
@@ -12,7 +40,8 @@ __global__ void __launch_bounds__(256) residual_close_kernel(const double* parti
 template <typename T, int PI, int K, int M, bool PER>
 __global__ void MOLT_PASS_ATTR xpass_kernel(const LineCoef c, const PassArgs a, DevState* st, int nlines, int TL,
                                             double* rpart, int vec) {
-  xpass_body<T, PI, K, M, PER>(c, a, st, nlines, TL, rpart, vec, blockIdx.x);
+  __shared__ T smem[ProgOf<PI, T>::type::F * XRow<T, K>::PADDED];
+  xpass_body<T, PI, K, M, PER>(c, a, st, nlines, TL, rpart, vec, blockIdx.x, smem);
 }
 
 template <typename T, int PI, int K, int M, bool PER>
@@ -217,9 +246,11 @@ __global__ void __launch_bounds__(64 * kRGF) yfused_kernel(const LineCoef c, con
   }
 }
 
+#ifdef MOLT_PART_COMMON
 __global__ void __launch_bounds__(256) zero_ints_kernel(int* p, int n) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
 }
+#endif
 
 // pointwise program with the identity in place of the sweep (the y-direction
 // of a one-dimensional problem)
@@ -242,6 +273,7 @@ __global__ void __launch_bounds__(256) pointwise_kernel(const PassArgs a, DevSta
 // --------------------------------------------------------------------------
 // step bookkeeping
 // --------------------------------------------------------------------------
+#ifdef MOLT_PART_COMMON
 __global__ void state_init_kernel(DevState* st, double tol, int max_iter, int fixed) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     st->resid_bits = 0ull;
@@ -255,8 +287,10 @@ __global__ void state_init_kernel(DevState* st, double tol, int max_iter, int fi
     st->last_resid = 0.0;
     st->mass = 0.0;
     st->energy = 0.0;
+    st->mass2 = 0.0;
   }
 }
+#endif
 
 template <typename T>
 __global__ void __launch_bounds__(256) copy_kernel(T* dst, const T* src, size_t n) {
@@ -277,6 +311,26 @@ __global__ void __launch_bounds__(256) diag_kernel(const T* u, int nx, int ny, i
   diag_body<T>(u, nx, ny, bc, hx, hy, eps, partials, blockIdx.x, gridDim.x);
 }
 
+template <typename T>
+__global__ void __launch_bounds__(256) diag_vch_kernel(const T* u, int nx, int ny, int bc, double hx, double hy,
+                                                       double eps, double* partials) {
+  diag_vch_body<T>(u, nx, ny, bc, hx, hy, eps, partials, blockIdx.x, gridDim.x);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) diag_vch_final_kernel(const double* partials, int nblocks, double area,
+                                                             DevState* st) {
+  diag_vch_final_body(partials, nblocks, area, st);
+}
+
+// vector model: (e, lin) of both components (n nodes per component)
+template <typename T>
+__global__ void __launch_bounds__(256) vch_react_kernel(const PassArgs a, DevState* st, size_t n) {
+  if (st != nullptr && st->done) return;
+  vch_react_body<T>(a, n, (size_t)blockIdx.x * blockDim.x + threadIdx.x, (size_t)gridDim.x * blockDim.x);
+}
+
+template <typename T>
 __global__ void __launch_bounds__(256) diag_final_kernel(const double* partials, int nblocks, double area,
                                                          DevState* st) {
   diag_final_body(partials, nblocks, area, st);
@@ -285,6 +339,7 @@ __global__ void __launch_bounds__(256) diag_final_kernel(const double* partials,
 // --------------------------------------------------------------------------
 // launchers
 // --------------------------------------------------------------------------
+#ifdef MOLT_PART_COMMON
 static int pick_kx(int n, int prec) {
   const int ks[4] = {4, 8, 16, 32};
   const int kmax = prec == MOLT_F64 ? 16 : 32;
@@ -350,6 +405,39 @@ void ypass_shape(int prec, int n, int* nth, int* nseg) {
   *nseg = (*nth + kRG - 1) / kRG;
 }
 
+// fused y-pass work items and record elements (FP32 path)
+size_t yfused_items(int n, int nx, int batch) {
+  const int nth = (n + kKF - 1) / kKF;
+  return (size_t)batch * ((nx + 63) / 64) * ((nth + kRGF - 1) / kRGF);
+}
+size_t yfused_rec_words(int n, int nx, int batch) { return yfused_items(n, nx, batch) * 3 * 2 * 64; }
+
+hipError_t launch_zero_ints(int* p, int n, hipStream_t s) {
+  hipLaunchKernelGGL(zero_ints_kernel, dim3((n + 255) / 256 < 1024 ? (n + 255) / 256 : 1024), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+
+size_t ypass_tot_elems(int prec, int n, int nx, int batch) {
+  (void)prec;
+  const int K = 4;  // the smallest ky: room for every shape
+  const int nth = (n + K - 1) / K;
+  const int nseg = (nth + kRG - 1) / kRG;
+  return (size_t)2 * 2 * nseg * nx * batch;  // F <= 2 fields, 2 directions, one entry per segment
+}
+
+hipError_t launch_state_init(DevState* st, double tol, int max_iter, int fixed, hipStream_t s) {
+  hipLaunchKernelGGL(state_init_kernel, dim3(1), dim3(64), 0, s, st, tol, max_iter, fixed);
+  return hipGetLastError();
+}
+
+int diag_blocks(size_t n) {
+  size_t b = (n + 255) / 256;
+  if (b > 1024) b = 1024;
+  return (int)(b < 1 ? 1 : b);
+}
+#endif  // MOLT_PART_COMMON
+
+#ifdef MOLT_PART_X
 // 16-byte vector access is used when every field pointer is 16-byte aligned and
 // rows are a whole number of 16-byte words
 template <typename T, int PI>
@@ -386,7 +474,7 @@ static hipError_t xpass_k(const LineCoef& c, const PassArgs& a, DevState* st, in
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (g_prof_on) prof_begin(KF_OTHER * 8, s);
-    hipLaunchKernelGGL(residual_close_kernel, dim3(1), dim3(256), 0, s, (const double*)rpart, (int)grid.x, st);
+    hipLaunchKernelGGL((residual_close_kernel<T>), dim3(1), dim3(256), 0, s, (const double*)rpart, (int)grid.x, st);
     if (g_prof_on) prof_end(KF_OTHER * 8, s);
   }
   return hipGetLastError();
@@ -406,45 +494,21 @@ static hipError_t xpass_t(const LineCoef& c, const PassArgs& a, DevState* st, in
   }
 }
 
-hipError_t launch_xpass(int prec, int prog, const LineCoef& c, const PassArgs& a, DevState* st, int nlines,
-                        double* rpart, hipStream_t s) {
-  if (prec == MOLT_F64) {
-    switch (prog) {
-      case PROG_SWEEP: return xpass_t<double, PROG_SWEEP>(c, a, st, nlines, rpart, s, prec);
-      case PROG_RHS: return xpass_t<double, PROG_RHS>(c, a, st, nlines, rpart, s, prec);
-      case PROG_P2: return xpass_t<double, PROG_P2>(c, a, st, nlines, rpart, s, prec);
-      case PROG_P4: return xpass_t<double, PROG_P4>(c, a, st, nlines, rpart, s, prec);
-    }
-  } else {
-    switch (prog) {
-      case PROG_SWEEP: return xpass_t<float, PROG_SWEEP>(c, a, st, nlines, rpart, s, prec);
-      case PROG_RHS: return xpass_t<float, PROG_RHS>(c, a, st, nlines, rpart, s, prec);
-      case PROG_P2: return xpass_t<float, PROG_P2>(c, a, st, nlines, rpart, s, prec);
-      case PROG_P4: return xpass_t<float, PROG_P4>(c, a, st, nlines, rpart, s, prec);
-    }
+hipError_t MOLT_KFN(launch_xpass)(int prog, const LineCoef& c, const PassArgs& a, DevState* st, int nlines,
+                                  double* rpart, hipStream_t s) {
+  constexpr int prec = sizeof(MOLT_KT) == 8 ? MOLT_F64 : MOLT_F32;
+  switch (prog) {
+    case PROG_SWEEP: return xpass_t<MOLT_KT, PROG_SWEEP>(c, a, st, nlines, rpart, s, prec);
+    case PROG_RHS: return xpass_t<MOLT_KT, PROG_RHS>(c, a, st, nlines, rpart, s, prec);
+    case PROG_P2: return xpass_t<MOLT_KT, PROG_P2>(c, a, st, nlines, rpart, s, prec);
+    case PROG_P4: return xpass_t<MOLT_KT, PROG_P4>(c, a, st, nlines, rpart, s, prec);
+    case PROG_P2V: return xpass_t<MOLT_KT, PROG_P2V>(c, a, st, nlines, rpart, s, prec);
   }
   return hipErrorInvalidValue;
 }
+#endif  // MOLT_PART_X
 
-// fused y-pass work items and record elements (FP32 path)
-size_t yfused_items(int n, int nx, int batch) {
-  const int nth = (n + kKF - 1) / kKF;
-  return (size_t)batch * ((nx + 63) / 64) * ((nth + kRGF - 1) / kRGF);
-}
-size_t yfused_rec_words(int n, int nx, int batch) { return yfused_items(n, nx, batch) * 3 * 2 * 64; }
-
-hipError_t launch_zero_ints(int* p, int n, hipStream_t s) {
-  hipLaunchKernelGGL(zero_ints_kernel, dim3((n + 255) / 256 < 1024 ? (n + 255) / 256 : 1024), dim3(256), 0, s, p, n);
-  return hipGetLastError();
-}
-
-size_t ypass_tot_elems(int prec, int n, int nx, int batch) {
-  (void)prec;
-  const int K = 4;  // the smallest ky: room for every shape
-  const int nth = (n + K - 1) / K;
-  const int nseg = (nth + kRG - 1) / kRG;
-  return (size_t)2 * 2 * nseg * nx * batch;  // F <= 2 fields, 2 directions, one entry per segment
-}
+#ifdef MOLT_PART_Y
 
 template <typename T, int PI, int K, int M, bool PER>
 static hipError_t ypass_km(const LineCoef& c, const PassArgs& a, DevState* st, int nx, int batch, T* tot, T* jln,
@@ -566,22 +630,14 @@ static hipError_t ypass_t(const LineCoef& c, const PassArgs& a, DevState* st, in
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_ypass(int prec, int prog, const LineCoef& c, const PassArgs& a, DevState* st, int nx, int batch,
-                        void* tot, void* jln, const YFused* fz, hipStream_t s) {
-  if (prec == MOLT_F64) {
-    switch (prog) {
-      case PROG_SWEEP: return ypass_t<double, PROG_SWEEP>(c, a, st, nx, batch, tot, jln, fz, s);
-      case PROG_RHS: return ypass_t<double, PROG_RHS>(c, a, st, nx, batch, tot, jln, fz, s);
-      case PROG_P1: return ypass_t<double, PROG_P1>(c, a, st, nx, batch, tot, jln, fz, s);
-      case PROG_P3: return ypass_t<double, PROG_P3>(c, a, st, nx, batch, tot, jln, fz, s);
-    }
-  } else {
-    switch (prog) {
-      case PROG_SWEEP: return ypass_t<float, PROG_SWEEP>(c, a, st, nx, batch, tot, jln, fz, s);
-      case PROG_RHS: return ypass_t<float, PROG_RHS>(c, a, st, nx, batch, tot, jln, fz, s);
-      case PROG_P1: return ypass_t<float, PROG_P1>(c, a, st, nx, batch, tot, jln, fz, s);
-      case PROG_P3: return ypass_t<float, PROG_P3>(c, a, st, nx, batch, tot, jln, fz, s);
-    }
+hipError_t MOLT_KFN(launch_ypass)(int prog, const LineCoef& c, const PassArgs& a, DevState* st, int nx, int batch,
+                                  void* tot, void* jln, const YFused* fz, hipStream_t s) {
+  switch (prog) {
+    case PROG_SWEEP: return ypass_t<MOLT_KT, PROG_SWEEP>(c, a, st, nx, batch, tot, jln, fz, s);
+    case PROG_RHS: return ypass_t<MOLT_KT, PROG_RHS>(c, a, st, nx, batch, tot, jln, fz, s);
+    case PROG_P1: return ypass_t<MOLT_KT, PROG_P1>(c, a, st, nx, batch, tot, jln, fz, s);
+    case PROG_P3: return ypass_t<MOLT_KT, PROG_P3>(c, a, st, nx, batch, tot, jln, fz, s);
+    case PROG_P1V: return ypass_t<MOLT_KT, PROG_P1V>(c, a, st, nx, batch, tot, jln, nullptr, s);
   }
   return hipErrorInvalidValue;
 }
@@ -593,64 +649,58 @@ static dim3 grid_1d(size_t n) {
   return dim3((unsigned)b);
 }
 
-hipError_t launch_pointwise(int prec, int prog, const PassArgs& a, DevState* st, size_t nelem, hipStream_t s) {
+hipError_t MOLT_KFN(launch_pointwise)(int prog, const PassArgs& a, DevState* st, size_t nelem, hipStream_t s) {
   dim3 g = grid_1d(nelem);
   if (g_prof_on) prof_begin(KF_POINTWISE * 8 + prog, s);
-  if (prec == MOLT_F64) {
-    if (prog == PROG_P1) hipLaunchKernelGGL((pointwise_kernel<double, PROG_P1>), g, dim3(256), 0, s, a, st, nelem);
-    else if (prog == PROG_P3) hipLaunchKernelGGL((pointwise_kernel<double, PROG_P3>), g, dim3(256), 0, s, a, st, nelem);
-    else return hipErrorInvalidValue;
-  } else {
-    if (prog == PROG_P1) hipLaunchKernelGGL((pointwise_kernel<float, PROG_P1>), g, dim3(256), 0, s, a, st, nelem);
-    else if (prog == PROG_P3) hipLaunchKernelGGL((pointwise_kernel<float, PROG_P3>), g, dim3(256), 0, s, a, st, nelem);
-    else return hipErrorInvalidValue;
-  }
+  if (prog == PROG_P1) hipLaunchKernelGGL((pointwise_kernel<MOLT_KT, PROG_P1>), g, dim3(256), 0, s, a, st, nelem);
+  else if (prog == PROG_P3) hipLaunchKernelGGL((pointwise_kernel<MOLT_KT, PROG_P3>), g, dim3(256), 0, s, a, st, nelem);
+  else if (prog == PROG_P1V) hipLaunchKernelGGL((pointwise_kernel<MOLT_KT, PROG_P1V>), g, dim3(256), 0, s, a, st, nelem);
+  else return hipErrorInvalidValue;
   if (g_prof_on) prof_end(KF_POINTWISE * 8 + prog, s);
   return hipGetLastError();
 }
 
-hipError_t launch_state_init(DevState* st, double tol, int max_iter, int fixed, hipStream_t s) {
-  hipLaunchKernelGGL(state_init_kernel, dim3(1), dim3(64), 0, s, st, tol, max_iter, fixed);
+hipError_t MOLT_KFN(launch_copy)(void* dst, const void* src, size_t n, hipStream_t s) {
+  hipLaunchKernelGGL((copy_kernel<MOLT_KT>), grid_1d(n), dim3(256), 0, s, (MOLT_KT*)dst, (const MOLT_KT*)src, n);
   return hipGetLastError();
 }
 
-hipError_t launch_copy(int prec, void* dst, const void* src, size_t n, hipStream_t s) {
-  if (prec == MOLT_F64)
-    hipLaunchKernelGGL((copy_kernel<double>), grid_1d(n), dim3(256), 0, s, (double*)dst, (const double*)src, n);
-  else
-    hipLaunchKernelGGL((copy_kernel<float>), grid_1d(n), dim3(256), 0, s, (float*)dst, (const float*)src, n);
+hipError_t MOLT_KFN(launch_finalize)(void* u, const void* base, const void* W, size_t n, hipStream_t s) {
+  hipLaunchKernelGGL((finalize_kernel<MOLT_KT>), grid_1d(n), dim3(256), 0, s, (MOLT_KT*)u, (const MOLT_KT*)base,
+                     (const MOLT_KT*)W, n);
   return hipGetLastError();
 }
 
-hipError_t launch_finalize(int prec, void* u, const void* base, const void* W, size_t n, hipStream_t s) {
-  if (prec == MOLT_F64)
-    hipLaunchKernelGGL((finalize_kernel<double>), grid_1d(n), dim3(256), 0, s, (double*)u, (const double*)base,
-                       (const double*)W, n);
-  else
-    hipLaunchKernelGGL((finalize_kernel<float>), grid_1d(n), dim3(256), 0, s, (float*)u, (const float*)base,
-                       (const float*)W, n);
+hipError_t MOLT_KFN(launch_vch_react)(const PassArgs& a, DevState* st, size_t n, hipStream_t s) {
+  dim3 g = grid_1d(n);
+  if (g_prof_on) prof_begin(KF_POINTWISE * 8 + PROG_P1V, s);
+  hipLaunchKernelGGL((vch_react_kernel<MOLT_KT>), g, dim3(256), 0, s, a, st, n);
+  if (g_prof_on) prof_end(KF_POINTWISE * 8 + PROG_P1V, s);
   return hipGetLastError();
 }
 
-int diag_blocks(size_t n) {
-  size_t b = (n + 255) / 256;
-  if (b > 1024) b = 1024;
-  return (int)(b < 1 ? 1 : b);
-}
-
-hipError_t launch_diag(int prec, const void* u, int nx, int ny, int bc, double hx, double hy, double eps,
-                       double* partials, DevState* st, hipStream_t s) {
+hipError_t MOLT_KFN(launch_diag_vch)(const void* u, int nx, int ny, int bc, double hx, double hy, double eps,
+                                     double* partials, DevState* st, hipStream_t s) {
   const int nb = diag_blocks((size_t)nx * ny);
-  if (prec == MOLT_F64)
-    hipLaunchKernelGGL((diag_kernel<double>), dim3(nb), dim3(256), 0, s, (const double*)u, nx, ny, bc, hx, hy, eps,
-                       partials);
-  else
-    hipLaunchKernelGGL((diag_kernel<float>), dim3(nb), dim3(256), 0, s, (const float*)u, nx, ny, bc, hx, hy, eps,
-                       partials);
+  hipLaunchKernelGGL((diag_vch_kernel<MOLT_KT>), dim3(nb), dim3(256), 0, s, (const MOLT_KT*)u, nx, ny, bc, hx, hy, eps,
+                     partials);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(diag_final_kernel, dim3(1), dim3(256), 0, s, (const double*)partials, nb, hx * hy, st);
+  hipLaunchKernelGGL((diag_vch_final_kernel<MOLT_KT>), dim3(1), dim3(256), 0, s, (const double*)partials, nb, hx * hy,
+                     st);
   return hipGetLastError();
 }
+
+hipError_t MOLT_KFN(launch_diag)(const void* u, int nx, int ny, int bc, double hx, double hy, double eps,
+                                 double* partials, DevState* st, hipStream_t s) {
+  const int nb = diag_blocks((size_t)nx * ny);
+  hipLaunchKernelGGL((diag_kernel<MOLT_KT>), dim3(nb), dim3(256), 0, s, (const MOLT_KT*)u, nx, ny, bc, hx, hy, eps,
+                     partials);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((diag_final_kernel<MOLT_KT>), dim3(1), dim3(256), 0, s, (const double*)partials, nb, hx * hy, st);
+  return hipGetLastError();
+}
+#endif  // MOLT_PART_Y
 
 }  // namespace molt

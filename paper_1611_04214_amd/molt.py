@@ -20,6 +20,9 @@ MOLT_EINVAL, MOLT_EUNSUPPORTED, MOLT_EHIP, MOLT_EWORKSPACE = -1, -2, -3, -4
 MOLT_BC_PERIODIC, MOLT_BC_NEUMANN, MOLT_BC_DIRICHLET = 0, 1, 2
 MOLT_BE, MOLT_BDF2 = 0, 1
 MOLT_INIT_PREV, MOLT_INIT_LINEAR = 0, 1
+MOLT_MODEL_CH, MOLT_MODEL_VCH = 0, 1
+#: sigma0 of the vector model (the Hessian of W at its minima is 18 I)
+VCH_SIGMA0 = 18.0
 MOLT_F64, MOLT_F32 = 0, 1
 
 #: every symbol include/molt.h declares
@@ -31,7 +34,7 @@ MOLT_TUNE_CLASSES = 7
 MOLT_OPT_FUSED_Y_MIN_ITEMS, MOLT_OPT_BATCH_TICKS, MOLT_OPT_BATCH_GRAPH = 1, 2, 3
 
 KERNEL_FAMILIES = ("xpass", "ytot", "ycomb", "yfin", "pointwise", "other")
-PROGRAMS = ("sweep", "rhs", "P1", "P2", "P3", "P4")
+PROGRAMS = ("sweep", "rhs", "P1", "P2", "P3", "P4", "P1v", "P2v")
 
 
 def kind_name(kind: int) -> str:
@@ -50,13 +53,15 @@ class molt_ch_params(ctypes.Structure):
     _fields_ = [("eps", ctypes.c_double), ("dt", ctypes.c_double), ("tol", ctypes.c_double),
                 ("sigma0", ctypes.c_double), ("stepper", ctypes.c_int32), ("max_iter", ctypes.c_int32),
                 ("init", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("fixed_iters", ctypes.c_int32), ("have_prev", ctypes.c_int32)]
+                ("fixed_iters", ctypes.c_int32), ("have_prev", ctypes.c_int32),
+                ("model", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class molt_step_info(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("converged", ctypes.c_int32),
                 ("residual", ctypes.c_double), ("mass", ctypes.c_double), ("energy", ctypes.c_double),
-                ("s1", ctypes.c_double), ("s2", ctypes.c_double), ("sigma", ctypes.c_double)]
+                ("s1", ctypes.c_double), ("s2", ctypes.c_double), ("sigma", ctypes.c_double),
+                ("mass2", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -240,8 +245,12 @@ def make_grid(nx: int, ny: int = 1, x0: float = 0.0, x1: float = 1.0, y0: float 
 
 def make_params(eps: float, dt: float, tol: float = 1e-10, stepper: int = MOLT_BE, max_iter: int = 300,
                 init: int = MOLT_INIT_PREV, precision: int = MOLT_F64, fixed_iters: int = 0,
-                have_prev: int = 0, sigma0: float = 2.0) -> molt_ch_params:
-    return molt_ch_params(eps, dt, tol, sigma0, stepper, max_iter, init, precision, fixed_iters, have_prev)
+                have_prev: int = 0, sigma0: float | None = None, model: int = MOLT_MODEL_CH) -> molt_ch_params:
+    """Step parameters; sigma0 defaults to 2 (Cahn-Hilliard) or 18 (vector model)."""
+    if sigma0 is None:
+        sigma0 = VCH_SIGMA0 if model == MOLT_MODEL_VCH else 2.0
+    return molt_ch_params(eps, dt, tol, sigma0, stepper, max_iter, init, precision, fixed_iters, have_prev,
+                          model, 0)
 
 
 def _stream(torch):

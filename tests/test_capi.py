@@ -35,9 +35,9 @@ def test_every_declared_symbol_is_exported(lib):
 def test_struct_layouts_match_header():
     # natural C alignment of the header's structs
     assert ctypes.sizeof(molt.molt_grid) == 48
-    assert ctypes.sizeof(molt.molt_ch_params) == 56
-    assert ctypes.sizeof(molt.molt_step_info) == 56
-    assert ctypes.sizeof(molt.molt_instance) == 120
+    assert ctypes.sizeof(molt.molt_ch_params) == 64
+    assert ctypes.sizeof(molt.molt_step_info) == 64
+    assert ctypes.sizeof(molt.molt_instance) == 128
 
 
 def test_strerror_names_every_status(lib):
