@@ -207,6 +207,50 @@ int32_t ch_solve_batch(const molt_instance* inst, int32_t count, void* d_work, s
                        molt_step_info* per_step, void* stream);
 
 /*
+ * Serving (continuous batching).  A server is a resident batched engine on
+ * one stream: requests are queued in submission order and admitted as soon as
+ * a slot and enough of the server's workspace pool are free (the footprint of
+ * a request is molt_server_footprint: its ch_solve workspace plus its step
+ * records); admitted requests advance together (the ticks of ch_solve_batch)
+ * and leave as soon as their last step ends, freeing their slot and memory
+ * for the next request.  A request's fields stay where the caller put them
+ * (device memory the caller owns and must not touch until the result is
+ * polled); its result is bitwise the same as alone or in any mix.
+ *  molt_server_bytes:  workspace for max_slots slots and a pool of pool_bytes.
+ *  molt_server_create: a server on a non-NULL stream over the caller's
+ *                      workspace (descriptors, control words, block maps, then
+ *                      the pool); allocates two small pinned host buffers.
+ *  molt_server_submit: queue a request (checked like a ch_solve_batch
+ *                      instance; its precision must be the server's;
+ *                      MOLT_EUNSUPPORTED if it can never fit the pool).
+ *  molt_server_run:    admit what fits, then queue `rounds` rounds of ticks
+ *                      (MOLT_OPT_BATCH_TICKS each); the rounds before the last
+ *                      one are retired, their finished requests become
+ *                      results.  Reports the admitted and queued counts.  With
+ *                      nothing admitted or queued it drains and returns.
+ *  molt_server_poll:   move up to max_results finished results out (in the
+ *                      order they finished); returns how many.
+ *  molt_server_destroy: synchronize the stream and release the server.
+ * One thread drives a server; servers on different streams are independent.
+ */
+typedef struct molt_server molt_server;
+typedef struct {
+  int64_t id;            /* the submit id */
+  int32_t status;        /* MOLT_OK or MOLT_NOT_CONVERGED (some step reached max_iter) */
+  int32_t steps;
+  int64_t iters;         /* fixed-point iterations over all steps */
+  molt_step_info last;   /* the last step's report */
+} molt_result;
+size_t molt_server_footprint(const molt_instance* inst);
+size_t molt_server_bytes(int32_t precision, int32_t max_slots, size_t pool_bytes);
+int32_t molt_server_create(int32_t precision, int32_t max_slots, void* d_work, size_t work_bytes, void* stream,
+                           molt_server** out);
+int32_t molt_server_submit(molt_server* server, const molt_instance* inst, int64_t id);
+int32_t molt_server_run(molt_server* server, int32_t rounds, int32_t* active, int32_t* queued);
+int32_t molt_server_poll(molt_server* server, molt_result* out, int32_t max_results);
+int32_t molt_server_destroy(molt_server* server);
+
+/*
  * Line-block shapes (not part of the method; they change only the rounding
  * order of the scans).  Per precision and line-length class (class c holds
  * lines of n <= 128 * 2^c nodes, c = 0..MOLT_TUNE_CLASSES-1, the last class

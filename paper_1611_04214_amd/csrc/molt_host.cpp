@@ -3,6 +3,8 @@
 #include <math.h>
 #include <string.h>
 
+#include <deque>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -941,6 +943,224 @@ static int32_t solve_batch_impl(const molt_instance* inst, int count, void* d_wo
   return status;
 }
 
+// --------------------------------------------------------------------------
+// serving: a resident batched engine that admits requests while others run
+// --------------------------------------------------------------------------
+// map entries one instance can need under any shape of the table
+static size_t map_entries_max(const molt_instance& in, int prec) {
+  const molt_grid& gr = in.grid;
+  const int nc = ncomp_of(&in.params);
+  const int ycols = (gr.nx + 63) / 64;
+  const int lpb = 256 / xpass_tl(gr.nx, xpass_min_k(gr.nx, prec));
+  return ((size_t)ycols * ypass_max_segments(gr.ny) + 2 * (size_t)ycols + (size_t)((gr.ny + lpb - 1) / lpb)) * nc +
+         (size_t)diag_blocks((size_t)gr.nx * gr.ny) + 1;
+}
+
+static size_t footprint(const molt_instance& in, int prec) {
+  return al256(ch_layout(&in.grid, prec, ncomp_of(&in.params)).total) +
+         al256((size_t)in.nsteps * sizeof(molt_step_info));
+}
+
+static size_t server_map_cap(int max_slots, size_t pool_bytes) { return (size_t)max_slots * 64 + pool_bytes / 1024; }
+
+}  // namespace molt
+
+struct molt_server {
+  struct Req {
+    int64_t id;
+    molt_instance inst;
+  };
+  struct Slot {
+    bool used = false;
+    int64_t id = 0;
+    long long admit_round = 0;
+    size_t off = 0, bytes = 0, map_need = 0;
+  };
+  int prec = 0, max_slots = 0;
+  hipStream_t s = nullptr, cs = nullptr;  // work stream, record-copy stream
+  char* w = nullptr;
+  molt::SlotDesc* sd = nullptr;
+  molt::SlotCtl* ctl = nullptr;
+  molt::BlkMap* map = nullptr;
+  size_t map_cap = 0, map_used = 0;
+  size_t pool_off = 0, pool_end = 0;
+  std::map<size_t, size_t> free_;  // pool: offset -> size of each free range
+  std::vector<Slot> slots;
+  std::vector<molt_instance> insts;  // by slot
+  std::vector<int> free_slots;
+  std::deque<Req> queue;
+  std::deque<molt_result> done;
+  molt::BatchMaps B;
+  bool dirty = false;
+  // pipeline of rounds: snapshots of the control words, one pinned buffer per round in flight
+  molt::SlotCtl* pin[2] = {nullptr, nullptr};
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  // pinned staging of uploads: one descriptor and control word per slot (a slot
+  // is reused only after its rounds are retired), two map buffers with events
+  molt::SlotDesc* up_desc = nullptr;
+  molt::SlotCtl* up_ctl = nullptr;
+  molt::BlkMap* up_map[2] = {nullptr, nullptr};
+  hipEvent_t ev_map[2] = {nullptr, nullptr};
+  int map_k = 0;
+  long long round_of[2] = {-1, -1};
+  long long rounds = 0;
+  int inflight = 0, head = 0;
+};
+
+namespace molt {
+
+static bool pool_alloc(molt_server* S, size_t bytes, size_t* off) {
+  for (auto it = S->free_.begin(); it != S->free_.end(); ++it) {
+    if (it->second < bytes) continue;
+    *off = it->first;
+    const size_t rest = it->second - bytes;
+    const size_t roff = it->first + bytes;
+    S->free_.erase(it);
+    if (rest) S->free_[roff] = rest;
+    return true;
+  }
+  return false;
+}
+
+static void pool_free(molt_server* S, size_t off, size_t bytes) {
+  auto it = S->free_.emplace(off, bytes).first;
+  auto nx = std::next(it);
+  if (nx != S->free_.end() && it->first + it->second == nx->first) {
+    it->second += nx->second;
+    S->free_.erase(nx);
+  }
+  if (it != S->free_.begin()) {
+    auto pv = std::prev(it);
+    if (pv->first + pv->second == it->first) {
+      pv->second += it->second;
+      S->free_.erase(it);
+    }
+  }
+}
+
+// retire the oldest round in flight: finished slots -> results, memory freed
+static int32_t server_retire(molt_server* S) {
+  const int b = S->head;
+  HIPCHK(hipEventSynchronize(S->ev[b]));
+  if (g_prof_on) prof_drain();
+  const long long r = S->round_of[b];
+  for (int i = 0; i < S->max_slots; ++i) {
+    molt_server::Slot& sl = S->slots[i];
+    if (!sl.used || sl.admit_round > r || S->pin[b][i].phase != PH_IDLE) continue;
+    const molt_instance& in = S->insts[i];
+    std::vector<molt_step_info> rec((size_t)in.nsteps);
+    const Layout L = ch_layout(&in.grid, S->prec, ncomp_of(&in.params));
+    molt_result res;
+    memset(&res, 0, sizeof(res));
+    res.id = sl.id;
+    res.steps = (int32_t)in.nsteps;
+    res.status = MOLT_OK;
+    if (in.nsteps > 0) {
+      HIPCHK(hipMemcpyAsync(rec.data(), S->w + sl.off + al256(L.total), rec.size() * sizeof(molt_step_info),
+                            hipMemcpyDeviceToHost, S->cs));
+      HIPCHK(hipStreamSynchronize(S->cs));
+      for (const molt_step_info& x : rec) {
+        res.iters += x.iters;
+        if (!x.converged) res.status = MOLT_NOT_CONVERGED;
+      }
+      res.last = rec.back();
+    }
+    S->done.push_back(res);
+    pool_free(S, sl.off, sl.bytes);
+    S->map_used -= sl.map_need;
+    sl = molt_server::Slot();
+    S->free_slots.push_back(i);
+    S->dirty = true;
+  }
+  S->head = 1 - b;
+  --S->inflight;
+  return MOLT_OK;
+}
+
+// admit queued requests (in order) while a slot, pool memory and map room are free
+static int32_t server_admit(molt_server* S) {
+  while (!S->queue.empty() && !S->free_slots.empty()) {
+    const molt_server::Req& q = S->queue.front();
+    const size_t need = footprint(q.inst, S->prec), mneed = map_entries_max(q.inst, S->prec);
+    if (S->map_used + mneed > S->map_cap) break;
+    size_t off = 0;
+    if (!pool_alloc(S, need, &off)) break;
+    const int i = S->free_slots.back();
+    S->free_slots.pop_back();
+    molt_server::Slot& sl = S->slots[i];
+    sl.used = true;
+    sl.id = q.id;
+    sl.admit_round = S->rounds;
+    sl.off = off;
+    sl.bytes = need;
+    sl.map_need = mneed;
+    S->map_used += mneed;
+    S->insts[i] = q.inst;
+    const Layout L = ch_layout(&q.inst.grid, S->prec, ncomp_of(&q.inst.params));
+    SlotDesc& d = S->up_desc[i];
+    fill_slot(q.inst, L, S->w + off, (molt_step_info*)(S->w + off + al256(L.total)), d);
+    SlotCtl& c = S->up_ctl[i];
+    c.phase = q.inst.nsteps > 0 ? PH_R : PH_IDLE;
+    c.step = 0;
+    c.var = 0;
+    c.pad = 0;
+    // stream order puts these after every round already queued
+    HIPCHK(hipMemcpyAsync(S->sd + i, &d, sizeof(d), hipMemcpyHostToDevice, S->s));
+    HIPCHK(hipMemcpyAsync(S->ctl + i, &c, sizeof(c), hipMemcpyHostToDevice, S->s));
+    S->queue.pop_front();
+    S->dirty = true;
+  }
+  return MOLT_OK;
+}
+
+static int server_active(const molt_server* S) {
+  int a = 0;
+  for (const molt_server::Slot& sl : S->slots) a += sl.used ? 1 : 0;
+  return a;
+}
+
+static int32_t server_run(molt_server* S, int nrounds) {
+  for (int r = 0; r < nrounds; ++r) {
+    if (S->inflight == 2) {
+      const int32_t rc = server_retire(S);
+      if (rc != MOLT_OK) return rc;
+    }
+    int32_t rc = server_admit(S);
+    if (rc != MOLT_OK) return rc;
+    if (server_active(S) == 0) {
+      while (S->inflight > 0)
+        if ((rc = server_retire(S)) != MOLT_OK) return rc;
+      rc = server_admit(S);
+      if (rc != MOLT_OK) return rc;
+      if (server_active(S) == 0) return MOLT_OK;
+    }
+    if (S->dirty) {
+      std::vector<int> act;
+      for (int i = 0; i < S->max_slots; ++i)
+        if (S->slots[i].used) act.push_back(i);
+      batch_maps(S->insts.data(), act, S->prec, S->B);
+      if (S->B.map.size() > S->map_cap) return fail(MOLT_EHIP, "internal: server maps exceed their area");
+      const int mb = S->map_k & 1;
+      HIPCHK(hipEventSynchronize(S->ev_map[mb]));  // the upload that last used this buffer
+      memcpy(S->up_map[mb], S->B.map.data(), S->B.map.size() * sizeof(BlkMap));
+      HIPCHK(hipMemcpyAsync(S->map, S->up_map[mb], S->B.map.size() * sizeof(BlkMap), hipMemcpyHostToDevice, S->s));
+      HIPCHK(hipEventRecord(S->ev_map[mb], S->s));
+      ++S->map_k;
+      S->dirty = false;
+    }
+    const int b = (S->head + S->inflight) & 1;
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < g_batch_ticks && e == hipSuccess; ++k) e = batch_tick(S->prec, S->B, S->sd, S->ctl, S->map, S->s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(S->pin[b], S->ctl, (size_t)S->max_slots * sizeof(SlotCtl), hipMemcpyDeviceToHost, S->s);
+    if (e == hipSuccess) e = hipEventRecord(S->ev[b], S->s);
+    if (e != hipSuccess) return fail(MOLT_EHIP, std::string("server round: ") + hipGetErrorString(e));
+    S->round_of[b] = S->rounds++;
+    ++S->inflight;
+  }
+  return MOLT_OK;
+}
+
 }  // namespace molt
 
 using namespace molt;
@@ -1211,6 +1431,125 @@ int32_t ch_solve_batch(const molt_instance* inst, int32_t count, void* d_work, s
                        molt_step_info* per_step, void* stream) {
   g_err.clear();
   return solve_batch_impl(inst, count, d_work, work_bytes, per_step, (hipStream_t)stream);
+}
+
+size_t molt_server_footprint(const molt_instance* inst) {
+  g_err.clear();
+  if (!inst || check_instance(*inst, inst->params.precision) != MOLT_OK) return 0;
+  return footprint(*inst, inst->params.precision);
+}
+
+size_t molt_server_bytes(int32_t precision, int32_t max_slots, size_t pool_bytes) {
+  g_err.clear();
+  if ((precision != MOLT_F64 && precision != MOLT_F32) || max_slots < 1 || max_slots > 65535 || pool_bytes == 0)
+    return 0;
+  return al256((size_t)max_slots * sizeof(SlotDesc)) + al256((size_t)max_slots * sizeof(SlotCtl)) +
+         al256(server_map_cap(max_slots, pool_bytes) * sizeof(BlkMap)) + al256(pool_bytes);
+}
+
+int32_t molt_server_create(int32_t precision, int32_t max_slots, void* d_work, size_t work_bytes, void* stream,
+                           molt_server** out) {
+  g_err.clear();
+  if (!out) return fail(MOLT_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!stream) return fail(MOLT_EINVAL, "a server needs a non-default stream");
+  const size_t fixed = molt_server_bytes(precision, max_slots, 256);
+  if (fixed == 0) return fail(MOLT_EINVAL, "bad precision or max_slots");
+  if (!d_work || work_bytes < fixed + 256) return fail(MOLT_EWORKSPACE, "workspace too small for a server");
+  // pool = what is left after the descriptors, control words and maps
+  size_t pool = work_bytes - fixed;
+  while (pool > 256 && molt_server_bytes(precision, max_slots, pool) > work_bytes) pool -= 4096 < pool ? 4096 : 1;
+  molt_server* S = new molt_server();
+  S->prec = precision;
+  S->max_slots = max_slots;
+  S->s = (hipStream_t)stream;
+  S->w = (char*)d_work;
+  size_t off = 0;
+  S->sd = (SlotDesc*)(S->w + off);
+  off += al256((size_t)max_slots * sizeof(SlotDesc));
+  S->ctl = (SlotCtl*)(S->w + off);
+  off += al256((size_t)max_slots * sizeof(SlotCtl));
+  S->map = (BlkMap*)(S->w + off);
+  S->map_cap = server_map_cap(max_slots, pool);
+  off += al256(S->map_cap * sizeof(BlkMap));
+  S->pool_off = off;
+  S->pool_end = work_bytes & ~(size_t)255;
+  if (S->pool_end <= S->pool_off) {
+    delete S;
+    return fail(MOLT_EWORKSPACE, "workspace too small for a server");
+  }
+  S->free_[S->pool_off] = S->pool_end - S->pool_off;
+  S->slots.resize(max_slots);
+  S->insts.resize(max_slots);
+  for (int i = max_slots - 1; i >= 0; --i) S->free_slots.push_back(i);
+  std::vector<SlotCtl> idle(max_slots);
+  for (SlotCtl& c : idle) c = SlotCtl{PH_IDLE, 0, 0, 0};
+  hipError_t e = hipStreamCreateWithFlags(&S->cs, hipStreamNonBlocking);
+  for (int b = 0; b < 2 && e == hipSuccess; ++b) {
+    e = hipHostMalloc((void**)&S->pin[b], (size_t)max_slots * sizeof(SlotCtl), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&S->ev[b], hipEventDisableTiming);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&S->up_map[b], S->map_cap * sizeof(BlkMap), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&S->ev_map[b], hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(S->ev_map[b], S->s);
+  }
+  if (e == hipSuccess) e = hipHostMalloc((void**)&S->up_desc, (size_t)max_slots * sizeof(SlotDesc), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&S->up_ctl, (size_t)max_slots * sizeof(SlotCtl), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipMemcpyAsync(S->ctl, idle.data(), idle.size() * sizeof(SlotCtl), hipMemcpyHostToDevice, S->s);
+  if (e == hipSuccess) e = hipStreamSynchronize(S->s);
+  if (e != hipSuccess) {
+    molt_server_destroy(S);
+    return fail(MOLT_EHIP, std::string("molt_server_create: ") + hipGetErrorString(e));
+  }
+  *out = S;
+  return MOLT_OK;
+}
+
+int32_t molt_server_submit(molt_server* S, const molt_instance* inst, int64_t id) {
+  g_err.clear();
+  if (!S || !inst) return fail(MOLT_EINVAL, "NULL server or instance");
+  const int32_t rc = check_instance(*inst, S->prec);
+  if (rc != MOLT_OK) return rc;
+  if (footprint(*inst, S->prec) > S->pool_end - S->pool_off || map_entries_max(*inst, S->prec) > S->map_cap)
+    return fail(MOLT_EUNSUPPORTED, "the request does not fit this server's workspace");
+  S->queue.push_back(molt_server::Req{id, *inst});
+  return MOLT_OK;
+}
+
+int32_t molt_server_run(molt_server* S, int32_t rounds, int32_t* active, int32_t* queued) {
+  g_err.clear();
+  if (!S || rounds < 0) return fail(MOLT_EINVAL, "NULL server or negative rounds");
+  const int32_t rc = server_run(S, rounds);
+  if (active) *active = server_active(S);
+  if (queued) *queued = (int32_t)S->queue.size();
+  return rc;
+}
+
+int32_t molt_server_poll(molt_server* S, molt_result* out, int32_t max_results) {
+  g_err.clear();
+  if (!S || (!out && max_results > 0) || max_results < 0) return fail(MOLT_EINVAL, "bad poll arguments");
+  int32_t m = 0;
+  while (m < max_results && !S->done.empty()) {
+    out[m++] = S->done.front();
+    S->done.pop_front();
+  }
+  return m;
+}
+
+int32_t molt_server_destroy(molt_server* S) {
+  g_err.clear();
+  if (!S) return MOLT_OK;
+  if (S->s) (void)hipStreamSynchronize(S->s);
+  for (int b = 0; b < 2; ++b) {
+    if (S->ev[b]) (void)hipEventDestroy(S->ev[b]);
+    if (S->pin[b]) (void)hipHostFree(S->pin[b]);
+    if (S->ev_map[b]) (void)hipEventDestroy(S->ev_map[b]);
+    if (S->up_map[b]) (void)hipHostFree(S->up_map[b]);
+  }
+  if (S->up_desc) (void)hipHostFree(S->up_desc);
+  if (S->up_ctl) (void)hipHostFree(S->up_ctl);
+  if (S->cs) (void)hipStreamDestroy(S->cs);
+  delete S;
+  return MOLT_OK;
 }
 
 }  // extern "C"

@@ -28,8 +28,10 @@ MOLT_F64, MOLT_F32 = 0, 1
 #: every symbol include/molt.h declares
 EXPORTS = ("mol_t_helmholtz_sweep", "molt_sweep_workspace_bytes", "ch_workspace_bytes", "ch_step",
            "ch_solve", "ch_batch_workspace_bytes", "ch_solve_batch", "molt_tune_get", "molt_tune_set",
-           "molt_autotune_workspace_bytes", "molt_autotune", "molt_strerror", "molt_last_error",
-           "molt_profile", "molt_profile_read", "molt_set_option")
+           "molt_autotune_workspace_bytes", "molt_autotune", "molt_server_footprint", "molt_server_bytes",
+           "molt_server_create", "molt_server_submit", "molt_server_run", "molt_server_poll",
+           "molt_server_destroy", "molt_strerror", "molt_last_error", "molt_profile", "molt_profile_read",
+           "molt_set_option")
 MOLT_TUNE_CLASSES = 7
 MOLT_OPT_FUSED_Y_MIN_ITEMS, MOLT_OPT_BATCH_TICKS, MOLT_OPT_BATCH_GRAPH = 1, 2, 3
 
@@ -70,6 +72,11 @@ class molt_step_info(ctypes.Structure):
 class molt_instance(ctypes.Structure):
     _fields_ = [("grid", molt_grid), ("params", molt_ch_params), ("d_u", ctypes.c_void_p),
                 ("nsteps", ctypes.c_int64)]
+
+
+class molt_result(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_int64), ("status", ctypes.c_int32), ("steps", ctypes.c_int32),
+                ("iters", ctypes.c_int64), ("last", molt_step_info)]
 
 
 class molt_prof_entry(ctypes.Structure):
@@ -114,6 +121,20 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.molt_autotune_workspace_bytes.restype = sz
     lib.molt_autotune.argtypes = [i32, i32, vp, sz, vp]
     lib.molt_autotune.restype = i32
+    lib.molt_server_footprint.argtypes = [I]
+    lib.molt_server_footprint.restype = sz
+    lib.molt_server_bytes.argtypes = [i32, i32, sz]
+    lib.molt_server_bytes.restype = sz
+    lib.molt_server_create.argtypes = [i32, i32, vp, sz, vp, ctypes.POINTER(vp)]
+    lib.molt_server_create.restype = i32
+    lib.molt_server_submit.argtypes = [vp, I, ctypes.c_int64]
+    lib.molt_server_submit.restype = i32
+    lib.molt_server_run.argtypes = [vp, i32, pi32, pi32]
+    lib.molt_server_run.restype = i32
+    lib.molt_server_poll.argtypes = [vp, ctypes.POINTER(molt_result), i32]
+    lib.molt_server_poll.restype = i32
+    lib.molt_server_destroy.argtypes = [vp]
+    lib.molt_server_destroy.restype = i32
     lib.molt_strerror.argtypes = [ctypes.c_int32]
     lib.molt_strerror.restype = ctypes.c_char_p
     lib.molt_last_error.argtypes = []
@@ -339,3 +360,63 @@ def solve_batch(specs, work=None, stream=None):
         out.append([recs[k + j] for j in range(int(s[3]))])
         k += int(s[3])
     return st, out
+
+
+# ------------------------------------------------------------------ serving --
+def molt_server_footprint(inst) -> int:
+    return load().molt_server_footprint(ctypes.byref(inst))
+
+
+def molt_server_bytes(precision: int, max_slots: int, pool_bytes: int) -> int:
+    return load().molt_server_bytes(precision, max_slots, pool_bytes)
+
+
+class Server:
+    """A resident continuous-batching server (molt_server_*) on one stream.
+
+    Requests are (grid, params, device tensor, nsteps); the tensor is solved in
+    place and kept referenced here until its result is polled."""
+
+    def __init__(self, precision: int, max_slots: int, pool_bytes: int, stream=None):
+        import torch
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        need = molt_server_bytes(precision, max_slots, pool_bytes)
+        if need == 0:
+            raise MoltError(MOLT_EINVAL, "molt_server_bytes")
+        self.work = workspace(need)
+        self._h = ctypes.c_void_p()
+        _check(load().molt_server_create(precision, max_slots, self.work.data_ptr(), self.work.numel(),
+                                         self.stream.cuda_stream, ctypes.byref(self._h)), "molt_server_create")
+        self._live = {}
+
+    def submit(self, grid: molt_grid, params: molt_ch_params, u, nsteps: int, rid: int) -> None:
+        inst = molt_instance(grid, params, u.data_ptr(), nsteps)
+        _check(load().molt_server_submit(self._h, ctypes.byref(inst), rid), "molt_server_submit")
+        self._live[rid] = u
+
+    def run(self, rounds: int = 1):
+        """Admit what fits and queue `rounds` rounds; returns (admitted, queued)."""
+        a, q = ctypes.c_int32(), ctypes.c_int32()
+        _check(load().molt_server_run(self._h, rounds, ctypes.byref(a), ctypes.byref(q)), "molt_server_run")
+        return a.value, q.value
+
+    def poll(self, max_results: int = 256) -> list:
+        buf = (molt_result * max_results)()
+        m = load().molt_server_poll(self._h, buf, max_results)
+        if m < 0:
+            raise MoltError(m, "molt_server_poll")
+        out = [buf[i] for i in range(m)]
+        for r in out:
+            self._live.pop(r.id, None)
+        return out
+
+    def close(self) -> None:
+        if self._h:
+            load().molt_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -143,3 +143,32 @@ def u0_vch(seed: int, ny: int, nx: int, stream: int = 0) -> np.ndarray:
     c = 0.9 / 3.0 + 0.1 * e / e.sum(axis=0)
     u = VCH_Z.T @ c
     return u.reshape(2, ny, nx)
+
+
+# Served workload: Poisson arrivals of vector-model requests.
+#: seed of the served workload's draws (fifth workload recipe)
+SERVE_SEED = BASE_SEED + 5
+
+
+def serve_requests(count: int, rate: float, seed: int = SERVE_SEED, n_min: int = 128, n_max: int = 2048,
+                   steps_min: int = 10, steps_max: int = 500) -> list:
+    """`count` requests with exponential inter-arrival gaps of mean 1/rate (s):
+    side n = round(exp(U(ln n_min, ln n_max))), steps uniform on
+    {steps_min..steps_max}, eps ~ U[0.005, 0.05], dt ~ U[1e-6, 1e-4], periodic
+    or Neumann and BE or BDF2 each with probability 1/2, domain [0,1]^2, M = 4,
+    tolerance 1e-8; the initial fractions come from u0_vch on stream 100 + i."""
+    gaps = -np.log(np.maximum(uniform(seed, count, 0), 2.0 ** -53)) / rate
+    un, us = uniform(seed, count, 1), uniform(seed, count, 2)
+    ue, ut = uniform(seed, count, 3), uniform(seed, count, 4)
+    ub, uq = uniform(seed, count, 5), uniform(seed, count, 6)
+    lo, hi = np.log(float(n_min)), np.log(float(n_max))
+    t = np.cumsum(gaps)
+    out = []
+    for i in range(count):
+        out.append(dict(id=i, arrival=float(t[i]), n=int(round(float(np.exp(lo + un[i] * (hi - lo))))),
+                        steps=steps_min + int(us[i] * (steps_max - steps_min + 1)),
+                        eps=0.005 + 0.045 * float(ue[i]), dt=1e-6 + (1e-4 - 1e-6) * float(ut[i]),
+                        bc="periodic" if ub[i] < 0.5 else "neumann",
+                        stepper="BE" if uq[i] < 0.5 else "BDF2", M=4, L=1.0, tol=1e-8,
+                        seed=seed, stream=100 + i))
+    return out

@@ -38,6 +38,7 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(molt.molt_ch_params) == 64
     assert ctypes.sizeof(molt.molt_step_info) == 64
     assert ctypes.sizeof(molt.molt_instance) == 128
+    assert ctypes.sizeof(molt.molt_result) == 88
 
 
 def test_strerror_names_every_status(lib):
@@ -177,3 +178,21 @@ def test_tune_table_defaults_and_validation(lib):
     assert molt.molt_autotune_workspace_bytes(molt.MOLT_F32, 100) == 0
     assert molt.molt_autotune_workspace_bytes(molt.MOLT_F32, 1024) > 7 * 1024 * 1024 * 4
     assert molt.molt_autotune(molt.MOLT_F32, 1024, 1, 10) == molt.MOLT_EWORKSPACE
+
+
+def test_server_queries_and_argument_checks(lib):
+    p = molt.make_params(0.02, 1e-5, precision=molt.MOLT_F32, model=molt.MOLT_MODEL_VCH, stepper=molt.MOLT_BDF2)
+    inst = molt.molt_instance(molt.make_grid(128, 128, M=4), p, 4096, 20)
+    fp = molt.molt_server_footprint(inst)
+    p1 = molt.make_params(0.02, 1e-5, precision=molt.MOLT_F32, stepper=molt.MOLT_BDF2)
+    one = molt.ch_workspace_bytes(molt.make_grid(128, 128, M=4), p1)
+    assert fp > 2 * 10 * 128 * 128 * 4 and fp > one  # two components, records
+    assert molt.molt_server_bytes(molt.MOLT_F32, 16, 1 << 20) > 1 << 20
+    assert molt.molt_server_bytes(molt.MOLT_F32, 0, 1 << 20) == 0
+    h = ctypes.c_void_p()
+    # a server needs a stream; a NULL stream or a tiny workspace is rejected before any device work
+    assert lib.molt_server_create(molt.MOLT_F32, 4, 4096, 1 << 30, None, ctypes.byref(h)) == molt.MOLT_EINVAL
+    assert lib.molt_server_create(molt.MOLT_F32, 4, 4096, 100, 1, ctypes.byref(h)) == molt.MOLT_EWORKSPACE
+    assert lib.molt_server_submit(None, ctypes.byref(inst), 1) == molt.MOLT_EINVAL
+    assert lib.molt_server_run(None, 1, None, None) == molt.MOLT_EINVAL
+    assert lib.molt_server_destroy(None) == molt.MOLT_OK
