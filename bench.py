@@ -25,7 +25,11 @@ Also printed on the same JSON line:
                 iterations), on this host's cores;
   batched       the batched workload (256 seeded instances of uneven sizes and
                 parameters, shapes autotuned): ch_solve_batch against one plain
-                ch_solve per instance, steps/s and Gpt-sweeps/s of each.
+                ch_solve per instance, steps/s and Gpt-sweeps/s of each;
+  served        the served workload (Poisson arrivals of vector-model
+                requests): continuous batching against a plain FIFO of
+                ch_solve calls, p50/p99 latency and steps/s of each, also at a
+                sub-capacity rate.
 """
 from __future__ import annotations
 
@@ -97,6 +101,11 @@ def parse():
                     help="steps per instance of the batched workload (0: skip it)")
     ap.add_argument("--batch-count", type=int, default=256, help="instances of the batched workload")
     ap.add_argument("--no-batch-plain", action="store_true", help="skip the plain-path timing of the batch")
+    ap.add_argument("--serve-count", type=int, default=64,
+                    help="requests of the served workload (0: skip it)")
+    ap.add_argument("--serve-rate", type=float, default=200.0, help="mean arrival rate of the served workload (1/s)")
+    ap.add_argument("--serve-sub-count", type=int, default=16,
+                    help="requests of the sub-capacity served trace (0: skip it)")
     ap.add_argument("--no-profile", action="store_true", help="do not time kernels with HIP events")
     ap.add_argument("--fused-min-items", type=int, default=None,
                     help="work items from which the single-kernel y-pass is used (library default 256)")
@@ -178,6 +187,105 @@ def run_batched(args, molt, synth):
                     "bitwise_equal_to_plain": all(torch.equal(xp[i], xs[i]) for i in range(len(inst))),
                     "same_iterations_as_plain": iters_p == iters})
     print(f"batched: {json.dumps(out)}", file=sys.stderr, flush=True)
+    return out
+
+
+def _serve_spec(molt, d):
+    bc = molt.MOLT_BC_PERIODIC if d["bc"] == "periodic" else molt.MOLT_BC_NEUMANN
+    g = molt.make_grid(d["n"], d["n"], 0.0, d["L"], 0.0, d["L"], bc, d["M"])
+    p = molt.make_params(d["eps"], d["dt"], tol=d["tol"], max_iter=20000, init=molt.MOLT_INIT_LINEAR,
+                         stepper=molt.MOLT_BDF2 if d["stepper"] == "BDF2" else molt.MOLT_BE,
+                         precision=molt.MOLT_F32, model=molt.MOLT_MODEL_VCH)
+    return g, p
+
+
+def _serve_trace(molt, reqs, u0, arrivals, pool_bytes):
+    """Real-time serving of a trace: requests are submitted when the wall clock
+    passes their arrival time; returns (latencies, makespan, fields)."""
+    import numpy as np
+    import torch
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    done, fields = {}, {}
+    with torch.cuda.stream(s):
+        srv = molt.Server(molt.MOLT_F32, 128, pool_bytes)
+        t0 = time.perf_counter()
+        k = 0
+        while len(done) < len(reqs):
+            now = time.perf_counter() - t0
+            while k < len(reqs) and arrivals[k] <= now:
+                g, p = _serve_spec(molt, reqs[k])
+                fields[k] = torch.from_numpy(u0[k]).to("cuda:0")
+                srv.submit(g, p, fields[k], reqs[k]["steps"], k)
+                k += 1
+            active, queued = srv.run(1)
+            for r in srv.poll():
+                done[r.id] = time.perf_counter() - t0
+            if active == 0 and queued == 0 and k < len(reqs):
+                time.sleep(max(0.0, arrivals[k] - (time.perf_counter() - t0)))
+        srv.close()
+    torch.cuda.synchronize()
+    makespan = time.perf_counter() - t0
+    lat = np.array([done[i] - arrivals[i] for i in range(len(reqs))])
+    return lat, makespan, fields
+
+
+def run_served(args, molt, synth):
+    """The served workload: Poisson arrivals of vector-model requests (sides
+    128..2048 log-uniform, 10..500 steps), served by continuous batching
+    (molt_server_*) in real time, against a plain FIFO that solves one request
+    at a time with ch_solve on the same GPU (its latencies follow from the
+    measured solve times: start = max(arrival, previous finish)).  Then a
+    sub-capacity trace: the first requests at half the measured served rate."""
+    import numpy as np
+    import torch
+    reqs = synth.serve_requests(args.serve_count, args.serve_rate)
+    u0 = [synth.u0_vch(d["seed"], d["n"], d["n"], d["stream"]).astype(np.float32) for d in reqs]
+    arrivals = [d["arrival"] for d in reqs]
+    free, _ = torch.cuda.mem_get_info()
+    pool = int(min(64 << 30, free // 2))
+    lat, makespan, fields = _serve_trace(molt, reqs, u0, arrivals, pool)
+    steps = sum(d["steps"] for d in reqs)
+    # plain FIFO: measured solve times, queueing from the arrival times
+    durs, same = [], True
+    for i, d in enumerate(reqs):
+        g, p = _serve_spec(molt, d)
+        x = torch.from_numpy(u0[i]).to("cuda:0")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        molt.solve(x, g, p, d["steps"])
+        torch.cuda.synchronize()
+        durs.append(time.perf_counter() - t0)
+        same = same and torch.equal(x.cpu(), fields[i].cpu())
+
+    def fifo(arr, dur):
+        fin, out = 0.0, []
+        for a, du in zip(arr, dur):
+            fin = max(a, fin) + du
+            out.append(fin - a)
+        return np.array(out), fin - arr[0]
+
+    flat, fspan = fifo(arrivals, durs)
+    pct = lambda a, q: round(float(np.percentile(a, q)), 4)
+    out = {"workload": f"{len(reqs)} vector-model requests (three-phase VCH, sigma0 18), Poisson arrivals at "
+                       f"{args.serve_rate}/s, sides 128..2048 log-uniform, 10..500 steps, eps U[0.005,0.05], "
+                       f"dt U[1e-6,1e-4], periodic/Neumann, BE/BDF2, FP32 tol 1e-8",
+           "requests": len(reqs), "total_steps": steps, "pool_bytes": pool,
+           "served": {"p50_s": pct(lat, 50), "p99_s": pct(lat, 99), "makespan_s": round(makespan, 3),
+                      "steps_per_s": round(steps / makespan, 1)},
+           "fifo_plain": {"p50_s": pct(flat, 50), "p99_s": pct(flat, 99), "makespan_s": round(fspan, 3),
+                          "steps_per_s": round(steps / fspan, 1), "busy_s": round(sum(durs), 3)},
+           "bitwise_equal_to_plain": same}
+    if args.serve_sub_count > 0:
+        m = min(args.serve_sub_count, len(reqs))
+        rate = 0.5 * len(reqs) / makespan  # half the measured served throughput (requests/s)
+        sub_arr = [arrivals[i] * args.serve_rate / rate for i in range(m)]
+        slat, _, _ = _serve_trace(molt, reqs[:m], u0[:m], sub_arr, pool)
+        sflat, _ = fifo(sub_arr, durs[:m])
+        out["sub_capacity"] = {"rate_per_s": round(rate, 3), "requests": m,
+                               "served": {"p50_s": pct(slat, 50), "p99_s": pct(slat, 99)},
+                               "fifo_plain": {"p50_s": pct(sflat, 50), "p99_s": pct(sflat, 99)}}
+    print(f"served: {json.dumps(out)}", file=sys.stderr, flush=True)
     return out
 
 
@@ -281,6 +389,7 @@ def main():
             roof["kernel_share_of_gpu_time"] = round(ms / total_ms, 3) if total_ms > 0 else None
 
     batched = run_batched(args, molt, synth) if args.batch_steps > 0 else None
+    served = run_served(args, molt, synth) if args.serve_count > 0 else None
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -322,6 +431,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "batched": batched,
+        "served": served,
         "kernels": kernels,
     }
     print(json.dumps(out), flush=True)
