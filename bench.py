@@ -109,6 +109,9 @@ def parse():
     ap.add_argument("--no-profile", action="store_true", help="do not time kernels with HIP events")
     ap.add_argument("--fused-min-items", type=int, default=None,
                     help="work items from which the single-kernel y-pass is used (library default 256)")
+    ap.add_argument("--shape", type=str, default="auto",
+                    help="line-block shape of the workload's line length: 'auto' (autotuned), 'default' "
+                         "(the library's table) or 'kx,ky'")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration) and exit")
     return ap.parse_args()
@@ -311,6 +314,14 @@ def main():
     name = "ch2d_periodic_bdf2_4096"
     w = synth.WORKLOADS[name]
     n = args.n
+    cls = next(c for c in range(molt.MOLT_TUNE_CLASSES) if n <= (128 << c) or c == molt.MOLT_TUNE_CLASSES - 1)
+    if args.shape == "auto":
+        molt.autotune(molt.MOLT_F32, n)
+    elif args.shape != "default":
+        kx, ky = (int(v) for v in args.shape.split(","))
+        if molt.molt_tune_set(molt.MOLT_F32, cls, kx, ky) != molt.MOLT_OK:
+            raise SystemExit(f"bench.py: shape {args.shape} is not valid for n = {n}")
+    shape = molt.molt_tune_get(molt.MOLT_F32, cls)
     grid = molt.make_grid(n, n, 0.0, w["L"], 0.0, w["L"], molt.MOLT_BC_PERIODIC, w["M"])
     init = molt.MOLT_INIT_LINEAR if args.init == "linear" else molt.MOLT_INIT_PREV
     params = molt.make_params(w["eps"], w["dt"], tol=w["tol"], stepper=molt.MOLT_BDF2, max_iter=args.max_iter,
@@ -422,7 +433,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"2D CH periodic {n}x{n} on [0,1]^2, eps=0.005, BDF2 dt=1e-5, tol 1e-8, M=4, "
                                f"FP32 sweeps, u0=0.3+0.05N(0,1), init={args.init}",
-                   "grid": [n, n], "steps_in_workload": w["steps"], "parallelism": "single GPU"},
+                   "grid": [n, n], "steps_in_workload": w["steps"], "parallelism": "single GPU",
+                   "line_block_shape": {"kx": shape[0], "ky": shape[1], "chosen": args.shape}},
         "steps_per_s": round(args.steps / elapsed, 4),
         "iters_per_step": iters,
         "warmup_iters": [k for k, _ in warm],

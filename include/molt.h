@@ -255,11 +255,14 @@ int32_t molt_server_destroy(molt_server* server);
  * order of the scans).  Per precision and line-length class (class c holds
  * lines of n <= 128 * 2^c nodes, c = 0..MOLT_TUNE_CLASSES-1, the last class
  * up to the longest supported line) the table holds kx, the nodes per thread
- * of an x-line (4, 8, 16, 32 FP32 only; a line fits one 256-thread block:
- * n <= 256*kx), and ky, the nodes per thread of a y-line (4, 8, 16 FP32 only).
+ * of an x-line (4, 8, 16, 32 FP32 only; a line is owned by at most 256
+ * threads, n <= 256*kx, or for lines longer than 2048 nodes by 512 threads,
+ * n <= 512*kx), and ky, the nodes per thread of a y-line (4, 8, 16 FP32 only).
  * Every path reads the table at call time, so ch_step, ch_solve and
- * ch_solve_batch agree bit for bit under one table.  Process-wide; change it
- * only while no solve is running.
+ * ch_solve_batch agree bit for bit under one table (the batched kernels give
+ * a row at most 256 threads: for a class whose kx needs 512 they take the
+ * smallest kx that fits 256, and agree with the others to rounding only).
+ * Process-wide; change it only while no solve is running.
  *  molt_tune_get / molt_tune_set: read / write one class (MOLT_EINVAL if the
  *    shape is not valid for the class).
  *  molt_autotune: for every class up to max_n (128..8192 FP32, ..4096 FP64),

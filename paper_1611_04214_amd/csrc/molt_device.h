@@ -547,7 +547,7 @@ __device__ __forceinline__ void boundary_terms(const LineCoef& c, double TLl, do
 // residual: block max written to a per-block slot; a one-block close kernel
 // folds the slots (order-independent max) and advances the iteration state.
 __device__ inline void residual_block(double r, double* partials, int slot) {
-  __shared__ double red[4];
+  __shared__ double red[8];  // one per wave, blocks of up to 512 threads
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) r = fmax(r, __shfl_down(r, off));
@@ -586,27 +586,28 @@ __device__ inline void residual_close_body(const double* partials, int nblocks, 
 
 // --------------------------------------------------------------------------
 // x-direction pass: rows are contiguous; TL threads (a multiple of 64) own one
-// row, 256/TL rows per 256-thread block.
+// row, BS/TL rows per block of BS = 256 (or 512, for rows of 512 threads).
 // --------------------------------------------------------------------------
-// LDS of one x-pass block: F <= 2 swept rows of 256*K nodes, one pad word per 16
-template <typename T, int K>
+// LDS of one x-pass block: F <= 2 swept rows of BS*K nodes, one pad word per 16
+template <typename T, int K, int BS = 256>
 struct XRow {
-  static constexpr int ROW = 256 * K;
+  static constexpr int ROW = BS * K;
   static constexpr int PADDED = ROW + ROW / 16;
   static constexpr int ELEMS = 2 * PADDED;
 };
 
-template <typename T, int PI, int K, int M, bool PER>
+template <typename T, int PI, int K, int M, bool PER, int BS = 256>
 __device__ __forceinline__ void xpass_body(const LineCoef& c, const PassArgs& a, DevState* st, int nlines, int TL,
                                            double* rpart, int vec, int bx, T* smem) {
   using P = typename ProgOf<PI, T>::type;
   constexpr int F = P::F, E = P::E, NR = P::NR, NO = P::NO;
   constexpr int H = M / 2, W = K + 2 * H;
   constexpr int V = 16 / (int)sizeof(T);
-  constexpr int ROW = 256 * K;  // nodes of all rows of one block
+  constexpr int ROW = BS * K;  // nodes of all rows of one block
+  constexpr int NWB = BS / 64;  // waves per block (and at most as many rows)
   if (st != nullptr && st->done) return;
-  __shared__ T sh_tot[F][2][4];
-  __shared__ double sh_line[4][F][3];
+  __shared__ T sh_tot[F][2][NWB];
+  __shared__ double sh_line[NWB][F][3];
   // swept fields (then the swept results) of the block's rows, one padding
   // word per 16 so that a thread's K consecutive nodes sit 17 words from its
   // neighbour's (no bank conflicts)
@@ -617,7 +618,7 @@ __device__ __forceinline__ void xpass_body(const LineCoef& c, const PassArgs& a,
   const int lil = tid / TL;
   const int t = tid - lil * TL;
   const int wl0 = lil * (TL >> 6);
-  const int line = bx * (256 / TL) + lil;
+  const int line = bx * (BS / TL) + lil;
   const bool act = line < nlines;
   const int n = c.n;
   const int j0 = t * K;

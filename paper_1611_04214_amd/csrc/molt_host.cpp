@@ -69,6 +69,7 @@ int diag_blocks(size_t n);
 int xpass_max_n(int prec);
 
 int xpass_pick_k(int n, int prec);
+int xpass_pick_k256(int n, int prec);
 int xpass_tl(int n, int K);
 void ypass_shape(int prec, int n, int* nth, int* nseg);
 // batched kernels, one translation unit per precision
@@ -650,7 +651,7 @@ static void batch_maps(const molt_instance* inst, const std::vector<int>& act, i
         for (int i : act) {
           const molt_grid& gr = inst[i].grid;
           if (gr.order_M != M || (gr.bc == MOLT_BC_PERIODIC) != (per == 1)) continue;
-          const int K = xpass_pick_k(gr.nx, prec);
+          const int K = xpass_pick_k256(gr.nx, prec);
           if (K != ks[kk]) continue;
           const int lpb = 256 / xpass_tl(gr.nx, K);
           const int lines = gr.ny * ncomp_of(&inst[i].params);
@@ -765,7 +766,7 @@ static void fill_slot(const molt_instance& in, const Layout& L, char* w, molt_st
   d.nsteps = (int32_t)in.nsteps;
   d.max_iter = p.max_iter;
   d.fixed = p.fixed_iters;
-  const int K = xpass_pick_k(g.nx, prec);
+  const int K = xpass_pick_k256(g.nx, prec);
   d.tlx = xpass_tl(g.nx, K);
   d.vecx = ((size_t)g.nx * esz) % 16 == 0 && (uintptr_t)in.d_u % 16 == 0 && (uintptr_t)w % 16 == 0;
   d.model = p.model;

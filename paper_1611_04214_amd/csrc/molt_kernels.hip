@@ -37,11 +37,11 @@ __global__ void __launch_bounds__(256) residual_close_kernel(const double* parti
   residual_close_body(partials, nblocks, st);
 }
 
-template <typename T, int PI, int K, int M, bool PER>
-__global__ void MOLT_PASS_ATTR xpass_kernel(const LineCoef c, const PassArgs a, DevState* st, int nlines, int TL,
-                                            double* rpart, int vec) {
-  __shared__ T smem[ProgOf<PI, T>::type::F * XRow<T, K>::PADDED];
-  xpass_body<T, PI, K, M, PER>(c, a, st, nlines, TL, rpart, vec, blockIdx.x, smem);
+template <typename T, int PI, int K, int M, bool PER, int BS>
+__global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(MOLT_OCC)))
+xpass_kernel(const LineCoef c, const PassArgs a, DevState* st, int nlines, int TL, double* rpart, int vec) {
+  __shared__ T smem[ProgOf<PI, T>::type::F * XRow<T, K, BS>::PADDED];
+  xpass_body<T, PI, K, M, PER, BS>(c, a, st, nlines, TL, rpart, vec, blockIdx.x, smem);
 }
 
 template <typename T, int PI, int K, int M, bool PER>
@@ -370,7 +370,10 @@ bool tune_valid(int prec, int cls, int kx, int ky) {
   const bool kx_ok = kx == 4 || kx == 8 || kx == 16 || (kx == 32 && prec == MOLT_F32);
   const bool ky_ok = ky == 4 || ky == 8 || (ky == 16 && prec == MOLT_F32);
   const int nmax = cls == kTuneClasses - 1 ? xpass_max_n(prec) : (128 << cls);
-  return kx_ok && ky_ok && nmax <= 256 * kx;
+  // rows of 512 threads only for lines longer than 2048 nodes (the batched
+  // kernels, which run 256-thread blocks, then take the smallest 256-thread kx)
+  const int row_threads = cls >= 5 ? 512 : 256;
+  return kx_ok && ky_ok && nmax <= row_threads * kx;
 }
 
 void tune_get(int prec, int cls, int* kx, int* ky) {
@@ -386,6 +389,11 @@ void tune_set(int prec, int cls, int kx, int ky) {
 // launch shapes shared with the batched driver
 int xpass_pick_k(int n, int prec) {
   const int k = g_kx[prec == MOLT_F32][tune_class(n)];
+  return n <= 512 * k ? k : pick_kx(n, prec);
+}
+// the batched kernels run 256-thread blocks: a row gets at most 256 threads
+int xpass_pick_k256(int n, int prec) {
+  const int k = g_kx[prec == MOLT_F32][tune_class(n)];
   return n <= 256 * k ? k : pick_kx(n, prec);
 }
 int ypass_pick_k(int n, int prec) { return g_ky[prec == MOLT_F32][tune_class(n)]; }
@@ -397,7 +405,7 @@ int ypass_max_segments(int n) {
 int xpass_min_k(int n, int prec) { return pick_kx(n, prec); }
 int xpass_tl(int n, int K) {
   const int need = (n + K - 1) / K;
-  return need <= 64 ? 64 : (need <= 128 ? 128 : 256);
+  return need <= 64 ? 64 : (need <= 128 ? 128 : (need <= 256 ? 256 : 512));
 }
 void ypass_shape(int prec, int n, int* nth, int* nseg) {
   const int K = ypass_pick_k(n, prec);
@@ -456,12 +464,20 @@ static hipError_t xpass_k(const LineCoef& c, const PassArgs& a, DevState* st, in
   const int vec = can_vec<T, PI>(a, c.n);
   // threads per line: 64, 128 or 256, so that 256/TL rows tile the block exactly
   const int TL = xpass_tl(c.n, K);
-  const int lpb = 256 / TL;
+  const int BS = TL > 256 ? 512 : 256;  // rows of 512 threads get a block of their own
+  const int lpb = BS / TL;
   dim3 grid((nlines + lpb - 1) / lpb);
   if (g_prof_on) prof_begin(KF_XPASS * 8 + PI, s);
   const bool per = c.bc == MOLT_BC_PERIODIC;
-#define MOLT_XL(MM, PP) \
-  hipLaunchKernelGGL((xpass_kernel<T, PI, K, MM, PP>), grid, dim3(256), 0, s, c, a, st, nlines, TL, rpart, vec)
+#define MOLT_XL(MM, PP)                                                                                            \
+  do {                                                                                                            \
+    if (BS == 512)                                                                                                \
+      hipLaunchKernelGGL((xpass_kernel<T, PI, K, MM, PP, 512>), grid, dim3(512), 0, s, c, a, st, nlines, TL, rpart, \
+                         vec);                                                                                    \
+    else                                                                                                          \
+      hipLaunchKernelGGL((xpass_kernel<T, PI, K, MM, PP, 256>), grid, dim3(256), 0, s, c, a, st, nlines, TL, rpart, \
+                         vec);                                                                                    \
+  } while (0)
   switch (c.M) {
     case 2: if (per) MOLT_XL(2, true); else MOLT_XL(2, false); break;
     case 4: if (per) MOLT_XL(4, true); else MOLT_XL(4, false); break;

@@ -168,6 +168,9 @@ def test_tune_table_defaults_and_validation(lib):
     assert molt.tune_table(molt.MOLT_F32) == [(4, 16), (4, 16), (4, 16), (4, 16), (8, 16), (16, 16), (32, 16)]
     assert molt.tune_table(molt.MOLT_F64) == [(4, 8), (4, 8), (4, 8), (4, 8), (8, 8), (16, 8), (16, 8)]
     assert molt.molt_tune_set(molt.MOLT_F32, 4, 4, 16) == molt.MOLT_EINVAL   # 2048 nodes need kx >= 8
+    assert molt.molt_tune_set(molt.MOLT_F32, 5, 4, 16) == molt.MOLT_EINVAL   # 4096 nodes: kx >= 8 (512 threads)
+    assert molt.molt_tune_set(molt.MOLT_F32, 5, 8, 16) == molt.MOLT_OK       # rows of 512 threads
+    assert molt.molt_tune_set(molt.MOLT_F32, 5, 16, 16) == molt.MOLT_OK
     assert molt.molt_tune_set(molt.MOLT_F64, 0, 32, 8) == molt.MOLT_EINVAL   # kx 32 is FP32 only
     assert molt.molt_tune_set(molt.MOLT_F64, 0, 4, 16) == molt.MOLT_EINVAL   # ky 16 is FP32 only
     assert molt.molt_tune_set(molt.MOLT_F32, 7, 4, 4) == molt.MOLT_EINVAL
