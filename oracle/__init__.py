@@ -48,7 +48,7 @@ class _Params(ctypes.Structure):
     _fields_ = [("eps", ctypes.c_double), ("dt", ctypes.c_double), ("tol", ctypes.c_double),
                 ("sigma0", ctypes.c_double), ("stepper", ctypes.c_int), ("max_iter", ctypes.c_int),
                 ("init", ctypes.c_int), ("fixed_iters", ctypes.c_int),
-                ("reaction", ctypes.c_int), ("react_k", ctypes.c_double)]
+                ("reaction", ctypes.c_int), ("react_k", ctypes.c_double), ("omega", ctypes.c_double)]
 
 
 class _Info(ctypes.Structure):
@@ -142,10 +142,11 @@ class Params:
     sigma0: float = 2.0
     reaction: int = 0          # 0: Cahn-Hilliard cubic; 1: linear f(v) = react_k*v (test hook)
     react_k: float = 0.0
+    omega: float = 1.0         # BDF2 step ratio dt_n / dt_{n-1} (variable steps)
 
     def c(self) -> _Params:
         return _Params(self.eps, self.dt, self.tol, self.sigma0, self.stepper, self.max_iter,
-                       self.init, self.fixed_iters, self.reaction, self.react_k)
+                       self.init, self.fixed_iters, self.reaction, self.react_k, self.omega)
 
 
 @dataclass
@@ -285,3 +286,82 @@ def vch_solve(grid: Grid, params: Params, u: np.ndarray, nsteps: int):
     if rc < 0:
         raise ValueError("oracle_vch_solve failed (%d)" % rc)
     return uu, [_info(infos[i]) for i in range(nsteps)]
+
+
+# --------------------------------------------------------- adaptive steps --
+@dataclass
+class AdaptParams:
+    """Algorithm 1 (Sec. 6): lte_tol is sigma_tol, nmaxit is N_maxit (each
+    solve's iteration cap), theta and gamma the safety factors."""
+    t_end: float
+    dt0: float
+    lte_tol: float
+    nmaxit: int = 600
+    theta: float = 0.8
+    gamma: float = 1.3
+    dt_min: float = 0.0
+    dt_max: float = float("inf")
+    max_attempts: int = 1000000
+
+
+def adapt_decision(eta: float, tol: float, nit: int, nmaxit: int, theta: float, gamma: float):
+    """Step-size control of Algorithm 1: (accepted, factor for the next trial step).
+    eta <= tol: accepted unless nit >= nmaxit; the factor is min(theta sqrt(tol/eta),
+    gamma) when nit/nmaxit < 0.7, min(theta sqrt(tol/eta), 1) below 1, and 1/gamma
+    for a failed fixed point.  eta > tol: rejected, factor 1/gamma if eta/tol > 2,
+    else theta sqrt(tol/eta)."""
+    grow = theta * np.sqrt(tol / eta) if eta > 0 else float("inf")
+    if eta <= tol:
+        r = nit / nmaxit
+        if r < 0.7:
+            return True, min(grow, gamma)
+        if r < 1.0:
+            return True, min(grow, 1.0)
+        return False, 1.0 / gamma
+    if eta / tol > 2.0:
+        return False, 1.0 / gamma
+    return False, grow
+
+
+def adaptive_solve(grid: Grid, params: Params, u0: np.ndarray, ap: AdaptParams, vch: bool = False,
+                   stop=None):
+    """Adaptive BE-BDF2 time stepping (Algorithm 1): each attempt solves a BE
+    step and a variable-step BDF2 step from the same state; eta = max|u_BE -
+    u_BDF2| and the BDF2 solution is kept (reading).  The first step has no
+    history: it uses the printed Richardson estimate eta = |u_dt - u_dt/2|/2 of
+    BE and keeps the two half steps.  `stop(t, u)` may end the run early.
+    Returns (u, records) with records (t, dt, eta, iters, accepted)."""
+    stepf = vch_step if vch else step
+    u = np.ascontiguousarray(u0, dtype=np.float64).copy()
+    uprev, dtprev = None, None
+    t, dt = 0.0, ap.dt0
+    recs = []
+    base = dict(eps=params.eps, tol=params.tol, max_iter=ap.nmaxit, init=params.init, sigma0=params.sigma0,
+                reaction=params.reaction, react_k=params.react_k)
+    for _ in range(ap.max_attempts):
+        if t >= ap.t_end * (1 - 1e-14):
+            break
+        dt = min(dt, ap.t_end - t, ap.dt_max)
+        if dt < ap.dt_min:
+            raise RuntimeError("time step fell below dt_min")
+        if uprev is None:
+            full, i1 = stepf(grid, Params(dt=dt, stepper=BE, **base), u)
+            half1, i2 = stepf(grid, Params(dt=dt / 2, stepper=BE, **base), u)
+            cand, i3 = stepf(grid, Params(dt=dt / 2, stepper=BE, **base), half1)
+            eta = 0.5 * float(np.abs(full - cand).max())
+            nit = max(i1.iters, i2.iters, i3.iters)
+        else:
+            be, i1 = stepf(grid, Params(dt=dt, stepper=BE, **base), u)
+            cand, i2 = stepf(grid, Params(dt=dt, stepper=BDF2, omega=dt / dtprev, **base), u, uprev)
+            eta = float(np.abs(be - cand).max())
+            nit = max(i1.iters, i2.iters)
+        ok, fac = adapt_decision(eta, ap.lte_tol, nit, ap.nmaxit, ap.theta, ap.gamma)
+        recs.append((t, dt, eta, nit, ok))
+        if ok:
+            uprev, u = u, cand
+            t += dt
+            dtprev = dt
+            if stop is not None and stop(t, u):
+                break
+        dt *= fac
+    return u, recs

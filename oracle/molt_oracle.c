@@ -54,6 +54,7 @@ typedef struct {
                           2: the vector model's reaction on the real axis, f(v) = 6((v-1)^5 - (v-1)^2)
                           (test hook) */
   double react_k;
+  double omega;        /* BDF2 step ratio dt_n / dt_{n-1}; 0 or 1: constant steps */
 } or_params;
 
 typedef struct {
@@ -469,7 +470,14 @@ int oracle_step(const or_grid *g, const or_params *p, double *u, const double *u
   if (!(p->eps > 0) || !(p->dt > 0) || !(p->sigma0 > 0)) return -1;
   const size_t n = (size_t)g->nx * g->ny;
   const int bdf2 = (p->stepper == OR_BDF2) && u_prev != NULL;
-  const double beta = bdf2 ? 2.0 / 3.0 : 1.0;
+  /* variable-step BDF2 (reading; the paper writes constant steps): with
+   * w = dt_n/dt_{n-1}, ((1+2w)/(1+w)) v^{n+1} - (1+w) v^n + (w^2/(1+w)) v^{n-1}
+   * = dt_n F(v^{n+1}), i.e. v^{n+1} - beta dt_n F = rc0 v^n + rc1 v^{n-1} with
+   * beta = (1+w)/(1+2w), rc0 = (1+w)^2/(1+2w), rc1 = -w^2/(1+2w); w = 1 gives
+   * 2/3, 4/3, -1/3 (eq. BDF2). */
+  const double w = (p->omega > 0.0) ? p->omega : 1.0;
+  const double beta = bdf2 ? (1.0 + w) / (1.0 + 2.0 * w) : 1.0;
+  const double rc0 = (1.0 + w) * (1.0 + w) / (1.0 + 2.0 * w), rc1 = -w * w / (1.0 + 2.0 * w);
   const double a = beta * p->dt;
   double s1, s2, sigma;
   stepper_params(p->eps, a, p->sigma0, &s1, &s2, &sigma);
@@ -489,8 +497,10 @@ int oracle_step(const or_grid *g, const or_params *p, double *u, const double *u
   if (!vn || !rhs || !R || !v || !gk || !c1 || !t1 || !t2 || !dv || !q || !vnew) return -2;
 
   for (size_t i = 0; i < n; i++) vn[i] = u[i] + 1.0;
-  if (bdf2)
+  if (bdf2 && w == 1.0)
     for (size_t i = 0; i < n; i++) rhs[i] = (4.0 * vn[i] - (u_prev[i] + 1.0)) / 3.0;
+  else if (bdf2)
+    for (size_t i = 0; i < n; i++) rhs[i] = rc0 * vn[i] + rc1 * (u_prev[i] + 1.0);
   else
     memcpy(rhs, vn, sizeof(double) * n);
 
@@ -659,7 +669,10 @@ int oracle_vch_step(const or_grid *g, const or_params *p, double *u, const doubl
   if (!(p->eps > 0) || !(p->dt > 0) || !(p->sigma0 > 0)) return -1;
   const size_t n = (size_t)g->nx * g->ny;
   const int bdf2 = (p->stepper == OR_BDF2) && u_prev != NULL;
-  const double a = (bdf2 ? 2.0 / 3.0 : 1.0) * p->dt;
+  /* variable-step BDF2 as in oracle_step */
+  const double w = (p->omega > 0.0) ? p->omega : 1.0;
+  const double rc0 = (1.0 + w) * (1.0 + w) / (1.0 + 2.0 * w), rc1 = -w * w / (1.0 + 2.0 * w);
+  const double a = (bdf2 ? (1.0 + w) / (1.0 + 2.0 * w) : 1.0) * p->dt;
   double s1, s2, sigma;
   stepper_params(p->eps, a, p->sigma0, &s1, &s2, &sigma);
   const double al1 = 1.0 / sqrt(s1), al2 = 1.0 / sqrt(s2);
@@ -681,8 +694,10 @@ int oracle_vch_step(const or_grid *g, const or_params *p, double *u, const doubl
   for (int c = 0; c < 2; c++)
     for (size_t i = 0; i < n; i++) vn[c * n + i] = u[c * n + i] - OR_Z[2][c];
   for (int c = 0; c < 2; c++) {
-    for (size_t i = 0; i < n; i++)
-      rhs[i] = bdf2 ? (4.0 * vn[c * n + i] - (u_prev[c * n + i] - OR_Z[2][c])) / 3.0 : vn[c * n + i];
+    for (size_t i = 0; i < n; i++) {
+      const double vp = bdf2 ? u_prev[c * n + i] - OR_Z[2][c] : 0.0;
+      rhs[i] = !bdf2 ? vn[c * n + i] : (w == 1.0 ? (4.0 * vn[c * n + i] - vp) / 3.0 : rc0 * vn[c * n + i] + rc1 * vp);
+    }
     Ainv(g, al2, rhs, t2, t1);
     Ainv(g, al1, t2, R + c * n, t1);
   }
