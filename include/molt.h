@@ -170,6 +170,48 @@ int32_t ch_solve(const molt_grid* grid, const molt_ch_params* params, void* d_u,
                  void* d_work, size_t work_bytes, molt_step_info* per_step, void* stream);
 
 /*
+ * Adaptive time steps (Sec. 6, Algorithm 1) with the BE-BDF2 estimator.  Each
+ * attempt solves a BE step and a variable-step BDF2 step (step ratio
+ * w = dt_n/dt_{n-1}: v^{n+1} - beta dt F = rc0 v^n + rc1 v^{n-1} with
+ * beta = (1+w)/(1+2w), rc0 = (1+w)^2/(1+2w), rc1 = -w^2/(1+2w)) from the same
+ * state; eta = max|u_BE - u_BDF2| and the BDF2 solution is kept.  The first
+ * step has no history and uses Algorithm 1's Richardson estimate of BE
+ * (eta = max|u_dt - u_dt/2|/2, keeping the two half steps).  Then, with
+ * N_it the largest iteration count of the attempt:
+ *   eta <= lte_tol, N_it/nmaxit < 0.7:  accept, dt *= min(theta sqrt(lte_tol/eta), gamma)
+ *   eta <= lte_tol, N_it/nmaxit < 1:    accept, dt *= min(theta sqrt(lte_tol/eta), 1)
+ *   eta <= lte_tol, N_it >= nmaxit:     reject, dt /= gamma
+ *   eta > lte_tol:                      reject, dt /= gamma if eta/lte_tol > 2,
+ *                                       else dt *= theta sqrt(lte_tol/eta)
+ * params: as for ch_step (stepper, dt, have_prev and fixed_iters are ignored;
+ * max_iter is nmaxit).  The last step is shortened to end at t_end.
+ * rec: one record per attempt (up to max_rec; *nrec = attempts made).
+ * Returns MOLT_NOT_CONVERGED if max_attempts ended the run early or the step
+ * fell below dt_min.  Synchronizes `stream`.
+ */
+typedef struct {
+  double t_end;        /* integrate from t = 0 to t_end */
+  double dt0;          /* first trial step */
+  double lte_tol;      /* the error tolerance of Algorithm 1 */
+  double theta, gamma; /* safety factors (0.8, 1.3 in the paper) */
+  double dt_min, dt_max;
+  int32_t nmaxit;      /* N_maxit: iteration cap of every solve */
+  int32_t max_attempts;
+} molt_adapt_params;
+
+typedef struct {
+  double t, dt, eta;   /* start time, trial step, error estimate */
+  int32_t iters;       /* largest fixed-point iteration count of the attempt */
+  int32_t accepted;
+  double energy;       /* energy of the accepted state (0 if rejected) */
+} molt_adapt_record;
+
+size_t ch_adaptive_workspace_bytes(const molt_grid* grid, const molt_ch_params* params);
+int32_t ch_solve_adaptive(const molt_grid* grid, const molt_ch_params* params, const molt_adapt_params* adapt,
+                          void* d_u, void* d_work, size_t work_bytes, molt_adapt_record* rec, int32_t max_rec,
+                          int32_t* nrec, double* t_final, void* stream);
+
+/*
  * Batched instances (independent problems advanced together on one device).
  *  grid, params: as for ch_solve; params.have_prev is ignored (a BDF2
  *                instance starts with a BE step, as in ch_solve).

@@ -83,11 +83,14 @@ struct ProgSweep {  // w = L^{-1} in0
 };
 
 template <typename T>
-struct ProgRhs {  // w = L^{-1} rhs, rhs = u^n (BE) or (4u^n - u^{n-1})/3 (BDF2)
+struct ProgRhs {  // w = L^{-1} rhs, rhs = u^n (BE), (4u^n - u^{n-1})/3 (BDF2) or rc0 u^n + rc1 u^{n-1}
   static constexpr int F = 1, E = 0, NR = 2, NO = 1;
   __device__ static bool need(const PassArgs& a, int r) { return r == 0 || a.bdf2; }
   __device__ static void sin(const PassArgs& a, const T* r, T* s) {
-    s[0] = a.bdf2 ? (T(4) * r[0] - r[1]) * T(1.0 / 3.0) : r[0];
+    if (a.bdf2 == 2)
+      s[0] = (T)a.rc0 * r[0] + (T)a.rc1 * r[1];
+    else
+      s[0] = a.bdf2 ? (T(4) * r[0] - r[1]) * T(1.0 / 3.0) : r[0];
   }
   __device__ static void ext(const PassArgs&, const T*, T*) {}
   __device__ static double fin(const PassArgs&, const T* w, const T*, T* o) {
@@ -1106,6 +1109,20 @@ __device__ __forceinline__ void diag_body(const T* u, int nx, int ny, int bc, do
     partials[2 * bx] = a;
     partials[2 * bx + 1] = b;
   }
+}
+
+// max |a - b| over n elements (FP64, order independent): one partial per block
+template <typename T>
+__device__ __forceinline__ void maxdiff_body(const T* a, const T* b, size_t n, double* partials, int bx, int nb) {
+  __shared__ double sm[4];
+  double m = 0.0;
+  for (size_t i = (size_t)bx * blockDim.x + threadIdx.x; i < n; i += (size_t)nb * blockDim.x)
+    m = fmax(m, fabs((double)a[i] - (double)b[i]));
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_down(m, off));
+  if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) partials[bx] = fmax(fmax(sm[0], sm[1]), fmax(sm[2], sm[3]));
 }
 
 // mass and energy of the field from the per-block partial sums

@@ -26,7 +26,9 @@ namespace molt {
                                double* partials, DevState* st, hipStream_t s);                                \
   hipError_t launch_diag_vch_##sfx(const void* u, int nx, int ny, int bc, double hx, double hy, double eps,   \
                                    double* partials, DevState* st, hipStream_t s);                             \
-  hipError_t launch_vch_react_##sfx(const PassArgs& a, DevState* st, size_t n, hipStream_t s);
+  hipError_t launch_vch_react_##sfx(const PassArgs& a, DevState* st, size_t n, hipStream_t s);                  \
+  hipError_t launch_maxdiff_##sfx(const void* a, const void* b, size_t n, double* partials, double* out,      \
+                                  hipStream_t s);
 MOLT_KERN_DECL(f32)
 MOLT_KERN_DECL(f64)
 #undef MOLT_KERN_DECL
@@ -58,6 +60,10 @@ static hipError_t launch_diag_vch(int prec, const void* u, int nx, int ny, int b
 }
 static hipError_t launch_vch_react(int prec, const PassArgs& a, DevState* st, size_t n, hipStream_t s) {
   return MOLT_PREC(launch_vch_react)(a, st, n, s);
+}
+static hipError_t launch_maxdiff(int prec, const void* a, const void* b, size_t n, double* partials, double* out,
+                                 hipStream_t s) {
+  return MOLT_PREC(launch_maxdiff)(a, b, n, partials, out, s);
 }
 #undef MOLT_PREC
 size_t yfused_items(int n, int nx, int batch);
@@ -351,8 +357,10 @@ static Layout ch_layout(const molt_grid* g, int prec, int ncomp) {
 // --------------------------------------------------------------------------
 // one step
 // --------------------------------------------------------------------------
+// omega: BDF2 step ratio dt_n / dt_{n-1} (1: constant steps, eq. BDF2; otherwise the variable-step form)
 static int32_t step_impl(const molt_grid* g, const molt_ch_params* p, void* d_u, void* d_u_prev, bool bdf2,
-                         void* d_work, size_t work_bytes, molt_step_info* info, hipStream_t s, int iter_hint) {
+                         void* d_work, size_t work_bytes, molt_step_info* info, hipStream_t s, int iter_hint,
+                         double omega = 1.0) {
   const int prec = p->precision;
   const int nc = ncomp_of(p);
   const bool vch = nc == 2;
@@ -370,7 +378,11 @@ static int32_t step_impl(const molt_grid* g, const molt_ch_params* p, void* d_u,
   const int nx = g->nx, ny = g->ny, M = g->order_M, bc = g->bc;
   const size_t n = (size_t)nx * ny;
   const bool two_d = ny > 1;
-  const StepParams sp = step_params(p->eps, p->dt, bdf2 ? 2.0 / 3.0 : 1.0, p->sigma0);
+  // variable-step BDF2 (w = omega): v^{n+1} - beta dt F = rc0 v^n + rc1 v^{n-1},
+  // beta = (1+w)/(1+2w), rc0 = (1+w)^2/(1+2w), rc1 = -w^2/(1+2w)
+  const bool var = bdf2 && omega != 1.0;
+  const double beta = !bdf2 ? 1.0 : (var ? (1.0 + omega) / (1.0 + 2.0 * omega) : 2.0 / 3.0);
+  const StepParams sp = step_params(p->eps, p->dt, beta, p->sigma0);
   const double al1 = 1.0 / sqrt(sp.s1), al2 = 1.0 / sqrt(sp.s2);
   const double hx = spacing(bc, nx, g->x0, g->x1);
   const double hy = two_d ? spacing(bc, ny, g->y0, g->y1) : 1.0;
@@ -397,7 +409,9 @@ static int32_t step_impl(const molt_grid* g, const molt_ch_params* p, void* d_u,
   // R = A1^{-1} A2^{-1} rhs, A_i^{-1} = Lx_i^{-1} Ly_i^{-1}
   PassArgs a;
   memset(&a, 0, sizeof(a));
-  a.bdf2 = bdf2 ? 1 : 0;
+  a.bdf2 = bdf2 ? (var ? 2 : 1) : 0;
+  a.rc0 = (1.0 + omega) * (1.0 + omega) / (1.0 + 2.0 * omega);
+  a.rc1 = -omega * omega / (1.0 + 2.0 * omega);
   a.in[0] = d_u;
   a.in[1] = bdf2 ? d_u_prev : d_u;
   // (vector model: both components at once, stacked as a batch of y-sweeps
@@ -945,6 +959,147 @@ static int32_t solve_batch_impl(const molt_instance* inst, int count, void* d_wo
 }
 
 // --------------------------------------------------------------------------
+// adaptive time steps (Sec. 6, Algorithm 1) with the BE-BDF2 estimator
+// --------------------------------------------------------------------------
+struct AdaptLayout {
+  Layout step;     // the step driver's workspace (first)
+  size_t fld[5];   // u_BE, candidate, u^{n-1}, trial history, u^n backup
+  size_t part, out, total;
+};
+
+static AdaptLayout adapt_layout(const molt_grid* g, const molt_ch_params* p) {
+  AdaptLayout A;
+  const int nc = ncomp_of(p);
+  A.step = ch_layout(g, p->precision, nc);
+  const size_t fb = al256((size_t)g->nx * g->ny * nc * (p->precision == MOLT_F64 ? 8 : 4));
+  size_t off = al256(A.step.total);
+  for (int i = 0; i < 5; ++i) {
+    A.fld[i] = off;
+    off += fb;
+  }
+  A.part = off;
+  off += al256((size_t)diag_blocks((size_t)g->nx * g->ny * nc) * sizeof(double));
+  A.out = off;
+  off += 256;
+  A.total = off;
+  return A;
+}
+
+// Algorithm 1's decision: accepted?, and the factor of the next trial step
+static bool adapt_decide(double eta, double tol, int nit, int nmaxit, double theta, double gamma, double* fac) {
+  const double grow = eta > 0.0 ? theta * sqrt(tol / eta) : INFINITY;
+  if (eta <= tol) {
+    const double r = (double)nit / (double)nmaxit;
+    if (r < 0.7) {
+      *fac = grow < gamma ? grow : gamma;
+      return true;
+    }
+    if (r < 1.0) {
+      *fac = grow < 1.0 ? grow : 1.0;
+      return true;
+    }
+    *fac = 1.0 / gamma;
+    return false;
+  }
+  *fac = eta / tol > 2.0 ? 1.0 / gamma : grow;
+  return false;
+}
+
+static int32_t check_adapt(const molt_adapt_params* ap) {
+  if (!ap) return fail(MOLT_EINVAL, "adaptive parameters are NULL");
+  if (!(ap->t_end > 0) || !(ap->dt0 > 0) || !(ap->lte_tol > 0) || ap->nmaxit < 1 || !(ap->theta > 0) ||
+      !(ap->gamma > 1) || !(ap->dt_min >= 0) || !(ap->dt_max > 0) || ap->max_attempts < 1)
+    return fail(MOLT_EINVAL, "need t_end, dt0, lte_tol, theta, dt_max > 0, gamma > 1, nmaxit, max_attempts >= 1");
+  return MOLT_OK;
+}
+
+static int32_t solve_adaptive_impl(const molt_grid* g, const molt_ch_params* p0, const molt_adapt_params* ap,
+                                   void* d_u, void* d_work, size_t work_bytes, molt_adapt_record* rec,
+                                   int32_t max_rec, int32_t* nrec, double* t_final, hipStream_t s) {
+  const AdaptLayout A = adapt_layout(g, p0);
+  if (!d_work || work_bytes < A.total)
+    return fail(MOLT_EWORKSPACE, "workspace smaller than ch_adaptive_workspace_bytes()");
+  const int prec = p0->precision;
+  const size_t nel = (size_t)g->nx * g->ny * ncomp_of(p0);
+  const size_t esz = prec == MOLT_F64 ? 8 : 4;
+  char* w = (char*)d_work;
+  void* ube = w + A.fld[0];
+  void* cand = w + A.fld[1];
+  void* uprev = w + A.fld[2];
+  void* hist = w + A.fld[3];
+  double* part = (double*)(w + A.part);
+  double* dout = (double*)(w + A.out);
+  molt_ch_params p = *p0;
+  p.max_iter = ap->nmaxit;
+  p.fixed_iters = 0;
+  double t = 0.0, dt = ap->dt0, dtprev = 0.0;
+  bool have_prev = false;
+  int32_t m = 0;
+  int32_t status = MOLT_OK;
+  const double tiny = 1e-14 * ap->t_end;
+  for (int32_t k = 0; k < ap->max_attempts && t < ap->t_end - tiny; ++k) {
+    dt = fmin(fmin(dt, ap->t_end - t), ap->dt_max);
+    if (dt < ap->dt_min) {
+      status = fail(MOLT_NOT_CONVERGED, "the time step fell below dt_min");
+      break;
+    }
+    molt_step_info i1, i2, i3;
+    memset(&i3, 0, sizeof(i3));
+    int32_t rc;
+    double eta;
+    HIPCHK(hipMemcpyAsync(ube, d_u, nel * esz, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(cand, d_u, nel * esz, hipMemcpyDeviceToDevice, s));
+    p.dt = dt;
+    if (!have_prev) {
+      // first step: Richardson (step-doubling) estimate of BE, keep the two half steps
+      if ((rc = step_impl(g, &p, ube, nullptr, false, d_work, A.step.total, &i1, s, 0)) < 0) return rc;
+      p.dt = 0.5 * dt;
+      if ((rc = step_impl(g, &p, cand, nullptr, false, d_work, A.step.total, &i2, s, 0)) < 0) return rc;
+      if ((rc = step_impl(g, &p, cand, nullptr, false, d_work, A.step.total, &i3, s, 0)) < 0) return rc;
+      HIPCHK(launch_maxdiff(prec, ube, cand, nel, part, dout, s));
+      HIPCHK(hipMemcpyAsync(&eta, dout, sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      eta *= 0.5;
+    } else {
+      // BE and variable-step BDF2 from the same state; keep the BDF2 solution
+      if ((rc = step_impl(g, &p, ube, nullptr, false, d_work, A.step.total, &i1, s, 0)) < 0) return rc;
+      HIPCHK(hipMemcpyAsync(hist, uprev, nel * esz, hipMemcpyDeviceToDevice, s));
+      if ((rc = step_impl(g, &p, cand, hist, true, d_work, A.step.total, &i2, s, 0, dt / dtprev)) < 0) return rc;
+      HIPCHK(launch_maxdiff(prec, ube, cand, nel, part, dout, s));
+      HIPCHK(hipMemcpyAsync(&eta, dout, sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+    }
+    int nit = i1.iters > i2.iters ? i1.iters : i2.iters;
+    if (i3.iters > nit) nit = i3.iters;
+    double fac = 1.0;
+    const bool ok = adapt_decide(eta, ap->lte_tol, nit, ap->nmaxit, ap->theta, ap->gamma, &fac);
+    if (rec && m < max_rec) {
+      rec[m].t = t;
+      rec[m].dt = dt;
+      rec[m].eta = eta;
+      rec[m].iters = nit;
+      rec[m].accepted = ok ? 1 : 0;
+      rec[m].energy = ok ? (have_prev ? i2.energy : i3.energy) : 0.0;
+    }
+    ++m;
+    if (ok) {
+      HIPCHK(hipMemcpyAsync(uprev, d_u, nel * esz, hipMemcpyDeviceToDevice, s));
+      HIPCHK(hipMemcpyAsync(d_u, cand, nel * esz, hipMemcpyDeviceToDevice, s));
+      t += dt;
+      dtprev = dt;
+      have_prev = true;
+    }
+    dt *= fac;
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  if (status == MOLT_OK && t < ap->t_end - tiny)
+    status = fail(MOLT_NOT_CONVERGED, "max_attempts reached before t_end");
+  if (nrec) *nrec = m;
+  if (t_final) *t_final = t;
+  return status;
+}
+
+// --------------------------------------------------------------------------
 // serving: a resident batched engine that admits requests while others run
 // --------------------------------------------------------------------------
 // map entries one instance can need under any shape of the table
@@ -1432,6 +1587,26 @@ int32_t ch_solve_batch(const molt_instance* inst, int32_t count, void* d_work, s
                        molt_step_info* per_step, void* stream) {
   g_err.clear();
   return solve_batch_impl(inst, count, d_work, work_bytes, per_step, (hipStream_t)stream);
+}
+
+size_t ch_adaptive_workspace_bytes(const molt_grid* g, const molt_ch_params* p) {
+  g_err.clear();
+  if (check_params(p) != MOLT_OK || check_grid(g, p->precision) != MOLT_OK) return 0;
+  return adapt_layout(g, p).total;
+}
+
+int32_t ch_solve_adaptive(const molt_grid* g, const molt_ch_params* p, const molt_adapt_params* ap, void* d_u,
+                          void* d_work, size_t work_bytes, molt_adapt_record* rec, int32_t max_rec, int32_t* nrec,
+                          double* t_final, void* stream) {
+  g_err.clear();
+  int32_t rc = check_params(p);
+  if (rc != MOLT_OK) return rc;
+  rc = check_grid(g, p->precision);
+  if (rc != MOLT_OK) return rc;
+  rc = check_adapt(ap);
+  if (rc != MOLT_OK) return rc;
+  if (!d_u || max_rec < 0) return fail(MOLT_EINVAL, "d_u is NULL or max_rec < 0");
+  return solve_adaptive_impl(g, p, ap, d_u, d_work, work_bytes, rec, max_rec, nrec, t_final, (hipStream_t)stream);
 }
 
 size_t molt_server_footprint(const molt_instance* inst) {

@@ -62,7 +62,8 @@ struct PassArgs {
   double sigma;    // linear part of f moved to the left-hand side
   double kappa;    // a/s1
   int mode;        // 0: full form (first iteration), 1: increment form
-  int bdf2;        // rhs program: 1 -> (4u - u_prev)/3
+  int bdf2;        // rhs program: 1 -> (4u - u_prev)/3; 2 -> rc0 u + rc1 u_prev (variable steps)
+  double rc0, rc1; // variable-step BDF2 rhs coefficients
 };
 
 // Workspace and control of the fused (single-kernel) y-pass.

@@ -331,6 +331,20 @@ __global__ void __launch_bounds__(256) vch_react_kernel(const PassArgs a, DevSta
 }
 
 template <typename T>
+__global__ void __launch_bounds__(256) maxdiff_kernel(const T* a, const T* b, size_t n, double* partials) {
+  maxdiff_body<T>(a, b, n, partials, blockIdx.x, gridDim.x);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(64) maxdiff_final_kernel(const double* partials, int nb, double* out) {
+  double m = 0.0;
+  for (int i = threadIdx.x; i < nb; i += 64) m = fmax(m, partials[i]);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_down(m, off));
+  if (threadIdx.x == 0) out[0] = m;
+}
+
+template <typename T>
 __global__ void __launch_bounds__(256) diag_final_kernel(const double* partials, int nblocks, double area,
                                                          DevState* st) {
   diag_final_body(partials, nblocks, area, st);
@@ -704,6 +718,18 @@ hipError_t MOLT_KFN(launch_diag_vch)(const void* u, int nx, int ny, int bc, doub
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((diag_vch_final_kernel<MOLT_KT>), dim3(1), dim3(256), 0, s, (const double*)partials, nb, hx * hy,
                      st);
+  return hipGetLastError();
+}
+
+// max |a - b| -> out[0] (partials: diag_blocks(n) doubles)
+hipError_t MOLT_KFN(launch_maxdiff)(const void* a, const void* b, size_t n, double* partials, double* out,
+                                    hipStream_t s) {
+  const int nb = diag_blocks(n);
+  hipLaunchKernelGGL((maxdiff_kernel<MOLT_KT>), dim3(nb), dim3(256), 0, s, (const MOLT_KT*)a, (const MOLT_KT*)b, n,
+                     partials);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((maxdiff_final_kernel<MOLT_KT>), dim3(1), dim3(64), 0, s, (const double*)partials, nb, out);
   return hipGetLastError();
 }
 

@@ -27,7 +27,8 @@ MOLT_F64, MOLT_F32 = 0, 1
 
 #: every symbol include/molt.h declares
 EXPORTS = ("mol_t_helmholtz_sweep", "molt_sweep_workspace_bytes", "ch_workspace_bytes", "ch_step",
-           "ch_solve", "ch_batch_workspace_bytes", "ch_solve_batch", "molt_tune_get", "molt_tune_set",
+           "ch_solve", "ch_adaptive_workspace_bytes", "ch_solve_adaptive", "ch_batch_workspace_bytes",
+           "ch_solve_batch", "molt_tune_get", "molt_tune_set",
            "molt_autotune_workspace_bytes", "molt_autotune", "molt_server_footprint", "molt_server_bytes",
            "molt_server_create", "molt_server_submit", "molt_server_run", "molt_server_poll",
            "molt_server_destroy", "molt_strerror", "molt_last_error", "molt_profile", "molt_profile_read",
@@ -69,6 +70,17 @@ class molt_step_info(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class molt_adapt_params(ctypes.Structure):
+    _fields_ = [("t_end", ctypes.c_double), ("dt0", ctypes.c_double), ("lte_tol", ctypes.c_double),
+                ("theta", ctypes.c_double), ("gamma", ctypes.c_double), ("dt_min", ctypes.c_double),
+                ("dt_max", ctypes.c_double), ("nmaxit", ctypes.c_int32), ("max_attempts", ctypes.c_int32)]
+
+
+class molt_adapt_record(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_double), ("dt", ctypes.c_double), ("eta", ctypes.c_double),
+                ("iters", ctypes.c_int32), ("accepted", ctypes.c_int32), ("energy", ctypes.c_double)]
+
+
 class molt_instance(ctypes.Structure):
     _fields_ = [("grid", molt_grid), ("params", molt_ch_params), ("d_u", ctypes.c_void_p),
                 ("nsteps", ctypes.c_int64)]
@@ -107,6 +119,12 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.ch_step.restype = ctypes.c_int32
     lib.ch_solve.argtypes = [G, P, vp, ctypes.c_int64, vp, sz, ctypes.POINTER(molt_step_info), vp]
     lib.ch_solve.restype = ctypes.c_int32
+    lib.ch_adaptive_workspace_bytes.argtypes = [G, P]
+    lib.ch_adaptive_workspace_bytes.restype = sz
+    lib.ch_solve_adaptive.argtypes = [G, P, ctypes.POINTER(molt_adapt_params), vp, vp, sz,
+                                      ctypes.POINTER(molt_adapt_record), ctypes.c_int32,
+                                      ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double), vp]
+    lib.ch_solve_adaptive.restype = ctypes.c_int32
     I = ctypes.POINTER(molt_instance)
     lib.ch_batch_workspace_bytes.argtypes = [I, ctypes.c_int32]
     lib.ch_batch_workspace_bytes.restype = sz
@@ -188,6 +206,36 @@ def ch_solve(grid: molt_grid, params: molt_ch_params, d_u: int, nsteps: int, d_w
              per_step=None, stream: int = 0) -> int:
     return load().ch_solve(ctypes.byref(grid), ctypes.byref(params), d_u, nsteps, d_work or None, work_bytes,
                            per_step, stream or None)
+
+
+def ch_adaptive_workspace_bytes(grid: molt_grid, params: molt_ch_params) -> int:
+    return load().ch_adaptive_workspace_bytes(ctypes.byref(grid), ctypes.byref(params))
+
+
+def ch_solve_adaptive(grid, params, adapt, d_u: int, d_work: int, work_bytes: int, rec=None, max_rec: int = 0,
+                      nrec=None, t_final=None, stream: int = 0) -> int:
+    return load().ch_solve_adaptive(ctypes.byref(grid), ctypes.byref(params), ctypes.byref(adapt), d_u,
+                                    d_work or None, work_bytes, rec, max_rec, nrec, t_final, stream or None)
+
+
+def make_adapt(t_end: float, dt0: float, lte_tol: float, nmaxit: int = 600, theta: float = 0.8,
+               gamma: float = 1.3, dt_min: float = 0.0, dt_max: float = 1e300,
+               max_attempts: int = 1000000) -> molt_adapt_params:
+    return molt_adapt_params(t_end, dt0, lte_tol, theta, gamma, dt_min, dt_max, nmaxit, max_attempts)
+
+
+def solve_adaptive(u, grid: molt_grid, params: molt_ch_params, adapt: molt_adapt_params, max_rec: int = 100000):
+    """ch_solve_adaptive in place on u; returns (status, [molt_adapt_record], t_final)."""
+    import torch
+    need = ch_adaptive_workspace_bytes(grid, params)
+    if need == 0:
+        raise MoltError(MOLT_EINVAL, "ch_adaptive_workspace_bytes")
+    work = workspace(need, u.device)
+    rec = (molt_adapt_record * max_rec)()
+    n, tf = ctypes.c_int32(), ctypes.c_double()
+    st = _check(ch_solve_adaptive(grid, params, adapt, u.data_ptr(), work.data_ptr(), work.numel(), rec, max_rec,
+                                  ctypes.byref(n), ctypes.byref(tf), _stream(torch)), "ch_solve_adaptive")
+    return st, [rec[i] for i in range(min(n.value, max_rec))], tf.value
 
 
 def ch_batch_workspace_bytes(inst, count: int) -> int:

@@ -39,6 +39,8 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(molt.molt_step_info) == 64
     assert ctypes.sizeof(molt.molt_instance) == 128
     assert ctypes.sizeof(molt.molt_result) == 88
+    assert ctypes.sizeof(molt.molt_adapt_params) == 64
+    assert ctypes.sizeof(molt.molt_adapt_record) == 40
 
 
 def test_strerror_names_every_status(lib):
@@ -199,3 +201,15 @@ def test_server_queries_and_argument_checks(lib):
     assert lib.molt_server_submit(None, ctypes.byref(inst), 1) == molt.MOLT_EINVAL
     assert lib.molt_server_run(None, 1, None, None) == molt.MOLT_EINVAL
     assert lib.molt_server_destroy(None) == molt.MOLT_OK
+
+
+@pytest.mark.parametrize("change", [dict(t_end=0.0), dict(dt0=-1.0), dict(lte_tol=0.0), dict(gamma=1.0),
+                                    dict(nmaxit=0), dict(max_attempts=0)])
+def test_adaptive_argument_checks(lib, change):
+    g = molt.make_grid(32, 32, M=4)
+    p = molt.make_params(0.05, 1e-3)
+    assert molt.ch_adaptive_workspace_bytes(g, p) > molt.ch_workspace_bytes(g, p)
+    ap = molt.make_adapt(1.0, 1e-3, 1e-3)
+    for k, v in change.items():
+        setattr(ap, k, v)
+    assert molt.ch_solve_adaptive(g, p, ap, 1, 1, 1 << 30) == molt.MOLT_EINVAL
