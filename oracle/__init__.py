@@ -22,7 +22,7 @@ _SRC = os.path.join(_HERE, "molt_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 BC_PERIODIC, BC_NEUMANN, BC_DIRICHLET = 0, 1, 2
-BE, BDF2 = 0, 1
+BE, BDF2, BDF3 = 0, 1, 2
 INIT_PREV, INIT_LINEAR = 0, 1
 
 
@@ -82,6 +82,10 @@ def _load():
         lib.oracle_energy.restype = ctypes.c_double
         lib.oracle_stepper_params.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int,
                                               ctypes.c_int, ctypes.c_double, dp]
+        lib.oracle_bdf3_step.argtypes = [ctypes.POINTER(_Grid), ctypes.POINTER(_Params), dp, dp, dp,
+                                         ctypes.POINTER(_Info)]
+        lib.oracle_sdirk2_step.argtypes = [ctypes.POINTER(_Grid), ctypes.POINTER(_Params), dp,
+                                           ctypes.POINTER(_Info)]
         lib.oracle_vch_W.argtypes = [ctypes.c_double, ctypes.c_double]
         lib.oracle_vch_W.restype = ctypes.c_double
         lib.oracle_vch_gradW.argtypes = [ctypes.c_double, ctypes.c_double, dp]
@@ -208,6 +212,31 @@ def step(grid: Grid, params: Params, u: np.ndarray, u_prev: np.ndarray | None = 
                          None if up is None else _dp(up), ctypes.byref(info))
     if rc < 0:
         raise ValueError("oracle_step failed (%d)" % rc)
+    return uu, _info(info)
+
+
+def bdf3_step(grid: Grid, params: Params, u: np.ndarray, u_prev: np.ndarray, u_prev2: np.ndarray):
+    """One BDF3 step (eq. BDF3) from u^n, u^{n-1}, u^{n-2}; returns (u_next, Info)."""
+    lib = _load()
+    uu = np.ascontiguousarray(u, dtype=np.float64).copy()
+    a = np.ascontiguousarray(u_prev, dtype=np.float64)
+    b = np.ascontiguousarray(u_prev2, dtype=np.float64)
+    info = _Info()
+    rc = lib.oracle_bdf3_step(ctypes.byref(grid.c()), ctypes.byref(params.c()), _dp(uu), _dp(a), _dp(b),
+                              ctypes.byref(info))
+    if rc < 0:
+        raise ValueError("oracle_bdf3_step failed (%d)" % rc)
+    return uu, _info(info)
+
+
+def sdirk2_step(grid: Grid, params: Params, u: np.ndarray):
+    """One SDIRK2 step (Sec. 4.2) as two BE stages of eta*dt; returns (u_next, Info)."""
+    lib = _load()
+    uu = np.ascontiguousarray(u, dtype=np.float64).copy()
+    info = _Info()
+    rc = lib.oracle_sdirk2_step(ctypes.byref(grid.c()), ctypes.byref(params.c()), _dp(uu), ctypes.byref(info))
+    if rc < 0:
+        raise ValueError("oracle_sdirk2_step failed (%d)" % rc)
     return uu, _info(info)
 
 

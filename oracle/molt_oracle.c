@@ -26,6 +26,7 @@
 
 #define OR_BE 0
 #define OR_BDF2 1
+#define OR_BDF3 2
 
 #define OR_INIT_PREV 0
 #define OR_INIT_LINEAR 1
@@ -371,7 +372,7 @@ static void stepper_params(double eps, double a, double sigma0, double *s1, doub
 }
 
 int oracle_stepper_params(double eps, double dt, int stepper, int first, double sigma0, double *out3) {
-  double beta = (stepper == OR_BDF2 && !first) ? 2.0 / 3.0 : 1.0;
+  double beta = first ? 1.0 : (stepper == OR_BDF2 ? 2.0 / 3.0 : (stepper == OR_BDF3 ? 6.0 / 11.0 : 1.0));
   stepper_params(eps, beta * dt, sigma0, &out3[0], &out3[1], &out3[2]);
   return 0;
 }
@@ -465,18 +466,22 @@ static void Dop(const or_grid *g, double alpha, const double *in, double *out, d
   for (size_t i = 0; i < n; i++) out[i] = t1[i] - out[i]; /* (I - Lx^{-1}) (...) */
 }
 
-int oracle_step(const or_grid *g, const or_params *p, double *u, const double *u_prev, or_info *info) {
+/* u_prev2 != NULL (with u_prev) and stepper == OR_BDF3: a BDF3 step (eq. BDF3),
+ * (I - beta dt F) v^{n+1} = (18 v^n - 9 v^{n-1} + 2 v^{n-2})/11, beta = 6/11. */
+static int step_core(const or_grid *g, const or_params *p, double *u, const double *u_prev,
+                     const double *u_prev2, or_info *info) {
   if (!grid_ok(g) || !p || !u) return -1;
   if (!(p->eps > 0) || !(p->dt > 0) || !(p->sigma0 > 0)) return -1;
   const size_t n = (size_t)g->nx * g->ny;
-  const int bdf2 = (p->stepper == OR_BDF2) && u_prev != NULL;
+  const int bdf3 = (p->stepper == OR_BDF3) && u_prev != NULL && u_prev2 != NULL;
+  const int bdf2 = !bdf3 && (p->stepper == OR_BDF2) && u_prev != NULL;
   /* variable-step BDF2 (reading; the paper writes constant steps): with
    * w = dt_n/dt_{n-1}, ((1+2w)/(1+w)) v^{n+1} - (1+w) v^n + (w^2/(1+w)) v^{n-1}
    * = dt_n F(v^{n+1}), i.e. v^{n+1} - beta dt_n F = rc0 v^n + rc1 v^{n-1} with
    * beta = (1+w)/(1+2w), rc0 = (1+w)^2/(1+2w), rc1 = -w^2/(1+2w); w = 1 gives
    * 2/3, 4/3, -1/3 (eq. BDF2). */
   const double w = (p->omega > 0.0) ? p->omega : 1.0;
-  const double beta = bdf2 ? (1.0 + w) / (1.0 + 2.0 * w) : 1.0;
+  const double beta = bdf3 ? 6.0 / 11.0 : (bdf2 ? (1.0 + w) / (1.0 + 2.0 * w) : 1.0);
   const double rc0 = (1.0 + w) * (1.0 + w) / (1.0 + 2.0 * w), rc1 = -w * w / (1.0 + 2.0 * w);
   const double a = beta * p->dt;
   double s1, s2, sigma;
@@ -497,7 +502,10 @@ int oracle_step(const or_grid *g, const or_params *p, double *u, const double *u
   if (!vn || !rhs || !R || !v || !gk || !c1 || !t1 || !t2 || !dv || !q || !vnew) return -2;
 
   for (size_t i = 0; i < n; i++) vn[i] = u[i] + 1.0;
-  if (bdf2 && w == 1.0)
+  if (bdf3)
+    for (size_t i = 0; i < n; i++)
+      rhs[i] = (18.0 * vn[i] - 9.0 * (u_prev[i] + 1.0) + 2.0 * (u_prev2[i] + 1.0)) / 11.0;
+  else if (bdf2 && w == 1.0)
     for (size_t i = 0; i < n; i++) rhs[i] = (4.0 * vn[i] - (u_prev[i] + 1.0)) / 3.0;
   else if (bdf2)
     for (size_t i = 0; i < n; i++) rhs[i] = rc0 * vn[i] + rc1 * (u_prev[i] + 1.0);
@@ -570,23 +578,70 @@ int oracle_step(const or_grid *g, const or_params *p, double *u, const double *u
   return (p->fixed_iters <= 0 && res >= p->tol) ? 1 : 0;
 }
 
+int oracle_step(const or_grid *g, const or_params *p, double *u, const double *u_prev, or_info *info) {
+  return step_core(g, p, u, u_prev, NULL, info);
+}
+
+int oracle_bdf3_step(const or_grid *g, const or_params *p, double *u, const double *u_prev,
+                     const double *u_prev2, or_info *info) {
+  if (!u_prev || !u_prev2 || p->stepper != OR_BDF3) return -1;
+  return step_core(g, p, u, u_prev, u_prev2, info);
+}
+
+/* SDIRK2 (Sec. 4.2, eta = 1 - sqrt(2)/2).  With the stage values
+ * V1 = v^n + eta dt K1 and V2 = W + eta dt K2, W = v^n + (1-eta) dt K1, the two
+ * stage equations read (I + eta eps^2 dt d4) V1 = v^n + eta dt d2 f(V1) and
+ * (I + eta eps^2 dt d4) V2 = W + eta dt d2 f(V2), i.e. two BE steps of size
+ * eta dt (from v^n, then from W = v^n + ((1-eta)/eta)(V1 - v^n)), and
+ * v^{n+1} = V2.  (Reading: the stages are solved in this form; the fixed
+ * points are the paper's stage solutions.)  info: the second stage's report,
+ * iters = both stages' iterations. */
+int oracle_sdirk2_step(const or_grid *g, const or_params *p, double *u, or_info *info) {
+  const size_t n = (size_t)g->nx * g->ny;
+  const double eta = 1.0 - sqrt(2.0) / 2.0;
+  or_params q = *p;
+  q.stepper = OR_BE;
+  q.dt = eta * p->dt;
+  double *v1 = (double *)malloc(sizeof(double) * n);
+  if (!v1) return -2;
+  memcpy(v1, u, sizeof(double) * n);
+  or_info i1;
+  int rc1 = step_core(g, &q, v1, NULL, NULL, &i1);
+  if (rc1 < 0) { free(v1); return rc1; }
+  for (size_t i = 0; i < n; i++) u[i] = u[i] + (1.0 - eta) / eta * (v1[i] - u[i]);  /* W */
+  int rc2 = step_core(g, &q, u, NULL, NULL, info);
+  free(v1);
+  if (rc2 < 0) return rc2;
+  if (info) info->iters += i1.iters;
+  return (rc1 > 0 || rc2 > 0) ? 1 : 0;
+}
+
 /* nsteps steps; BDF2 takes a BE first step (reading: the paper's start-up
- * for BDF2 is not stated; a BE first step reproduces its Table 1).
+ * for BDF2 is not stated; a BE first step reproduces its Table 1); BDF3 takes
+ * two SDIRK2 steps first (Sec. 4.4).
  * infos: nsteps entries or NULL.  Returns 1 if any step hit max_iter. */
 int oracle_solve(const or_grid *g, const or_params *p, double *u, int nsteps, or_info *infos) {
   if (!grid_ok(g) || !p || !u || nsteps < 0) return -1;
   const size_t n = (size_t)g->nx * g->ny;
   double *prev = (double *)malloc(sizeof(double) * n);
+  double *prev2 = (double *)malloc(sizeof(double) * n);
   double *cur = (double *)malloc(sizeof(double) * n);
   int status = 0;
   for (int s = 0; s < nsteps; s++) {
     memcpy(cur, u, sizeof(double) * n);
-    int rc = oracle_step(g, p, u, s == 0 ? NULL : prev, infos ? &infos[s] : NULL);
+    int rc;
+    if (p->stepper == OR_BDF3)
+      rc = s < 2 ? oracle_sdirk2_step(g, p, u, infos ? &infos[s] : NULL)
+                 : step_core(g, p, u, prev, prev2, infos ? &infos[s] : NULL);
+    else
+      rc = step_core(g, p, u, s == 0 ? NULL : prev, NULL, infos ? &infos[s] : NULL);
     if (rc < 0) { status = rc; break; }
     if (rc > 0) status = 1;
+    memcpy(prev2, prev, sizeof(double) * n);
     memcpy(prev, cur, sizeof(double) * n);
   }
   free(prev);
+  free(prev2);
   free(cur);
   return status;
 }

@@ -295,6 +295,52 @@ def test_table1_bdf2_column(oracle_mod):
 
 
 @pytest.mark.slow
+def test_table2_bdf3_column(oracle_mod):
+    """Sec. 4.4, Table 2, BDF3 column (BDF3 after two SDIRK2 steps, the SDIRK2
+    stages solved as BE steps of eta*dt): every printed digit of the first
+    five rows, the last within 1e-4 (it is at the level the 1e-12 fixed-point
+    tolerance leaves)."""
+    gold = _read_golden("table2_bdf3.txt")
+    g = oracle_mod.Grid(nx=512, bc=0, M=6)
+    u0 = synth.u0_table1(g.nodes_x())
+    sols = []
+    dts = [r[0] for r in gold] + [gold[-1][0] / 2]
+    for dt in dts:
+        p = oracle_mod.Params(eps=0.18, dt=dt, tol=1e-12, stepper=oracle_mod.BDF3, max_iter=100000)
+        u, _ = oracle_mod.solve(g, p, u0, int(round(1.0 / dt)))
+        sols.append(u)
+    errs = [np.abs(sols[i] - sols[i + 1]).max() for i in range(len(gold))]
+    for (dt, e_paper, _), e in zip(gold[:5], errs[:5]):
+        assert float("%.4e" % e) == e_paper, (dt, e, e_paper)
+    assert abs(errs[5] / gold[5][1] - 1) < 1e-4
+
+
+def test_sdirk2_is_second_order_and_bdf3_third(oracle_mod):
+    """SDIRK2 steps alone are second order and BDF3 with its SDIRK2 start-up is
+    third order, on a smooth problem with the linear reaction hook (the stiff
+    Table 2 problem reaches third order only at small steps)."""
+    g = oracle_mod.Grid(nx=64, bc=0, M=6)
+    x = g.nodes_x()
+    u0 = 0.3 * np.cos(x) + 0.1 * np.sin(2 * x)
+
+    def run(stepper, dt):
+        p = oracle_mod.Params(eps=0.18, dt=dt, tol=1e-14, stepper=stepper, max_iter=100000, reaction=1,
+                              react_k=0.5)
+        if stepper == oracle_mod.BE:  # SDIRK2 steps only
+            u = u0.copy()
+            for _ in range(int(round(1.0 / dt))):
+                u, _ = oracle_mod.sdirk2_step(g, p, u)
+            return u
+        return oracle_mod.solve(g, p, u0, int(round(1.0 / dt)))[0]
+
+    for stepper, order in ((oracle_mod.BE, 2), (oracle_mod.BDF3, 3)):
+        us = [run(stepper, 0.05 / 2 ** k) for k in range(4)]
+        e = [np.abs(us[i] - us[i + 1]).max() for i in range(3)]
+        o = [np.log2(e[i] / e[i + 1]) for i in range(2)]
+        assert all(abs(v - order) < 0.1 for v in o), (stepper, e, o)
+
+
+@pytest.mark.slow
 def test_table4_bdf2_column(oracle_mod):
     """Sec. 5.1, Table 4, BDF2 column, within 0.5%: pins the 2D splitting-
     absorbing iteration in both regimes (dt = 0.1, 0.05 factorize; 0.025 and
