@@ -50,9 +50,12 @@ extern "C" {
 #define MOLT_BC_NEUMANN 1
 #define MOLT_BC_DIRICHLET 2
 
-/* time steppers (Sec. 3.1 eq. CH_BE; Sec. 4.1 eq. BDF2) */
+/* time steppers (Sec. 3.1 eq. CH_BE; Sec. 4.1 eqs. BDF2, BDF3).  BDF3 starts
+ * with two SDIRK2 steps (Sec. 4.2, 4.4), each solved as two BE stages of size
+ * (1 - sqrt(2)/2) dt. */
 #define MOLT_BE 0
 #define MOLT_BDF2 1
+#define MOLT_BDF3 2
 
 /* models: the Cahn-Hilliard equation (eq. CahnHilliard) or the vector model of
  * three phases (eqs. CH_vector, CH_vector_reaction; Sec. 5.2) */
@@ -87,13 +90,16 @@ typedef struct {
  *  eps, dt      > 0
  *  tol          stop when max|v^{k+1} - v^k| < tol (ignored if fixed_iters > 0)
  *  sigma0       f'(0) of the shifted reaction; 2 for Cahn-Hilliard
- *  stepper      MOLT_BE or MOLT_BDF2
+ *  stepper      MOLT_BE, MOLT_BDF2 or MOLT_BDF3 (ch_step, ch_solve; batched and
+ *               served instances take MOLT_BE or MOLT_BDF2)
  *  max_iter     iteration cap (the step reports MOLT_NOT_CONVERGED if reached)
  *  init         MOLT_INIT_PREV or MOLT_INIT_LINEAR
  *  precision    MOLT_F64 or MOLT_F32
  *  fixed_iters  > 0: run exactly this many iterations (parity mode)
- *  have_prev    ch_step only: 1 if d_u_prev holds u^{n-1} (a BDF2 step), 0 for
- *               the start-up step (taken as BE)
+ *  have_prev    ch_step only: history fields held by d_u_prev.  BDF2: 1 if
+ *               d_u_prev holds u^{n-1} (a BDF2 step), 0 for the start-up step
+ *               (taken as BE).  BDF3: d_u_prev holds two fields,
+ *               [u^{n-1} | u^{n-2}]; 2 gives a BDF3 step, less an SDIRK2 step.
  *  model        MOLT_MODEL_CH, or MOLT_MODEL_VCH: u = (u1, u2) with
  *               W(u) = prod_i |u - z_i|^2 over the cube roots of unity z_i; the
  *               scheme shifts by z_3 and the paper's sigma0 is 18 (Sec. 5.2).
@@ -154,7 +160,8 @@ size_t ch_workspace_bytes(const molt_grid* grid, const molt_ch_params* params);
  *  d_u:      in u^n, out u^{n+1} (the paper's u; the shift v = u+1 is internal).
  *  d_u_prev: BDF2 history.  If params->have_prev and stepper == BDF2 it holds
  *            u^{n-1} and a BDF2 step is taken; otherwise a BE step.  If not
- *            NULL it receives u^n on return (history rotated in place).
+ *            NULL it receives u^n on return (history rotated in place).  BDF3:
+ *            two fields [u^{n-1} | u^{n-2}] (see have_prev), rotated likewise.
  *  info:     filled when not NULL.
  * Synchronizes `stream` before returning.
  */
@@ -162,8 +169,10 @@ int32_t ch_step(const molt_grid* grid, const molt_ch_params* params, void* d_u, 
                 void* d_work, size_t work_bytes, molt_step_info* info, void* stream);
 
 /*
- * ch_solve -- nsteps steps from d_u (BDF2: BE start-up step, then BDF2 with
- * the history kept in the workspace).  per_step: nsteps entries or NULL.
+ * ch_solve -- nsteps steps from d_u (BDF2: BE start-up step, then BDF2; BDF3:
+ * two SDIRK2 start-up steps, then BDF3; the history kept in the workspace).
+ * per_step: nsteps entries or NULL (an SDIRK2 step reports both stages'
+ * iterations).
  * Returns MOLT_NOT_CONVERGED if any step reached max_iter.
  */
 int32_t ch_solve(const molt_grid* grid, const molt_ch_params* params, void* d_u, int64_t nsteps,

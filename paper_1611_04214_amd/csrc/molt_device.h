@@ -83,11 +83,14 @@ struct ProgSweep {  // w = L^{-1} in0
 };
 
 template <typename T>
-struct ProgRhs {  // w = L^{-1} rhs, rhs = u^n (BE), (4u^n - u^{n-1})/3 (BDF2) or rc0 u^n + rc1 u^{n-1}
-  static constexpr int F = 1, E = 0, NR = 2, NO = 1;
-  __device__ static bool need(const PassArgs& a, int r) { return r == 0 || a.bdf2; }
+struct ProgRhs {  // w = L^{-1} rhs, rhs = u^n (BE), (4u^n - u^{n-1})/3 (BDF2), rc0 u^n + rc1 u^{n-1}
+                  // (variable-step BDF2) or (18u^n - 9u^{n-1} + 2u^{n-2})/11 (BDF3)
+  static constexpr int F = 1, E = 0, NR = 3, NO = 1;
+  __device__ static bool need(const PassArgs& a, int r) { return r == 0 || (r == 1 && a.bdf2) || a.bdf2 == 3; }
   __device__ static void sin(const PassArgs& a, const T* r, T* s) {
-    if (a.bdf2 == 2)
+    if (a.bdf2 == 3)
+      s[0] = (T(18) * r[0] - T(9) * r[1] + T(2) * r[2]) * T(1.0 / 11.0);
+    else if (a.bdf2 == 2)
       s[0] = (T)a.rc0 * r[0] + (T)a.rc1 * r[1];
     else
       s[0] = a.bdf2 ? (T(4) * r[0] - r[1]) * T(1.0 / 3.0) : r[0];

@@ -28,7 +28,8 @@ namespace molt {
                                    double* partials, DevState* st, hipStream_t s);                             \
   hipError_t launch_vch_react_##sfx(const PassArgs& a, DevState* st, size_t n, hipStream_t s);                  \
   hipError_t launch_maxdiff_##sfx(const void* a, const void* b, size_t n, double* partials, double* out,      \
-                                  hipStream_t s);
+                                  hipStream_t s);                                                              \
+  hipError_t launch_lerp_##sfx(void* out, const void* x, const void* y, double c, size_t n, hipStream_t s);
 MOLT_KERN_DECL(f32)
 MOLT_KERN_DECL(f64)
 #undef MOLT_KERN_DECL
@@ -64,6 +65,9 @@ static hipError_t launch_vch_react(int prec, const PassArgs& a, DevState* st, si
 static hipError_t launch_maxdiff(int prec, const void* a, const void* b, size_t n, double* partials, double* out,
                                  hipStream_t s) {
   return MOLT_PREC(launch_maxdiff)(a, b, n, partials, out, s);
+}
+static hipError_t launch_lerp(int prec, void* out, const void* x, const void* y, double c, size_t n, hipStream_t s) {
+  return MOLT_PREC(launch_lerp)(out, x, y, c, n, s);
 }
 #undef MOLT_PREC
 size_t yfused_items(int n, int nx, int batch);
@@ -328,14 +332,16 @@ struct Layout {
 
 static int ncomp_of(const molt_ch_params* p) { return p->model == MOLT_MODEL_VCH ? 2 : 1; }
 
-static Layout ch_layout(const molt_grid* g, int prec, int ncomp) {
+static Layout ch_layout(const molt_grid* g, int prec, int ncomp, bool bdf3 = false) {
   Layout L;
   const size_t esz = prec == MOLT_F64 ? 8 : 4;
   const size_t n = (size_t)g->nx * g->ny;
   size_t off = 0;
   for (int i = 0; i < F_COUNT; ++i) {
     L.fld[i] = off;
-    const bool used = (i != F_E && i != F_LIN) || ncomp == 2;
+    bool used = true;
+    if (i == F_E || i == F_LIN) used = ncomp == 2;
+    if (i == F_HIST2 || i == F_STAGE) used = bdf3;
     off += used ? al256(n * ncomp * esz) : 0;
   }
   L.tot = off;
@@ -358,13 +364,15 @@ static Layout ch_layout(const molt_grid* g, int prec, int ncomp) {
 // one step
 // --------------------------------------------------------------------------
 // omega: BDF2 step ratio dt_n / dt_{n-1} (1: constant steps, eq. BDF2; otherwise the variable-step form)
+// d_u_prev2 (with bdf2): a BDF3 step (eq. BDF3) from u^n, u^{n-1}, u^{n-2}
 static int32_t step_impl(const molt_grid* g, const molt_ch_params* p, void* d_u, void* d_u_prev, bool bdf2,
                          void* d_work, size_t work_bytes, molt_step_info* info, hipStream_t s, int iter_hint,
-                         double omega = 1.0) {
+                         double omega = 1.0, void* d_u_prev2 = nullptr) {
   const int prec = p->precision;
   const int nc = ncomp_of(p);
   const bool vch = nc == 2;
-  const Layout L = ch_layout(g, prec, nc);
+  const bool bdf3 = bdf2 && d_u_prev2 != nullptr;
+  const Layout L = ch_layout(g, prec, nc, p->stepper == MOLT_BDF3);
   if (!d_work || work_bytes < L.total) return fail(MOLT_EWORKSPACE, "workspace smaller than ch_workspace_bytes()");
   char* w = (char*)d_work;
   void* F[F_COUNT];
@@ -380,8 +388,8 @@ static int32_t step_impl(const molt_grid* g, const molt_ch_params* p, void* d_u,
   const bool two_d = ny > 1;
   // variable-step BDF2 (w = omega): v^{n+1} - beta dt F = rc0 v^n + rc1 v^{n-1},
   // beta = (1+w)/(1+2w), rc0 = (1+w)^2/(1+2w), rc1 = -w^2/(1+2w)
-  const bool var = bdf2 && omega != 1.0;
-  const double beta = !bdf2 ? 1.0 : (var ? (1.0 + omega) / (1.0 + 2.0 * omega) : 2.0 / 3.0);
+  const bool var = bdf2 && !bdf3 && omega != 1.0;
+  const double beta = !bdf2 ? 1.0 : (bdf3 ? 6.0 / 11.0 : (var ? (1.0 + omega) / (1.0 + 2.0 * omega) : 2.0 / 3.0));
   const StepParams sp = step_params(p->eps, p->dt, beta, p->sigma0);
   const double al1 = 1.0 / sqrt(sp.s1), al2 = 1.0 / sqrt(sp.s2);
   const double hx = spacing(bc, nx, g->x0, g->x1);
@@ -409,11 +417,12 @@ static int32_t step_impl(const molt_grid* g, const molt_ch_params* p, void* d_u,
   // R = A1^{-1} A2^{-1} rhs, A_i^{-1} = Lx_i^{-1} Ly_i^{-1}
   PassArgs a;
   memset(&a, 0, sizeof(a));
-  a.bdf2 = bdf2 ? (var ? 2 : 1) : 0;
+  a.bdf2 = bdf2 ? (bdf3 ? 3 : (var ? 2 : 1)) : 0;
   a.rc0 = (1.0 + omega) * (1.0 + omega) / (1.0 + 2.0 * omega);
   a.rc1 = -omega * omega / (1.0 + 2.0 * omega);
   a.in[0] = d_u;
   a.in[1] = bdf2 ? d_u_prev : d_u;
+  a.in[2] = bdf3 ? d_u_prev2 : d_u;
   // (vector model: both components at once, stacked as a batch of y-sweeps
   // and as 2*ny rows of x-sweeps)
   const int xl = ny * nc;
@@ -438,7 +447,8 @@ static int32_t step_impl(const molt_grid* g, const molt_ch_params* p, void* d_u,
     a.out[0] = F[F_R];
     HIPCHK(launch_xpass(prec, PROG_SWEEP, cx1, a, nullptr, xl, nullptr, s));
   }
-  // history: u^n -> u_prev (after the rhs has consumed u^{n-1})
+  // history: u^{n-1} -> u_prev2, u^n -> u_prev (after the rhs has consumed them)
+  if (d_u_prev2 && d_u_prev) HIPCHK(launch_copy(prec, d_u_prev2, d_u_prev, n * nc, s));
   if (d_u_prev) HIPCHK(launch_copy(prec, d_u_prev, d_u, n * nc, s));
 
   void* base = p->init == MOLT_INIT_LINEAR ? F[F_R] : d_u;
@@ -544,11 +554,45 @@ static int32_t step_impl(const molt_grid* g, const molt_ch_params* p, void* d_u,
   return conv ? MOLT_OK : MOLT_NOT_CONVERGED;
 }
 
+// SDIRK2 (Sec. 4.2, eta = 1 - sqrt(2)/2), the start-up of BDF3: written for the
+// stage values V1 = v^n + eta dt K1, V2 = W + eta dt K2 with
+// W = v^n + (1-eta) dt K1, the two stage equations are BE steps of size
+// eta dt, from v^n and from W = v^n + ((1-eta)/eta)(V1 - v^n); v^{n+1} = V2.
+// The histories (if given) are rotated: u_prev2 <- u_prev, u_prev <- u^n.
+static int32_t sdirk2_impl(const molt_grid* g, const molt_ch_params* p, void* d_u, void* d_u_prev,
+                           void* d_u_prev2, void* d_work, size_t work_bytes, molt_step_info* info, hipStream_t s) {
+  const int prec = p->precision;
+  const int nc = ncomp_of(p);
+  const Layout L = ch_layout(g, prec, nc, true);
+  if (!d_work || work_bytes < L.total) return fail(MOLT_EWORKSPACE, "workspace smaller than ch_workspace_bytes()");
+  const size_t nel = (size_t)g->nx * g->ny * nc;
+  void* stage = (char*)d_work + L.fld[F_STAGE];
+  const double eta = 1.0 - sqrt(2.0) / 2.0;
+  molt_ch_params q = *p;
+  q.dt = eta * p->dt;
+  molt_step_info i1, i2;
+  HIPCHK(launch_copy(prec, stage, d_u, nel, s));
+  int32_t rc1 = step_impl(g, &q, stage, nullptr, false, d_work, work_bytes, &i1, s, 0);
+  if (rc1 < 0) return rc1;
+  if (d_u_prev2 && d_u_prev) HIPCHK(launch_copy(prec, d_u_prev2, d_u_prev, nel, s));
+  if (d_u_prev) HIPCHK(launch_copy(prec, d_u_prev, d_u, nel, s));
+  HIPCHK(launch_lerp(prec, d_u, d_u, stage, (1.0 - eta) / eta, nel, s));
+  int32_t rc2 = step_impl(g, &q, d_u, nullptr, false, d_work, work_bytes, &i2, s, 0);
+  if (rc2 < 0) return rc2;
+  if (info) {
+    *info = i2;
+    info->iters = i1.iters + i2.iters;
+    info->converged = i1.converged && i2.converged;
+  }
+  return (rc1 == MOLT_NOT_CONVERGED || rc2 == MOLT_NOT_CONVERGED) ? MOLT_NOT_CONVERGED : MOLT_OK;
+}
+
 static int32_t check_params(const molt_ch_params* p) {
   if (!p) return fail(MOLT_EINVAL, "params is NULL");
   if (!(p->eps > 0) || !(p->dt > 0)) return fail(MOLT_EINVAL, "eps and dt must be positive");
   if (!(p->sigma0 > 0)) return fail(MOLT_EINVAL, "sigma0 must be positive");
-  if (p->stepper != MOLT_BE && p->stepper != MOLT_BDF2) return fail(MOLT_EINVAL, "unknown stepper");
+  if (p->stepper != MOLT_BE && p->stepper != MOLT_BDF2 && p->stepper != MOLT_BDF3)
+    return fail(MOLT_EINVAL, "unknown stepper");
   if (p->init != MOLT_INIT_PREV && p->init != MOLT_INIT_LINEAR) return fail(MOLT_EINVAL, "unknown init");
   if (p->fixed_iters < 0) return fail(MOLT_EINVAL, "fixed_iters must be >= 0");
   if (p->model != MOLT_MODEL_CH && p->model != MOLT_MODEL_VCH) return fail(MOLT_EINVAL, "unknown model");
@@ -621,6 +665,7 @@ static int32_t check_instance(const molt_instance& in, int prec) {
   if (rc != MOLT_OK) return rc;
   if (in.grid.ny < 2) return fail(MOLT_EUNSUPPORTED, "batched instances must be two-dimensional");
   if (in.grid.bc == MOLT_BC_DIRICHLET) return fail(MOLT_EUNSUPPORTED, "Dirichlet boundaries are sweep-only");
+  if (in.params.stepper == MOLT_BDF3) return fail(MOLT_EUNSUPPORTED, "batched instances take BE or BDF2");
   if (!in.d_u) return fail(MOLT_EINVAL, "instance field is NULL");
   if (in.nsteps < 0 || in.nsteps > 0x7fffffffLL) return fail(MOLT_EINVAL, "nsteps out of range");
   return MOLT_OK;
@@ -1032,6 +1077,7 @@ static int32_t solve_adaptive_impl(const molt_grid* g, const molt_ch_params* p0,
   molt_ch_params p = *p0;
   p.max_iter = ap->nmaxit;
   p.fixed_iters = 0;
+  p.stepper = MOLT_BDF2;  // Algorithm 1 runs the BE-BDF2 pair whatever stepper was asked for
   double t = 0.0, dt = ap->dt0, dtprev = 0.0;
   bool have_prev = false;
   int32_t m = 0;
@@ -1433,7 +1479,7 @@ int32_t mol_t_helmholtz_sweep(const molt_grid* g, int32_t axis, double alpha, in
 size_t ch_workspace_bytes(const molt_grid* g, const molt_ch_params* p) {
   g_err.clear();
   if (check_params(p) != MOLT_OK || check_grid(g, p->precision) != MOLT_OK) return 0;
-  return ch_layout(g, p->precision, ncomp_of(p)).total;
+  return ch_layout(g, p->precision, ncomp_of(p), p->stepper == MOLT_BDF3).total;
 }
 
 int32_t ch_step(const molt_grid* g, const molt_ch_params* p, void* d_u, void* d_u_prev, void* d_work,
@@ -1444,6 +1490,14 @@ int32_t ch_step(const molt_grid* g, const molt_ch_params* p, void* d_u, void* d_
   rc = check_grid(g, p->precision);
   if (rc != MOLT_OK) return rc;
   if (!d_u) return fail(MOLT_EINVAL, "d_u is NULL");
+  if (p->stepper == MOLT_BDF3) {
+    // d_u_prev: [u^{n-1} | u^{n-2}]; a BDF3 step with both, else an SDIRK2 step
+    const size_t fb = (size_t)g->nx * g->ny * ncomp_of(p) * (p->precision == MOLT_F64 ? 8 : 4);
+    void* prev2 = d_u_prev ? (char*)d_u_prev + fb : nullptr;
+    if (p->have_prev >= 2 && d_u_prev)
+      return step_impl(g, p, d_u, d_u_prev, true, d_work, work_bytes, info, (hipStream_t)stream, 0, 1.0, prev2);
+    return sdirk2_impl(g, p, d_u, d_u_prev, prev2, d_work, work_bytes, info, (hipStream_t)stream);
+  }
   const bool bdf2 = p->stepper == MOLT_BDF2 && p->have_prev && d_u_prev != nullptr;
   return step_impl(g, p, d_u, d_u_prev, bdf2, d_work, work_bytes, info, (hipStream_t)stream, 0);
 }
@@ -1456,16 +1510,23 @@ int32_t ch_solve(const molt_grid* g, const molt_ch_params* p, void* d_u, int64_t
   rc = check_grid(g, p->precision);
   if (rc != MOLT_OK) return rc;
   if (!d_u || nsteps < 0) return fail(MOLT_EINVAL, "d_u is NULL or nsteps < 0");
-  const Layout L = ch_layout(g, p->precision, ncomp_of(p));
+  const bool bdf3 = p->stepper == MOLT_BDF3;
+  const Layout L = ch_layout(g, p->precision, ncomp_of(p), bdf3);
   if (!d_work || work_bytes < L.total) return fail(MOLT_EWORKSPACE, "workspace smaller than ch_workspace_bytes()");
   void* hist = (char*)d_work + L.fld[F_HIST];
+  void* hist2 = (char*)d_work + L.fld[F_HIST2];
   int32_t status = MOLT_OK;
   int hint = 0;
   for (int64_t k = 0; k < nsteps; ++k) {
     const bool bdf2 = p->stepper == MOLT_BDF2 && k > 0;
     molt_step_info inf;
-    rc = step_impl(g, p, d_u, p->stepper == MOLT_BDF2 ? hist : nullptr, bdf2, d_work, work_bytes, &inf,
-                   (hipStream_t)stream, hint);
+    if (bdf3 && k < 2)  // BDF3 start-up: two SDIRK2 steps (Sec. 4.4)
+      rc = sdirk2_impl(g, p, d_u, hist, hist2, d_work, work_bytes, &inf, (hipStream_t)stream);
+    else if (bdf3)
+      rc = step_impl(g, p, d_u, hist, true, d_work, work_bytes, &inf, (hipStream_t)stream, hint, 1.0, hist2);
+    else
+      rc = step_impl(g, p, d_u, p->stepper == MOLT_BDF2 ? hist : nullptr, bdf2, d_work, work_bytes, &inf,
+                     (hipStream_t)stream, hint);
     if (rc < 0) return rc;
     if (rc == MOLT_NOT_CONVERGED) status = MOLT_NOT_CONVERGED;
     hint = inf.iters;

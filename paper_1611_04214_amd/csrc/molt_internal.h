@@ -62,7 +62,8 @@ struct PassArgs {
   double sigma;    // linear part of f moved to the left-hand side
   double kappa;    // a/s1
   int mode;        // 0: full form (first iteration), 1: increment form
-  int bdf2;        // rhs program: 1 -> (4u - u_prev)/3; 2 -> rc0 u + rc1 u_prev (variable steps)
+  int bdf2;        // rhs program: 1 -> (4u - u_prev)/3; 2 -> rc0 u + rc1 u_prev (variable steps);
+                   // 3 -> (18u - 9u_prev + 2u_prev2)/11 (BDF3)
   double rc0, rc1; // variable-step BDF2 rhs coefficients
 };
 
@@ -85,8 +86,9 @@ enum SlotPhase { PH_R = 0, PH_IT = 1, PH_IDLE = 2 };
 
 // workspace fields of one problem
 // (vector model: every field holds both components; F_E, F_LIN hold the
-// reaction and linear parts of the iterate, empty for Cahn-Hilliard)
-enum { F_R = 0, F_DL, F_W, F_A1, F_B1, F_C, F_Q, F_M, F_N, F_HIST, F_E, F_LIN, F_COUNT };
+// reaction and linear parts of the iterate, empty for Cahn-Hilliard; BDF3:
+// F_HIST2 the second history, F_STAGE the SDIRK2 stage value, empty otherwise)
+enum { F_R = 0, F_DL, F_W, F_A1, F_B1, F_C, F_Q, F_M, F_N, F_HIST, F_E, F_LIN, F_HIST2, F_STAGE, F_COUNT };
 
 struct SlotCtl {  // mutable control of one slot (device)
   int phase;      // SlotPhase

@@ -721,6 +721,19 @@ hipError_t MOLT_KFN(launch_diag_vch)(const void* u, int nx, int ny, int bc, doub
   return hipGetLastError();
 }
 
+// out = x + c (y - x)
+template <typename T>
+__global__ void __launch_bounds__(256) lerp_kernel(T* out, const T* x, const T* y, double c, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    out[i] = x[i] + (T)c * (y[i] - x[i]);
+}
+
+hipError_t MOLT_KFN(launch_lerp)(void* out, const void* x, const void* y, double c, size_t n, hipStream_t s) {
+  hipLaunchKernelGGL((lerp_kernel<MOLT_KT>), grid_1d(n), dim3(256), 0, s, (MOLT_KT*)out, (const MOLT_KT*)x,
+                     (const MOLT_KT*)y, c, n);
+  return hipGetLastError();
+}
+
 // max |a - b| -> out[0] (partials: diag_blocks(n) doubles)
 hipError_t MOLT_KFN(launch_maxdiff)(const void* a, const void* b, size_t n, double* partials, double* out,
                                     hipStream_t s) {

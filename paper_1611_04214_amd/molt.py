@@ -18,7 +18,7 @@ LIB_PATH = os.environ.get("MOLT_LIB", os.path.join(HERE, "libmolt.so"))
 MOLT_OK, MOLT_NOT_CONVERGED = 0, 1
 MOLT_EINVAL, MOLT_EUNSUPPORTED, MOLT_EHIP, MOLT_EWORKSPACE = -1, -2, -3, -4
 MOLT_BC_PERIODIC, MOLT_BC_NEUMANN, MOLT_BC_DIRICHLET = 0, 1, 2
-MOLT_BE, MOLT_BDF2 = 0, 1
+MOLT_BE, MOLT_BDF2, MOLT_BDF3 = 0, 1, 2
 MOLT_INIT_PREV, MOLT_INIT_LINEAR = 0, 1
 MOLT_MODEL_CH, MOLT_MODEL_VCH = 0, 1
 #: sigma0 of the vector model (the Hessian of W at its minima is 18 I)

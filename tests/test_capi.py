@@ -56,6 +56,9 @@ def test_workspace_queries(lib):
     p.precision = molt.MOLT_F64
     w64 = molt.ch_workspace_bytes(g, p)
     assert w32 > 10 * 64 * 48 * 4 and w64 > w32
+    # BDF3 keeps a second history and the SDIRK2 stage value: two fields more
+    p.stepper = molt.MOLT_BDF3
+    assert molt.ch_workspace_bytes(g, p) >= w64 + 2 * 64 * 48 * 8
     assert molt.molt_sweep_workspace_bytes(g, 0, molt.MOLT_F32, 1) > 0
     assert molt.molt_sweep_workspace_bytes(g, 1, molt.MOLT_F32, 3) > 3 * 64 * 48 * 4
 
@@ -123,7 +126,7 @@ def test_batch_workspace_query(lib):
 
 
 @pytest.mark.parametrize("case", ["count0", "mixed_precision", "one_d", "dirichlet", "null_field",
-                                  "negative_steps", "bad_params"])
+                                  "negative_steps", "bad_params", "bdf3"])
 def test_batch_argument_checks(lib, case):
     p = molt.make_params(0.02, 1e-5, precision=molt.MOLT_F32)
     g = molt.make_grid(64, 64, bc=molt.MOLT_BC_PERIODIC, M=4)
@@ -144,6 +147,8 @@ def test_batch_argument_checks(lib, case):
         arr[0].nsteps = -1
     elif case == "bad_params":
         arr[1].params.eps = -1.0
+    elif case == "bdf3":
+        arr[0].params.stepper = molt.MOLT_BDF3
     assert molt.ch_batch_workspace_bytes(arr, count) == 0
     rc = molt.ch_solve_batch(arr, count, 1, 1 << 40)
     assert rc in (molt.MOLT_EINVAL, molt.MOLT_EUNSUPPORTED), rc
