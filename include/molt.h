@@ -158,6 +158,12 @@ size_t ch_workspace_bytes(const molt_grid* grid, const molt_ch_params* params);
  * ch_step -- one time step of the Cahn-Hilliard equation (Sec. 3.1 eq. CH_BE,
  * Sec. 4.1 eq. BDF2) by the factored fixed point of Sec. 5.1.
  *  d_u:      in u^n, out u^{n+1} (the paper's u; the shift v = u+1 is internal).
+ *            Dirichlet grids: the walls hold the homogeneous condition of the
+ *            shifted variable (eq. CahnHilliard_v), u = -1 (vector model:
+ *            u = z3 = (-1/2, -sqrt(3)/2)); u^n (and the histories) must hold
+ *            that value on the walls, and u^{n+1} keeps it.  The step shifts
+ *            d_u and the histories in place while it runs and back after it
+ *            (so they may differ from their inputs by one rounding).
  *  d_u_prev: BDF2 history.  If params->have_prev and stepper == BDF2 it holds
  *            u^{n-1} and a BDF2 step is taken; otherwise a BE step.  If not
  *            NULL it receives u^n on return (history rotated in place).  BDF3:

@@ -21,7 +21,10 @@ ARCH = os.environ.get("MOLT_OFFLOAD_ARCH", "gfx950")
 SOURCES = [("molt_kernels.hip", ("MOLT_PART_X",)), ("molt_kernels.hip", ("MOLT_PART_Y",)),
            ("molt_kernels.hip", ("MOLT_PART_X", "MOLT_PREC_F64")), ("molt_kernels.hip", ("MOLT_PART_Y", "MOLT_PREC_F64")),
            ("molt_batch.hip", ()), ("molt_batch.hip", ("MOLT_BATCH_F64",)), ("molt_host.cpp", ())]
-FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+# -ffp-contract=on: a multiply-add is fused only within one source expression,
+# so every kernel that inlines the same device code rounds alike (the batched
+# kernels reproduce the single-problem ones bit for bit)
+FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=on",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 

@@ -35,6 +35,7 @@ __device__ __forceinline__ PassArgs slot_args(const SlotDesc& d, int ph, int pas
   for (int i = 0; i < 6; ++i) a.in[i] = nullptr;
 #pragma unroll
   for (int i = 0; i < 3; ++i) a.out[i] = nullptr;
+  a.ushift[0] = a.ushift[1] = 0.0;  // batched instances hold u (no Dirichlet walls)
   void* const* F = d.fld;
   if (ph == PH_R) {
     a.sigma = 0.0;

@@ -102,20 +102,27 @@ struct ProgRhs {  // w = L^{-1} rhs, rhs = u^n (BE), (4u^n - u^{n-1})/3 (BDF2), 
   }
 };
 
-// reaction part and linear part of the current iterate
-//  full form:      e = g(u) (constant dropped), lin = u
+// reaction part and linear part of the current iterate; the fields hold
+// x = u - c (c = a.ushift[0]: 0, or -1 for the shifted variable v = u + 1 of
+// eq. CahnHilliard_v), g(x) = f(x + c) - sigma x with f(u) = u^3 - u
+//  full form:      e = g(x) (constant dropped when c = 0), lin = x
 //  increment form: e = g(p) - g(q) = dl*(p^2 + p q + q^2 - 1 - sigma), lin = dl,
-//                  p = base + W (current iterate), q = p - dl (previous)
+//                  p = base + c + W (current iterate in u), q = p - dl (previous)
+// (contraction is spelled out, so every kernel that inlines this rounds alike
+// whatever it knows of the arguments)
 template <typename T>
 __device__ __forceinline__ void react_lin(const PassArgs& a, T base, T W, T dl, T& e, T& lin) {
+#pragma clang fp contract(off)
   const T sg = (T)a.sigma;
+  const T c = (T)a.ushift[0];
   if (a.mode == 0) {
-    e = base * base * base - (T(1) + sg) * base;
+    const T bu = base + c;
+    e = fma(-sg, base, fma(bu * bu, bu, -bu));
     lin = base;
   } else {
-    const T p = base + W;
+    const T p = base + c + W;
     const T q = p - dl;
-    e = dl * (p * p + p * q + q * q - T(1) - sg);
+    e = dl * (fma(p, p + q, q * q) - (T(1) + sg));
     lin = dl;
   }
 }
@@ -1165,18 +1172,23 @@ __device__ __forceinline__ void diag_final_body(const double* partials, int nblo
 //    |p|^2 - |q|^2 = Re(d conj(p + q)): every term is proportional to d, so an
 //    FP32 increment keeps its relative accuracy.
 // --------------------------------------------------------------------------
+// (c1, c2): u = stored value + c; 0 when the fields hold u, z3 when they hold
+// the shifted variable v = u - z3 (Dirichlet steps)
 template <typename T>
-__device__ __forceinline__ void vch_react(T b1, T b2, T w1, T w2, T d1, T d2, T sigma, int mode, T* e, T* lin) {
+__device__ __forceinline__ void vch_react(T b1, T b2, T w1, T w2, T d1, T d2, T c1u, T c2u, T sigma, int mode,
+                                          T* e, T* lin) {
+#pragma clang fp contract(off)
   if (mode == 0) {
-    const T p2 = b1 * b1 + b2 * b2;
+    const T u1 = b1 + c1u, u2 = b2 + c2u;
+    const T p2 = u1 * u1 + u2 * u2;
     const T p4 = p2 * p2;
-    // conj(w)^2 = (b1^2 - b2^2, -2 b1 b2)
-    e[0] = T(6) * (p4 * b1 - (b1 * b1 - b2 * b2)) - sigma * b1;
-    e[1] = T(6) * (p4 * b2 + T(2) * b1 * b2) - sigma * b2;
+    // conj(w)^2 = (u1^2 - u2^2, -2 u1 u2)
+    e[0] = T(6) * (p4 * u1 - (u1 * u1 - u2 * u2)) - sigma * b1;
+    e[1] = T(6) * (p4 * u2 + T(2) * u1 * u2) - sigma * b2;
     lin[0] = b1;
     lin[1] = b2;
   } else {
-    const T p1 = b1 + w1, p2c = b2 + w2;  // current iterate p
+    const T p1 = b1 + c1u + w1, p2c = b2 + c2u + w2;  // current iterate p (in u)
     const T q1 = p1 - d1, q2 = p2c - d2;  // previous iterate q
     const T s1 = p1 + q1, s2 = p2c + q2;
     const T P2 = p1 * p1 + p2c * p2c, Q2 = q1 * q1 + q2 * q2;
@@ -1202,12 +1214,13 @@ __device__ __forceinline__ void vch_react_body(const PassArgs& a, size_t n, size
   T* E = (T*)a.out[0];
   T* L = (T*)a.out[1];
   const T sg = (T)a.sigma;
+  const T c1 = (T)a.ushift[0], c2 = (T)a.ushift[1];
   for (size_t i = i0; i < n; i += step) {
     T e[2], lin[2];
     if (a.mode == 0)
-      vch_react<T>(B[i], B[n + i], T(0), T(0), T(0), T(0), sg, 0, e, lin);
+      vch_react<T>(B[i], B[n + i], T(0), T(0), T(0), T(0), c1, c2, sg, 0, e, lin);
     else
-      vch_react<T>(B[i], B[n + i], Wf[i], Wf[n + i], D[i], D[n + i], sg, 1, e, lin);
+      vch_react<T>(B[i], B[n + i], Wf[i], Wf[n + i], D[i], D[n + i], c1, c2, sg, 1, e, lin);
     E[i] = e[0];
     E[n + i] = e[1];
     L[i] = lin[0];

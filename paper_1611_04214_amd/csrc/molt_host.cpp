@@ -29,7 +29,8 @@ namespace molt {
   hipError_t launch_vch_react_##sfx(const PassArgs& a, DevState* st, size_t n, hipStream_t s);                  \
   hipError_t launch_maxdiff_##sfx(const void* a, const void* b, size_t n, double* partials, double* out,      \
                                   hipStream_t s);                                                              \
-  hipError_t launch_lerp_##sfx(void* out, const void* x, const void* y, double c, size_t n, hipStream_t s);
+  hipError_t launch_lerp_##sfx(void* out, const void* x, const void* y, double c, size_t n, hipStream_t s); \
+  hipError_t launch_addc_##sfx(void* x, double c0, double c1, size_t n, int nc, hipStream_t s);
 MOLT_KERN_DECL(f32)
 MOLT_KERN_DECL(f64)
 #undef MOLT_KERN_DECL
@@ -68,6 +69,9 @@ static hipError_t launch_maxdiff(int prec, const void* a, const void* b, size_t 
 }
 static hipError_t launch_lerp(int prec, void* out, const void* x, const void* y, double c, size_t n, hipStream_t s) {
   return MOLT_PREC(launch_lerp)(out, x, y, c, n, s);
+}
+static hipError_t launch_addc(int prec, void* x, double c0, double c1, size_t n, int nc, hipStream_t s) {
+  return MOLT_PREC(launch_addc)(x, c0, c1, n, nc, s);
 }
 #undef MOLT_PREC
 size_t yfused_items(int n, int nx, int batch);
@@ -401,6 +405,20 @@ static int32_t step_impl(const molt_grid* g, const molt_ch_params* p, void* d_u,
     cy2 = make_line(ny, bc, M, al2, hy);
   }
 
+  // Dirichlet walls: the line inverses no longer preserve constants, so the
+  // step runs in the shifted variable of eq. CahnHilliard_v (v = u + 1; the
+  // vector model's v = u - z3), whose walls are homogeneous.  The caller's
+  // field and histories are shifted in place for the step and back after it.
+  const bool vform = bc == MOLT_BC_DIRICHLET;
+  double ush[2] = {0.0, 0.0};
+  if (vform) {
+    ush[0] = vch ? -0.5 : -1.0;
+    ush[1] = vch ? -0.5 * sqrt(3.0) : 0.0;
+    HIPCHK(launch_addc(prec, d_u, -ush[0], -ush[1], n, nc, s));
+    if (d_u_prev) HIPCHK(launch_addc(prec, d_u_prev, -ush[0], -ush[1], n, nc, s));
+    if (d_u_prev2) HIPCHK(launch_addc(prec, d_u_prev2, -ush[0], -ush[1], n, nc, s));
+  }
+
   HIPCHK(launch_state_init(st, p->tol, p->max_iter, p->fixed_iters, s));
   YFused fz;
   memset(&fz, 0, sizeof(fz));
@@ -466,6 +484,8 @@ static int32_t step_impl(const molt_grid* g, const molt_ch_params* p, void* d_u,
       q.sigma = sp.sigma;
       q.kappa = sp.a / sp.s1;
       q.mode = it == 0 ? 0 : 1;
+      q.ushift[0] = ush[0];
+      q.ushift[1] = ush[1];
       // P1 (y, alpha1): a1 = Y1 e, b1 = Y1 lin (vector model: e, lin from the
       // pointwise reaction pass, then both components swept as a batch)
       q.in[0] = base;
@@ -531,6 +551,11 @@ static int32_t step_impl(const molt_grid* g, const molt_ch_params* p, void* d_u,
     batch = batch < 32 ? batch * 2 : 32;
   }
   HIPCHK(launch_finalize(prec, d_u, base, F[F_W], n * nc, s));
+  if (vform) {
+    HIPCHK(launch_addc(prec, d_u, ush[0], ush[1], n, nc, s));
+    if (d_u_prev) HIPCHK(launch_addc(prec, d_u_prev, ush[0], ush[1], n, nc, s));
+    if (d_u_prev2) HIPCHK(launch_addc(prec, d_u_prev2, ush[0], ush[1], n, nc, s));
+  }
   if (vch)
     HIPCHK(launch_diag_vch(prec, d_u, nx, ny, bc, hx, hy, p->eps, partials, st, s));
   else
@@ -664,7 +689,7 @@ static int32_t check_instance(const molt_instance& in, int prec) {
   rc = check_grid(&in.grid, prec);
   if (rc != MOLT_OK) return rc;
   if (in.grid.ny < 2) return fail(MOLT_EUNSUPPORTED, "batched instances must be two-dimensional");
-  if (in.grid.bc == MOLT_BC_DIRICHLET) return fail(MOLT_EUNSUPPORTED, "Dirichlet boundaries are sweep-only");
+  if (in.grid.bc == MOLT_BC_DIRICHLET) return fail(MOLT_EUNSUPPORTED, "batched instances take periodic or Neumann boundaries");
   if (in.params.stepper == MOLT_BDF3) return fail(MOLT_EUNSUPPORTED, "batched instances take BE or BDF2");
   if (!in.d_u) return fail(MOLT_EINVAL, "instance field is NULL");
   if (in.nsteps < 0 || in.nsteps > 0x7fffffffLL) return fail(MOLT_EINVAL, "nsteps out of range");

@@ -65,6 +65,8 @@ struct PassArgs {
   int bdf2;        // rhs program: 1 -> (4u - u_prev)/3; 2 -> rc0 u + rc1 u_prev (variable steps);
                    // 3 -> (18u - 9u_prev + 2u_prev2)/11 (BDF3)
   double rc0, rc1; // variable-step BDF2 rhs coefficients
+  double ushift[2];// u = stored value + ushift, per component: 0 when the fields hold u; the
+                   // shifted variable v = u - ushift of Dirichlet steps otherwise
 };
 
 // Workspace and control of the fused (single-kernel) y-pass.

@@ -734,6 +734,19 @@ hipError_t MOLT_KFN(launch_lerp)(void* out, const void* x, const void* y, double
   return hipGetLastError();
 }
 
+// x += c0 on the first n values, x += c1 on the next n (nc = 2)
+template <typename T>
+__global__ void __launch_bounds__(256) addc_kernel(T* x, double c0, double c1, size_t n, int nc) {
+  const size_t tot = n * (size_t)nc;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < tot; i += (size_t)gridDim.x * blockDim.x)
+    x[i] += (T)(i < n ? c0 : c1);
+}
+
+hipError_t MOLT_KFN(launch_addc)(void* x, double c0, double c1, size_t n, int nc, hipStream_t s) {
+  hipLaunchKernelGGL((addc_kernel<MOLT_KT>), grid_1d(n * (size_t)nc), dim3(256), 0, s, (MOLT_KT*)x, c0, c1, n, nc);
+  return hipGetLastError();
+}
+
 // max |a - b| -> out[0] (partials: diag_blocks(n) doubles)
 hipError_t MOLT_KFN(launch_maxdiff)(const void* a, const void* b, size_t n, double* partials, double* out,
                                     hipStream_t s) {

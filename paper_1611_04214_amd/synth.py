@@ -145,6 +145,22 @@ def u0_vch(seed: int, ny: int, nx: int, stream: int = 0) -> np.ndarray:
     return u.reshape(2, ny, nx)
 
 
+def with_walls(u: np.ndarray, value) -> np.ndarray:
+    """A copy of u with every wall node (first/last row and column; both ends
+    of a 1D line) set to `value` (a scalar, or one value per component for a
+    (2, ny, nx) vector field): inputs for Dirichlet walls."""
+    w = np.array(u, dtype=np.float64, copy=True)
+    comps = [w] if w.ndim < 3 else [w[k] for k in range(w.shape[0])]
+    vals = [value] if w.ndim < 3 else list(value)
+    for f, v in zip(comps, vals):
+        if f.ndim == 1 or f.shape[0] == 1:  # a line: its two ends
+            f.reshape(-1)[[0, -1]] = v
+        else:
+            f[0, :] = f[-1, :] = v
+            f[:, 0] = f[:, -1] = v
+    return w
+
+
 # Served workload: Poisson arrivals of vector-model requests.
 #: seed of the served workload's draws (fifth workload recipe)
 SERVE_SEED = BASE_SEED + 5

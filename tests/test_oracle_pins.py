@@ -426,6 +426,55 @@ def test_linear_reaction_neumann_matches_dense_solve(oracle_mod):
     assert np.abs((un + 1.0).reshape(-1) - v).max() < 1e-12
 
 
+@pytest.mark.parametrize("dt", [0.01, 0.03])
+def test_linear_reaction_dirichlet_matches_dense_solve(oracle_mod, dt):
+    """Dirichlet walls (u = -1, i.e. v = 0 in eq. CahnHilliard_v's variable):
+    every line inverse maps onto fields vanishing at the walls, so on the
+    interior nodes the converged iterate solves, with Lx_i, Ly_i the inverses
+    of the interior blocks of the assembled 1D line operators for alpha_i,
+    (Lx1 + Ly1 - I)(Lx2 + Ly2 - I) v = rhs + (a/s1)(2I - Lx1 - Ly1)(k - sigma) v
+    (dense solve) in the completed-square branch (one alpha, a < eps^2); the
+    walls stay at -1.  (With two alphas the boundary-corrected inverses of
+    different alpha do not commute, so the unsplit form holds only up to their
+    commutator; the two-alpha algebra is pinned by the periodic Fourier test.)"""
+    nx, ny, M, eps, kk = 14, 11, 4, 0.2, 0.9
+    g = oracle_mod.Grid(nx=nx, ny=ny, bc=2, M=M, x0=0, x1=1.0, y0=0, y1=0.8)
+    rng = np.random.default_rng(6)
+    u = 0.2 * rng.standard_normal((ny, nx))
+    u[0, :] = u[-1, :] = -1.0
+    u[:, 0] = u[:, -1] = -1.0
+    p = oracle_mod.Params(eps=eps, dt=dt, tol=1e-15, stepper=oracle_mod.BE, max_iter=50000,
+                          reaction=1, react_k=kk)
+    un, info = oracle_mod.step(g, p, u)
+    wall = np.concatenate([un[0, :], un[-1, :], un[:, 0], un[:, -1]])
+    assert np.abs(wall + 1.0).max() < 1e-14
+    s1, s2, sig = info.s1, info.s2, info.sigma
+    gx = oracle_mod.Grid(nx=nx, bc=2, M=M, x0=0, x1=1.0)
+    gy = oracle_mod.Grid(nx=ny, bc=2, M=M, x0=0, x1=0.8)
+
+    def inner_inv(gl, n, alpha):
+        Sm = np.column_stack([oracle_mod.sweep(gl, 0, alpha, e) for e in np.eye(n)])
+        assert np.abs(Sm[[0, -1]]).max() < 1e-15  # w(a) = w(b) = 0
+        return np.linalg.inv(Sm[1:-1, 1:-1])
+
+    ix, iy = nx - 2, ny - 2
+    I = np.eye(ix * iy)
+    ops = []
+    for s in (s1, s2):
+        al = 1 / np.sqrt(s)
+        Lx = np.kron(np.eye(iy), inner_inv(gx, nx, al))
+        Ly = np.kron(inner_inv(gy, ny, al), np.eye(ix))
+        ops.append((Lx, Ly))
+    # the fixed point of the lagged splitting: (A1 - E1)(A2 - E2) v = rhs +
+    # a Lap (k - sigma) v with A_i - E_i = Lx_i + Ly_i - I and a Lap =
+    # (a/s1)(2I - Lx1 - Ly1) (the second derivatives peeled with alpha_1)
+    H1 = ops[0][0] + ops[0][1] - I
+    H2 = ops[1][0] + ops[1][1] - I
+    A = H1 @ H2 - (dt / s1) * (2 * I - ops[0][0] - ops[0][1]) * (kk - sig)
+    v = np.linalg.solve(A, (u[1:-1, 1:-1] + 1.0).reshape(-1))
+    assert np.abs((un[1:-1, 1:-1] + 1.0).reshape(-1) - v).max() < 1e-12
+
+
 # ----------------------------------------------------------- invariants ------
 def test_periodic_mass_is_conserved(oracle_mod):
     """Each periodic L^{-1} preserves the mean, so BE and BDF2 conserve sum(u)."""
@@ -480,6 +529,22 @@ def test_energy_is_non_increasing(oracle_mod):
     _, infos = oracle_mod.solve(g, p, u, 15)
     e += [i.energy for i in infos]
     assert all(e[i + 1] <= e[i] + 1e-12 * abs(e[i]) for i in range(len(e) - 1))
+
+
+@pytest.mark.parametrize("stepper", ["BE", "BDF2", "BDF3"])
+def test_dirichlet_walls_hold_and_energy_decreases(oracle_mod, stepper):
+    """Dirichlet walls at u = -1 (v = 0): every step keeps them (to rounding)
+    and the energy does not increase, for each stepper and both branches."""
+    g = oracle_mod.Grid(nx=40, ny=33, bc=2, M=4, x0=0, x1=1.0, y0=0, y1=0.8)
+    u = synth.with_walls(synth.u0_uniform_noise(synth.BASE_SEED + 3, 33, 40, 0.3), -1.0)
+    stp = {"BE": oracle_mod.BE, "BDF2": oracle_mod.BDF2, "BDF3": oracle_mod.BDF3}[stepper]
+    for dt in (1e-4, 3e-3):
+        p = oracle_mod.Params(eps=0.03, dt=dt, tol=1e-11, stepper=stp, max_iter=5000)
+        un, infos = oracle_mod.solve(g, p, u, 5)
+        wall = np.concatenate([un[0, :], un[-1, :], un[:, 0], un[:, -1]])
+        assert np.abs(wall + 1.0).max() < 1e-13
+        e = [oracle_mod.energy(g, 0.03, u)] + [i.energy for i in infos]
+        assert all(e[i + 1] <= e[i] + 1e-12 * abs(e[i]) for i in range(len(e) - 1)), (dt, e)
 
 
 def test_backward_euler_is_first_order(oracle_mod):
