@@ -63,7 +63,8 @@ BYTES_PER_POINT_FUSED = {"yfin_P1": (12 + 8, 4 + 8), "yfin_P3": (8 + 8, 8 + 8)}
 
 
 COUNTERS = os.path.join(ROOT, "profiles", "xpass_4096_fp32_hbm_counters.md")
-KERNEL_SOURCES = ("molt_device.h", "molt_kernels.hip", "molt_internal.h")
+# what decides the x-pass kernel's code: its sources and the compile flags
+KERNEL_SOURCES = ("csrc/molt_device.h", "csrc/molt_kernels.hip", "csrc/molt_internal.h", "build.py")
 
 
 def counter_traffic(kernel: str, n: int):
@@ -80,7 +81,7 @@ def counter_traffic(kernel: str, n: int):
             kv[k.strip()] = v.strip()
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_1611_04214_amd", "csrc", f), "rb") as fh:
+        with open(os.path.join(ROOT, "paper_1611_04214_amd", f), "rb") as fh:
             h.update(fh.read())
     if kv.get("kernel") != kernel or kv.get("kernel_sources_sha256") != h.hexdigest():
         return None
