@@ -19,7 +19,10 @@ reported beside it.
 Also printed on the same JSON line:
   roofline      the dominant kernel's algorithmic HBM bytes per launch divided
                 by its average duration, timed with HIP events on the library's
-                launch stream over the timed region, against 8 TB/s;
+                launch stream over the timed region, against 8 TB/s (the last
+                warm-up step times every kernel, which names the dominant one
+                and gives the `kernels` breakdown; the timed steps time that
+                kernel alone, as events around every launch slow the stream);
   cpu_baseline  the FP64 oracle on a bounded sample of the same workload
                 (first BE step of the full field with a fixed number of
                 iterations), on this host's cores;
@@ -343,15 +346,30 @@ def main():
 
     step_idx = 0
     warm = []
-    for _ in range(args.warmup):
+    warm_prof = {}
+    for k in range(args.warmup):
+        # the last warm-up step times every kernel (per-kernel breakdown, and the
+        # dominant kernel); the timed steps then time that kernel alone, since
+        # the events around every launch would slow the stream measurably
+        last = k == args.warmup - 1 and not args.no_profile
+        if last:
+            molt.molt_profile_only(-1)
+            molt.molt_profile(1)
         t = time.perf_counter()
         inf = one_step(step_idx)
         step_idx += 1
         warm.append((inf.iters, time.perf_counter() - t))
+        if last:
+            warm_prof = molt.molt_profile_read()
+            molt.molt_profile(0)
         print(f"warmup step {step_idx}: iters={inf.iters} residual={inf.residual:.3e} "
               f"time={warm[-1][1]:.3f}s", file=sys.stderr, flush=True)
 
     if not args.no_profile:
+        fused_w = "ytot_P1" not in warm_prof
+        table_w = dict(BYTES_PER_POINT, **(BYTES_PER_POINT_FUSED if fused_w else {}))
+        dom_w = max((k for k in warm_prof if k in table_w), key=lambda k: warm_prof[k][1], default=None)
+        molt.molt_profile_only(molt.kind_of(dom_w) if dom_w is not None else -1)
         molt.molt_profile(1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -365,6 +383,7 @@ def main():
     t1 = time.perf_counter()
     prof = molt.molt_profile_read() if not args.no_profile else {}
     molt.molt_profile(0)
+    molt.molt_profile_only(-1)
 
     elapsed = t1 - t0
     iters = [i.iters for i in infos]
@@ -374,12 +393,14 @@ def main():
     value = executed / elapsed / 1e9
 
     roof = None
-    kernels = {}
+    # per-kernel breakdown: the last warm-up step (every kernel timed), else
+    # the timed steps when there was no warm-up
+    every = warm_prof or prof
+    kernels = {kname: {"launches": launches, "avg_us": 1e3 * ms / max(launches, 1)}
+               for kname, (launches, ms) in every.items()}
     if prof:
         nsteps = len(infos)
-        for kname, (launches, ms) in prof.items():
-            kernels[kname] = {"launches": launches, "avg_us": 1e3 * ms / max(launches, 1)}
-        fused = "ytot_P1" not in prof
+        fused = "ytot_P1" not in every
         table = dict(BYTES_PER_POINT, **(BYTES_PER_POINT_FUSED if fused else {}))
         dom = max((k for k in prof if k in table), key=lambda k: prof[k][1], default=None)
         if dom is not None:
@@ -397,8 +418,10 @@ def main():
                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": counter_traffic(dom, n),
                     "kernel": dom + (" (single-kernel y-pass)" if fused and dom.startswith("yfin") else ""),
                     "bytes_per_launch": per_launch, "avg_launch_us": round(avg_s * 1e6, 2)}
-            total_ms = sum(v[1] for v in prof.values())
-            roof["kernel_share_of_gpu_time"] = round(ms / total_ms, 3) if total_ms > 0 else None
+            total_ms = sum(v[1] for v in every.values())
+            roof["kernel_share_of_gpu_time"] = (round(every[dom][1] / total_ms, 3)
+                                                if total_ms > 0 and dom in every else None)
+            roof["timed_in_timed_steps"] = sorted(prof)
 
     batched = run_batched(args, molt, synth) if args.batch_steps > 0 else None
     served = run_served(args, molt, synth) if args.serve_count > 0 else None

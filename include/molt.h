@@ -341,7 +341,11 @@ int32_t molt_autotune(int32_t precision, int32_t max_n, void* d_work, size_t wor
  * combine, 3 y-pass final, 4 pointwise; program 0 sweep, 1 rhs sweep, 2-5 the
  * four fixed-point passes P1-P4.  molt_profile(1) enables and resets,
  * molt_profile(0) disables; molt_profile_read fills up to max_entries kinds
- * that ran and returns how many.  Process-wide; use from one thread.
+ * that ran and returns how many.  molt_profile_only(kind) restricts the timing
+ * to one kind (two events per launch of it, none elsewhere: the events cost
+ * the stream a few microseconds each), molt_profile_only(-1) times every kind
+ * again; MOLT_EINVAL for a kind outside -1..47.  Process-wide; use from one
+ * thread.
  */
 typedef struct {
   int32_t kind;
@@ -349,6 +353,7 @@ typedef struct {
   double total_ms;
 } molt_prof_entry;
 int32_t molt_profile(int32_t enable);
+int32_t molt_profile_only(int32_t kind);
 int32_t molt_profile_read(molt_prof_entry* out, int32_t max_entries);
 
 /*

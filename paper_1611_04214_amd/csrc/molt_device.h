@@ -54,6 +54,8 @@ __device__ __forceinline__ int wrapi(int j, int n) {
   int r = j % n;
   return r < 0 ? r + n : r;
 }
+// j in [-n, 2n): one correction instead of a division
+__device__ __forceinline__ int wrap1(int j, int n) { return j < 0 ? j + n : (j >= n ? j - n : j); }
 
 // --------------------------------------------------------------------------
 // pass programs
@@ -115,16 +117,16 @@ __device__ __forceinline__ void react_lin(const PassArgs& a, T base, T W, T dl, 
 #pragma clang fp contract(off)
   const T sg = (T)a.sigma;
   const T c = (T)a.ushift[0];
-  if (a.mode == 0) {
-    const T bu = base + c;
-    e = fma(-sg, base, fma(bu * bu, bu, -bu));
-    lin = base;
-  } else {
-    const T p = base + c + W;
-    const T q = p - dl;
-    e = dl * (fma(p, p + q, q * q) - (T(1) + sg));
-    lin = dl;
-  }
+  // both forms, then a select: no branch for the compiler to sink the loads of
+  // W and dl into
+  const T bu = base + c;
+  const T e0 = fma(-sg, base, fma(bu * bu, bu, -bu));
+  const T p = base + c + W;
+  const T q = p - dl;
+  const T e1 = dl * (fma(p, p + q, q * q) - (T(1) + sg));
+  const bool full = a.mode == 0;
+  e = full ? e0 : e1;
+  lin = full ? base : dl;
 }
 
 template <typename T>
@@ -244,11 +246,23 @@ template <typename T> struct ProgOf<PROG_P2, T> { using type = ProgP2<T>; };
 template <typename T> struct ProgOf<PROG_P3, T> { using type = ProgP3<T>; };
 template <typename T> struct ProgOf<PROG_P4, T> { using type = ProgP4<T>; };
 
+// field f of a program's raw inputs, or field 0 (always read, same size) in
+// place of a field it does not read: loads are then unconditional, so the
+// compiler can issue all of a thread's loads before the first use, and the
+// stand-in loads hit the cache lines of field 0's
+template <typename T, class P>
+__device__ __forceinline__ const T* raw_ptr(const PassArgs& a, int f) {
+  return (const T*)(P::need(a, f) ? a.in[f] : a.in[0]);
+}
+
 // raw values of one node (scalar loads; fields the program does not read are 0)
 template <typename T, class P>
 __device__ __forceinline__ void load_raw(const PassArgs& a, size_t i, T* r) {
 #pragma unroll
-  for (int f = 0; f < P::NR; ++f) r[f] = P::need(a, f) ? ((const T*)a.in[f])[i] : T(0);
+  for (int f = 0; f < P::NR; ++f) {
+    const T v = raw_ptr<T, P>(a, f)[i];
+    r[f] = P::need(a, f) ? v : T(0);
+  }
 }
 
 // 16-byte vector access of 16/sizeof(T) consecutive elements
@@ -290,24 +304,18 @@ struct Seg {
                          T (&s)[F][W]) {
     const int n = c.n;
     constexpr bool per = PER;
+    const bool near = n >= K + H;  // then every window index is within one period
     if (vec && j0 + K <= n) {
 #pragma unroll
       for (int q = 0; q < K / V; ++q) {
         T r[NR][V];
 #pragma unroll
-        for (int f = 0; f < NR; ++f) {
-          if (P::need(a, f)) {
-            ld16((const T*)a.in[f] + lbase + (size_t)(j0 + q * V), r[f]);
-          } else {
-#pragma unroll
-            for (int v = 0; v < V; ++v) r[f][v] = T(0);
-          }
-        }
+        for (int f = 0; f < NR; ++f) ld16(raw_ptr<T, P>(a, f) + lbase + (size_t)(j0 + q * V), r[f]);
 #pragma unroll
         for (int v = 0; v < V; ++v) {
           T rv[NR], sv[F], xv[E > 0 ? E : 1];
 #pragma unroll
-          for (int f = 0; f < NR; ++f) rv[f] = r[f][v];
+          for (int f = 0; f < NR; ++f) rv[f] = P::need(a, f) ? r[f][v] : T(0);
           P::sin(a, rv, sv);
 #pragma unroll
           for (int f = 0; f < F; ++f) s[f][H + q * V + v] = sv[f];
@@ -322,7 +330,7 @@ struct Seg {
 #pragma unroll
       for (int k = 0; k < K; ++k) {
         const int j = j0 + k;
-        const int jj = per ? wrapi(j, n) : min(j, n - 1);
+        const int jj = per ? (near ? wrap1(j, n) : wrapi(j, n)) : min(j, n - 1);
         T rv[NR], sv[F], xv[E > 0 ? E : 1];
         load_raw<T, P>(a, lbase + (size_t)jj * stride, rv);
         P::sin(a, rv, sv);
@@ -339,7 +347,7 @@ struct Seg {
     for (int k = 0; k < 2 * H; ++k) {  // halo nodes (ends of non-periodic lines: clamped, replaced below)
       const int kk = k < H ? k : K + k;
       const int j = j0 - H + kk;
-      const int jj = per ? wrapi(j, n) : min(max(j, 0), n - 1);
+      const int jj = per ? (near ? wrap1(j, n) : wrapi(j, n)) : min(max(j, 0), n - 1);
       T rv[NR], sv[F];
       load_raw<T, P>(a, lbase + (size_t)jj * stride, rv);
       P::sin(a, rv, sv);
@@ -645,25 +653,25 @@ __device__ __forceinline__ void xpass_body(const LineCoef& c, const PassArgs& a,
   // phase A: coalesced loads, the program's pointwise part in the load layout
   if (act) {
     if (vec) {
+      // every load of the thread first (positions past the line read its
+      // first element and are dropped), then the pointwise part
+      T r[K / V][NR][V];
+#pragma unroll
+      for (int it = 0; it < K / V; ++it) {
+        const int e0 = (it * TL + t) * V;
+        const size_t off = lbase + (size_t)(e0 < n ? e0 : 0);
+#pragma unroll
+        for (int f = 0; f < NR; ++f) ld16(raw_ptr<T, P>(a, f) + off, r[it][f]);
+      }
 #pragma unroll
       for (int it = 0; it < K / V; ++it) {
         const int e0 = (it * TL + t) * V;
         if (e0 < n) {
-          T r[NR][V];
-#pragma unroll
-          for (int f = 0; f < NR; ++f) {
-            if (P::need(a, f)) {
-              ld16((const T*)a.in[f] + lbase + (size_t)e0, r[f]);
-            } else {
-#pragma unroll
-              for (int v = 0; v < V; ++v) r[f][v] = T(0);
-            }
-          }
 #pragma unroll
           for (int v = 0; v < V; ++v) {
             T rv[NR], sv[F], xv[E > 0 ? E : 1];
 #pragma unroll
-            for (int f = 0; f < NR; ++f) rv[f] = r[f][v];
+            for (int f = 0; f < NR; ++f) rv[f] = P::need(a, f) ? r[it][f][v] : T(0);
             P::sin(a, rv, sv);
 #pragma unroll
             for (int f = 0; f < F; ++f) sh_row[f][MOLT_PAD(rowoff + e0 + v)] = sv[f];

@@ -160,7 +160,10 @@ hipEvent_t ev_get() {
 }
 }  // namespace
 
+static int g_prof_only = -1;  // time only this kind (-1: every kind)
+
 void prof_begin(int kind, hipStream_t s) {
+  if (g_prof_only >= 0 && kind != g_prof_only) return;
   std::lock_guard<std::mutex> lk(g_prof_mu);
   hipEvent_t e = ev_get();
   if (e) (void)hipEventRecord(e, s);
@@ -168,6 +171,7 @@ void prof_begin(int kind, hipStream_t s) {
 }
 
 void prof_end(int kind, hipStream_t s) {
+  if (g_prof_only >= 0 && kind != g_prof_only) return;
   std::lock_guard<std::mutex> lk(g_prof_mu);
   hipEvent_t e = ev_get();
   if (e) (void)hipEventRecord(e, s);
@@ -1431,6 +1435,13 @@ int32_t molt_profile(int32_t enable) {
     g_prof_n[k] = 0;
   }
   g_prof_on = enable != 0;
+  return MOLT_OK;
+}
+
+int32_t molt_profile_only(int32_t kind) {
+  if (kind < -1 || kind >= kProfKinds) return fail(MOLT_EINVAL, "profile kind out of range");
+  prof_drain();
+  g_prof_only = kind;
   return MOLT_OK;
 }
 

@@ -31,7 +31,8 @@ EXPORTS = ("mol_t_helmholtz_sweep", "molt_sweep_workspace_bytes", "ch_workspace_
            "ch_solve_batch", "molt_tune_get", "molt_tune_set",
            "molt_autotune_workspace_bytes", "molt_autotune", "molt_server_footprint", "molt_server_bytes",
            "molt_server_create", "molt_server_submit", "molt_server_run", "molt_server_poll",
-           "molt_server_destroy", "molt_strerror", "molt_last_error", "molt_profile", "molt_profile_read",
+           "molt_server_destroy", "molt_strerror", "molt_last_error", "molt_profile", "molt_profile_only",
+           "molt_profile_read",
            "molt_set_option")
 MOLT_TUNE_CLASSES = 7
 MOLT_OPT_FUSED_Y_MIN_ITEMS, MOLT_OPT_BATCH_TICKS, MOLT_OPT_BATCH_GRAPH = 1, 2, 3
@@ -43,6 +44,12 @@ PROGRAMS = ("sweep", "rhs", "P1", "P2", "P3", "P4", "P1v", "P2v")
 def kind_name(kind: int) -> str:
     f, p = divmod(kind, 8)
     return f"{KERNEL_FAMILIES[f]}_{PROGRAMS[p] if p < len(PROGRAMS) else p}"
+
+
+def kind_of(name: str) -> int:
+    """Inverse of kind_name."""
+    fam, prog = name.split("_", 1)
+    return KERNEL_FAMILIES.index(fam) * 8 + PROGRAMS.index(prog)
 
 
 class molt_grid(ctypes.Structure):
@@ -161,6 +168,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.molt_set_option.restype = ctypes.c_int32
     lib.molt_profile.argtypes = [ctypes.c_int32]
     lib.molt_profile.restype = ctypes.c_int32
+    lib.molt_profile_only.argtypes = [ctypes.c_int32]
+    lib.molt_profile_only.restype = ctypes.c_int32
     lib.molt_profile_read.argtypes = [ctypes.POINTER(molt_prof_entry), ctypes.c_int32]
     lib.molt_profile_read.restype = ctypes.c_int32
     _lib = lib
@@ -295,6 +304,10 @@ def molt_set_option(option: int, value: int) -> int:
 
 def molt_profile(enable: int) -> int:
     return load().molt_profile(enable)
+
+
+def molt_profile_only(kind: int) -> int:
+    return load().molt_profile_only(kind)
 
 
 def molt_profile_read(max_entries: int = 48) -> dict:
