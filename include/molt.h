@@ -90,8 +90,9 @@ typedef struct {
  *  eps, dt      > 0
  *  tol          stop when max|v^{k+1} - v^k| < tol (ignored if fixed_iters > 0)
  *  sigma0       f'(0) of the shifted reaction; 2 for Cahn-Hilliard
- *  stepper      MOLT_BE, MOLT_BDF2 or MOLT_BDF3 (ch_step, ch_solve; batched and
- *               served instances take MOLT_BE or MOLT_BDF2)
+ *  stepper      MOLT_BE, MOLT_BDF2 or MOLT_BDF3 (ch_step, ch_solve, Cahn-Hilliard
+ *               model; the vector model and batched and served instances take
+ *               MOLT_BE or MOLT_BDF2: MOLT_EUNSUPPORTED otherwise)
  *  max_iter     iteration cap (the step reports MOLT_NOT_CONVERGED if reached)
  *  init         MOLT_INIT_PREV or MOLT_INIT_LINEAR
  *  precision    MOLT_F64 or MOLT_F32

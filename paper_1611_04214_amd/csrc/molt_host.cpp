@@ -626,7 +626,17 @@ static int32_t check_params(const molt_ch_params* p) {
   if (p->fixed_iters < 0) return fail(MOLT_EINVAL, "fixed_iters must be >= 0");
   if (p->model != MOLT_MODEL_CH && p->model != MOLT_MODEL_VCH) return fail(MOLT_EINVAL, "unknown model");
   if (p->fixed_iters == 0 && (p->max_iter < 1 || !(p->tol >= 0))) return fail(MOLT_EINVAL, "need max_iter >= 1 and tol >= 0");
+  if (p->model == MOLT_MODEL_VCH && p->stepper == MOLT_BDF3)
+    return fail(MOLT_EUNSUPPORTED, "the vector model takes BE or BDF2");
   return MOLT_OK;
+}
+
+// the adaptive driver runs its own BE-BDF2 pair: the stepper asked for is not checked
+static int32_t check_adapt_params(const molt_ch_params* p) {
+  if (!p) return fail(MOLT_EINVAL, "params is NULL");
+  molt_ch_params q = *p;
+  q.stepper = MOLT_BDF2;
+  return check_params(&q);
 }
 
 // --------------------------------------------------------------------------
@@ -1688,7 +1698,7 @@ int32_t ch_solve_batch(const molt_instance* inst, int32_t count, void* d_work, s
 
 size_t ch_adaptive_workspace_bytes(const molt_grid* g, const molt_ch_params* p) {
   g_err.clear();
-  if (check_params(p) != MOLT_OK || check_grid(g, p->precision) != MOLT_OK) return 0;
+  if (check_adapt_params(p) != MOLT_OK || check_grid(g, p->precision) != MOLT_OK) return 0;
   return adapt_layout(g, p).total;
 }
 
@@ -1696,7 +1706,7 @@ int32_t ch_solve_adaptive(const molt_grid* g, const molt_ch_params* p, const mol
                           void* d_work, size_t work_bytes, molt_adapt_record* rec, int32_t max_rec, int32_t* nrec,
                           double* t_final, void* stream) {
   g_err.clear();
-  int32_t rc = check_params(p);
+  int32_t rc = check_adapt_params(p);
   if (rc != MOLT_OK) return rc;
   rc = check_grid(g, p->precision);
   if (rc != MOLT_OK) return rc;

@@ -91,6 +91,15 @@ def test_bad_params_are_rejected(lib, change):
     assert molt.ch_step(g, p, 1, 0, 1, 1 << 30) == molt.MOLT_EINVAL
 
 
+def test_vector_model_with_bdf3_is_unsupported(lib):
+    g = molt.make_grid(32, 32, M=4)
+    p = molt.make_params(0.05, 1e-5, stepper=molt.MOLT_BDF3, model=molt.MOLT_MODEL_VCH)
+    assert molt.ch_workspace_bytes(g, p) == 0
+    assert molt.ch_step(g, p, 1, 0, 1, 1 << 30) == molt.MOLT_EUNSUPPORTED
+    # the adaptive driver ignores the stepper
+    assert molt.ch_adaptive_workspace_bytes(g, p) > 0
+
+
 def test_small_workspace_is_rejected(lib):
     g = molt.make_grid(32, 32, M=4)
     p = molt.make_params(0.05, 1e-3)
