@@ -326,7 +326,9 @@ int32_t molt_server_destroy(molt_server* server);
  *  molt_autotune: for every class up to max_n (128..8192 FP32, ..4096 FP64),
  *    times an iteration y-pass for each ky, then an iteration x-pass for each
  *    kx, on an n x n periodic field in the caller's workspace (at least
- *    molt_autotune_workspace_bytes), and stores the fastest shapes.
+ *    molt_autotune_workspace_bytes), and stores the fastest shapes; the
+ *    current entry is timed first and a shape replaces it only when at least
+ *    3 % faster (8 timed launches each), so that repeated tunings agree.
  *    Synchronizes `stream`.
  */
 #define MOLT_TUNE_CLASSES 7

@@ -43,8 +43,9 @@ CASES = [
     ("1d_fact", 129, 1, 1.0, 0.05, 5e-3, 6),
     ("2d_cs", 45, 33, 0.7, 0.03, 2e-4, 4),
     ("2d_fact", 45, 33, 0.7, 0.03, 2e-3, 2),
-    ("2d_tiles", 530, 300, 0.56, 0.01, 1e-4, 4),
 ]
+# several x tiles and y segments and a ragged tail: one stepper, one initial iterate
+TILES = ("2d_tiles", 530, 300, 0.56, 0.01, 1e-4, 4)
 STEPPERS = {"BE": (molt.MOLT_BE, oracle.BE), "BDF2": (molt.MOLT_BDF2, oracle.BDF2),
             "BDF3": (molt.MOLT_BDF3, oracle.BDF3)}
 
@@ -58,13 +59,13 @@ def _fields(nx, ny, seed):
     return u, up, up2
 
 
-@pytest.mark.parametrize("c", CASES, ids=[c[0] for c in CASES])
-@pytest.mark.parametrize("stepper", list(STEPPERS))
-@pytest.mark.parametrize("init", [molt.MOLT_INIT_PREV, molt.MOLT_INIT_LINEAR])
+STEP_PARAMS = [(c, s, i) for c in CASES for s in STEPPERS for i in (molt.MOLT_INIT_PREV, molt.MOLT_INIT_LINEAR)]
+STEP_PARAMS.append((TILES, "BDF2", molt.MOLT_INIT_LINEAR))
+
+
+@pytest.mark.parametrize("c,stepper,init", STEP_PARAMS, ids=[f"{c[0]}-{s}-{i}" for c, s, i in STEP_PARAMS])
 def test_dirichlet_step_fixed_iterations_fp64(c, stepper, init):
     name, nx, ny, y1, eps, dt, M = c
-    if name == "2d_tiles" and (stepper != "BDF2" or init != molt.MOLT_INIT_LINEAR):
-        pytest.skip("the multi-tile shape runs one stepper and initial iterate")
     g = molt.make_grid(nx, ny, 0.0, 1.0, 0.0, y1, molt.MOLT_BC_DIRICHLET, M)
     u, up, up2 = _fields(nx, ny, 51)
     ms, os_ = STEPPERS[stepper]
