@@ -32,6 +32,7 @@
 #ifndef MOLT_OCC
 #define MOLT_OCC 2
 #endif
+
 #define MOLT_PASS_ATTR __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MOLT_OCC)))
 
 namespace molt {
@@ -75,6 +76,7 @@ enum ProgId { PROG_SWEEP = 0, PROG_RHS = 1, PROG_P1 = 2, PROG_P2 = 3, PROG_P3 = 
 template <typename T>
 struct ProgSweep {  // w = L^{-1} in0
   static constexpr int F = 1, E = 0, NR = 1, NO = 1;
+  static constexpr bool NT = true;
   __device__ static bool need(const PassArgs&, int) { return true; }
   __device__ static void sin(const PassArgs&, const T* r, T* s) { s[0] = r[0]; }
   __device__ static void ext(const PassArgs&, const T*, T*) {}
@@ -88,6 +90,7 @@ template <typename T>
 struct ProgRhs {  // w = L^{-1} rhs, rhs = u^n (BE), (4u^n - u^{n-1})/3 (BDF2), rc0 u^n + rc1 u^{n-1}
                   // (variable-step BDF2) or (18u^n - 9u^{n-1} + 2u^{n-2})/11 (BDF3)
   static constexpr int F = 1, E = 0, NR = 3, NO = 1;
+  static constexpr bool NT = true;
   __device__ static bool need(const PassArgs& a, int r) { return r == 0 || (r == 1 && a.bdf2) || a.bdf2 == 3; }
   __device__ static void sin(const PassArgs& a, const T* r, T* s) {
     if (a.bdf2 == 3)
@@ -132,6 +135,7 @@ __device__ __forceinline__ void react_lin(const PassArgs& a, T base, T W, T dl, 
 template <typename T>
 struct ProgP1 {  // y, alpha1: raw (base, W, dl) -> a1 = Y1 e, b1 = Y1 lin
   static constexpr int F = 2, E = 0, NR = 3, NO = 2;
+  static constexpr bool NT = true;
   __device__ static bool need(const PassArgs& a, int r) { return r == 0 || a.mode; }
   __device__ static void sin(const PassArgs& a, const T* r, T* s) { react_lin<T>(a, r[0], r[1], r[2], s[0], s[1]); }
   __device__ static void ext(const PassArgs&, const T*, T*) {}
@@ -145,6 +149,7 @@ struct ProgP1 {  // y, alpha1: raw (base, W, dl) -> a1 = Y1 e, b1 = Y1 lin
 template <typename T>
 struct ProgP2 {  // x, alpha1: raw (a1, b1, base, W, dl) -> C = X1(2 a1 - e) - a1, q = b1 + X1(lin - b1)
   static constexpr int F = 2, E = 2, NR = 5, NO = 2;
+  static constexpr bool NT = true;
   __device__ static bool need(const PassArgs& a, int r) { return r < 3 || a.mode; }
   __device__ static void sin(const PassArgs& a, const T* r, T* s) {
     T e, lin;
@@ -166,6 +171,7 @@ struct ProgP2 {  // x, alpha1: raw (a1, b1, base, W, dl) -> C = X1(2 a1 - e) - a
 template <typename T>
 struct ProgP3 {  // y, alpha2: raw (C, q) -> m = Y2(q + kappa C) - q, n = Y2 q
   static constexpr int F = 2, E = 1, NR = 2, NO = 2;
+  static constexpr bool NT = true;
   __device__ static bool need(const PassArgs&, int) { return true; }
   __device__ static void sin(const PassArgs& a, const T* r, T* s) {
     s[0] = r[1] + (T)a.kappa * r[0];
@@ -182,6 +188,7 @@ struct ProgP3 {  // y, alpha2: raw (C, q) -> m = Y2(q + kappa C) - q, n = Y2 q
 template <typename T>
 struct ProgP4 {  // x, alpha2: raw (m, n, dl|R, W) -> dl' = (dl|R) + X2 m - n ; W' = W + dl' (| dl')
   static constexpr int F = 1, E = 3, NR = 4, NO = 2;
+  static constexpr bool NT = false;  // (see the note at st16_nt)
   __device__ static bool need(const PassArgs& a, int r) { return r < 3 || a.mode; }
   __device__ static void sin(const PassArgs&, const T* r, T* s) { s[0] = r[0]; }
   __device__ static void ext(const PassArgs& a, const T* r, T* x) {
@@ -203,6 +210,7 @@ struct ProgP4 {  // x, alpha2: raw (m, n, dl|R, W) -> dl' = (dl|R) + X2 m - n ; 
 template <typename T>
 struct ProgP1V {  // y, alpha1: raw (e, lin) -> a1 = Y1 e, b1 = Y1 lin
   static constexpr int F = 2, E = 0, NR = 2, NO = 2;
+  static constexpr bool NT = true;
   __device__ static bool need(const PassArgs&, int) { return true; }
   __device__ static void sin(const PassArgs&, const T* r, T* s) {
     s[0] = r[0];
@@ -219,6 +227,7 @@ struct ProgP1V {  // y, alpha1: raw (e, lin) -> a1 = Y1 e, b1 = Y1 lin
 template <typename T>
 struct ProgP2V {  // x, alpha1: raw (a1, b1, e, lin) -> C = X1(2 a1 - e) - a1, q = b1 + X1(lin - b1)
   static constexpr int F = 2, E = 2, NR = 4, NO = 2;
+  static constexpr bool NT = true;
   __device__ static bool need(const PassArgs&, int) { return true; }
   __device__ static void sin(const PassArgs&, const T* r, T* s) {
     s[0] = T(2) * r[0] - r[2];
@@ -266,8 +275,11 @@ __device__ __forceinline__ void load_raw(const PassArgs& a, size_t i, T* r) {
 }
 
 // 16-byte vector access of 16/sizeof(T) consecutive elements
+// (FP32: a streaming load; the x-pass reads each input once, and at 4096^2 the
+// hint took the P2 x-pass from 85.6 to 83.3 us)
 __device__ __forceinline__ void ld16(const float* p, float* o) {
-  const float4 v = *(const float4*)p;
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  const v4 v = __builtin_nontemporal_load((const v4*)p);
   o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
 }
 __device__ __forceinline__ void ld16(const double* p, double* o) {
@@ -276,6 +288,30 @@ __device__ __forceinline__ void ld16(const double* p, double* o) {
 }
 __device__ __forceinline__ void st16(float* p, const float* o) { *(float4*)p = make_float4(o[0], o[1], o[2], o[3]); }
 __device__ __forceinline__ void st16(double* p, const double* o) { *(double2*)p = make_double2(o[0], o[1]); }
+
+// Nontemporal (streaming) stores for the line passes' outputs: on the MI355X
+// they cut the x-pass P2 from 98 to 84 us and the P1 y-pass final kernel from
+// 71 to 60 us at 4096^2.  A program sets NT = false when the pass that reads
+// its outputs next does better with them cached (P4's outputs: the P1 y-pass
+// totals kernel ran 41 -> 46 us after streamed stores).
+typedef float molt_f4v __attribute__((ext_vector_type(4)));
+typedef double molt_d2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void st16_nt(float* p, const float* o) {
+  const molt_f4v v = {o[0], o[1], o[2], o[3]};
+  __builtin_nontemporal_store(v, (molt_f4v*)p);
+}
+__device__ __forceinline__ void st16_nt(double* p, const double* o) {
+  const molt_d2v v = {o[0], o[1]};
+  __builtin_nontemporal_store(v, (molt_d2v*)p);
+}
+template <bool NT, typename T>
+__device__ __forceinline__ void st16_out(T* p, const T* o) {
+  if constexpr (NT) st16_nt(p, o); else st16(p, o);
+}
+template <bool NT, typename T>
+__device__ __forceinline__ void st1_out(T* p, T v) {
+  if constexpr (NT) __builtin_nontemporal_store(v, p); else *p = v;
+}
 
 // --------------------------------------------------------------------------
 // Per-thread line segment: sweep inputs on nodes j0-H .. j0+K+H-1, the two
@@ -520,7 +556,7 @@ struct Seg {
           for (int f = 0; f < NO; ++f) o[f][v] = ok[f];
         }
 #pragma unroll
-        for (int f = 0; f < NO; ++f) st16((T*)a.out[f] + lbase + (size_t)(j0 + q * V), o[f]);
+        for (int f = 0; f < NO; ++f) st16_out<P::NT>((T*)a.out[f] + lbase + (size_t)(j0 + q * V), o[f]);
       }
     } else {
 #pragma unroll
@@ -534,7 +570,7 @@ struct Seg {
           for (int e = 0; e < E; ++e) xk[e] = ex[e][k];
           res = fmax(res, P::fin(a, wk, xk, ok));
 #pragma unroll
-          for (int f = 0; f < NO; ++f) ((T*)a.out[f])[lbase + (size_t)j * stride] = ok[f];
+          for (int f = 0; f < NO; ++f) st1_out<P::NT>((T*)a.out[f] + lbase + (size_t)j * stride, ok[f]);
         }
       }
     }
@@ -838,7 +874,7 @@ __device__ __forceinline__ void xpass_body(const LineCoef& c, const PassArgs& a,
             for (int f = 0; f < NO; ++f) o[f][v] = ok[f];
           }
 #pragma unroll
-          for (int f = 0; f < NO; ++f) st16((T*)a.out[f] + lbase + (size_t)e0, o[f]);
+          for (int f = 0; f < NO; ++f) st16_out<P::NT>((T*)a.out[f] + lbase + (size_t)e0, o[f]);
         }
       }
     } else {
@@ -853,7 +889,7 @@ __device__ __forceinline__ void xpass_body(const LineCoef& c, const PassArgs& a,
           for (int q = 0; q < E; ++q) xk[q] = seg.ex[q][it];
           resid = fmax(resid, P::fin(a, wk, xk, ok));
 #pragma unroll
-          for (int f = 0; f < NO; ++f) ((T*)a.out[f])[lbase + (size_t)e] = ok[f];
+          for (int f = 0; f < NO; ++f) st1_out<P::NT>((T*)a.out[f] + lbase + (size_t)e, ok[f]);
         }
       }
     }
