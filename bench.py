@@ -299,7 +299,7 @@ def run_served(args, molt, synth):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py: the benchmark runs on one GPU; --gpus {args.gpus} is not supported "
               "(the multi-GPU decomposition is design-only)", file=sys.stderr)
         sys.exit(2)
     if args.copy_calibration_mib:
