@@ -617,9 +617,10 @@ __device__ inline void residual_block(double r, double* partials, int slot) {
   }
 }
 
+// (blocks of up to 1024 threads; the max is order-independent)
 __device__ inline void residual_close_body(const double* partials, int nblocks, DevState* st) {
   if (st->done) return;
-  __shared__ double red[4];
+  __shared__ double red[16];
   double r = 0.0;
   for (int i = threadIdx.x; i < nblocks; i += blockDim.x) r = fmax(r, partials[i]);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -628,7 +629,8 @@ __device__ inline void residual_close_body(const double* partials, int nblocks, 
   if (lane == 0) red[wave] = r;
   __syncthreads();
   if (threadIdx.x == 0) {
-    const double res = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    double res = red[0];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) res = fmax(res, red[w]);
     const int it = st->iters + 1;
     st->iters = it;
     st->last_resid = res;

@@ -33,7 +33,7 @@ int xpass_tl(int n, int K);
 int diag_blocks(size_t n);
 
 template <typename T>
-__global__ void __launch_bounds__(256) residual_close_kernel(const double* partials, int nblocks, DevState* st) {
+__global__ void __launch_bounds__(1024) residual_close_kernel(const double* partials, int nblocks, DevState* st) {
   residual_close_body(partials, nblocks, st);
 }
 
@@ -504,7 +504,7 @@ static hipError_t xpass_k(const LineCoef& c, const PassArgs& a, DevState* st, in
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (g_prof_on) prof_begin(KF_OTHER * 8, s);
-    hipLaunchKernelGGL((residual_close_kernel<T>), dim3(1), dim3(256), 0, s, (const double*)rpart, (int)grid.x, st);
+    hipLaunchKernelGGL((residual_close_kernel<T>), dim3(1), dim3(1024), 0, s, (const double*)rpart, (int)grid.x, st);
     if (g_prof_on) prof_end(KF_OTHER * 8, s);
   }
   return hipGetLastError();
