@@ -461,10 +461,14 @@ hipError_t MOLT_BFN(launch_batch_x)(int K, int M, bool per, int pass, const Slot
 
 // close, step finish, diagnostics and tick end (kind "other_1") of the listed slots
 hipError_t MOLT_BFN(launch_batch_tail)(const SlotDesc* sd, SlotCtl* ctl, const BlkMap* slots, int nslots,
-                                      const BlkMap* pmap, int npblk, hipStream_t s) {
+                                      const BlkMap* pmap, int npblk, bool close_only, hipStream_t s) {
   if (nslots <= 0) return hipSuccess;
   if (g_prof_on) prof_begin(KF_OTHER * 8 + 1, s);
   hipLaunchKernelGGL((close_batch_kernel<MOLT_BT>), dim3(nslots), dim3(256), 0, s, sd, (const SlotCtl*)ctl, slots);
+  if (close_only) {
+    if (g_prof_on) prof_end(KF_OTHER * 8 + 1, s);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL((finish_batch_kernel<MOLT_BT>), dim3(npblk), dim3(256), 0, s, sd, (const SlotCtl*)ctl, pmap);
   hipLaunchKernelGGL((diag_batch_kernel<MOLT_BT>), dim3(npblk), dim3(256), 0, s, sd, (const SlotCtl*)ctl, pmap);
   hipLaunchKernelGGL((tick_end_batch_kernel<MOLT_BT>), dim3(nslots), dim3(256), 0, s, sd, ctl, slots);

@@ -95,7 +95,7 @@ void ypass_shape(int prec, int n, int* nth, int* nseg);
   hipError_t launch_batch_x_##sfx(int K, int M, bool per, int pass, const SlotDesc* sd, const SlotCtl* ctl,    \
                                   const BlkMap* map, int nblk, hipStream_t s);                                 \
   hipError_t launch_batch_tail_##sfx(const SlotDesc* sd, SlotCtl* ctl, const BlkMap* slots, int nslots,        \
-                                     const BlkMap* pmap, int npblk, hipStream_t s);                            \
+                                     const BlkMap* pmap, int npblk, bool close_only, hipStream_t s);           \
   hipError_t launch_batch_react_##sfx(const SlotDesc* sd, const SlotCtl* ctl, const BlkMap* pmap, int npblk,   \
                                       hipStream_t s);                                                          \
   hipError_t launch_batch_init_##sfx(const SlotDesc* sd, SlotCtl* ctl, int nslots, hipStream_t s);             \
@@ -136,6 +136,7 @@ bool g_prof_on = false;
 static long long g_fused_min_items = 1LL << 40;  // single-kernel y-pass off by default
 static int g_batch_ticks = 8;                     // batched solve: ticks between host checks
 static int g_batch_graph = 1;                     // batched solve: replay the ticks as a HIP graph
+static int g_batch_lean = 16;                     // batched solve: lean ticks with at most this many instances
 namespace {
 struct PendingEv {
   int kind;
@@ -656,8 +657,8 @@ static hipError_t launch_batch_x(int prec, int K, int M, bool per, int pass, con
   return MOLT_BATCH_PREC(launch_batch_x)(K, M, per, pass, sd, ctl, map, nblk, s);
 }
 static hipError_t launch_batch_tail(int prec, const SlotDesc* sd, SlotCtl* ctl, const BlkMap* slots, int nslots,
-                                    const BlkMap* pmap, int npblk, hipStream_t s) {
-  return MOLT_BATCH_PREC(launch_batch_tail)(sd, ctl, slots, nslots, pmap, npblk, s);
+                                    const BlkMap* pmap, int npblk, bool close_only, hipStream_t s) {
+  return MOLT_BATCH_PREC(launch_batch_tail)(sd, ctl, slots, nslots, pmap, npblk, close_only, s);
 }
 static hipError_t launch_batch_react(int prec, const SlotDesc* sd, const SlotCtl* ctl, const BlkMap* pmap, int npblk,
                                      hipStream_t s) {
@@ -684,7 +685,8 @@ struct BatchPlan {
   size_t nrec = 0;
   size_t desc = 0, ctl = 0, rec = 0, map = 0, cnt = 0, total = 0;
   size_t nmap = 0;          // capacity of the map area in entries
-  long long max_ticks = 0;  // upper bound of the ticks any slot needs
+  long long max_ticks = 0;  // upper bound of the ticks any slot needs (plain rounds)
+  long long max_steps = 0;  // most steps of any slot (lean rounds add up to 2 rounds a step)
 };
 
 // Block maps of the slots in `act` (ascending): per-group ranges of one map.
@@ -782,6 +784,7 @@ static int32_t batch_plan(const molt_instance* inst, int count, BatchPlan& P) {
   P.rec_first.resize(count);
   P.nrec = 0;
   P.max_ticks = 0;
+  P.max_steps = 0;
   size_t nmap = 0;
   for (int i = 0; i < count; ++i) {
     const int32_t rc = check_instance(inst[i], prec);
@@ -796,6 +799,7 @@ static int32_t batch_plan(const molt_instance* inst, int count, BatchPlan& P) {
     const long long cap = p.fixed_iters > 0 ? p.fixed_iters : p.max_iter;
     const long long ticks = (long long)inst[i].nsteps * (cap + 1);
     if (ticks > P.max_ticks) P.max_ticks = ticks;
+    if (inst[i].nsteps > P.max_steps) P.max_steps = inst[i].nsteps;
     // map entries of the most fine-grained shapes the table allows
     const molt_grid& gr = inst[i].grid;
     const int nseg = ypass_max_segments(gr.ny);
@@ -876,8 +880,10 @@ static void fill_slot(const molt_instance& in, const Layout& L, char* w, molt_st
   d.dblocks = diag_blocks((size_t)g.nx * g.ny);
 }
 
+// close_only: the iteration's close without the step finish and phase update
+// (lean ticks: a round of lean ticks ends with one full tick)
 static hipError_t batch_tick(int prec, const BatchMaps& B, const SlotDesc* sd, SlotCtl* ctl, const BlkMap* map,
-                             hipStream_t s) {
+                             hipStream_t s, bool close_only = false) {
   hipError_t e;
   if (B.any_vch && (e = launch_batch_react(prec, sd, ctl, map + B.pt_off, B.pt_n, s)) != hipSuccess) return e;
   for (int pass = 1; pass <= 3; pass += 2) {
@@ -892,16 +898,16 @@ static hipError_t batch_tick(int prec, const BatchMaps& B, const SlotDesc* sd, S
       if ((e = launch_batch_x(prec, g.K, g.M, g.per != 0, pass + 1, sd, ctl, map + g.off, g.nblk, s)) != hipSuccess)
         return e;
   }
-  return launch_batch_tail(prec, sd, ctl, map + B.sl_off, B.sl_n, map + B.pt_off, B.pt_n, s);
+  return launch_batch_tail(prec, sd, ctl, map + B.sl_off, B.sl_n, map + B.pt_off, B.pt_n, close_only, s);
 }
 
 // `ticks` ticks and the active-slot count, captured as one executable graph
 static hipError_t capture_round(int prec, const BatchMaps& B, const SlotDesc* sd, SlotCtl* ctl, const BlkMap* map,
-                                int count, int* dcnt, int ticks, hipStream_t s, hipGraphExec_t* exec) {
+                                int count, int* dcnt, int ticks, bool lean, hipStream_t s, hipGraphExec_t* exec) {
   hipGraph_t graph = nullptr;
   hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed);
   if (e != hipSuccess) return e;
-  for (int k = 0; k < ticks && e == hipSuccess; ++k) e = batch_tick(prec, B, sd, ctl, map, s);
+  for (int k = 0; k < ticks && e == hipSuccess; ++k) e = batch_tick(prec, B, sd, ctl, map, s, lean && k < ticks - 1);
   if (e == hipSuccess) e = launch_batch_count(prec, ctl, count, dcnt, s);
   const hipError_t e2 = hipStreamEndCapture(s, &graph);
   if (e == hipSuccess) e = e2;
@@ -951,14 +957,22 @@ static int32_t solve_batch_impl(const molt_instance* inst, int count, void* d_wo
   for (int b = 0; b < 2 && err.empty(); ++b)
     if (hipEventCreateWithFlags(&ev[b], hipEventDisableTiming) != hipSuccess) err = "hipEventCreate failed";
   std::vector<SlotCtl> hctl;
-  const long long max_rounds = P.max_ticks / ticks + 3;
+  // a lean round finishes a step only at its end: the R phase and the wait
+  // after convergence take up to one round each
+  const long long max_rounds = (P.max_ticks + 2LL * ticks * P.max_steps) / ticks + 3;
   long long rounds = 0, since = 0;  // rounds in all, rounds since the maps were last built
   int planned = (int)act.size();
   bool finished = act.empty();
+  // with at most this many instances left, a round's ticks but the last run
+  // only the iteration (no step finish): a converged instance waits for the
+  // round's end to start its next step, but each iteration of a lone long
+  // instance takes three kernel launches fewer
+  const int lean_slots = g_batch_lean;
+  bool lean = planned <= lean_slots;
   while (err.empty() && !finished) {
     hipError_t e = hipSuccess;
     if (use_graph && !exec) {
-      e = capture_round(prec, B, sd, ctl, map, count, dcnt, ticks, s, &exec);
+      e = capture_round(prec, B, sd, ctl, map, count, dcnt, ticks, lean, s, &exec);
       if (e != hipSuccess) {
         err = std::string("batched tick capture: ") + hipGetErrorString(e);
         break;
@@ -968,7 +982,7 @@ static int32_t solve_batch_impl(const molt_instance* inst, int count, void* d_wo
     if (exec) {
       e = hipGraphLaunch(exec, s);
     } else {
-      for (int k = 0; k < ticks && e == hipSuccess; ++k) e = batch_tick(prec, B, sd, ctl, map, s);
+      for (int k = 0; k < ticks && e == hipSuccess; ++k) e = batch_tick(prec, B, sd, ctl, map, s, lean && k < ticks - 1);
       if (e == hipSuccess) e = launch_batch_count(prec, ctl, count, dcnt, s);
     }
     if (e == hipSuccess) e = hipMemcpyAsync(&pin[b], dcnt, sizeof(int), hipMemcpyDeviceToHost, s);
@@ -1016,6 +1030,7 @@ static int32_t solve_batch_impl(const molt_instance* inst, int count, void* d_wo
         break;
       }
       planned = (int)act.size();
+      lean = planned <= lean_slots;
       since = 0;
       if (exec) {
         (void)hipGraphExecDestroy(exec);
@@ -1433,6 +1448,10 @@ int32_t molt_set_option(int32_t option, int64_t value) {
   }
   if (option == MOLT_OPT_BATCH_GRAPH && (value == 0 || value == 1)) {
     g_batch_graph = (int)value;
+    return MOLT_OK;
+  }
+  if (option == MOLT_OPT_BATCH_LEAN && value >= 0 && value <= 1024) {
+    g_batch_lean = (int)value;
     return MOLT_OK;
   }
   return fail(MOLT_EINVAL, "unknown option or value out of range");

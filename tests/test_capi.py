@@ -176,6 +176,8 @@ def test_batch_options(lib):
     assert molt.molt_set_option(molt.MOLT_OPT_BATCH_TICKS, 8) == molt.MOLT_OK
     assert molt.molt_set_option(molt.MOLT_OPT_BATCH_GRAPH, 2) == molt.MOLT_EINVAL
     assert molt.molt_set_option(molt.MOLT_OPT_BATCH_GRAPH, 1) == molt.MOLT_OK
+    assert molt.molt_set_option(molt.MOLT_OPT_BATCH_LEAN, -1) == molt.MOLT_EINVAL
+    assert molt.molt_set_option(molt.MOLT_OPT_BATCH_LEAN, 2) == molt.MOLT_OK
     assert molt.molt_set_option(99, 1) == molt.MOLT_EINVAL
     assert molt.molt_profile_only(48) == molt.MOLT_EINVAL
     assert molt.molt_profile_only(-1) == molt.MOLT_OK

@@ -28,6 +28,7 @@ def _lib():
     yield
     molt.molt_set_option(molt.MOLT_OPT_BATCH_TICKS, 8)
     molt.molt_set_option(molt.MOLT_OPT_BATCH_GRAPH, 1)
+    molt.molt_set_option(molt.MOLT_OPT_BATCH_LEAN, LEAN_DEFAULT)
 
 
 def _og(g):
@@ -106,9 +107,13 @@ def test_batch_fp32_against_fp64_oracle():
         assert err.max() <= 1e-5, (i, err.max())
 
 
-def _run_batch(idx, prec, ticks=8, graph=1):
+LEAN_DEFAULT = 16  # the library's default for MOLT_OPT_BATCH_LEAN
+
+
+def _run_batch(idx, prec, ticks=8, graph=1, lean=LEAN_DEFAULT):
     assert molt.molt_set_option(molt.MOLT_OPT_BATCH_TICKS, ticks) == 0
     assert molt.molt_set_option(molt.MOLT_OPT_BATCH_GRAPH, graph) == 0
+    assert molt.molt_set_option(molt.MOLT_OPT_BATCH_LEAN, lean) == 0
     dt = torch.float64 if prec == molt.MOLT_F64 else torch.float32
     specs = []
     for i in idx:
@@ -137,6 +142,14 @@ def test_batch_alone_equals_in_batch_bitwise(prec):
     st2, xr, _ = _run_batch(full[::-1], prec, ticks=1, graph=0)
     for k, i in enumerate(full[::-1]):
         assert torch.equal(xr[k], xs[i]), i
+    # lean ticks from the start (graph replay, and launched one by one), and never
+    for lean, graph in ((1024, 1), (1024, 0), (0, 1)):
+        st3, xl, rl = _run_batch(full, prec, graph=graph, lean=lean)
+        assert st3 == molt.MOLT_OK
+        for i in full:
+            assert torch.equal(xl[i], xs[i]), (lean, graph, i)
+            assert [(r.iters, r.residual, r.mass, r.energy) for r in rl[i]] == \
+                   [(r.iters, r.residual, r.mass, r.energy) for r in recs[i]], (lean, graph, i)
 
 
 @pytest.mark.parametrize("prec", [molt.MOLT_F32, molt.MOLT_F64], ids=["f32", "f64"])
