@@ -373,8 +373,9 @@ int32_t molt_profile_read(molt_prof_entry* out, int32_t max_entries);
  *  MOLT_OPT_BATCH_GRAPH (0 or 1, default 1): replay those ticks as one
  *    captured HIP graph (used when the stream is not NULL and kernel timing is
  *    off); 0 launches the kernels one by one. */
-/*  MOLT_OPT_BATCH_LEAN (0..1024, default 16): with at most this many instances
- *    still running, every tick of a round but its last runs the iteration
+/*  MOLT_OPT_BATCH_LEAN (0..1024, default 16): in ch_solve_batch (not the
+ *    server), with at most this many instances still running, every tick of a
+ *    round but its last runs the iteration
  *    only (no step finish): fewer launches per iteration for the last long
  *    instances, while an instance that converged waits for the round's end
  *    to start its next step.  Results are unchanged. */
