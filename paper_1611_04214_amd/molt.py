@@ -177,11 +177,60 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
 
 
 class MoltError(RuntimeError):
-    def __init__(self, status: int, where: str):
+    def __init__(self, status: int, where: str, detail: str | None = None):
         lib = load()
-        super().__init__(f"{where}: {lib.molt_strerror(status).decode()} ({status}): "
-                         f"{lib.molt_last_error().decode()}")
+        if detail is None:
+            detail = lib.molt_last_error().decode()
+        super().__init__(f"{where}: {lib.molt_strerror(status).decode()} ({status}): {detail}")
         self.status = status
+
+
+def _check_tensor(t, where: str, what: str, precision: int, numel: int | None, multiple_of: int | None = None):
+    """Raise MoltError (MOLT_EINVAL) unless t is a contiguous device tensor of
+    the element type the precision names (float64 for MOLT_F64, float32 for
+    MOLT_F32) holding exactly numel elements (or a positive multiple of
+    multiple_of): the library takes a bare address and would otherwise read or
+    write outside the tensor."""
+    import torch
+    want = {MOLT_F64: torch.float64, MOLT_F32: torch.float32}.get(precision)
+    if want is None:
+        raise MoltError(MOLT_EINVAL, where, f"unknown precision {precision}")
+    if not isinstance(t, torch.Tensor):
+        raise MoltError(MOLT_EINVAL, where, f"{what} must be a torch tensor")
+    if t.dtype != want:
+        raise MoltError(MOLT_EINVAL, where, f"{what} is {t.dtype}, the precision needs {want}")
+    if not t.is_contiguous():
+        raise MoltError(MOLT_EINVAL, where, f"{what} must be contiguous")
+    if numel is not None and t.numel() != numel:
+        raise MoltError(MOLT_EINVAL, where, f"{what} holds {t.numel()} elements, the call needs {numel}")
+    if multiple_of is not None and (t.numel() == 0 or t.numel() % multiple_of != 0):
+        raise MoltError(MOLT_EINVAL, where,
+                        f"{what} holds {t.numel()} elements, not a positive multiple of {multiple_of}")
+
+
+def _check_device(where: str, *named) -> None:
+    """Every (name, tensor) on one HIP device (after the type and size checks)."""
+    dev = None
+    for what, t in named:
+        if not t.is_cuda:
+            raise MoltError(MOLT_EINVAL, where, f"{what} must be on a HIP device")
+        if dev is not None and t.device != dev:
+            raise MoltError(MOLT_EINVAL, where, f"{what} is on another device")
+        dev = t.device
+
+
+def _field_elems(grid: molt_grid, params: molt_ch_params) -> int:
+    """Elements of one field of this problem (both components for the vector model)."""
+    return grid.nx * grid.ny * (2 if params.model == MOLT_MODEL_VCH else 1)
+
+
+def _check_workspace(work, need: int, where: str, device) -> None:
+    import torch
+    if not isinstance(work, torch.Tensor) or not work.is_contiguous() or work.device != device:
+        raise MoltError(MOLT_EINVAL, where, "the workspace must be a contiguous tensor on the field's device")
+    if work.numel() * work.element_size() < need:
+        raise MoltError(MOLT_EWORKSPACE, where, f"workspace of {work.numel() * work.element_size()} bytes, "
+                                                f"the call needs {need}")
 
 
 def _check(status: int, where: str, allow_not_converged: bool = True) -> int:
@@ -236,6 +285,8 @@ def make_adapt(t_end: float, dt0: float, lte_tol: float, nmaxit: int = 600, thet
 def solve_adaptive(u, grid: molt_grid, params: molt_ch_params, adapt: molt_adapt_params, max_rec: int = 100000):
     """ch_solve_adaptive in place on u; returns (status, [molt_adapt_record], t_final)."""
     import torch
+    _check_tensor(u, "ch_solve_adaptive", "u", params.precision, _field_elems(grid, params))
+    _check_device("ch_solve_adaptive", ("u", u))
     need = ch_adaptive_workspace_bytes(grid, params)
     if need == 0:
         raise MoltError(MOLT_EINVAL, "ch_adaptive_workspace_bytes")
@@ -348,15 +399,22 @@ def workspace(nbytes: int, device="cuda"):
 def sweep(field, grid: molt_grid, axis: int, alpha: float, out=None, work=None):
     """L^{-1} along axis of a (batch, ny, nx) / (ny, nx) / (nx,) device tensor."""
     import torch
+    where = "mol_t_helmholtz_sweep"
+    if field.dtype not in (torch.float64, torch.float32):
+        raise MoltError(MOLT_EINVAL, where, f"field is {field.dtype}; float64 or float32 only")
     prec = MOLT_F64 if field.dtype == torch.float64 else MOLT_F32
     f = field.contiguous()
+    _check_tensor(f, where, "field", prec, None, multiple_of=grid.nx * grid.ny)
     batch = f.numel() // (grid.nx * grid.ny)
     out = torch.empty_like(f) if out is None else out
+    _check_tensor(out, where, "out", prec, f.numel())
+    _check_device(where, ("field", f), ("out", out))
     need = molt_sweep_workspace_bytes(grid, axis, prec, batch)
     if need == 0:
         raise MoltError(MOLT_EINVAL, "molt_sweep_workspace_bytes")
-    if work is None or work.numel() < need:
+    if work is None:
         work = workspace(need, f.device)
+    _check_workspace(work, need, where, f.device)
     _check(mol_t_helmholtz_sweep(grid, axis, alpha, prec, f.data_ptr(), out.data_ptr(), batch, work.data_ptr(),
                                  work.numel(), _stream(torch)), "mol_t_helmholtz_sweep")
     return out
@@ -365,11 +423,18 @@ def sweep(field, grid: molt_grid, axis: int, alpha: float, out=None, work=None):
 def step(u, grid: molt_grid, params: molt_ch_params, u_prev=None, work=None) -> molt_step_info:
     """One ch_step in place on the device tensor u (u_prev: BDF2 history, rotated in place)."""
     import torch
+    ne = _field_elems(grid, params)
+    _check_tensor(u, "ch_step", "u", params.precision, ne)
+    if u_prev is not None:
+        _check_tensor(u_prev, "ch_step", "u_prev", params.precision,
+                      ne * (2 if params.stepper == MOLT_BDF3 else 1))
+    _check_device("ch_step", ("u", u), *([] if u_prev is None else [("u_prev", u_prev)]))
     need = ch_workspace_bytes(grid, params)
     if need == 0:
         raise MoltError(MOLT_EINVAL, "ch_workspace_bytes")
-    if work is None or work.numel() < need:
+    if work is None:
         work = workspace(need, u.device)
+    _check_workspace(work, need, "ch_step", u.device)
     info = molt_step_info()
     _check(ch_step(grid, params, u.data_ptr(), 0 if u_prev is None else u_prev.data_ptr(), work.data_ptr(),
                    work.numel(), info, _stream(torch)), "ch_step")
@@ -379,11 +444,14 @@ def step(u, grid: molt_grid, params: molt_ch_params, u_prev=None, work=None) -> 
 def solve(u, grid: molt_grid, params: molt_ch_params, nsteps: int, work=None):
     """ch_solve in place on u; returns (status, [molt_step_info])."""
     import torch
+    _check_tensor(u, "ch_solve", "u", params.precision, _field_elems(grid, params))
+    _check_device("ch_solve", ("u", u))
     need = ch_workspace_bytes(grid, params)
     if need == 0:
         raise MoltError(MOLT_EINVAL, "ch_workspace_bytes")
-    if work is None or work.numel() < need:
+    if work is None:
         work = workspace(need, u.device)
+    _check_workspace(work, need, "ch_solve", u.device)
     infos = (molt_step_info * max(nsteps, 1))()
     st = _check(ch_solve(grid, params, u.data_ptr(), nsteps, work.data_ptr(), work.numel(), infos,
                          _stream(torch)), "ch_solve")
@@ -405,13 +473,19 @@ def solve_batch(specs, work=None, stream=None):
     """ch_solve_batch over (grid, params, device tensor, nsteps) tuples, in place on
     the tensors; returns (status, per-instance lists of molt_step_info)."""
     import torch
+    if not specs:
+        raise MoltError(MOLT_EINVAL, "ch_solve_batch", "no instances")
+    dev = specs[0][2].device
+    for i, (g, p, u, _) in enumerate(specs):
+        _check_tensor(u, "ch_solve_batch", f"instance {i}'s field", p.precision, _field_elems(g, p))
+    _check_device("ch_solve_batch", *[(f"instance {i}'s field", sp[2]) for i, sp in enumerate(specs)])
     inst = make_instances(specs)
     need = ch_batch_workspace_bytes(inst, len(specs))
     if need == 0:
         raise MoltError(MOLT_EINVAL, "ch_batch_workspace_bytes")
-    dev = specs[0][2].device
-    if work is None or work.numel() < need:
+    if work is None:
         work = workspace(need, dev)
+    _check_workspace(work, need, "ch_solve_batch", dev)
     nrec = sum(int(s[3]) for s in specs)
     recs = (molt_step_info * max(nrec, 1))()
     st = _check(ch_solve_batch(inst, len(specs), work.data_ptr(), work.numel(), recs,
@@ -451,6 +525,8 @@ class Server:
         self._live = {}
 
     def submit(self, grid: molt_grid, params: molt_ch_params, u, nsteps: int, rid: int) -> None:
+        _check_tensor(u, "molt_server_submit", "u", params.precision, _field_elems(grid, params))
+        _check_device("molt_server_submit", ("the server's workspace", self.work), ("u", u))
         inst = molt_instance(grid, params, u.data_ptr(), nsteps)
         _check(load().molt_server_submit(self._h, ctypes.byref(inst), rid), "molt_server_submit")
         self._live[rid] = u
