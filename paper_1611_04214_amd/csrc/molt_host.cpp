@@ -77,6 +77,9 @@ static hipError_t launch_addc(int prec, void* x, double c0, double c1, size_t n,
 size_t yfused_items(int n, int nx, int batch);
 size_t yfused_rec_words(int n, int nx, int batch);
 hipError_t launch_zero_ints(int* p, int n, hipStream_t s);
+hipError_t launch_widen(void* dst64, const void* src32, size_t n, hipStream_t s);
+hipError_t launch_narrow(void* dst32, const void* src64, size_t n, hipStream_t s);
+hipError_t launch_finalize_mixed(void* u32, const void* base64, const void* W32, size_t n, hipStream_t s);
 hipError_t launch_state_init(DevState* st, double tol, int max_iter, int fixed, hipStream_t s);
 size_t ypass_tot_elems(int prec, int n, int nx, int batch);
 int diag_blocks(size_t n);
@@ -334,24 +337,43 @@ static int32_t check_grid(const molt_grid* g, int prec) {
 
 static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Workspace of one problem.  An FP32 problem also holds an FP64 shadow: the
+// right-hand side sweeps R = A1^{-1} A2^{-1} rhs and the first (full-form)
+// fixed-point iteration of every step run in FP64 on it (fld64, tot64, jln64,
+// and FP64 copies of the step's inputs in64), and only the increments of the
+// later iterations run in FP32.  The splitting's fixed point amplifies an
+// error in its data by (I - T)^{-1}, whose largest entries (modes that are
+// high in both directions, small alpha*h) are ~1/(4 lambda^2): FP32 rounding
+// of R or of the first increment, at the ulp of u, would be amplified to a
+// persistent drift instead of a 1e-8 increment.
 struct Layout {
   size_t fld[F_COUNT];
-  size_t tot, jln, state, partials, rpart, frec, total;
+  size_t tot, jln, state, partials, rpart, frec;
+  bool hybrid;               // FP32 problem with its FP64 shadow
+  size_t fld64[F_COUNT];     // FP64 shadow fields (hybrid only)
+  size_t tot64, jln64;       // FP64 y-pass scratch
+  size_t in64[3];            // FP64 copies of u^n, u^{n-1}, u^{n-2}
+  size_t total;
 };
 
 static int ncomp_of(const molt_ch_params* p) { return p->model == MOLT_MODEL_VCH ? 2 : 1; }
 
-static Layout ch_layout(const molt_grid* g, int prec, int ncomp, bool bdf3 = false) {
+static bool field_used(int i, int ncomp, bool bdf3) {
+  if (i == F_E || i == F_LIN) return ncomp == 2;
+  if (i == F_HIST2 || i == F_STAGE) return bdf3;
+  return true;
+}
+
+// shadow = false: no FP64 shadow even for FP32 (the batched engine)
+static Layout ch_layout(const molt_grid* g, int prec, int ncomp, bool bdf3 = false, bool shadow = true) {
   Layout L;
+  memset(&L, 0, sizeof(L));
   const size_t esz = prec == MOLT_F64 ? 8 : 4;
   const size_t n = (size_t)g->nx * g->ny;
   size_t off = 0;
   for (int i = 0; i < F_COUNT; ++i) {
     L.fld[i] = off;
-    bool used = true;
-    if (i == F_E || i == F_LIN) used = ncomp == 2;
-    if (i == F_HIST2 || i == F_STAGE) used = bdf3;
-    off += used ? al256(n * ncomp * esz) : 0;
+    off += field_used(i, ncomp, bdf3) ? al256(n * ncomp * esz) : 0;
   }
   L.tot = off;
   off += al256(g->ny > 1 ? ypass_tot_elems(prec, g->ny, g->nx, ncomp) * esz : 0);
@@ -365,6 +387,21 @@ static Layout ch_layout(const molt_grid* g, int prec, int ncomp, bool bdf3 = fal
   off += al256((size_t)g->ny * ncomp * sizeof(double));
   L.frec = off;  // fused y-pass: published segment totals
   off += al256(g->ny > 1 ? yfused_rec_words(g->ny, g->nx, ncomp) * sizeof(unsigned long long) : 0);
+  L.hybrid = prec == MOLT_F32 && shadow;
+  if (L.hybrid) {
+    for (int i = 0; i < F_COUNT; ++i) {
+      L.fld64[i] = off;
+      off += field_used(i, ncomp, bdf3) ? al256(n * ncomp * 8) : 0;
+    }
+    L.tot64 = off;
+    off += al256(g->ny > 1 ? ypass_tot_elems(MOLT_F64, g->ny, g->nx, ncomp) * 8 : 0);
+    L.jln64 = off;
+    off += al256((size_t)2 * g->nx * ncomp * 8);
+    for (int i = 0; i < 3; ++i) {
+      L.in64[i] = off;
+      off += (i < 2 || bdf3) ? al256(n * ncomp * 8) : 0;
+    }
+  }
   L.total = off;
   return L;
 }
@@ -372,6 +409,124 @@ static Layout ch_layout(const molt_grid* g, int prec, int ncomp, bool bdf3 = fal
 // --------------------------------------------------------------------------
 // one step
 // --------------------------------------------------------------------------
+// The line coefficients and launch geometry of one step.
+struct StepGeo {
+  int nx, ny, nc, xl;  // xl: x-lines (ny rows per component)
+  size_t n;            // nodes per component
+  bool two_d, vch;
+  LineCoef cx1, cx2, cy1, cy2;
+};
+
+// R = A1^{-1} A2^{-1} rhs, A_i^{-1} = Lx_i^{-1} Ly_i^{-1} (Sec. 5.1, first term
+// of eq. CH_BE_2D_3), with rhs of the stepper (eq. CH_BE; eqs. BDF2, BDF3) from
+// in0..in2 = u^n, u^{n-1}, u^{n-2}; A1, B1 are scratch fields of the precision
+static int32_t enqueue_rhs(int prec, const StepGeo& G, const PassArgs& rhs_args, void* const* F, void* tot, void* jln,
+                           DevState* st, YFused* fz, hipStream_t s) {
+  PassArgs a = rhs_args;
+  if (G.two_d) {
+    a.out[0] = F[F_A1];
+    if (fz) ++fz->epoch;
+    HIPCHK(launch_ypass(prec, PROG_RHS, G.cy2, a, st, G.nx, G.nc, tot, jln, fz, s));
+    a.in[0] = F[F_A1];
+    a.out[0] = F[F_B1];
+    HIPCHK(launch_xpass(prec, PROG_SWEEP, G.cx2, a, nullptr, G.xl, nullptr, s));
+    a.in[0] = F[F_B1];
+    a.out[0] = F[F_A1];
+    if (fz) ++fz->epoch;
+    HIPCHK(launch_ypass(prec, PROG_SWEEP, G.cy1, a, st, G.nx, G.nc, tot, jln, fz, s));
+    a.in[0] = F[F_A1];
+    a.out[0] = F[F_R];
+    HIPCHK(launch_xpass(prec, PROG_SWEEP, G.cx1, a, nullptr, G.xl, nullptr, s));
+  } else {
+    a.out[0] = F[F_B1];
+    HIPCHK(launch_xpass(prec, PROG_RHS, G.cx2, a, nullptr, G.xl, nullptr, s));
+    a.in[0] = F[F_B1];
+    a.out[0] = F[F_R];
+    HIPCHK(launch_xpass(prec, PROG_SWEEP, G.cx1, a, nullptr, G.xl, nullptr, s));
+  }
+  return MOLT_OK;
+}
+
+// One fixed-point iteration (Sec. 5.1, eqs. CH_BE_2D_3, CH_2D_Doperator1/2) as
+// the four passes P1..P4 on the fields F of the precision; mode 0 the full form
+// from the iterate `base`, mode 1 the increment form (base + W the iterate,
+// DL the last increment).  P4 writes DL, W and the residual partials.
+static int32_t enqueue_iteration(int prec, const StepGeo& G, const StepParams& sp, const double* ush, int mode,
+                                 const void* base, void* const* F, void* tot, void* jln, DevState* st, double* rpart,
+                                 YFused* fz, hipStream_t s) {
+  PassArgs q;
+  memset(&q, 0, sizeof(q));
+  q.sigma = sp.sigma;
+  q.kappa = sp.a / sp.s1;
+  q.mode = mode;
+  q.ushift[0] = ush[0];
+  q.ushift[1] = ush[1];
+  // P1 (y, alpha1): a1 = Y1 e, b1 = Y1 lin (vector model: e, lin from the
+  // pointwise reaction pass, then both components swept as a batch)
+  q.in[0] = base;
+  q.in[1] = F[F_W];
+  q.in[2] = F[F_DL];
+  if (G.vch) {
+    q.out[0] = F[F_E];
+    q.out[1] = F[F_LIN];
+    HIPCHK(launch_vch_react(prec, q, st, G.n, s));
+    q.in[0] = F[F_E];
+    q.in[1] = F[F_LIN];
+    q.in[2] = nullptr;
+  }
+  q.out[0] = F[F_A1];
+  q.out[1] = F[F_B1];
+  const int p1 = G.vch ? PROG_P1V : PROG_P1;
+  if (G.two_d) {
+    if (fz) ++fz->epoch;
+    HIPCHK(launch_ypass(prec, p1, G.cy1, q, st, G.nx, G.nc, tot, jln, fz, s));
+  } else {
+    HIPCHK(launch_pointwise(prec, p1, q, st, G.n * G.nc, s));
+  }
+  // P2 (x, alpha1): C, q
+  q.in[0] = F[F_A1];
+  q.in[1] = F[F_B1];
+  if (G.vch) {
+    q.in[2] = F[F_E];
+    q.in[3] = F[F_LIN];
+    q.in[4] = nullptr;
+  } else {
+    q.in[2] = base;
+    q.in[3] = F[F_W];
+    q.in[4] = F[F_DL];
+  }
+  q.out[0] = F[F_C];
+  q.out[1] = F[F_Q];
+  HIPCHK(launch_xpass(prec, G.vch ? PROG_P2V : PROG_P2, G.cx1, q, st, G.xl, nullptr, s));
+  // P3 (y, alpha2): m, n
+  q.in[0] = F[F_C];
+  q.in[1] = F[F_Q];
+  q.in[2] = q.in[3] = q.in[4] = nullptr;
+  q.out[0] = F[F_M];
+  q.out[1] = F[F_N];
+  if (G.two_d) {
+    if (fz) ++fz->epoch;
+    HIPCHK(launch_ypass(prec, PROG_P3, G.cy2, q, st, G.nx, G.nc, tot, jln, fz, s));
+  } else {
+    HIPCHK(launch_pointwise(prec, PROG_P3, q, st, G.n * G.nc, s));
+  }
+  // P4 (x, alpha2): increment and running sum, residual
+  q.in[0] = F[F_M];
+  q.in[1] = F[F_N];
+  q.in[2] = mode ? F[F_DL] : F[F_R];
+  q.in[3] = F[F_W];
+  q.out[0] = F[F_DL];
+  q.out[1] = F[F_W];
+  HIPCHK(launch_xpass(prec, PROG_P4, G.cx2, q, st, G.xl, rpart, s));
+  return MOLT_OK;
+}
+
+#define MOLT_RC(expr)                     \
+  do {                                    \
+    const int32_t rc_ = (expr);           \
+    if (rc_ != MOLT_OK) return rc_;       \
+  } while (0)
+
 // omega: BDF2 step ratio dt_n / dt_{n-1} (1: constant steps, eq. BDF2; otherwise the variable-step form)
 // d_u_prev2 (with bdf2): a BDF3 step (eq. BDF3) from u^n, u^{n-1}, u^{n-2}
 static int32_t step_impl(const molt_grid* g, const molt_ch_params* p, void* d_u, void* d_u_prev, bool bdf2,
@@ -385,16 +540,27 @@ static int32_t step_impl(const molt_grid* g, const molt_ch_params* p, void* d_u,
   if (!d_work || work_bytes < L.total) return fail(MOLT_EWORKSPACE, "workspace smaller than ch_workspace_bytes()");
   char* w = (char*)d_work;
   void* F[F_COUNT];
-  for (int i = 0; i < F_COUNT; ++i) F[i] = w + L.fld[i];
+  void* F64[F_COUNT];
+  for (int i = 0; i < F_COUNT; ++i) {
+    F[i] = w + L.fld[i];
+    F64[i] = L.hybrid ? w + L.fld64[i] : nullptr;
+  }
   void* tot = w + L.tot;
   void* jln = w + L.jln;
   DevState* st = (DevState*)(w + L.state);
   double* partials = (double*)(w + L.partials);
   double* rpart = (double*)(w + L.rpart);
 
+  StepGeo G;
+  G.nx = g->nx;
+  G.ny = g->ny;
+  G.nc = nc;
+  G.vch = vch;
+  G.xl = g->ny * nc;
+  G.n = (size_t)g->nx * g->ny;
+  G.two_d = g->ny > 1;
   const int nx = g->nx, ny = g->ny, M = g->order_M, bc = g->bc;
-  const size_t n = (size_t)nx * ny;
-  const bool two_d = ny > 1;
+  const size_t n = G.n;
   // variable-step BDF2 (w = omega): v^{n+1} - beta dt F = rc0 v^n + rc1 v^{n-1},
   // beta = (1+w)/(1+2w), rc0 = (1+w)^2/(1+2w), rc1 = -w^2/(1+2w)
   const bool var = bdf2 && !bdf3 && omega != 1.0;
@@ -402,12 +568,12 @@ static int32_t step_impl(const molt_grid* g, const molt_ch_params* p, void* d_u,
   const StepParams sp = step_params(p->eps, p->dt, beta, p->sigma0);
   const double al1 = 1.0 / sqrt(sp.s1), al2 = 1.0 / sqrt(sp.s2);
   const double hx = spacing(bc, nx, g->x0, g->x1);
-  const double hy = two_d ? spacing(bc, ny, g->y0, g->y1) : 1.0;
-  const LineCoef cx1 = make_line(nx, bc, M, al1, hx), cx2 = make_line(nx, bc, M, al2, hx);
-  LineCoef cy1, cy2;
-  if (two_d) {
-    cy1 = make_line(ny, bc, M, al1, hy);
-    cy2 = make_line(ny, bc, M, al2, hy);
+  const double hy = G.two_d ? spacing(bc, ny, g->y0, g->y1) : 1.0;
+  G.cx1 = make_line(nx, bc, M, al1, hx);
+  G.cx2 = make_line(nx, bc, M, al2, hx);
+  if (G.two_d) {
+    G.cy1 = make_line(ny, bc, M, al1, hy);
+    G.cy2 = make_line(ny, bc, M, al2, hy);
   }
 
   // Dirichlet walls: the line inverses no longer preserve constants, so the
@@ -427,7 +593,7 @@ static int32_t step_impl(const molt_grid* g, const molt_ch_params* p, void* d_u,
   HIPCHK(launch_state_init(st, p->tol, p->max_iter, p->fixed_iters, s));
   YFused fz;
   memset(&fz, 0, sizeof(fz));
-  if (two_d) {
+  if (G.two_d) {
     fz.rec = w + L.frec;
     fz.max_items = yfused_items(ny, nx, nc);
     fz.min_items = g_fused_min_items > 0x7fffffffLL ? 0x7fffffff : (int)g_fused_min_items;
@@ -436,126 +602,71 @@ static int32_t step_impl(const molt_grid* g, const molt_ch_params* p, void* d_u,
     // epochs restart at 1 every step: clear the words (as 32-bit ints)
     HIPCHK(launch_zero_ints((int*)fz.rec, (int)(2 * yfused_rec_words(ny, nx, nc)), s));
   }
+  YFused* fzp = G.two_d ? &fz : nullptr;
 
-  // R = A1^{-1} A2^{-1} rhs, A_i^{-1} = Lx_i^{-1} Ly_i^{-1}
-  PassArgs a;
-  memset(&a, 0, sizeof(a));
-  a.bdf2 = bdf2 ? (bdf3 ? 3 : (var ? 2 : 1)) : 0;
-  a.rc0 = (1.0 + omega) * (1.0 + omega) / (1.0 + 2.0 * omega);
-  a.rc1 = -omega * omega / (1.0 + 2.0 * omega);
-  a.in[0] = d_u;
-  a.in[1] = bdf2 ? d_u_prev : d_u;
-  a.in[2] = bdf3 ? d_u_prev2 : d_u;
-  // (vector model: both components at once, stacked as a batch of y-sweeps
-  // and as 2*ny rows of x-sweeps)
-  const int xl = ny * nc;
-  if (two_d) {
-    a.out[0] = F[F_A1];
-    ++fz.epoch;
-    HIPCHK(launch_ypass(prec, PROG_RHS, cy2, a, st, nx, nc, tot, jln, &fz, s));
-    a.in[0] = F[F_A1];
-    a.out[0] = F[F_B1];
-    HIPCHK(launch_xpass(prec, PROG_SWEEP, cx2, a, nullptr, xl, nullptr, s));
-    a.in[0] = F[F_B1];
-    a.out[0] = F[F_A1];
-    ++fz.epoch;
-    HIPCHK(launch_ypass(prec, PROG_SWEEP, cy1, a, st, nx, nc, tot, jln, &fz, s));
-    a.in[0] = F[F_A1];
-    a.out[0] = F[F_R];
-    HIPCHK(launch_xpass(prec, PROG_SWEEP, cx1, a, nullptr, xl, nullptr, s));
+  // rhs of the stepper
+  PassArgs ra;
+  memset(&ra, 0, sizeof(ra));
+  ra.bdf2 = bdf2 ? (bdf3 ? 3 : (var ? 2 : 1)) : 0;
+  ra.rc0 = (1.0 + omega) * (1.0 + omega) / (1.0 + 2.0 * omega);
+  ra.rc1 = -omega * omega / (1.0 + 2.0 * omega);
+  const size_t nel = n * nc;
+  const void* base = nullptr;     // the iterate of the full form (precision prec)
+  const void* base64 = nullptr;   // its FP64 value (hybrid)
+  int it = 0;
+  if (!L.hybrid) {
+    ra.in[0] = d_u;
+    ra.in[1] = bdf2 ? d_u_prev : d_u;
+    ra.in[2] = bdf3 ? d_u_prev2 : d_u;
+    MOLT_RC(enqueue_rhs(prec, G, ra, F, tot, jln, st, fzp, s));
+    base = p->init == MOLT_INIT_LINEAR ? F[F_R] : d_u;
   } else {
-    a.out[0] = F[F_B1];
-    HIPCHK(launch_xpass(prec, PROG_RHS, cx2, a, nullptr, xl, nullptr, s));
-    a.in[0] = F[F_B1];
-    a.out[0] = F[F_R];
-    HIPCHK(launch_xpass(prec, PROG_SWEEP, cx1, a, nullptr, xl, nullptr, s));
+    // FP64 shadow: the inputs widened, R and the first iteration in FP64,
+    // then the increment and running sum narrowed for the FP32 iterations
+    void* u64 = w + L.in64[0];
+    void* p64 = w + L.in64[1];
+    void* q64 = w + L.in64[2];
+    HIPCHK(launch_widen(u64, d_u, nel, s));
+    if (bdf2) HIPCHK(launch_widen(p64, d_u_prev, nel, s));
+    if (bdf3) HIPCHK(launch_widen(q64, d_u_prev2, nel, s));
+    ra.in[0] = u64;
+    ra.in[1] = bdf2 ? p64 : u64;
+    ra.in[2] = bdf3 ? q64 : u64;
+    MOLT_RC(enqueue_rhs(MOLT_F64, G, ra, F64, w + L.tot64, w + L.jln64, st, nullptr, s));
+    base64 = p->init == MOLT_INIT_LINEAR ? F64[F_R] : u64;
+    MOLT_RC(enqueue_iteration(MOLT_F64, G, sp, ush, 0, base64, F64, w + L.tot64, w + L.jln64, st, rpart, nullptr,
+                              s));
+    HIPCHK(launch_narrow(F[F_DL], F64[F_DL], nel, s));
+    HIPCHK(launch_narrow(F[F_W], F64[F_W], nel, s));
+    if (p->init == MOLT_INIT_LINEAR) HIPCHK(launch_narrow(F[F_R], F64[F_R], nel, s));
+    base = p->init == MOLT_INIT_LINEAR ? F[F_R] : d_u;
+    it = 1;
   }
   // history: u^{n-1} -> u_prev2, u^n -> u_prev (after the rhs has consumed them)
-  if (d_u_prev2 && d_u_prev) HIPCHK(launch_copy(prec, d_u_prev2, d_u_prev, n * nc, s));
-  if (d_u_prev) HIPCHK(launch_copy(prec, d_u_prev, d_u, n * nc, s));
+  if (d_u_prev2 && d_u_prev) HIPCHK(launch_copy(prec, d_u_prev2, d_u_prev, nel, s));
+  if (d_u_prev) HIPCHK(launch_copy(prec, d_u_prev, d_u, nel, s));
+  // (init PREV: the iterate's base is u^n, which the history copy above has
+  // just saved; d_u itself is overwritten only by the final result)
 
-  void* base = p->init == MOLT_INIT_LINEAR ? F[F_R] : d_u;
   const int fixed = p->fixed_iters;
   const int cap = fixed > 0 ? fixed : p->max_iter;
-  int it = 0;
   int batch = iter_hint > 1 ? iter_hint - 1 : 2;
   DevState hst;
   memset(&hst, 0, sizeof(hst));
   for (;;) {
     const int nb = batch < cap - it ? batch : cap - it;
-    for (int b = 0; b < nb; ++b, ++it) {
-      PassArgs q;
-      memset(&q, 0, sizeof(q));
-      q.sigma = sp.sigma;
-      q.kappa = sp.a / sp.s1;
-      q.mode = it == 0 ? 0 : 1;
-      q.ushift[0] = ush[0];
-      q.ushift[1] = ush[1];
-      // P1 (y, alpha1): a1 = Y1 e, b1 = Y1 lin (vector model: e, lin from the
-      // pointwise reaction pass, then both components swept as a batch)
-      q.in[0] = base;
-      q.in[1] = F[F_W];
-      q.in[2] = F[F_DL];
-      if (vch) {
-        q.out[0] = F[F_E];
-        q.out[1] = F[F_LIN];
-        HIPCHK(launch_vch_react(prec, q, st, n, s));
-        q.in[0] = F[F_E];
-        q.in[1] = F[F_LIN];
-        q.in[2] = nullptr;
-      }
-      q.out[0] = F[F_A1];
-      q.out[1] = F[F_B1];
-      const int p1 = vch ? PROG_P1V : PROG_P1;
-      if (two_d) {
-        ++fz.epoch;
-        HIPCHK(launch_ypass(prec, p1, cy1, q, st, nx, nc, tot, jln, &fz, s));
-      } else {
-        HIPCHK(launch_pointwise(prec, p1, q, st, n * nc, s));
-      }
-      // P2 (x, alpha1): C, q
-      q.in[0] = F[F_A1];
-      q.in[1] = F[F_B1];
-      if (vch) {
-        q.in[2] = F[F_E];
-        q.in[3] = F[F_LIN];
-        q.in[4] = nullptr;
-      } else {
-        q.in[2] = base;
-        q.in[3] = F[F_W];
-        q.in[4] = F[F_DL];
-      }
-      q.out[0] = F[F_C];
-      q.out[1] = F[F_Q];
-      HIPCHK(launch_xpass(prec, vch ? PROG_P2V : PROG_P2, cx1, q, st, xl, nullptr, s));
-      // P3 (y, alpha2): m, n
-      q.in[0] = F[F_C];
-      q.in[1] = F[F_Q];
-      q.in[2] = q.in[3] = q.in[4] = nullptr;
-      q.out[0] = F[F_M];
-      q.out[1] = F[F_N];
-      if (two_d) {
-        ++fz.epoch;
-        HIPCHK(launch_ypass(prec, PROG_P3, cy2, q, st, nx, nc, tot, jln, &fz, s));
-      } else {
-        HIPCHK(launch_pointwise(prec, PROG_P3, q, st, n * nc, s));
-      }
-      // P4 (x, alpha2): increment and running sum, residual
-      q.in[0] = F[F_M];
-      q.in[1] = F[F_N];
-      q.in[2] = q.mode ? F[F_DL] : F[F_R];
-      q.in[3] = F[F_W];
-      q.out[0] = F[F_DL];
-      q.out[1] = F[F_W];
-      HIPCHK(launch_xpass(prec, PROG_P4, cx2, q, st, xl, rpart, s));
-    }
+    for (int b = 0; b < nb; ++b, ++it)
+      MOLT_RC(enqueue_iteration(prec, G, sp, ush, it == 0 ? 0 : 1, base, F, tot, jln, st, rpart, fzp, s));
     HIPCHK(hipMemcpyAsync(&hst, st, sizeof(DevState), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     if (g_prof_on) prof_drain();
     if (hst.done || it >= cap) break;
     batch = batch < 32 ? batch * 2 : 32;
   }
-  HIPCHK(launch_finalize(prec, d_u, base, F[F_W], n * nc, s));
+  if (L.hybrid)
+    HIPCHK(launch_finalize_mixed(d_u, base64, F[F_W], nel, s));
+  else
+    HIPCHK(launch_finalize(prec, d_u, base, F[F_W], nel, s));
   if (vform) {
     HIPCHK(launch_addc(prec, d_u, ush[0], ush[1], n, nc, s));
     if (d_u_prev) HIPCHK(launch_addc(prec, d_u_prev, ush[0], ush[1], n, nc, s));
@@ -790,7 +901,7 @@ static int32_t batch_plan(const molt_instance* inst, int count, BatchPlan& P) {
     const int32_t rc = check_instance(inst[i], prec);
     if (rc != MOLT_OK) return fail(rc, "instance " + std::to_string(i) + ": " + g_err);
     const int nc = ncomp_of(&inst[i].params);
-    P.lay[i] = ch_layout(&inst[i].grid, prec, nc);
+    P.lay[i] = ch_layout(&inst[i].grid, prec, nc, false, false);
     P.slot_off[i] = off;
     off += al256(P.lay[i].total);
     P.rec_first[i] = P.nrec;
@@ -1213,7 +1324,7 @@ static size_t map_entries_max(const molt_instance& in, int prec) {
 }
 
 static size_t footprint(const molt_instance& in, int prec) {
-  return al256(ch_layout(&in.grid, prec, ncomp_of(&in.params)).total) +
+  return al256(ch_layout(&in.grid, prec, ncomp_of(&in.params), false, false).total) +
          al256((size_t)in.nsteps * sizeof(molt_step_info));
 }
 
@@ -1305,7 +1416,7 @@ static int32_t server_retire(molt_server* S) {
     if (!sl.used || sl.admit_round > r || S->pin[b][i].phase != PH_IDLE) continue;
     const molt_instance& in = S->insts[i];
     std::vector<molt_step_info> rec((size_t)in.nsteps);
-    const Layout L = ch_layout(&in.grid, S->prec, ncomp_of(&in.params));
+    const Layout L = ch_layout(&in.grid, S->prec, ncomp_of(&in.params), false, false);
     molt_result res;
     memset(&res, 0, sizeof(res));
     res.id = sl.id;
@@ -1352,7 +1463,7 @@ static int32_t server_admit(molt_server* S) {
     sl.map_need = mneed;
     S->map_used += mneed;
     S->insts[i] = q.inst;
-    const Layout L = ch_layout(&q.inst.grid, S->prec, ncomp_of(&q.inst.params));
+    const Layout L = ch_layout(&q.inst.grid, S->prec, ncomp_of(&q.inst.params), false, false);
     SlotDesc& d = S->up_desc[i];
     fill_slot(q.inst, L, S->w + off, (molt_step_info*)(S->w + off + al256(L.total)), d);
     SlotCtl& c = S->up_ctl[i];
@@ -1420,6 +1531,72 @@ static int32_t server_run(molt_server* S, int nrounds) {
 }  // namespace molt
 
 using namespace molt;
+
+// --------------------------------------------------------------------------
+// the line inverse along one axis of `batch` stacked fields (shared by
+// mol_t_helmholtz_sweep and its no-allocation variant)
+// --------------------------------------------------------------------------
+namespace molt {
+
+int32_t set_error(int32_t code, const char* msg) { return fail(code, msg); }
+
+int32_t sweep_check(const molt_grid* g, int32_t axis, double alpha, int32_t precision, const void* d_in,
+                    const void* d_out, int64_t batch) {
+  int32_t rc = check_grid(g, precision);
+  if (rc != MOLT_OK) return rc;
+  if (axis != 0 && axis != 1) return fail(MOLT_EINVAL, "axis must be 0 or 1");
+  if (!(alpha > 0) || !isfinite(alpha)) return fail(MOLT_EINVAL, "alpha must be positive");
+  if (batch < 1 || batch > 65535) return fail(MOLT_EINVAL, "batch must be in 1..65535");
+  if (!d_in || !d_out) return fail(MOLT_EINVAL, "NULL field pointer");
+  return MOLT_OK;
+}
+
+// y-pass scratch of a sweep under the current shape table: segment totals /
+// seeds (one field, two directions, per segment and column) and the periodic
+// closing-cell quadratures (one per column), each 256-byte aligned
+void sweep_scratch_layout(const molt_grid* g, int32_t precision, int64_t batch, size_t* tot_bytes,
+                          size_t* jln_bytes) {
+  const size_t esz = precision == MOLT_F64 ? 8 : 4;
+  int nth = 0, nseg = 0;
+  ypass_shape(precision, g->ny, &nth, &nseg);
+  *tot_bytes = al256((size_t)2 * nseg * g->nx * batch * esz);
+  *jln_bytes = al256((size_t)g->nx * batch * esz);
+}
+
+// tot, jln: y-pass scratch (axis 1, ny > 1); cpy: a field-sized buffer for an
+// in-place y sweep (NULL: in-place y sweeps are refused)
+int32_t sweep_impl(const molt_grid* g, int32_t axis, double alpha, int32_t precision, const void* d_in, void* d_out,
+                   int64_t batch, void* tot, void* jln, void* cpy, hipStream_t s) {
+  const size_t n = (size_t)g->nx * g->ny;
+  const size_t esz = precision == MOLT_F64 ? 8 : 4;
+  PassArgs a;
+  memset(&a, 0, sizeof(a));
+  a.in[0] = d_in;
+  a.out[0] = d_out;
+  if (axis == 0) {
+    const double hx = spacing(g->bc, g->nx, g->x0, g->x1);
+    const LineCoef c = make_line(g->nx, g->bc, g->order_M, alpha, hx);
+    const long long nlines = (long long)g->ny * batch;
+    if (nlines > 0x7fffffffLL) return fail(MOLT_EUNSUPPORTED, "too many lines");
+    HIPCHK(launch_xpass(precision, PROG_SWEEP, c, a, nullptr, (int)nlines, nullptr, s));
+    return MOLT_OK;
+  }
+  if (g->ny == 1) {  // y-direction of a 1D problem: identity
+    if (d_in != d_out) HIPCHK(hipMemcpyAsync(d_out, d_in, n * esz * batch, hipMemcpyDeviceToDevice, s));
+    return MOLT_OK;
+  }
+  if (d_in == d_out) {  // neighbouring segments read each other's rows: sweep from a copy
+    if (cpy == nullptr) return fail(MOLT_EINVAL, "an in-place y sweep needs a workspace copy of the field");
+    HIPCHK(launch_copy(precision, cpy, d_in, n * batch, s));
+    a.in[0] = cpy;
+  }
+  const double hy = spacing(g->bc, g->ny, g->y0, g->y1);
+  const LineCoef c = make_line(g->ny, g->bc, g->order_M, alpha, hy);
+  HIPCHK(launch_ypass(precision, PROG_SWEEP, c, a, nullptr, g->nx, (int)batch, tot, jln, nullptr, s));
+  return MOLT_OK;
+}
+
+}  // namespace molt
 
 extern "C" {
 
@@ -1500,45 +1677,18 @@ size_t molt_sweep_workspace_bytes(const molt_grid* g, int32_t axis, int32_t prec
 int32_t mol_t_helmholtz_sweep(const molt_grid* g, int32_t axis, double alpha, int32_t precision, const void* d_in,
                               void* d_out, int64_t batch, void* d_work, size_t work_bytes, void* stream) {
   g_err.clear();
-  int32_t rc = check_grid(g, precision);
+  int32_t rc = sweep_check(g, axis, alpha, precision, d_in, d_out, batch);
   if (rc != MOLT_OK) return rc;
-  if (axis != 0 && axis != 1) return fail(MOLT_EINVAL, "axis must be 0 or 1");
-  if (!(alpha > 0) || !isfinite(alpha)) return fail(MOLT_EINVAL, "alpha must be positive");
-  if (batch < 1 || batch > 65535) return fail(MOLT_EINVAL, "batch must be in 1..65535");
-  if (!d_in || !d_out) return fail(MOLT_EINVAL, "NULL field pointer");
-  hipStream_t s = (hipStream_t)stream;
-  const size_t n = (size_t)g->nx * g->ny;
+  if (axis == 0 || g->ny == 1) return sweep_impl(g, axis, alpha, precision, d_in, d_out, batch, nullptr, nullptr,
+                                                 nullptr, (hipStream_t)stream);
   const size_t esz = precision == MOLT_F64 ? 8 : 4;
-  PassArgs a;
-  memset(&a, 0, sizeof(a));
-  a.in[0] = d_in;
-  a.out[0] = d_out;
-  if (axis == 0) {
-    const double hx = spacing(g->bc, g->nx, g->x0, g->x1);
-    const LineCoef c = make_line(g->nx, g->bc, g->order_M, alpha, hx);
-    const long long nlines = (long long)g->ny * batch;
-    if (nlines > 0x7fffffffLL) return fail(MOLT_EUNSUPPORTED, "too many lines");
-    HIPCHK(launch_xpass(precision, PROG_SWEEP, c, a, nullptr, (int)nlines, nullptr, s));
-    return MOLT_OK;
-  }
-  if (g->ny == 1) {  // y-direction of a 1D problem: identity
-    if (d_in != d_out) HIPCHK(hipMemcpyAsync(d_out, d_in, n * esz * batch, hipMemcpyDeviceToDevice, s));
-    return MOLT_OK;
-  }
   const size_t need = molt_sweep_workspace_bytes(g, axis, precision, batch);
   if (!d_work || work_bytes < need) return fail(MOLT_EWORKSPACE, "workspace smaller than molt_sweep_workspace_bytes()");
   char* w = (char*)d_work;
   void* tot = w;
   void* jln = w + al256(ypass_tot_elems(precision, g->ny, g->nx, (int)batch) * esz);
   void* cpy = (char*)jln + al256((size_t)2 * g->nx * batch * esz);
-  if (d_in == d_out) {  // neighbouring segments read each other's rows: sweep from a copy
-    HIPCHK(launch_copy(precision, cpy, d_in, n * batch, s));
-    a.in[0] = cpy;
-  }
-  const double hy = spacing(g->bc, g->ny, g->y0, g->y1);
-  const LineCoef c = make_line(g->ny, g->bc, g->order_M, alpha, hy);
-  HIPCHK(launch_ypass(precision, PROG_SWEEP, c, a, nullptr, g->nx, (int)batch, tot, jln, nullptr, s));
-  return MOLT_OK;
+  return sweep_impl(g, axis, alpha, precision, d_in, d_out, batch, tot, jln, cpy, (hipStream_t)stream);
 }
 
 size_t ch_workspace_bytes(const molt_grid* g, const molt_ch_params* p) {

@@ -439,6 +439,38 @@ hipError_t launch_zero_ints(int* p, int n, hipStream_t s) {
   return hipGetLastError();
 }
 
+// FP32 <-> FP64 copies of the FP64 shadow of an FP32 step, and its final
+// u^{n+1} = base + W formed in FP64 and rounded once
+__global__ void __launch_bounds__(256) widen_kernel(double* dst, const float* src, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    dst[i] = (double)src[i];
+}
+__global__ void __launch_bounds__(256) narrow_kernel(float* dst, const double* src, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    dst[i] = (float)src[i];
+}
+__global__ void __launch_bounds__(256) finalize_mixed_kernel(float* u, const double* base, const float* W, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    u[i] = (float)(base[i] + (double)W[i]);
+}
+static dim3 grid_elems(size_t n) {
+  size_t b = (n + 255) / 256;
+  return dim3((unsigned)(b > 8192 ? 8192 : (b < 1 ? 1 : b)));
+}
+hipError_t launch_widen(void* dst64, const void* src32, size_t n, hipStream_t s) {
+  hipLaunchKernelGGL(widen_kernel, grid_elems(n), dim3(256), 0, s, (double*)dst64, (const float*)src32, n);
+  return hipGetLastError();
+}
+hipError_t launch_narrow(void* dst32, const void* src64, size_t n, hipStream_t s) {
+  hipLaunchKernelGGL(narrow_kernel, grid_elems(n), dim3(256), 0, s, (float*)dst32, (const double*)src64, n);
+  return hipGetLastError();
+}
+hipError_t launch_finalize_mixed(void* u32, const void* base64, const void* W32, size_t n, hipStream_t s) {
+  hipLaunchKernelGGL(finalize_mixed_kernel, grid_elems(n), dim3(256), 0, s, (float*)u32, (const double*)base64,
+                     (const float*)W32, n);
+  return hipGetLastError();
+}
+
 size_t ypass_tot_elems(int prec, int n, int nx, int batch) {
   (void)prec;
   const int K = 4;  // the smallest ky: room for every shape
