@@ -27,24 +27,55 @@
 
 namespace molt {
 
+// A hybrid slot (an FP32 instance with an FP64 shadow) runs its R phase and
+// the first (full-form) iteration of each step in the FP64 kernels and the
+// later iterations in the FP32 kernels; both are launched every tick and each
+// leaves the other's slots alone.
+__device__ __forceinline__ bool slot_fp64_phase(const SlotDesc& d, const SlotCtl& cc) {
+  return cc.phase == PH_R || (cc.phase == PH_IT && d.st->iters == 0);
+}
+template <typename T>
+__device__ __forceinline__ bool slot_mine(const SlotDesc& d, const SlotCtl& cc) {
+  if (!d.hybrid) return true;
+  return slot_fp64_phase(d, cc) == (sizeof(T) == 8);
+}
+
+// the fields and line-block shapes a slot uses in the kernels of type T
+struct SlotView {
+  void* const* F;
+  void* tot;
+  void* jln;
+  const void* u;     // u^n as the rhs and the full form read it
+  const void* hist;  // u^{n-1}
+  int32_t ynth, ynseg, yk, tlx, vecx, xblocks;
+};
+template <typename T>
+__device__ __forceinline__ SlotView slot_view(const SlotDesc& d) {
+  if (sizeof(T) == 8 && d.hybrid)
+    return SlotView{d.fld64, d.tot64, d.jln64, d.u64, d.hist64, d.ynth64, d.ynseg64, d.yk64, d.tlx64, d.vecx64,
+                    d.xblocks64};
+  return SlotView{d.fld, d.tot, d.jln, d.u, d.fld[F_HIST], d.ynth, d.ynseg, d.yk, d.tlx, d.vecx, d.xblocks};
+}
+
 // arguments of pass `pass` (1..4) of a slot in phase ph (the same fields as
 // the single-problem driver uses)
-__device__ __forceinline__ PassArgs slot_args(const SlotDesc& d, int ph, int pass, int var, int mode) {
+__device__ __forceinline__ PassArgs slot_args(const SlotDesc& d, const SlotView& v, int ph, int pass, int var,
+                                              int mode) {
   PassArgs a;
 #pragma unroll
   for (int i = 0; i < 6; ++i) a.in[i] = nullptr;
 #pragma unroll
   for (int i = 0; i < 3; ++i) a.out[i] = nullptr;
   a.ushift[0] = a.ushift[1] = 0.0;  // batched instances hold u (no Dirichlet walls)
-  void* const* F = d.fld;
+  void* const* F = v.F;
   if (ph == PH_R) {
     a.sigma = 0.0;
     a.kappa = 0.0;
     a.mode = 0;
     a.bdf2 = var;
     if (pass == 1) {
-      a.in[0] = d.u;
-      a.in[1] = var ? F[F_HIST] : d.u;
+      a.in[0] = v.u;
+      a.in[1] = var ? v.hist : v.u;
       a.out[0] = F[F_A1];
     } else if (pass == 2) {
       a.in[0] = F[F_A1];
@@ -61,7 +92,7 @@ __device__ __forceinline__ PassArgs slot_args(const SlotDesc& d, int ph, int pas
     a.kappa = d.kappa[var];
     a.mode = mode;
     a.bdf2 = 0;
-    const void* base = d.init == MOLT_INIT_LINEAR ? F[F_R] : d.u;
+    const void* base = d.init == MOLT_INIT_LINEAR ? F[F_R] : v.u;
     const bool vch = d.model == MOLT_MODEL_VCH;
     if (pass == 0) {  // vector model: the pointwise reaction pass
       a.in[0] = base;
@@ -108,40 +139,41 @@ __global__ void MOLT_PASS_ATTR ypass_batch_kernel(const SlotDesc* __restrict__ s
   const BlkMap e = map[blockIdx.x];
   const SlotDesc& d = sd[e.slot];
   const SlotCtl cc = ctl[e.slot];
-  if (cc.phase == PH_IDLE) return;
+  if (cc.phase == PH_IDLE || !slot_mine<T>(d, cc)) return;
+  const SlotView v = slot_view<T>(d);
   // block = (strip bx, segment by, component bz)
   const int bx = e.blk % d.ycols, rest = e.blk / d.ycols;
-  const int by = rest % d.ynseg, bz = rest / d.ynseg;
+  const int by = rest % v.ynseg, bz = rest / v.ynseg;
   const size_t fstride = (size_t)d.ny * (size_t)d.nx;
   const int var = cc.var;
   if (cc.phase == PH_R) {
     constexpr int PR = PASS == 1 ? PROG_RHS : PROG_SWEEP;
-    const PassArgs a = slot_args(d, PH_R, PASS, var, 0);
+    const PassArgs a = slot_args(d, v, PH_R, PASS, var, 0);
     const LineCoef& c = d.cy[var][PASS == 1 ? 1 : 0];
     if constexpr (FIN)
-      yfin_body<T, PR, K, M, PER>(c, a, nullptr, d.nx, d.ynth, d.ynseg, fstride, (const T*)d.tot, bx, by, bz);
+      yfin_body<T, PR, K, M, PER>(c, a, nullptr, d.nx, v.ynth, v.ynseg, fstride, (const T*)v.tot, bx, by, bz);
     else
-      ytot_body<T, PR, K, M, PER>(c, a, nullptr, d.nx, d.ynth, d.ynseg, fstride, (T*)d.tot, (T*)d.jln, bx, by, bz);
+      ytot_body<T, PR, K, M, PER>(c, a, nullptr, d.nx, v.ynth, v.ynseg, fstride, (T*)v.tot, (T*)v.jln, bx, by, bz);
   } else {
     DevState* st = d.st;
     if (st->done) return;
-    const PassArgs a = slot_args(d, PH_IT, PASS, var, st->iters > 0 ? 1 : 0);
+    const PassArgs a = slot_args(d, v, PH_IT, PASS, var, st->iters > 0 ? 1 : 0);
     const LineCoef& c = d.cy[var][PASS == 1 ? 0 : 1];
     if constexpr (PASS == 1) {
       if (d.model == MOLT_MODEL_VCH) {
         if constexpr (FIN)
-          yfin_body<T, PROG_P1V, K, M, PER>(c, a, st, d.nx, d.ynth, d.ynseg, fstride, (const T*)d.tot, bx, by, bz);
+          yfin_body<T, PROG_P1V, K, M, PER>(c, a, st, d.nx, v.ynth, v.ynseg, fstride, (const T*)v.tot, bx, by, bz);
         else
-          ytot_body<T, PROG_P1V, K, M, PER>(c, a, st, d.nx, d.ynth, d.ynseg, fstride, (T*)d.tot, (T*)d.jln, bx, by,
+          ytot_body<T, PROG_P1V, K, M, PER>(c, a, st, d.nx, v.ynth, v.ynseg, fstride, (T*)v.tot, (T*)v.jln, bx, by,
                                             bz);
         return;
       }
     }
     constexpr int PI = PASS == 1 ? PROG_P1 : PROG_P3;
     if constexpr (FIN)
-      yfin_body<T, PI, K, M, PER>(c, a, st, d.nx, d.ynth, d.ynseg, fstride, (const T*)d.tot, bx, by, bz);
+      yfin_body<T, PI, K, M, PER>(c, a, st, d.nx, v.ynth, v.ynseg, fstride, (const T*)v.tot, bx, by, bz);
     else
-      ytot_body<T, PI, K, M, PER>(c, a, st, d.nx, d.ynth, d.ynseg, fstride, (T*)d.tot, (T*)d.jln, bx, by, bz);
+      ytot_body<T, PI, K, M, PER>(c, a, st, d.nx, v.ynth, v.ynseg, fstride, (T*)v.tot, (T*)v.jln, bx, by, bz);
   }
 }
 
@@ -153,7 +185,8 @@ __global__ void __launch_bounds__(1024) ycomb_batch_kernel(const SlotDesc* __res
   const BlkMap e = map[blockIdx.x];
   const SlotDesc& d = sd[e.slot];
   const SlotCtl cc = ctl[e.slot];
-  if (cc.phase == PH_IDLE) return;
+  if (cc.phase == PH_IDLE || !slot_mine<T>(d, cc)) return;
+  const SlotView v = slot_view<T>(d);
   const bool r = cc.phase == PH_R;
   const int F = r ? 1 : 2;
   // block = (strip bx, field f, component b)
@@ -162,11 +195,11 @@ __global__ void __launch_bounds__(1024) ycomb_batch_kernel(const SlotDesc* __res
   if (f >= F) return;
   // pass 1: alpha2 in the R phase, alpha1 in an iteration; pass 3 the other way
   const LineCoef& c = d.cy[cc.var][((pass == 1) == r) ? 1 : 0];
-  const int ct = (d.ynseg + kCombWaves - 1) / kCombWaves;
+  const int ct = (v.ynseg + kCombWaves - 1) / kCombWaves;
   if (ct <= 8)
-    ycomb_body<T, 8>(c, r ? nullptr : d.st, d.nx, d.ynseg, kRG * d.yk, F, (T*)d.tot, (const T*)d.jln, bx, f, b);
+    ycomb_body<T, 8>(c, r ? nullptr : d.st, d.nx, v.ynseg, kRG * v.yk, F, (T*)v.tot, (const T*)v.jln, bx, f, b);
   else
-    ycomb_body<T, 32>(c, r ? nullptr : d.st, d.nx, d.ynseg, kRG * d.yk, F, (T*)d.tot, (const T*)d.jln, bx, f, b);
+    ycomb_body<T, 32>(c, r ? nullptr : d.st, d.nx, v.ynseg, kRG * v.yk, F, (T*)v.tot, (const T*)v.jln, bx, f, b);
 }
 
 // x-pass `PASS` (2 or 4)
@@ -177,26 +210,27 @@ __global__ void MOLT_PASS_ATTR xpass_batch_kernel(const SlotDesc* __restrict__ s
   const BlkMap e = map[blockIdx.x];
   const SlotDesc& d = sd[e.slot];
   const SlotCtl cc = ctl[e.slot];
-  if (cc.phase == PH_IDLE) return;
+  if (cc.phase == PH_IDLE || !slot_mine<T>(d, cc)) return;
+  const SlotView v = slot_view<T>(d);
   const int var = cc.var;
   const int nlines = d.ny * d.ncomp;  // the components' rows, stacked
   if (cc.phase == PH_R) {
-    const PassArgs a = slot_args(d, PH_R, PASS, var, 0);
-    xpass_body<T, PROG_SWEEP, K, M, PER>(d.cx[var][PASS == 2 ? 1 : 0], a, nullptr, nlines, d.tlx, nullptr, d.vecx,
+    const PassArgs a = slot_args(d, v, PH_R, PASS, var, 0);
+    xpass_body<T, PROG_SWEEP, K, M, PER>(d.cx[var][PASS == 2 ? 1 : 0], a, nullptr, nlines, v.tlx, nullptr, v.vecx,
                                          e.blk, smem);
   } else {
     DevState* st = d.st;
     if (st->done) return;
-    const PassArgs a = slot_args(d, PH_IT, PASS, var, st->iters > 0 ? 1 : 0);
+    const PassArgs a = slot_args(d, v, PH_IT, PASS, var, st->iters > 0 ? 1 : 0);
     if constexpr (PASS == 2) {
       if (d.model == MOLT_MODEL_VCH) {
-        xpass_body<T, PROG_P2V, K, M, PER>(d.cx[var][0], a, st, nlines, d.tlx, nullptr, d.vecx, e.blk, smem);
+        xpass_body<T, PROG_P2V, K, M, PER>(d.cx[var][0], a, st, nlines, v.tlx, nullptr, v.vecx, e.blk, smem);
         return;
       }
     }
     constexpr int PI = PASS == 2 ? PROG_P2 : PROG_P4;
-    xpass_body<T, PI, K, M, PER>(d.cx[var][PASS == 2 ? 0 : 1], a, st, nlines, d.tlx, PASS == 4 ? d.rpart : nullptr,
-                                 d.vecx, e.blk, smem);
+    xpass_body<T, PI, K, M, PER>(d.cx[var][PASS == 2 ? 0 : 1], a, st, nlines, v.tlx, PASS == 4 ? d.rpart : nullptr,
+                                 v.vecx, e.blk, smem);
   }
 }
 
@@ -208,7 +242,8 @@ __global__ void __launch_bounds__(256) close_batch_kernel(const SlotDesc* __rest
   const int slot = slots[blockIdx.x].slot;
   const SlotDesc& d = sd[slot];
   if (ctl[slot].phase != PH_IT) return;
-  residual_close_body(d.rpart, d.xblocks, d.st);
+  // (a hybrid slot's first iteration ran the FP64 x-pass and its blocks)
+  residual_close_body(d.rpart, (d.hybrid && d.st->iters == 0) ? d.xblocks64 : d.xblocks, d.st);
 }
 
 // step finish of converged slots: u^{n-1} <- u^n (the BDF2 history), u^{n+1} = base + W
@@ -222,8 +257,18 @@ __global__ void __launch_bounds__(256) finish_batch_kernel(const SlotDesc* __res
   const size_t n = (size_t)d.nx * (size_t)d.ny * (size_t)d.ncomp;
   T* u = (T*)d.u;
   T* h = (T*)d.fld[F_HIST];
-  const T* base = d.init == MOLT_INIT_LINEAR ? (const T*)d.fld[F_R] : u;
   const T* W = (const T*)d.fld[F_W];
+  if (sizeof(T) == 4 && d.hybrid) {  // u^{n+1} from the FP64 base, rounded once
+    const double* base = (const double*)(d.init == MOLT_INIT_LINEAR ? d.fld64[F_R] : d.u64);
+    for (size_t i = (size_t)e.blk * blockDim.x + threadIdx.x; i < n; i += (size_t)d.dblocks * blockDim.x) {
+      const T uo = u[i];
+      const double b = base[i];
+      h[i] = uo;
+      u[i] = (T)(b + (double)W[i]);
+    }
+    return;
+  }
+  const T* base = d.init == MOLT_INIT_LINEAR ? (const T*)d.fld[F_R] : u;
   for (size_t i = (size_t)e.blk * blockDim.x + threadIdx.x; i < n; i += (size_t)d.dblocks * blockDim.x) {
     const T uo = u[i];
     const T b = base[i];
@@ -231,6 +276,45 @@ __global__ void __launch_bounds__(256) finish_batch_kernel(const SlotDesc* __res
     u[i] = b + W[i];
   }
 }
+
+#ifndef MOLT_BATCH_F64  // (precision-independent: defined once)
+// hybrid slots: u^n (and u^{n-1} for a BDF2 step) widened to FP64 at the
+// start of a step, before the FP64 rhs sweeps read them
+__global__ void __launch_bounds__(256) widen_batch_kernel(const SlotDesc* __restrict__ sd,
+                                                          const SlotCtl* __restrict__ ctl,
+                                                          const BlkMap* __restrict__ map) {
+  const BlkMap e = map[blockIdx.x];
+  const SlotDesc& d = sd[e.slot];
+  const SlotCtl cc = ctl[e.slot];
+  if (!d.hybrid || cc.phase != PH_R) return;
+  const size_t n = (size_t)d.nx * (size_t)d.ny * (size_t)d.ncomp;
+  const float* u = (const float*)d.u;
+  const float* h = (const float*)d.fld[F_HIST];
+  double* u64 = (double*)d.u64;
+  double* h64 = (double*)d.hist64;
+  for (size_t i = (size_t)e.blk * blockDim.x + threadIdx.x; i < n; i += (size_t)d.dblocks * blockDim.x) {
+    u64[i] = (double)u[i];
+    if (cc.var) h64[i] = (double)h[i];
+  }
+}
+
+// hybrid slots after their FP64 first iteration: the increment and running
+// sum (and R, the base of the iterate) narrowed for the FP32 iterations
+__global__ void __launch_bounds__(256) narrow_batch_kernel(const SlotDesc* __restrict__ sd,
+                                                           const SlotCtl* __restrict__ ctl,
+                                                           const BlkMap* __restrict__ map) {
+  const BlkMap e = map[blockIdx.x];
+  const SlotDesc& d = sd[e.slot];
+  if (!d.hybrid || ctl[e.slot].phase != PH_IT || d.st->iters != 1) return;
+  const size_t n = (size_t)d.nx * (size_t)d.ny * (size_t)d.ncomp;
+  const bool lin = d.init == MOLT_INIT_LINEAR;
+  for (size_t i = (size_t)e.blk * blockDim.x + threadIdx.x; i < n; i += (size_t)d.dblocks * blockDim.x) {
+    ((float*)d.fld[F_DL])[i] = (float)((const double*)d.fld64[F_DL])[i];
+    ((float*)d.fld[F_W])[i] = (float)((const double*)d.fld64[F_W])[i];
+    if (lin) ((float*)d.fld[F_R])[i] = (float)((const double*)d.fld64[F_R])[i];
+  }
+}
+#endif
 
 template <typename T>
 __global__ void __launch_bounds__(256) diag_batch_kernel(const SlotDesc* __restrict__ sd,
@@ -253,8 +337,8 @@ __global__ void __launch_bounds__(256) react_batch_kernel(const SlotDesc* __rest
   const BlkMap e = map[blockIdx.x];
   const SlotDesc& d = sd[e.slot];
   const SlotCtl cc = ctl[e.slot];
-  if (d.model != MOLT_MODEL_VCH || cc.phase != PH_IT || d.st->done) return;
-  const PassArgs a = slot_args(d, PH_IT, 0, cc.var, d.st->iters > 0 ? 1 : 0);
+  if (d.model != MOLT_MODEL_VCH || cc.phase != PH_IT || d.st->done || !slot_mine<T>(d, cc)) return;
+  const PassArgs a = slot_args(d, slot_view<T>(d), PH_IT, 0, cc.var, d.st->iters > 0 ? 1 : 0);
   vch_react_body<T>(a, (size_t)d.nx * (size_t)d.ny, (size_t)e.blk * blockDim.x + threadIdx.x,
                     (size_t)d.dblocks * blockDim.x);
 }
@@ -461,10 +545,14 @@ hipError_t MOLT_BFN(launch_batch_x)(int K, int M, bool per, int pass, const Slot
 
 // close, step finish, diagnostics and tick end (kind "other_1") of the listed slots
 hipError_t MOLT_BFN(launch_batch_tail)(const SlotDesc* sd, SlotCtl* ctl, const BlkMap* slots, int nslots,
-                                      const BlkMap* pmap, int npblk, bool close_only, hipStream_t s) {
+                                      const BlkMap* pmap, int npblk, bool close_only, bool hybrid, hipStream_t s) {
   if (nslots <= 0) return hipSuccess;
   if (g_prof_on) prof_begin(KF_OTHER * 8 + 1, s);
   hipLaunchKernelGGL((close_batch_kernel<MOLT_BT>), dim3(nslots), dim3(256), 0, s, sd, (const SlotCtl*)ctl, slots);
+#ifndef MOLT_BATCH_F64
+  if (hybrid)
+    hipLaunchKernelGGL(narrow_batch_kernel, dim3(npblk), dim3(256), 0, s, sd, (const SlotCtl*)ctl, pmap);
+#endif
   if (close_only) {
     if (g_prof_on) prof_end(KF_OTHER * 8 + 1, s);
     return hipGetLastError();
@@ -475,6 +563,14 @@ hipError_t MOLT_BFN(launch_batch_tail)(const SlotDesc* sd, SlotCtl* ctl, const B
   if (g_prof_on) prof_end(KF_OTHER * 8 + 1, s);
   return hipGetLastError();
 }
+
+#ifndef MOLT_BATCH_F64
+hipError_t launch_batch_widen(const SlotDesc* sd, const SlotCtl* ctl, const BlkMap* pmap, int npblk, hipStream_t s) {
+  if (npblk <= 0) return hipSuccess;
+  hipLaunchKernelGGL(widen_batch_kernel, dim3(npblk), dim3(256), 0, s, sd, ctl, pmap);
+  return hipGetLastError();
+}
+#endif
 
 hipError_t MOLT_BFN(launch_batch_react)(const SlotDesc* sd, const SlotCtl* ctl, const BlkMap* pmap, int npblk,
                                        hipStream_t s) {

@@ -98,7 +98,8 @@ void ypass_shape(int prec, int n, int* nth, int* nseg);
   hipError_t launch_batch_x_##sfx(int K, int M, bool per, int pass, const SlotDesc* sd, const SlotCtl* ctl,    \
                                   const BlkMap* map, int nblk, hipStream_t s);                                 \
   hipError_t launch_batch_tail_##sfx(const SlotDesc* sd, SlotCtl* ctl, const BlkMap* slots, int nslots,        \
-                                     const BlkMap* pmap, int npblk, bool close_only, hipStream_t s);           \
+                                     const BlkMap* pmap, int npblk, bool close_only, bool hybrid,              \
+                                     hipStream_t s);                                                           \
   hipError_t launch_batch_react_##sfx(const SlotDesc* sd, const SlotCtl* ctl, const BlkMap* pmap, int npblk,   \
                                       hipStream_t s);                                                          \
   hipError_t launch_batch_init_##sfx(const SlotDesc* sd, SlotCtl* ctl, int nslots, hipStream_t s);             \
@@ -106,6 +107,7 @@ void ypass_shape(int prec, int n, int* nth, int* nseg);
 MOLT_BATCH_DECL(f32)
 MOLT_BATCH_DECL(f64)
 #undef MOLT_BATCH_DECL
+hipError_t launch_batch_widen(const SlotDesc* sd, const SlotCtl* ctl, const BlkMap* pmap, int npblk, hipStream_t s);
 int ypass_pick_k(int n, int prec);
 int ypass_max_segments(int n);
 int xpass_min_k(int n, int prec);
@@ -364,8 +366,7 @@ static bool field_used(int i, int ncomp, bool bdf3) {
   return true;
 }
 
-// shadow = false: no FP64 shadow even for FP32 (the batched engine)
-static Layout ch_layout(const molt_grid* g, int prec, int ncomp, bool bdf3 = false, bool shadow = true) {
+static Layout ch_layout(const molt_grid* g, int prec, int ncomp, bool bdf3 = false) {
   Layout L;
   memset(&L, 0, sizeof(L));
   const size_t esz = prec == MOLT_F64 ? 8 : 4;
@@ -387,7 +388,7 @@ static Layout ch_layout(const molt_grid* g, int prec, int ncomp, bool bdf3 = fal
   off += al256((size_t)g->ny * ncomp * sizeof(double));
   L.frec = off;  // fused y-pass: published segment totals
   off += al256(g->ny > 1 ? yfused_rec_words(g->ny, g->nx, ncomp) * sizeof(unsigned long long) : 0);
-  L.hybrid = prec == MOLT_F32 && shadow;
+  L.hybrid = prec == MOLT_F32;
   if (L.hybrid) {
     for (int i = 0; i < F_COUNT; ++i) {
       L.fld64[i] = off;
@@ -768,8 +769,8 @@ static hipError_t launch_batch_x(int prec, int K, int M, bool per, int pass, con
   return MOLT_BATCH_PREC(launch_batch_x)(K, M, per, pass, sd, ctl, map, nblk, s);
 }
 static hipError_t launch_batch_tail(int prec, const SlotDesc* sd, SlotCtl* ctl, const BlkMap* slots, int nslots,
-                                    const BlkMap* pmap, int npblk, bool close_only, hipStream_t s) {
-  return MOLT_BATCH_PREC(launch_batch_tail)(sd, ctl, slots, nslots, pmap, npblk, close_only, s);
+                                    const BlkMap* pmap, int npblk, bool close_only, bool hybrid, hipStream_t s) {
+  return MOLT_BATCH_PREC(launch_batch_tail)(sd, ctl, slots, nslots, pmap, npblk, close_only, hybrid, s);
 }
 static hipError_t launch_batch_react(int prec, const SlotDesc* sd, const SlotCtl* ctl, const BlkMap* pmap, int npblk,
                                      hipStream_t s) {
@@ -801,9 +802,12 @@ struct BatchPlan {
 };
 
 // Block maps of the slots in `act` (ascending): per-group ranges of one map.
+// An FP32 batch is hybrid: its R phases and first iterations run the FP64
+// kernels, grouped by the FP64 shapes (yg64, xg64).
 struct BatchMaps {
   bool any_vch = false;  // a vector-model slot is listed: the tick runs the reaction pass
-  std::vector<BatchGroup> yg, xg;
+  bool hybrid = false;
+  std::vector<BatchGroup> yg, xg, yg64, xg64;
   size_t comb_off = 0, pt_off = 0, sl_off = 0;
   int comb_n = 0, pt_n = 0, sl_n = 0;
   std::vector<BlkMap> map;
@@ -825,36 +829,28 @@ static int32_t check_instance(const molt_instance& in, int prec) {
 
 // y-passes are grouped by (M, boundary kind), x-passes by (K, M, boundary
 // kind); the combine, pointwise and per-slot kernels take every listed slot.
-static void batch_maps(const molt_instance* inst, const std::vector<int>& act, int prec, BatchMaps& B) {
-  B.yg.clear();
-  B.xg.clear();
-  B.map.clear();
-  B.any_vch = false;
-  for (int i : act) B.any_vch = B.any_vch || inst[i].params.model == MOLT_MODEL_VCH;
-  std::vector<BlkMap>& m = B.map;
+// y-pass and x-pass groups of one precision's shapes, appended to the map
+static void batch_pass_groups(const molt_instance* inst, const std::vector<int>& act, int prec,
+                              std::vector<BlkMap>& m, std::vector<BatchGroup>& yg, std::vector<BatchGroup>& xg) {
   const int ks[4] = {4, 8, 16, 32};
+  yg.clear();
+  xg.clear();
   for (int kk = 0; kk < 3; ++kk)
-  for (int M = 2; M <= 6; M += 2)
-    for (int per = 1; per >= 0; --per) {
-      BatchGroup g{ks[kk], M, per, m.size(), 0};
-      for (int i : act) {
-        const molt_grid& gr = inst[i].grid;
-        if (gr.order_M != M || (gr.bc == MOLT_BC_PERIODIC) != (per == 1)) continue;
-        if (ypass_pick_k(gr.ny, prec) != ks[kk]) continue;
-        int nth, nseg;
-        ypass_shape(prec, gr.ny, &nth, &nseg);
-        const int nb = ((gr.nx + 63) / 64) * nseg * ncomp_of(&inst[i].params);
-        for (int b = 0; b < nb; ++b) m.push_back(BlkMap{i, b});
+    for (int M = 2; M <= 6; M += 2)
+      for (int per = 1; per >= 0; --per) {
+        BatchGroup g{ks[kk], M, per, m.size(), 0};
+        for (int i : act) {
+          const molt_grid& gr = inst[i].grid;
+          if (gr.order_M != M || (gr.bc == MOLT_BC_PERIODIC) != (per == 1)) continue;
+          if (ypass_pick_k(gr.ny, prec) != ks[kk]) continue;
+          int nth, nseg;
+          ypass_shape(prec, gr.ny, &nth, &nseg);
+          const int nb = ((gr.nx + 63) / 64) * nseg * ncomp_of(&inst[i].params);
+          for (int b = 0; b < nb; ++b) m.push_back(BlkMap{i, b});
+        }
+        g.nblk = (int)(m.size() - g.off);
+        if (g.nblk > 0) yg.push_back(g);
       }
-      g.nblk = (int)(m.size() - g.off);
-      if (g.nblk > 0) B.yg.push_back(g);
-    }
-  B.comb_off = m.size();
-  for (int i : act) {
-    const int nb = 2 * ((inst[i].grid.nx + 63) / 64) * ncomp_of(&inst[i].params);
-    for (int b = 0; b < nb; ++b) m.push_back(BlkMap{i, b});
-  }
-  B.comb_n = (int)(m.size() - B.comb_off);
   for (int kk = 0; kk < 4; ++kk)
     for (int M = 2; M <= 6; M += 2)
       for (int per = 1; per >= 0; --per) {
@@ -870,8 +866,28 @@ static void batch_maps(const molt_instance* inst, const std::vector<int>& act, i
           for (int b = 0; b < nb; ++b) m.push_back(BlkMap{i, b});
         }
         g.nblk = (int)(m.size() - g.off);
-        if (g.nblk > 0) B.xg.push_back(g);
+        if (g.nblk > 0) xg.push_back(g);
       }
+}
+
+// y-passes are grouped by (K, M, boundary kind), x-passes by (K, M, boundary
+// kind); the combine, pointwise and per-slot kernels take every listed slot.
+static void batch_maps(const molt_instance* inst, const std::vector<int>& act, int prec, BatchMaps& B) {
+  B.map.clear();
+  B.any_vch = false;
+  B.hybrid = prec == MOLT_F32;
+  for (int i : act) B.any_vch = B.any_vch || inst[i].params.model == MOLT_MODEL_VCH;
+  std::vector<BlkMap>& m = B.map;
+  batch_pass_groups(inst, act, prec, m, B.yg, B.xg);
+  B.yg64.clear();
+  B.xg64.clear();
+  if (B.hybrid) batch_pass_groups(inst, act, MOLT_F64, m, B.yg64, B.xg64);
+  B.comb_off = m.size();
+  for (int i : act) {
+    const int nb = 2 * ((inst[i].grid.nx + 63) / 64) * ncomp_of(&inst[i].params);
+    for (int b = 0; b < nb; ++b) m.push_back(BlkMap{i, b});
+  }
+  B.comb_n = (int)(m.size() - B.comb_off);
   B.pt_off = m.size();
   for (int i : act) {
     const int nb = diag_blocks((size_t)inst[i].grid.nx * inst[i].grid.ny);
@@ -881,6 +897,21 @@ static void batch_maps(const molt_instance* inst, const std::vector<int>& act, i
   B.sl_off = m.size();
   for (int i : act) m.push_back(BlkMap{i, 0});
   B.sl_n = (int)(m.size() - B.sl_off);
+}
+
+// map entries one instance can need under any shape of the table (both
+// precisions' pass maps for an FP32 instance)
+static size_t map_entries_max(const molt_instance& in, int prec) {
+  const molt_grid& gr = in.grid;
+  const int nc = ncomp_of(&in.params);
+  const int ycols = (gr.nx + 63) / 64;
+  size_t e = 2 * (size_t)ycols * nc + (size_t)diag_blocks((size_t)gr.nx * gr.ny) + 1;
+  for (int pr = prec; ; pr = MOLT_F64) {
+    const int lpb = 256 / xpass_tl(gr.nx, xpass_min_k(gr.nx, pr));
+    e += ((size_t)ycols * ypass_max_segments(gr.ny) + (size_t)((gr.ny + lpb - 1) / lpb)) * nc;
+    if (pr == MOLT_F64) break;
+  }
+  return e;
 }
 
 // Workspace layout of a batch; the map area holds the maps of every slot (the
@@ -901,7 +932,7 @@ static int32_t batch_plan(const molt_instance* inst, int count, BatchPlan& P) {
     const int32_t rc = check_instance(inst[i], prec);
     if (rc != MOLT_OK) return fail(rc, "instance " + std::to_string(i) + ": " + g_err);
     const int nc = ncomp_of(&inst[i].params);
-    P.lay[i] = ch_layout(&inst[i].grid, prec, nc, false, false);
+    P.lay[i] = ch_layout(&inst[i].grid, prec, nc);
     P.slot_off[i] = off;
     off += al256(P.lay[i].total);
     P.rec_first[i] = P.nrec;
@@ -912,13 +943,7 @@ static int32_t batch_plan(const molt_instance* inst, int count, BatchPlan& P) {
     if (ticks > P.max_ticks) P.max_ticks = ticks;
     if (inst[i].nsteps > P.max_steps) P.max_steps = inst[i].nsteps;
     // map entries of the most fine-grained shapes the table allows
-    const molt_grid& gr = inst[i].grid;
-    const int nseg = ypass_max_segments(gr.ny);
-    const int ycols = (gr.nx + 63) / 64;
-    const int K = xpass_min_k(gr.nx, prec);
-    const int lpb = 256 / xpass_tl(gr.nx, K);
-    nmap += ((size_t)ycols * nseg + 2 * (size_t)ycols + (size_t)((gr.ny + lpb - 1) / lpb)) * nc +
-            (size_t)diag_blocks((size_t)gr.nx * gr.ny) + 1;
+    nmap += map_entries_max(inst[i], prec);
   }
   if (nmap > 0x7fffffffULL) return fail(MOLT_EUNSUPPORTED, "batch too large");
   P.desc = off;
@@ -989,6 +1014,20 @@ static void fill_slot(const molt_instance& in, const Layout& L, char* w, molt_st
   d.yk = ypass_pick_k(g.ny, prec);
   d.ycols = (g.nx + 63) / 64;
   d.dblocks = diag_blocks((size_t)g.nx * g.ny);
+  d.hybrid = L.hybrid ? 1 : 0;
+  if (L.hybrid) {
+    for (int f = 0; f < F_COUNT; ++f) d.fld64[f] = w + L.fld64[f];
+    d.tot64 = w + L.tot64;
+    d.jln64 = w + L.jln64;
+    d.u64 = w + L.in64[0];
+    d.hist64 = w + L.in64[1];
+    const int K64 = xpass_pick_k256(g.nx, MOLT_F64);
+    d.tlx64 = xpass_tl(g.nx, K64);
+    d.vecx64 = ((size_t)g.nx * 8) % 16 == 0 && (uintptr_t)w % 16 == 0;
+    d.xblocks64 = (g.ny * d.ncomp + 256 / d.tlx64 - 1) / (256 / d.tlx64);
+    ypass_shape(MOLT_F64, g.ny, &d.ynth64, &d.ynseg64);
+    d.yk64 = ypass_pick_k(g.ny, MOLT_F64);
+  }
 }
 
 // close_only: the iteration's close without the step finish and phase update
@@ -996,20 +1035,34 @@ static void fill_slot(const molt_instance& in, const Layout& L, char* w, molt_st
 static hipError_t batch_tick(int prec, const BatchMaps& B, const SlotDesc* sd, SlotCtl* ctl, const BlkMap* map,
                              hipStream_t s, bool close_only = false) {
   hipError_t e;
-  if (B.any_vch && (e = launch_batch_react(prec, sd, ctl, map + B.pt_off, B.pt_n, s)) != hipSuccess) return e;
+  // a hybrid batch runs every pass in the FP64 kernels (slots in their R phase
+  // or first iteration) and in the FP32 kernels (the others)
+  const int nprec = B.hybrid ? 2 : 1;
+  const int precs[2] = {B.hybrid ? MOLT_F64 : prec, prec};
+  if (B.hybrid && (e = launch_batch_widen(sd, ctl, map + B.pt_off, B.pt_n, s)) != hipSuccess) return e;
+  for (int k = 0; k < nprec && B.any_vch; ++k)
+    if ((e = launch_batch_react(precs[k], sd, ctl, map + B.pt_off, B.pt_n, s)) != hipSuccess) return e;
   for (int pass = 1; pass <= 3; pass += 2) {
-    for (const BatchGroup& g : B.yg)
-      if ((e = launch_batch_y(prec, g.K, g.M, g.per != 0, pass, false, sd, ctl, map + g.off, g.nblk, s)) != hipSuccess)
-        return e;
-    if ((e = launch_batch_comb(prec, pass, sd, ctl, map + B.comb_off, B.comb_n, s)) != hipSuccess) return e;
-    for (const BatchGroup& g : B.yg)
-      if ((e = launch_batch_y(prec, g.K, g.M, g.per != 0, pass, true, sd, ctl, map + g.off, g.nblk, s)) != hipSuccess)
-        return e;
-    for (const BatchGroup& g : B.xg)
-      if ((e = launch_batch_x(prec, g.K, g.M, g.per != 0, pass + 1, sd, ctl, map + g.off, g.nblk, s)) != hipSuccess)
-        return e;
+    for (int k = 0; k < nprec; ++k) {
+      const int pr = precs[k];
+      const std::vector<BatchGroup>& yg = (B.hybrid && k == 0) ? B.yg64 : B.yg;
+      for (const BatchGroup& g : yg)
+        if ((e = launch_batch_y(pr, g.K, g.M, g.per != 0, pass, false, sd, ctl, map + g.off, g.nblk, s)) != hipSuccess)
+          return e;
+      if ((e = launch_batch_comb(pr, pass, sd, ctl, map + B.comb_off, B.comb_n, s)) != hipSuccess) return e;
+      for (const BatchGroup& g : yg)
+        if ((e = launch_batch_y(pr, g.K, g.M, g.per != 0, pass, true, sd, ctl, map + g.off, g.nblk, s)) != hipSuccess)
+          return e;
+    }
+    for (int k = 0; k < nprec; ++k) {
+      const int pr = precs[k];
+      const std::vector<BatchGroup>& xg = (B.hybrid && k == 0) ? B.xg64 : B.xg;
+      for (const BatchGroup& g : xg)
+        if ((e = launch_batch_x(pr, g.K, g.M, g.per != 0, pass + 1, sd, ctl, map + g.off, g.nblk, s)) != hipSuccess)
+          return e;
+    }
   }
-  return launch_batch_tail(prec, sd, ctl, map + B.sl_off, B.sl_n, map + B.pt_off, B.pt_n, close_only, s);
+  return launch_batch_tail(prec, sd, ctl, map + B.sl_off, B.sl_n, map + B.pt_off, B.pt_n, close_only, B.hybrid, s);
 }
 
 // `ticks` ticks and the active-slot count, captured as one executable graph
@@ -1313,18 +1366,9 @@ static int32_t solve_adaptive_impl(const molt_grid* g, const molt_ch_params* p0,
 // --------------------------------------------------------------------------
 // serving: a resident batched engine that admits requests while others run
 // --------------------------------------------------------------------------
-// map entries one instance can need under any shape of the table
-static size_t map_entries_max(const molt_instance& in, int prec) {
-  const molt_grid& gr = in.grid;
-  const int nc = ncomp_of(&in.params);
-  const int ycols = (gr.nx + 63) / 64;
-  const int lpb = 256 / xpass_tl(gr.nx, xpass_min_k(gr.nx, prec));
-  return ((size_t)ycols * ypass_max_segments(gr.ny) + 2 * (size_t)ycols + (size_t)((gr.ny + lpb - 1) / lpb)) * nc +
-         (size_t)diag_blocks((size_t)gr.nx * gr.ny) + 1;
-}
 
 static size_t footprint(const molt_instance& in, int prec) {
-  return al256(ch_layout(&in.grid, prec, ncomp_of(&in.params), false, false).total) +
+  return al256(ch_layout(&in.grid, prec, ncomp_of(&in.params)).total) +
          al256((size_t)in.nsteps * sizeof(molt_step_info));
 }
 
@@ -1416,7 +1460,7 @@ static int32_t server_retire(molt_server* S) {
     if (!sl.used || sl.admit_round > r || S->pin[b][i].phase != PH_IDLE) continue;
     const molt_instance& in = S->insts[i];
     std::vector<molt_step_info> rec((size_t)in.nsteps);
-    const Layout L = ch_layout(&in.grid, S->prec, ncomp_of(&in.params), false, false);
+    const Layout L = ch_layout(&in.grid, S->prec, ncomp_of(&in.params));
     molt_result res;
     memset(&res, 0, sizeof(res));
     res.id = sl.id;
@@ -1463,7 +1507,7 @@ static int32_t server_admit(molt_server* S) {
     sl.map_need = mneed;
     S->map_used += mneed;
     S->insts[i] = q.inst;
-    const Layout L = ch_layout(&q.inst.grid, S->prec, ncomp_of(&q.inst.params), false, false);
+    const Layout L = ch_layout(&q.inst.grid, S->prec, ncomp_of(&q.inst.params));
     SlotDesc& d = S->up_desc[i];
     fill_slot(q.inst, L, S->w + off, (molt_step_info*)(S->w + off + al256(L.total)), d);
     SlotCtl& c = S->up_ctl[i];

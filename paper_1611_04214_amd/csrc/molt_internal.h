@@ -119,7 +119,17 @@ struct SlotDesc {          // constants of one slot, built on the host
   int32_t ynth, ynseg, ycols, dblocks;  // y-pass: threads per column, segments, 64-column strips
   int32_t yk;                           // y-pass nodes per thread
   int32_t model, ncomp;                 // MOLT_MODEL_*, field components (1 or 2)
-  int32_t pad_;
+  // FP32 instance with an FP64 shadow: its R phase and the first (full-form)
+  // iteration of every step run in the FP64 kernels on these fields, its
+  // later iterations in FP32 (the single-problem path does the same)
+  int32_t hybrid;
+  void* fld64[F_COUNT];
+  void* tot64;
+  void* jln64;
+  void* u64;                            // u^n widened at the start of a step
+  void* hist64;                         // u^{n-1} widened (BDF2 steps)
+  int32_t tlx64, vecx64, xblocks64;     // FP64 x-pass shape
+  int32_t ynth64, ynseg64, yk64;        // FP64 y-pass shape
 };
 
 // one block of a batched launch: (slot, block index within the slot)
