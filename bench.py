@@ -32,7 +32,17 @@ Also printed on the same JSON line:
   served        the served workload (Poisson arrivals of vector-model
                 requests): continuous batching against a plain FIFO of
                 ch_solve calls, p50/p99 latency and steps/s of each, also at a
-                sub-capacity rate.
+                sub-capacity rate and near capacity;
+  error         the FP32 result's max-abs and L2 error: against the FP64 path
+                on the full field (two steps), and against the FP64 oracle on a
+                periodic patch with the workload's grid spacing, eps and dt;
+  sweep         the standalone line inverse (mol_t_helmholtz_sweep) along x
+                and along y of the 4096^2 field, FP32 and FP64: Gpt-sweeps/s and
+                the fraction of 8 TB/s;
+  ch1d, ch2d_neumann  the 1D (N=256, BE, FP64, 200 steps) and 512^2 Neumann
+                (BDF2, 2000 steps, FP64 then FP32) workloads: steps/s on the
+                GPU and of the oracle (one core and all cores), errors.
+The process frees its device memory and prints the JSON line last.
 """
 from __future__ import annotations
 
@@ -48,21 +58,25 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 
-# Algorithmic HBM bytes per grid point of one launch, FP32, as (increment
-# form, first-iteration full form): field reads + writes, plus the three-kernel
-# y-pass's per-segment totals / seeds (2 fields x 2 directions x 4 B per 64 rows).
+# Algorithmic HBM bytes per grid point of one launch of the FP32 iteration
+# kernels (increment form: every FP32 iteration after a step's FP64 first one):
+# field reads + writes, plus the three-kernel y-pass's per-segment totals /
+# seeds (2 fields x 2 directions x 4 B per 64 rows).
 BYTES_PER_POINT = {
-    "ytot_P1": (12 + 0.25, 4 + 0.25),
-    "ycomb_P1": (0.5, 0.5),
-    "yfin_P1": (12 + 0.25 + 8, 4 + 0.25 + 8),
-    "xpass_P2": (20 + 8, 12 + 8),
-    "ytot_P3": (8 + 0.25, 8 + 0.25),
-    "ycomb_P3": (0.5, 0.5),
-    "yfin_P3": (8 + 0.25 + 8, 8 + 0.25 + 8),
-    "xpass_P4": (16 + 8, 12 + 8),
+    "ytot_P1": 12 + 0.25,
+    "ycomb_P1": 0.5,
+    "yfin_P1": 12 + 0.25 + 8,
+    "xpass_P2": 20 + 8,
+    "ytot_P3": 8 + 0.25,
+    "ycomb_P3": 0.5,
+    "yfin_P3": 8 + 0.25 + 8,
+    "xpass_P4": 16 + 8,
 }
 # the single-kernel y-pass is timed under the yfin kinds and reads its inputs once
-BYTES_PER_POINT_FUSED = {"yfin_P1": (12 + 8, 4 + 8), "yfin_P3": (8 + 8, 8 + 8)}
+BYTES_PER_POINT_FUSED = {"yfin_P1": 12 + 8, "yfin_P3": 8 + 8}
+# one whole FP32 iteration with every field read once and written once:
+# P1 3 reads + 2 writes, P2 5 + 2, P3 2 + 2, P4 4 + 2, 4 B each
+ITER_BYTES_PER_POINT = 88.0
 
 
 COUNTERS = os.path.join(ROOT, "profiles", "xpass_4096_fp32_hbm_counters.md")
@@ -101,15 +115,19 @@ def parse():
     ap.add_argument("--max-iter", type=int, default=50000, help="iteration cap per step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=24, help="oracle iterations in the CPU sample")
-    ap.add_argument("--batch-steps", type=int, default=10,
+    ap.add_argument("--batch-steps", type=int, default=100,
                     help="steps per instance of the batched workload (0: skip it)")
     ap.add_argument("--batch-count", type=int, default=256, help="instances of the batched workload")
     ap.add_argument("--no-batch-plain", action="store_true", help="skip the plain-path timing of the batch")
-    ap.add_argument("--serve-count", type=int, default=64,
+    ap.add_argument("--serve-count", type=int, default=200,
                     help="requests of the served workload (0: skip it)")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="mean arrival rate of the served workload (1/s)")
-    ap.add_argument("--serve-sub-count", type=int, default=16,
-                    help="requests of the sub-capacity served trace (0: skip it)")
+    ap.add_argument("--serve-sub-count", type=int, default=200,
+                    help="requests of the sub-capacity and near-capacity served traces (0: skip them)")
+    ap.add_argument("--no-small", action="store_true", help="skip the 1D and 512^2 Neumann workloads")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the standalone sweep measurement")
+    ap.add_argument("--no-error", action="store_true", help="skip the FP32 error measurement")
+    ap.add_argument("--c2-steps", type=int, default=2000, help="steps of the 512^2 Neumann workload")
     ap.add_argument("--no-profile", action="store_true", help="do not time kernels with HIP events")
     ap.add_argument("--fused-min-items", type=int, default=None,
                     help="work items from which the single-kernel y-pass is used (library default 256)")
@@ -175,6 +193,7 @@ def run_batched(args, molt, synth):
            "status": st, "batched_s": round(tb, 3), "batched_steps_per_s": round(nsteps / tb, 1),
            "batched_gpt_sweeps_per_s": round(sweeps / tb / 1e9, 2),
            "ticks_max": max(ticks), "ticks_median": int(np.median(ticks)),
+           "us_per_tick_upper_bound_longest": round(1e6 * tb / max(ticks), 1),
            "mean_iters_per_step": round(float(np.mean([np.mean(x) for x in iters])), 1),
            "autotune_s": round(tune_s, 3), "shape_table_fp32": table[:4]}
     if not args.no_batch_plain:
@@ -284,15 +303,231 @@ def run_served(args, molt, synth):
                           "steps_per_s": round(steps / fspan, 1), "busy_s": round(sum(durs), 3)},
            "bitwise_equal_to_plain": same}
     if args.serve_sub_count > 0:
+        # the same requests re-timed at half and at 0.9 of the measured served
+        # throughput (the overloaded trace's requests per second)
         m = min(args.serve_sub_count, len(reqs))
-        rate = 0.5 * len(reqs) / makespan  # half the measured served throughput (requests/s)
-        sub_arr = [arrivals[i] * args.serve_rate / rate for i in range(m)]
-        slat, _, _ = _serve_trace(molt, reqs[:m], u0[:m], sub_arr, pool)
-        sflat, _ = fifo(sub_arr, durs[:m])
-        out["sub_capacity"] = {"rate_per_s": round(rate, 3), "requests": m,
-                               "served": {"p50_s": pct(slat, 50), "p99_s": pct(slat, 99)},
-                               "fifo_plain": {"p50_s": pct(sflat, 50), "p99_s": pct(sflat, 99)}}
+        cap = len(reqs) / makespan
+        out["capacity_req_per_s"] = round(cap, 3)
+        for key, frac in (("sub_capacity", 0.5), ("near_capacity", 0.9)):
+            rate = frac * cap
+            sub_arr = [arrivals[i] * args.serve_rate / rate for i in range(m)]
+            slat, sspan, _ = _serve_trace(molt, reqs[:m], u0[:m], sub_arr, pool)
+            sflat, _ = fifo(sub_arr, durs[:m])
+            out[key] = {"rate_per_s": round(rate, 3), "requests": m,
+                        "served": {"p50_s": pct(slat, 50), "p99_s": pct(slat, 99), "makespan_s": round(sspan, 3)},
+                        "fifo_plain": {"p50_s": pct(sflat, 50), "p99_s": pct(sflat, 99)}}
     print(f"served: {json.dumps(out)}", file=sys.stderr, flush=True)
+    return out
+
+
+def host_threads() -> int:
+    """Threads for the oracle's all-core leg: OMP_NUM_THREADS when set (the
+    process's share of the host), else the logical CPUs."""
+    try:
+        return max(1, int(os.environ["OMP_NUM_THREADS"]))
+    except (KeyError, ValueError):
+        return os.cpu_count() or 1
+
+
+def cpu_info():
+    """(model name, logical CPUs) of this host."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return model, os.cpu_count() or 1
+
+
+def _timed(fn):
+    import torch
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    r = fn()
+    torch.cuda.synchronize()
+    return r, time.perf_counter() - t
+
+
+def run_error(molt, synth, oracle, w, n):
+    """Max-abs and L2 error of the FP32 path on the 4096^2 workload: two steps
+    (BE start-up, one BDF2 step) of the full field in FP32 and in FP64 on the
+    GPU (the FP64 path matches the oracle to 1e-12 relative in the tests), and
+    three steps of a 256^2 periodic patch with the workload's grid spacing,
+    eps and dt against the FP64 oracle at the same tolerance."""
+    import numpy as np
+    import torch
+    out = {}
+    grid = molt.make_grid(n, n, 0.0, w["L"], 0.0, w["L"], molt.MOLT_BC_PERIODIC, w["M"])
+    u0 = synth.workload_u0("ch2d_periodic_bdf2_4096", n)
+    res = {}
+    for prec, dt in ((molt.MOLT_F64, torch.float64), (molt.MOLT_F32, torch.float32)):
+        p = molt.make_params(w["eps"], w["dt"], tol=w["tol"], stepper=molt.MOLT_BDF2, max_iter=20000,
+                             init=molt.MOLT_INIT_LINEAR, precision=prec)
+        x = torch.tensor(u0, dtype=dt, device="cuda:0")
+        (st, infos), _ = _timed(lambda: molt.solve(x, grid, p, 2))
+        res[prec] = (x.double().cpu().numpy(), [i.iters for i in infos], infos[-1].mass)
+        del x
+    d = res[molt.MOLT_F32][0] - res[molt.MOLT_F64][0]
+    out["full_field_vs_fp64_gpu"] = {
+        "steps": 2, "max_abs": float(np.abs(d).max()), "l2": float(np.sqrt((d ** 2).mean())),
+        "iters_fp32": res[molt.MOLT_F32][1], "iters_fp64": res[molt.MOLT_F64][1],
+        "mass_fp32_minus_fp64": res[molt.MOLT_F32][2] - res[molt.MOLT_F64][2]}
+    m = 256
+    L = w["L"] * m / n
+    g = molt.make_grid(m, m, 0.0, L, 0.0, L, molt.MOLT_BC_PERIODIC, w["M"])
+    up = synth.u0_normal_noise(synth.BASE_SEED + 7, m, m, 0.3, 0.05)
+    og = oracle.Grid(nx=m, ny=m, x0=0.0, x1=L, y0=0.0, y1=L, bc=oracle.BC_PERIODIC, M=w["M"])
+    po = oracle.Params(eps=w["eps"], dt=w["dt"], tol=w["tol"], stepper=oracle.BDF2, max_iter=20000,
+                       init=oracle.INIT_LINEAR)
+    ref, rinf = oracle.solve(og, po, up, 3)
+    x = torch.tensor(up, dtype=torch.float32, device="cuda:0")
+    p = molt.make_params(w["eps"], w["dt"], tol=w["tol"], stepper=molt.MOLT_BDF2, max_iter=20000,
+                         init=molt.MOLT_INIT_LINEAR, precision=molt.MOLT_F32)
+    st, infos = molt.solve(x, g, p, 3)
+    e = x.double().cpu().numpy() - ref
+    out["patch_vs_oracle"] = {
+        "patch": f"{m}x{m} periodic, h = 1/{n}, eps {w['eps']}, BDF2 dt {w['dt']}, tol {w['tol']}, 3 steps",
+        "max_abs": float(np.abs(e).max()), "l2": float(np.sqrt((e ** 2).mean())),
+        "iters_fp32": [i.iters for i in infos], "iters_oracle": [i.iters for i in rinf]}
+    out["target_max_abs"] = 1e-5
+    print(f"error: {json.dumps(out)}", file=sys.stderr, flush=True)
+    return out
+
+
+def run_sweep(molt, n, L, M, launches=20):
+    """The standalone line inverse along x and along y of an n x n periodic
+    field, FP32 and FP64, timed with events around `launches` back-to-back
+    launches on the current stream (one launch = one inverse of every line)."""
+    import torch
+    out = {}
+    g = molt.make_grid(n, n, 0.0, L, 0.0, L, molt.MOLT_BC_PERIODIC, M)
+    stream = torch.cuda.current_stream()
+    for prec, dt, tag in ((molt.MOLT_F32, torch.float32, "fp32"), (molt.MOLT_F64, torch.float64, "fp64")):
+        x = torch.rand(n, n, dtype=dt, device="cuda:0", generator=torch.Generator("cuda:0").manual_seed(7))
+        y = torch.empty_like(x)
+        esz = x.element_size()
+        for axis, name in ((0, "x"), (1, "y")):
+            need = molt.molt_sweep_workspace_bytes(g, axis, prec, 1)
+            work = molt.workspace(need)
+            args = (g, axis, 278.3, prec, x.data_ptr(), y.data_ptr(), 1, work.data_ptr(), work.numel(),
+                    stream.cuda_stream)
+            for _ in range(3):
+                molt.mol_t_helmholtz_sweep(*args)
+            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            ev0.record(stream)
+            for _ in range(launches):
+                rc = molt.mol_t_helmholtz_sweep(*args)
+            ev1.record(stream)
+            torch.cuda.synchronize()
+            if rc != molt.MOLT_OK:
+                raise molt.MoltError(rc, "mol_t_helmholtz_sweep")
+            sec = ev0.elapsed_time(ev1) / 1e3 / launches
+            byts = n * n * 2 * esz  # read the field once, write it once
+            out[f"{name}_{tag}"] = {"gpt_sweeps_per_s": round(n * n / sec / 1e9, 1), "us_per_launch": round(sec * 1e6, 2),
+                                    "gb_per_s": round(byts / sec / 1e9, 1),
+                                    "frac_of_8tbs": round(byts / sec / 1e9 / HBM_PEAK_GBS, 4)}
+            del work
+        del x, y
+    out["field"] = f"{n}x{n} periodic, alpha = 278.3 (the 4096^2 workload's), M = {M}; bytes = field read + written"
+    print(f"sweep: {json.dumps(out)}", file=sys.stderr, flush=True)
+    return out
+
+
+def run_small(args, molt, synth, oracle):
+    """The 1D workload (N = 256, BE, FP64, tol 1e-10, 200 steps) and the 512^2
+    Neumann workload (BDF2 dt 5e-5, 2000 steps; FP64, then FP32 with the FP64
+    setup phase): steps/s on the GPU and of the oracle on one core and on all
+    cores, and their errors."""
+    import numpy as np
+    import torch
+    nthreads = host_threads()
+    out = {}
+    # ---- 1D
+    w = synth.WORKLOADS["ch1d_be_n256"]
+    u0 = synth.workload_u0("ch1d_be_n256")
+    g = molt.make_grid(w["n"], 1, 0.0, w["L"], 0.0, 1.0, molt.MOLT_BC_PERIODIC, w["M"])
+    p = molt.make_params(w["eps"], w["dt"], tol=w["tol"], stepper=molt.MOLT_BE, max_iter=5000,
+                         precision=molt.MOLT_F64)
+    x = torch.tensor(u0, dtype=torch.float64, device="cuda:0")
+    molt.solve(x.clone(), g, p, 2)  # warm-up
+    (st, infos), tg = _timed(lambda: molt.solve(x, g, p, w["steps"]))
+    og = oracle.Grid(nx=w["n"], bc=oracle.BC_PERIODIC, M=w["M"], x0=0.0, x1=w["L"])
+    po = oracle.Params(eps=w["eps"], dt=w["dt"], tol=w["tol"], stepper=oracle.BE, max_iter=5000)
+    times = {}
+    for th in (1, nthreads):
+        oracle.set_threads(th)
+        t = time.perf_counter()
+        ref, rinf = oracle.solve(og, po, u0, w["steps"])
+        times[th] = time.perf_counter() - t
+    e = x.cpu().numpy() - ref
+    print(f"ch1d: gpu {tg:.2f} s, oracle 1 core {times[1]:.2f} s", file=sys.stderr, flush=True)
+    out["ch1d"] = {"workload": "1D CH periodic [0,2pi], N=256, eps 0.05, BE dt 1e-3, tol 1e-10, M=4, 200 steps, FP64",
+                   "gpu_steps_per_s": round(w["steps"] / tg, 1), "oracle_steps_per_s_1core": round(w["steps"] / times[1], 1),
+                   f"oracle_steps_per_s_{nthreads}cores": round(w["steps"] / times[nthreads], 1),
+                   "max_abs_vs_oracle": float(np.abs(e).max()), "l2_vs_oracle": float(np.sqrt((e ** 2).mean())),
+                   "same_iterations": [i.iters for i in infos] == [i.iters for i in rinf],
+                   "iters_total": int(sum(i.iters for i in infos))}
+    # ---- 512^2 Neumann
+    w = synth.WORKLOADS["ch2d_neumann_bdf2_512"]
+    n = w["n"]
+    u0 = synth.workload_u0("ch2d_neumann_bdf2_512")
+    g = molt.make_grid(n, n, 0.0, 1.0, 0.0, 1.0, molt.MOLT_BC_NEUMANN, w["M"])
+    nst = args.c2_steps
+    fields, rec = {}, {}
+    for prec, dt, tol in ((molt.MOLT_F64, torch.float64, 1e-10), (molt.MOLT_F32, torch.float32, 1e-8)):
+        p = molt.make_params(w["eps"], w["dt"], tol=tol, stepper=molt.MOLT_BDF2, max_iter=5000,
+                             init=molt.MOLT_INIT_LINEAR, precision=prec)
+        x = torch.tensor(u0, dtype=dt, device="cuda:0")
+        (st, infos), tg = _timed(lambda: molt.solve(x, g, p, nst))
+        fields[prec] = x.double().cpu().numpy()
+        it = [i.iters for i in infos]
+        print(f"ch2d_neumann: precision {prec}: {nst} steps in {tg:.1f} s, mean iterations {np.mean(it):.1f}",
+              file=sys.stderr, flush=True)
+        rec[prec] = {"status": st, "gpu_steps_per_s": round(nst / tg, 1), "seconds": round(tg, 2),
+                     "iters_first": it[:4], "iters_mean": round(float(np.mean(it)), 1), "iters_max": max(it),
+                     "steps_over_300_iters": int(sum(1 for k in it if k > 300)),
+                     "energy_first_last": [infos[0].energy, infos[-1].energy],
+                     "gpt_sweeps_per_s": round(n * n * sum(4 + 7 * k for k in it) / tg / 1e9, 2)}
+    d = fields[molt.MOLT_F32] - fields[molt.MOLT_F64]
+    # the oracle: 3 converged steps (all cores, compared with both GPU runs'
+    # first 3 steps), and a bounded 1-core sample
+    og = oracle.Grid(nx=n, ny=n, x0=0.0, x1=1.0, y0=0.0, y1=1.0, bc=oracle.BC_NEUMANN, M=w["M"])
+    oracle.set_threads(nthreads)
+    po = oracle.Params(eps=w["eps"], dt=w["dt"], tol=1e-10, stepper=oracle.BDF2, max_iter=5000,
+                       init=oracle.INIT_LINEAR)
+    t = time.perf_counter()
+    ref, rinf = oracle.solve(og, po, u0, 3)
+    t_all = time.perf_counter() - t
+    errs = {}
+    for prec, dt, tol in ((molt.MOLT_F64, torch.float64, 1e-10), (molt.MOLT_F32, torch.float32, 1e-8)):
+        p = molt.make_params(w["eps"], w["dt"], tol=tol, stepper=molt.MOLT_BDF2, max_iter=5000,
+                             init=molt.MOLT_INIT_LINEAR, precision=prec)
+        x = torch.tensor(u0, dtype=dt, device="cuda:0")
+        molt.solve(x, g, p, 3)
+        e = x.double().cpu().numpy() - ref
+        errs[prec] = {"max_abs": float(np.abs(e).max()), "l2": float(np.sqrt((e ** 2).mean()))}
+    oracle.set_threads(1)
+    po1 = oracle.Params(eps=w["eps"], dt=w["dt"], stepper=oracle.BE, fixed_iters=10, init=oracle.INIT_LINEAR)
+    t = time.perf_counter()
+    oracle.step(og, po1, u0)
+    t_one = time.perf_counter() - t
+    oracle.set_threads(nthreads)
+    its = sum(i.iters for i in rinf)
+    out["ch2d_neumann"] = {
+        "workload": f"2D CH Neumann [0,1]^2, 512x512, eps 0.01, BDF2 dt 5e-5 (BE start-up), M=4, init R, "
+                    f"{nst} steps; FP64 tol 1e-10, FP32 tol 1e-8, iteration cap 5000",
+        "fp64": rec[molt.MOLT_F64], "fp32": rec[molt.MOLT_F32],
+        "fp32_vs_fp64_after_all_steps": {"max_abs": float(np.abs(d).max()), "l2": float(np.sqrt((d ** 2).mean()))},
+        "vs_oracle_after_3_steps": {"fp64": errs[molt.MOLT_F64], "fp32": errs[molt.MOLT_F32],
+                                    "oracle_iters": [i.iters for i in rinf]},
+        "oracle_gpt_sweeps_per_s": {f"{nthreads}cores": round(n * n * (12 + 7 * its) / t_all / 1e9, 4),
+                                    "1core": round(n * n * (4 + 7 * 10) / t_one / 1e9, 4)},
+        "oracle_steps_per_s": {f"{nthreads}cores (first 3 steps)": round(3 / t_all, 3)},
+    }
+    print(f"small: {json.dumps(out)}", file=sys.stderr, flush=True)
     return out
 
 
@@ -404,14 +639,14 @@ def main():
         table = dict(BYTES_PER_POINT, **(BYTES_PER_POINT_FUSED if fused else {}))
         dom = max((k for k in prof if k in table), key=lambda k: prof[k][1], default=None)
         if dom is not None:
-            # one launch of each fixed-point pass per iteration did work; launches
-            # queued after convergence exit at once, and their (small) time is
-            # left in the total (pessimistic)
+            # the FP32 kernels run the increment-form iterations (each step's
+            # first iteration runs in FP64, timed under the f64_ kinds); one
+            # launch of each pass per iteration did work, launches queued after
+            # convergence exit at once and their (small) time is left in the
+            # total (pessimistic)
             _, ms = prof[dom]
-            real = sum(iters)
-            b_delta, b_full = table[dom]
-            bytes_total = pts * ((real - nsteps) * b_delta + nsteps * b_full)
-            per_launch = bytes_total / real
+            real = sum(iters) - nsteps
+            per_launch = pts * table[dom]
             avg_s = ms / 1e3 / real
             achieved = per_launch / avg_s / 1e9
             roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -422,25 +657,58 @@ def main():
             roof["kernel_share_of_gpu_time"] = (round(every[dom][1] / total_ms, 3)
                                                 if total_ms > 0 and dom in every else None)
             roof["timed_in_timed_steps"] = sorted(prof)
+    if warm_prof:
+        # the whole FP32 iteration: every field read once and written once
+        # (ITER_BYTES_PER_POINT) over the summed time of the iteration's FP32
+        # kernels in the last warm-up step (which timed every kernel)
+        it_kinds = [k for k in warm_prof if k in BYTES_PER_POINT or k == "other_sweep"]
+        it_ms = sum(warm_prof[k][1] for k in it_kinds)
+        real_w = warm[-1][0] - 1
+        if it_ms > 0 and real_w > 0:
+            per_it_s = it_ms / 1e3 / real_w
+            gbs = float(n) * n * ITER_BYTES_PER_POINT / per_it_s / 1e9
+            whole = {"achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_point": ITER_BYTES_PER_POINT,
+                     "kernel_us_per_iteration": round(per_it_s * 1e6, 2),
+                     "kernels": sorted(it_kinds),
+                     # what the kernels move (the three-kernel y-pass reads its inputs twice)
+                     "moved_bytes_per_point": sum(BYTES_PER_POINT[k] for k in BYTES_PER_POINT if k in warm_prof)}
+            wall_us = 1e6 * elapsed / max(sum(iters), 1)
+            whole["wall_us_per_iteration_timed_steps"] = round(wall_us, 2)
+            if roof is None:
+                roof = {}
+            roof["whole_iteration"] = whole
 
+    import oracle
+    oracle.build(force=False)
+    error = run_error(molt, synth, oracle, w, n) if not args.no_error else None
+    sweep = run_sweep(molt, n, w["L"], w["M"]) if not args.no_sweep else None
+    small = run_small(args, molt, synth, oracle) if not args.no_small else None
     batched = run_batched(args, molt, synth) if args.batch_steps > 0 else None
     served = run_served(args, molt, synth) if args.serve_count > 0 else None
 
     cpu = None
     if not args.no_cpu_baseline:
-        import oracle
-        oracle.build(force=False)
         og = oracle.Grid(nx=n, ny=n, x0=0.0, x1=w["L"], y0=0.0, y1=w["L"], bc=oracle.BC_PERIODIC, M=w["M"])
-        po = oracle.Params(eps=w["eps"], dt=w["dt"], stepper=oracle.BE, fixed_iters=args.cpu_iters,
-                           init=oracle.INIT_LINEAR if init == molt.MOLT_INIT_LINEAR else oracle.INIT_PREV)
-        tc = time.perf_counter()
-        oracle.step(og, po, u0, None)
-        tcpu = time.perf_counter() - tc
-        cpu_pts = pts * (4 + 7 * args.cpu_iters)
-        cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-        cpu = {"value": round(cpu_pts / tcpu / 1e9, 4), "unit": "Gpt-sweeps/s", "cores": cores, "kind": "oracle",
-               "sample": f"first BE step of the {n}^2 workload with {args.cpu_iters} fixed-point iterations "
-                         f"(4 + 7 per iteration point-sweeps per point), FP64 oracle, {tcpu:.1f} s"}
+        model, ncpu = cpu_info()
+        legs = {}
+        for th, its in ((host_threads(), args.cpu_iters), (1, max(2, args.cpu_iters // 8))):
+            used = oracle.set_threads(th)
+            po = oracle.Params(eps=w["eps"], dt=w["dt"], stepper=oracle.BE, fixed_iters=its,
+                               init=oracle.INIT_LINEAR if init == molt.MOLT_INIT_LINEAR else oracle.INIT_PREV)
+            tc = time.perf_counter()
+            oracle.step(og, po, u0, None)
+            tcpu = time.perf_counter() - tc
+            legs[used] = (pts * (4 + 7 * its) / tcpu / 1e9, its, tcpu)
+        oracle.set_threads(host_threads())
+        allc = max(legs)
+        v, its, tcpu = legs[allc]
+        v1, its1, t1c = legs[1]
+        cpu = {"value": round(v, 4), "unit": "Gpt-sweeps/s", "cores": allc, "kind": "oracle",
+               "sample": f"first BE step of the {n}^2 workload with {its} fixed-point iterations "
+                         f"(4 + 7 per iteration point-sweeps per point), FP64 oracle, {tcpu:.1f} s on {allc} threads",
+               "single_core": {"value": round(v1, 4), "iterations": its1, "seconds": round(t1c, 1)},
+               "cpu_model": model, "logical_cpus": ncpu}
 
     out = {
         "metric": "2D CH Gpt-sweeps/s (% HBM peak) + steps/s vs plain path; served p50/p99",
@@ -466,10 +734,19 @@ def main():
         "gpt_sweeps_nominal_8_per_iter": round(nominal / elapsed / 1e9, 3),
         "roofline": roof,
         "cpu_baseline": cpu,
+        "error": error,
+        "sweep": sweep,
+        "ch1d": small["ch1d"] if small else None,
+        "ch2d_neumann": small["ch2d_neumann"] if small else None,
         "batched": batched,
         "served": served,
         "kernels": kernels,
     }
+    # leave nothing behind: device memory released and the stream drained
+    # before the line is printed
+    del u, up, work
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
     print(json.dumps(out), flush=True)
 
 

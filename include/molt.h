@@ -340,14 +340,15 @@ int32_t molt_autotune(int32_t precision, int32_t max_n, void* d_work, size_t wor
 /*
  * Kernel timing (not part of the method): HIP events recorded around every
  * kernel the library launches, on the launch stream, accumulated per kind.
- * kind = family*8 + program; family 0 x-pass, 1 y-pass totals, 2 y-pass
- * combine, 3 y-pass final, 4 pointwise; program 0 sweep, 1 rhs sweep, 2-5 the
- * four fixed-point passes P1-P4.  molt_profile(1) enables and resets,
+ * kind = family*8 + program, plus 48 for FP64 launches (an FP32 step runs its
+ * R sweeps and first iteration in FP64); family 0 x-pass, 1 y-pass totals,
+ * 2 y-pass combine, 3 y-pass final, 4 pointwise, 5 other; program 0 sweep,
+ * 1 rhs sweep, 2-5 the four fixed-point passes P1-P4.  molt_profile(1) enables and resets,
  * molt_profile(0) disables; molt_profile_read fills up to max_entries kinds
  * that ran and returns how many.  molt_profile_only(kind) restricts the timing
  * to one kind (two events per launch of it, none elsewhere: the events cost
  * the stream a few microseconds each), molt_profile_only(-1) times every kind
- * again; MOLT_EINVAL for a kind outside -1..47.  Process-wide; use from one
+ * again; MOLT_EINVAL for a kind outside -1..95.  Process-wide; use from one
  * thread.
  */
 typedef struct {

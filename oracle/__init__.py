@@ -251,6 +251,15 @@ def solve(grid: Grid, params: Params, u: np.ndarray, nsteps: int):
     return uu, [_info(infos[i]) for i in range(nsteps)]
 
 
+def set_threads(n: int) -> int:
+    """Threads of the oracle's OpenMP loops over lines (for timing it on one
+    core or on all cores); returns the count now in effect."""
+    _load()
+    gomp = ctypes.CDLL("libgomp.so.1")
+    gomp.omp_set_num_threads(int(n))
+    return int(gomp.omp_get_max_threads())
+
+
 def mass(grid: Grid, u: np.ndarray) -> float:
     lib = _load()
     uu = np.ascontiguousarray(u, dtype=np.float64)

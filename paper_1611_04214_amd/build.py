@@ -51,9 +51,15 @@ def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
-    os.replace(tmp, out)
     for o in objs:
         os.remove(o)
+    # every symbol of the library's own namespace must be defined in it
+    und = subprocess.run(["nm", "-D", "--undefined-only", tmp], capture_output=True, text=True).stdout
+    missing = [ln.split()[-1] for ln in und.splitlines() if "_ZN4molt" in ln or " molt_" in ln]
+    if missing:
+        os.remove(tmp)
+        raise RuntimeError(f"libmolt.so would leave its own symbols undefined: {missing}")
+    os.replace(tmp, out)
     return out
 
 

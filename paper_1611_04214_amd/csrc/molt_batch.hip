@@ -32,7 +32,7 @@ namespace molt {
 // later iterations in the FP32 kernels; both are launched every tick and each
 // leaves the other's slots alone.
 __device__ __forceinline__ bool slot_fp64_phase(const SlotDesc& d, const SlotCtl& cc) {
-  return cc.phase == PH_R || (cc.phase == PH_IT && d.st->iters == 0);
+  return cc.phase == PH_R || (cc.phase == PH_IT && d.st->iters % kRestartEvery == 0);
 }
 template <typename T>
 __device__ __forceinline__ bool slot_mine(const SlotDesc& d, const SlotCtl& cc) {
@@ -40,21 +40,32 @@ __device__ __forceinline__ bool slot_mine(const SlotDesc& d, const SlotCtl& cc) 
   return slot_fp64_phase(d, cc) == (sizeof(T) == 8);
 }
 
+// 0: full form (the first iteration, and a hybrid slot's FP64 restarts), 1: increment form
+template <typename T>
+__device__ __forceinline__ int slot_mode(const SlotDesc& d) {
+  return (d.hybrid && sizeof(T) == 8) || d.st->iters == 0 ? 0 : 1;
+}
+
 // the fields and line-block shapes a slot uses in the kernels of type T
 struct SlotView {
   void* const* F;
   void* tot;
   void* jln;
-  const void* u;     // u^n as the rhs and the full form read it
+  const void* u;     // u^n as the rhs reads it
   const void* hist;  // u^{n-1}
+  const void* base;  // the iterate is base + W
   int32_t ynth, ynseg, yk, tlx, vecx, xblocks;
 };
 template <typename T>
 __device__ __forceinline__ SlotView slot_view(const SlotDesc& d) {
-  if (sizeof(T) == 8 && d.hybrid)
-    return SlotView{d.fld64, d.tot64, d.jln64, d.u64, d.hist64, d.ynth64, d.ynseg64, d.yk64, d.tlx64, d.vecx64,
-                    d.xblocks64};
-  return SlotView{d.fld, d.tot, d.jln, d.u, d.fld[F_HIST], d.ynth, d.ynseg, d.yk, d.tlx, d.vecx, d.xblocks};
+  const bool lin = d.init == MOLT_INIT_LINEAR;
+  if (sizeof(T) == 8 && d.hybrid)  // first iteration from R or u^n, restarts from the iterate in F_HIST
+    return SlotView{d.fld64, d.tot64, d.jln64, d.u64, d.hist64,
+                    d.st->iters == 0 ? (lin ? d.fld64[F_R] : d.u64) : d.fld64[F_HIST],
+                    d.ynth64, d.ynseg64, d.yk64, d.tlx64, d.vecx64, d.xblocks64};
+  // (a hybrid slot's FP32 iterations run from the re-based first iterate in F_R)
+  return SlotView{d.fld, d.tot, d.jln, d.u, d.fld[F_HIST], (lin || d.hybrid) ? d.fld[F_R] : d.u,
+                  d.ynth, d.ynseg, d.yk, d.tlx, d.vecx, d.xblocks};
 }
 
 // arguments of pass `pass` (1..4) of a slot in phase ph (the same fields as
@@ -92,7 +103,7 @@ __device__ __forceinline__ PassArgs slot_args(const SlotDesc& d, const SlotView&
     a.kappa = d.kappa[var];
     a.mode = mode;
     a.bdf2 = 0;
-    const void* base = d.init == MOLT_INIT_LINEAR ? F[F_R] : v.u;
+    const void* base = v.base;
     const bool vch = d.model == MOLT_MODEL_VCH;
     if (pass == 0) {  // vector model: the pointwise reaction pass
       a.in[0] = base;
@@ -157,7 +168,7 @@ __global__ void MOLT_PASS_ATTR ypass_batch_kernel(const SlotDesc* __restrict__ s
   } else {
     DevState* st = d.st;
     if (st->done) return;
-    const PassArgs a = slot_args(d, v, PH_IT, PASS, var, st->iters > 0 ? 1 : 0);
+    const PassArgs a = slot_args(d, v, PH_IT, PASS, var, slot_mode<T>(d));
     const LineCoef& c = d.cy[var][PASS == 1 ? 0 : 1];
     if constexpr (PASS == 1) {
       if (d.model == MOLT_MODEL_VCH) {
@@ -221,7 +232,7 @@ __global__ void MOLT_PASS_ATTR xpass_batch_kernel(const SlotDesc* __restrict__ s
   } else {
     DevState* st = d.st;
     if (st->done) return;
-    const PassArgs a = slot_args(d, v, PH_IT, PASS, var, st->iters > 0 ? 1 : 0);
+    const PassArgs a = slot_args(d, v, PH_IT, PASS, var, slot_mode<T>(d));
     if constexpr (PASS == 2) {
       if (d.model == MOLT_MODEL_VCH) {
         xpass_body<T, PROG_P2V, K, M, PER>(d.cx[var][0], a, st, nlines, v.tlx, nullptr, v.vecx, e.blk, smem);
@@ -242,8 +253,8 @@ __global__ void __launch_bounds__(256) close_batch_kernel(const SlotDesc* __rest
   const int slot = slots[blockIdx.x].slot;
   const SlotDesc& d = sd[slot];
   if (ctl[slot].phase != PH_IT) return;
-  // (a hybrid slot's first iteration ran the FP64 x-pass and its blocks)
-  residual_close_body(d.rpart, (d.hybrid && d.st->iters == 0) ? d.xblocks64 : d.xblocks, d.st);
+  // (a hybrid slot's FP64 iterations ran the FP64 x-pass and its blocks)
+  residual_close_body(d.rpart, (d.hybrid && d.st->iters % kRestartEvery == 0) ? d.xblocks64 : d.xblocks, d.st);
 }
 
 // step finish of converged slots: u^{n-1} <- u^n (the BDF2 history), u^{n+1} = base + W
@@ -258,17 +269,7 @@ __global__ void __launch_bounds__(256) finish_batch_kernel(const SlotDesc* __res
   T* u = (T*)d.u;
   T* h = (T*)d.fld[F_HIST];
   const T* W = (const T*)d.fld[F_W];
-  if (sizeof(T) == 4 && d.hybrid) {  // u^{n+1} from the FP64 base, rounded once
-    const double* base = (const double*)(d.init == MOLT_INIT_LINEAR ? d.fld64[F_R] : d.u64);
-    for (size_t i = (size_t)e.blk * blockDim.x + threadIdx.x; i < n; i += (size_t)d.dblocks * blockDim.x) {
-      const T uo = u[i];
-      const double b = base[i];
-      h[i] = uo;
-      u[i] = (T)(b + (double)W[i]);
-    }
-    return;
-  }
-  const T* base = d.init == MOLT_INIT_LINEAR ? (const T*)d.fld[F_R] : u;
+  const T* base = (d.init == MOLT_INIT_LINEAR || d.hybrid) ? (const T*)d.fld[F_R] : u;
   for (size_t i = (size_t)e.blk * blockDim.x + threadIdx.x; i < n; i += (size_t)d.dblocks * blockDim.x) {
     const T uo = u[i];
     const T b = base[i];
@@ -298,20 +299,35 @@ __global__ void __launch_bounds__(256) widen_batch_kernel(const SlotDesc* __rest
   }
 }
 
-// hybrid slots after their FP64 first iteration: the increment and running
-// sum (and R, the base of the iterate) narrowed for the FP32 iterations
-__global__ void __launch_bounds__(256) narrow_batch_kernel(const SlotDesc* __restrict__ sd,
+// hybrid slots after an iteration (the tail of a tick, after the close): after
+// an FP64 iteration, its iterate re-based into the FP32 base (F_R) and running
+// sum and the increment narrowed; before an FP64 restart, the iterate base +
+// W in FP64 (F_HIST of the shadow).  The single-problem driver's schedule.
+__global__ void __launch_bounds__(256) rebase_batch_kernel(const SlotDesc* __restrict__ sd,
                                                            const SlotCtl* __restrict__ ctl,
                                                            const BlkMap* __restrict__ map) {
   const BlkMap e = map[blockIdx.x];
   const SlotDesc& d = sd[e.slot];
-  if (!d.hybrid || ctl[e.slot].phase != PH_IT || d.st->iters != 1) return;
+  if (!d.hybrid || ctl[e.slot].phase != PH_IT) return;
+  const int it = d.st->iters;
+  if (it == 0) return;
+  const bool after64 = (it - 1) % kRestartEvery == 0;
+  if (!after64 && (it % kRestartEvery != 0 || d.st->done)) return;
   const size_t n = (size_t)d.nx * (size_t)d.ny * (size_t)d.ncomp;
-  const bool lin = d.init == MOLT_INIT_LINEAR;
+  float* base = (float*)d.fld[F_R];
+  float* W = (float*)d.fld[F_W];
+  const double* base64 =
+      (const double*)(it == 1 ? (d.init == MOLT_INIT_LINEAR ? d.fld64[F_R] : d.u64) : d.fld64[F_HIST]);
   for (size_t i = (size_t)e.blk * blockDim.x + threadIdx.x; i < n; i += (size_t)d.dblocks * blockDim.x) {
-    ((float*)d.fld[F_DL])[i] = (float)((const double*)d.fld64[F_DL])[i];
-    ((float*)d.fld[F_W])[i] = (float)((const double*)d.fld64[F_W])[i];
-    if (lin) ((float*)d.fld[F_R])[i] = (float)((const double*)d.fld64[F_R])[i];
+    if (after64) {
+      const double v = base64[i] + ((const double*)d.fld64[F_W])[i];
+      const float b = (float)v;
+      base[i] = b;
+      W[i] = (float)(v - (double)b);
+      ((float*)d.fld[F_DL])[i] = (float)((const double*)d.fld64[F_DL])[i];
+    } else {
+      ((double*)d.fld64[F_HIST])[i] = (double)base[i] + (double)W[i];
+    }
   }
 }
 #endif
@@ -338,7 +354,7 @@ __global__ void __launch_bounds__(256) react_batch_kernel(const SlotDesc* __rest
   const SlotDesc& d = sd[e.slot];
   const SlotCtl cc = ctl[e.slot];
   if (d.model != MOLT_MODEL_VCH || cc.phase != PH_IT || d.st->done || !slot_mine<T>(d, cc)) return;
-  const PassArgs a = slot_args(d, slot_view<T>(d), PH_IT, 0, cc.var, d.st->iters > 0 ? 1 : 0);
+  const PassArgs a = slot_args(d, slot_view<T>(d), PH_IT, 0, cc.var, slot_mode<T>(d));
   vch_react_body<T>(a, (size_t)d.nx * (size_t)d.ny, (size_t)e.blk * blockDim.x + threadIdx.x,
                     (size_t)d.dblocks * blockDim.x);
 }
@@ -479,9 +495,9 @@ hipError_t MOLT_BFN(launch_batch_y)(int K, int M, bool per, int pass, bool fin, 
                                    const SlotCtl* ctl, const BlkMap* map, int nblk, hipStream_t s) {
   if (nblk <= 0) return hipSuccess;
   const int kind = (fin ? KF_YFIN : KF_YTOT) * 8 + (pass == 1 ? PROG_P1 : PROG_P3);
-  if (g_prof_on) prof_begin(kind, s);
+  if (g_prof_on) prof_begin(prof_kind<MOLT_BT>(kind), s);
   const hipError_t e = ybatch_t<MOLT_BT>(K, M, per, pass, fin, sd, ctl, map, nblk, s);
-  if (g_prof_on) prof_end(kind, s);
+  if (g_prof_on) prof_end(prof_kind<MOLT_BT>(kind), s);
   return e;
 }
 
@@ -489,9 +505,9 @@ hipError_t MOLT_BFN(launch_batch_comb)(int pass, const SlotDesc* sd, const SlotC
                                       int nblk, hipStream_t s) {
   if (nblk <= 0) return hipSuccess;
   const int kind = KF_YCOMB * 8 + (pass == 1 ? PROG_P1 : PROG_P3);
-  if (g_prof_on) prof_begin(kind, s);
+  if (g_prof_on) prof_begin(prof_kind<MOLT_BT>(kind), s);
   hipLaunchKernelGGL((ycomb_batch_kernel<MOLT_BT>), dim3(nblk), dim3(64, kCombWaves), 0, s, sd, ctl, map, pass);
-  if (g_prof_on) prof_end(kind, s);
+  if (g_prof_on) prof_end(prof_kind<MOLT_BT>(kind), s);
   return hipGetLastError();
 }
 
@@ -537,9 +553,9 @@ hipError_t MOLT_BFN(launch_batch_x)(int K, int M, bool per, int pass, const Slot
                                    const BlkMap* map, int nblk, hipStream_t s) {
   if (nblk <= 0) return hipSuccess;
   const int kind = KF_XPASS * 8 + (pass == 2 ? PROG_P2 : PROG_P4);
-  if (g_prof_on) prof_begin(kind, s);
+  if (g_prof_on) prof_begin(prof_kind<MOLT_BT>(kind), s);
   const hipError_t e = xbatch_t<MOLT_BT>(K, M, per, pass, sd, ctl, map, nblk, s);
-  if (g_prof_on) prof_end(kind, s);
+  if (g_prof_on) prof_end(prof_kind<MOLT_BT>(kind), s);
   return e;
 }
 
@@ -547,20 +563,20 @@ hipError_t MOLT_BFN(launch_batch_x)(int K, int M, bool per, int pass, const Slot
 hipError_t MOLT_BFN(launch_batch_tail)(const SlotDesc* sd, SlotCtl* ctl, const BlkMap* slots, int nslots,
                                       const BlkMap* pmap, int npblk, bool close_only, bool hybrid, hipStream_t s) {
   if (nslots <= 0) return hipSuccess;
-  if (g_prof_on) prof_begin(KF_OTHER * 8 + 1, s);
+  if (g_prof_on) prof_begin(prof_kind<MOLT_BT>(KF_OTHER * 8 + 1), s);
   hipLaunchKernelGGL((close_batch_kernel<MOLT_BT>), dim3(nslots), dim3(256), 0, s, sd, (const SlotCtl*)ctl, slots);
 #ifndef MOLT_BATCH_F64
   if (hybrid)
-    hipLaunchKernelGGL(narrow_batch_kernel, dim3(npblk), dim3(256), 0, s, sd, (const SlotCtl*)ctl, pmap);
+    hipLaunchKernelGGL(rebase_batch_kernel, dim3(npblk), dim3(256), 0, s, sd, (const SlotCtl*)ctl, pmap);
 #endif
   if (close_only) {
-    if (g_prof_on) prof_end(KF_OTHER * 8 + 1, s);
+    if (g_prof_on) prof_end(prof_kind<MOLT_BT>(KF_OTHER * 8 + 1), s);
     return hipGetLastError();
   }
   hipLaunchKernelGGL((finish_batch_kernel<MOLT_BT>), dim3(npblk), dim3(256), 0, s, sd, (const SlotCtl*)ctl, pmap);
   hipLaunchKernelGGL((diag_batch_kernel<MOLT_BT>), dim3(npblk), dim3(256), 0, s, sd, (const SlotCtl*)ctl, pmap);
   hipLaunchKernelGGL((tick_end_batch_kernel<MOLT_BT>), dim3(nslots), dim3(256), 0, s, sd, ctl, slots);
-  if (g_prof_on) prof_end(KF_OTHER * 8 + 1, s);
+  if (g_prof_on) prof_end(prof_kind<MOLT_BT>(KF_OTHER * 8 + 1), s);
   return hipGetLastError();
 }
 
@@ -575,9 +591,9 @@ hipError_t launch_batch_widen(const SlotDesc* sd, const SlotCtl* ctl, const BlkM
 hipError_t MOLT_BFN(launch_batch_react)(const SlotDesc* sd, const SlotCtl* ctl, const BlkMap* pmap, int npblk,
                                        hipStream_t s) {
   if (npblk <= 0) return hipSuccess;
-  if (g_prof_on) prof_begin(KF_POINTWISE * 8 + PROG_P1V, s);
+  if (g_prof_on) prof_begin(prof_kind<MOLT_BT>(KF_POINTWISE * 8 + PROG_P1V), s);
   hipLaunchKernelGGL((react_batch_kernel<MOLT_BT>), dim3(npblk), dim3(256), 0, s, sd, ctl, pmap);
-  if (g_prof_on) prof_end(KF_POINTWISE * 8 + PROG_P1V, s);
+  if (g_prof_on) prof_end(prof_kind<MOLT_BT>(KF_POINTWISE * 8 + PROG_P1V), s);
   return hipGetLastError();
 }
 

@@ -78,8 +78,11 @@ size_t yfused_items(int n, int nx, int batch);
 size_t yfused_rec_words(int n, int nx, int batch);
 hipError_t launch_zero_ints(int* p, int n, hipStream_t s);
 hipError_t launch_widen(void* dst64, const void* src32, size_t n, hipStream_t s);
-hipError_t launch_narrow(void* dst32, const void* src64, size_t n, hipStream_t s);
-hipError_t launch_finalize_mixed(void* u32, const void* base64, const void* W32, size_t n, hipStream_t s);
+hipError_t launch_rebase_mixed(void* base32, void* W32, void* DL32, const void* base64, const void* W64,
+                               const void* DL64, const DevState* st, int expect, size_t n, hipStream_t s);
+hipError_t launch_iterate64(void* v64, const void* base32, const void* W32, const DevState* st, size_t n,
+                            hipStream_t s);
+
 hipError_t launch_state_init(DevState* st, double tol, int max_iter, int fixed, hipStream_t s);
 size_t ypass_tot_elems(int prec, int n, int nx, int batch);
 int diag_blocks(size_t n);
@@ -623,7 +626,8 @@ static int32_t step_impl(const molt_grid* g, const molt_ch_params* p, void* d_u,
     base = p->init == MOLT_INIT_LINEAR ? F[F_R] : d_u;
   } else {
     // FP64 shadow: the inputs widened, R and the first iteration in FP64,
-    // then the increment and running sum narrowed for the FP32 iterations
+    // then the iterate re-based and the increment narrowed for the FP32
+    // iterations
     void* u64 = w + L.in64[0];
     void* p64 = w + L.in64[1];
     void* q64 = w + L.in64[2];
@@ -637,10 +641,10 @@ static int32_t step_impl(const molt_grid* g, const molt_ch_params* p, void* d_u,
     base64 = p->init == MOLT_INIT_LINEAR ? F64[F_R] : u64;
     MOLT_RC(enqueue_iteration(MOLT_F64, G, sp, ush, 0, base64, F64, w + L.tot64, w + L.jln64, st, rpart, nullptr,
                               s));
-    HIPCHK(launch_narrow(F[F_DL], F64[F_DL], nel, s));
-    HIPCHK(launch_narrow(F[F_W], F64[F_W], nel, s));
-    if (p->init == MOLT_INIT_LINEAR) HIPCHK(launch_narrow(F[F_R], F64[F_R], nel, s));
-    base = p->init == MOLT_INIT_LINEAR ? F[F_R] : d_u;
+    // the FP32 iterations' base is the first iterate rounded to FP32, their
+    // running sum starts at its rounding error
+    HIPCHK(launch_rebase_mixed(F[F_R], F[F_W], F[F_DL], base64, F64[F_W], F64[F_DL], st, 1, nel, s));
+    base = F[F_R];
     it = 1;
   }
   // history: u^{n-1} -> u_prev2, u^n -> u_prev (after the rhs has consumed them)
@@ -656,18 +660,25 @@ static int32_t step_impl(const molt_grid* g, const molt_ch_params* p, void* d_u,
   memset(&hst, 0, sizeof(hst));
   for (;;) {
     const int nb = batch < cap - it ? batch : cap - it;
-    for (int b = 0; b < nb; ++b, ++it)
+    for (int b = 0; b < nb; ++b, ++it) {
+      if (L.hybrid && it % kRestartEvery == 0) {
+        // FP64 restart: the full form from the iterate, then re-based
+        void* v64 = F64[F_HIST];
+        HIPCHK(launch_iterate64(v64, F[F_R], F[F_W], st, nel, s));
+        MOLT_RC(enqueue_iteration(MOLT_F64, G, sp, ush, 0, v64, F64, w + L.tot64, w + L.jln64, st, rpart, nullptr,
+                                  s));
+        HIPCHK(launch_rebase_mixed(F[F_R], F[F_W], F[F_DL], v64, F64[F_W], F64[F_DL], st, it + 1, nel, s));
+        continue;
+      }
       MOLT_RC(enqueue_iteration(prec, G, sp, ush, it == 0 ? 0 : 1, base, F, tot, jln, st, rpart, fzp, s));
+    }
     HIPCHK(hipMemcpyAsync(&hst, st, sizeof(DevState), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     if (g_prof_on) prof_drain();
     if (hst.done || it >= cap) break;
     batch = batch < 32 ? batch * 2 : 32;
   }
-  if (L.hybrid)
-    HIPCHK(launch_finalize_mixed(d_u, base64, F[F_W], nel, s));
-  else
-    HIPCHK(launch_finalize(prec, d_u, base, F[F_W], nel, s));
+  HIPCHK(launch_finalize(prec, d_u, base, F[F_W], nel, s));
   if (vform) {
     HIPCHK(launch_addc(prec, d_u, ush[0], ush[1], n, nc, s));
     if (d_u_prev) HIPCHK(launch_addc(prec, d_u_prev, ush[0], ush[1], n, nc, s));

@@ -86,6 +86,16 @@ struct YFused {
 // --------------------------------------------------------------------------
 enum SlotPhase { PH_R = 0, PH_IT = 1, PH_IDLE = 2 };
 
+// An FP32 step runs iteration k in FP64 (full form, from the iterate) when
+// k % kRestartEvery == 0, in FP32 (increment form) otherwise; the same
+// schedule in the single-problem and batched paths.  FP32 rounding of the
+// intermediates injects noise relative to the current increments; the part of
+// it that lands in nearly neutral modes of the iteration (high in both
+// directions, or localized at Neumann ends) is not damped, and after large
+// early increments it can stay above the tolerance.  A full-form FP64
+// iteration measures the true increment and restarts the recurrence from it.
+constexpr int kRestartEvery = 64;
+
 // workspace fields of one problem
 // (vector model: every field holds both components; F_E, F_LIN hold the
 // reaction and linear parts of the iterate, empty for Cahn-Hilliard; BDF3:
@@ -140,7 +150,13 @@ struct BlkMap {
 // Optional per-kernel timing with HIP events on the launch stream (off unless
 // molt_profile(1) was called).  kind = family * 8 + program.
 enum KernelFamily { KF_XPASS = 0, KF_YTOT = 1, KF_YCOMB = 2, KF_YFIN = 3, KF_POINTWISE = 4, KF_OTHER = 5 };
-constexpr int kProfKinds = 48;
+// FP64 launches are counted apart: kind + kProfF64
+constexpr int kProfF64 = 48;
+constexpr int kProfKinds = 96;
+template <typename T>
+constexpr int prof_kind(int kind) {
+  return kind + (sizeof(T) == 8 ? kProfF64 : 0);
+}
 void prof_begin(int kind, hipStream_t s);
 void prof_end(int kind, hipStream_t s);
 extern bool g_prof_on;

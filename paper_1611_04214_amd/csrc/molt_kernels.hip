@@ -439,20 +439,40 @@ hipError_t launch_zero_ints(int* p, int n, hipStream_t s) {
   return hipGetLastError();
 }
 
-// FP32 <-> FP64 copies of the FP64 shadow of an FP32 step, and its final
-// u^{n+1} = base + W formed in FP64 and rounded once
+// The FP64 shadow of an FP32 step: its inputs widened, and the iterate after
+// the FP64 first iteration re-based for the FP32 increment iterations.
 __global__ void __launch_bounds__(256) widen_kernel(double* dst, const float* src, size_t n) {
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
     dst[i] = (double)src[i];
 }
-__global__ void __launch_bounds__(256) narrow_kernel(float* dst, const double* src, size_t n) {
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-    dst[i] = (float)src[i];
+
+// After an FP64 (full-form) iteration that ran as iteration expect-1: the new
+// iterate v = base64 + W64 split into base32 = fl32(v) and W32 = fl32(v -
+// base32), and the increment narrowed, so that the FP32 increment iterations
+// add their increments to a running sum that starts at ~ulp(v).  Skipped when
+// that iteration did not run (the step had converged before it).
+__global__ void __launch_bounds__(256) rebase_mixed_kernel(float* base32, float* W32, float* DL32, const double* base64,
+                                                           const double* W64, const double* DL64, const DevState* st,
+                                                           int expect, size_t n) {
+  if (st->iters != expect) return;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const double v = base64[i] + W64[i];
+    const float b = (float)v;
+    base32[i] = b;
+    W32[i] = (float)(v - (double)b);
+    DL32[i] = (float)DL64[i];
+  }
 }
-__global__ void __launch_bounds__(256) finalize_mixed_kernel(float* u, const double* base, const float* W, size_t n) {
+
+// Before an FP64 restart iteration: the iterate base32 + W32 in FP64 (unless
+// the step has converged)
+__global__ void __launch_bounds__(256) iterate64_kernel(double* v64, const float* base32, const float* W32,
+                                                        const DevState* st, size_t n) {
+  if (st->done) return;
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-    u[i] = (float)(base[i] + (double)W[i]);
+    v64[i] = (double)base32[i] + (double)W32[i];
 }
+
 static dim3 grid_elems(size_t n) {
   size_t b = (n + 255) / 256;
   return dim3((unsigned)(b > 8192 ? 8192 : (b < 1 ? 1 : b)));
@@ -461,13 +481,16 @@ hipError_t launch_widen(void* dst64, const void* src32, size_t n, hipStream_t s)
   hipLaunchKernelGGL(widen_kernel, grid_elems(n), dim3(256), 0, s, (double*)dst64, (const float*)src32, n);
   return hipGetLastError();
 }
-hipError_t launch_narrow(void* dst32, const void* src64, size_t n, hipStream_t s) {
-  hipLaunchKernelGGL(narrow_kernel, grid_elems(n), dim3(256), 0, s, (float*)dst32, (const double*)src64, n);
+hipError_t launch_rebase_mixed(void* base32, void* W32, void* DL32, const void* base64, const void* W64,
+                               const void* DL64, const DevState* st, int expect, size_t n, hipStream_t s) {
+  hipLaunchKernelGGL(rebase_mixed_kernel, grid_elems(n), dim3(256), 0, s, (float*)base32, (float*)W32, (float*)DL32,
+                     (const double*)base64, (const double*)W64, (const double*)DL64, st, expect, n);
   return hipGetLastError();
 }
-hipError_t launch_finalize_mixed(void* u32, const void* base64, const void* W32, size_t n, hipStream_t s) {
-  hipLaunchKernelGGL(finalize_mixed_kernel, grid_elems(n), dim3(256), 0, s, (float*)u32, (const double*)base64,
-                     (const float*)W32, n);
+hipError_t launch_iterate64(void* v64, const void* base32, const void* W32, const DevState* st, size_t n,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(iterate64_kernel, grid_elems(n), dim3(256), 0, s, (double*)v64, (const float*)base32,
+                     (const float*)W32, st, n);
   return hipGetLastError();
 }
 
@@ -513,7 +536,7 @@ static hipError_t xpass_k(const LineCoef& c, const PassArgs& a, DevState* st, in
   const int BS = TL > 256 ? 512 : 256;  // rows of 512 threads get a block of their own
   const int lpb = BS / TL;
   dim3 grid((nlines + lpb - 1) / lpb);
-  if (g_prof_on) prof_begin(KF_XPASS * 8 + PI, s);
+  if (g_prof_on) prof_begin(prof_kind<MOLT_KT>(KF_XPASS * 8 + PI), s);
   const bool per = c.bc == MOLT_BC_PERIODIC;
 #define MOLT_XL(MM, PP)                                                                                            \
   do {                                                                                                            \
@@ -531,13 +554,13 @@ static hipError_t xpass_k(const LineCoef& c, const PassArgs& a, DevState* st, in
     default: return hipErrorInvalidValue;
   }
 #undef MOLT_XL
-  if (g_prof_on) prof_end(KF_XPASS * 8 + PI, s);
+  if (g_prof_on) prof_end(prof_kind<MOLT_KT>(KF_XPASS * 8 + PI), s);
   if (rpart != nullptr) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if (g_prof_on) prof_begin(KF_OTHER * 8, s);
+    if (g_prof_on) prof_begin(prof_kind<MOLT_KT>(KF_OTHER * 8), s);
     hipLaunchKernelGGL((residual_close_kernel<T>), dim3(1), dim3(1024), 0, s, (const double*)rpart, (int)grid.x, st);
-    if (g_prof_on) prof_end(KF_OTHER * 8, s);
+    if (g_prof_on) prof_end(prof_kind<MOLT_KT>(KF_OTHER * 8), s);
   }
   return hipGetLastError();
 }
@@ -581,16 +604,16 @@ static hipError_t ypass_km(const LineCoef& c, const PassArgs& a, DevState* st, i
   const size_t fstride = (size_t)c.n * nx;
   dim3 blk(64, kRG);
   dim3 grid((nx + 63) / 64, nseg, batch);
-  if (g_prof_on) prof_begin(KF_YTOT * 8 + PI, s);
+  if (g_prof_on) prof_begin(prof_kind<MOLT_KT>(KF_YTOT * 8 + PI), s);
   hipLaunchKernelGGL((ytot_kernel<T, PI, K, M, PER>), grid, blk, 0, s, c, a, st, nx, nth, nseg, fstride, tot, jln);
-  if (g_prof_on) prof_end(KF_YTOT * 8 + PI, s);
+  if (g_prof_on) prof_end(prof_kind<MOLT_KT>(KF_YTOT * 8 + PI), s);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   // the combine runs over segments of kRG*K rows
   const int ct = (nseg + kCombWaves - 1) / kCombWaves;
   const dim3 cgrid((nx + 63) / 64, P::F, batch), cblk(64, kCombWaves);
   const int S = kRG * K;
-  if (g_prof_on) prof_begin(KF_YCOMB * 8 + PI, s);
+  if (g_prof_on) prof_begin(prof_kind<MOLT_KT>(KF_YCOMB * 8 + PI), s);
   if (ct <= 8)
     hipLaunchKernelGGL((ycomb_kernel<T, 8>), cgrid, cblk, 0, s, c, st, nx, nseg, S, P::F, tot, (const T*)jln);
   else if (ct <= 16)
@@ -599,13 +622,13 @@ static hipError_t ypass_km(const LineCoef& c, const PassArgs& a, DevState* st, i
     hipLaunchKernelGGL((ycomb_kernel<T, 32>), cgrid, cblk, 0, s, c, st, nx, nseg, S, P::F, tot, (const T*)jln);
   else
     return hipErrorInvalidValue;
-  if (g_prof_on) prof_end(KF_YCOMB * 8 + PI, s);
+  if (g_prof_on) prof_end(prof_kind<MOLT_KT>(KF_YCOMB * 8 + PI), s);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if (g_prof_on) prof_begin(KF_YFIN * 8 + PI, s);
+  if (g_prof_on) prof_begin(prof_kind<MOLT_KT>(KF_YFIN * 8 + PI), s);
   hipLaunchKernelGGL((yfin_kernel<T, PI, K, M, PER>), grid, blk, 0, s, c, a, st, nx, nth, nseg, fstride,
                      (const T*)tot);
-  if (g_prof_on) prof_end(KF_YFIN * 8 + PI, s);
+  if (g_prof_on) prof_end(prof_kind<MOLT_KT>(KF_YFIN * 8 + PI), s);
   return hipGetLastError();
 }
 
@@ -643,10 +666,10 @@ static hipError_t yfused_km(const LineCoef& c, const PassArgs& a, DevState* st, 
   unsigned long long* rec = (unsigned long long*)fz.rec;
   long long spin = fz.spin_limit;
   void* args[] = {&cc, &aa, &stp, &nxv, &nthv, &Gv, &nsv, &niv, &fstride, &rec, &ep, &spin};
-  if (g_prof_on) prof_begin(KF_YFIN * 8 + PI, s);
+  if (g_prof_on) prof_begin(prof_kind<MOLT_KT>(KF_YFIN * 8 + PI), s);
   hipError_t e = hipLaunchCooperativeKernel((const void*)yfused_kernel<T, PI, K, M, true>, dim3(grid),
                                             dim3(64, kRGF), args, 0, s);
-  if (g_prof_on) prof_end(KF_YFIN * 8 + PI, s);
+  if (g_prof_on) prof_end(prof_kind<MOLT_KT>(KF_YFIN * 8 + PI), s);
   if (e == hipSuccess) *used = true;
   return e;
 }
@@ -713,12 +736,12 @@ static dim3 grid_1d(size_t n) {
 
 hipError_t MOLT_KFN(launch_pointwise)(int prog, const PassArgs& a, DevState* st, size_t nelem, hipStream_t s) {
   dim3 g = grid_1d(nelem);
-  if (g_prof_on) prof_begin(KF_POINTWISE * 8 + prog, s);
+  if (g_prof_on) prof_begin(prof_kind<MOLT_KT>(KF_POINTWISE * 8 + prog), s);
   if (prog == PROG_P1) hipLaunchKernelGGL((pointwise_kernel<MOLT_KT, PROG_P1>), g, dim3(256), 0, s, a, st, nelem);
   else if (prog == PROG_P3) hipLaunchKernelGGL((pointwise_kernel<MOLT_KT, PROG_P3>), g, dim3(256), 0, s, a, st, nelem);
   else if (prog == PROG_P1V) hipLaunchKernelGGL((pointwise_kernel<MOLT_KT, PROG_P1V>), g, dim3(256), 0, s, a, st, nelem);
   else return hipErrorInvalidValue;
-  if (g_prof_on) prof_end(KF_POINTWISE * 8 + prog, s);
+  if (g_prof_on) prof_end(prof_kind<MOLT_KT>(KF_POINTWISE * 8 + prog), s);
   return hipGetLastError();
 }
 
@@ -735,9 +758,9 @@ hipError_t MOLT_KFN(launch_finalize)(void* u, const void* base, const void* W, s
 
 hipError_t MOLT_KFN(launch_vch_react)(const PassArgs& a, DevState* st, size_t n, hipStream_t s) {
   dim3 g = grid_1d(n);
-  if (g_prof_on) prof_begin(KF_POINTWISE * 8 + PROG_P1V, s);
+  if (g_prof_on) prof_begin(prof_kind<MOLT_KT>(KF_POINTWISE * 8 + PROG_P1V), s);
   hipLaunchKernelGGL((vch_react_kernel<MOLT_KT>), g, dim3(256), 0, s, a, st, n);
-  if (g_prof_on) prof_end(KF_POINTWISE * 8 + PROG_P1V, s);
+  if (g_prof_on) prof_end(prof_kind<MOLT_KT>(KF_POINTWISE * 8 + PROG_P1V), s);
   return hipGetLastError();
 }
 

@@ -41,15 +41,22 @@ KERNEL_FAMILIES = ("xpass", "ytot", "ycomb", "yfin", "pointwise", "other")
 PROGRAMS = ("sweep", "rhs", "P1", "P2", "P3", "P4", "P1v", "P2v")
 
 
+#: kinds of FP64 launches are offset by this (their names start with "f64_")
+PROF_F64 = 48
+
+
 def kind_name(kind: int) -> str:
-    f, p = divmod(kind, 8)
-    return f"{KERNEL_FAMILIES[f]}_{PROGRAMS[p] if p < len(PROGRAMS) else p}"
+    f, p = divmod(kind % PROF_F64, 8)
+    return ("f64_" if kind >= PROF_F64 else "") + f"{KERNEL_FAMILIES[f]}_{PROGRAMS[p] if p < len(PROGRAMS) else p}"
 
 
 def kind_of(name: str) -> int:
     """Inverse of kind_name."""
+    off = 0
+    if name.startswith("f64_"):
+        off, name = PROF_F64, name[4:]
     fam, prog = name.split("_", 1)
-    return KERNEL_FAMILIES.index(fam) * 8 + PROGRAMS.index(prog)
+    return off + KERNEL_FAMILIES.index(fam) * 8 + PROGRAMS.index(prog)
 
 
 class molt_grid(ctypes.Structure):
@@ -250,6 +257,7 @@ def molt_sweep_workspace_bytes(grid: molt_grid, axis: int, precision: int, batch
     return load().molt_sweep_workspace_bytes(ctypes.byref(grid), axis, precision, batch)
 
 
+
 def ch_workspace_bytes(grid: molt_grid, params: molt_ch_params) -> int:
     return load().ch_workspace_bytes(ctypes.byref(grid), ctypes.byref(params))
 
@@ -361,7 +369,7 @@ def molt_profile_only(kind: int) -> int:
     return load().molt_profile_only(kind)
 
 
-def molt_profile_read(max_entries: int = 48) -> dict:
+def molt_profile_read(max_entries: int = 96) -> dict:
     """{kind name: (launches, total_ms)} of the kernels timed since molt_profile(1)."""
     buf = (molt_prof_entry * max_entries)()
     m = load().molt_profile_read(buf, max_entries)
