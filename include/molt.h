@@ -150,6 +150,32 @@ int32_t mol_t_helmholtz_sweep(const molt_grid* grid, int32_t axis, double alpha,
 size_t molt_sweep_workspace_bytes(const molt_grid* grid, int32_t axis, int32_t precision, int64_t batch);
 
 /*
+ * mol_t_helmholtz_sweep_noalloc -- mol_t_helmholtz_sweep without a workspace,
+ * for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc).  Same
+ * arguments, same kernels and the same results (bit for bit) as
+ * mol_t_helmholtz_sweep, except:
+ *  - The y sweep's scratch (segment totals and seeds, closing-cell
+ *    quadratures) is a static device array of MOLT_NOALLOC_SCRATCH_BYTES
+ *    (molt_noalloc_scratch_bytes()) that each device the library runs on holds
+ *    until the process ends.  A y sweep that needs more returns
+ *    MOLT_EUNSUPPORTED (it needs about 2*nx*ny*batch*esz/(4*ky) bytes, ky the
+ *    shape table's nodes per thread: a 4096 x 4096 FP32 field in one call).
+ *  - In-place y sweeps (d_in == d_out) return MOLT_EINVAL: they need a copy of
+ *    the field, which only the workspace variant has room for.
+ *  - Every call on one device shares that device's array: calls that overlap on
+ *    one device (several streams or threads) race and must be serialized by
+ *    the caller.  Nothing needs clearing between calls.
+ * No hipMalloc, hipFree or allocating library call is made.  The first call on a
+ * device looks up the array's address on that device (it must be current).
+ * Asynchronous on `stream`.
+ */
+#define MOLT_NOALLOC_SCRATCH_BYTES (16u * 1024u * 1024u)
+int32_t mol_t_helmholtz_sweep_noalloc(const molt_grid* grid, int32_t axis, double alpha, int32_t precision,
+                                      const void* d_in, void* d_out, int64_t batch, void* stream);
+size_t molt_noalloc_scratch_bytes(void);
+
+/*
  * ch_workspace_bytes -- bytes of device workspace ch_step / ch_solve need for
  * this grid and these parameters (0 on invalid arguments).
  */

@@ -20,7 +20,8 @@ ARCH = os.environ.get("MOLT_OFFLOAD_ARCH", "gfx950")
 # the single-problem kernels once per pass direction), in parallel
 SOURCES = [("molt_kernels.hip", ("MOLT_PART_X",)), ("molt_kernels.hip", ("MOLT_PART_Y",)),
            ("molt_kernels.hip", ("MOLT_PART_X", "MOLT_PREC_F64")), ("molt_kernels.hip", ("MOLT_PART_Y", "MOLT_PREC_F64")),
-           ("molt_batch.hip", ()), ("molt_batch.hip", ("MOLT_BATCH_F64",)), ("molt_host.cpp", ())]
+           ("molt_batch.hip", ()), ("molt_batch.hip", ("MOLT_BATCH_F64",)), ("molt_noalloc.hip", ()),
+           ("molt_host.cpp", ())]
 # -ffp-contract=on: a multiply-add is fused only within one source expression,
 # so every kernel that inlines the same device code rounds alike (the batched
 # kernels reproduce the single-problem ones bit for bit)

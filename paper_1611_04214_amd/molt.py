@@ -33,7 +33,7 @@ EXPORTS = ("mol_t_helmholtz_sweep", "molt_sweep_workspace_bytes", "ch_workspace_
            "molt_server_create", "molt_server_submit", "molt_server_run", "molt_server_poll",
            "molt_server_destroy", "molt_strerror", "molt_last_error", "molt_profile", "molt_profile_only",
            "molt_profile_read",
-           "molt_set_option")
+           "molt_set_option", "mol_t_helmholtz_sweep_noalloc", "molt_noalloc_scratch_bytes")
 MOLT_TUNE_CLASSES = 7
 MOLT_OPT_FUSED_Y_MIN_ITEMS, MOLT_OPT_BATCH_TICKS, MOLT_OPT_BATCH_GRAPH, MOLT_OPT_BATCH_LEAN = 1, 2, 3, 5
 
@@ -127,6 +127,11 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.mol_t_helmholtz_sweep.restype = ctypes.c_int32
     lib.molt_sweep_workspace_bytes.argtypes = [G, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64]
     lib.molt_sweep_workspace_bytes.restype = sz
+    lib.mol_t_helmholtz_sweep_noalloc.argtypes = [G, ctypes.c_int32, ctypes.c_double, ctypes.c_int32, vp, vp,
+                                                  ctypes.c_int64, vp]
+    lib.mol_t_helmholtz_sweep_noalloc.restype = ctypes.c_int32
+    lib.molt_noalloc_scratch_bytes.argtypes = []
+    lib.molt_noalloc_scratch_bytes.restype = sz
     lib.ch_workspace_bytes.argtypes = [G, P]
     lib.ch_workspace_bytes.restype = sz
     lib.ch_step.argtypes = [G, P, vp, vp, vp, sz, ctypes.POINTER(molt_step_info), vp]
@@ -256,6 +261,15 @@ def mol_t_helmholtz_sweep(grid: molt_grid, axis: int, alpha: float, precision: i
 def molt_sweep_workspace_bytes(grid: molt_grid, axis: int, precision: int, batch: int) -> int:
     return load().molt_sweep_workspace_bytes(ctypes.byref(grid), axis, precision, batch)
 
+
+def mol_t_helmholtz_sweep_noalloc(grid: molt_grid, axis: int, alpha: float, precision: int, d_in: int, d_out: int,
+                                  batch: int, stream: int = 0) -> int:
+    return load().mol_t_helmholtz_sweep_noalloc(ctypes.byref(grid), axis, alpha, precision, d_in, d_out, batch,
+                                                stream or None)
+
+
+def molt_noalloc_scratch_bytes() -> int:
+    return load().molt_noalloc_scratch_bytes()
 
 
 def ch_workspace_bytes(grid: molt_grid, params: molt_ch_params) -> int:

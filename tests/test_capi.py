@@ -231,3 +231,18 @@ def test_adaptive_argument_checks(lib, change):
     for k, v in change.items():
         setattr(ap, k, v)
     assert molt.ch_solve_adaptive(g, p, ap, 1, 1, 1 << 30) == molt.MOLT_EINVAL
+
+
+def test_noalloc_sweep_refuses_what_its_scratch_cannot_hold(lib):
+    """Checked on the host before any device call: an in-place y sweep needs the
+    workspace variant, and a y sweep larger than the static scratch is refused
+    with the size it would need."""
+    assert molt.molt_noalloc_scratch_bytes() == 16 * 1024 * 1024
+    g = molt.make_grid(4096, 4096)
+    fake_in, fake_out = 0x10000, 0x20000
+    rc = molt.mol_t_helmholtz_sweep_noalloc(g, 1, 100.0, molt.MOLT_F32, fake_in, fake_in, 1, 0)
+    assert rc == molt.MOLT_EINVAL and "in-place" in molt.molt_last_error()
+    rc = molt.mol_t_helmholtz_sweep_noalloc(g, 1, 100.0, molt.MOLT_F64, fake_in, fake_out, 64, 0)
+    assert rc == molt.MOLT_EUNSUPPORTED and "scratch" in molt.molt_last_error()
+    rc = molt.mol_t_helmholtz_sweep_noalloc(g, 2, 100.0, molt.MOLT_F32, fake_in, fake_out, 1, 0)
+    assert rc == molt.MOLT_EINVAL
