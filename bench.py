@@ -496,14 +496,17 @@ def run_small(args, molt, synth, oracle):
     # first 3 steps), and a bounded 1-core sample
     og = oracle.Grid(nx=n, ny=n, x0=0.0, x1=1.0, y0=0.0, y1=1.0, bc=oracle.BC_NEUMANN, M=w["M"])
     oracle.set_threads(nthreads)
-    po = oracle.Params(eps=w["eps"], dt=w["dt"], tol=1e-10, stepper=oracle.BDF2, max_iter=5000,
+    # (at tol 1e-8: the first steps of the workload need thousands of
+    # iterations at 1e-10, too long for the oracle here)
+    po = oracle.Params(eps=w["eps"], dt=w["dt"], tol=1e-8, stepper=oracle.BDF2, max_iter=5000,
                        init=oracle.INIT_LINEAR)
     t = time.perf_counter()
     ref, rinf = oracle.solve(og, po, u0, 3)
     t_all = time.perf_counter() - t
+    print(f"ch2d_neumann: oracle 3 steps on {nthreads} threads in {t_all:.1f} s", file=sys.stderr, flush=True)
     errs = {}
-    for prec, dt, tol in ((molt.MOLT_F64, torch.float64, 1e-10), (molt.MOLT_F32, torch.float32, 1e-8)):
-        p = molt.make_params(w["eps"], w["dt"], tol=tol, stepper=molt.MOLT_BDF2, max_iter=5000,
+    for prec, dt in ((molt.MOLT_F64, torch.float64), (molt.MOLT_F32, torch.float32)):
+        p = molt.make_params(w["eps"], w["dt"], tol=1e-8, stepper=molt.MOLT_BDF2, max_iter=5000,
                              init=molt.MOLT_INIT_LINEAR, precision=prec)
         x = torch.tensor(u0, dtype=dt, device="cuda:0")
         molt.solve(x, g, p, 3)
@@ -521,8 +524,8 @@ def run_small(args, molt, synth, oracle):
                     f"{nst} steps; FP64 tol 1e-10, FP32 tol 1e-8, iteration cap 5000",
         "fp64": rec[molt.MOLT_F64], "fp32": rec[molt.MOLT_F32],
         "fp32_vs_fp64_after_all_steps": {"max_abs": float(np.abs(d).max()), "l2": float(np.sqrt((d ** 2).mean()))},
-        "vs_oracle_after_3_steps": {"fp64": errs[molt.MOLT_F64], "fp32": errs[molt.MOLT_F32],
-                                    "oracle_iters": [i.iters for i in rinf]},
+        "vs_oracle_after_3_steps_tol_1e-8": {"fp64": errs[molt.MOLT_F64], "fp32": errs[molt.MOLT_F32],
+                                             "oracle_iters": [i.iters for i in rinf]},
         "oracle_gpt_sweeps_per_s": {f"{nthreads}cores": round(n * n * (12 + 7 * its) / t_all / 1e9, 4),
                                     "1core": round(n * n * (4 + 7 * 10) / t_one / 1e9, 4)},
         "oracle_steps_per_s": {f"{nthreads}cores (first 3 steps)": round(3 / t_all, 3)},
