@@ -206,6 +206,9 @@ def run_batched(args, molt, synth):
             g, p = spec(d)
             _, infos = molt.solve(xp[i], g, p, args.batch_steps, work=ws)
             iters_p.append([r.iters for r in infos])
+            if (i + 1) % 32 == 0:
+                print(f"batched: plain path {i + 1}/{len(inst)} instances, {time.perf_counter() - t0:.1f} s",
+                      file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         tp = time.perf_counter() - t0
         out.update({"plain_s": round(tp, 3), "plain_steps_per_s": round(nsteps / tp, 1),
@@ -247,6 +250,9 @@ def _serve_trace(molt, reqs, u0, arrivals, pool_bytes):
             active, queued = srv.run(1)
             for r in srv.poll():
                 done[r.id] = time.perf_counter() - t0
+                if len(done) % 25 == 0:
+                    print(f"served trace: {len(done)}/{len(reqs)} done at {done[r.id]:.1f} s", file=sys.stderr,
+                          flush=True)
             if active == 0 and queued == 0 and k < len(reqs):
                 time.sleep(max(0.0, arrivals[k] - (time.perf_counter() - t0)))
         srv.close()
@@ -283,6 +289,8 @@ def run_served(args, molt, synth):
         torch.cuda.synchronize()
         durs.append(time.perf_counter() - t0)
         same = same and torch.equal(x.cpu(), fields[i].cpu())
+        if (i + 1) % 25 == 0:
+            print(f"plain FIFO: {i + 1}/{len(reqs)} solved, busy {sum(durs):.1f} s", file=sys.stderr, flush=True)
 
     def fifo(arr, dur):
         fin, out = 0.0, []
@@ -477,9 +485,10 @@ def run_small(args, molt, synth, oracle):
     g = molt.make_grid(n, n, 0.0, 1.0, 0.0, 1.0, molt.MOLT_BC_NEUMANN, w["M"])
     nst = args.c2_steps
     fields, rec = {}, {}
-    for prec, dt, tol in ((molt.MOLT_F64, torch.float64, 1e-10), (molt.MOLT_F32, torch.float32, 1e-8)):
+    for prec, dt, tol in ((molt.MOLT_F64, torch.float64, 1e-10), (molt.MOLT_F32, torch.float32, 1e-8),
+                          ("f64_1e-8", torch.float64, 1e-8)):
         p = molt.make_params(w["eps"], w["dt"], tol=tol, stepper=molt.MOLT_BDF2, max_iter=5000,
-                             init=molt.MOLT_INIT_LINEAR, precision=prec)
+                             init=molt.MOLT_INIT_LINEAR, precision=molt.MOLT_F64 if dt == torch.float64 else molt.MOLT_F32)
         x = torch.tensor(u0, dtype=dt, device="cuda:0")
         (st, infos), tg = _timed(lambda: molt.solve(x, g, p, nst))
         fields[prec] = x.double().cpu().numpy()
@@ -492,6 +501,7 @@ def run_small(args, molt, synth, oracle):
                      "energy_first_last": [infos[0].energy, infos[-1].energy],
                      "gpt_sweeps_per_s": round(n * n * sum(4 + 7 * k for k in it) / tg / 1e9, 2)}
     d = fields[molt.MOLT_F32] - fields[molt.MOLT_F64]
+    d8 = fields[molt.MOLT_F32] - fields["f64_1e-8"]
     # the oracle: 3 converged steps (all cores, compared with both GPU runs'
     # first 3 steps), and a bounded 1-core sample
     og = oracle.Grid(nx=n, ny=n, x0=0.0, x1=1.0, y0=0.0, y1=1.0, bc=oracle.BC_NEUMANN, M=w["M"])
@@ -523,7 +533,13 @@ def run_small(args, molt, synth, oracle):
         "workload": f"2D CH Neumann [0,1]^2, 512x512, eps 0.01, BDF2 dt 5e-5 (BE start-up), M=4, init R, "
                     f"{nst} steps; FP64 tol 1e-10, FP32 tol 1e-8, iteration cap 5000",
         "fp64": rec[molt.MOLT_F64], "fp32": rec[molt.MOLT_F32],
-        "fp32_vs_fp64_after_all_steps": {"max_abs": float(np.abs(d).max()), "l2": float(np.sqrt((d ** 2).mean()))},
+        "fp64_tol_1e-8": rec["f64_1e-8"],
+        # the FP32 error proper: against FP64 at the same tolerance; against
+        # FP64 at 1e-10 it also holds the tolerance's own error
+        "fp32_vs_fp64_same_tol_after_all_steps": {"max_abs": float(np.abs(d8).max()),
+                                                  "l2": float(np.sqrt((d8 ** 2).mean()))},
+        "fp32_vs_fp64_tol_1e-10_after_all_steps": {"max_abs": float(np.abs(d).max()),
+                                                   "l2": float(np.sqrt((d ** 2).mean()))},
         "vs_oracle_after_3_steps_tol_1e-8": {"fp64": errs[molt.MOLT_F64], "fp32": errs[molt.MOLT_F32],
                                              "oracle_iters": [i.iters for i in rinf]},
         "oracle_gpt_sweeps_per_s": {f"{nthreads}cores": round(n * n * (12 + 7 * its) / t_all / 1e9, 4),
@@ -634,7 +650,12 @@ def main():
     # per-kernel breakdown: the last warm-up step (every kernel timed), else
     # the timed steps when there was no warm-up
     every = warm_prof or prof
-    kernels = {kname: {"launches": launches, "avg_us": 1e3 * ms / max(launches, 1)}
+    # launches queued after convergence exit at once: the FP32 iteration
+    # kinds are averaged over the iterations that ran (their total time
+    # includes the no-op launches: pessimistic), the others over launches
+    real_w = max(warm[-1][0] - 1 - (warm[-1][0] - 1) // 64, 1) if warm else max(sum(iters) - len(iters), 1)
+    kernels = {kname: {"launches": launches,
+                       "avg_us": 1e3 * ms / (real_w if kname in BYTES_PER_POINT else max(launches, 1))}
                for kname, (launches, ms) in every.items()}
     if prof:
         nsteps = len(infos)
@@ -648,7 +669,9 @@ def main():
             # convergence exit at once and their (small) time is left in the
             # total (pessimistic)
             _, ms = prof[dom]
-            real = sum(iters) - nsteps
+            # FP32 iterations: all but each step's first and its FP64 restarts
+            # (every 64th)
+            real = sum(k - 1 - (k - 1) // 64 for k in iters)
             per_launch = pts * table[dom]
             avg_s = ms / 1e3 / real
             achieved = per_launch / avg_s / 1e9
@@ -666,7 +689,6 @@ def main():
         # kernels in the last warm-up step (which timed every kernel)
         it_kinds = [k for k in warm_prof if k in BYTES_PER_POINT or k == "other_sweep"]
         it_ms = sum(warm_prof[k][1] for k in it_kinds)
-        real_w = warm[-1][0] - 1
         if it_ms > 0 and real_w > 0:
             per_it_s = it_ms / 1e3 / real_w
             gbs = float(n) * n * ITER_BYTES_PER_POINT / per_it_s / 1e9

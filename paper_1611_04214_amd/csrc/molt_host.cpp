@@ -655,7 +655,12 @@ static int32_t step_impl(const molt_grid* g, const molt_ch_params* p, void* d_u,
 
   const int fixed = p->fixed_iters;
   const int cap = fixed > 0 ? fixed : p->max_iter;
-  int batch = iter_hint > 1 ? iter_hint - 1 : 2;
+  // iterations are enqueued in batches between host checks of the device
+  // state: a batch grows with the iterations already done (a quarter of them,
+  // 2..32), so a step that converges in a few iterations queues few that
+  // exit at once, and a long one checks rarely; a hint (the previous step's
+  // count) lets the first batch cover most of the step
+  int batch = iter_hint > 2 ? iter_hint - 2 : 2;
   DevState hst;
   memset(&hst, 0, sizeof(hst));
   for (;;) {
@@ -676,7 +681,7 @@ static int32_t step_impl(const molt_grid* g, const molt_ch_params* p, void* d_u,
     HIPCHK(hipStreamSynchronize(s));
     if (g_prof_on) prof_drain();
     if (hst.done || it >= cap) break;
-    batch = batch < 32 ? batch * 2 : 32;
+    batch = it / 4 < 2 ? 2 : (it / 4 > 32 ? 32 : it / 4);
   }
   HIPCHK(launch_finalize(prec, d_u, base, F[F_W], nel, s));
   if (vform) {
