@@ -60,26 +60,24 @@ HBM_PEAK_GBS = 8000.0
 
 # Algorithmic HBM bytes per grid point of one launch of the FP32 iteration
 # kernels (increment form: every FP32 iteration after a step's FP64 first one):
-# field reads + writes, plus the three-kernel y-pass's per-segment totals /
-# seeds (2 fields x 2 directions x 4 B per 64 rows).
+# field reads + writes; the single-read y-pass (timed under the yfin kinds)
+# also writes its per-segment totals, the combine reads them and writes the
+# seeds, and the next x-pass reads the seeds (2 fields x 2 directions x 4 B per
+# 64-row segment: 0.25 B per point each).
 BYTES_PER_POINT = {
-    "ytot_P1": 12 + 0.25,
+    "yfin_P1": 12 + 8 + 0.25,
     "ycomb_P1": 0.5,
-    "yfin_P1": 12 + 0.25 + 8,
-    "xpass_P2": 20 + 8,
-    "ytot_P3": 8 + 0.25,
+    "xpass_P2": 20 + 8 + 0.25,
+    "yfin_P3": 8 + 8 + 0.25,
     "ycomb_P3": 0.5,
-    "yfin_P3": 8 + 0.25 + 8,
-    "xpass_P4": 16 + 8,
+    "xpass_P4": 16 + 8 + 0.25,
 }
-# the single-kernel y-pass is timed under the yfin kinds and reads its inputs once
-BYTES_PER_POINT_FUSED = {"yfin_P1": 12 + 8, "yfin_P3": 8 + 8}
 # one whole FP32 iteration with every field read once and written once:
 # P1 3 reads + 2 writes, P2 5 + 2, P3 2 + 2, P4 4 + 2, 4 B each
 ITER_BYTES_PER_POINT = 88.0
 
 
-COUNTERS = os.path.join(ROOT, "profiles", "xpass_4096_fp32_hbm_counters.md")
+COUNTERS = os.path.join(ROOT, "profiles", "linepass_4096_fp32_hbm_counters.md")
 # what decides the x-pass kernel's code: its sources and the compile flags
 KERNEL_SOURCES = ("csrc/molt_device.h", "csrc/molt_kernels.hip", "csrc/molt_internal.h", "build.py")
 
@@ -129,8 +127,6 @@ def parse():
     ap.add_argument("--no-error", action="store_true", help="skip the FP32 error measurement")
     ap.add_argument("--c2-steps", type=int, default=2000, help="steps of the 512^2 Neumann workload")
     ap.add_argument("--no-profile", action="store_true", help="do not time kernels with HIP events")
-    ap.add_argument("--fused-min-items", type=int, default=None,
-                    help="work items from which the single-kernel y-pass is used (library default 256)")
     ap.add_argument("--shape", type=str, default="auto",
                     help="line-block shape of the workload's line length: 'auto' (autotuned), 'default' "
                          "(the library's table) or 'kx,ky'")
@@ -567,8 +563,6 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     molt.load()
-    if args.fused_min_items is not None:
-        molt.molt_set_option(molt.MOLT_OPT_FUSED_Y_MIN_ITEMS, args.fused_min_items)
     name = "ch2d_periodic_bdf2_4096"
     w = synth.WORKLOADS[name]
     n = args.n
@@ -620,9 +614,7 @@ def main():
               f"time={warm[-1][1]:.3f}s", file=sys.stderr, flush=True)
 
     if not args.no_profile:
-        fused_w = "ytot_P1" not in warm_prof
-        table_w = dict(BYTES_PER_POINT, **(BYTES_PER_POINT_FUSED if fused_w else {}))
-        dom_w = max((k for k in warm_prof if k in table_w), key=lambda k: warm_prof[k][1], default=None)
+        dom_w = max((k for k in warm_prof if k in BYTES_PER_POINT), key=lambda k: warm_prof[k][1], default=None)
         molt.molt_profile_only(molt.kind_of(dom_w) if dom_w is not None else -1)
         molt.molt_profile(1)
     torch.cuda.synchronize()
@@ -659,8 +651,7 @@ def main():
                for kname, (launches, ms) in every.items()}
     if prof:
         nsteps = len(infos)
-        fused = "ytot_P1" not in every
-        table = dict(BYTES_PER_POINT, **(BYTES_PER_POINT_FUSED if fused else {}))
+        table = BYTES_PER_POINT
         dom = max((k for k in prof if k in table), key=lambda k: prof[k][1], default=None)
         if dom is not None:
             # the FP32 kernels run the increment-form iterations (each step's
@@ -677,7 +668,7 @@ def main():
             achieved = per_launch / avg_s / 1e9
             roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": counter_traffic(dom, n),
-                    "kernel": dom + (" (single-kernel y-pass)" if fused and dom.startswith("yfin") else ""),
+                    "kernel": dom,
                     "bytes_per_launch": per_launch, "avg_launch_us": round(avg_s * 1e6, 2)}
             total_ms = sum(v[1] for v in every.values())
             roof["kernel_share_of_gpu_time"] = (round(every[dom][1] / total_ms, 3)
@@ -696,7 +687,6 @@ def main():
                      "frac": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_point": ITER_BYTES_PER_POINT,
                      "kernel_us_per_iteration": round(per_it_s * 1e6, 2),
                      "kernels": sorted(it_kinds),
-                     # what the kernels move (the three-kernel y-pass reads its inputs twice)
                      "moved_bytes_per_point": sum(BYTES_PER_POINT[k] for k in BYTES_PER_POINT if k in warm_prof)}
             wall_us = 1e6 * elapsed / max(sum(iters), 1)
             whole["wall_us_per_iteration_timed_steps"] = round(wall_us, 2)

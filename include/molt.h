@@ -388,13 +388,8 @@ int32_t molt_profile_read(molt_prof_entry* out, int32_t max_entries);
 
 /*
  * Tuning options (process-wide; not part of the method).
- *  MOLT_OPT_FUSED_Y_MIN_ITEMS: the single-kernel y-pass (FP32, periodic) is
- *    used when a pass has at least this many (64-column x segment) work items;
- *    0 uses it whenever it applies; the default (2^40) never does, because
- *    on the 4096^2 workload it has not yet beaten the three-kernel y-pass.
  * Returns MOLT_OK or MOLT_EINVAL for an unknown option or a value out of range.
  */
-#define MOLT_OPT_FUSED_Y_MIN_ITEMS 1
 /*  MOLT_OPT_BATCH_TICKS (1..1024, default 8): device ticks of ch_solve_batch
  *    between two host checks of whether every instance has finished.
  *  MOLT_OPT_BATCH_GRAPH (0 or 1, default 1): replay those ticks as one

@@ -68,6 +68,19 @@ __device__ __forceinline__ SlotView slot_view(const SlotDesc& d) {
                   d.ynth, d.ynseg, d.yk, d.tlx, d.vecx, d.xblocks};
 }
 
+// corrections of the deferred y-pass (lines cy, nf swept fields) for the x-pass after it
+__device__ __forceinline__ YCorr slot_ycorr(const SlotDesc& d, const SlotView& v, const LineCoef& cy, int nf) {
+  YCorr y;
+  y.seeds = v.tot;
+  y.nf = nf;
+  y.nseg = v.ynseg;
+  y.S = kRG * v.yk;
+  y.ny = d.ny;
+  y.nx = d.nx;
+  y.nu = cy.nu;
+  return y;
+}
+
 // arguments of pass `pass` (1..4) of a slot in phase ph (the same fields as
 // the single-problem driver uses)
 __device__ __forceinline__ PassArgs slot_args(const SlotDesc& d, const SlotView& v, int ph, int pass, int var,
@@ -78,6 +91,8 @@ __device__ __forceinline__ PassArgs slot_args(const SlotDesc& d, const SlotView&
 #pragma unroll
   for (int i = 0; i < 3; ++i) a.out[i] = nullptr;
   a.ushift[0] = a.ushift[1] = 0.0;  // batched instances hold u (no Dirichlet walls)
+  a.corr.seeds = nullptr;
+  a.rc0 = a.rc1 = 0.0;
   void* const* F = v.F;
   if (ph == PH_R) {
     a.sigma = 0.0;
@@ -142,9 +157,9 @@ __device__ __forceinline__ PassArgs slot_args(const SlotDesc& d, const SlotView&
   return a;
 }
 
-// y-pass `PASS` (1 or 3) with K nodes per thread: totals (FIN = false) or
-// final scans (FIN = true)
-template <typename T, int K, int M, bool PER, int PASS, bool FIN>
+// deferred y-pass `PASS` (1 or 3) with K nodes per thread (segment-local
+// scans and segment totals; the combine writes the seeds the x-pass adds)
+template <typename T, int K, int M, bool PER, int PASS>
 __global__ void MOLT_PASS_ATTR ypass_batch_kernel(const SlotDesc* __restrict__ sd, const SlotCtl* __restrict__ ctl,
                                                   const BlkMap* __restrict__ map) {
   const BlkMap e = map[blockIdx.x];
@@ -161,10 +176,7 @@ __global__ void MOLT_PASS_ATTR ypass_batch_kernel(const SlotDesc* __restrict__ s
     constexpr int PR = PASS == 1 ? PROG_RHS : PROG_SWEEP;
     const PassArgs a = slot_args(d, v, PH_R, PASS, var, 0);
     const LineCoef& c = d.cy[var][PASS == 1 ? 1 : 0];
-    if constexpr (FIN)
-      yfin_body<T, PR, K, M, PER>(c, a, nullptr, d.nx, v.ynth, v.ynseg, fstride, (const T*)v.tot, bx, by, bz);
-    else
-      ytot_body<T, PR, K, M, PER>(c, a, nullptr, d.nx, v.ynth, v.ynseg, fstride, (T*)v.tot, (T*)v.jln, bx, by, bz);
+    yloc_body<T, PR, K, M, PER>(c, a, nullptr, d.nx, v.ynth, v.ynseg, fstride, (T*)v.tot, (T*)v.jln, bx, by, bz);
   } else {
     DevState* st = d.st;
     if (st->done) return;
@@ -172,19 +184,13 @@ __global__ void MOLT_PASS_ATTR ypass_batch_kernel(const SlotDesc* __restrict__ s
     const LineCoef& c = d.cy[var][PASS == 1 ? 0 : 1];
     if constexpr (PASS == 1) {
       if (d.model == MOLT_MODEL_VCH) {
-        if constexpr (FIN)
-          yfin_body<T, PROG_P1V, K, M, PER>(c, a, st, d.nx, v.ynth, v.ynseg, fstride, (const T*)v.tot, bx, by, bz);
-        else
-          ytot_body<T, PROG_P1V, K, M, PER>(c, a, st, d.nx, v.ynth, v.ynseg, fstride, (T*)v.tot, (T*)v.jln, bx, by,
-                                            bz);
+        yloc_body<T, PROG_P1V, K, M, PER>(c, a, st, d.nx, v.ynth, v.ynseg, fstride, (T*)v.tot, (T*)v.jln, bx, by,
+                                          bz);
         return;
       }
     }
     constexpr int PI = PASS == 1 ? PROG_P1 : PROG_P3;
-    if constexpr (FIN)
-      yfin_body<T, PI, K, M, PER>(c, a, st, d.nx, v.ynth, v.ynseg, fstride, (const T*)v.tot, bx, by, bz);
-    else
-      ytot_body<T, PI, K, M, PER>(c, a, st, d.nx, v.ynth, v.ynseg, fstride, (T*)v.tot, (T*)v.jln, bx, by, bz);
+    yloc_body<T, PI, K, M, PER>(c, a, st, d.nx, v.ynth, v.ynseg, fstride, (T*)v.tot, (T*)v.jln, bx, by, bz);
   }
 }
 
@@ -226,13 +232,17 @@ __global__ void MOLT_PASS_ATTR xpass_batch_kernel(const SlotDesc* __restrict__ s
   const int var = cc.var;
   const int nlines = d.ny * d.ncomp;  // the components' rows, stacked
   if (cc.phase == PH_R) {
-    const PassArgs a = slot_args(d, v, PH_R, PASS, var, 0);
+    PassArgs a = slot_args(d, v, PH_R, PASS, var, 0);
+    // the y-pass before: the rhs (alpha2) before pass 2, the sweep (alpha1) before pass 4
+    a.corr = slot_ycorr(d, v, d.cy[var][PASS == 2 ? 1 : 0], 1);
     xpass_body<T, PROG_SWEEP, K, M, PER>(d.cx[var][PASS == 2 ? 1 : 0], a, nullptr, nlines, v.tlx, nullptr, v.vecx,
                                          e.blk, smem);
   } else {
     DevState* st = d.st;
     if (st->done) return;
-    const PassArgs a = slot_args(d, v, PH_IT, PASS, var, slot_mode<T>(d));
+    PassArgs a = slot_args(d, v, PH_IT, PASS, var, slot_mode<T>(d));
+    // the y-pass before: P1 (alpha1) before pass 2, P3 (alpha2) before pass 4
+    a.corr = slot_ycorr(d, v, d.cy[var][PASS == 2 ? 0 : 1], 2);
     if constexpr (PASS == 2) {
       if (d.model == MOLT_MODEL_VCH) {
         xpass_body<T, PROG_P2V, K, M, PER>(d.cx[var][0], a, st, nlines, v.tlx, nullptr, v.vecx, e.blk, smem);
@@ -451,53 +461,48 @@ __global__ void __launch_bounds__(256) count_active_kernel(const SlotCtl* __rest
 // launchers
 // --------------------------------------------------------------------------
 template <typename T, int K, int M, bool PER>
-static hipError_t ybatch_m(int pass, bool fin, const SlotDesc* sd, const SlotCtl* ctl, const BlkMap* map, int nblk,
+static hipError_t ybatch_m(int pass, const SlotDesc* sd, const SlotCtl* ctl, const BlkMap* map, int nblk,
                            hipStream_t s) {
   const dim3 blk(64, kRG);
-  if (pass == 1) {
-    if (fin) hipLaunchKernelGGL((ypass_batch_kernel<T, K, M, PER, 1, true>), dim3(nblk), blk, 0, s, sd, ctl, map);
-    else hipLaunchKernelGGL((ypass_batch_kernel<T, K, M, PER, 1, false>), dim3(nblk), blk, 0, s, sd, ctl, map);
-  } else {
-    if (fin) hipLaunchKernelGGL((ypass_batch_kernel<T, K, M, PER, 3, true>), dim3(nblk), blk, 0, s, sd, ctl, map);
-    else hipLaunchKernelGGL((ypass_batch_kernel<T, K, M, PER, 3, false>), dim3(nblk), blk, 0, s, sd, ctl, map);
-  }
+  if (pass == 1) hipLaunchKernelGGL((ypass_batch_kernel<T, K, M, PER, 1>), dim3(nblk), blk, 0, s, sd, ctl, map);
+  else hipLaunchKernelGGL((ypass_batch_kernel<T, K, M, PER, 3>), dim3(nblk), blk, 0, s, sd, ctl, map);
   return hipGetLastError();
 }
 
 template <typename T, int K>
-static hipError_t ybatch_k(int M, bool per, int pass, bool fin, const SlotDesc* sd, const SlotCtl* ctl,
-                           const BlkMap* map, int nblk, hipStream_t s) {
+static hipError_t ybatch_k(int M, bool per, int pass, const SlotDesc* sd, const SlotCtl* ctl, const BlkMap* map,
+                           int nblk, hipStream_t s) {
   switch (M) {
-    case 2: return per ? ybatch_m<T, K, 2, true>(pass, fin, sd, ctl, map, nblk, s)
-                       : ybatch_m<T, K, 2, false>(pass, fin, sd, ctl, map, nblk, s);
-    case 4: return per ? ybatch_m<T, K, 4, true>(pass, fin, sd, ctl, map, nblk, s)
-                       : ybatch_m<T, K, 4, false>(pass, fin, sd, ctl, map, nblk, s);
-    case 6: return per ? ybatch_m<T, K, 6, true>(pass, fin, sd, ctl, map, nblk, s)
-                       : ybatch_m<T, K, 6, false>(pass, fin, sd, ctl, map, nblk, s);
+    case 2: return per ? ybatch_m<T, K, 2, true>(pass, sd, ctl, map, nblk, s)
+                       : ybatch_m<T, K, 2, false>(pass, sd, ctl, map, nblk, s);
+    case 4: return per ? ybatch_m<T, K, 4, true>(pass, sd, ctl, map, nblk, s)
+                       : ybatch_m<T, K, 4, false>(pass, sd, ctl, map, nblk, s);
+    case 6: return per ? ybatch_m<T, K, 6, true>(pass, sd, ctl, map, nblk, s)
+                       : ybatch_m<T, K, 6, false>(pass, sd, ctl, map, nblk, s);
   }
   return hipErrorInvalidValue;
 }
 
 template <typename T>
-static hipError_t ybatch_t(int K, int M, bool per, int pass, bool fin, const SlotDesc* sd, const SlotCtl* ctl,
+static hipError_t ybatch_t(int K, int M, bool per, int pass, const SlotDesc* sd, const SlotCtl* ctl,
                            const BlkMap* map, int nblk, hipStream_t s) {
   switch (K) {
-    case 4: return ybatch_k<T, 4>(M, per, pass, fin, sd, ctl, map, nblk, s);
-    case 8: return ybatch_k<T, 8>(M, per, pass, fin, sd, ctl, map, nblk, s);
+    case 4: return ybatch_k<T, 4>(M, per, pass, sd, ctl, map, nblk, s);
+    case 8: return ybatch_k<T, 8>(M, per, pass, sd, ctl, map, nblk, s);
     case 16:
-      if constexpr (sizeof(T) == 4) return ybatch_k<T, 16>(M, per, pass, fin, sd, ctl, map, nblk, s);
+      if constexpr (sizeof(T) == 4) return ybatch_k<T, 16>(M, per, pass, sd, ctl, map, nblk, s);
       return hipErrorInvalidValue;
   }
   return hipErrorInvalidValue;
 }
 
-hipError_t MOLT_BFN(launch_batch_y)(int K, int M, bool per, int pass, bool fin, const SlotDesc* sd,
-                                   const SlotCtl* ctl, const BlkMap* map, int nblk, hipStream_t s) {
+hipError_t MOLT_BFN(launch_batch_y)(int K, int M, bool per, int pass, const SlotDesc* sd, const SlotCtl* ctl,
+                                   const BlkMap* map, int nblk, hipStream_t s) {
   if (nblk <= 0) return hipSuccess;
-  const int kind = (fin ? KF_YFIN : KF_YTOT) * 8 + (pass == 1 ? PROG_P1 : PROG_P3);
-  if (g_prof_on) prof_begin(prof_kind<MOLT_BT>(kind), s);
-  const hipError_t e = ybatch_t<MOLT_BT>(K, M, per, pass, fin, sd, ctl, map, nblk, s);
-  if (g_prof_on) prof_end(prof_kind<MOLT_BT>(kind), s);
+  const int kind = prof_kind<MOLT_BT>(KF_YFIN * 8 + (pass == 1 ? PROG_P1 : PROG_P3));
+  if (g_prof_on) prof_begin(kind, s);
+  const hipError_t e = ybatch_t<MOLT_BT>(K, M, per, pass, sd, ctl, map, nblk, s);
+  if (g_prof_on) prof_end(kind, s);
   return e;
 }
 

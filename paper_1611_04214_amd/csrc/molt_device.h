@@ -35,6 +35,7 @@
 
 #define MOLT_PASS_ATTR __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MOLT_OCC)))
 
+
 namespace molt {
 
 // --------------------------------------------------------------------------
@@ -313,6 +314,41 @@ __device__ __forceinline__ void st1_out(T* p, T v) {
   if constexpr (NT) __builtin_nontemporal_store(v, p); else *p = v;
 }
 
+// Corrections an x-pass applies to the raw fields it reads from a deferred
+// y-pass (see YCorr): for its row, the factors 1/2 d^(j - j0s) and
+// 1/2 d^(jls - j) and the seed rows of the row's segment.
+template <typename T>
+struct RowCorr {
+  const T* sL[2];
+  const T* sR[2];
+  T cL, cR;
+  int nf;  // 0: nothing to correct
+  __device__ void init(const YCorr& yc, int line) {
+    nf = yc.seeds != nullptr ? yc.nf : 0;
+    if (nf == 0) return;
+    const int b = line / yc.ny, j = line - b * yc.ny;
+    const int seg = j / yc.S;
+    const int j0s = seg * yc.S;
+    const int jls = min(j0s + yc.S - 1, yc.ny - 1);
+    cL = T(0.5) * dpow<T>(yc.nu, (double)(j - j0s));
+    cR = T(0.5) * dpow<T>(yc.nu, (double)(jls - j));
+    const size_t plane = (size_t)yc.nseg * yc.nx;
+#pragma unroll
+    for (int f = 0; f < 2; ++f) {
+      const T* base = (const T*)yc.seeds + ((size_t)(b * yc.nf + (f < yc.nf ? f : 0)) * 2) * plane + (size_t)seg * yc.nx;
+      sL[f] = base;
+      sR[f] = base + plane;
+    }
+  }
+  // raw values r of column col (fields f < nf corrected)
+  template <int NR>
+  __device__ __forceinline__ void apply(int col, T* r) const {
+#pragma unroll
+    for (int f = 0; f < (NR < 2 ? NR : 2); ++f)
+      if (f < nf) r[f] += cL * sL[f][col] + cR * sR[f][col];
+  }
+};
+
 // --------------------------------------------------------------------------
 // Per-thread line segment: sweep inputs on nodes j0-H .. j0+K+H-1, the two
 // local quadratures on the K owned nodes, zero-seeded totals and the final
@@ -395,7 +431,7 @@ struct Seg {
   // J^L, J^R on the owned nodes from the window values s (nodes j0-H ..
   // j0+K+H-1); boundary nodes of non-periodic lines are redone in FP64
   __device__ void stencils(const LineCoef& c, const PassArgs& a, size_t lbase, size_t stride, int j0,
-                           const T (&s)[F][W]) {
+                           const T (&s)[F][W], const RowCorr<T>* rc = nullptr) {
     const int n = c.n;
     constexpr bool per = PER;
     T wl[M + 1], wr[M + 1];
@@ -422,7 +458,7 @@ struct Seg {
       }
     }
     if constexpr (!PER) {
-      if (j0 < H || j0 + K + H > n) boundary_nodes(c, a, lbase, stride, j0);
+      if (j0 < H || j0 + K + H > n) boundary_nodes(c, a, lbase, stride, j0, rc);
     }
   }
 
@@ -433,7 +469,9 @@ struct Seg {
   // FP64 and only the result is rounded to T.  The in-range window values are
   // reloaded here (only the threads at the two ends of a line get here), so
   // the window array of the interior path is not kept alive.
-  __device__ void boundary_nodes(const LineCoef& c, const PassArgs& a, size_t lbase, size_t stride, int j0) {
+  // (rc: the x-pass's row corrections, applied to every reloaded value)
+  __device__ void boundary_nodes(const LineCoef& c, const PassArgs& a, size_t lbase, size_t stride, int j0,
+                                 const RowCorr<T>* rc) {
     const int n = c.n;
     double gl[F][H], gr[F][H];
 #pragma unroll
@@ -447,7 +485,9 @@ struct Seg {
 #pragma unroll
       for (int i = 0; i <= M; ++i) {
         T rv[NR], sv[F];
-        load_raw<T, P>(a, lbase + (size_t)(side == 0 ? i : n - 1 - M + i) * stride, rv);
+        const int jn = side == 0 ? i : n - 1 - M + i;
+        load_raw<T, P>(a, lbase + (size_t)jn * stride, rv);
+        if (rc != nullptr) rc->template apply<NR>(jn, rv);
         P::sin(a, rv, sv);
 #pragma unroll
         for (int f = 0; f < F; ++f) e[f][i] = (double)sv[f];
@@ -476,7 +516,9 @@ struct Seg {
           for (int i = 0; i <= M; ++i) {
             const int jw = j - H + i;
             T rv[NR], sv[F];
-            load_raw<T, P>(a, lbase + (size_t)min(max(jw, 0), n - 1) * stride, rv);
+            const int jc = min(max(jw, 0), n - 1);
+            load_raw<T, P>(a, lbase + (size_t)jc * stride, rv);
+            if (rc != nullptr) rc->template apply<NR>(jc, rv);
             P::sin(a, rv, sv);
             double v = (double)sv[f];
 #pragma unroll
@@ -688,18 +730,44 @@ __device__ __forceinline__ void xpass_body(const LineCoef& c, const PassArgs& a,
 #define MOLT_PAD(e) ((e) + ((e) >> 4))
 
   Seg<T, P, K, M, PER> seg;
+  // corrections of the deferred y-pass whose outputs this pass reads
+  RowCorr<T> rc;
+  rc.init(a.corr, act ? line : 0);
+  constexpr int NC = NR < 2 ? NR : 2;  // raw fields that can be corrected
   // phase A: coalesced loads, the program's pointwise part in the load layout
   if (act) {
     if (vec) {
       // every load of the thread first (positions past the line read its
       // first element and are dropped), then the pointwise part
       T r[K / V][NR][V];
+      // the deferred y-pass's seeds are loaded with the raw fields (all
+      // loads in flight together) and folded in after the last of them;
+      // folding each group as it arrives keeps fewer registers but
+      // serializes the loads (P2 92 -> 117 us at 4096^2)
+      T sl[K / V][NC][V], sr[K / V][NC][V];
 #pragma unroll
       for (int it = 0; it < K / V; ++it) {
         const int e0 = (it * TL + t) * V;
         const size_t off = lbase + (size_t)(e0 < n ? e0 : 0);
 #pragma unroll
         for (int f = 0; f < NR; ++f) ld16(raw_ptr<T, P>(a, f) + off, r[it][f]);
+        const int ec = e0 < n ? e0 : 0;
+#pragma unroll
+        for (int f = 0; f < NC; ++f)
+          if (f < rc.nf) {
+            ld16(rc.sL[f] + ec, sl[it][f]);
+            ld16(rc.sR[f] + ec, sr[it][f]);
+          }
+      }
+      if (rc.nf > 0) {
+#pragma unroll
+        for (int it = 0; it < K / V; ++it)
+#pragma unroll
+          for (int f = 0; f < NC; ++f)
+            if (f < rc.nf) {
+#pragma unroll
+              for (int v = 0; v < V; ++v) r[it][f][v] += rc.cL * sl[it][f][v] + rc.cR * sr[it][f][v];
+            }
       }
 #pragma unroll
       for (int it = 0; it < K / V; ++it) {
@@ -728,6 +796,7 @@ __device__ __forceinline__ void xpass_body(const LineCoef& c, const PassArgs& a,
         if (e < n) {
           T rv[NR], sv[F], xv[E > 0 ? E : 1];
           load_raw<T, P>(a, lbase + (size_t)e, rv);
+          rc.template apply<NR>(e, rv);
           P::sin(a, rv, sv);
 #pragma unroll
           for (int f = 0; f < F; ++f) sh_row[f][MOLT_PAD(rowoff + e)] = sv[f];
@@ -758,7 +827,7 @@ __device__ __forceinline__ void xpass_body(const LineCoef& c, const PassArgs& a,
 #pragma unroll
       for (int f = 0; f < F; ++f) sw[f][k] = sh_row[f][MOLT_PAD(rowoff + jj)];
     }
-    seg.stencils(c, a, lbase, 1, j0, sw);
+    seg.stencils(c, a, lbase, 1, j0, sw, &rc);
     seg.totals(d, j0, n, AL, AR);
   } else {
 #pragma unroll
@@ -910,7 +979,6 @@ __device__ __forceinline__ void xpass_body(const LineCoef& c, const PassArgs& a,
 //         boundary solve and the seeds, written over tot
 //  yfin: seeded scans and the program outputs
 // --------------------------------------------------------------------------
-constexpr int kRG = 4;
 
 template <typename T, int PI, int K, int M, bool PER>
 __device__ __forceinline__ void ytot_body(const LineCoef& c, const PassArgs& a, DevState* st, int nx, int nth,
@@ -966,6 +1034,87 @@ __device__ __forceinline__ void ytot_body(const LineCoef& c, const PassArgs& a, 
     ab[((size_t)(f * 2 + 0) * nseg + sg) * nx + col] = L;
     ab[((size_t)(f * 2 + 1) * nseg + sg) * nx + col] = R;
   }
+}
+
+
+// yloc: the deferred y-pass in one read of its inputs.  Each segment of
+// kRG*K rows is scanned from zero (block-internal carries through LDS), the
+// program's outputs are written from these segment-local values, and the
+// segment's zero-seeded totals (and the periodic closing quadrature) go to agg
+// / jlnb for ycomb, whose seeds the next x-pass adds (YCorr).
+template <typename T, int PI, int K, int M, bool PER>
+__device__ __forceinline__ void yloc_body(const LineCoef& c, const PassArgs& a, DevState* st, int nx, int nth,
+                                          int nseg, size_t fstride, T* agg, T* jlnb, int bx, int by, int bz) {
+  using P = typename ProgOf<PI, T>::type;
+  constexpr int F = P::F;
+  if (st != nullptr && st->done) return;
+  __shared__ T shA[F][2][kRG][64];
+  const int lx = threadIdx.x, r = threadIdx.y;
+  const int col = bx * 64 + lx;
+  const int sg = by;
+  const int t = sg * kRG + r;
+  const int b = bz;
+  const bool ok = col < nx && t < nth;
+  const int n = c.n, j0 = t * K;
+  const size_t lbase = (size_t)b * fstride + (size_t)(col < nx ? col : 0);
+  const T d = (T)c.d;
+  Seg<T, P, K, M, PER> seg;
+  T AL[F], AR[F];
+  if (ok) {
+    seg.build(c, a, lbase, (size_t)nx, j0, false);
+    seg.totals(d, j0, n, AL, AR);
+    if (t == 0) {
+#pragma unroll
+      for (int f = 0; f < F; ++f) jlnb[((size_t)b * F + f) * nx + col] = seg.jln[f];
+    }
+  } else {
+#pragma unroll
+    for (int f = 0; f < F; ++f) AL[f] = AR[f] = T(0);
+  }
+#pragma unroll
+  for (int f = 0; f < F; ++f) {
+    shA[f][0][r][lx] = AL[f];
+    shA[f][1][r][lx] = AR[f];
+  }
+  __syncthreads();
+  const int j0s = sg * kRG * K;
+  const int jls = min(j0s + kRG * K - 1, n - 1);
+  if (r == 0 && col < nx) {
+    // the segment's zero-seeded totals: L at its last row, R at its first row
+    T* ab = agg + (size_t)b * (size_t)(F * 2) * nseg * nx;
+#pragma unroll
+    for (int f = 0; f < F; ++f) {
+      T L = T(0), R = T(0);
+#pragma unroll
+      for (int g = 0; g < kRG; ++g) {
+        const int tt = sg * kRG + g;
+        if (tt < nth) {
+          const int jl = min(tt * K + K - 1, n - 1);
+          L += dpow<T>(c.nu, (double)(jls - jl)) * shA[f][0][g][lx];
+          R += dpow<T>(c.nu, (double)(tt * K - j0s)) * shA[f][1][g][lx];
+        }
+      }
+      ab[((size_t)(f * 2 + 0) * nseg + sg) * nx + col] = L;
+      ab[((size_t)(f * 2 + 1) * nseg + sg) * nx + col] = R;
+    }
+  }
+  if (!ok) return;
+  // carries from the segment's other thread rows only (the segment starts
+  // from zero at both ends)
+  const T mK = dpow<T>(c.nu, (double)K);
+  T gL[F], gR[F];
+#pragma unroll
+  for (int f = 0; f < F; ++f) {
+    T cl = T(0), cr = T(0);
+    for (int g = 0; g < r; ++g) cl = mK * cl + shA[f][0][g][lx];
+    for (int g = kRG - 1; g > r; --g)
+      if (sg * kRG + g < nth) cr = mK * cr + shA[f][1][g][lx];
+    gL[f] = d * cl;
+    gR[f] = d * cr;
+  }
+  T w[F][K];
+  seg.finalize(d, j0, n, gL, gR, w);
+  seg.store(a, lbase, (size_t)nx, j0, n, false, w);
 }
 
 

@@ -18,7 +18,7 @@ namespace molt {
   hipError_t launch_xpass_##sfx(int prog, const LineCoef& c, const PassArgs& a, DevState* st, int nlines,     \
                                 double* rpart, hipStream_t s);                                                 \
   hipError_t launch_ypass_##sfx(int prog, const LineCoef& c, const PassArgs& a, DevState* st, int nx,         \
-                                int batch, void* tot, void* jln, const YFused* fz, hipStream_t s);             \
+                                int batch, void* tot, void* jln, bool deferred, hipStream_t s);                \
   hipError_t launch_pointwise_##sfx(int prog, const PassArgs& a, DevState* st, size_t nelem, hipStream_t s);  \
   hipError_t launch_copy_##sfx(void* dst, const void* src, size_t n, hipStream_t s);                          \
   hipError_t launch_finalize_##sfx(void* u, const void* base, const void* W, size_t n, hipStream_t s);        \
@@ -40,8 +40,8 @@ hipError_t launch_xpass(int prec, int prog, const LineCoef& c, const PassArgs& a
   return MOLT_PREC(launch_xpass)(prog, c, a, st, nlines, rpart, s);
 }
 hipError_t launch_ypass(int prec, int prog, const LineCoef& c, const PassArgs& a, DevState* st, int nx, int batch,
-                        void* tot, void* jln, const YFused* fz, hipStream_t s) {
-  return MOLT_PREC(launch_ypass)(prog, c, a, st, nx, batch, tot, jln, fz, s);
+                        void* tot, void* jln, bool deferred, hipStream_t s) {
+  return MOLT_PREC(launch_ypass)(prog, c, a, st, nx, batch, tot, jln, deferred, s);
 }
 static hipError_t launch_pointwise(int prec, int prog, const PassArgs& a, DevState* st, size_t nelem, hipStream_t s) {
   return MOLT_PREC(launch_pointwise)(prog, a, st, nelem, s);
@@ -74,8 +74,6 @@ static hipError_t launch_addc(int prec, void* x, double c0, double c1, size_t n,
   return MOLT_PREC(launch_addc)(x, c0, c1, n, nc, s);
 }
 #undef MOLT_PREC
-size_t yfused_items(int n, int nx, int batch);
-size_t yfused_rec_words(int n, int nx, int batch);
 hipError_t launch_zero_ints(int* p, int n, hipStream_t s);
 hipError_t launch_widen(void* dst64, const void* src32, size_t n, hipStream_t s);
 hipError_t launch_rebase_mixed(void* base32, void* W32, void* DL32, const void* base64, const void* W64,
@@ -94,7 +92,7 @@ int xpass_tl(int n, int K);
 void ypass_shape(int prec, int n, int* nth, int* nseg);
 // batched kernels, one translation unit per precision
 #define MOLT_BATCH_DECL(sfx)                                                                                    \
-  hipError_t launch_batch_y_##sfx(int K, int M, bool per, int pass, bool fin, const SlotDesc* sd,              \
+  hipError_t launch_batch_y_##sfx(int K, int M, bool per, int pass, const SlotDesc* sd,                        \
                                   const SlotCtl* ctl, const BlkMap* map, int nblk, hipStream_t s);             \
   hipError_t launch_batch_comb_##sfx(int pass, const SlotDesc* sd, const SlotCtl* ctl, const BlkMap* map,      \
                                      int nblk, hipStream_t s);                                                 \
@@ -141,7 +139,6 @@ static int32_t fail(int32_t code, const std::string& msg) {
 // per-kernel HIP-event profiler (process-wide; meant for one profiling thread)
 // --------------------------------------------------------------------------
 bool g_prof_on = false;
-static long long g_fused_min_items = 1LL << 40;  // single-kernel y-pass off by default
 static int g_batch_ticks = 8;                     // batched solve: ticks between host checks
 static int g_batch_graph = 1;                     // batched solve: replay the ticks as a HIP graph
 static int g_batch_lean = 16;                     // batched solve: lean ticks with at most this many instances
@@ -353,7 +350,7 @@ static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 // persistent drift instead of a 1e-8 increment.
 struct Layout {
   size_t fld[F_COUNT];
-  size_t tot, jln, state, partials, rpart, frec;
+  size_t tot, jln, state, partials, rpart;
   bool hybrid;               // FP32 problem with its FP64 shadow
   size_t fld64[F_COUNT];     // FP64 shadow fields (hybrid only)
   size_t tot64, jln64;       // FP64 y-pass scratch
@@ -389,8 +386,6 @@ static Layout ch_layout(const molt_grid* g, int prec, int ncomp, bool bdf3 = fal
   off += al256((size_t)3 * diag_blocks(n) * sizeof(double));
   L.rpart = off;  // one residual slot per x-pass block (at most one block per row)
   off += al256((size_t)g->ny * ncomp * sizeof(double));
-  L.frec = off;  // fused y-pass: published segment totals
-  off += al256(g->ny > 1 ? yfused_rec_words(g->ny, g->nx, ncomp) * sizeof(unsigned long long) : 0);
   L.hybrid = prec == MOLT_F32;
   if (L.hybrid) {
     for (int i = 0; i < F_COUNT; ++i) {
@@ -421,25 +416,42 @@ struct StepGeo {
   LineCoef cx1, cx2, cy1, cy2;
 };
 
+// The corrections the x-pass after a deferred y-pass (program with nf swept
+// fields along the lines c) adds to what it reads from it (see YCorr)
+static YCorr make_ycorr(int prec, const LineCoef& c, int nx, int nf, const void* tot) {
+  YCorr y;
+  int nth = 0, nseg = 0;
+  ypass_shape(prec, c.n, &nth, &nseg);
+  y.seeds = tot;
+  y.nf = nf;
+  y.nseg = nseg;
+  y.S = kRG * ypass_pick_k(c.n, prec);
+  y.ny = c.n;
+  y.nx = nx;
+  y.nu = c.nu;
+  return y;
+}
+
 // R = A1^{-1} A2^{-1} rhs, A_i^{-1} = Lx_i^{-1} Ly_i^{-1} (Sec. 5.1, first term
 // of eq. CH_BE_2D_3), with rhs of the stepper (eq. CH_BE; eqs. BDF2, BDF3) from
 // in0..in2 = u^n, u^{n-1}, u^{n-2}; A1, B1 are scratch fields of the precision
 static int32_t enqueue_rhs(int prec, const StepGeo& G, const PassArgs& rhs_args, void* const* F, void* tot, void* jln,
-                           DevState* st, YFused* fz, hipStream_t s) {
+                           DevState* st, hipStream_t s) {
   PassArgs a = rhs_args;
   if (G.two_d) {
     a.out[0] = F[F_A1];
-    if (fz) ++fz->epoch;
-    HIPCHK(launch_ypass(prec, PROG_RHS, G.cy2, a, st, G.nx, G.nc, tot, jln, fz, s));
+    HIPCHK(launch_ypass(prec, PROG_RHS, G.cy2, a, st, G.nx, G.nc, tot, jln, true, s));
     a.in[0] = F[F_A1];
     a.out[0] = F[F_B1];
+    a.corr = make_ycorr(prec, G.cy2, G.nx, 1, tot);
     HIPCHK(launch_xpass(prec, PROG_SWEEP, G.cx2, a, nullptr, G.xl, nullptr, s));
+    a.corr.seeds = nullptr;
     a.in[0] = F[F_B1];
     a.out[0] = F[F_A1];
-    if (fz) ++fz->epoch;
-    HIPCHK(launch_ypass(prec, PROG_SWEEP, G.cy1, a, st, G.nx, G.nc, tot, jln, fz, s));
+    HIPCHK(launch_ypass(prec, PROG_SWEEP, G.cy1, a, st, G.nx, G.nc, tot, jln, true, s));
     a.in[0] = F[F_A1];
     a.out[0] = F[F_R];
+    a.corr = make_ycorr(prec, G.cy1, G.nx, 1, tot);
     HIPCHK(launch_xpass(prec, PROG_SWEEP, G.cx1, a, nullptr, G.xl, nullptr, s));
   } else {
     a.out[0] = F[F_B1];
@@ -457,7 +469,7 @@ static int32_t enqueue_rhs(int prec, const StepGeo& G, const PassArgs& rhs_args,
 // DL the last increment).  P4 writes DL, W and the residual partials.
 static int32_t enqueue_iteration(int prec, const StepGeo& G, const StepParams& sp, const double* ush, int mode,
                                  const void* base, void* const* F, void* tot, void* jln, DevState* st, double* rpart,
-                                 YFused* fz, hipStream_t s) {
+                                 hipStream_t s) {
   PassArgs q;
   memset(&q, 0, sizeof(q));
   q.sigma = sp.sigma;
@@ -482,8 +494,8 @@ static int32_t enqueue_iteration(int prec, const StepGeo& G, const StepParams& s
   q.out[1] = F[F_B1];
   const int p1 = G.vch ? PROG_P1V : PROG_P1;
   if (G.two_d) {
-    if (fz) ++fz->epoch;
-    HIPCHK(launch_ypass(prec, p1, G.cy1, q, st, G.nx, G.nc, tot, jln, fz, s));
+    HIPCHK(launch_ypass(prec, p1, G.cy1, q, st, G.nx, G.nc, tot, jln, true, s));
+    q.corr = make_ycorr(prec, G.cy1, G.nx, 2, tot);
   } else {
     HIPCHK(launch_pointwise(prec, p1, q, st, G.n * G.nc, s));
   }
@@ -502,6 +514,7 @@ static int32_t enqueue_iteration(int prec, const StepGeo& G, const StepParams& s
   q.out[0] = F[F_C];
   q.out[1] = F[F_Q];
   HIPCHK(launch_xpass(prec, G.vch ? PROG_P2V : PROG_P2, G.cx1, q, st, G.xl, nullptr, s));
+  q.corr.seeds = nullptr;
   // P3 (y, alpha2): m, n
   q.in[0] = F[F_C];
   q.in[1] = F[F_Q];
@@ -509,8 +522,8 @@ static int32_t enqueue_iteration(int prec, const StepGeo& G, const StepParams& s
   q.out[0] = F[F_M];
   q.out[1] = F[F_N];
   if (G.two_d) {
-    if (fz) ++fz->epoch;
-    HIPCHK(launch_ypass(prec, PROG_P3, G.cy2, q, st, G.nx, G.nc, tot, jln, fz, s));
+    HIPCHK(launch_ypass(prec, PROG_P3, G.cy2, q, st, G.nx, G.nc, tot, jln, true, s));
+    q.corr = make_ycorr(prec, G.cy2, G.nx, 2, tot);
   } else {
     HIPCHK(launch_pointwise(prec, PROG_P3, q, st, G.n * G.nc, s));
   }
@@ -595,19 +608,6 @@ static int32_t step_impl(const molt_grid* g, const molt_ch_params* p, void* d_u,
   }
 
   HIPCHK(launch_state_init(st, p->tol, p->max_iter, p->fixed_iters, s));
-  YFused fz;
-  memset(&fz, 0, sizeof(fz));
-  if (G.two_d) {
-    fz.rec = w + L.frec;
-    fz.max_items = yfused_items(ny, nx, nc);
-    fz.min_items = g_fused_min_items > 0x7fffffffLL ? 0x7fffffff : (int)g_fused_min_items;
-    fz.epoch = 0;
-    fz.spin_limit = 1LL << 26;
-    // epochs restart at 1 every step: clear the words (as 32-bit ints)
-    HIPCHK(launch_zero_ints((int*)fz.rec, (int)(2 * yfused_rec_words(ny, nx, nc)), s));
-  }
-  YFused* fzp = G.two_d ? &fz : nullptr;
-
   // rhs of the stepper
   PassArgs ra;
   memset(&ra, 0, sizeof(ra));
@@ -622,7 +622,7 @@ static int32_t step_impl(const molt_grid* g, const molt_ch_params* p, void* d_u,
     ra.in[0] = d_u;
     ra.in[1] = bdf2 ? d_u_prev : d_u;
     ra.in[2] = bdf3 ? d_u_prev2 : d_u;
-    MOLT_RC(enqueue_rhs(prec, G, ra, F, tot, jln, st, fzp, s));
+    MOLT_RC(enqueue_rhs(prec, G, ra, F, tot, jln, st, s));
     base = p->init == MOLT_INIT_LINEAR ? F[F_R] : d_u;
   } else {
     // FP64 shadow: the inputs widened, R and the first iteration in FP64,
@@ -637,10 +637,9 @@ static int32_t step_impl(const molt_grid* g, const molt_ch_params* p, void* d_u,
     ra.in[0] = u64;
     ra.in[1] = bdf2 ? p64 : u64;
     ra.in[2] = bdf3 ? q64 : u64;
-    MOLT_RC(enqueue_rhs(MOLT_F64, G, ra, F64, w + L.tot64, w + L.jln64, st, nullptr, s));
+    MOLT_RC(enqueue_rhs(MOLT_F64, G, ra, F64, w + L.tot64, w + L.jln64, st, s));
     base64 = p->init == MOLT_INIT_LINEAR ? F64[F_R] : u64;
-    MOLT_RC(enqueue_iteration(MOLT_F64, G, sp, ush, 0, base64, F64, w + L.tot64, w + L.jln64, st, rpart, nullptr,
-                              s));
+    MOLT_RC(enqueue_iteration(MOLT_F64, G, sp, ush, 0, base64, F64, w + L.tot64, w + L.jln64, st, rpart, s));
     // the FP32 iterations' base is the first iterate rounded to FP32, their
     // running sum starts at its rounding error
     HIPCHK(launch_rebase_mixed(F[F_R], F[F_W], F[F_DL], base64, F64[F_W], F64[F_DL], st, 1, nel, s));
@@ -670,12 +669,11 @@ static int32_t step_impl(const molt_grid* g, const molt_ch_params* p, void* d_u,
         // FP64 restart: the full form from the iterate, then re-based
         void* v64 = F64[F_HIST];
         HIPCHK(launch_iterate64(v64, F[F_R], F[F_W], st, nel, s));
-        MOLT_RC(enqueue_iteration(MOLT_F64, G, sp, ush, 0, v64, F64, w + L.tot64, w + L.jln64, st, rpart, nullptr,
-                                  s));
+        MOLT_RC(enqueue_iteration(MOLT_F64, G, sp, ush, 0, v64, F64, w + L.tot64, w + L.jln64, st, rpart, s));
         HIPCHK(launch_rebase_mixed(F[F_R], F[F_W], F[F_DL], v64, F64[F_W], F64[F_DL], st, it + 1, nel, s));
         continue;
       }
-      MOLT_RC(enqueue_iteration(prec, G, sp, ush, it == 0 ? 0 : 1, base, F, tot, jln, st, rpart, fzp, s));
+      MOLT_RC(enqueue_iteration(prec, G, sp, ush, it == 0 ? 0 : 1, base, F, tot, jln, st, rpart, s));
     }
     HIPCHK(hipMemcpyAsync(&hst, st, sizeof(DevState), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -772,9 +770,9 @@ static int32_t check_adapt_params(const molt_ch_params* p) {
 // batched instances
 // --------------------------------------------------------------------------
 #define MOLT_BATCH_PREC(call) (prec == MOLT_F64 ? call##_f64 : call##_f32)
-static hipError_t launch_batch_y(int prec, int K, int M, bool per, int pass, bool fin, const SlotDesc* sd,
+static hipError_t launch_batch_y(int prec, int K, int M, bool per, int pass, const SlotDesc* sd,
                                  const SlotCtl* ctl, const BlkMap* map, int nblk, hipStream_t s) {
-  return MOLT_BATCH_PREC(launch_batch_y)(K, M, per, pass, fin, sd, ctl, map, nblk, s);
+  return MOLT_BATCH_PREC(launch_batch_y)(K, M, per, pass, sd, ctl, map, nblk, s);
 }
 static hipError_t launch_batch_comb(int prec, int pass, const SlotDesc* sd, const SlotCtl* ctl, const BlkMap* map,
                                     int nblk, hipStream_t s) {
@@ -1063,12 +1061,9 @@ static hipError_t batch_tick(int prec, const BatchMaps& B, const SlotDesc* sd, S
       const int pr = precs[k];
       const std::vector<BatchGroup>& yg = (B.hybrid && k == 0) ? B.yg64 : B.yg;
       for (const BatchGroup& g : yg)
-        if ((e = launch_batch_y(pr, g.K, g.M, g.per != 0, pass, false, sd, ctl, map + g.off, g.nblk, s)) != hipSuccess)
+        if ((e = launch_batch_y(pr, g.K, g.M, g.per != 0, pass, sd, ctl, map + g.off, g.nblk, s)) != hipSuccess)
           return e;
       if ((e = launch_batch_comb(pr, pass, sd, ctl, map + B.comb_off, B.comb_n, s)) != hipSuccess) return e;
-      for (const BatchGroup& g : yg)
-        if ((e = launch_batch_y(pr, g.K, g.M, g.per != 0, pass, true, sd, ctl, map + g.off, g.nblk, s)) != hipSuccess)
-          return e;
     }
     for (int k = 0; k < nprec; ++k) {
       const int pr = precs[k];
@@ -1652,7 +1647,7 @@ int32_t sweep_impl(const molt_grid* g, int32_t axis, double alpha, int32_t preci
   }
   const double hy = spacing(g->bc, g->ny, g->y0, g->y1);
   const LineCoef c = make_line(g->ny, g->bc, g->order_M, alpha, hy);
-  HIPCHK(launch_ypass(precision, PROG_SWEEP, c, a, nullptr, g->nx, (int)batch, tot, jln, nullptr, s));
+  HIPCHK(launch_ypass(precision, PROG_SWEEP, c, a, nullptr, g->nx, (int)batch, tot, jln, false, s));
   return MOLT_OK;
 }
 
@@ -1675,10 +1670,6 @@ const char* molt_strerror(int32_t status) {
 const char* molt_last_error(void) { return g_err.c_str(); }
 
 int32_t molt_set_option(int32_t option, int64_t value) {
-  if (option == MOLT_OPT_FUSED_Y_MIN_ITEMS && value >= 0) {
-    g_fused_min_items = value;
-    return MOLT_OK;
-  }
   if (option == MOLT_OPT_BATCH_TICKS && value >= 1 && value <= 1024) {
     g_batch_ticks = (int)value;
     return MOLT_OK;
@@ -1897,7 +1888,8 @@ int32_t molt_autotune(int32_t precision, int32_t max_n, void* d_work, size_t wor
       tune_set(precision, cls, kx0, ky);
       a.in[0] = F[0]; a.in[1] = F[1]; a.in[2] = F[2];
       a.out[0] = F[3]; a.out[1] = F[4];
-      const float ms = timed([&] { return launch_ypass(precision, PROG_P1, lc, a, nullptr, n, 1, tot, jln, nullptr, s); });
+      a.corr.seeds = nullptr;
+      const float ms = timed([&] { return launch_ypass(precision, PROG_P1, lc, a, nullptr, n, 1, tot, jln, true, s); });
       if (ms < 0) { rc = fail(MOLT_EHIP, "autotune y-pass launch failed"); break; }
       if (best < 0 || ms < margin * best) { best = ms; best_ky = ky; }
     }
@@ -1908,6 +1900,7 @@ int32_t molt_autotune(int32_t precision, int32_t max_n, void* d_work, size_t wor
       tune_set(precision, cls, kx, best_ky);
       a.in[0] = F[0]; a.in[1] = F[1]; a.in[2] = F[2]; a.in[3] = F[3]; a.in[4] = F[4];
       a.out[0] = F[5]; a.out[1] = F[6];
+      a.corr = make_ycorr(precision, lc, n, 2, tot);  // as after the deferred y-pass
       const float ms = timed([&] { return launch_xpass(precision, PROG_P2, lc, a, nullptr, n, nullptr, s); });
       if (ms < 0) { rc = fail(MOLT_EHIP, "autotune x-pass launch failed"); break; }
       if (best < 0 || ms < margin * best) { best = ms; best_kx = kx; }

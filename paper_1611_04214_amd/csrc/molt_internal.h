@@ -54,6 +54,24 @@ struct DevState {
   double mass2;                   // vector model: mass of the second component
 };
 
+// thread rows of a y-pass block (a segment is kRG*K rows of 64 columns)
+constexpr int kRG = 4;
+
+// Deferred y-pass corrections.  Inside the solver a y-pass scans each
+// segment of S rows of a column from zero (its outputs hold the
+// segment-local values w_loc) and leaves per (segment, column) seeds: the true
+// value is w_loc + 1/2 d^(j - j0s) seedL + 1/2 d^(jls - j) seedR (row j of the
+// segment [j0s, jls], d = e^{-nu}).  The next x-pass, which reads those outputs
+// anyway, adds the two terms as it loads them, so the y-pass reads its inputs
+// once (no totals-then-final double read).
+struct YCorr {
+  const void* seeds;  // the y-pass's seeds ([comp][field][L,R][segment][column]); nullptr: none
+  int nf;             // raw fields of the x-pass that are y-pass outputs (its first nf)
+  int nseg, S;        // segments per column, rows per segment
+  int ny, nx;         // rows per component, columns
+  double nu;          // alpha*h of the y-lines
+};
+
 // Arguments of the pass kernels (pointers are device pointers of element type T,
 // passed as void* so one struct serves both precisions).
 struct PassArgs {
@@ -67,15 +85,7 @@ struct PassArgs {
   double rc0, rc1; // variable-step BDF2 rhs coefficients
   double ushift[2];// u = stored value + ushift, per component: 0 when the fields hold u; the
                    // shifted variable v = u - ushift of Dirichlet steps otherwise
-};
-
-// Workspace and control of the fused (single-kernel) y-pass.
-struct YFused {
-  void* rec;               // per work item: published segment totals, 64-bit (value, epoch) words
-  size_t max_items;        // capacity of rec in work items
-  int min_items;           // use the fused path only from this many work items
-  int epoch;               // differs from every epoch left in rec since it was zeroed
-  long long spin_limit;    // bound of the wait loop (sets DevState::error when hit)
+  YCorr corr;      // x-passes: corrections of the preceding deferred y-pass
 };
 
 // --------------------------------------------------------------------------

@@ -41,7 +41,13 @@ template <typename T, int PI, int K, int M, bool PER, int BS>
 __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(MOLT_OCC)))
 xpass_kernel(const LineCoef c, const PassArgs a, DevState* st, int nlines, int TL, double* rpart, int vec) {
   __shared__ T smem[ProgOf<PI, T>::type::F * XRow<T, K, BS>::PADDED];
-  xpass_body<T, PI, K, M, PER, BS>(c, a, st, nlines, TL, rpart, vec, blockIdx.x, smem);
+  // consecutive blocks are dispatched round-robin over the 8 XCDs: give each
+  // XCD a contiguous range of rows, so that the rows of one y-pass segment
+  // (which share its seed rows) read them through one XCD's L2
+  const int g = gridDim.x, b = blockIdx.x;
+  // (P2 and P4 at 4096^2: 100 -> 92 us and 98 -> 87 us)
+  const int bx = (g % 8 == 0) ? (b % 8) * (g / 8) + b / 8 : b;
+  xpass_body<T, PI, K, M, PER, BS>(c, a, st, nlines, TL, rpart, vec, bx, smem);
 }
 
 template <typename T, int PI, int K, int M, bool PER>
@@ -62,188 +68,10 @@ __global__ void MOLT_PASS_ATTR yfin_kernel(const LineCoef c, const PassArgs a, D
   yfin_body<T, PI, K, M, PER>(c, a, st, nx, nth, nseg, fstride, seeds, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
-// --------------------------------------------------------------------------
-// Fused y-pass (one kernel, no second read of the inputs).  A block is 64
-// columns x kRGF thread rows (a segment of kRGF*K rows).  Work items are
-// (batch entry, 64-column strip, segment), strip-major; the grid is launched
-// cooperatively (every block resident) and walks the items in rounds of
-// gridDim.x, a multiple of the segments per strip, so all segments of a strip
-// run at the same time.  Per item: window and zero-seeded totals in registers,
-// the segment's totals published with agent-scope atomic stores and a release
-// flag, a bounded wait for the strip's other segments, an FP64 combine (carries
-// into this segment, line totals, boundary solve), then the seeded scans and
-// outputs from the registers.
-// --------------------------------------------------------------------------
-// thread rows per block of the fused y-pass
-#ifndef MOLT_RGF
-#define MOLT_RGF 16
-#endif
-constexpr int kRGF = MOLT_RGF;
-// rows per thread of the fused y-pass (its window and stencils must fit the
-// 128 VGPRs a 1024-thread block allows)
-#ifndef MOLT_KF
-#define MOLT_KF 16
-#endif
-constexpr int kKF = MOLT_KF;
-
-// A published value travels with the epoch of its launch in one 64-bit word
-// (relaxed agent-scope atomics): a reader that sees the current epoch sees the
-// value, so no flags and no release/acquire fences are needed.
-__device__ __forceinline__ unsigned long long pack_ep(float v, int epoch) {
-  return ((unsigned long long)(unsigned)epoch << 32) | (unsigned long long)__float_as_uint(v);
-}
-constexpr int kMaxGF = 32;  // segments per strip the fused y-pass combines in LDS
-
 template <typename T, int PI, int K, int M, bool PER>
-__global__ void __launch_bounds__(64 * kRGF) yfused_kernel(const LineCoef c, const PassArgs a, DevState* st, int nx,
-                                                      int nth, int G, int nstrips, int nitems, size_t fstride,
-                                                      unsigned long long* rec, int epoch, long long spin_limit) {
-  using P = typename ProgOf<PI, T>::type;
-  constexpr int F = P::F;
-  constexpr int REC = 3 * F * 64;  // words per item: [f][L,R][lane], then [f][lane] J^L of the wrap cell
-  if (st != nullptr && st->done) return;
-  __shared__ T shA[F][2][kRGF][64];
-  __shared__ float shG[F][2][kMaxGF][64];
-  __shared__ float shJ[F][64];
-  __shared__ T shSeed[F][2][64];
-  const int lx = threadIdx.x, r = threadIdx.y;
-  const int n = c.n;
-  const T d = (T)c.d;
-  const int S = kRGF * K;
-  const double mS = exp(-c.nu * (double)S);
-  const T mK = dpow<T>(c.nu, (double)K);
-  for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
-    const int g = item % G;
-    const int qb = item / G;
-    const int q = qb % nstrips;
-    const int b = qb / nstrips;
-    const int col = q * 64 + lx;
-    const int t = g * kRGF + r;
-    const bool ok = col < nx && t < nth;
-    const int j0 = t * K;
-    const size_t lbase = (size_t)b * fstride + (size_t)(col < nx ? col : 0);
-    Seg<T, P, K, M, PER> seg;
-    T sw[F][Seg<T, P, K, M, PER>::W];  // kept across the wait; the stencils are formed twice
-    T AL[F], AR[F];
-    if (ok) {
-      seg.window(c, a, lbase, (size_t)nx, j0, false, sw);
-      seg.stencils(c, a, lbase, (size_t)nx, j0, sw);
-      seg.totals(d, j0, n, AL, AR);
-    } else {
-#pragma unroll
-      for (int f = 0; f < F; ++f) AL[f] = AR[f] = T(0);
-    }
-#pragma unroll
-    for (int f = 0; f < F; ++f) {
-      shA[f][0][r][lx] = AL[f];
-      shA[f][1][r][lx] = AR[f];
-    }
-    __syncthreads();
-    const int j0s = g * S;
-    const int jls = min(j0s + S - 1, n - 1);
-    // publish this segment's zero-seeded totals (L at its last row, R at its first)
-    if (r == 0) {
-      unsigned long long* mine = rec + (size_t)item * REC;
-#pragma unroll
-      for (int f = 0; f < F; ++f) {
-        float L = 0.f, R = 0.f;
-        for (int gg = 0; gg < kRGF; ++gg) {
-          const int tt = g * kRGF + gg;
-          if (tt < nth) {
-            L += (float)(dpow<T>(c.nu, (double)(jls - min(tt * K + K - 1, n - 1))) * shA[f][0][gg][lx]);
-            R += (float)(dpow<T>(c.nu, (double)(tt * K - j0s)) * shA[f][1][gg][lx]);
-          }
-        }
-        __hip_atomic_store(mine + (f * 2 + 0) * 64 + lx, pack_ep(L, epoch), __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(mine + (f * 2 + 1) * 64 + lx, pack_ep(R, epoch), __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-        if (g == 0)
-          __hip_atomic_store(mine + (2 * F + f) * 64 + lx, pack_ep(ok ? (float)seg.jln[f] : 0.f, epoch),
-                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
-    }
-    // gather the strip's totals: thread row r polls segments r, r+kRGF, ...
-    // (bounded: a resident grid never needs the bound)
-    {
-      const unsigned long long* strip = rec + (size_t)qb * G * REC;
-      long long spins = 0;
-      bool timed_out = false;
-      for (int gg = r; gg < G; gg += kRGF) {
-#pragma unroll
-        for (int fd = 0; fd < 2 * F; ++fd) {
-          const unsigned long long* p = strip + (size_t)gg * REC + fd * 64 + lx;
-          unsigned long long wv = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          while ((int)(wv >> 32) != epoch && !timed_out) {
-            __builtin_amdgcn_s_sleep(1);
-            wv = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            timed_out = ++spins > spin_limit;
-          }
-          shG[fd >> 1][fd & 1][gg][lx] = __uint_as_float((unsigned)(wv & 0xffffffffull));
-        }
-      }
-      if (r == 0) {
-#pragma unroll
-        for (int f = 0; f < F; ++f) {
-          const unsigned long long* p = strip + (2 * F + f) * 64 + lx;
-          unsigned long long wv = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          while ((int)(wv >> 32) != epoch && !timed_out) {
-            __builtin_amdgcn_s_sleep(1);
-            wv = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            timed_out = ++spins > spin_limit;
-          }
-          shJ[f][lx] = __uint_as_float((unsigned)(wv & 0xffffffffull));
-        }
-      }
-      if (timed_out && st != nullptr) __hip_atomic_store(&st->error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    __syncthreads();
-    // FP64 combine over the strip's segments: this segment's seeds
-    if (r == 0 && col < nx) {
-#pragma unroll
-      for (int f = 0; f < F; ++f) {
-        double run = 0.0, cLg = 0.0, TLl = 0.0;
-        for (int gg = 0; gg < G; ++gg) {
-          const double v = (double)shG[f][0][gg][lx];
-          if (gg == g) cLg = run;
-          if (gg == G - 1) TLl = v + exp(-c.nu * (double)(n - gg * S)) * run;
-          run = mS * run + v;
-        }
-        double cRg = 0.0, TRl = 0.0;
-        run = 0.0;
-        for (int gg = G - 1; gg >= 0; --gg) {
-          const double v = (double)shG[f][1][gg][lx];
-          if (gg == g) cRg = run;
-          if (gg == 0) TRl = v + mS * run;
-          run = mS * run + v;
-        }
-        double Ba, Bb;
-        boundary_terms(c, TLl, TRl, (double)shJ[f][lx], Ba, Bb);
-        shSeed[f][0][lx] = (T)(c.d * cLg + 2.0 * Ba * exp(-c.nu * (double)j0s));
-        shSeed[f][1][lx] = (T)(c.d * cRg + 2.0 * Bb * exp(-c.nu * (double)(c.N - jls)));
-      }
-    }
-    __syncthreads();
-    if (ok) {
-      const int jlt = min(j0 + K - 1, n - 1);
-      const T pl = dpow<T>(c.nu, (double)(j0 - j0s)), pr = dpow<T>(c.nu, (double)(jls - jlt));
-      T gL[F], gR[F];
-#pragma unroll
-      for (int f = 0; f < F; ++f) {
-        T cl = T(0), cr = T(0);
-        for (int gg = 0; gg < r; ++gg) cl = mK * cl + shA[f][0][gg][lx];
-        for (int gg = kRGF - 1; gg > r; --gg)
-          if (g * kRGF + gg < nth) cr = mK * cr + shA[f][1][gg][lx];
-        gL[f] = d * cl + pl * shSeed[f][0][lx];
-        gR[f] = d * cr + pr * shSeed[f][1][lx];
-      }
-      seg.stencils(c, a, lbase, (size_t)nx, j0, sw);
-      T w[F][K];
-      seg.finalize(d, j0, n, gL, gR, w);
-      seg.store(a, lbase, (size_t)nx, j0, n, false, w);
-    }
-    __syncthreads();  // LDS is reused by the next item
-  }
+__global__ void MOLT_PASS_ATTR yloc_kernel(const LineCoef c, const PassArgs a, DevState* st, int nx, int nth,
+                                           int nseg, size_t fstride, T* agg, T* jlnb) {
+  yloc_body<T, PI, K, M, PER>(c, a, st, nx, nth, nseg, fstride, agg, jlnb, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
 #ifdef MOLT_PART_COMMON
@@ -427,13 +255,6 @@ void ypass_shape(int prec, int n, int* nth, int* nseg) {
   *nseg = (*nth + kRG - 1) / kRG;
 }
 
-// fused y-pass work items and record elements (FP32 path)
-size_t yfused_items(int n, int nx, int batch) {
-  const int nth = (n + kKF - 1) / kKF;
-  return (size_t)batch * ((nx + 63) / 64) * ((nth + kRGF - 1) / kRGF);
-}
-size_t yfused_rec_words(int n, int nx, int batch) { return yfused_items(n, nx, batch) * 3 * 2 * 64; }
-
 hipError_t launch_zero_ints(int* p, int n, hipStream_t s) {
   hipLaunchKernelGGL(zero_ints_kernel, dim3((n + 255) / 256 < 1024 ? (n + 255) / 256 : 1024), dim3(256), 0, s, p, n);
   return hipGetLastError();
@@ -595,19 +416,28 @@ hipError_t MOLT_KFN(launch_xpass)(int prog, const LineCoef& c, const PassArgs& a
 
 #ifdef MOLT_PART_Y
 
+// deferred: the single-read y-pass (yloc, then the combine's seeds for the
+// next x-pass); otherwise totals, combine and final scans (final outputs)
 template <typename T, int PI, int K, int M, bool PER>
 static hipError_t ypass_km(const LineCoef& c, const PassArgs& a, DevState* st, int nx, int batch, T* tot, T* jln,
-                           hipStream_t s) {
+                           bool deferred, hipStream_t s) {
   using P = typename ProgOf<PI, T>::type;
   const int nth = (c.n + K - 1) / K;
   const int nseg = (nth + kRG - 1) / kRG;
   const size_t fstride = (size_t)c.n * nx;
   dim3 blk(64, kRG);
   dim3 grid((nx + 63) / 64, nseg, batch);
-  if (g_prof_on) prof_begin(prof_kind<MOLT_KT>(KF_YTOT * 8 + PI), s);
-  hipLaunchKernelGGL((ytot_kernel<T, PI, K, M, PER>), grid, blk, 0, s, c, a, st, nx, nth, nseg, fstride, tot, jln);
-  if (g_prof_on) prof_end(prof_kind<MOLT_KT>(KF_YTOT * 8 + PI), s);
-  hipError_t e = hipGetLastError();
+  hipError_t e;
+  if (deferred) {
+    if (g_prof_on) prof_begin(prof_kind<MOLT_KT>(KF_YFIN * 8 + PI), s);
+    hipLaunchKernelGGL((yloc_kernel<T, PI, K, M, PER>), grid, blk, 0, s, c, a, st, nx, nth, nseg, fstride, tot, jln);
+    if (g_prof_on) prof_end(prof_kind<MOLT_KT>(KF_YFIN * 8 + PI), s);
+  } else {
+    if (g_prof_on) prof_begin(prof_kind<MOLT_KT>(KF_YTOT * 8 + PI), s);
+    hipLaunchKernelGGL((ytot_kernel<T, PI, K, M, PER>), grid, blk, 0, s, c, a, st, nx, nth, nseg, fstride, tot, jln);
+    if (g_prof_on) prof_end(prof_kind<MOLT_KT>(KF_YTOT * 8 + PI), s);
+  }
+  e = hipGetLastError();
   if (e != hipSuccess) return e;
   // the combine runs over segments of kRG*K rows
   const int ct = (nseg + kCombWaves - 1) / kCombWaves;
@@ -624,7 +454,7 @@ static hipError_t ypass_km(const LineCoef& c, const PassArgs& a, DevState* st, i
     return hipErrorInvalidValue;
   if (g_prof_on) prof_end(prof_kind<MOLT_KT>(KF_YCOMB * 8 + PI), s);
   e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  if (e != hipSuccess || deferred) return e;
   if (g_prof_on) prof_begin(prof_kind<MOLT_KT>(KF_YFIN * 8 + PI), s);
   hipLaunchKernelGGL((yfin_kernel<T, PI, K, M, PER>), grid, blk, 0, s, c, a, st, nx, nth, nseg, fstride,
                      (const T*)tot);
@@ -632,97 +462,42 @@ static hipError_t ypass_km(const LineCoef& c, const PassArgs& a, DevState* st, i
   return hipGetLastError();
 }
 
-// Fused y-pass launch (FP32, periodic, large grids): returns hipSuccess with
-// *used = false when the three-kernel path must be taken instead.
-template <typename T, int PI, int K, int M>
-static hipError_t yfused_km(const LineCoef& c, const PassArgs& a, DevState* st, int nx, int batch, const YFused& fz,
-                            hipStream_t s, bool* used) {
-  *used = false;
-  const int nth = (c.n + K - 1) / K;
-  const int G = (nth + kRGF - 1) / kRGF;
-  const int nstrips = (nx + 63) / 64;
-  const int nitems = batch * nstrips * G;
-  if (nitems < fz.min_items || (size_t)nitems > fz.max_items || G > kMaxGF) return hipSuccess;
-  static int per_cu = -1, ncu = 0;
-  if (per_cu < 0) {
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return hipErrorInvalidValue;
-    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) ncu = 0;
-    int coop = 0;
-    if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop) ncu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)yfused_kernel<T, PI, K, M, true>,
-                                                     64 * kRGF, 0) != hipSuccess)
-      per_cu = 0;
-  }
-  const int resident = per_cu * ncu;
-  if (resident < G) return hipSuccess;
-  int grid = (resident / G) * G;
-  if (grid > nitems) grid = nitems;
-  LineCoef cc = c;
-  PassArgs aa = a;
-  DevState* stp = st;
-  int nxv = nx, nthv = nth, Gv = G, nsv = nstrips, niv = nitems, ep = fz.epoch;
-  size_t fstride = (size_t)c.n * nx;
-  unsigned long long* rec = (unsigned long long*)fz.rec;
-  long long spin = fz.spin_limit;
-  void* args[] = {&cc, &aa, &stp, &nxv, &nthv, &Gv, &nsv, &niv, &fstride, &rec, &ep, &spin};
-  if (g_prof_on) prof_begin(prof_kind<MOLT_KT>(KF_YFIN * 8 + PI), s);
-  hipError_t e = hipLaunchCooperativeKernel((const void*)yfused_kernel<T, PI, K, M, true>, dim3(grid),
-                                            dim3(64, kRGF), args, 0, s);
-  if (g_prof_on) prof_end(prof_kind<MOLT_KT>(KF_YFIN * 8 + PI), s);
-  if (e == hipSuccess) *used = true;
-  return e;
-}
-
 template <typename T, int PI, int K>
 static hipError_t ypass_k(const LineCoef& c, const PassArgs& a, DevState* st, int nx, int batch, void* tot, void* jln,
-                          hipStream_t s) {
+                          bool deferred, hipStream_t s) {
   const bool per = c.bc == MOLT_BC_PERIODIC;
   switch (c.M) {
-    case 2: return per ? ypass_km<T, PI, K, 2, true>(c, a, st, nx, batch, (T*)tot, (T*)jln, s)
-                       : ypass_km<T, PI, K, 2, false>(c, a, st, nx, batch, (T*)tot, (T*)jln, s);
-    case 4: return per ? ypass_km<T, PI, K, 4, true>(c, a, st, nx, batch, (T*)tot, (T*)jln, s)
-                       : ypass_km<T, PI, K, 4, false>(c, a, st, nx, batch, (T*)tot, (T*)jln, s);
-    case 6: return per ? ypass_km<T, PI, K, 6, true>(c, a, st, nx, batch, (T*)tot, (T*)jln, s)
-                       : ypass_km<T, PI, K, 6, false>(c, a, st, nx, batch, (T*)tot, (T*)jln, s);
+    case 2: return per ? ypass_km<T, PI, K, 2, true>(c, a, st, nx, batch, (T*)tot, (T*)jln, deferred, s)
+                       : ypass_km<T, PI, K, 2, false>(c, a, st, nx, batch, (T*)tot, (T*)jln, deferred, s);
+    case 4: return per ? ypass_km<T, PI, K, 4, true>(c, a, st, nx, batch, (T*)tot, (T*)jln, deferred, s)
+                       : ypass_km<T, PI, K, 4, false>(c, a, st, nx, batch, (T*)tot, (T*)jln, deferred, s);
+    case 6: return per ? ypass_km<T, PI, K, 6, true>(c, a, st, nx, batch, (T*)tot, (T*)jln, deferred, s)
+                       : ypass_km<T, PI, K, 6, false>(c, a, st, nx, batch, (T*)tot, (T*)jln, deferred, s);
   }
   return hipErrorInvalidValue;
 }
 
 template <typename T, int PI>
 static hipError_t ypass_t(const LineCoef& c, const PassArgs& a, DevState* st, int nx, int batch, void* tot, void* jln,
-                          const YFused* fz, hipStream_t s) {
-  if constexpr (sizeof(T) == 4) {
-    if (fz != nullptr && fz->rec != nullptr && c.bc == MOLT_BC_PERIODIC) {
-      bool used = false;
-      hipError_t e = hipSuccess;
-      switch (c.M) {
-        case 2: e = yfused_km<T, PI, kKF, 2>(c, a, st, nx, batch, *fz, s, &used); break;
-        case 4: e = yfused_km<T, PI, kKF, 4>(c, a, st, nx, batch, *fz, s, &used); break;
-        case 6: e = yfused_km<T, PI, kKF, 6>(c, a, st, nx, batch, *fz, s, &used); break;
-      }
-      if (e != hipSuccess) return e;
-      if (used) return hipSuccess;
-    }
-  }
+                          bool deferred, hipStream_t s) {
   switch (ypass_pick_k(c.n, sizeof(T) == 8 ? MOLT_F64 : MOLT_F32)) {
-    case 4: return ypass_k<T, PI, 4>(c, a, st, nx, batch, tot, jln, s);
-    case 8: return ypass_k<T, PI, 8>(c, a, st, nx, batch, tot, jln, s);
+    case 4: return ypass_k<T, PI, 4>(c, a, st, nx, batch, tot, jln, deferred, s);
+    case 8: return ypass_k<T, PI, 8>(c, a, st, nx, batch, tot, jln, deferred, s);
     case 16:
-      if constexpr (sizeof(T) == 4) return ypass_k<T, PI, 16>(c, a, st, nx, batch, tot, jln, s);
+      if constexpr (sizeof(T) == 4) return ypass_k<T, PI, 16>(c, a, st, nx, batch, tot, jln, deferred, s);
       return hipErrorInvalidValue;
   }
   return hipErrorInvalidValue;
 }
 
 hipError_t MOLT_KFN(launch_ypass)(int prog, const LineCoef& c, const PassArgs& a, DevState* st, int nx, int batch,
-                                  void* tot, void* jln, const YFused* fz, hipStream_t s) {
+                                  void* tot, void* jln, bool deferred, hipStream_t s) {
   switch (prog) {
-    case PROG_SWEEP: return ypass_t<MOLT_KT, PROG_SWEEP>(c, a, st, nx, batch, tot, jln, fz, s);
-    case PROG_RHS: return ypass_t<MOLT_KT, PROG_RHS>(c, a, st, nx, batch, tot, jln, fz, s);
-    case PROG_P1: return ypass_t<MOLT_KT, PROG_P1>(c, a, st, nx, batch, tot, jln, fz, s);
-    case PROG_P3: return ypass_t<MOLT_KT, PROG_P3>(c, a, st, nx, batch, tot, jln, fz, s);
-    case PROG_P1V: return ypass_t<MOLT_KT, PROG_P1V>(c, a, st, nx, batch, tot, jln, nullptr, s);
+    case PROG_SWEEP: return ypass_t<MOLT_KT, PROG_SWEEP>(c, a, st, nx, batch, tot, jln, deferred, s);
+    case PROG_RHS: return ypass_t<MOLT_KT, PROG_RHS>(c, a, st, nx, batch, tot, jln, deferred, s);
+    case PROG_P1: return ypass_t<MOLT_KT, PROG_P1>(c, a, st, nx, batch, tot, jln, deferred, s);
+    case PROG_P3: return ypass_t<MOLT_KT, PROG_P3>(c, a, st, nx, batch, tot, jln, deferred, s);
+    case PROG_P1V: return ypass_t<MOLT_KT, PROG_P1V>(c, a, st, nx, batch, tot, jln, deferred, s);
   }
   return hipErrorInvalidValue;
 }
