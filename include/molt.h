@@ -401,9 +401,16 @@ int32_t molt_profile_read(molt_prof_entry* out, int32_t max_entries);
  *    only (no step finish): fewer launches per iteration for the last long
  *    instances, while an instance that converged waits for the round's end
  *    to start its next step.  Results are unchanged. */
+/*  MOLT_OPT_STEP_GRAPH (0 or 1, default 1): in ch_step, ch_solve and the
+ *    drivers built on them, launch runs of 4 increment-form iterations as one
+ *    executable HIP graph, captured on a private stream of the library the
+ *    first time a run with those arguments is needed and kept (at most 8 per
+ *    process, least recently used replaced); off while kernel timing is on.
+ *    0 launches every kernel on the caller's stream.  Results are unchanged. */
 #define MOLT_OPT_BATCH_TICKS 2
 #define MOLT_OPT_BATCH_GRAPH 3
 #define MOLT_OPT_BATCH_LEAN 5
+#define MOLT_OPT_STEP_GRAPH 6
 int32_t molt_set_option(int32_t option, int64_t value);
 
 /* Static name of a status code. */

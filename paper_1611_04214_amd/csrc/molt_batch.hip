@@ -334,7 +334,7 @@ __global__ void __launch_bounds__(256) rebase_batch_kernel(const SlotDesc* __res
       const float b = (float)v;
       base[i] = b;
       W[i] = (float)(v - (double)b);
-      ((float*)d.fld[F_DL])[i] = (float)((const double*)d.fld64[F_DL])[i];
+      ((float*)d.fld[F_DL])[i] = (float)((const double*)d.fld64[F_W])[i];  // full form: DL = W
     } else {
       ((double*)d.fld64[F_HIST])[i] = (double)base[i] + (double)W[i];
     }

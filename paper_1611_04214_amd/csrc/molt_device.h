@@ -319,12 +319,21 @@ __device__ __forceinline__ void st1_out(T* p, T v) {
 // 1/2 d^(jls - j) and the seed rows of the row's segment.
 template <typename T>
 struct RowCorr {
-  const T* sL[2];
-  const T* sR[2];
+  // seed rows of fields 0 and 1 (named members, not arrays: a field index the
+  // compiler cannot resolve then selects a register instead of indexing the
+  // object in scratch memory)
+  const T* sL0;
+  const T* sL1;
+  const T* sR0;
+  const T* sR1;
   T cL, cR;
   int nf;  // 0: nothing to correct
+  __device__ __forceinline__ const T* seedL(int f) const { return f == 0 ? sL0 : sL1; }
+  __device__ __forceinline__ const T* seedR(int f) const { return f == 0 ? sR0 : sR1; }
   __device__ void init(const YCorr& yc, int line) {
     nf = yc.seeds != nullptr ? yc.nf : 0;
+    sL0 = sL1 = sR0 = sR1 = nullptr;
+    cL = cR = T(0);
     if (nf == 0) return;
     const int b = line / yc.ny, j = line - b * yc.ny;
     const int seg = j / yc.S;
@@ -333,19 +342,19 @@ struct RowCorr {
     cL = T(0.5) * dpow<T>(yc.nu, (double)(j - j0s));
     cR = T(0.5) * dpow<T>(yc.nu, (double)(jls - j));
     const size_t plane = (size_t)yc.nseg * yc.nx;
-#pragma unroll
-    for (int f = 0; f < 2; ++f) {
-      const T* base = (const T*)yc.seeds + ((size_t)(b * yc.nf + (f < yc.nf ? f : 0)) * 2) * plane + (size_t)seg * yc.nx;
-      sL[f] = base;
-      sR[f] = base + plane;
-    }
+    const T* base0 = (const T*)yc.seeds + ((size_t)(b * yc.nf) * 2) * plane + (size_t)seg * yc.nx;
+    const T* base1 = (const T*)yc.seeds + ((size_t)(b * yc.nf + (yc.nf > 1 ? 1 : 0)) * 2) * plane + (size_t)seg * yc.nx;
+    sL0 = base0;
+    sR0 = base0 + plane;
+    sL1 = base1;
+    sR1 = base1 + plane;
   }
   // raw values r of column col (fields f < nf corrected)
   template <int NR>
   __device__ __forceinline__ void apply(int col, T* r) const {
 #pragma unroll
     for (int f = 0; f < (NR < 2 ? NR : 2); ++f)
-      if (f < nf) r[f] += cL * sL[f][col] + cR * sR[f][col];
+      if (f < nf) r[f] += cL * seedL(f)[col] + cR * seedR(f)[col];
   }
 };
 
@@ -368,7 +377,9 @@ struct Seg {
   __device__ void build(const LineCoef& c, const PassArgs& a, size_t lbase, size_t stride, int j0, bool vec) {
     T s[F][W];
     window(c, a, lbase, stride, j0, vec, s);
-    stencils(c, a, lbase, stride, j0, s);
+    RowCorr<T> none;
+    none.nf = 0;
+    stencils(c, a, lbase, stride, j0, s, none);
   }
 
   // swept values on nodes j0-H .. j0+K+H-1 (and the kept values of the owned nodes)
@@ -430,8 +441,8 @@ struct Seg {
 
   // J^L, J^R on the owned nodes from the window values s (nodes j0-H ..
   // j0+K+H-1); boundary nodes of non-periodic lines are redone in FP64
-  __device__ void stencils(const LineCoef& c, const PassArgs& a, size_t lbase, size_t stride, int j0,
-                           const T (&s)[F][W], const RowCorr<T>* rc = nullptr) {
+  __device__ __attribute__((always_inline)) void stencils(const LineCoef& c, const PassArgs& a, size_t lbase, size_t stride, int j0,
+                           const T (&s)[F][W], const RowCorr<T>& rc) {
     const int n = c.n;
     constexpr bool per = PER;
     T wl[M + 1], wr[M + 1];
@@ -469,9 +480,9 @@ struct Seg {
   // FP64 and only the result is rounded to T.  The in-range window values are
   // reloaded here (only the threads at the two ends of a line get here), so
   // the window array of the interior path is not kept alive.
-  // (rc: the x-pass's row corrections, applied to every reloaded value)
-  __device__ void boundary_nodes(const LineCoef& c, const PassArgs& a, size_t lbase, size_t stride, int j0,
-                                 const RowCorr<T>* rc) {
+  // (rc: the x-pass's row corrections, applied to every reloaded value; nf = 0 for none)
+  __device__ __attribute__((always_inline)) void boundary_nodes(const LineCoef& c, const PassArgs& a, size_t lbase, size_t stride, int j0,
+                                 const RowCorr<T>& rc) {
     const int n = c.n;
     double gl[F][H], gr[F][H];
 #pragma unroll
@@ -487,7 +498,7 @@ struct Seg {
         T rv[NR], sv[F];
         const int jn = side == 0 ? i : n - 1 - M + i;
         load_raw<T, P>(a, lbase + (size_t)jn * stride, rv);
-        if (rc != nullptr) rc->template apply<NR>(jn, rv);
+        rc.template apply<NR>(jn, rv);
         P::sin(a, rv, sv);
 #pragma unroll
         for (int f = 0; f < F; ++f) e[f][i] = (double)sv[f];
@@ -518,7 +529,7 @@ struct Seg {
             T rv[NR], sv[F];
             const int jc = min(max(jw, 0), n - 1);
             load_raw<T, P>(a, lbase + (size_t)jc * stride, rv);
-            if (rc != nullptr) rc->template apply<NR>(jc, rv);
+            rc.template apply<NR>(jc, rv);
             P::sin(a, rv, sv);
             double v = (double)sv[f];
 #pragma unroll
@@ -755,8 +766,8 @@ __device__ __forceinline__ void xpass_body(const LineCoef& c, const PassArgs& a,
 #pragma unroll
         for (int f = 0; f < NC; ++f)
           if (f < rc.nf) {
-            ld16(rc.sL[f] + ec, sl[it][f]);
-            ld16(rc.sR[f] + ec, sr[it][f]);
+            ld16(rc.seedL(f) + ec, sl[it][f]);
+            ld16(rc.seedR(f) + ec, sr[it][f]);
           }
       }
       if (rc.nf > 0) {
@@ -827,7 +838,7 @@ __device__ __forceinline__ void xpass_body(const LineCoef& c, const PassArgs& a,
 #pragma unroll
       for (int f = 0; f < F; ++f) sw[f][k] = sh_row[f][MOLT_PAD(rowoff + jj)];
     }
-    seg.stencils(c, a, lbase, 1, j0, sw, &rc);
+    seg.stencils(c, a, lbase, 1, j0, sw, rc);
     seg.totals(d, j0, n, AL, AR);
   } else {
 #pragma unroll
@@ -1267,31 +1278,34 @@ __device__ __forceinline__ void yfin_body(const LineCoef& c, const PassArgs& a, 
   seg.store(a, lbase, (size_t)nx, j0, n, false, w);
 }
 
-// FP64 mass and energy partial sums (fixed grid, fixed order: deterministic)
+// FP64 mass and energy partial sums (fixed grid, fixed order: deterministic).
+// Block bx takes rows bx, bx + nb, ...; its threads stride along the row.
 template <typename T>
 __device__ __forceinline__ void diag_body(const T* u, int nx, int ny, int bc, double hx, double hy, double eps,
                                           double* partials, int bx, int nb) {
   __shared__ double sm[2][4];
   const bool per = bc == MOLT_BC_PERIODIC;
+  const double ihx = 1.0 / hx, ihy = 1.0 / hy, ge = 0.5 * eps * eps;
   double ms = 0.0, en = 0.0;
-  const size_t n = (size_t)nx * ny;
-  for (size_t i = (size_t)bx * blockDim.x + threadIdx.x; i < n; i += (size_t)nb * blockDim.x) {
-    const int ix = (int)(i % nx), iy = (int)(i / nx);
-    const double wx = per ? 1.0 : ((ix == 0 || ix == nx - 1) ? 0.5 : 1.0);
+  for (int iy = bx; iy < ny; iy += nb) {
     const double wy = (ny == 1 || per) ? 1.0 : ((iy == 0 || iy == ny - 1) ? 0.5 : 1.0);
-    const double uu = (double)u[i];
-    ms += wx * wy * uu;
-    const double q = uu * uu - 1.0;
-    en += wx * wy * 0.25 * q * q;
-    if (per || ix < nx - 1) {
-      const double un = (double)u[(size_t)iy * nx + (ix + 1 == nx ? 0 : ix + 1)];
-      const double g = (un - uu) / hx;
-      en += 0.5 * eps * eps * g * g * wy;
-    }
-    if (ny > 1 && (per || iy < ny - 1)) {
-      const double un = (double)u[(size_t)(iy + 1 == ny ? 0 : iy + 1) * nx + ix];
-      const double g = (un - uu) / hy;
-      en += 0.5 * eps * eps * g * g * wx;
+    const T* row = u + (size_t)iy * nx;
+    const T* up = u + (size_t)(iy + 1 == ny ? 0 : iy + 1) * nx;
+    const bool gy = ny > 1 && (per || iy < ny - 1);
+    for (int ix = threadIdx.x; ix < nx; ix += blockDim.x) {
+      const double wx = per ? 1.0 : ((ix == 0 || ix == nx - 1) ? 0.5 : 1.0);
+      const double uu = (double)row[ix];
+      ms += wx * wy * uu;
+      const double q = uu * uu - 1.0;
+      en += wx * wy * 0.25 * q * q;
+      if (per || ix < nx - 1) {
+        const double g = ((double)row[ix + 1 == nx ? 0 : ix + 1] - uu) * ihx;
+        en += ge * g * g * wy;
+      }
+      if (gy) {
+        const double g = ((double)up[ix] - uu) * ihy;
+        en += ge * g * g * wx;
+      }
     }
   }
 #pragma unroll
@@ -1431,28 +1445,33 @@ __device__ __forceinline__ void diag_vch_body(const T* u, int nx, int ny, int bc
                                               double* partials, int bx, int nb) {
   __shared__ double sm[3][4];
   const bool per = bc == MOLT_BC_PERIODIC;
+  const double ihx = 1.0 / hx, ihy = 1.0 / hy, ge = 0.5 * eps * eps;
   double m1 = 0.0, m2 = 0.0, en = 0.0;
   const size_t n = (size_t)nx * ny;
-  for (size_t i = (size_t)bx * blockDim.x + threadIdx.x; i < n; i += (size_t)nb * blockDim.x) {
-    const int ix = (int)(i % nx), iy = (int)(i / nx);
-    const double wx = per ? 1.0 : ((ix == 0 || ix == nx - 1) ? 0.5 : 1.0);
+  for (int iy = bx; iy < ny; iy += nb) {
     const double wy = (ny == 1 || per) ? 1.0 : ((iy == 0 || iy == ny - 1) ? 0.5 : 1.0);
-    const double a = (double)u[i], b = (double)u[n + i];
-    m1 += wx * wy * a;
-    m2 += wx * wy * b;
-    // |w^3 - 1|^2 with w^3 = (a^3 - 3ab^2, 3a^2 b - b^3)
-    const double r = a * a * a - 3.0 * a * b * b - 1.0, s = 3.0 * a * a * b - b * b * b;
-    en += wx * wy * (r * r + s * s);
-    for (int c = 0; c < 2; ++c) {
-      const T* uc = u + c * n;
-      const double uu = (double)uc[i];
-      if (per || ix < nx - 1) {
-        const double g = ((double)uc[(size_t)iy * nx + (ix + 1 == nx ? 0 : ix + 1)] - uu) / hx;
-        en += 0.5 * eps * eps * g * g * wy;
-      }
-      if (ny > 1 && (per || iy < ny - 1)) {
-        const double g = ((double)uc[(size_t)(iy + 1 == ny ? 0 : iy + 1) * nx + ix] - uu) / hy;
-        en += 0.5 * eps * eps * g * g * wx;
+    const size_t r0 = (size_t)iy * nx, r1 = (size_t)(iy + 1 == ny ? 0 : iy + 1) * nx;
+    const bool gy = ny > 1 && (per || iy < ny - 1);
+    for (int ix = threadIdx.x; ix < nx; ix += blockDim.x) {
+      const double wx = per ? 1.0 : ((ix == 0 || ix == nx - 1) ? 0.5 : 1.0);
+      const size_t i = r0 + ix;
+      const double a = (double)u[i], b = (double)u[n + i];
+      m1 += wx * wy * a;
+      m2 += wx * wy * b;
+      // |w^3 - 1|^2 with w^3 = (a^3 - 3ab^2, 3a^2 b - b^3)
+      const double r = a * a * a - 3.0 * a * b * b - 1.0, s = 3.0 * a * a * b - b * b * b;
+      en += wx * wy * (r * r + s * s);
+      for (int c = 0; c < 2; ++c) {
+        const T* uc = u + c * n;
+        const double uu = (double)uc[i];
+        if (per || ix < nx - 1) {
+          const double g = ((double)uc[r0 + (ix + 1 == nx ? 0 : ix + 1)] - uu) * ihx;
+          en += ge * g * g * wy;
+        }
+        if (gy) {
+          const double g = ((double)uc[r1 + ix] - uu) * ihy;
+          en += ge * g * g * wx;
+        }
       }
     }
   }

@@ -77,7 +77,7 @@ static hipError_t launch_addc(int prec, void* x, double c0, double c1, size_t n,
 hipError_t launch_zero_ints(int* p, int n, hipStream_t s);
 hipError_t launch_widen(void* dst64, const void* src32, size_t n, hipStream_t s);
 hipError_t launch_rebase_mixed(void* base32, void* W32, void* DL32, const void* base64, const void* W64,
-                               const void* DL64, const DevState* st, int expect, size_t n, hipStream_t s);
+                               const DevState* st, int expect, size_t n, hipStream_t s);
 hipError_t launch_iterate64(void* v64, const void* base32, const void* W32, const DevState* st, size_t n,
                             hipStream_t s);
 
@@ -544,6 +544,128 @@ static int32_t enqueue_iteration(int prec, const StepGeo& G, const StepParams& s
     if (rc_ != MOLT_OK) return rc_;       \
   } while (0)
 
+// --------------------------------------------------------------------------
+// Runs of increment-form iterations replayed as executable graphs.  Every
+// increment iteration of a step launches the same kernels with the same
+// arguments (what changes lives in the device state), so a run of kIterRun of
+// them is captured once -- on a private stream of the library, so that the
+// caller's stream (the null stream included) need not support capture -- and
+// then launched on the caller's stream, one launch in place of ~7 per
+// iteration.  The graphs are cached by everything their kernels are given:
+// device, precision, geometry and line coefficients, step parameters, the
+// workspace's field pointers and the line-block shapes in force.
+// --------------------------------------------------------------------------
+constexpr int kIterRun = 4;
+constexpr int kIterGraphs = 8;  // cached graphs (least recently used replaced)
+
+struct IterKey {
+  int dev, prec, mode;
+  int kx, ky;
+  StepGeo G;
+  double sigma, kappa, s1, ush[2];
+  const void* base;
+  void* F[F_COUNT];
+  void* tot;
+  void* jln;
+  DevState* st;
+  double* rpart;
+};
+
+struct IterGraph {
+  IterKey key;
+  hipGraphExec_t exec;
+  unsigned long long used;
+};
+
+static std::mutex g_graph_mu;
+static std::vector<IterGraph> g_iter_graphs;
+static unsigned long long g_graph_clock = 0;
+static bool g_iter_graph_on = true;
+static std::map<int, hipStream_t> g_capture_streams;
+
+static hipStream_t capture_stream(int dev) {
+  auto it = g_capture_streams.find(dev);
+  if (it != g_capture_streams.end()) return it->second;
+  hipStream_t cs = nullptr;
+  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return nullptr;
+  g_capture_streams[dev] = cs;
+  return cs;
+}
+
+// forward declaration (defined below)
+static int32_t enqueue_iteration(int prec, const StepGeo& G, const StepParams& sp, const double* ush, int mode,
+                                 const void* base, void* const* F, void* tot, void* jln, DevState* st, double* rpart,
+                                 hipStream_t s);
+
+// the executable graph of kIterRun increment iterations for this key, captured
+// on first use; nullptr when graphs are off or the capture failed (the caller
+// then launches the kernels itself)
+static hipGraphExec_t iteration_graph(int prec, const StepGeo& G, const StepParams& sp, const double* ush,
+                                      const void* base, void* const* F, void* tot, void* jln, DevState* st,
+                                      double* rpart) {
+  if (!g_iter_graph_on || g_prof_on) return nullptr;
+  IterKey k;
+  memset(&k, 0, sizeof(k));
+  if (hipGetDevice(&k.dev) != hipSuccess) return nullptr;
+  k.prec = prec;
+  k.mode = 1;
+  k.kx = xpass_pick_k(G.nx, prec);
+  k.ky = G.two_d ? ypass_pick_k(G.ny, prec) : 0;
+  k.G = G;
+  k.sigma = sp.sigma;
+  k.kappa = sp.a;
+  k.s1 = sp.s1;
+  k.ush[0] = ush[0];
+  k.ush[1] = ush[1];
+  k.base = base;
+  for (int i = 0; i < F_COUNT; ++i) k.F[i] = F[i];
+  k.tot = tot;
+  k.jln = jln;
+  k.st = st;
+  k.rpart = rpart;
+  std::lock_guard<std::mutex> lock(g_graph_mu);
+  for (IterGraph& e : g_iter_graphs)
+    if (memcmp(&e.key, &k, sizeof(k)) == 0) {
+      e.used = ++g_graph_clock;
+      return e.exec;
+    }
+  hipStream_t cs = capture_stream(k.dev);
+  if (cs == nullptr) return nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  if (hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed) != hipSuccess) return nullptr;
+  int32_t rc = MOLT_OK;
+  for (int i = 0; i < kIterRun && rc == MOLT_OK; ++i)
+    rc = enqueue_iteration(prec, G, sp, ush, 1, base, F, tot, jln, st, rpart, cs);
+  const hipError_t e = hipStreamEndCapture(cs, &graph);
+  if (rc == MOLT_OK && e == hipSuccess && graph != nullptr &&
+      hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess)
+    exec = nullptr;
+  if (graph) (void)hipGraphDestroy(graph);
+  (void)hipGetLastError();
+  if (exec == nullptr) return nullptr;
+  if ((int)g_iter_graphs.size() >= kIterGraphs) {
+    size_t lru = 0;
+    for (size_t i = 1; i < g_iter_graphs.size(); ++i)
+      if (g_iter_graphs[i].used < g_iter_graphs[lru].used) lru = i;
+    // launches of the evicted graph may still be queued
+    (void)hipDeviceSynchronize();
+    (void)hipGraphExecDestroy(g_iter_graphs[lru].exec);
+    g_iter_graphs.erase(g_iter_graphs.begin() + lru);
+  }
+  g_iter_graphs.push_back(IterGraph{k, exec, ++g_graph_clock});
+  return exec;
+}
+
+// host copy of the device state, read back after each batch of iterations
+// (pinned, so that the read is one direct copy)
+static DevState* state_readback() {
+  static thread_local DevState* pin = nullptr;
+  if (pin == nullptr && hipHostMalloc((void**)&pin, sizeof(DevState), hipHostMallocPortable) != hipSuccess)
+    pin = nullptr;
+  return pin;
+}
+
 // omega: BDF2 step ratio dt_n / dt_{n-1} (1: constant steps, eq. BDF2; otherwise the variable-step form)
 // d_u_prev2 (with bdf2): a BDF3 step (eq. BDF3) from u^n, u^{n-1}, u^{n-2}
 static int32_t step_impl(const molt_grid* g, const molt_ch_params* p, void* d_u, void* d_u_prev, bool bdf2,
@@ -569,6 +691,7 @@ static int32_t step_impl(const molt_grid* g, const molt_ch_params* p, void* d_u,
   double* rpart = (double*)(w + L.rpart);
 
   StepGeo G;
+  memset(&G, 0, sizeof(G));  // (graph keys compare it byte for byte)
   G.nx = g->nx;
   G.ny = g->ny;
   G.nc = nc;
@@ -642,7 +765,7 @@ static int32_t step_impl(const molt_grid* g, const molt_ch_params* p, void* d_u,
     MOLT_RC(enqueue_iteration(MOLT_F64, G, sp, ush, 0, base64, F64, w + L.tot64, w + L.jln64, st, rpart, s));
     // the FP32 iterations' base is the first iterate rounded to FP32, their
     // running sum starts at its rounding error
-    HIPCHK(launch_rebase_mixed(F[F_R], F[F_W], F[F_DL], base64, F64[F_W], F64[F_DL], st, 1, nel, s));
+    HIPCHK(launch_rebase_mixed(F[F_R], F[F_W], F[F_DL], base64, F64[F_W], st, 1, nel, s));
     base = F[F_R];
     it = 1;
   }
@@ -660,7 +783,9 @@ static int32_t step_impl(const molt_grid* g, const molt_ch_params* p, void* d_u,
   // exit at once, and a long one checks rarely; a hint (the previous step's
   // count) lets the first batch cover most of the step
   int batch = iter_hint > 2 ? iter_hint - 2 : 2;
-  DevState hst;
+  DevState* pin = state_readback();
+  if (pin == nullptr) return fail(MOLT_EHIP, "hipHostMalloc of the state read-back failed");
+  DevState& hst = *pin;
   memset(&hst, 0, sizeof(hst));
   for (;;) {
     const int nb = batch < cap - it ? batch : cap - it;
@@ -670,8 +795,19 @@ static int32_t step_impl(const molt_grid* g, const molt_ch_params* p, void* d_u,
         void* v64 = F64[F_HIST];
         HIPCHK(launch_iterate64(v64, F[F_R], F[F_W], st, nel, s));
         MOLT_RC(enqueue_iteration(MOLT_F64, G, sp, ush, 0, v64, F64, w + L.tot64, w + L.jln64, st, rpart, s));
-        HIPCHK(launch_rebase_mixed(F[F_R], F[F_W], F[F_DL], v64, F64[F_W], F64[F_DL], st, it + 1, nel, s));
+        HIPCHK(launch_rebase_mixed(F[F_R], F[F_W], F[F_DL], v64, F64[F_W], st, it + 1, nel, s));
         continue;
+      }
+      // a whole run of increment iterations with no restart in it: one graph launch
+      const int next_restart = L.hybrid ? (it / kRestartEvery + 1) * kRestartEvery : INT32_MAX;
+      if (it > 0 && nb - b >= kIterRun && it + kIterRun <= next_restart) {
+        hipGraphExec_t ex = iteration_graph(prec, G, sp, ush, base, F, tot, jln, st, rpart);
+        if (ex != nullptr) {
+          HIPCHK(hipGraphLaunch(ex, s));
+          b += kIterRun - 1;
+          it += kIterRun - 1;
+          continue;
+        }
       }
       MOLT_RC(enqueue_iteration(prec, G, sp, ush, it == 0 ? 0 : 1, base, F, tot, jln, st, rpart, s));
     }
@@ -1680,6 +1816,11 @@ int32_t molt_set_option(int32_t option, int64_t value) {
   }
   if (option == MOLT_OPT_BATCH_LEAN && value >= 0 && value <= 1024) {
     g_batch_lean = (int)value;
+    return MOLT_OK;
+  }
+  if (option == MOLT_OPT_STEP_GRAPH && (value == 0 || value == 1)) {
+    std::lock_guard<std::mutex> lock(g_graph_mu);
+    g_iter_graph_on = value == 1;
     return MOLT_OK;
   }
   return fail(MOLT_EINVAL, "unknown option or value out of range");

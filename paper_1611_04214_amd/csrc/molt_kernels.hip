@@ -196,9 +196,11 @@ int xpass_max_n(int prec) { return prec == MOLT_F64 ? 4096 : 8192; }
 // Line-block shapes: nodes per thread along x (kx) and along y (ky) per line
 // length class (n <= 128, 256, ..., 8192) and precision; process-wide, set by
 // molt_tune_set or measured by molt_autotune.  Defaults: the smallest kx that
-// fits a line in one 256-thread block; ky = 16 (FP32) / 8 (FP64).
+// fits a line in one 256-thread block, except FP32 lines of 8192 nodes, whose
+// iteration passes spill registers at 32 nodes per thread (they take 16 in
+// 512-thread rows); ky = 16 (FP32) / 8 (FP64).
 // --------------------------------------------------------------------------
-static int g_kx[2][kTuneClasses] = {{4, 4, 4, 4, 8, 16, 16}, {4, 4, 4, 4, 8, 16, 32}};
+static int g_kx[2][kTuneClasses] = {{4, 4, 4, 4, 8, 16, 16}, {4, 4, 4, 4, 8, 16, 16}};
 static int g_ky[2][kTuneClasses] = {{8, 8, 8, 8, 8, 8, 8}, {16, 16, 16, 16, 16, 16, 16}};
 
 int tune_class(int n) {
@@ -270,18 +272,21 @@ __global__ void __launch_bounds__(256) widen_kernel(double* dst, const float* sr
 // After an FP64 (full-form) iteration that ran as iteration expect-1: the new
 // iterate v = base64 + W64 split into base32 = fl32(v) and W32 = fl32(v -
 // base32), and the increment narrowed, so that the FP32 increment iterations
-// add their increments to a running sum that starts at ~ulp(v).  Skipped when
-// that iteration did not run (the step had converged before it).
+// add their increments to a running sum that starts at ~ulp(v).  In the full
+// form the increment equals W64 (P4 writes DL = W = its result), so DL64 is
+// not read.  Skipped when that iteration did not run (the step had converged
+// before it).
 __global__ void __launch_bounds__(256) rebase_mixed_kernel(float* base32, float* W32, float* DL32, const double* base64,
-                                                           const double* W64, const double* DL64, const DevState* st,
-                                                           int expect, size_t n) {
+                                                           const double* W64, const DevState* st, int expect,
+                                                           size_t n) {
   if (st->iters != expect) return;
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-    const double v = base64[i] + W64[i];
+    const double w = W64[i];
+    const double v = base64[i] + w;
     const float b = (float)v;
     base32[i] = b;
     W32[i] = (float)(v - (double)b);
-    DL32[i] = (float)DL64[i];
+    DL32[i] = (float)w;
   }
 }
 
@@ -303,9 +308,9 @@ hipError_t launch_widen(void* dst64, const void* src32, size_t n, hipStream_t s)
   return hipGetLastError();
 }
 hipError_t launch_rebase_mixed(void* base32, void* W32, void* DL32, const void* base64, const void* W64,
-                               const void* DL64, const DevState* st, int expect, size_t n, hipStream_t s) {
+                               const DevState* st, int expect, size_t n, hipStream_t s) {
   hipLaunchKernelGGL(rebase_mixed_kernel, grid_elems(n), dim3(256), 0, s, (float*)base32, (float*)W32, (float*)DL32,
-                     (const double*)base64, (const double*)W64, (const double*)DL64, st, expect, n);
+                     (const double*)base64, (const double*)W64, st, expect, n);
   return hipGetLastError();
 }
 hipError_t launch_iterate64(void* v64, const void* base32, const void* W32, const DevState* st, size_t n,
@@ -389,7 +394,11 @@ static hipError_t xpass_k(const LineCoef& c, const PassArgs& a, DevState* st, in
 template <typename T, int PI>
 static hipError_t xpass_t(const LineCoef& c, const PassArgs& a, DevState* st, int nlines, double* rpart, hipStream_t s,
                           int prec) {
-  switch (xpass_pick_k(c.n, prec)) {
+  int k = xpass_pick_k(c.n, prec);
+  // the FP64 iteration passes (several fields per node) spill registers at 16
+  // nodes per thread; they take 8 in rows of up to 512 threads
+  if (sizeof(T) == 8 && k == 16 && (PI == PROG_P2 || PI == PROG_P4 || PI == PROG_P2V) && c.n <= 512 * 8) k = 8;
+  switch (k) {
     case 4: return xpass_k<T, PI, 4>(c, a, st, nlines, rpart, s);
     case 8: return xpass_k<T, PI, 8>(c, a, st, nlines, rpart, s);
     case 16: return xpass_k<T, PI, 16>(c, a, st, nlines, rpart, s);

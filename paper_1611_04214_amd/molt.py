@@ -35,7 +35,7 @@ EXPORTS = ("mol_t_helmholtz_sweep", "molt_sweep_workspace_bytes", "ch_workspace_
            "molt_profile_read",
            "molt_set_option", "mol_t_helmholtz_sweep_noalloc", "molt_noalloc_scratch_bytes")
 MOLT_TUNE_CLASSES = 7
-MOLT_OPT_BATCH_TICKS, MOLT_OPT_BATCH_GRAPH, MOLT_OPT_BATCH_LEAN = 2, 3, 5
+MOLT_OPT_BATCH_TICKS, MOLT_OPT_BATCH_GRAPH, MOLT_OPT_BATCH_LEAN, MOLT_OPT_STEP_GRAPH = 2, 3, 5, 6
 
 KERNEL_FAMILIES = ("xpass", "ytot", "ycomb", "yfin", "pointwise", "other")
 PROGRAMS = ("sweep", "rhs", "P1", "P2", "P3", "P4", "P1v", "P2v")

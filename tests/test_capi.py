@@ -179,6 +179,9 @@ def test_batch_options(lib):
     assert molt.molt_set_option(molt.MOLT_OPT_BATCH_GRAPH, 1) == molt.MOLT_OK
     assert molt.molt_set_option(molt.MOLT_OPT_BATCH_LEAN, -1) == molt.MOLT_EINVAL
     assert molt.molt_set_option(molt.MOLT_OPT_BATCH_LEAN, 2) == molt.MOLT_OK
+    assert molt.molt_set_option(molt.MOLT_OPT_STEP_GRAPH, 2) == molt.MOLT_EINVAL
+    assert molt.molt_set_option(molt.MOLT_OPT_STEP_GRAPH, 0) == molt.MOLT_OK
+    assert molt.molt_set_option(molt.MOLT_OPT_STEP_GRAPH, 1) == molt.MOLT_OK
     assert molt.molt_set_option(99, 1) == molt.MOLT_EINVAL
     assert molt.molt_profile_only(95) == molt.MOLT_OK  # FP64 launches: kinds 48..95
     assert molt.molt_profile_only(96) == molt.MOLT_EINVAL
@@ -186,8 +189,9 @@ def test_batch_options(lib):
 
 
 def test_tune_table_defaults_and_validation(lib):
-    # defaults: the smallest kx that fits a line in one block; ky 16 (FP32) / 8 (FP64)
-    assert molt.tune_table(molt.MOLT_F32) == [(4, 16), (4, 16), (4, 16), (4, 16), (8, 16), (16, 16), (32, 16)]
+    # defaults: the smallest kx that fits a line in one 256-thread block, but 16 in
+    # 512-thread rows for FP32 lines of 8192 (kx 32 spills); ky 16 (FP32) / 8 (FP64)
+    assert molt.tune_table(molt.MOLT_F32) == [(4, 16), (4, 16), (4, 16), (4, 16), (8, 16), (16, 16), (16, 16)]
     assert molt.tune_table(molt.MOLT_F64) == [(4, 8), (4, 8), (4, 8), (4, 8), (8, 8), (16, 8), (16, 8)]
     assert molt.molt_tune_set(molt.MOLT_F32, 4, 4, 16) == molt.MOLT_EINVAL   # 2048 nodes need kx >= 8
     assert molt.molt_tune_set(molt.MOLT_F32, 5, 4, 16) == molt.MOLT_EINVAL   # 4096 nodes: kx >= 8 (512 threads)
