@@ -92,6 +92,8 @@ __device__ __forceinline__ PassArgs slot_args(const SlotDesc& d, const SlotView&
   for (int i = 0; i < 3; ++i) a.out[i] = nullptr;
   a.ushift[0] = a.ushift[1] = 0.0;  // batched instances hold u (no Dirichlet walls)
   a.corr.seeds = nullptr;
+  a.close_part = nullptr;  // (the batched close is a kernel of its own)
+  a.defer_close = 0;
   a.rc0 = a.rc1 = 0.0;
   void* const* F = v.F;
   if (ph == PH_R) {
@@ -382,8 +384,7 @@ __global__ void __launch_bounds__(256) tick_end_batch_kernel(const SlotDesc* __r
   __syncthreads();  // every thread has read the control word before it changes
   if (cc.phase == PH_R) {
     if (threadIdx.x == 0) {
-      st->resid_bits = 0ull;
-      st->blocks_done = 0u;
+      st->open_parts = 0;
       st->done = 0;
       st->iters = 0;
       st->max_iter = d.max_iter;

@@ -696,6 +696,44 @@ __device__ inline void residual_close_body(const double* partials, int nblocks, 
 }
 
 
+// The close of an iteration whose P4 x-pass left st->open_parts residual
+// partials (nothing when none is pending or the step is done), by the threads
+// of one block of any shape; returns the state's done flag after it (block
+// uniform, so the caller need not read back the flag it may have just set).
+__device__ inline int residual_close_pending(const double* partials, DevState* st) {
+  __shared__ int sh_done;
+  const int nb = st->open_parts, done0 = st->done;
+  if (done0 || nb == 0) return done0;
+  __shared__ double red[16];
+  const int tid = threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z);
+  const int nt = blockDim.x * blockDim.y * blockDim.z;
+  double r = 0.0;
+  for (int i = tid; i < nb; i += nt) r = fmax(r, partials[i]);
+  const int lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) r = fmax(r, __shfl_down(r, off));
+  if (lane == 0) red[wave] = r;
+  __syncthreads();
+  if (tid == 0) {
+    double res = red[0];
+    for (int w = 1; w < (nt >> 6); ++w) res = fmax(res, red[w]);
+    const int it = st->iters + 1;
+    int done = 0;
+    if (st->fixed > 0) {
+      if (it >= st->fixed) done = 1;
+    } else if (res < st->tol || it >= st->max_iter) {
+      done = 1;
+    }
+    st->iters = it;
+    st->last_resid = res;
+    st->done = done;
+    st->open_parts = 0;
+    sh_done = done;
+  }
+  __syncthreads();
+  return sh_done;
+}
+
 // --------------------------------------------------------------------------
 // x-direction pass: rows are contiguous; TL threads (a multiple of 64) own one
 // row, BS/TL rows per block of BS = 256 (or 512, for rows of 512 threads).
@@ -1058,7 +1096,14 @@ __device__ __forceinline__ void yloc_body(const LineCoef& c, const PassArgs& a, 
                                           int nseg, size_t fstride, T* agg, T* jlnb, int bx, int by, int bz) {
   using P = typename ProgOf<PI, T>::type;
   constexpr int F = P::F;
-  if (st != nullptr && st->done) return;
+  // P1 of an iteration: its first block closes the previous iteration (the
+  // other blocks may still see done = 0 and compute this pass's temporaries,
+  // which the next passes, seeing the close, then leave unused)
+  if (a.close_part != nullptr && bx == 0 && by == 0 && bz == 0) {
+    if (residual_close_pending(a.close_part, st)) return;
+  } else if (st != nullptr && st->done) {
+    return;
+  }
   __shared__ T shA[F][2][kRG][64];
   const int lx = threadIdx.x, r = threadIdx.y;
   const int col = bx * 64 + lx;

@@ -80,6 +80,7 @@ hipError_t launch_rebase_mixed(void* base32, void* W32, void* DL32, const void* 
                                const DevState* st, int expect, size_t n, hipStream_t s);
 hipError_t launch_iterate64(void* v64, const void* base32, const void* W32, const DevState* st, size_t n,
                             hipStream_t s);
+hipError_t launch_close_pending(const double* rpart, DevState* st, hipStream_t s);
 
 hipError_t launch_state_init(DevState* st, double tol, int max_iter, int fixed, hipStream_t s);
 size_t ypass_tot_elems(int prec, int n, int nx, int batch);
@@ -183,6 +184,21 @@ void prof_end(int kind, hipStream_t s) {
   if (e) (void)hipEventRecord(e, s);
   if (g_open[kind] && e) g_pending.push_back({kind, g_open[kind], e});
   g_open[kind] = nullptr;
+}
+
+void prof_pair(int kind, hipEvent_t* b, hipEvent_t* e) {
+  *b = *e = nullptr;
+  if (g_prof_only >= 0 && kind != g_prof_only) return;
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  hipEvent_t x = ev_get(), y = ev_get();
+  if (x && y) {
+    g_pending.push_back({kind, x, y});
+    *b = x;
+    *e = y;
+    return;
+  }
+  if (x) g_ev_pool.push_back(x);
+  if (y) g_ev_pool.push_back(y);
 }
 
 // accumulate every recorded pair (the caller has synchronized the stream)
@@ -466,10 +482,13 @@ static int32_t enqueue_rhs(int prec, const StepGeo& G, const PassArgs& rhs_args,
 // One fixed-point iteration (Sec. 5.1, eqs. CH_BE_2D_3, CH_2D_Doperator1/2) as
 // the four passes P1..P4 on the fields F of the precision; mode 0 the full form
 // from the iterate `base`, mode 1 the increment form (base + W the iterate,
-// DL the last increment).  P4 writes DL, W and the residual partials.
+// DL the last increment).  P4 writes DL, W and the residual partials; the
+// close (residual, count, stop) follows it, or with defer_close is left to
+// the next iteration's P1 y-pass or an explicit close.  P1 (2D) always closes
+// a pending previous iteration first.
 static int32_t enqueue_iteration(int prec, const StepGeo& G, const StepParams& sp, const double* ush, int mode,
                                  const void* base, void* const* F, void* tot, void* jln, DevState* st, double* rpart,
-                                 hipStream_t s) {
+                                 bool defer_close, hipStream_t s) {
   PassArgs q;
   memset(&q, 0, sizeof(q));
   q.sigma = sp.sigma;
@@ -494,7 +513,9 @@ static int32_t enqueue_iteration(int prec, const StepGeo& G, const StepParams& s
   q.out[1] = F[F_B1];
   const int p1 = G.vch ? PROG_P1V : PROG_P1;
   if (G.two_d) {
+    q.close_part = rpart;
     HIPCHK(launch_ypass(prec, p1, G.cy1, q, st, G.nx, G.nc, tot, jln, true, s));
+    q.close_part = nullptr;
     q.corr = make_ycorr(prec, G.cy1, G.nx, 2, tot);
   } else {
     HIPCHK(launch_pointwise(prec, p1, q, st, G.n * G.nc, s));
@@ -534,6 +555,7 @@ static int32_t enqueue_iteration(int prec, const StepGeo& G, const StepParams& s
   q.in[3] = F[F_W];
   q.out[0] = F[F_DL];
   q.out[1] = F[F_W];
+  q.defer_close = defer_close && G.two_d ? 1 : 0;
   HIPCHK(launch_xpass(prec, PROG_P4, G.cx2, q, st, G.xl, rpart, s));
   return MOLT_OK;
 }
@@ -595,7 +617,7 @@ static hipStream_t capture_stream(int dev) {
 // forward declaration (defined below)
 static int32_t enqueue_iteration(int prec, const StepGeo& G, const StepParams& sp, const double* ush, int mode,
                                  const void* base, void* const* F, void* tot, void* jln, DevState* st, double* rpart,
-                                 hipStream_t s);
+                                 bool defer_close, hipStream_t s);
 
 // the executable graph of kIterRun increment iterations for this key, captured
 // on first use; nullptr when graphs are off or the capture failed (the caller
@@ -636,7 +658,7 @@ static hipGraphExec_t iteration_graph(int prec, const StepGeo& G, const StepPara
   if (hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed) != hipSuccess) return nullptr;
   int32_t rc = MOLT_OK;
   for (int i = 0; i < kIterRun && rc == MOLT_OK; ++i)
-    rc = enqueue_iteration(prec, G, sp, ush, 1, base, F, tot, jln, st, rpart, cs);
+    rc = enqueue_iteration(prec, G, sp, ush, 1, base, F, tot, jln, st, rpart, G.two_d, cs);
   const hipError_t e = hipStreamEndCapture(cs, &graph);
   if (rc == MOLT_OK && e == hipSuccess && graph != nullptr &&
       hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess)
@@ -762,7 +784,7 @@ static int32_t step_impl(const molt_grid* g, const molt_ch_params* p, void* d_u,
     ra.in[2] = bdf3 ? q64 : u64;
     MOLT_RC(enqueue_rhs(MOLT_F64, G, ra, F64, w + L.tot64, w + L.jln64, st, s));
     base64 = p->init == MOLT_INIT_LINEAR ? F64[F_R] : u64;
-    MOLT_RC(enqueue_iteration(MOLT_F64, G, sp, ush, 0, base64, F64, w + L.tot64, w + L.jln64, st, rpart, s));
+    MOLT_RC(enqueue_iteration(MOLT_F64, G, sp, ush, 0, base64, F64, w + L.tot64, w + L.jln64, st, rpart, false, s));
     // the FP32 iterations' base is the first iterate rounded to FP32, their
     // running sum starts at its rounding error
     HIPCHK(launch_rebase_mixed(F[F_R], F[F_W], F[F_DL], base64, F64[F_W], st, 1, nel, s));
@@ -794,7 +816,7 @@ static int32_t step_impl(const molt_grid* g, const molt_ch_params* p, void* d_u,
         // FP64 restart: the full form from the iterate, then re-based
         void* v64 = F64[F_HIST];
         HIPCHK(launch_iterate64(v64, F[F_R], F[F_W], st, nel, s));
-        MOLT_RC(enqueue_iteration(MOLT_F64, G, sp, ush, 0, v64, F64, w + L.tot64, w + L.jln64, st, rpart, s));
+        MOLT_RC(enqueue_iteration(MOLT_F64, G, sp, ush, 0, v64, F64, w + L.tot64, w + L.jln64, st, rpart, false, s));
         HIPCHK(launch_rebase_mixed(F[F_R], F[F_W], F[F_DL], v64, F64[F_W], st, it + 1, nel, s));
         continue;
       }
@@ -809,8 +831,10 @@ static int32_t step_impl(const molt_grid* g, const molt_ch_params* p, void* d_u,
           continue;
         }
       }
-      MOLT_RC(enqueue_iteration(prec, G, sp, ush, it == 0 ? 0 : 1, base, F, tot, jln, st, rpart, s));
+      MOLT_RC(enqueue_iteration(prec, G, sp, ush, it == 0 ? 0 : 1, base, F, tot, jln, st, rpart, true, s));
     }
+    // the batch's last iteration is closed before its state is read
+    HIPCHK(launch_close_pending(rpart, st, s));
     HIPCHK(hipMemcpyAsync(&hst, st, sizeof(DevState), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     if (g_prof_on) prof_drain();

@@ -1,6 +1,7 @@
 // molt_internal.h -- types shared by the host driver and the HIP kernels of
 // libmolt (not part of the public ABI).
 #pragma once
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stddef.h>
 #include <stdint.h>
@@ -41,8 +42,8 @@ struct LineCoef {
 // iterations after convergence become no-ops (no host round trip per
 // iteration).
 struct DevState {
-  unsigned long long resid_bits;  // atomicMax of the FP64 bits of max|delta| (>= 0)
-  unsigned int blocks_done;       // last-block counter of the residual kernel
+  int open_parts;                 // residual partials of an iteration not yet closed (the block
+                                  // count of its P4 x-pass); 0: none pending
   int done;                       // 1: converged or max_iter reached
   int iters;                      // iterations completed in this step
   int max_iter;
@@ -86,6 +87,10 @@ struct PassArgs {
   double ushift[2];// u = stored value + ushift, per component: 0 when the fields hold u; the
                    // shifted variable v = u - ushift of Dirichlet steps otherwise
   YCorr corr;      // x-passes: corrections of the preceding deferred y-pass
+  // P1 y-pass: residual partials of the previous iteration, closed by the
+  // pass's first block before its own work (nullptr: no close here)
+  const double* close_part;
+  int defer_close; // P4 x-pass: leave its close to the next P1 y-pass or an explicit close
 };
 
 // --------------------------------------------------------------------------
@@ -169,6 +174,22 @@ constexpr int prof_kind(int kind) {
 }
 void prof_begin(int kind, hipStream_t s);
 void prof_end(int kind, hipStream_t s);
+// a pair of events for one timed launch of `kind` (both nullptr when that kind
+// is not timed); the launch stamps the kernel's own start and end into them
+void prof_pair(int kind, hipEvent_t* b, hipEvent_t* e);
 extern bool g_prof_on;
+
+// One kernel launch; while kernel timing is on (and `kind` is timed) the
+// kernel's start and end are stamped by the dispatch itself
+// (hipExtLaunchKernelGGL), so the measured interval is the kernel's alone,
+// without the event packets' own processing that an event pair recorded
+// around the launch adds.
+template <typename... KA, typename... A>
+inline void launch_timed(int kind, void (*kern)(KA...), dim3 grid, dim3 block, uint32_t shmem, hipStream_t s,
+                         A... args) {
+  hipEvent_t b = nullptr, e = nullptr;
+  if (g_prof_on) prof_pair(kind, &b, &e);
+  hipExtLaunchKernelGGL(kern, grid, block, shmem, s, b, e, 0, args...);
+}
 
 }  // namespace molt

@@ -33,8 +33,8 @@ int xpass_tl(int n, int K);
 int diag_blocks(size_t n);
 
 template <typename T>
-__global__ void __launch_bounds__(1024) residual_close_kernel(const double* partials, int nblocks, DevState* st) {
-  residual_close_body(partials, nblocks, st);
+__global__ void __launch_bounds__(1024) residual_close_kernel(const double* partials, DevState* st) {
+  (void)residual_close_pending(partials, st);
 }
 
 template <typename T, int PI, int K, int M, bool PER, int BS>
@@ -47,6 +47,9 @@ xpass_kernel(const LineCoef c, const PassArgs a, DevState* st, int nlines, int T
   const int g = gridDim.x, b = blockIdx.x;
   // (P2 and P4 at 4096^2: 100 -> 92 us and 98 -> 87 us)
   const int bx = (g % 8 == 0) ? (b % 8) * (g / 8) + b / 8 : b;
+  // (before the body: a block that returns early must not skip it; done
+  // does not change during the pass)
+  if (rpart != nullptr && b == 0 && threadIdx.x == 0 && !st->done) st->open_parts = g;
   xpass_body<T, PI, K, M, PER, BS>(c, a, st, nlines, TL, rpart, vec, bx, smem);
 }
 
@@ -104,8 +107,7 @@ __global__ void __launch_bounds__(256) pointwise_kernel(const PassArgs a, DevSta
 #ifdef MOLT_PART_COMMON
 __global__ void state_init_kernel(DevState* st, double tol, int max_iter, int fixed) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
-    st->resid_bits = 0ull;
-    st->blocks_done = 0u;
+    st->open_parts = 0;
     st->done = 0;
     st->iters = 0;
     st->max_iter = max_iter;
@@ -328,6 +330,15 @@ size_t ypass_tot_elems(int prec, int n, int nx, int batch) {
   return (size_t)2 * 2 * nseg * nx * batch;  // F <= 2 fields, 2 directions, one entry per segment
 }
 
+// the close of an iteration still pending (no-op when none is)
+__global__ void __launch_bounds__(1024) close_pending_kernel(const double* partials, DevState* st) {
+  (void)residual_close_pending(partials, st);
+}
+hipError_t launch_close_pending(const double* rpart, DevState* st, hipStream_t s) {
+  launch_timed(KF_OTHER * 8, close_pending_kernel, dim3(1), dim3(1024), 0, s, rpart, st);
+  return hipGetLastError();
+}
+
 hipError_t launch_state_init(DevState* st, double tol, int max_iter, int fixed, hipStream_t s) {
   hipLaunchKernelGGL(state_init_kernel, dim3(1), dim3(64), 0, s, st, tol, max_iter, fixed);
   return hipGetLastError();
@@ -362,16 +373,16 @@ static hipError_t xpass_k(const LineCoef& c, const PassArgs& a, DevState* st, in
   const int BS = TL > 256 ? 512 : 256;  // rows of 512 threads get a block of their own
   const int lpb = BS / TL;
   dim3 grid((nlines + lpb - 1) / lpb);
-  if (g_prof_on) prof_begin(prof_kind<MOLT_KT>(KF_XPASS * 8 + PI), s);
+  const int kind = prof_kind<MOLT_KT>(KF_XPASS * 8 + PI);
   const bool per = c.bc == MOLT_BC_PERIODIC;
-#define MOLT_XL(MM, PP)                                                                                            \
-  do {                                                                                                            \
-    if (BS == 512)                                                                                                \
-      hipLaunchKernelGGL((xpass_kernel<T, PI, K, MM, PP, 512>), grid, dim3(512), 0, s, c, a, st, nlines, TL, rpart, \
-                         vec);                                                                                    \
-    else                                                                                                          \
-      hipLaunchKernelGGL((xpass_kernel<T, PI, K, MM, PP, 256>), grid, dim3(256), 0, s, c, a, st, nlines, TL, rpart, \
-                         vec);                                                                                    \
+#define MOLT_XL(MM, PP)                                                                                          \
+  do {                                                                                                          \
+    if (BS == 512)                                                                                              \
+      launch_timed(kind, xpass_kernel<T, PI, K, MM, PP, 512>, grid, dim3(512), 0, s, c, a, st, nlines, TL, rpart, \
+                   vec);                                                                                        \
+    else                                                                                                        \
+      launch_timed(kind, xpass_kernel<T, PI, K, MM, PP, 256>, grid, dim3(256), 0, s, c, a, st, nlines, TL, rpart, \
+                   vec);                                                                                        \
   } while (0)
   switch (c.M) {
     case 2: if (per) MOLT_XL(2, true); else MOLT_XL(2, false); break;
@@ -380,13 +391,11 @@ static hipError_t xpass_k(const LineCoef& c, const PassArgs& a, DevState* st, in
     default: return hipErrorInvalidValue;
   }
 #undef MOLT_XL
-  if (g_prof_on) prof_end(prof_kind<MOLT_KT>(KF_XPASS * 8 + PI), s);
-  if (rpart != nullptr) {
+  if (rpart != nullptr && !a.defer_close) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if (g_prof_on) prof_begin(prof_kind<MOLT_KT>(KF_OTHER * 8), s);
-    hipLaunchKernelGGL((residual_close_kernel<T>), dim3(1), dim3(1024), 0, s, (const double*)rpart, (int)grid.x, st);
-    if (g_prof_on) prof_end(prof_kind<MOLT_KT>(KF_OTHER * 8), s);
+    launch_timed(prof_kind<MOLT_KT>(KF_OTHER * 8), residual_close_kernel<T>, dim3(1), dim3(1024), 0, s,
+                 (const double*)rpart, st);
   }
   return hipGetLastError();
 }
@@ -438,13 +447,11 @@ static hipError_t ypass_km(const LineCoef& c, const PassArgs& a, DevState* st, i
   dim3 grid((nx + 63) / 64, nseg, batch);
   hipError_t e;
   if (deferred) {
-    if (g_prof_on) prof_begin(prof_kind<MOLT_KT>(KF_YFIN * 8 + PI), s);
-    hipLaunchKernelGGL((yloc_kernel<T, PI, K, M, PER>), grid, blk, 0, s, c, a, st, nx, nth, nseg, fstride, tot, jln);
-    if (g_prof_on) prof_end(prof_kind<MOLT_KT>(KF_YFIN * 8 + PI), s);
+    launch_timed(prof_kind<MOLT_KT>(KF_YFIN * 8 + PI), yloc_kernel<T, PI, K, M, PER>, grid, blk, 0, s, c, a, st, nx,
+                 nth, nseg, fstride, tot, jln);
   } else {
-    if (g_prof_on) prof_begin(prof_kind<MOLT_KT>(KF_YTOT * 8 + PI), s);
-    hipLaunchKernelGGL((ytot_kernel<T, PI, K, M, PER>), grid, blk, 0, s, c, a, st, nx, nth, nseg, fstride, tot, jln);
-    if (g_prof_on) prof_end(prof_kind<MOLT_KT>(KF_YTOT * 8 + PI), s);
+    launch_timed(prof_kind<MOLT_KT>(KF_YTOT * 8 + PI), ytot_kernel<T, PI, K, M, PER>, grid, blk, 0, s, c, a, st, nx,
+                 nth, nseg, fstride, tot, jln);
   }
   e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -452,22 +459,19 @@ static hipError_t ypass_km(const LineCoef& c, const PassArgs& a, DevState* st, i
   const int ct = (nseg + kCombWaves - 1) / kCombWaves;
   const dim3 cgrid((nx + 63) / 64, P::F, batch), cblk(64, kCombWaves);
   const int S = kRG * K;
-  if (g_prof_on) prof_begin(prof_kind<MOLT_KT>(KF_YCOMB * 8 + PI), s);
+  const int ckind = prof_kind<MOLT_KT>(KF_YCOMB * 8 + PI);
   if (ct <= 8)
-    hipLaunchKernelGGL((ycomb_kernel<T, 8>), cgrid, cblk, 0, s, c, st, nx, nseg, S, P::F, tot, (const T*)jln);
+    launch_timed(ckind, ycomb_kernel<T, 8>, cgrid, cblk, 0, s, c, st, nx, nseg, S, (int)P::F, tot, (const T*)jln);
   else if (ct <= 16)
-    hipLaunchKernelGGL((ycomb_kernel<T, 16>), cgrid, cblk, 0, s, c, st, nx, nseg, S, P::F, tot, (const T*)jln);
+    launch_timed(ckind, ycomb_kernel<T, 16>, cgrid, cblk, 0, s, c, st, nx, nseg, S, (int)P::F, tot, (const T*)jln);
   else if (ct <= 32)
-    hipLaunchKernelGGL((ycomb_kernel<T, 32>), cgrid, cblk, 0, s, c, st, nx, nseg, S, P::F, tot, (const T*)jln);
+    launch_timed(ckind, ycomb_kernel<T, 32>, cgrid, cblk, 0, s, c, st, nx, nseg, S, (int)P::F, tot, (const T*)jln);
   else
     return hipErrorInvalidValue;
-  if (g_prof_on) prof_end(prof_kind<MOLT_KT>(KF_YCOMB * 8 + PI), s);
   e = hipGetLastError();
   if (e != hipSuccess || deferred) return e;
-  if (g_prof_on) prof_begin(prof_kind<MOLT_KT>(KF_YFIN * 8 + PI), s);
-  hipLaunchKernelGGL((yfin_kernel<T, PI, K, M, PER>), grid, blk, 0, s, c, a, st, nx, nth, nseg, fstride,
-                     (const T*)tot);
-  if (g_prof_on) prof_end(prof_kind<MOLT_KT>(KF_YFIN * 8 + PI), s);
+  launch_timed(prof_kind<MOLT_KT>(KF_YFIN * 8 + PI), yfin_kernel<T, PI, K, M, PER>, grid, blk, 0, s, c, a, st, nx,
+               nth, nseg, fstride, (const T*)tot);
   return hipGetLastError();
 }
 
@@ -520,12 +524,11 @@ static dim3 grid_1d(size_t n) {
 
 hipError_t MOLT_KFN(launch_pointwise)(int prog, const PassArgs& a, DevState* st, size_t nelem, hipStream_t s) {
   dim3 g = grid_1d(nelem);
-  if (g_prof_on) prof_begin(prof_kind<MOLT_KT>(KF_POINTWISE * 8 + prog), s);
-  if (prog == PROG_P1) hipLaunchKernelGGL((pointwise_kernel<MOLT_KT, PROG_P1>), g, dim3(256), 0, s, a, st, nelem);
-  else if (prog == PROG_P3) hipLaunchKernelGGL((pointwise_kernel<MOLT_KT, PROG_P3>), g, dim3(256), 0, s, a, st, nelem);
-  else if (prog == PROG_P1V) hipLaunchKernelGGL((pointwise_kernel<MOLT_KT, PROG_P1V>), g, dim3(256), 0, s, a, st, nelem);
+  const int kind = prof_kind<MOLT_KT>(KF_POINTWISE * 8 + prog);
+  if (prog == PROG_P1) launch_timed(kind, pointwise_kernel<MOLT_KT, PROG_P1>, g, dim3(256), 0, s, a, st, nelem);
+  else if (prog == PROG_P3) launch_timed(kind, pointwise_kernel<MOLT_KT, PROG_P3>, g, dim3(256), 0, s, a, st, nelem);
+  else if (prog == PROG_P1V) launch_timed(kind, pointwise_kernel<MOLT_KT, PROG_P1V>, g, dim3(256), 0, s, a, st, nelem);
   else return hipErrorInvalidValue;
-  if (g_prof_on) prof_end(prof_kind<MOLT_KT>(KF_POINTWISE * 8 + prog), s);
   return hipGetLastError();
 }
 
@@ -542,9 +545,8 @@ hipError_t MOLT_KFN(launch_finalize)(void* u, const void* base, const void* W, s
 
 hipError_t MOLT_KFN(launch_vch_react)(const PassArgs& a, DevState* st, size_t n, hipStream_t s) {
   dim3 g = grid_1d(n);
-  if (g_prof_on) prof_begin(prof_kind<MOLT_KT>(KF_POINTWISE * 8 + PROG_P1V), s);
-  hipLaunchKernelGGL((vch_react_kernel<MOLT_KT>), g, dim3(256), 0, s, a, st, n);
-  if (g_prof_on) prof_end(prof_kind<MOLT_KT>(KF_POINTWISE * 8 + PROG_P1V), s);
+  launch_timed(prof_kind<MOLT_KT>(KF_POINTWISE * 8 + PROG_P1V), vch_react_kernel<MOLT_KT>, g, dim3(256), 0, s, a, st,
+               n);
   return hipGetLastError();
 }
 
