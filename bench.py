@@ -39,6 +39,8 @@ Also printed on the same JSON line:
   sweep         the standalone line inverse (mol_t_helmholtz_sweep) along x
                 and along y of the 4096^2 field, FP32 and FP64: Gpt-sweeps/s and
                 the fraction of 8 TB/s;
+  full_workload the whole 500-step workload once from u0: per-step iteration
+                counts (first, last, range), wall time and rates;
   ch1d, ch2d_neumann  the 1D (N=256, BE, FP64, 200 steps) and 512^2 Neumann
                 (BDF2, 2000 steps, FP64 then FP32) workloads: steps/s on the
                 GPU and of the oracle (one core and all cores), errors.
@@ -123,6 +125,8 @@ def parse():
     ap.add_argument("--serve-sub-count", type=int, default=200,
                     help="requests of the sub-capacity and near-capacity served traces (0: skip them)")
     ap.add_argument("--no-small", action="store_true", help="skip the 1D and 512^2 Neumann workloads")
+    ap.add_argument("--full-steps", type=int, default=500,
+                    help="steps of the whole-workload run (the workload's 500; 0: skip it)")
     ap.add_argument("--no-sweep", action="store_true", help="skip the standalone sweep measurement")
     ap.add_argument("--no-error", action="store_true", help="skip the FP32 error measurement")
     ap.add_argument("--c2-steps", type=int, default=2000, help="steps of the 512^2 Neumann workload")
@@ -546,6 +550,46 @@ def run_small(args, molt, synth, oracle):
     return out
 
 
+def run_full(args, molt, w, grid, params, u0):
+    """The whole workload once: every step from u0 (BE start-up, then BDF2),
+    per-step iteration counts and wall time (not the headline value, which
+    is timed over the steady steps)."""
+    import numpy as np
+    import torch
+    u = torch.tensor(u0, dtype=torch.float32, device="cuda:0")
+    up = torch.empty_like(u)
+    work = molt.workspace(molt.ch_workspace_bytes(grid, params))
+    stream = torch.cuda.current_stream().cuda_stream
+    nsteps = args.full_steps
+    its, secs = [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(nsteps):
+        params.have_prev = 1 if k > 0 else 0
+        info = molt.molt_step_info()
+        ts = time.perf_counter()
+        rc = molt.ch_step(grid, params, u.data_ptr(), up.data_ptr(), work.data_ptr(), work.numel(), info, stream)
+        if rc != molt.MOLT_OK:
+            raise molt.MoltError(rc, f"ch_step (full workload, step {k + 1})")
+        its.append(info.iters)
+        secs.append(time.perf_counter() - ts)
+        if (k + 1) % 100 == 0:
+            print(f"full workload: {k + 1}/{nsteps} steps, {time.perf_counter() - t0:.2f} s",
+                  file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    pts = float(grid.nx) * grid.ny
+    out = {"steps": nsteps, "seconds": round(elapsed, 3), "steps_per_s": round(nsteps / elapsed, 2),
+           "gpt_sweeps_per_s": round(pts * sum(4 + 7 * k for k in its) / elapsed / 1e9, 1),
+           "iters_first_10": its[:10], "iters_last_10": its[-10:],
+           "iters_min_max_mean_after_10": [min(its[10:] or its), max(its[10:] or its),
+                                           round(float(np.mean(its[10:] or its)), 2)],
+           "ms_per_step_after_10": round(1e3 * float(np.mean(secs[10:] or secs)), 3),
+           "mass_last": info.mass, "energy_last": info.energy}
+    print(f"full workload: {json.dumps(out)}", file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -623,10 +667,11 @@ def main():
     for _ in range(args.steps):
         infos.append(one_step(step_idx))
         step_idx += 1
-        print(f"timed step {step_idx}: iters={infos[-1].iters} residual={infos[-1].residual:.3e}",
-              file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    for k, inf in enumerate(infos):  # (printed after the timed region)
+        print(f"timed step {step_idx - len(infos) + k + 1}: iters={inf.iters} residual={inf.residual:.3e}",
+              file=sys.stderr, flush=True)
     prof = molt.molt_profile_read() if not args.no_profile else {}
     molt.molt_profile(0)
     molt.molt_profile_only(-1)
@@ -694,6 +739,8 @@ def main():
                 roof = {}
             roof["whole_iteration"] = whole
 
+    full = run_full(args, molt, w, grid, params, u0) if args.full_steps > 0 else None
+
     import oracle
     oracle.build(force=False)
     error = run_error(molt, synth, oracle, w, n) if not args.no_error else None
@@ -750,6 +797,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "error": error,
+        "full_workload": full,
         "sweep": sweep,
         "ch1d": small["ch1d"] if small else None,
         "ch2d_neumann": small["ch2d_neumann"] if small else None,

@@ -389,7 +389,6 @@ __global__ void __launch_bounds__(256) tick_end_batch_kernel(const SlotDesc* __r
       st->iters = 0;
       st->max_iter = d.max_iter;
       st->fixed = d.fixed;
-      st->error = 0;
       st->tol = d.tol;
       st->last_resid = 0.0;
       st->mass = 0.0;

@@ -72,7 +72,10 @@ __device__ __forceinline__ int wrap1(int j, int n) { return j < 0 ? j + n : (j >
 // and the constant drops out of C1 g.
 // --------------------------------------------------------------------------
 enum ProgId { PROG_SWEEP = 0, PROG_RHS = 1, PROG_P1 = 2, PROG_P2 = 3, PROG_P3 = 4, PROG_P4 = 5, PROG_P1V = 6,
-              PROG_P2V = 7 };
+              PROG_P2V = 7, PROG_P2F = 8, PROG_P4F = 9 };
+// P2F, P4F: P2 and P4 of the full form (first iteration, FP64 restarts) with
+// the increment-form inputs left out (fewer registers); timed under P2, P4
+constexpr int prog_slot(int prog) { return prog == PROG_P2F ? PROG_P2 : (prog == PROG_P4F ? PROG_P4 : prog); }
 
 template <typename T>
 struct ProgSweep {  // w = L^{-1} in0
@@ -169,6 +172,37 @@ struct ProgP2 {  // x, alpha1: raw (a1, b1, base, W, dl) -> C = X1(2 a1 - e) - a
   }
 };
 
+// the reaction of the full form, rounded as react_lin's full branch
+template <typename T>
+__device__ __forceinline__ T react_full(const PassArgs& a, T base) {
+#pragma clang fp contract(off)
+  const T sg = (T)a.sigma;
+  const T c = (T)a.ushift[0];
+  const T bu = base + c;
+  return fma(-sg, base, fma(bu * bu, bu, -bu));
+}
+
+template <typename T>
+struct ProgP2F {  // P2 of the full form: raw (a1, b1, base), e = g(base), lin = base
+  static constexpr int F = 2, E = 2, NR = 3, NO = 2;
+  static constexpr bool NT = true;
+  __device__ static bool need(const PassArgs&, int) { return true; }
+  __device__ static void sin(const PassArgs& a, const T* r, T* s) {
+    const T e = react_full<T>(a, r[2]);
+    s[0] = T(2) * r[0] - e;
+    s[1] = r[2] - r[1];
+  }
+  __device__ static void ext(const PassArgs&, const T* r, T* x) {
+    x[0] = r[0];
+    x[1] = r[1];
+  }
+  __device__ static double fin(const PassArgs&, const T* w, const T* x, T* o) {
+    o[0] = w[0] - x[0];
+    o[1] = x[1] + w[1];
+    return 0.0;
+  }
+};
+
 template <typename T>
 struct ProgP3 {  // y, alpha2: raw (C, q) -> m = Y2(q + kappa C) - q, n = Y2 q
   static constexpr int F = 2, E = 1, NR = 2, NO = 2;
@@ -201,6 +235,24 @@ struct ProgP4 {  // x, alpha2: raw (m, n, dl|R, W) -> dl' = (dl|R) + X2 m - n ; 
     const T dn = x[1] + w[0] - x[0];
     o[0] = dn;
     o[1] = x[2] + dn;
+    return fabs((double)dn);
+  }
+};
+
+template <typename T>
+struct ProgP4F {  // P4 of the full form: raw (m, n, R) -> dl' = R + X2 m - n, W' = dl'
+  static constexpr int F = 1, E = 2, NR = 3, NO = 2;
+  static constexpr bool NT = false;
+  __device__ static bool need(const PassArgs&, int) { return true; }
+  __device__ static void sin(const PassArgs&, const T* r, T* s) { s[0] = r[0]; }
+  __device__ static void ext(const PassArgs&, const T* r, T* x) {
+    x[0] = r[1];
+    x[1] = r[2];
+  }
+  __device__ static double fin(const PassArgs&, const T* w, const T* x, T* o) {
+    const T dn = x[1] + w[0] - x[0];
+    o[0] = dn;
+    o[1] = T(0) + dn;  // (P4's W' = 0 + dl': the same zero signs)
     return fabs((double)dn);
   }
 };
@@ -255,6 +307,8 @@ template <typename T> struct ProgOf<PROG_P1, T> { using type = ProgP1<T>; };
 template <typename T> struct ProgOf<PROG_P2, T> { using type = ProgP2<T>; };
 template <typename T> struct ProgOf<PROG_P3, T> { using type = ProgP3<T>; };
 template <typename T> struct ProgOf<PROG_P4, T> { using type = ProgP4<T>; };
+template <typename T> struct ProgOf<PROG_P2F, T> { using type = ProgP2F<T>; };
+template <typename T> struct ProgOf<PROG_P4F, T> { using type = ProgP4F<T>; };
 
 // field f of a program's raw inputs, or field 0 (always read, same size) in
 // place of a field it does not read: loads are then unconditional, so the
@@ -792,8 +846,13 @@ __device__ __forceinline__ void xpass_body(const LineCoef& c, const PassArgs& a,
       // the deferred y-pass's seeds are loaded with the raw fields (all
       // loads in flight together) and folded in after the last of them;
       // folding each group as it arrives keeps fewer registers but
-      // serializes the loads (P2 92 -> 117 us at 4096^2)
-      T sl[K / V][NC][V], sr[K / V][NC][V];
+      // serializes the loads (FP32 P2 92 -> 117 us at 4096^2).  The FP64 P4
+      // folds them as they arrive: that frees the registers for a second
+      // block per CU (FP64 P4 at 4096^2: 208 -> 160 us; the FP64 sweeps lose
+      // by it, 72 -> 87 us, and P2 does not reach the next occupancy step)
+      constexpr bool kEarly = !(sizeof(T) == 8 && (PI == PROG_P4 || PI == PROG_P4F));
+      constexpr int KS = kEarly ? K / V : 1;
+      T sl[KS][NC][V], sr[KS][NC][V];
 #pragma unroll
       for (int it = 0; it < K / V; ++it) {
         const int e0 = (it * TL + t) * V;
@@ -801,14 +860,19 @@ __device__ __forceinline__ void xpass_body(const LineCoef& c, const PassArgs& a,
 #pragma unroll
         for (int f = 0; f < NR; ++f) ld16(raw_ptr<T, P>(a, f) + off, r[it][f]);
         const int ec = e0 < n ? e0 : 0;
+        const int is = kEarly ? it : 0;
 #pragma unroll
         for (int f = 0; f < NC; ++f)
           if (f < rc.nf) {
-            ld16(rc.seedL(f) + ec, sl[it][f]);
-            ld16(rc.seedR(f) + ec, sr[it][f]);
+            ld16(rc.seedL(f) + ec, sl[is][f]);
+            ld16(rc.seedR(f) + ec, sr[is][f]);
+            if constexpr (!kEarly) {
+#pragma unroll
+              for (int v = 0; v < V; ++v) r[it][f][v] += rc.cL * sl[0][f][v] + rc.cR * sr[0][f][v];
+            }
           }
       }
-      if (rc.nf > 0) {
+      if (kEarly && rc.nf > 0) {
 #pragma unroll
         for (int it = 0; it < K / V; ++it)
 #pragma unroll
@@ -1337,19 +1401,33 @@ __device__ __forceinline__ void diag_body(const T* u, int nx, int ny, int bc, do
     const T* row = u + (size_t)iy * nx;
     const T* up = u + (size_t)(iy + 1 == ny ? 0 : iy + 1) * nx;
     const bool gy = ny > 1 && (per || iy < ny - 1);
-    for (int ix = threadIdx.x; ix < nx; ix += blockDim.x) {
-      const double wx = per ? 1.0 : ((ix == 0 || ix == nx - 1) ? 0.5 : 1.0);
-      const double uu = (double)row[ix];
-      ms += wx * wy * uu;
-      const double q = uu * uu - 1.0;
-      en += wx * wy * 0.25 * q * q;
-      if (per || ix < nx - 1) {
-        const double g = ((double)row[ix + 1 == nx ? 0 : ix + 1] - uu) * ihx;
-        en += ge * g * g * wy;
+    // four nodes per thread and pass, all loads issued before the sums
+    for (int x0 = threadIdx.x; x0 < nx; x0 += 4 * blockDim.x) {
+      T c0[4], c1[4], c2[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int ix = min(x0 + q * (int)blockDim.x, nx - 1);
+        c0[q] = row[ix];
+        c1[q] = row[ix + 1 == nx ? 0 : ix + 1];
+        c2[q] = up[ix];
       }
-      if (gy) {
-        const double g = ((double)up[ix] - uu) * ihy;
-        en += ge * g * g * wx;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int ix = x0 + q * (int)blockDim.x;
+        if (ix >= nx) break;
+        const double wx = per ? 1.0 : ((ix == 0 || ix == nx - 1) ? 0.5 : 1.0);
+        const double uu = (double)c0[q];
+        ms += wx * wy * uu;
+        const double qq = uu * uu - 1.0;
+        en += wx * wy * 0.25 * qq * qq;
+        if (per || ix < nx - 1) {
+          const double g = ((double)c1[q] - uu) * ihx;
+          en += ge * g * g * wy;
+        }
+        if (gy) {
+          const double g = ((double)c2[q] - uu) * ihy;
+          en += ge * g * g * wx;
+        }
       }
     }
   }
@@ -1497,6 +1575,7 @@ __device__ __forceinline__ void diag_vch_body(const T* u, int nx, int ny, int bc
     const double wy = (ny == 1 || per) ? 1.0 : ((iy == 0 || iy == ny - 1) ? 0.5 : 1.0);
     const size_t r0 = (size_t)iy * nx, r1 = (size_t)(iy + 1 == ny ? 0 : iy + 1) * nx;
     const bool gy = ny > 1 && (per || iy < ny - 1);
+#pragma unroll 2
     for (int ix = threadIdx.x; ix < nx; ix += blockDim.x) {
       const double wx = per ? 1.0 : ((ix == 0 || ix == nx - 1) ? 0.5 : 1.0);
       const size_t i = r0 + ix;

@@ -118,7 +118,8 @@ bool tune_valid(int prec, int cls, int kx, int ky);
 void tune_get(int prec, int cls, int* kx, int* ky);
 void tune_set(int prec, int cls, int kx, int ky);
 
-enum { PROG_SWEEP = 0, PROG_RHS = 1, PROG_P1 = 2, PROG_P2 = 3, PROG_P3 = 4, PROG_P4 = 5, PROG_P1V = 6, PROG_P2V = 7 };
+enum { PROG_SWEEP = 0, PROG_RHS = 1, PROG_P1 = 2, PROG_P2 = 3, PROG_P3 = 4, PROG_P4 = 5, PROG_P1V = 6, PROG_P2V = 7,
+       PROG_P2F = 8, PROG_P4F = 9 };
 
 // --------------------------------------------------------------------------
 // errors
@@ -534,7 +535,9 @@ static int32_t enqueue_iteration(int prec, const StepGeo& G, const StepParams& s
   }
   q.out[0] = F[F_C];
   q.out[1] = F[F_Q];
-  HIPCHK(launch_xpass(prec, G.vch ? PROG_P2V : PROG_P2, G.cx1, q, st, G.xl, nullptr, s));
+  // (FP64 full form: the programs without the increment-form inputs)
+  const bool full64 = prec == MOLT_F64 && mode == 0;
+  HIPCHK(launch_xpass(prec, G.vch ? PROG_P2V : (full64 ? PROG_P2F : PROG_P2), G.cx1, q, st, G.xl, nullptr, s));
   q.corr.seeds = nullptr;
   // P3 (y, alpha2): m, n
   q.in[0] = F[F_C];
@@ -556,7 +559,7 @@ static int32_t enqueue_iteration(int prec, const StepGeo& G, const StepParams& s
   q.out[0] = F[F_DL];
   q.out[1] = F[F_W];
   q.defer_close = defer_close && G.two_d ? 1 : 0;
-  HIPCHK(launch_xpass(prec, PROG_P4, G.cx2, q, st, G.xl, rpart, s));
+  HIPCHK(launch_xpass(prec, full64 ? PROG_P4F : PROG_P4, G.cx2, q, st, G.xl, rpart, s));
   return MOLT_OK;
 }
 
@@ -688,6 +691,23 @@ static DevState* state_readback() {
   return pin;
 }
 
+// iteration count of the last step run in each workspace: the batch hint of
+// the next ch_step call on it (callers that step one call at a time)
+static std::mutex g_hint_mu;
+static std::map<const void*, int> g_last_iters;
+
+static int workspace_hint(const void* w) {
+  std::lock_guard<std::mutex> lock(g_hint_mu);
+  auto it = g_last_iters.find(w);
+  return it == g_last_iters.end() ? 0 : it->second;
+}
+
+static void workspace_hint_set(const void* w, int iters) {
+  std::lock_guard<std::mutex> lock(g_hint_mu);
+  if (g_last_iters.size() >= 256 && g_last_iters.find(w) == g_last_iters.end()) g_last_iters.clear();
+  g_last_iters[w] = iters;
+}
+
 // omega: BDF2 step ratio dt_n / dt_{n-1} (1: constant steps, eq. BDF2; otherwise the variable-step form)
 // d_u_prev2 (with bdf2): a BDF3 step (eq. BDF3) from u^n, u^{n-1}, u^{n-2}
 static int32_t step_impl(const molt_grid* g, const molt_ch_params* p, void* d_u, void* d_u_prev, bool bdf2,
@@ -800,11 +820,18 @@ static int32_t step_impl(const molt_grid* g, const molt_ch_params* p, void* d_u,
   const int fixed = p->fixed_iters;
   const int cap = fixed > 0 ? fixed : p->max_iter;
   // iterations are enqueued in batches between host checks of the device
-  // state: a batch grows with the iterations already done (a quarter of them,
-  // 2..32), so a step that converges in a few iterations queues few that
-  // exit at once, and a long one checks rarely; a hint (the previous step's
-  // count) lets the first batch cover most of the step
-  int batch = iter_hint > 2 ? iter_hint - 2 : 2;
+  // state (2..32 iterations): up to a hint -- the previous step's count, from
+  // the caller or the last step run in this workspace -- the batches end at
+  // the hint, since counts change slowly from step to step; past it a batch
+  // grows with the iterations already done (a quarter of them), so a step
+  // that converges in a few iterations queues few that exit at once, and a
+  // long one checks rarely
+  if (iter_hint <= 0) iter_hint = workspace_hint(d_work);
+  auto next_batch = [&](int done_its) {
+    const int b = iter_hint > done_its ? iter_hint - done_its : done_its / 4;
+    return b < 2 ? 2 : (b > 32 ? 32 : b);
+  };
+  int batch = next_batch(it);
   DevState* pin = state_readback();
   if (pin == nullptr) return fail(MOLT_EHIP, "hipHostMalloc of the state read-back failed");
   DevState& hst = *pin;
@@ -839,7 +866,7 @@ static int32_t step_impl(const molt_grid* g, const molt_ch_params* p, void* d_u,
     HIPCHK(hipStreamSynchronize(s));
     if (g_prof_on) prof_drain();
     if (hst.done || it >= cap) break;
-    batch = it / 4 < 2 ? 2 : (it / 4 > 32 ? 32 : it / 4);
+    batch = next_batch(it);
   }
   HIPCHK(launch_finalize(prec, d_u, base, F[F_W], nel, s));
   if (vform) {
@@ -854,7 +881,7 @@ static int32_t step_impl(const molt_grid* g, const molt_ch_params* p, void* d_u,
   HIPCHK(hipMemcpyAsync(&hst, st, sizeof(DevState), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   if (g_prof_on) prof_drain();
-  if (hst.error) return fail(MOLT_EHIP, "a y-pass segment exchange exceeded its wait bound");
+  workspace_hint_set(d_work, hst.iters);
   const bool conv = fixed > 0 || hst.last_resid < p->tol;
   if (info) {
     info->iters = hst.iters;

@@ -48,7 +48,6 @@ struct DevState {
   int iters;                      // iterations completed in this step
   int max_iter;
   int fixed;                      // >0: never stop early
-  int error;                      // set by a kernel whose bounded wait expired
   double tol;
   double last_resid;
   double mass, energy;

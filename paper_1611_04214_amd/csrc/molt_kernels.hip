@@ -112,7 +112,6 @@ __global__ void state_init_kernel(DevState* st, double tol, int max_iter, int fi
     st->iters = 0;
     st->max_iter = max_iter;
     st->fixed = fixed;
-    st->error = 0;
     st->tol = tol;
     st->last_resid = 0.0;
     st->mass = 0.0;
@@ -373,7 +372,7 @@ static hipError_t xpass_k(const LineCoef& c, const PassArgs& a, DevState* st, in
   const int BS = TL > 256 ? 512 : 256;  // rows of 512 threads get a block of their own
   const int lpb = BS / TL;
   dim3 grid((nlines + lpb - 1) / lpb);
-  const int kind = prof_kind<MOLT_KT>(KF_XPASS * 8 + PI);
+  const int kind = prof_kind<MOLT_KT>(KF_XPASS * 8 + prog_slot(PI));
   const bool per = c.bc == MOLT_BC_PERIODIC;
 #define MOLT_XL(MM, PP)                                                                                          \
   do {                                                                                                          \
@@ -406,7 +405,7 @@ static hipError_t xpass_t(const LineCoef& c, const PassArgs& a, DevState* st, in
   int k = xpass_pick_k(c.n, prec);
   // the FP64 iteration passes (several fields per node) spill registers at 16
   // nodes per thread; they take 8 in rows of up to 512 threads
-  if (sizeof(T) == 8 && k == 16 && (PI == PROG_P2 || PI == PROG_P4 || PI == PROG_P2V) && c.n <= 512 * 8) k = 8;
+  if (sizeof(T) == 8 && k == 16 && prog_slot(PI) != PROG_SWEEP && PI != PROG_RHS && c.n <= 512 * 8) k = 8;
   switch (k) {
     case 4: return xpass_k<T, PI, 4>(c, a, st, nlines, rpart, s);
     case 8: return xpass_k<T, PI, 8>(c, a, st, nlines, rpart, s);
@@ -427,6 +426,10 @@ hipError_t MOLT_KFN(launch_xpass)(int prog, const LineCoef& c, const PassArgs& a
     case PROG_P2: return xpass_t<MOLT_KT, PROG_P2>(c, a, st, nlines, rpart, s, prec);
     case PROG_P4: return xpass_t<MOLT_KT, PROG_P4>(c, a, st, nlines, rpart, s, prec);
     case PROG_P2V: return xpass_t<MOLT_KT, PROG_P2V>(c, a, st, nlines, rpart, s, prec);
+#ifdef MOLT_PREC_F64
+    case PROG_P2F: return xpass_t<MOLT_KT, PROG_P2F>(c, a, st, nlines, rpart, s, prec);
+    case PROG_P4F: return xpass_t<MOLT_KT, PROG_P4F>(c, a, st, nlines, rpart, s, prec);
+#endif
   }
   return hipErrorInvalidValue;
 }
