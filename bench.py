@@ -40,7 +40,8 @@ Also printed on the same JSON line:
                 and along y of the 4096^2 field, FP32 and FP64: Gpt-sweeps/s and
                 the fraction of 8 TB/s;
   full_workload the whole 500-step workload once from u0: per-step iteration
-                counts (first, last, range), wall time and rates;
+                counts (first, last, range), wall time and rates, and the FP32
+                result's error against the same steps in FP64;
   ch1d, ch2d_neumann  the 1D (N=256, BE, FP64, 200 steps) and 512^2 Neumann
                 (BDF2, 2000 steps, FP64 then FP32) workloads: steps/s on the
                 GPU and of the oracle (one core and all cores), errors.
@@ -127,6 +128,8 @@ def parse():
     ap.add_argument("--no-small", action="store_true", help="skip the 1D and 512^2 Neumann workloads")
     ap.add_argument("--full-steps", type=int, default=500,
                     help="steps of the whole-workload run (the workload's 500; 0: skip it)")
+    ap.add_argument("--no-full-fp64", dest="full_fp64", action="store_false",
+                    help="skip the FP64 run of the whole workload (its FP32 error)")
     ap.add_argument("--no-sweep", action="store_true", help="skip the standalone sweep measurement")
     ap.add_argument("--no-error", action="store_true", help="skip the FP32 error measurement")
     ap.add_argument("--c2-steps", type=int, default=2000, help="steps of the 512^2 Neumann workload")
@@ -579,13 +582,43 @@ def run_full(args, molt, w, grid, params, u0):
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     pts = float(grid.nx) * grid.ny
+    # the same steps in FP64 (the GPU path the tests pin to the oracle at
+    # 1e-12 relative): the FP32 result's error after the whole workload
+    err = None
+    if args.full_fp64:
+        p64 = molt.make_params(params.eps, params.dt, tol=params.tol, stepper=params.stepper,
+                               max_iter=params.max_iter, init=params.init, precision=molt.MOLT_F64)
+        u64 = torch.tensor(u0, dtype=torch.float64, device="cuda:0")
+        up64 = torch.empty_like(u64)
+        work64 = molt.workspace(molt.ch_workspace_bytes(grid, p64))
+        its64 = []
+        t64 = time.perf_counter()
+        for k in range(nsteps):
+            p64.have_prev = 1 if k > 0 else 0
+            inf64 = molt.molt_step_info()
+            rc = molt.ch_step(grid, p64, u64.data_ptr(), up64.data_ptr(), work64.data_ptr(), work64.numel(), inf64,
+                              stream)
+            if rc != molt.MOLT_OK:
+                raise molt.MoltError(rc, f"ch_step (full workload FP64, step {k + 1})")
+            its64.append(inf64.iters)
+            if (k + 1) % 100 == 0:
+                print(f"full workload FP64: {k + 1}/{nsteps} steps, {time.perf_counter() - t64:.2f} s",
+                      file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        t64 = time.perf_counter() - t64
+        d = u.double() - u64
+        err = {"max_abs": float(d.abs().max()), "l2": float(d.pow(2).mean().sqrt()),
+               "fp64_seconds": round(t64, 3), "fp64_iters_mean_after_10": round(float(np.mean(its64[10:] or its64)), 2),
+               "steps_with_equal_iteration_counts": int(sum(a == b for a, b in zip(its, its64))),
+               "mass_fp32_minus_fp64": info.mass - inf64.mass}
+        del u64, up64, work64
     out = {"steps": nsteps, "seconds": round(elapsed, 3), "steps_per_s": round(nsteps / elapsed, 2),
            "gpt_sweeps_per_s": round(pts * sum(4 + 7 * k for k in its) / elapsed / 1e9, 1),
            "iters_first_10": its[:10], "iters_last_10": its[-10:],
            "iters_min_max_mean_after_10": [min(its[10:] or its), max(its[10:] or its),
                                            round(float(np.mean(its[10:] or its)), 2)],
            "ms_per_step_after_10": round(1e3 * float(np.mean(secs[10:] or secs)), 3),
-           "mass_last": info.mass, "energy_last": info.energy}
+           "mass_last": info.mass, "energy_last": info.energy, "fp32_vs_fp64_after_all_steps": err}
     print(f"full workload: {json.dumps(out)}", file=sys.stderr, flush=True)
     return out
 
