@@ -3,6 +3,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <atomic>
 #include <deque>
 #include <map>
 #include <mutex>
@@ -605,7 +606,7 @@ struct IterGraph {
 static std::mutex g_graph_mu;
 static std::vector<IterGraph> g_iter_graphs;
 static unsigned long long g_graph_clock = 0;
-static bool g_iter_graph_on = true;
+static std::atomic<bool> g_iter_graph_on{true};
 static std::map<int, hipStream_t> g_capture_streams;
 
 static hipStream_t capture_stream(int dev) {
@@ -1870,7 +1871,6 @@ int32_t molt_set_option(int32_t option, int64_t value) {
     return MOLT_OK;
   }
   if (option == MOLT_OPT_STEP_GRAPH && (value == 0 || value == 1)) {
-    std::lock_guard<std::mutex> lock(g_graph_mu);
     g_iter_graph_on = value == 1;
     return MOLT_OK;
   }
