@@ -206,7 +206,8 @@ struct ProgP2F {  // P2 of the full form: raw (a1, b1, base), e = g(base), lin =
 template <typename T>
 struct ProgP3 {  // y, alpha2: raw (C, q) -> m = Y2(q + kappa C) - q, n = Y2 q
   static constexpr int F = 2, E = 1, NR = 2, NO = 2;
-  static constexpr bool NT = true;
+  // cacheable outputs, read back by P4 (4096^2: P3 56 -> 50 us, P4 84 -> 83 us)
+  static constexpr bool NT = false;
   __device__ static bool need(const PassArgs&, int) { return true; }
   __device__ static void sin(const PassArgs& a, const T* r, T* s) {
     s[0] = r[1] + (T)a.kappa * r[0];
