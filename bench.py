@@ -204,10 +204,12 @@ def run_batched(args, molt, synth):
         ws = molt.workspace(max(molt.ch_workspace_bytes(*spec(d)) for d in inst))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        iters_p = []
+        iters_p, secs_p = [], []
         for i, d in enumerate(inst):
             g, p = spec(d)
+            ti = time.perf_counter()
             _, infos = molt.solve(xp[i], g, p, args.batch_steps, work=ws)
+            secs_p.append(time.perf_counter() - ti)
             iters_p.append([r.iters for r in infos])
             if (i + 1) % 32 == 0:
                 print(f"batched: plain path {i + 1}/{len(inst)} instances, {time.perf_counter() - t0:.1f} s",
@@ -218,6 +220,25 @@ def run_batched(args, molt, synth):
                     "speedup_vs_plain": round(tp / tb, 2),
                     "bitwise_equal_to_plain": all(torch.equal(xp[i], xs[i]) for i in range(len(inst))),
                     "same_iterations_as_plain": iters_p == iters})
+        # the instance with the most ticks sets the batch's wall time: alone
+        # in a batch of one and on the plain path
+        k = int(np.argmax(ticks))
+        d = inst[k]
+        xt = u0[k].clone()
+        g, p = spec(d)
+        with torch.cuda.stream(s):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            molt.solve_batch([(g, p, xt, args.batch_steps)])
+            torch.cuda.synchronize()
+            ta = time.perf_counter() - t0
+        out["tail"] = {"instance": k, "n": d["n"], "bc": d["bc"], "stepper": d["stepper"], "ticks": ticks[k],
+                       "iters_per_step_mean": round(float(np.mean(iters[k])), 1),
+                       "alone_in_a_batch_s": round(ta, 3), "us_per_tick_alone": round(1e6 * ta / ticks[k], 1),
+                       "plain_s": round(secs_p[k], 3),
+                       "us_per_iteration_plain": round(1e6 * secs_p[k] / max(sum(iters[k]), 1), 1),
+                       "alone_share_of_batched_s": round(ta / tb, 3),
+                       "bitwise_equal_to_batched": bool(torch.equal(xt, xs[k]))}
     print(f"batched: {json.dumps(out)}", file=sys.stderr, flush=True)
     return out
 
