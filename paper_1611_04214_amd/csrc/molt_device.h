@@ -26,6 +26,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "molt_internal.h"
 
 // Minimum waves per SIMD requested for the line-pass kernels (caps their VGPRs).
@@ -72,10 +74,14 @@ __device__ __forceinline__ int wrap1(int j, int n) { return j < 0 ? j + n : (j >
 // and the constant drops out of C1 g.
 // --------------------------------------------------------------------------
 enum ProgId { PROG_SWEEP = 0, PROG_RHS = 1, PROG_P1 = 2, PROG_P2 = 3, PROG_P3 = 4, PROG_P4 = 5, PROG_P1V = 6,
-              PROG_P2V = 7, PROG_P2F = 8, PROG_P4F = 9 };
+              PROG_P2V = 7, PROG_P2F = 8, PROG_P4F = 9, PROG_RHSW = 10 };
 // P2F, P4F: P2 and P4 of the full form (first iteration, FP64 restarts) with
-// the increment-form inputs left out (fewer registers); timed under P2, P4
-constexpr int prog_slot(int prog) { return prog == PROG_P2F ? PROG_P2 : (prog == PROG_P4F ? PROG_P4 : prog); }
+// the increment-form inputs left out (fewer registers); RHSW: the rhs read
+// from FP32 fields by the FP64 kernels (the setup of an FP32 step, without
+// widened copies of u^n and its histories); timed under P2, P4, RHS
+constexpr int prog_slot(int prog) {
+  return prog == PROG_P2F ? PROG_P2 : (prog == PROG_P4F ? PROG_P4 : (prog == PROG_RHSW ? PROG_RHS : prog));
+}
 
 template <typename T>
 struct ProgSweep {  // w = L^{-1} in0
@@ -109,6 +115,20 @@ struct ProgRhs {  // w = L^{-1} rhs, rhs = u^n (BE), (4u^n - u^{n-1})/3 (BDF2), 
     o[0] = w[0];
     return 0.0;
   }
+};
+
+template <typename T>
+struct ProgRhsW : ProgRhs<T> {};  // ProgRhs on FP32 raw fields (see RawType)
+
+// element type of a program's raw input fields: T, except the FP32 fields the
+// FP64 rhs of an FP32 step reads (converted exactly on load)
+template <class P, typename T>
+struct RawType {
+  using type = T;
+};
+template <>
+struct RawType<ProgRhsW<double>, double> {
+  using type = float;
 };
 
 // reaction part and linear part of the current iterate; the fields hold
@@ -310,14 +330,15 @@ template <typename T> struct ProgOf<PROG_P3, T> { using type = ProgP3<T>; };
 template <typename T> struct ProgOf<PROG_P4, T> { using type = ProgP4<T>; };
 template <typename T> struct ProgOf<PROG_P2F, T> { using type = ProgP2F<T>; };
 template <typename T> struct ProgOf<PROG_P4F, T> { using type = ProgP4F<T>; };
+template <typename T> struct ProgOf<PROG_RHSW, T> { using type = ProgRhsW<T>; };
 
 // field f of a program's raw inputs, or field 0 (always read, same size) in
 // place of a field it does not read: loads are then unconditional, so the
 // compiler can issue all of a thread's loads before the first use, and the
 // stand-in loads hit the cache lines of field 0's
 template <typename T, class P>
-__device__ __forceinline__ const T* raw_ptr(const PassArgs& a, int f) {
-  return (const T*)(P::need(a, f) ? a.in[f] : a.in[0]);
+__device__ __forceinline__ const typename RawType<P, T>::type* raw_ptr(const PassArgs& a, int f) {
+  return (const typename RawType<P, T>::type*)(P::need(a, f) ? a.in[f] : a.in[0]);
 }
 
 // raw values of one node (scalar loads; fields the program does not read are 0)
@@ -325,7 +346,7 @@ template <typename T, class P>
 __device__ __forceinline__ void load_raw(const PassArgs& a, size_t i, T* r) {
 #pragma unroll
   for (int f = 0; f < P::NR; ++f) {
-    const T v = raw_ptr<T, P>(a, f)[i];
+    const T v = (T)raw_ptr<T, P>(a, f)[i];
     r[f] = P::need(a, f) ? v : T(0);
   }
 }
@@ -352,6 +373,23 @@ __device__ __forceinline__ void st16(double* p, const double* o) { *(double2*)p 
 // totals kernel ran 41 -> 46 us after streamed stores).
 typedef float molt_f4v __attribute__((ext_vector_type(4)));
 typedef double molt_d2v __attribute__((ext_vector_type(2)));
+// 16/sizeof(T) consecutive raw values of field f at element `off` (the FP32
+// fields of an FP64 program: one 8-byte load of two floats, widened)
+template <typename T, class P>
+__device__ __forceinline__ void ld16_raw(const PassArgs& a, int f, size_t off, T* o) {
+  using R = typename RawType<P, T>::type;
+  const R* p = raw_ptr<T, P>(a, f) + off;
+  if constexpr (std::is_same<R, T>::value) {
+    ld16(p, o);
+  } else {
+    static_assert(sizeof(T) == 8 && sizeof(R) == 4, "FP32 inputs of FP64 programs only");
+    typedef float v2 __attribute__((ext_vector_type(2)));
+    const v2 x = *(const v2*)p;
+    o[0] = (T)x.x;
+    o[1] = (T)x.y;
+  }
+}
+
 __device__ __forceinline__ void st16_nt(float* p, const float* o) {
   const molt_f4v v = {o[0], o[1], o[2], o[3]};
   __builtin_nontemporal_store(v, (molt_f4v*)p);
@@ -448,7 +486,7 @@ struct Seg {
       for (int q = 0; q < K / V; ++q) {
         T r[NR][V];
 #pragma unroll
-        for (int f = 0; f < NR; ++f) ld16(raw_ptr<T, P>(a, f) + lbase + (size_t)(j0 + q * V), r[f]);
+        for (int f = 0; f < NR; ++f) ld16_raw<T, P>(a, f, lbase + (size_t)(j0 + q * V), r[f]);
 #pragma unroll
         for (int v = 0; v < V; ++v) {
           T rv[NR], sv[F], xv[E > 0 ? E : 1];
@@ -859,7 +897,7 @@ __device__ __forceinline__ void xpass_body(const LineCoef& c, const PassArgs& a,
         const int e0 = (it * TL + t) * V;
         const size_t off = lbase + (size_t)(e0 < n ? e0 : 0);
 #pragma unroll
-        for (int f = 0; f < NR; ++f) ld16(raw_ptr<T, P>(a, f) + off, r[it][f]);
+        for (int f = 0; f < NR; ++f) ld16_raw<T, P>(a, f, off, r[it][f]);
         const int ec = e0 < n ? e0 : 0;
         const int is = kEarly ? it : 0;
 #pragma unroll

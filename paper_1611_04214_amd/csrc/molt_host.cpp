@@ -120,7 +120,7 @@ void tune_get(int prec, int cls, int* kx, int* ky);
 void tune_set(int prec, int cls, int kx, int ky);
 
 enum { PROG_SWEEP = 0, PROG_RHS = 1, PROG_P1 = 2, PROG_P2 = 3, PROG_P3 = 4, PROG_P4 = 5, PROG_P1V = 6, PROG_P2V = 7,
-       PROG_P2F = 8, PROG_P4F = 9 };
+       PROG_P2F = 8, PROG_P4F = 9, PROG_RHSW = 10 };
 
 // --------------------------------------------------------------------------
 // errors
@@ -453,12 +453,13 @@ static YCorr make_ycorr(int prec, const LineCoef& c, int nx, int nf, const void*
 // R = A1^{-1} A2^{-1} rhs, A_i^{-1} = Lx_i^{-1} Ly_i^{-1} (Sec. 5.1, first term
 // of eq. CH_BE_2D_3), with rhs of the stepper (eq. CH_BE; eqs. BDF2, BDF3) from
 // in0..in2 = u^n, u^{n-1}, u^{n-2}; A1, B1 are scratch fields of the precision
+// (rhs_prog: PROG_RHS, or PROG_RHSW for FP64 kernels reading FP32 fields)
 static int32_t enqueue_rhs(int prec, const StepGeo& G, const PassArgs& rhs_args, void* const* F, void* tot, void* jln,
-                           DevState* st, hipStream_t s) {
+                           DevState* st, hipStream_t s, int rhs_prog = PROG_RHS) {
   PassArgs a = rhs_args;
   if (G.two_d) {
     a.out[0] = F[F_A1];
-    HIPCHK(launch_ypass(prec, PROG_RHS, G.cy2, a, st, G.nx, G.nc, tot, jln, true, s));
+    HIPCHK(launch_ypass(prec, rhs_prog, G.cy2, a, st, G.nx, G.nc, tot, jln, true, s));
     a.in[0] = F[F_A1];
     a.out[0] = F[F_B1];
     a.corr = make_ycorr(prec, G.cy2, G.nx, 1, tot);
@@ -473,7 +474,7 @@ static int32_t enqueue_rhs(int prec, const StepGeo& G, const PassArgs& rhs_args,
     HIPCHK(launch_xpass(prec, PROG_SWEEP, G.cx1, a, nullptr, G.xl, nullptr, s));
   } else {
     a.out[0] = F[F_B1];
-    HIPCHK(launch_xpass(prec, PROG_RHS, G.cx2, a, nullptr, G.xl, nullptr, s));
+    HIPCHK(launch_xpass(prec, rhs_prog, G.cx2, a, nullptr, G.xl, nullptr, s));
     a.in[0] = F[F_B1];
     a.out[0] = F[F_R];
     HIPCHK(launch_xpass(prec, PROG_SWEEP, G.cx1, a, nullptr, G.xl, nullptr, s));
@@ -791,20 +792,19 @@ static int32_t step_impl(const molt_grid* g, const molt_ch_params* p, void* d_u,
     MOLT_RC(enqueue_rhs(prec, G, ra, F, tot, jln, st, s));
     base = p->init == MOLT_INIT_LINEAR ? F[F_R] : d_u;
   } else {
-    // FP64 shadow: the inputs widened, R and the first iteration in FP64,
-    // then the iterate re-based and the increment narrowed for the FP32
-    // iterations
-    void* u64 = w + L.in64[0];
-    void* p64 = w + L.in64[1];
-    void* q64 = w + L.in64[2];
-    HIPCHK(launch_widen(u64, d_u, nel, s));
-    if (bdf2) HIPCHK(launch_widen(p64, d_u_prev, nel, s));
-    if (bdf3) HIPCHK(launch_widen(q64, d_u_prev2, nel, s));
-    ra.in[0] = u64;
-    ra.in[1] = bdf2 ? p64 : u64;
-    ra.in[2] = bdf3 ? q64 : u64;
-    MOLT_RC(enqueue_rhs(MOLT_F64, G, ra, F64, w + L.tot64, w + L.jln64, st, s));
-    base64 = p->init == MOLT_INIT_LINEAR ? F64[F_R] : u64;
+    // FP64 shadow: R (the FP64 kernels read the FP32 fields, widening each
+    // value exactly) and the first iteration in FP64, then the iterate
+    // re-based and the increment narrowed for the FP32 iterations
+    ra.in[0] = d_u;
+    ra.in[1] = bdf2 ? d_u_prev : d_u;
+    ra.in[2] = bdf3 ? d_u_prev2 : d_u;
+    MOLT_RC(enqueue_rhs(MOLT_F64, G, ra, F64, w + L.tot64, w + L.jln64, st, s, PROG_RHSW));
+    base64 = F64[F_R];
+    if (p->init != MOLT_INIT_LINEAR) {  // the first iterate is u^n itself, in FP64
+      void* u64 = w + L.in64[0];
+      HIPCHK(launch_widen(u64, d_u, nel, s));
+      base64 = u64;
+    }
     MOLT_RC(enqueue_iteration(MOLT_F64, G, sp, ush, 0, base64, F64, w + L.tot64, w + L.jln64, st, rpart, false, s));
     // the FP32 iterations' base is the first iterate rounded to FP32, their
     // running sum starts at its rounding error

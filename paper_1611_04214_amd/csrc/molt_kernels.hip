@@ -405,7 +405,7 @@ static hipError_t xpass_t(const LineCoef& c, const PassArgs& a, DevState* st, in
   int k = xpass_pick_k(c.n, prec);
   // the FP64 iteration passes (several fields per node) spill registers at 16
   // nodes per thread; they take 8 in rows of up to 512 threads
-  if (sizeof(T) == 8 && k == 16 && prog_slot(PI) != PROG_SWEEP && PI != PROG_RHS && c.n <= 512 * 8) k = 8;
+  if (sizeof(T) == 8 && k == 16 && prog_slot(PI) != PROG_SWEEP && prog_slot(PI) != PROG_RHS && c.n <= 512 * 8) k = 8;
   switch (k) {
     case 4: return xpass_k<T, PI, 4>(c, a, st, nlines, rpart, s);
     case 8: return xpass_k<T, PI, 8>(c, a, st, nlines, rpart, s);
@@ -429,6 +429,7 @@ hipError_t MOLT_KFN(launch_xpass)(int prog, const LineCoef& c, const PassArgs& a
 #ifdef MOLT_PREC_F64
     case PROG_P2F: return xpass_t<MOLT_KT, PROG_P2F>(c, a, st, nlines, rpart, s, prec);
     case PROG_P4F: return xpass_t<MOLT_KT, PROG_P4F>(c, a, st, nlines, rpart, s, prec);
+    case PROG_RHSW: return xpass_t<MOLT_KT, PROG_RHSW>(c, a, st, nlines, rpart, s, prec);
 #endif
   }
   return hipErrorInvalidValue;
@@ -450,10 +451,10 @@ static hipError_t ypass_km(const LineCoef& c, const PassArgs& a, DevState* st, i
   dim3 grid((nx + 63) / 64, nseg, batch);
   hipError_t e;
   if (deferred) {
-    launch_timed(prof_kind<MOLT_KT>(KF_YFIN * 8 + PI), yloc_kernel<T, PI, K, M, PER>, grid, blk, 0, s, c, a, st, nx,
+    launch_timed(prof_kind<MOLT_KT>(KF_YFIN * 8 + prog_slot(PI)), yloc_kernel<T, PI, K, M, PER>, grid, blk, 0, s, c, a, st, nx,
                  nth, nseg, fstride, tot, jln);
   } else {
-    launch_timed(prof_kind<MOLT_KT>(KF_YTOT * 8 + PI), ytot_kernel<T, PI, K, M, PER>, grid, blk, 0, s, c, a, st, nx,
+    launch_timed(prof_kind<MOLT_KT>(KF_YTOT * 8 + prog_slot(PI)), ytot_kernel<T, PI, K, M, PER>, grid, blk, 0, s, c, a, st, nx,
                  nth, nseg, fstride, tot, jln);
   }
   e = hipGetLastError();
@@ -462,7 +463,7 @@ static hipError_t ypass_km(const LineCoef& c, const PassArgs& a, DevState* st, i
   const int ct = (nseg + kCombWaves - 1) / kCombWaves;
   const dim3 cgrid((nx + 63) / 64, P::F, batch), cblk(64, kCombWaves);
   const int S = kRG * K;
-  const int ckind = prof_kind<MOLT_KT>(KF_YCOMB * 8 + PI);
+  const int ckind = prof_kind<MOLT_KT>(KF_YCOMB * 8 + prog_slot(PI));
   if (ct <= 8)
     launch_timed(ckind, ycomb_kernel<T, 8>, cgrid, cblk, 0, s, c, st, nx, nseg, S, (int)P::F, tot, (const T*)jln);
   else if (ct <= 16)
@@ -473,7 +474,7 @@ static hipError_t ypass_km(const LineCoef& c, const PassArgs& a, DevState* st, i
     return hipErrorInvalidValue;
   e = hipGetLastError();
   if (e != hipSuccess || deferred) return e;
-  launch_timed(prof_kind<MOLT_KT>(KF_YFIN * 8 + PI), yfin_kernel<T, PI, K, M, PER>, grid, blk, 0, s, c, a, st, nx,
+  launch_timed(prof_kind<MOLT_KT>(KF_YFIN * 8 + prog_slot(PI)), yfin_kernel<T, PI, K, M, PER>, grid, blk, 0, s, c, a, st, nx,
                nth, nseg, fstride, (const T*)tot);
   return hipGetLastError();
 }
@@ -511,6 +512,9 @@ hipError_t MOLT_KFN(launch_ypass)(int prog, const LineCoef& c, const PassArgs& a
   switch (prog) {
     case PROG_SWEEP: return ypass_t<MOLT_KT, PROG_SWEEP>(c, a, st, nx, batch, tot, jln, deferred, s);
     case PROG_RHS: return ypass_t<MOLT_KT, PROG_RHS>(c, a, st, nx, batch, tot, jln, deferred, s);
+#ifdef MOLT_PREC_F64
+    case PROG_RHSW: return ypass_t<MOLT_KT, PROG_RHSW>(c, a, st, nx, batch, tot, jln, deferred, s);
+#endif
     case PROG_P1: return ypass_t<MOLT_KT, PROG_P1>(c, a, st, nx, batch, tot, jln, deferred, s);
     case PROG_P3: return ypass_t<MOLT_KT, PROG_P3>(c, a, st, nx, batch, tot, jln, deferred, s);
     case PROG_P1V: return ypass_t<MOLT_KT, PROG_P1V>(c, a, st, nx, batch, tot, jln, deferred, s);
