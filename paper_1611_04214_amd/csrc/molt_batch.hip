@@ -51,8 +51,8 @@ struct SlotView {
   void* const* F;
   void* tot;
   void* jln;
-  const void* u;     // u^n as the rhs reads it
-  const void* hist;  // u^{n-1}
+  const void* u;     // u^n as the rhs reads it (a hybrid slot's FP64 rhs: the FP32 field)
+  const void* hist;  // u^{n-1} (likewise)
   const void* base;  // the iterate is base + W
   int32_t ynth, ynseg, yk, tlx, vecx, xblocks;
 };
@@ -60,7 +60,7 @@ template <typename T>
 __device__ __forceinline__ SlotView slot_view(const SlotDesc& d) {
   const bool lin = d.init == MOLT_INIT_LINEAR;
   if (sizeof(T) == 8 && d.hybrid)  // first iteration from R or u^n, restarts from the iterate in F_HIST
-    return SlotView{d.fld64, d.tot64, d.jln64, d.u64, d.hist64,
+    return SlotView{d.fld64, d.tot64, d.jln64, d.u, d.fld[F_HIST],
                     d.st->iters == 0 ? (lin ? d.fld64[F_R] : d.u64) : d.fld64[F_HIST],
                     d.ynth64, d.ynseg64, d.yk64, d.tlx64, d.vecx64, d.xblocks64};
   // (a hybrid slot's FP32 iterations run from the re-based first iterate in F_R)
@@ -178,6 +178,13 @@ __global__ void MOLT_PASS_ATTR ypass_batch_kernel(const SlotDesc* __restrict__ s
     constexpr int PR = PASS == 1 ? PROG_RHS : PROG_SWEEP;
     const PassArgs a = slot_args(d, v, PH_R, PASS, var, 0);
     const LineCoef& c = d.cy[var][PASS == 1 ? 1 : 0];
+    if constexpr (sizeof(T) == 8 && PASS == 1) {
+      if (d.hybrid) {  // the FP64 rhs of an FP32 slot reads its FP32 fields
+        yloc_body<T, PROG_RHSW, K, M, PER>(c, a, nullptr, d.nx, v.ynth, v.ynseg, fstride, (T*)v.tot, (T*)v.jln, bx,
+                                           by, bz);
+        return;
+      }
+    }
     yloc_body<T, PR, K, M, PER>(c, a, nullptr, d.nx, v.ynth, v.ynseg, fstride, (T*)v.tot, (T*)v.jln, bx, by, bz);
   } else {
     DevState* st = d.st;
@@ -299,16 +306,14 @@ __global__ void __launch_bounds__(256) widen_batch_kernel(const SlotDesc* __rest
   const BlkMap e = map[blockIdx.x];
   const SlotDesc& d = sd[e.slot];
   const SlotCtl cc = ctl[e.slot];
-  if (!d.hybrid || cc.phase != PH_R) return;
+  // (only the first iterate of an init-PREV slot, u^n, is read in FP64 from a
+  // copy: the rhs reads the FP32 fields)
+  if (!d.hybrid || cc.phase != PH_R || d.init == MOLT_INIT_LINEAR) return;
   const size_t n = (size_t)d.nx * (size_t)d.ny * (size_t)d.ncomp;
   const float* u = (const float*)d.u;
-  const float* h = (const float*)d.fld[F_HIST];
   double* u64 = (double*)d.u64;
-  double* h64 = (double*)d.hist64;
-  for (size_t i = (size_t)e.blk * blockDim.x + threadIdx.x; i < n; i += (size_t)d.dblocks * blockDim.x) {
+  for (size_t i = (size_t)e.blk * blockDim.x + threadIdx.x; i < n; i += (size_t)d.dblocks * blockDim.x)
     u64[i] = (double)u[i];
-    if (cc.var) h64[i] = (double)h[i];
-  }
 }
 
 // hybrid slots after an iteration (the tail of a tick, after the close): after

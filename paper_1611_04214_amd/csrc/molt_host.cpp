@@ -1008,6 +1008,7 @@ struct BatchPlan {
 // kernels, grouped by the FP64 shapes (yg64, xg64).
 struct BatchMaps {
   bool any_vch = false;  // a vector-model slot is listed: the tick runs the reaction pass
+  bool any_prev = false; // an init-PREV slot is listed: a hybrid tick widens u^n for it
   bool hybrid = false;
   std::vector<BatchGroup> yg, xg, yg64, xg64;
   size_t comb_off = 0, pt_off = 0, sl_off = 0;
@@ -1077,8 +1078,10 @@ static void batch_pass_groups(const molt_instance* inst, const std::vector<int>&
 static void batch_maps(const molt_instance* inst, const std::vector<int>& act, int prec, BatchMaps& B) {
   B.map.clear();
   B.any_vch = false;
+  B.any_prev = false;
   B.hybrid = prec == MOLT_F32;
   for (int i : act) B.any_vch = B.any_vch || inst[i].params.model == MOLT_MODEL_VCH;
+  for (int i : act) B.any_prev = B.any_prev || inst[i].params.init != MOLT_INIT_LINEAR;
   std::vector<BlkMap>& m = B.map;
   batch_pass_groups(inst, act, prec, m, B.yg, B.xg);
   B.yg64.clear();
@@ -1241,7 +1244,7 @@ static hipError_t batch_tick(int prec, const BatchMaps& B, const SlotDesc* sd, S
   // or first iteration) and in the FP32 kernels (the others)
   const int nprec = B.hybrid ? 2 : 1;
   const int precs[2] = {B.hybrid ? MOLT_F64 : prec, prec};
-  if (B.hybrid && (e = launch_batch_widen(sd, ctl, map + B.pt_off, B.pt_n, s)) != hipSuccess) return e;
+  if (B.hybrid && B.any_prev && (e = launch_batch_widen(sd, ctl, map + B.pt_off, B.pt_n, s)) != hipSuccess) return e;
   for (int k = 0; k < nprec && B.any_vch; ++k)
     if ((e = launch_batch_react(precs[k], sd, ctl, map + B.pt_off, B.pt_n, s)) != hipSuccess) return e;
   for (int pass = 1; pass <= 3; pass += 2) {
