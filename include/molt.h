@@ -196,7 +196,10 @@ size_t ch_workspace_bytes(const molt_grid* grid, const molt_ch_params* params);
  *            NULL it receives u^n on return (history rotated in place).  BDF3:
  *            two fields [u^{n-1} | u^{n-2}] (see have_prev), rotated likewise.
  *  info:     filled when not NULL.
- * Synchronizes `stream` before returning.
+ * Synchronizes `stream` before returning.  The library remembers the
+ * iteration count of the last step run in each workspace and uses it to size
+ * its batches of queued iterations on the next call with that workspace
+ * (results do not depend on it).
  */
 int32_t ch_step(const molt_grid* grid, const molt_ch_params* params, void* d_u, void* d_u_prev,
                 void* d_work, size_t work_bytes, molt_step_info* info, void* stream);
