@@ -74,13 +74,15 @@ __device__ __forceinline__ int wrap1(int j, int n) { return j < 0 ? j + n : (j >
 // and the constant drops out of C1 g.
 // --------------------------------------------------------------------------
 enum ProgId { PROG_SWEEP = 0, PROG_RHS = 1, PROG_P1 = 2, PROG_P2 = 3, PROG_P3 = 4, PROG_P4 = 5, PROG_P1V = 6,
-              PROG_P2V = 7, PROG_P2F = 8, PROG_P4F = 9, PROG_RHSW = 10 };
+              PROG_P2V = 7, PROG_P2F = 8, PROG_P4F = 9, PROG_RHSW = 10, PROG_P4R = 11 };
 // P2F, P4F: P2 and P4 of the full form (first iteration, FP64 restarts) with
 // the increment-form inputs left out (fewer registers); RHSW: the rhs read
 // from FP32 fields by the FP64 kernels (the setup of an FP32 step, without
-// widened copies of u^n and its histories); timed under P2, P4, RHS
+// widened copies of u^n and its histories); P4R: P4F writing the re-based FP32
+// iterate of an FP32 step; timed under P2, P4, RHS, P4
 constexpr int prog_slot(int prog) {
-  return prog == PROG_P2F ? PROG_P2 : (prog == PROG_P4F ? PROG_P4 : (prog == PROG_RHSW ? PROG_RHS : prog));
+  return prog == PROG_P2F ? PROG_P2
+                          : ((prog == PROG_P4F || prog == PROG_P4R) ? PROG_P4 : (prog == PROG_RHSW ? PROG_RHS : prog));
 }
 
 template <typename T>
@@ -129,6 +131,12 @@ struct RawType {
 template <>
 struct RawType<ProgRhsW<double>, double> {
   using type = float;
+};
+// element type of a program's outputs: T, except P4R's FP32 fields (each
+// output rounded once on store)
+template <class P, typename T>
+struct OutType {
+  using type = T;
 };
 
 // reaction part and linear part of the current iterate; the fields hold
@@ -278,6 +286,42 @@ struct ProgP4F {  // P4 of the full form: raw (m, n, R) -> dl' = R + X2 m - n, W
   }
 };
 
+template <typename T>
+struct ProgP4R {  // P4F of an FP64 iteration in an FP32 step: raw (m, n, R), the iterate's base read
+                  // late (see Late) -> the FP32 fields the FP32 iterations continue from (see
+                  // OutType): dl' = R + X2 m - n, v = base + (0 + dl') split into fl32(v) and the rest
+  static constexpr int F = 1, E = 2, NR = 3, NO = 3;
+  static constexpr bool NT = false;
+  __device__ static bool need(const PassArgs&, int) { return true; }
+  __device__ static void sin(const PassArgs&, const T* r, T* s) { s[0] = r[0]; }
+  __device__ static void ext(const PassArgs&, const T* r, T* x) {
+    x[0] = r[1];
+    x[1] = r[2];
+  }
+  // x[2]: the late input, the base of the iterate
+  __device__ static double fin(const PassArgs&, const T* w, const T* x, T* o) {
+    const T dn = x[1] + w[0] - x[0];
+    const T wn = T(0) + dn;  // (P4F's W', which the FP64 iterate holds)
+    const T v = x[2] + wn;
+    const T b = (T)(float)v;
+    o[0] = wn;     // dl', rounded to FP32 by the store (dl' = W' in the full form)
+    o[1] = v - b;  // the FP32 running sum starts at the rounding error of the base
+    o[2] = b;      // the FP32 base
+    return fabs((double)dn);
+  }
+};
+
+// inputs a program reads only where it forms its outputs (a.in[NR], ...),
+// appended to its kept values: no registers held across the pass
+template <class P>
+struct Late {
+  static constexpr int n = 0;
+};
+template <typename T>
+struct Late<ProgP4R<T>> {
+  static constexpr int n = 1;
+};
+
 // Vector model: the reaction and linear parts (e, lin) of both components are
 // formed by a pointwise pre-pass (vch_react_body); P1 and P2 then sweep them
 // like any stacked pair of fields.
@@ -331,6 +375,11 @@ template <typename T> struct ProgOf<PROG_P4, T> { using type = ProgP4<T>; };
 template <typename T> struct ProgOf<PROG_P2F, T> { using type = ProgP2F<T>; };
 template <typename T> struct ProgOf<PROG_P4F, T> { using type = ProgP4F<T>; };
 template <typename T> struct ProgOf<PROG_RHSW, T> { using type = ProgRhsW<T>; };
+template <typename T> struct ProgOf<PROG_P4R, T> { using type = ProgP4R<T>; };
+template <>
+struct OutType<ProgP4R<double>, double> {
+  using type = float;
+};
 
 // field f of a program's raw inputs, or field 0 (always read, same size) in
 // place of a field it does not read: loads are then unconditional, so the
@@ -405,6 +454,25 @@ __device__ __forceinline__ void st16_out(T* p, const T* o) {
 template <bool NT, typename T>
 __device__ __forceinline__ void st1_out(T* p, T v) {
   if constexpr (NT) __builtin_nontemporal_store(v, p); else *p = v;
+}
+// output f of a program: 16/sizeof(T) values at element `off`, or one value at
+// element `i` (FP32 outputs of an FP64 program: rounded, one 8-byte store)
+template <typename T, class P>
+__device__ __forceinline__ void st16_prog(const PassArgs& a, int f, size_t off, const T* o) {
+  using O = typename OutType<P, T>::type;
+  if constexpr (std::is_same<O, T>::value) {
+    st16_out<P::NT>((T*)a.out[f] + off, o);
+  } else {
+    static_assert(sizeof(T) == 8 && sizeof(O) == 4, "FP32 outputs of FP64 programs only");
+    typedef float v2 __attribute__((ext_vector_type(2)));
+    const v2 x = {(float)o[0], (float)o[1]};
+    *(v2*)((O*)a.out[f] + off) = x;
+  }
+}
+template <typename T, class P>
+__device__ __forceinline__ void st1_prog(const PassArgs& a, int f, size_t i, T v) {
+  using O = typename OutType<P, T>::type;
+  st1_out<P::NT>((O*)a.out[f] + i, (O)v);
 }
 
 // Corrections an x-pass applies to the raw fields it reads from a deferred
@@ -702,7 +770,7 @@ struct Seg {
           for (int f = 0; f < NO; ++f) o[f][v] = ok[f];
         }
 #pragma unroll
-        for (int f = 0; f < NO; ++f) st16_out<P::NT>((T*)a.out[f] + lbase + (size_t)(j0 + q * V), o[f]);
+        for (int f = 0; f < NO; ++f) st16_prog<T, P>(a, f, lbase + (size_t)(j0 + q * V), o[f]);
       }
     } else {
 #pragma unroll
@@ -716,7 +784,7 @@ struct Seg {
           for (int e = 0; e < E; ++e) xk[e] = ex[e][k];
           res = fmax(res, P::fin(a, wk, xk, ok));
 #pragma unroll
-          for (int f = 0; f < NO; ++f) st1_out<P::NT>((T*)a.out[f] + lbase + (size_t)j * stride, ok[f]);
+          for (int f = 0; f < NO; ++f) st1_prog<T, P>(a, f, lbase + (size_t)j * stride, ok[f]);
         }
       }
     }
@@ -843,7 +911,7 @@ template <typename T, int PI, int K, int M, bool PER, int BS = 256>
 __device__ __forceinline__ void xpass_body(const LineCoef& c, const PassArgs& a, DevState* st, int nlines, int TL,
                                            double* rpart, int vec, int bx, T* smem) {
   using P = typename ProgOf<PI, T>::type;
-  constexpr int F = P::F, E = P::E, NR = P::NR, NO = P::NO;
+  constexpr int F = P::F, E = P::E, NR = P::NR, NO = P::NO, LT = Late<P>::n;
   constexpr int H = M / 2, W = K + 2 * H;
   constexpr int V = 16 / (int)sizeof(T);
   constexpr int ROW = BS * K;  // nodes of all rows of one block
@@ -889,7 +957,7 @@ __device__ __forceinline__ void xpass_body(const LineCoef& c, const PassArgs& a,
       // folds them as they arrive: that frees the registers for a second
       // block per CU (FP64 P4 at 4096^2: 208 -> 160 us; the FP64 sweeps lose
       // by it, 72 -> 87 us, and P2 does not reach the next occupancy step)
-      constexpr bool kEarly = !(sizeof(T) == 8 && (PI == PROG_P4 || PI == PROG_P4F));
+      constexpr bool kEarly = !(sizeof(T) == 8 && prog_slot(PI) == PROG_P4);
       constexpr int KS = kEarly ? K / V : 1;
       T sl[KS][NC][V], sr[KS][NC][V];
 #pragma unroll
@@ -1085,19 +1153,24 @@ __device__ __forceinline__ void xpass_body(const LineCoef& c, const PassArgs& a,
         const int e0 = (it * TL + t) * V;
         if (e0 < n) {
           T o[NO][V];
+          T lv[LT > 0 ? LT : 1][V];
+#pragma unroll
+          for (int l = 0; l < LT; ++l) ld16((const T*)a.in[NR + l] + lbase + (size_t)e0, lv[l]);
 #pragma unroll
           for (int v = 0; v < V; ++v) {
-            T wk[F], xk[E > 0 ? E : 1], ok[NO];
+            T wk[F], xk[E + LT > 0 ? E + LT : 1], ok[NO];
 #pragma unroll
             for (int f = 0; f < F; ++f) wk[f] = sh_row[f][MOLT_PAD(rowoff + e0 + v)];
 #pragma unroll
             for (int e = 0; e < E; ++e) xk[e] = seg.ex[e][it * V + v];
+#pragma unroll
+            for (int l = 0; l < LT; ++l) xk[E + l] = lv[l][v];
             resid = fmax(resid, P::fin(a, wk, xk, ok));
 #pragma unroll
             for (int f = 0; f < NO; ++f) o[f][v] = ok[f];
           }
 #pragma unroll
-          for (int f = 0; f < NO; ++f) st16_out<P::NT>((T*)a.out[f] + lbase + (size_t)e0, o[f]);
+          for (int f = 0; f < NO; ++f) st16_prog<T, P>(a, f, lbase + (size_t)e0, o[f]);
         }
       }
     } else {
@@ -1105,14 +1178,16 @@ __device__ __forceinline__ void xpass_body(const LineCoef& c, const PassArgs& a,
       for (int it = 0; it < K; ++it) {
         const int e = it * TL + t;
         if (e < n) {
-          T wk[F], xk[E > 0 ? E : 1], ok[NO];
+          T wk[F], xk[E + LT > 0 ? E + LT : 1], ok[NO];
 #pragma unroll
           for (int f = 0; f < F; ++f) wk[f] = sh_row[f][MOLT_PAD(rowoff + e)];
 #pragma unroll
           for (int q = 0; q < E; ++q) xk[q] = seg.ex[q][it];
+#pragma unroll
+          for (int l = 0; l < LT; ++l) xk[E + l] = ((const T*)a.in[NR + l])[lbase + (size_t)e];
           resid = fmax(resid, P::fin(a, wk, xk, ok));
 #pragma unroll
-          for (int f = 0; f < NO; ++f) st1_out<P::NT>((T*)a.out[f] + lbase + (size_t)e, ok[f]);
+          for (int f = 0; f < NO; ++f) st1_prog<T, P>(a, f, lbase + (size_t)e, ok[f]);
         }
       }
     }

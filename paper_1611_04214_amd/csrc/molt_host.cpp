@@ -77,8 +77,6 @@ static hipError_t launch_addc(int prec, void* x, double c0, double c1, size_t n,
 #undef MOLT_PREC
 hipError_t launch_zero_ints(int* p, int n, hipStream_t s);
 hipError_t launch_widen(void* dst64, const void* src32, size_t n, hipStream_t s);
-hipError_t launch_rebase_mixed(void* base32, void* W32, void* DL32, const void* base64, const void* W64,
-                               const DevState* st, int expect, size_t n, hipStream_t s);
 hipError_t launch_iterate64(void* v64, const void* base32, const void* W32, const DevState* st, size_t n,
                             hipStream_t s);
 hipError_t launch_close_pending(const double* rpart, DevState* st, hipStream_t s);
@@ -120,7 +118,7 @@ void tune_get(int prec, int cls, int* kx, int* ky);
 void tune_set(int prec, int cls, int kx, int ky);
 
 enum { PROG_SWEEP = 0, PROG_RHS = 1, PROG_P1 = 2, PROG_P2 = 3, PROG_P3 = 4, PROG_P4 = 5, PROG_P1V = 6, PROG_P2V = 7,
-       PROG_P2F = 8, PROG_P4F = 9, PROG_RHSW = 10 };
+       PROG_P2F = 8, PROG_P4F = 9, PROG_RHSW = 10, PROG_P4R = 11 };
 
 // --------------------------------------------------------------------------
 // errors
@@ -488,10 +486,12 @@ static int32_t enqueue_rhs(int prec, const StepGeo& G, const PassArgs& rhs_args,
 // DL the last increment).  P4 writes DL, W and the residual partials; the
 // close (residual, count, stop) follows it, or with defer_close is left to
 // the next iteration's P1 y-pass or an explicit close.  P1 (2D) always closes
-// a pending previous iteration first.
+// a pending previous iteration first.  F32 (an FP64 full-form iteration of an
+// FP32 step): P4 writes the re-based FP32 iterate -- base fl32(v), running sum
+// v - fl32(v), increment -- into those fields instead of its FP64 outputs.
 static int32_t enqueue_iteration(int prec, const StepGeo& G, const StepParams& sp, const double* ush, int mode,
                                  const void* base, void* const* F, void* tot, void* jln, DevState* st, double* rpart,
-                                 bool defer_close, hipStream_t s) {
+                                 bool defer_close, hipStream_t s, void* const* F32) {
   PassArgs q;
   memset(&q, 0, sizeof(q));
   q.sigma = sp.sigma;
@@ -561,7 +561,15 @@ static int32_t enqueue_iteration(int prec, const StepGeo& G, const StepParams& s
   q.out[0] = F[F_DL];
   q.out[1] = F[F_W];
   q.defer_close = defer_close && G.two_d ? 1 : 0;
-  HIPCHK(launch_xpass(prec, full64 ? PROG_P4F : PROG_P4, G.cx2, q, st, G.xl, rpart, s));
+  int p4 = full64 ? PROG_P4F : PROG_P4;
+  if (full64 && F32 != nullptr) {
+    p4 = PROG_P4R;
+    q.in[3] = base;  // (read late: after the program's three raw fields)
+    q.out[0] = F32[F_DL];
+    q.out[1] = F32[F_W];
+    q.out[2] = F32[F_R];
+  }
+  HIPCHK(launch_xpass(prec, p4, G.cx2, q, st, G.xl, rpart, s));
   return MOLT_OK;
 }
 
@@ -622,7 +630,7 @@ static hipStream_t capture_stream(int dev) {
 // forward declaration (defined below)
 static int32_t enqueue_iteration(int prec, const StepGeo& G, const StepParams& sp, const double* ush, int mode,
                                  const void* base, void* const* F, void* tot, void* jln, DevState* st, double* rpart,
-                                 bool defer_close, hipStream_t s);
+                                 bool defer_close, hipStream_t s, void* const* F32 = nullptr);
 
 // the executable graph of kIterRun increment iterations for this key, captured
 // on first use; nullptr when graphs are off or the capture failed (the caller
@@ -805,10 +813,10 @@ static int32_t step_impl(const molt_grid* g, const molt_ch_params* p, void* d_u,
       HIPCHK(launch_widen(u64, d_u, nel, s));
       base64 = u64;
     }
-    MOLT_RC(enqueue_iteration(MOLT_F64, G, sp, ush, 0, base64, F64, w + L.tot64, w + L.jln64, st, rpart, false, s));
     // the FP32 iterations' base is the first iterate rounded to FP32, their
-    // running sum starts at its rounding error
-    HIPCHK(launch_rebase_mixed(F[F_R], F[F_W], F[F_DL], base64, F64[F_W], st, 1, nel, s));
+    // running sum starts at its rounding error (written by the iteration's P4)
+    MOLT_RC(enqueue_iteration(MOLT_F64, G, sp, ush, 0, base64, F64, w + L.tot64, w + L.jln64, st, rpart, false, s,
+                              F));
     base = F[F_R];
     it = 1;
   }
@@ -844,8 +852,8 @@ static int32_t step_impl(const molt_grid* g, const molt_ch_params* p, void* d_u,
         // FP64 restart: the full form from the iterate, then re-based
         void* v64 = F64[F_HIST];
         HIPCHK(launch_iterate64(v64, F[F_R], F[F_W], st, nel, s));
-        MOLT_RC(enqueue_iteration(MOLT_F64, G, sp, ush, 0, v64, F64, w + L.tot64, w + L.jln64, st, rpart, false, s));
-        HIPCHK(launch_rebase_mixed(F[F_R], F[F_W], F[F_DL], v64, F64[F_W], st, it + 1, nel, s));
+        MOLT_RC(enqueue_iteration(MOLT_F64, G, sp, ush, 0, v64, F64, w + L.tot64, w + L.jln64, st, rpart, false, s,
+                                  F));
         continue;
       }
       // a whole run of increment iterations with no restart in it: one graph launch

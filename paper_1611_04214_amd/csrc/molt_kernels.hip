@@ -270,27 +270,6 @@ __global__ void __launch_bounds__(256) widen_kernel(double* dst, const float* sr
     dst[i] = (double)src[i];
 }
 
-// After an FP64 (full-form) iteration that ran as iteration expect-1: the new
-// iterate v = base64 + W64 split into base32 = fl32(v) and W32 = fl32(v -
-// base32), and the increment narrowed, so that the FP32 increment iterations
-// add their increments to a running sum that starts at ~ulp(v).  In the full
-// form the increment equals W64 (P4 writes DL = W = its result), so DL64 is
-// not read.  Skipped when that iteration did not run (the step had converged
-// before it).
-__global__ void __launch_bounds__(256) rebase_mixed_kernel(float* base32, float* W32, float* DL32, const double* base64,
-                                                           const double* W64, const DevState* st, int expect,
-                                                           size_t n) {
-  if (st->iters != expect) return;
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-    const double w = W64[i];
-    const double v = base64[i] + w;
-    const float b = (float)v;
-    base32[i] = b;
-    W32[i] = (float)(v - (double)b);
-    DL32[i] = (float)w;
-  }
-}
-
 // Before an FP64 restart iteration: the iterate base32 + W32 in FP64 (unless
 // the step has converged)
 __global__ void __launch_bounds__(256) iterate64_kernel(double* v64, const float* base32, const float* W32,
@@ -306,12 +285,6 @@ static dim3 grid_elems(size_t n) {
 }
 hipError_t launch_widen(void* dst64, const void* src32, size_t n, hipStream_t s) {
   hipLaunchKernelGGL(widen_kernel, grid_elems(n), dim3(256), 0, s, (double*)dst64, (const float*)src32, n);
-  return hipGetLastError();
-}
-hipError_t launch_rebase_mixed(void* base32, void* W32, void* DL32, const void* base64, const void* W64,
-                               const DevState* st, int expect, size_t n, hipStream_t s) {
-  hipLaunchKernelGGL(rebase_mixed_kernel, grid_elems(n), dim3(256), 0, s, (float*)base32, (float*)W32, (float*)DL32,
-                     (const double*)base64, (const double*)W64, st, expect, n);
   return hipGetLastError();
 }
 hipError_t launch_iterate64(void* v64, const void* base32, const void* W32, const DevState* st, size_t n,
@@ -357,7 +330,7 @@ template <typename T, int PI>
 static int can_vec(const PassArgs& a, int n) {
   using P = typename ProgOf<PI, T>::type;
   if ((n * (int)sizeof(T)) % 16 != 0) return 0;
-  for (int f = 0; f < P::NR; ++f)
+  for (int f = 0; f < P::NR + Late<P>::n; ++f)
     if (((uintptr_t)a.in[f]) % 16 != 0) return 0;
   for (int f = 0; f < P::NO; ++f)
     if (((uintptr_t)a.out[f]) % 16 != 0) return 0;
@@ -430,6 +403,7 @@ hipError_t MOLT_KFN(launch_xpass)(int prog, const LineCoef& c, const PassArgs& a
     case PROG_P2F: return xpass_t<MOLT_KT, PROG_P2F>(c, a, st, nlines, rpart, s, prec);
     case PROG_P4F: return xpass_t<MOLT_KT, PROG_P4F>(c, a, st, nlines, rpart, s, prec);
     case PROG_RHSW: return xpass_t<MOLT_KT, PROG_RHSW>(c, a, st, nlines, rpart, s, prec);
+    case PROG_P4R: return xpass_t<MOLT_KT, PROG_P4R>(c, a, st, nlines, rpart, s, prec);
 #endif
   }
   return hipErrorInvalidValue;
