@@ -31,13 +31,16 @@ namespace molt {
 // the first (full-form) iteration of each step in the FP64 kernels and the
 // later iterations in the FP32 kernels; both are launched every tick and each
 // leaves the other's slots alone.
-__device__ __forceinline__ bool slot_fp64_phase(const SlotDesc& d, const SlotCtl& cc) {
-  return cc.phase == PH_R || (cc.phase == PH_IT && d.st->iters % kRestartEvery == 0);
+// the precision of a slot's next tick, kept in its control word by whatever
+// changes the phase or the iteration count (init, close, tick end), so that a
+// kernel of the other precision leaves after reading that one word
+__device__ __forceinline__ int slot_fp64_next(const SlotDesc& d, int phase, int iters) {
+  if (!d.hybrid) return 1;  // (an unmixed batch is FP64)
+  return phase == PH_R || (phase == PH_IT && iters % kRestartEvery == 0) ? 1 : 0;
 }
 template <typename T>
-__device__ __forceinline__ bool slot_mine(const SlotDesc& d, const SlotCtl& cc) {
-  if (!d.hybrid) return true;
-  return slot_fp64_phase(d, cc) == (sizeof(T) == 8);
+__device__ __forceinline__ bool slot_mine(const SlotDesc&, const SlotCtl& cc) {
+  return cc.fp64 == (sizeof(T) == 8 ? 1 : 0);
 }
 
 // 0: full form (the first iteration, and a hybrid slot's FP64 restarts), 1: increment form
@@ -266,14 +269,15 @@ __global__ void MOLT_PASS_ATTR xpass_batch_kernel(const SlotDesc* __restrict__ s
 
 // iteration close: one block per listed slot
 template <typename T>
-__global__ void __launch_bounds__(256) close_batch_kernel(const SlotDesc* __restrict__ sd,
-                                                          const SlotCtl* __restrict__ ctl,
+__global__ void __launch_bounds__(256) close_batch_kernel(const SlotDesc* __restrict__ sd, SlotCtl* ctl,
                                                           const BlkMap* __restrict__ slots) {
   const int slot = slots[blockIdx.x].slot;
   const SlotDesc& d = sd[slot];
   if (ctl[slot].phase != PH_IT) return;
   // (a hybrid slot's FP64 iterations ran the FP64 x-pass and its blocks)
   residual_close_body(d.rpart, (d.hybrid && d.st->iters % kRestartEvery == 0) ? d.xblocks64 : d.xblocks, d.st);
+  __syncthreads();  // (thread 0 of the close has counted the iteration)
+  if (threadIdx.x == 0) ctl[slot].fp64 = slot_fp64_next(d, PH_IT, d.st->iters);
 }
 
 // step finish of converged slots: u^{n-1} <- u^n (the BDF2 history), u^{n+1} = base + W
@@ -401,6 +405,7 @@ __global__ void __launch_bounds__(256) tick_end_batch_kernel(const SlotDesc* __r
       st->mass2 = 0.0;
       SlotCtl nc = cc;
       nc.phase = PH_IT;
+      nc.fp64 = slot_fp64_next(d, PH_IT, 0);
       ctl[slot] = nc;
     }
     return;
@@ -425,7 +430,6 @@ __global__ void __launch_bounds__(256) tick_end_batch_kernel(const SlotDesc* __r
     d.rec[cc.step] = r;
     SlotCtl nc;
     nc.step = cc.step + 1;
-    nc.pad = 0;
     if (nc.step < d.nsteps) {
       nc.phase = PH_R;
       nc.var = d.stepper == MOLT_BDF2 ? 1 : 0;
@@ -433,6 +437,7 @@ __global__ void __launch_bounds__(256) tick_end_batch_kernel(const SlotDesc* __r
       nc.phase = PH_IDLE;
       nc.var = var;
     }
+    nc.fp64 = slot_fp64_next(d, nc.phase, 0);
     ctl[slot] = nc;
   }
 }
@@ -444,7 +449,7 @@ __global__ void __launch_bounds__(256) init_batch_kernel(const SlotDesc* __restr
     c.phase = sd[i].nsteps > 0 ? PH_R : PH_IDLE;
     c.step = 0;
     c.var = 0;
-    c.pad = 0;
+    c.fp64 = slot_fp64_next(sd[i], c.phase, 0);
     ctl[i] = c;
   }
 }
@@ -574,7 +579,7 @@ hipError_t MOLT_BFN(launch_batch_tail)(const SlotDesc* sd, SlotCtl* ctl, const B
                                       const BlkMap* pmap, int npblk, bool close_only, bool hybrid, hipStream_t s) {
   if (nslots <= 0) return hipSuccess;
   if (g_prof_on) prof_begin(prof_kind<MOLT_BT>(KF_OTHER * 8 + 1), s);
-  hipLaunchKernelGGL((close_batch_kernel<MOLT_BT>), dim3(nslots), dim3(256), 0, s, sd, (const SlotCtl*)ctl, slots);
+  hipLaunchKernelGGL((close_batch_kernel<MOLT_BT>), dim3(nslots), dim3(256), 0, s, sd, ctl, slots);
 #ifndef MOLT_BATCH_F64
   if (hybrid)
     hipLaunchKernelGGL(rebase_batch_kernel, dim3(npblk), dim3(256), 0, s, sd, (const SlotCtl*)ctl, pmap);

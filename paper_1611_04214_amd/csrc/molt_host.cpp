@@ -1724,7 +1724,7 @@ static int32_t server_admit(molt_server* S) {
     c.phase = q.inst.nsteps > 0 ? PH_R : PH_IDLE;
     c.step = 0;
     c.var = 0;
-    c.pad = 0;
+    c.fp64 = (S->prec == MOLT_F64 || c.phase == PH_R) ? 1 : 0;  // (as the device's slot_fp64_next)
     // stream order puts these after every round already queued
     HIPCHK(hipMemcpyAsync(S->sd + i, &d, sizeof(d), hipMemcpyHostToDevice, S->s));
     HIPCHK(hipMemcpyAsync(S->ctl + i, &c, sizeof(c), hipMemcpyHostToDevice, S->s));

@@ -120,7 +120,8 @@ struct SlotCtl {  // mutable control of one slot (device)
   int phase;      // SlotPhase
   int step;       // steps completed
   int var;        // coefficient set of the current step: 0 BE, 1 BDF2
-  int pad;
+  int fp64;       // 1: the slot's next tick runs in the FP64 kernels (always in an FP64
+                  // batch; an FP32 slot's R phase, first iteration and restarts)
 };
 
 struct SlotDesc {          // constants of one slot, built on the host
